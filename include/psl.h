@@ -1,0 +1,216 @@
+/*
+ * psl.h -- libpsl: MI355X (gfx950) engine for the data-parallel hot path of
+ * the two-phase stochastic search for +-1 sequences with a low peak sidelobe
+ * level (Bosković & Brest, arXiv 2107.09801).
+ *
+ * Problem statement followed by every call:
+ *   Eq. (1)  a sequence S_L of L elements, each +1 or -1;
+ *   Eq. (2)  C_k = sum_{i=1}^{L-k} s_i s_{i+k}, k = 0..L-1;
+ *   Eq. (3)  PSL = max |C_k| over the sidelobes k = 1..L-1;
+ *   Eq. (5)  F = sum_{k=1}^{L-1} |C_k|^alpha, alpha the current phase's
+ *            exponent;
+ *   Algorithm 1 (Search) and the Section 3 text: the limited neighbourhood,
+ *   the move to the best neighbour, best-PSL tracking, the unimproved
+ *   counter and the phase switch (Rand_flip of the local best, exponent swap).
+ *
+ * Conventions
+ *   Indices are 0-based: element i is the paper's s_{i+1}; C[k] for k in
+ *   [0, L). Sequences cross the boundary packed: ceil(L/64) 64-bit words,
+ *   element i in bit (i % 64) of word i/64, bit 1 meaning -1, bits at and
+ *   beyond L zero.
+ *   Every call returns a psl_status. Nothing throws or aborts across the
+ *   boundary. Errors from asynchronous device work surface at the next call
+ *   that synchronises (psl_sync, psl_read_walk, psl_eval_neighbourhood, ...).
+ *   A context is used by one host thread at a time, except the psl_serve_*
+ *   calls, which are thread-safe.
+ *   All device memory a context uses is owned by the context. Pointers
+ *   documented as device pointers are caller-owned device memory on the
+ *   context's device; host pointers are caller-owned host memory.
+ *
+ * Readings where the paper is silent or ambiguous (shared with the tests):
+ *   - PSL runs over 1 <= k <= L-1.
+ *   - alpha is an integer in [1,16]; |c|^alpha comes from a per-|c| FP64
+ *     table whose entry is the left-to-right product c*c*...*c.
+ *   - Best-neighbour choice: the first neighbour in scan order whose F lies
+ *     within F_min*(1+tau) of the minimum, tau = 1e-12 (the strict-less-than
+ *     scan of Algorithm 1 when the band holds only exact ties).
+ *   - Improvement test: improved iff v_step < v_local*(1-tau), worse iff
+ *     v_step > v_local*(1+tau), otherwise no bookkeeping change.
+ *   - psl_best starts at the initial pivot's PSL (the best sequence is the
+ *     initial pivot); local_best starts at the initial pivot and is not
+ *     reassigned at a switch.
+ *   - Rand_flip flips FLIP_lmt distinct positions (draw r mod L, skip
+ *     repeats, FLIP_lmt <= 1024).
+ *   - Random numbers are counter-based SplitMix64 (Steele, Lea & Flood 2014):
+ *     draw(seed, ctr) = mix(seed + (ctr+1)*0x9E3779B97F4A7C15). Counters:
+ *     initial pivot word w -> w; start of step t -> (1<<60)|t; switch q,
+ *     attempt r -> (2<<60)|(q<<24)|r. Element i of a random initial pivot
+ *     is bit (i%64) of draw(seed, i/64). start = draw mod L.
+ *   - switch_period 0 is the paper's trigger (unimproved > LS_lmt); P > 0
+ *     switches after the bookkeeping of step t whenever (t+1) mod P == 0.
+ */
+#ifndef PSL_H
+#define PSL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define PSL_API __attribute__((visibility("default")))
+#else
+#define PSL_API
+#endif
+
+typedef int32_t psl_status;
+#define PSL_OK        0
+#define PSL_E_INVAL  (-1)   /* an argument is out of range or inconsistent  */
+#define PSL_E_NOMEM  (-2)   /* device memory (or the arena) is exhausted     */
+#define PSL_E_HIP    (-3)   /* a HIP runtime call or kernel failed           */
+#define PSL_E_STATE  (-4)   /* unknown walk or ticket, or wrong call order   */
+#define PSL_E_AGAIN  (-5)   /* serving: the job is queued or running         */
+#define PSL_E_FULL   (-6)   /* serving: the job can never fit the budget     */
+
+#define PSL_L_MAX        1048575u   /* 2^20 - 1, the paper's largest L        */
+#define PSL_ALPHA_MAX    16u
+#define PSL_FLIP_LMT_MAX 1024u
+
+typedef struct psl_ctx psl_ctx;
+
+/* Control parameters of Search (Algorithm 1; the list in Section 4.1). */
+typedef struct {
+    uint32_t L;              /* sequence length, 2 <= L <= PSL_L_MAX          */
+    uint32_t alpha1;         /* exponent of the first phase, 1..16            */
+    uint32_t alpha2;         /* exponent of the second phase, 1..16           */
+    uint32_t n_lmt;          /* N_lmt, 1..L; 0 means L (full neighbourhood)   */
+    uint32_t ls_lmt;         /* LS_lmt, used when switch_period == 0          */
+    uint32_t flip_lmt;       /* FLIP_lmt, 0..min(L, PSL_FLIP_LMT_MAX)         */
+    uint32_t switch_period;  /* 0: paper trigger; P > 0: every P steps        */
+    uint32_t reserved;       /* must be 0                                     */
+    uint64_t seed;           /* SEED of Rand                                  */
+} psl_walk_cfg;
+
+/* Result of one limited-neighbourhood evaluation (the scan of Algorithm 1). */
+typedef struct {
+    uint32_t j_best;    /* element index of the move (best neighbour)         */
+    uint32_t i_best;    /* its scan index: j_best = (start + i_best + 1) % L   */
+    double   F_best;    /* its F (value_step)                                  */
+    double   F_min;     /* the minimum F over the scanned neighbours           */
+    uint32_t j_psl;     /* element index of the first neighbour with min PSL  */
+    int32_t  psl_min;   /* that PSL                                            */
+    int32_t  psl_k;     /* PSL of the move                                     */
+    uint32_t flags;     /* reserved, 0                                         */
+} psl_choice;
+
+/* Snapshot of a walk's scalar state. */
+typedef struct {
+    uint32_t L, alpha1, alpha2, alpha;   /* alpha: the current exponent      */
+    uint32_t n_lmt, ls_lmt, flip_lmt, switch_period;
+    uint64_t seed;
+    uint64_t t;                /* steps done                                  */
+    uint64_t q;                /* switches done                               */
+    double   value_local;      /* F of the phase's local best                 */
+    double   F_pivot;          /* F of the pivot in the current exponent      */
+    int32_t  psl_pivot;        /* PSL of the pivot                            */
+    int32_t  psl_best;         /* best PSL seen (solution_best's PSL)         */
+    uint32_t unimproved;
+    uint32_t last_k;           /* element flipped by the last step            */
+    double   last_value_step;  /* F of the last move                          */
+    uint32_t last_start;       /* start of the last limited neighbourhood     */
+    uint32_t last_flags;       /* PSL_STEP_* bits of the last step            */
+} psl_walk_state;
+
+#define PSL_STEP_IMPROVED     1u
+#define PSL_STEP_WORSE        2u
+#define PSL_STEP_SWITCHED     4u
+#define PSL_STEP_PSL_IMPROVED 8u
+
+/* ------------------------------------------------------------ context */
+
+/* Create a context on HIP device `device`. `hip_stream` is a hipStream_t to
+ * run on (NULL: the context creates its own). If `arena` is non-NULL it is a
+ * caller-owned device buffer of `arena_bytes` bytes from which every walk slab
+ * is carved (it must outlive the context); otherwise slabs come from hipMalloc.
+ * Errors: PSL_E_INVAL (bad device or null out), PSL_E_HIP. */
+PSL_API psl_status psl_ctx_create(int device, void *hip_stream, void *arena, size_t arena_bytes,
+                          psl_ctx **out);
+
+/* Destroy a context: stops serving, waits for its work, frees its memory. */
+PSL_API void psl_ctx_destroy(psl_ctx *ctx);
+
+/* Text of the last error on this context (never NULL; "" if none). */
+PSL_API const char *psl_last_error(const psl_ctx *ctx);
+
+/* Wait for all work queued on the context's stream. */
+PSL_API psl_status psl_sync(psl_ctx *ctx);
+
+/* ------------------------------------------------------------- walks */
+
+/* Start `n` walks with the same control parameters: the lines of Algorithm 1
+ * before its loop. Walk w's pivot is init_bits[w] (host, packed) when
+ * init_bits and init_bits[w] are non-NULL, otherwise Rand(L, cfg->seed + w).
+ * Computes C (Eq. (2)), F in alpha1 (Eq. (5)) as value_local, the PSL
+ * (Eq. (3)) as psl_best; local_best and solution_best start as the pivot.
+ * walk_ids_out (host, n entries) receives the walk handles. Blocking.
+ * Errors: PSL_E_INVAL (cfg out of range), PSL_E_NOMEM, PSL_E_HIP. */
+PSL_API psl_status psl_init_walks(psl_ctx *ctx, const psl_walk_cfg *cfg, uint32_t n,
+                          const uint64_t *const *init_bits, uint32_t *walk_ids_out);
+
+/* Release walks (their slabs return to the context). PSL_E_STATE for an
+ * unknown handle (the others are still released). */
+PSL_API psl_status psl_free_walks(psl_ctx *ctx, const uint32_t *walk_ids, uint32_t n);
+
+/* Neighborhood(pivot, f, alpha, N_lmt, start) of Algorithm 1 for one walk,
+ * with the walk's current exponent, followed by the scan that picks the move
+ * and the best-PSL neighbour. Pure: the walk is not changed. Entry i-1 of
+ * the outputs belongs to element j = (start + i) % L, i = 1..n_lmt
+ * (1 <= n_lmt <= L, start < L). F_dev (FP64) and psl_dev (int32) are
+ * optional device arrays of n_lmt entries; out (host) receives the choice.
+ * Blocking. Errors: PSL_E_INVAL, PSL_E_STATE (unknown walk), PSL_E_HIP. */
+PSL_API psl_status psl_eval_neighbourhood(psl_ctx *ctx, uint32_t walk, uint32_t start,
+                                  uint32_t n_lmt, double *F_dev, int32_t *psl_dev,
+                                  psl_choice *out);
+
+/* Flip(pivot, j) of Algorithm 1: element j changes sign and C is updated in
+ * O(L) by the one-element flip C'_k = C_k - 2 s_j (s_{j+k} + s_{j-k}) (terms
+ * that stay in bounds only); the pivot's F and PSL are recomputed. No
+ * bookkeeping, best tracking or phase logic runs. Blocking.
+ * Errors: PSL_E_INVAL (j >= L), PSL_E_STATE, PSL_E_HIP. */
+PSL_API psl_status psl_apply_flip(psl_ctx *ctx, uint32_t walk, uint32_t j);
+
+/* Run `steps` iterations of the loop of Algorithm 1 on each of the `n`
+ * walks (host array of handles, no repeats): random start, limited
+ * neighbourhood, best-neighbour and best-PSL scan, Flip, the three-way
+ * comparison and the phase switch. Work is queued on the context's stream;
+ * with PSL_STEP_BLOCKING the call waits for it. Walks of different L may be
+ * mixed. Errors: PSL_E_INVAL, PSL_E_STATE, PSL_E_NOMEM, PSL_E_HIP. */
+#define PSL_STEP_BLOCKING 1u
+PSL_API psl_status psl_step_batch(psl_ctx *ctx, const uint32_t *walk_ids, uint32_t n,
+                          uint32_t steps, uint32_t flags);
+
+/* Copy a walk to host memory. `out` receives the scalars; pivot_bits,
+ * local_best_bits and best_bits (ceil(L/64) words each) and C (L int32) are
+ * optional host buffers. Waits for queued work first.
+ * Errors: PSL_E_STATE, PSL_E_HIP. */
+PSL_API psl_status psl_read_walk(psl_ctx *ctx, uint32_t walk, psl_walk_state *out,
+                         uint64_t *pivot_bits, uint64_t *local_best_bits,
+                         uint64_t *best_bits, int32_t *C);
+
+/* ----------------------------------------------------- introspection */
+
+/* Number of device work items, blocks per item and k-splits the evaluation
+ * of one walk of length L with n_lmt candidates uses (for tests and bench). */
+PSL_API psl_status psl_eval_shape(psl_ctx *ctx, uint32_t L, uint32_t n_lmt, uint32_t n_walks,
+                          uint32_t *cand_tiles, uint32_t *k_splits);
+
+/* Library version string. */
+PSL_API const char *psl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSL_H */

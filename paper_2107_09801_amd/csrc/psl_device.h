@@ -1,0 +1,88 @@
+// psl_device.h -- device-side layout of a walk and the kernel entry points.
+//
+// Internal to libpsl (not part of the C-ABI). One WalkDev per walk slot lives
+// in device memory; kernels read and update it, the host copies it only at
+// init and read-back.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace psl {
+
+constexpr double kTau = 1e-12;       // relative band of the best-neighbour and
+                                     // improvement comparisons
+constexpr int kEvalWaves = 4;        // wavefronts per evaluation block
+constexpr int kEvalThreads = 64 * kEvalWaves;
+constexpr int kTileK = 256;          // shifts staged per LDS tile
+constexpr int kRowStride = 5;        // T(|C_k + 2m|), m = -2..2
+
+struct WalkDev {
+    // storage (slab)
+    uint64_t *pivot;        // nw words
+    uint64_t *local_best;   // nw words
+    uint64_t *best;         // nw words (solution_best)
+    int32_t *C;             // L entries, C[0] = L
+    // control parameters
+    uint64_t seed;
+    uint32_t L, nw;
+    uint32_t alpha1, alpha2;
+    uint32_t n_lmt, ls_lmt, flip_lmt, switch_period;
+    // state
+    uint32_t alpha;
+    uint32_t unimproved;
+    uint64_t t;             // steps done
+    uint64_t q;             // switches done
+    double value_local;
+    double F_pivot;
+    int32_t psl_pivot;
+    int32_t psl_best;
+    // last step
+    uint32_t start;
+    uint32_t k;             // move (element index)
+    uint32_t i_best;        // its scan index
+    uint32_t j_psl;
+    double value_step;
+    double F_min;
+    int32_t psl_k;
+    int32_t psl_min;
+    uint32_t flags;
+    uint32_t pending;       // 1: C, F and PSL of the pivot must be rebuilt
+};
+
+struct Tables {
+    const double *T[17];    // T[alpha][c] = c^alpha, left-to-right product
+    uint32_t n;             // entries per table
+    uint32_t pad;
+};
+
+// One walk of a batch, with its evaluation scratch (host-set per batch).
+struct BatchEntry {
+    double *Fpart;          // ksplit * n_lmt partial sums of T(|C'|)
+    uint32_t *Mpart;        // ksplit * n_lmt partial maxima of hi32(T(|C'|))
+    double *F;              // n_lmt: F per scan index
+    int32_t *P;             // n_lmt: PSL per scan index
+    uint32_t slot;          // walk slot
+    uint32_t ksplit;        // k-splits of the evaluation
+    uint32_t tiles;         // candidate tiles of the evaluation
+    uint32_t n_lmt;         // candidates evaluated
+    uint32_t start;         // start, when fixed by the caller
+    uint32_t fixed;         // 1: start and n_lmt come from this entry
+};
+
+// Eval work item: walk position in the batch, candidate tile, k-split index.
+struct EvalItem {
+    uint32_t walk;
+    uint32_t tile;
+    uint32_t ks;
+    uint32_t pad;
+};
+
+enum : uint32_t {
+    STEP_IMPROVED = 1u,
+    STEP_WORSE = 2u,
+    STEP_SWITCHED = 4u,
+    STEP_PSL_IMPROVED = 8u,
+};
+
+}  // namespace psl

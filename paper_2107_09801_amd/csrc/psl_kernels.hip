@@ -1,0 +1,630 @@
+// psl_kernels.hip -- gfx950 kernels of libpsl.
+//
+// The hot path is the limited-neighbourhood evaluation of Algorithm 1 (the
+// Neighborhood call): for every candidate flip j and every shift k the
+// one-element flip gives C'_k = C_k - 2 s_j (s_{j+k}[j+k<L] + s_{j-k}[j-k>=0])
+// (Section 3, with Eq. (2)), and from the C'_k the kernel accumulates
+// F_j = sum_k |C'_k|^alpha (Eq. (5)) and PSL_j = max_k |C'_k| (Eq. (3)).
+//
+// Layout: one lane per candidate, 64 candidates per wavefront, four
+// wavefronts per block. Shifts are swept in tiles of kTileK; for each shift of
+// a tile the block stages in LDS the five values T(|C_k + 2m|), m = -2..2, that
+// C'_k can take, so the per-(j,k) work is: two bits of the packed sequence
+// (already XOR-ed with s_j), a row index, one LDS read, one FP64 add and one
+// 32-bit max of its high word. Bits come from 32-shift windows of the packed sequence, one funnel
+// shift per window, and the in-bounds masks of the window decide (uniformly
+// per wavefront, almost always) which of four branch-free forms applies.
+#include "psl_device.h"
+#include "psl_launch.h"
+
+#include <climits>
+
+namespace psl {
+
+// ------------------------------------------------------------ helpers
+
+// Counter-based SplitMix64 (Steele, Lea & Flood 2014): output ctr+1 of the
+// stream whose state starts at seed.
+__device__ __forceinline__ uint64_t draw(uint64_t seed, uint64_t ctr)
+{
+    uint64_t z = seed + (ctr + 1u) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint32_t step_start(const WalkDev &w)
+{
+    return (uint32_t)(draw(w.seed, (1ull << 60) | w.t) % (uint64_t)w.L);
+}
+
+__device__ __forceinline__ uint32_t get_bit(const uint64_t *b, uint32_t i)
+{
+    return (uint32_t)((b[i >> 6] >> (i & 63u)) & 1u);
+}
+
+// Bits [pos, pos+32) of a packed sequence held as nw32 32-bit words; bits
+// outside the words read as 0.
+__device__ __forceinline__ uint32_t bits32_at(const uint32_t *__restrict__ w32, int nw32,
+                                              int pos)
+{
+    int wi = pos >> 5;
+    uint32_t sh = (uint32_t)pos & 31u;
+    uint32_t lo = (wi >= 0 && wi < nw32) ? w32[wi] : 0u;
+    uint32_t hi = (wi + 1 >= 0 && wi + 1 < nw32) ? w32[wi + 1] : 0u;
+    return __builtin_amdgcn_alignbit(hi, lo, sh);
+}
+
+__device__ __forceinline__ double dmax(double a, double b) { return a > b ? a : b; }
+
+// High 32 bits of a non-negative double. Over the power table they are
+// strictly increasing in |c| (consecutive entries differ by a factor of at
+// least 1 + 2^-19 for alpha >= 2 and |c| <= 2^20 + 8; for alpha = 1 the
+// entries are integers below 2^21, exact in 20 fraction bits), so the
+// running maximum of T(|C'|) can be kept as a 32-bit unsigned maximum.
+__device__ __forceinline__ uint32_t hi32(double v)
+{
+    return (uint32_t)((uint64_t)__double_as_longlong(v) >> 32);
+}
+
+// Neumaier's compensated addition.
+__device__ __forceinline__ void nsum_add(double &sum, double &comp, double x)
+{
+    double t = sum + x;
+    if (fabs(sum) >= fabs(x)) comp += (sum - t) + x;
+    else                      comp += (x - t) + sum;
+    sum = t;
+}
+
+// Smallest c with hi32(T[c]) >= h: |c| from the high word of T(|c|).
+__device__ __forceinline__ int32_t table_inverse(const double *T, uint32_t n, uint32_t h)
+{
+    uint32_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (hi32(T[mid]) < h) lo = mid + 1;
+        else                  hi = mid;
+    }
+    return (int32_t)lo;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous range of work items so that the blocks of one walk share an L2.
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t nb)
+{
+    const uint32_t nx = 8;
+    uint32_t q = nb / nx, r = nb % nx;
+    uint32_t x = b % nx, local = b / nx;
+    return x * q + (x < r ? x : r) + local;
+}
+
+// ------------------------------------------------------- power tables
+
+__global__ void k_power_table(double *T, uint32_t n, uint32_t alpha)
+{
+    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    double x = (double)c, p = x;
+    for (uint32_t a = 1; a < alpha; ++a) p = p * x;
+    T[c] = p;
+}
+
+// ------------------------------------------------------------- init
+
+// Random initial pivots (Rand(L, SEED)) for batch entries with want[b] != 0,
+// then local_best = best = pivot for every entry.
+__global__ void k_init_bits(WalkDev *walks, const BatchEntry *batch, const uint32_t *want)
+{
+    WalkDev &w = walks[batch[blockIdx.y].slot];
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= w.nw) return;
+    uint64_t v = w.pivot[i];
+    if (want[blockIdx.y]) {
+        v = draw(w.seed, i);
+        if (i == w.nw - 1 && (w.L & 63u)) v &= (1ull << (w.L & 63u)) - 1ull;
+        w.pivot[i] = v;
+    }
+    w.local_best[i] = v;
+    w.best[i] = v;
+}
+
+// Eq. (2) from the packed pivot: C_k = (L-k) - 2 * #(s_i != s_{i+k}).
+// only_pending: skip walks without a pending rebuild.
+__global__ void k_corr(WalkDev *walks, const BatchEntry *batch, int only_pending)
+{
+    WalkDev &w = walks[batch[blockIdx.y].slot];
+    if (only_pending && !w.pending) return;
+    const uint32_t L = w.L;
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= L) return;
+    const uint64_t *b = w.pivot;
+    const uint32_t n = L - k;
+    int32_t diff = 0;
+    for (uint32_t i = 0; i < n; i += 64) {
+        uint64_t a = b[i >> 6];
+        uint32_t p = i + k;
+        uint32_t wi = p >> 6, sh = p & 63u;
+        uint64_t lo = b[wi];
+        uint64_t hi = (wi + 1 < w.nw) ? b[wi + 1] : 0ull;
+        uint64_t c = sh ? ((lo >> sh) | (hi << (64u - sh))) : lo;
+        uint64_t x = a ^ c;
+        uint32_t rem = n - i;
+        if (rem < 64) x &= (1ull << rem) - 1ull;
+        diff += __popcll(x);
+    }
+    w.C[k] = (int32_t)n - 2 * diff;
+}
+
+// F of the pivot (Eq. (5)) and its PSL (Eq. (3)) from C, one block per walk,
+// fixed blocking so a given C always gives the same F bits.
+// mode 0: initial (value_local, F_pivot, psl_pivot, psl_best);
+// mode 1: after a switch, pending walks only (value_local, F_pivot,
+//         psl_pivot, unimproved = 0, pending = 0);
+// mode 2: after a forced flip (F_pivot, psl_pivot).
+constexpr int kFitThreads = 256;
+__global__ __launch_bounds__(kFitThreads) void k_fitness(WalkDev *walks, const BatchEntry *batch,
+                                                         Tables tabs, int mode)
+{
+    WalkDev &w = walks[batch[blockIdx.x].slot];
+    if (mode == 1 && !w.pending) return;
+    const double *T = tabs.T[w.alpha];
+    double sum = 0.0, comp = 0.0;
+    int32_t peak = 0;
+    for (uint32_t k = 1 + threadIdx.x; k < w.L; k += kFitThreads) {
+        int32_t c = w.C[k];
+        int32_t a = c < 0 ? -c : c;
+        nsum_add(sum, comp, T[a]);
+        peak = a > peak ? a : peak;
+    }
+    __shared__ double s_sum[kFitThreads], s_comp[kFitThreads];
+    __shared__ int32_t s_peak[kFitThreads];
+    s_sum[threadIdx.x] = sum;
+    s_comp[threadIdx.x] = comp;
+    s_peak[threadIdx.x] = peak;
+    __syncthreads();
+    for (int h = kFitThreads / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            double a = s_sum[threadIdx.x], ca = s_comp[threadIdx.x];
+            nsum_add(a, ca, s_sum[threadIdx.x + h]);
+            s_sum[threadIdx.x] = a;
+            s_comp[threadIdx.x] = ca + s_comp[threadIdx.x + h];
+            int32_t p2 = s_peak[threadIdx.x + h];
+            if (p2 > s_peak[threadIdx.x]) s_peak[threadIdx.x] = p2;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double F = s_sum[0] + s_comp[0];
+        int32_t p = s_peak[0];
+        w.F_pivot = F;
+        w.psl_pivot = p;
+        if (mode == 0) {
+            w.value_local = F;
+            w.psl_best = p;
+        } else if (mode == 1) {
+            w.value_local = F;
+            w.unimproved = 0;
+            w.pending = 0;
+        }
+    }
+}
+
+// --------------------------------------------- neighbourhood evaluation
+
+__global__ __launch_bounds__(kEvalThreads) void k_eval(const WalkDev *__restrict__ walks,
+                                                       const BatchEntry *__restrict__ batch,
+                                                       const EvalItem *__restrict__ items,
+                                                       Tables tabs)
+{
+    __shared__ double rows[kTileK * kRowStride];
+
+    const EvalItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
+    const BatchEntry be = batch[it.walk];
+    const WalkDev &w = walks[be.slot];
+    const int L = (int)w.L;
+    const uint32_t n_lmt = be.fixed ? be.n_lmt : w.n_lmt;
+    const uint32_t start = be.fixed ? be.start : step_start(w);
+    const double *__restrict__ T = tabs.T[w.alpha];
+    const int32_t *__restrict__ C = w.C;
+    const uint32_t *__restrict__ w32 = reinterpret_cast<const uint32_t *>(w.pivot);
+    const int nw32 = (int)w.nw * 2;
+
+    // shifts of this split, in whole 32-shift chunks from k = 1
+    const int nchunks = (L - 1 + 31) / 32;
+    const int per = (nchunks + (int)be.ksplit - 1) / (int)be.ksplit;
+    const int c_lo = (int)it.ks * per;
+    const int c_hi = min(nchunks, c_lo + per);
+    const int k_lo = 1 + 32 * c_lo;
+    const int k_hi = min(L, 1 + 32 * c_hi);
+
+    // this lane's candidate; inactive lanes keep a valid j and store nothing
+    const uint32_t i = it.tile * kEvalThreads + threadIdx.x;
+    const bool active = i < n_lmt;
+    const uint32_t ii = active ? i : n_lmt - 1;
+    const int j = (int)((start + 1u + ii) % (uint32_t)L);
+    const uint32_t SJ = ((w32[j >> 5] >> (j & 31)) & 1u) ? 0xFFFFFFFFu : 0u;
+
+    double sum = 0.0, comp = 0.0;
+    uint32_t mx = 0;
+    for (int kt = k_lo; kt < k_hi; kt += kTileK) {
+        const int kt_end = min(k_hi, kt + kTileK);
+        __syncthreads();
+        for (int t = threadIdx.x; t < kt_end - kt; t += kEvalThreads) {
+            const int c = C[kt + t];
+#pragma unroll
+            for (int m = 0; m < kRowStride; ++m) {
+                int a = c + 2 * m - 4;
+                a = a < 0 ? -a : a;
+                rows[t * kRowStride + m] = T[a];
+            }
+        }
+        __syncthreads();
+
+        double acc = 0.0;
+        for (int k0 = kt; k0 < kt_end; k0 += 32) {
+            const int tcount = min(32, kt_end - k0);
+            const double *rb = rows + (k0 - kt) * kRowStride;
+            // xr bit t: s_j s_{j+k0+t} == -1; xl bit 31-t: s_j s_{j-k0-t} == -1
+            const uint32_t XR = bits32_at(w32, nw32, j + k0) ^ SJ;
+            const uint32_t XL = bits32_at(w32, nw32, j - k0 - 31) ^ SJ;
+            const int nR = L - j - k0;   // shifts k0.. with j+k < L
+            const int nL = j - k0 + 1;   // shifts k0.. with j-k >= 0
+            const uint32_t VR = nR >= 32 ? ~0u : (nR <= 0 ? 0u : ((1u << nR) - 1u));
+            const uint32_t VL = nL >= 32 ? ~0u : (nL <= 0 ? 0u : (~0u << (32 - nL)));
+            const bool full = tcount == 32;
+            if (full && __all(VR == ~0u && VL == ~0u)) {
+                // both neighbours in bounds: C' = C + 4(xr + xl - 1)
+#pragma unroll
+                for (int t = 0; t < 32; ++t) {
+                    const uint32_t xr = (XR >> t) & 1u;
+                    const uint32_t xl = (XL >> (31 - t)) & 1u;
+                    const double v = rb[t * kRowStride + 2 * (xr + xl)];
+                    acc += v;
+                    mx = max(mx, hi32(v));
+                }
+            } else if (full && __all(VR == ~0u && VL == 0u)) {
+                // right neighbour only: C' = C + 2(2 xr - 1)
+#pragma unroll
+                for (int t = 0; t < 32; ++t) {
+                    const uint32_t xr = (XR >> t) & 1u;
+                    const double v = rb[t * kRowStride + 1 + 2 * xr];
+                    acc += v;
+                    mx = max(mx, hi32(v));
+                }
+            } else if (full && __all(VR == 0u && VL == ~0u)) {
+                // left neighbour only
+#pragma unroll
+                for (int t = 0; t < 32; ++t) {
+                    const uint32_t xl = (XL >> (31 - t)) & 1u;
+                    const double v = rb[t * kRowStride + 1 + 2 * xl];
+                    acc += v;
+                    mx = max(mx, hi32(v));
+                }
+            } else if (full && __all(VR == 0u && VL == 0u)) {
+                // neither: C' = C
+#pragma unroll
+                for (int t = 0; t < 32; ++t) {
+                    const double v = rb[t * kRowStride + 2];
+                    acc += v;
+                    mx = max(mx, hi32(v));
+                }
+            } else {
+                for (int t = 0; t < tcount; ++t) {
+                    int m = 2;
+                    if ((VR >> t) & 1u) m += ((XR >> t) & 1u) ? 1 : -1;
+                    if ((VL >> (31 - t)) & 1u) m += ((XL >> (31 - t)) & 1u) ? 1 : -1;
+                    const double v = rb[t * kRowStride + m];
+                    acc += v;
+                    mx = max(mx, hi32(v));
+                }
+            }
+        }
+        nsum_add(sum, comp, acc);
+    }
+    if (active) {
+        const size_t o = (size_t)it.ks * n_lmt + i;
+        be.Fpart[o] = sum + comp;
+        be.Mpart[o] = mx;
+    }
+}
+
+// ------------------------------------------------------- selection
+
+struct ChoiceDev {
+    uint32_t i_best, j_best;
+    double F_best, F_min;
+    uint32_t j_psl;
+    int32_t psl_min;
+    int32_t psl_k;
+    uint32_t pad;
+};
+
+constexpr int kSelThreads = 1024;
+
+// Combines the k-split partials into F and PSL per candidate, then the scan
+// of Algorithm 1: the move is the first candidate in scan order within
+// F_min*(1+tau); the best-PSL neighbour is the first with the minimum PSL.
+// pure != 0: write the choice to out[b] and leave the walk unchanged.
+// Otherwise record the choice in the walk and, on a strict PSL improvement,
+// update psl_best and solution_best = pivot with j_psl flipped.
+__global__ __launch_bounds__(kSelThreads) void k_select(WalkDev *walks, const BatchEntry *batch,
+                                                        Tables tabs, int pure, ChoiceDev *out)
+{
+    const BatchEntry be = batch[blockIdx.x];
+    WalkDev &w = walks[be.slot];
+    const uint32_t n = be.fixed ? be.n_lmt : w.n_lmt;
+    const uint32_t start = be.fixed ? be.start : step_start(w);
+    const uint32_t L = w.L;
+    const uint32_t ks = be.ksplit;
+    const double *T = tabs.T[w.alpha];
+
+    double fmin = INFINITY;
+    int32_t pmin = INT_MAX;
+    uint32_t ipmin = UINT_MAX;
+    for (uint32_t i = threadIdx.x; i < n; i += kSelThreads) {
+        double f = 0.0;
+        uint32_t m = 0;
+        for (uint32_t s = 0; s < ks; ++s) {
+            f += be.Fpart[(size_t)s * n + i];
+            m = max(m, be.Mpart[(size_t)s * n + i]);
+        }
+        const int32_t p = table_inverse(T, tabs.n, m);
+        be.F[i] = f;
+        be.P[i] = p;
+        fmin = f < fmin ? f : fmin;
+        if (p < pmin) { pmin = p; ipmin = i; }
+    }
+    __shared__ double s_f[kSelThreads];
+    __shared__ int32_t s_p[kSelThreads];
+    __shared__ uint32_t s_i[kSelThreads];
+    s_f[threadIdx.x] = fmin;
+    s_p[threadIdx.x] = pmin;
+    s_i[threadIdx.x] = ipmin;
+    __syncthreads();
+    for (int h = kSelThreads / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            const int o = threadIdx.x + h;
+            if (s_f[o] < s_f[threadIdx.x]) s_f[threadIdx.x] = s_f[o];
+            if (s_p[o] < s_p[threadIdx.x] || (s_p[o] == s_p[threadIdx.x] && s_i[o] < s_i[threadIdx.x])) {
+                s_p[threadIdx.x] = s_p[o];
+                s_i[threadIdx.x] = s_i[o];
+            }
+        }
+        __syncthreads();
+    }
+    const double Fmin = s_f[0];
+    const int32_t Pmin = s_p[0];
+    const uint32_t iPmin = s_i[0];
+    const double thr = Fmin * (1.0 + kTau);
+    __syncthreads();
+
+    // first scan index inside the band (each thread re-reads its own writes)
+    uint32_t ifirst = UINT_MAX;
+    for (uint32_t i = threadIdx.x; i < n; i += kSelThreads) {
+        if (be.F[i] <= thr) { ifirst = i; break; }
+    }
+    s_i[threadIdx.x] = ifirst;
+    __syncthreads();
+    for (int h = kSelThreads / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            const uint32_t o = s_i[threadIdx.x + h];
+            if (o < s_i[threadIdx.x]) s_i[threadIdx.x] = o;
+        }
+        __syncthreads();
+    }
+    const uint32_t ib = s_i[0];
+    const uint32_t kb = (uint32_t)(((uint64_t)start + 1u + ib) % L);
+    const uint32_t jp = (uint32_t)(((uint64_t)start + 1u + iPmin) % L);
+
+    // thread ib % kSelThreads wrote F[ib] and P[ib]; it hands them over
+    __shared__ double s_Fb;
+    __shared__ int32_t s_Pb;
+    __shared__ int s_improve;
+    if (threadIdx.x == ib % kSelThreads) {
+        s_Fb = be.F[ib];
+        s_Pb = be.P[ib];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double Fb = s_Fb;
+        const int32_t Pb = s_Pb;
+        if (pure) {
+            ChoiceDev c;
+            c.i_best = ib; c.j_best = kb; c.F_best = Fb; c.F_min = Fmin;
+            c.j_psl = jp; c.psl_min = Pmin; c.psl_k = Pb; c.pad = 0;
+            out[blockIdx.x] = c;
+            s_improve = 0;
+        } else {
+            w.start = start;
+            w.k = kb;
+            w.i_best = ib;
+            w.value_step = Fb;
+            w.F_min = Fmin;
+            w.psl_k = Pb;
+            w.j_psl = jp;
+            w.psl_min = Pmin;
+            w.flags = 0;
+            s_improve = Pmin < w.psl_best;
+            if (s_improve) {
+                w.psl_best = Pmin;
+                w.flags = STEP_PSL_IMPROVED;
+            }
+        }
+    }
+    __syncthreads();
+    if (s_improve) {
+        for (uint32_t x = threadIdx.x; x < w.nw; x += kSelThreads) {
+            uint64_t v = w.pivot[x];
+            if (x == (jp >> 6)) v ^= 1ull << (jp & 63u);
+            w.best[x] = v;
+        }
+    }
+}
+
+// ------------------------------------------------------------ flip
+
+// Flip(pivot, j), part 1: C_k += -2 s_j (s_{j+k} + s_{j-k}) over the terms in
+// bounds, read from the pivot before its bit changes. j_fixed < 0: the walk's
+// recorded move.
+__global__ void k_apply(WalkDev *walks, const BatchEntry *batch, int64_t j_fixed)
+{
+    WalkDev &w = walks[batch[blockIdx.y].slot];
+    const uint32_t L = w.L;
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x + 1u;
+    if (k >= L) return;
+    const uint32_t j = j_fixed >= 0 ? (uint32_t)j_fixed : w.k;
+    const uint64_t *b = w.pivot;
+    const int sj = get_bit(b, j) ? -1 : 1;
+    int d = 0;
+    if (j + k < L) d += get_bit(b, j + k) ? -1 : 1;
+    if (k <= j) d += get_bit(b, j - k) ? -1 : 1;
+    w.C[k] -= 2 * sj * d;
+}
+
+// Flip(pivot, j), part 2, for a forced flip: the bit itself.
+__global__ void k_flip_bit(WalkDev *walks, const BatchEntry *batch, uint32_t j)
+{
+    WalkDev &w = walks[batch[0].slot];
+    if (threadIdx.x == 0) w.pivot[j >> 6] ^= 1ull << (j & 63u);
+}
+
+constexpr int kBookThreads = 256;
+
+// The rest of one loop iteration of Algorithm 1 after the C update: the
+// move's bit, the three-way comparison with v_local, the unimproved counter,
+// the local best, and the phase switch (Rand_flip of the local best and the
+// exponent swap; C, F and PSL of the new pivot are rebuilt by k_corr and
+// k_fitness on walks left pending).
+__global__ __launch_bounds__(kBookThreads) void k_bookkeep(WalkDev *walks, const BatchEntry *batch)
+{
+    WalkDev &w = walks[batch[blockIdx.x].slot];
+    __shared__ int s_improved, s_switch;
+    __shared__ uint32_t s_pos[1024];
+    if (threadIdx.x == 0) {
+        const uint32_t k = w.k;
+        w.pivot[k >> 6] ^= 1ull << (k & 63u);
+        w.F_pivot = w.value_step;
+        w.psl_pivot = w.psl_k;
+        const double v = w.value_step;
+        const double lo = w.value_local * (1.0 - kTau);
+        const double hi = w.value_local * (1.0 + kTau);
+        int improved = 0, sw = 0;
+        uint32_t flags = w.flags;
+        if (v < lo) {
+            improved = 1;
+            w.unimproved = 0;
+            w.value_local = v;
+            flags |= STEP_IMPROVED;
+        } else if (v > hi) {
+            w.unimproved += 1;
+            flags |= STEP_WORSE;
+            if (w.switch_period == 0 && w.unimproved > w.ls_lmt) sw = 1;
+        }
+        if (w.switch_period > 0 && ((w.t + 1u) % w.switch_period) == 0) sw = 1;
+        w.t += 1;
+        if (sw) flags |= STEP_SWITCHED;
+        w.flags = flags;
+        s_improved = improved;
+        s_switch = sw;
+    }
+    __syncthreads();
+    if (s_improved) {
+        for (uint32_t x = threadIdx.x; x < w.nw; x += kBookThreads) w.local_best[x] = w.pivot[x];
+    }
+    __syncthreads();
+    if (s_switch) {
+        for (uint32_t x = threadIdx.x; x < w.nw; x += kBookThreads) w.pivot[x] = w.local_best[x];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const uint32_t L = w.L;
+            uint32_t cnt = 0;
+            for (uint64_t r = 0; cnt < w.flip_lmt && r < (1ull << 24); ++r) {
+                const uint64_t ctr = (2ull << 60) | (w.q << 24) | r;
+                const uint32_t pos = (uint32_t)(draw(w.seed, ctr) % (uint64_t)L);
+                bool dup = false;
+                for (uint32_t x = 0; x < cnt; ++x) dup |= (s_pos[x] == pos);
+                if (dup) continue;
+                s_pos[cnt++] = pos;
+                w.pivot[pos >> 6] ^= 1ull << (pos & 63u);
+            }
+            w.alpha = (w.alpha == w.alpha1) ? w.alpha2 : w.alpha1;
+            w.q += 1;
+            w.pending = 1;
+        }
+    }
+}
+
+// ------------------------------------------------------------ launches
+
+hipError_t launch_power_table(double *T, uint32_t n, uint32_t alpha, hipStream_t s)
+{
+    k_power_table<<<(n + 255) / 256, 256, 0, s>>>(T, n, alpha);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_bits(WalkDev *walks, const BatchEntry *batch, const uint32_t *want,
+                            uint32_t nb, uint32_t max_nw, hipStream_t s)
+{
+    k_init_bits<<<dim3((max_nw + 255) / 256, nb), 256, 0, s>>>(walks, batch, want);
+    return hipGetLastError();
+}
+
+hipError_t launch_corr(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t max_L,
+                       int only_pending, hipStream_t s)
+{
+    k_corr<<<dim3((max_L + 255) / 256, nb), 256, 0, s>>>(walks, batch, only_pending);
+    return hipGetLastError();
+}
+
+hipError_t launch_fitness(WalkDev *walks, const BatchEntry *batch, uint32_t nb, const Tables &tabs,
+                          int mode, hipStream_t s)
+{
+    k_fitness<<<nb, kFitThreads, 0, s>>>(walks, batch, tabs, mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_eval(const WalkDev *walks, const BatchEntry *batch, const EvalItem *items,
+                       uint32_t n_items, const Tables &tabs, hipStream_t s)
+{
+    k_eval<<<n_items, kEvalThreads, 0, s>>>(walks, batch, items, tabs);
+    return hipGetLastError();
+}
+
+hipError_t launch_select(WalkDev *walks, const BatchEntry *batch, uint32_t nb, const Tables &tabs,
+                         int pure, void *out, hipStream_t s)
+{
+    k_select<<<nb, kSelThreads, 0, s>>>(walks, batch, tabs, pure, (ChoiceDev *)out);
+    return hipGetLastError();
+}
+
+size_t choice_dev_size() { return sizeof(ChoiceDev); }
+
+void choice_dev_unpack(const void *p, uint32_t *i_best, uint32_t *j_best, double *F_best,
+                       double *F_min, uint32_t *j_psl, int32_t *psl_min, int32_t *psl_k)
+{
+    const ChoiceDev *c = (const ChoiceDev *)p;
+    *i_best = c->i_best; *j_best = c->j_best; *F_best = c->F_best; *F_min = c->F_min;
+    *j_psl = c->j_psl; *psl_min = c->psl_min; *psl_k = c->psl_k;
+}
+
+hipError_t launch_apply(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t max_L,
+                        int64_t j_fixed, hipStream_t s)
+{
+    if (max_L < 2) return hipSuccess;
+    k_apply<<<dim3((max_L - 1 + 255) / 256, nb), 256, 0, s>>>(walks, batch, j_fixed);
+    return hipGetLastError();
+}
+
+hipError_t launch_flip_bit(WalkDev *walks, const BatchEntry *batch, uint32_t j, hipStream_t s)
+{
+    k_flip_bit<<<1, 64, 0, s>>>(walks, batch, j);
+    return hipGetLastError();
+}
+
+hipError_t launch_bookkeep(WalkDev *walks, const BatchEntry *batch, uint32_t nb, hipStream_t s)
+{
+    k_bookkeep<<<nb, kBookThreads, 0, s>>>(walks, batch);
+    return hipGetLastError();
+}
+
+}  // namespace psl

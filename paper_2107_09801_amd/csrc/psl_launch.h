@@ -1,0 +1,27 @@
+// psl_launch.h -- host-side launchers of the libpsl kernels (internal).
+#pragma once
+
+#include "psl_device.h"
+
+namespace psl {
+
+hipError_t launch_power_table(double *T, uint32_t n, uint32_t alpha, hipStream_t s);
+hipError_t launch_init_bits(WalkDev *walks, const BatchEntry *batch, const uint32_t *want,
+                            uint32_t nb, uint32_t max_nw, hipStream_t s);
+hipError_t launch_corr(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t max_L,
+                       int only_pending, hipStream_t s);
+hipError_t launch_fitness(WalkDev *walks, const BatchEntry *batch, uint32_t nb, const Tables &tabs,
+                          int mode, hipStream_t s);
+hipError_t launch_eval(const WalkDev *walks, const BatchEntry *batch, const EvalItem *items,
+                       uint32_t n_items, const Tables &tabs, hipStream_t s);
+hipError_t launch_select(WalkDev *walks, const BatchEntry *batch, uint32_t nb, const Tables &tabs,
+                         int pure, void *out, hipStream_t s);
+size_t choice_dev_size();
+void choice_dev_unpack(const void *p, uint32_t *i_best, uint32_t *j_best, double *F_best,
+                       double *F_min, uint32_t *j_psl, int32_t *psl_min, int32_t *psl_k);
+hipError_t launch_apply(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t max_L,
+                        int64_t j_fixed, hipStream_t s);
+hipError_t launch_flip_bit(WalkDev *walks, const BatchEntry *batch, uint32_t j, hipStream_t s);
+hipError_t launch_bookkeep(WalkDev *walks, const BatchEntry *batch, uint32_t nb, hipStream_t s);
+
+}  // namespace psl

@@ -1,0 +1,680 @@
+// psl_runtime.hip -- host runtime of libpsl: contexts, device memory, walks,
+// batches and the C-ABI entry points declared in include/psl.h.
+#include "psl.h"
+#include "psl_device.h"
+#include "psl_launch.h"
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+using namespace psl;
+
+namespace {
+
+// ------------------------------------------------------------ arena
+
+// First-fit allocator over a caller-provided device buffer. Offsets are
+// 256-byte aligned; freed ranges merge with their neighbours.
+class Arena {
+public:
+    void reset(char *base, size_t bytes)
+    {
+        base_ = base;
+        free_.clear();
+        if (base && bytes >= kAlign) free_[0] = bytes & ~(kAlign - 1);
+    }
+    bool active() const { return base_ != nullptr; }
+    void *alloc(size_t bytes)
+    {
+        bytes = (bytes + kAlign - 1) & ~(kAlign - 1);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                size_t off = it->first, len = it->second;
+                free_.erase(it);
+                if (len > bytes) free_[off + bytes] = len - bytes;
+                used_[off] = bytes;
+                return base_ + off;
+            }
+        }
+        return nullptr;
+    }
+    void release(void *p)
+    {
+        size_t off = (size_t)((char *)p - base_);
+        auto u = used_.find(off);
+        if (u == used_.end()) return;
+        size_t len = u->second;
+        used_.erase(u);
+        auto nx = free_.lower_bound(off);
+        if (nx != free_.end() && off + len == nx->first) {
+            len += nx->second;
+            nx = free_.erase(nx);
+        }
+        if (nx != free_.begin()) {
+            auto pv = std::prev(nx);
+            if (pv->first + pv->second == off) {
+                pv->second += len;
+                return;
+            }
+        }
+        free_[off] = len;
+    }
+
+private:
+    static constexpr size_t kAlign = 256;
+    char *base_ = nullptr;
+    std::map<size_t, size_t> free_, used_;
+};
+
+// Host record of a walk slot.
+struct WalkHost {
+    bool active = false;
+    uint32_t L = 0, nw = 0, n_lmt = 0;
+    void *slab = nullptr;
+    size_t slab_bytes = 0;
+};
+
+// A batch as laid out on the device; cached by its walk list.
+struct BatchPlan {
+    std::vector<uint32_t> ids;
+    uint32_t max_L = 0, max_nw = 0;
+    uint32_t n_items = 0;
+    BatchEntry *d_batch = nullptr;
+    EvalItem *d_items = nullptr;
+    double *d_fpart = nullptr, *d_f = nullptr;
+    uint32_t *d_mpart = nullptr;
+    int32_t *d_p = nullptr;
+};
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+
+struct psl_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    Arena arena;
+    std::vector<WalkHost> walks;
+    std::vector<uint32_t> free_slots;
+    WalkDev *d_walks = nullptr;
+    uint32_t walk_cap = 0;
+    double *d_T[PSL_ALPHA_MAX + 1] = {};
+    uint32_t T_n = 0;                 // entries per power table
+    BatchPlan plan;                   // last step batch
+    BatchPlan pure;                   // single-walk plan of psl_eval_neighbourhood
+    void *d_choice = nullptr;
+    std::string err;
+};
+
+namespace {
+
+psl_status fail(psl_ctx *ctx, psl_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    return st;
+}
+
+#define HIP_TRY(ctx, expr)                                                              \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail((ctx), PSL_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));      \
+    } while (0)
+
+psl_status dev_alloc(psl_ctx *ctx, void **p, size_t bytes, bool from_arena)
+{
+    *p = nullptr;
+    if (bytes == 0) bytes = 256;
+    if (from_arena && ctx->arena.active()) {
+        *p = ctx->arena.alloc(bytes);
+        if (!*p) return fail(ctx, PSL_E_NOMEM, "arena exhausted (%zu bytes requested)", bytes);
+        return PSL_OK;
+    }
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(ctx, PSL_E_NOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    }
+    return PSL_OK;
+}
+
+void dev_free(psl_ctx *ctx, void *p, bool from_arena)
+{
+    if (!p) return;
+    if (from_arena && ctx->arena.active()) ctx->arena.release(p);
+    else (void)hipFree(p);
+}
+
+void plan_free(psl_ctx *ctx, BatchPlan &pl)
+{
+    dev_free(ctx, pl.d_batch, false);
+    dev_free(ctx, pl.d_items, false);
+    dev_free(ctx, pl.d_fpart, false);
+    dev_free(ctx, pl.d_mpart, false);
+    dev_free(ctx, pl.d_f, false);
+    dev_free(ctx, pl.d_p, false);
+    pl = BatchPlan();
+}
+
+// Power tables for every exponent, |c| up to L_max + 4.
+psl_status ensure_tables(psl_ctx *ctx, uint32_t L)
+{
+    uint32_t need = L + 8;
+    if (need <= ctx->T_n) return PSL_OK;
+    uint32_t n = std::max<uint32_t>(need, 1024);
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    for (uint32_t a = 1; a <= PSL_ALPHA_MAX; ++a) {
+        dev_free(ctx, ctx->d_T[a], false);
+        ctx->d_T[a] = nullptr;
+    }
+    ctx->T_n = 0;
+    for (uint32_t a = 1; a <= PSL_ALPHA_MAX; ++a) {
+        void *p;
+        psl_status st = dev_alloc(ctx, &p, sizeof(double) * n, false);
+        if (st) return st;
+        ctx->d_T[a] = (double *)p;
+        HIP_TRY(ctx, launch_power_table(ctx->d_T[a], n, a, ctx->stream));
+    }
+    ctx->T_n = n;
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return PSL_OK;
+}
+
+Tables tables_of(const psl_ctx *ctx)
+{
+    Tables t;
+    memset(&t, 0, sizeof t);
+    for (uint32_t a = 1; a <= PSL_ALPHA_MAX; ++a) t.T[a] = ctx->d_T[a];
+    t.n = ctx->T_n;
+    return t;
+}
+
+psl_status ensure_walk_cap(psl_ctx *ctx, uint32_t cap)
+{
+    if (cap <= ctx->walk_cap) return PSL_OK;
+    uint32_t ncap = std::max<uint32_t>(cap, std::max<uint32_t>(64, ctx->walk_cap * 2));
+    void *p;
+    psl_status st = dev_alloc(ctx, &p, sizeof(WalkDev) * ncap, false);
+    if (st) return st;
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->d_walks) {
+        HIP_TRY(ctx, hipMemcpy(p, ctx->d_walks, sizeof(WalkDev) * ctx->walk_cap,
+                               hipMemcpyDeviceToDevice));
+        dev_free(ctx, ctx->d_walks, false);
+    }
+    ctx->d_walks = (WalkDev *)p;
+    ctx->walk_cap = ncap;
+    return PSL_OK;
+}
+
+bool walk_ok(const psl_ctx *ctx, uint32_t id)
+{
+    return id < ctx->walks.size() && ctx->walks[id].active;
+}
+
+// Evaluation shape: candidate tiles of kEvalThreads and k-splits so that a
+// batch offers enough blocks to fill 256 CUs.
+void eval_shape(uint32_t L, uint32_t n_lmt, uint32_t total_tiles, uint32_t *tiles, uint32_t *ksplit)
+{
+    *tiles = (n_lmt + kEvalThreads - 1) / kEvalThreads;
+    const uint32_t target = 4096;
+    uint32_t nchunks = (L - 1 + 31) / 32;
+    uint32_t ks = 1;
+    if (total_tiles < target) ks = (target + total_tiles - 1) / total_tiles;
+    uint32_t ks_max = std::max<uint32_t>(1, nchunks / (kTileK / 32));
+    *ksplit = std::min(ks, ks_max);
+}
+
+// Builds (or reuses) the device layout of a batch: entries, eval work items
+// and scratch. n_fixed / start_fixed != UINT32_MAX: a pure single evaluation.
+psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t n, uint32_t n_fixed,
+                     uint32_t start_fixed)
+{
+    const bool fixed = n_fixed != UINT32_MAX;
+    if (!fixed && pl.d_batch && pl.ids.size() == n && std::equal(ids, ids + n, pl.ids.begin()))
+        return PSL_OK;
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    plan_free(ctx, pl);
+    pl.ids.assign(ids, ids + n);
+    std::vector<uint32_t> n_l(n), tiles(n), ks(n);
+    uint64_t total_tiles = 0;
+    for (uint32_t b = 0; b < n; ++b) {
+        const WalkHost &h = ctx->walks[ids[b]];
+        n_l[b] = fixed ? n_fixed : h.n_lmt;
+        total_tiles += (n_l[b] + kEvalThreads - 1) / kEvalThreads;
+        pl.max_L = std::max(pl.max_L, h.L);
+        pl.max_nw = std::max(pl.max_nw, h.nw);
+    }
+    size_t n_part = 0, n_cand = 0;
+    uint64_t n_items = 0;
+    for (uint32_t b = 0; b < n; ++b) {
+        eval_shape(ctx->walks[ids[b]].L, n_l[b], (uint32_t)std::min<uint64_t>(total_tiles, 1u << 30),
+                   &tiles[b], &ks[b]);
+        n_part += (size_t)ks[b] * n_l[b];
+        n_cand += n_l[b];
+        n_items += (uint64_t)tiles[b] * ks[b];
+    }
+    if (n_items >= (1ull << 31)) return fail(ctx, PSL_E_INVAL, "batch too large (%llu work items)",
+                                             (unsigned long long)n_items);
+    void *p;
+    psl_status st;
+    if ((st = dev_alloc(ctx, &p, sizeof(double) * n_part, false))) return st;
+    pl.d_fpart = (double *)p;
+    if ((st = dev_alloc(ctx, &p, sizeof(uint32_t) * n_part, false))) return st;
+    pl.d_mpart = (uint32_t *)p;
+    if ((st = dev_alloc(ctx, &p, sizeof(double) * n_cand, false))) return st;
+    pl.d_f = (double *)p;
+    if ((st = dev_alloc(ctx, &p, sizeof(int32_t) * n_cand, false))) return st;
+    pl.d_p = (int32_t *)p;
+    std::vector<BatchEntry> be(n);
+    std::vector<EvalItem> items;
+    items.reserve(n_items);
+    size_t op = 0, oc = 0;
+    for (uint32_t b = 0; b < n; ++b) {
+        BatchEntry &e = be[b];
+        memset(&e, 0, sizeof e);
+        e.Fpart = pl.d_fpart + op;
+        e.Mpart = pl.d_mpart + op;
+        e.F = pl.d_f + oc;
+        e.P = pl.d_p + oc;
+        e.slot = ids[b];
+        e.ksplit = ks[b];
+        e.tiles = tiles[b];
+        e.n_lmt = n_l[b];
+        e.start = fixed ? start_fixed : 0;
+        e.fixed = fixed ? 1 : 0;
+        op += (size_t)ks[b] * n_l[b];
+        oc += n_l[b];
+        for (uint32_t t = 0; t < tiles[b]; ++t)
+            for (uint32_t s = 0; s < ks[b]; ++s) items.push_back(EvalItem{b, t, s, 0});
+    }
+    if ((st = dev_alloc(ctx, &p, sizeof(BatchEntry) * n, false))) return st;
+    pl.d_batch = (BatchEntry *)p;
+    if ((st = dev_alloc(ctx, &p, sizeof(EvalItem) * items.size(), false))) return st;
+    pl.d_items = (EvalItem *)p;
+    HIP_TRY(ctx, hipMemcpy(pl.d_batch, be.data(), sizeof(BatchEntry) * n, hipMemcpyHostToDevice));
+    HIP_TRY(ctx, hipMemcpy(pl.d_items, items.data(), sizeof(EvalItem) * items.size(),
+                           hipMemcpyHostToDevice));
+    pl.n_items = (uint32_t)items.size();
+    return PSL_OK;
+}
+
+psl_status check_cfg(psl_ctx *ctx, const psl_walk_cfg *c)
+{
+    if (!c) return fail(ctx, PSL_E_INVAL, "cfg is NULL");
+    if (c->L < 2 || c->L > PSL_L_MAX) return fail(ctx, PSL_E_INVAL, "L=%u out of [2, %u]", c->L, PSL_L_MAX);
+    if (c->alpha1 < 1 || c->alpha1 > PSL_ALPHA_MAX || c->alpha2 < 1 || c->alpha2 > PSL_ALPHA_MAX)
+        return fail(ctx, PSL_E_INVAL, "alpha out of [1, %u]", PSL_ALPHA_MAX);
+    if (c->n_lmt > c->L) return fail(ctx, PSL_E_INVAL, "n_lmt=%u > L=%u", c->n_lmt, c->L);
+    if (c->flip_lmt > c->L || c->flip_lmt > PSL_FLIP_LMT_MAX)
+        return fail(ctx, PSL_E_INVAL, "flip_lmt=%u out of range", c->flip_lmt);
+    if (c->reserved != 0) return fail(ctx, PSL_E_INVAL, "reserved must be 0");
+    return PSL_OK;
+}
+
+psl_status single_plan(psl_ctx *ctx, uint32_t walk, BatchPlan &pl)
+{
+    // a one-walk plan with the walk's own n_lmt (used by psl_apply_flip)
+    return make_plan(ctx, pl, &walk, 1, UINT32_MAX, 0);
+}
+
+}  // namespace
+
+// ================================================================= C-ABI
+
+extern "C" {
+
+const char *psl_version(void) { return "libpsl 0.1 (gfx950)"; }
+
+psl_status psl_ctx_create(int device, void *hip_stream, void *arena, size_t arena_bytes, psl_ctx **out)
+{
+    if (!out) return PSL_E_INVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        (void)hipGetLastError();
+        return PSL_E_INVAL;
+    }
+    psl_ctx *ctx = new psl_ctx();
+    ctx->device = device;
+    if (hipSetDevice(device) != hipSuccess) {
+        delete ctx;
+        return PSL_E_HIP;
+    }
+    if (hip_stream) {
+        ctx->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete ctx;
+            return PSL_E_HIP;
+        }
+        ctx->own_stream = true;
+    }
+    if (arena) ctx->arena.reset((char *)arena, arena_bytes);
+    if (hipMalloc(&ctx->d_choice, 256) != hipSuccess) {
+        if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+        delete ctx;
+        return PSL_E_HIP;
+    }
+    *out = ctx;
+    return PSL_OK;
+}
+
+void psl_ctx_destroy(psl_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto &h : ctx->walks)
+        if (h.active) dev_free(ctx, h.slab, true);
+    plan_free(ctx, ctx->plan);
+    plan_free(ctx, ctx->pure);
+    for (uint32_t a = 1; a <= PSL_ALPHA_MAX; ++a) dev_free(ctx, ctx->d_T[a], false);
+    dev_free(ctx, ctx->d_walks, false);
+    dev_free(ctx, ctx->d_choice, false);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+const char *psl_last_error(const psl_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+psl_status psl_sync(psl_ctx *ctx)
+{
+    if (!ctx) return PSL_E_INVAL;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return PSL_OK;
+}
+
+psl_status psl_init_walks(psl_ctx *ctx, const psl_walk_cfg *cfg, uint32_t n,
+                          const uint64_t *const *init_bits, uint32_t *walk_ids_out)
+{
+    if (!ctx) return PSL_E_INVAL;
+    psl_status st = check_cfg(ctx, cfg);
+    if (st) return st;
+    if (n == 0) return PSL_OK;
+    if (!walk_ids_out) return fail(ctx, PSL_E_INVAL, "walk_ids_out is NULL");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    if ((st = ensure_tables(ctx, cfg->L))) return st;
+
+    const uint32_t L = cfg->L, nw = (L + 63) / 64;
+    const size_t bits_bytes = align_up(sizeof(uint64_t) * nw, 256);
+    const size_t slab_bytes = 3 * bits_bytes + align_up(sizeof(int32_t) * L, 256);
+
+    // slots
+    std::vector<uint32_t> ids(n);
+    for (uint32_t b = 0; b < n; ++b) {
+        if (!ctx->free_slots.empty()) {
+            ids[b] = ctx->free_slots.back();
+            ctx->free_slots.pop_back();
+        } else {
+            ids[b] = (uint32_t)ctx->walks.size();
+            ctx->walks.push_back(WalkHost());
+        }
+    }
+    auto rollback = [&](uint32_t upto) {
+        for (uint32_t b = 0; b < n; ++b) {
+            WalkHost &h = ctx->walks[ids[b]];
+            if (b < upto && h.slab) dev_free(ctx, h.slab, true);
+            h = WalkHost();
+            ctx->free_slots.push_back(ids[b]);
+        }
+    };
+    if ((st = ensure_walk_cap(ctx, (uint32_t)ctx->walks.size()))) {
+        rollback(0);
+        return st;
+    }
+    std::vector<WalkDev> wd(n);
+    std::vector<uint32_t> want(n);
+    for (uint32_t b = 0; b < n; ++b) {
+        void *slab;
+        if ((st = dev_alloc(ctx, &slab, slab_bytes, true))) {
+            rollback(b);
+            return st;
+        }
+        WalkHost &h = ctx->walks[ids[b]];
+        h.active = true;
+        h.L = L;
+        h.nw = nw;
+        h.n_lmt = cfg->n_lmt ? cfg->n_lmt : L;
+        h.slab = slab;
+        h.slab_bytes = slab_bytes;
+        WalkDev &w = wd[b];
+        memset(&w, 0, sizeof w);
+        char *base = (char *)slab;
+        w.pivot = (uint64_t *)base;
+        w.local_best = (uint64_t *)(base + bits_bytes);
+        w.best = (uint64_t *)(base + 2 * bits_bytes);
+        w.C = (int32_t *)(base + 3 * bits_bytes);
+        w.seed = cfg->seed + b;
+        w.L = L;
+        w.nw = nw;
+        w.alpha1 = cfg->alpha1;
+        w.alpha2 = cfg->alpha2;
+        w.alpha = cfg->alpha1;
+        w.n_lmt = h.n_lmt;
+        w.ls_lmt = cfg->ls_lmt;
+        w.flip_lmt = cfg->flip_lmt;
+        w.switch_period = cfg->switch_period;
+        const uint64_t *given = init_bits ? init_bits[b] : nullptr;
+        want[b] = given ? 0u : 1u;
+        if (given) {
+            uint64_t last = given[nw - 1];
+            if ((L & 63u) && (last >> (L & 63u))) {
+                rollback(b + 1);
+                return fail(ctx, PSL_E_INVAL, "init_bits[%u] has bits set at or beyond L", b);
+            }
+            HIP_TRY(ctx, hipMemcpyAsync(w.pivot, given, sizeof(uint64_t) * nw,
+                                        hipMemcpyHostToDevice, ctx->stream));
+        }
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->d_walks + ids[b], &w, sizeof(WalkDev),
+                                    hipMemcpyHostToDevice, ctx->stream));
+    }
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    // init plan: entries only (no eval scratch needed), on a temporary plan
+    BatchPlan tmp;
+    {
+        void *p;
+        if ((st = dev_alloc(ctx, &p, sizeof(BatchEntry) * n, false))) return st;
+        tmp.d_batch = (BatchEntry *)p;
+        std::vector<BatchEntry> be(n);
+        for (uint32_t b = 0; b < n; ++b) {
+            memset(&be[b], 0, sizeof(BatchEntry));
+            be[b].slot = ids[b];
+        }
+        void *dw;
+        if ((st = dev_alloc(ctx, &dw, sizeof(uint32_t) * n, false))) {
+            plan_free(ctx, tmp);
+            return st;
+        }
+        HIP_TRY(ctx, hipMemcpy(tmp.d_batch, be.data(), sizeof(BatchEntry) * n, hipMemcpyHostToDevice));
+        HIP_TRY(ctx, hipMemcpy(dw, want.data(), sizeof(uint32_t) * n, hipMemcpyHostToDevice));
+        const Tables tabs = tables_of(ctx);
+        hipError_t e = launch_init_bits(ctx->d_walks, tmp.d_batch, (const uint32_t *)dw, n, nw, ctx->stream);
+        if (e == hipSuccess) e = launch_corr(ctx->d_walks, tmp.d_batch, n, L, 0, ctx->stream);
+        if (e == hipSuccess) e = launch_fitness(ctx->d_walks, tmp.d_batch, n, tabs, 0, ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        dev_free(ctx, dw, false);
+        plan_free(ctx, tmp);
+        if (e != hipSuccess) return fail(ctx, PSL_E_HIP, "walk init: %s", hipGetErrorString(e));
+    }
+    memcpy(walk_ids_out, ids.data(), sizeof(uint32_t) * n);
+    return PSL_OK;
+}
+
+psl_status psl_free_walks(psl_ctx *ctx, const uint32_t *walk_ids, uint32_t n)
+{
+    if (!ctx || (n && !walk_ids)) return PSL_E_INVAL;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    psl_status st = PSL_OK;
+    for (uint32_t b = 0; b < n; ++b) {
+        uint32_t id = walk_ids[b];
+        if (!walk_ok(ctx, id)) {
+            st = fail(ctx, PSL_E_STATE, "unknown walk %u", id);
+            continue;
+        }
+        WalkHost &h = ctx->walks[id];
+        dev_free(ctx, h.slab, true);
+        h = WalkHost();
+        ctx->free_slots.push_back(id);
+    }
+    plan_free(ctx, ctx->plan);   // cached layouts may name freed walks
+    plan_free(ctx, ctx->pure);
+    return st;
+}
+
+psl_status psl_eval_neighbourhood(psl_ctx *ctx, uint32_t walk, uint32_t start, uint32_t n_lmt,
+                                  double *F_dev, int32_t *psl_dev, psl_choice *out)
+{
+    if (!ctx) return PSL_E_INVAL;
+    if (!walk_ok(ctx, walk)) return fail(ctx, PSL_E_STATE, "unknown walk %u", walk);
+    const WalkHost &h = ctx->walks[walk];
+    if (n_lmt < 1 || n_lmt > h.L || start >= h.L)
+        return fail(ctx, PSL_E_INVAL, "start=%u n_lmt=%u for L=%u", start, n_lmt, h.L);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    psl_status st = make_plan(ctx, ctx->pure, &walk, 1, n_lmt, start);
+    if (st) return st;
+    const Tables tabs = tables_of(ctx);
+    HIP_TRY(ctx, launch_eval(ctx->d_walks, ctx->pure.d_batch, ctx->pure.d_items, ctx->pure.n_items,
+                             tabs, ctx->stream));
+    HIP_TRY(ctx, launch_select(ctx->d_walks, ctx->pure.d_batch, 1, tabs, 1, ctx->d_choice, ctx->stream));
+    if (F_dev)
+        HIP_TRY(ctx, hipMemcpyAsync(F_dev, ctx->pure.d_f, sizeof(double) * n_lmt,
+                                    hipMemcpyDeviceToDevice, ctx->stream));
+    if (psl_dev)
+        HIP_TRY(ctx, hipMemcpyAsync(psl_dev, ctx->pure.d_p, sizeof(int32_t) * n_lmt,
+                                    hipMemcpyDeviceToDevice, ctx->stream));
+    std::vector<char> host(choice_dev_size());
+    HIP_TRY(ctx, hipMemcpyAsync(host.data(), ctx->d_choice, host.size(), hipMemcpyDeviceToHost,
+                                ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    if (out) {
+        memset(out, 0, sizeof *out);
+        choice_dev_unpack(host.data(), &out->i_best, &out->j_best, &out->F_best, &out->F_min,
+                          &out->j_psl, &out->psl_min, &out->psl_k);
+    }
+    return PSL_OK;
+}
+
+psl_status psl_apply_flip(psl_ctx *ctx, uint32_t walk, uint32_t j)
+{
+    if (!ctx) return PSL_E_INVAL;
+    if (!walk_ok(ctx, walk)) return fail(ctx, PSL_E_STATE, "unknown walk %u", walk);
+    const WalkHost &h = ctx->walks[walk];
+    if (j >= h.L) return fail(ctx, PSL_E_INVAL, "j=%u >= L=%u", j, h.L);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    BatchPlan one;
+    void *p;
+    psl_status st = dev_alloc(ctx, &p, sizeof(BatchEntry), false);
+    if (st) return st;
+    one.d_batch = (BatchEntry *)p;
+    BatchEntry e;
+    memset(&e, 0, sizeof e);
+    e.slot = walk;
+    hipError_t r = hipMemcpy(one.d_batch, &e, sizeof e, hipMemcpyHostToDevice);
+    const Tables tabs = tables_of(ctx);
+    if (r == hipSuccess) r = launch_apply(ctx->d_walks, one.d_batch, 1, h.L, (int64_t)j, ctx->stream);
+    if (r == hipSuccess) r = launch_flip_bit(ctx->d_walks, one.d_batch, j, ctx->stream);
+    if (r == hipSuccess) r = launch_fitness(ctx->d_walks, one.d_batch, 1, tabs, 2, ctx->stream);
+    if (r == hipSuccess) r = hipStreamSynchronize(ctx->stream);
+    plan_free(ctx, one);
+    if (r != hipSuccess) return fail(ctx, PSL_E_HIP, "apply_flip: %s", hipGetErrorString(r));
+    return PSL_OK;
+}
+
+psl_status psl_step_batch(psl_ctx *ctx, const uint32_t *walk_ids, uint32_t n, uint32_t steps,
+                          uint32_t flags)
+{
+    if (!ctx) return PSL_E_INVAL;
+    if (n == 0 || steps == 0) return PSL_OK;
+    if (!walk_ids) return fail(ctx, PSL_E_INVAL, "walk_ids is NULL");
+    std::vector<uint32_t> sorted(walk_ids, walk_ids + n);
+    std::sort(sorted.begin(), sorted.end());
+    for (uint32_t b = 0; b < n; ++b) {
+        if (!walk_ok(ctx, sorted[b])) return fail(ctx, PSL_E_STATE, "unknown walk %u", sorted[b]);
+        if (b && sorted[b] == sorted[b - 1]) return fail(ctx, PSL_E_INVAL, "walk %u repeated", sorted[b]);
+    }
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    psl_status st = make_plan(ctx, ctx->plan, walk_ids, n, UINT32_MAX, 0);
+    if (st) return st;
+    const BatchPlan &pl = ctx->plan;
+    const Tables tabs = tables_of(ctx);
+    for (uint32_t s = 0; s < steps; ++s) {
+        HIP_TRY(ctx, launch_eval(ctx->d_walks, pl.d_batch, pl.d_items, pl.n_items, tabs, ctx->stream));
+        HIP_TRY(ctx, launch_select(ctx->d_walks, pl.d_batch, n, tabs, 0, nullptr, ctx->stream));
+        HIP_TRY(ctx, launch_apply(ctx->d_walks, pl.d_batch, n, pl.max_L, -1, ctx->stream));
+        HIP_TRY(ctx, launch_bookkeep(ctx->d_walks, pl.d_batch, n, ctx->stream));
+        HIP_TRY(ctx, launch_corr(ctx->d_walks, pl.d_batch, n, pl.max_L, 1, ctx->stream));
+        HIP_TRY(ctx, launch_fitness(ctx->d_walks, pl.d_batch, n, tabs, 1, ctx->stream));
+    }
+    if (flags & PSL_STEP_BLOCKING) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return PSL_OK;
+}
+
+psl_status psl_read_walk(psl_ctx *ctx, uint32_t walk, psl_walk_state *out, uint64_t *pivot_bits,
+                         uint64_t *local_best_bits, uint64_t *best_bits, int32_t *C)
+{
+    if (!ctx) return PSL_E_INVAL;
+    if (!walk_ok(ctx, walk)) return fail(ctx, PSL_E_STATE, "unknown walk %u", walk);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    WalkDev w;
+    HIP_TRY(ctx, hipMemcpy(&w, ctx->d_walks + walk, sizeof w, hipMemcpyDeviceToHost));
+    if (pivot_bits) HIP_TRY(ctx, hipMemcpy(pivot_bits, w.pivot, 8 * w.nw, hipMemcpyDeviceToHost));
+    if (local_best_bits)
+        HIP_TRY(ctx, hipMemcpy(local_best_bits, w.local_best, 8 * w.nw, hipMemcpyDeviceToHost));
+    if (best_bits) HIP_TRY(ctx, hipMemcpy(best_bits, w.best, 8 * w.nw, hipMemcpyDeviceToHost));
+    if (C) HIP_TRY(ctx, hipMemcpy(C, w.C, sizeof(int32_t) * w.L, hipMemcpyDeviceToHost));
+    if (out) {
+        memset(out, 0, sizeof *out);
+        out->L = w.L;
+        out->alpha1 = w.alpha1;
+        out->alpha2 = w.alpha2;
+        out->alpha = w.alpha;
+        out->n_lmt = w.n_lmt;
+        out->ls_lmt = w.ls_lmt;
+        out->flip_lmt = w.flip_lmt;
+        out->switch_period = w.switch_period;
+        out->seed = w.seed;
+        out->t = w.t;
+        out->q = w.q;
+        out->value_local = w.value_local;
+        out->F_pivot = w.F_pivot;
+        out->psl_pivot = w.psl_pivot;
+        out->psl_best = w.psl_best;
+        out->unimproved = w.unimproved;
+        out->last_k = w.k;
+        out->last_value_step = w.value_step;
+        out->last_start = w.start;
+        out->last_flags = w.flags;
+    }
+    return PSL_OK;
+}
+
+psl_status psl_eval_shape(psl_ctx *ctx, uint32_t L, uint32_t n_lmt, uint32_t n_walks,
+                          uint32_t *cand_tiles, uint32_t *k_splits)
+{
+    (void)ctx;
+    if (L < 2 || L > PSL_L_MAX || n_lmt < 1 || n_lmt > L || n_walks < 1 || !cand_tiles || !k_splits)
+        return PSL_E_INVAL;
+    uint32_t tiles = (n_lmt + kEvalThreads - 1) / kEvalThreads;
+    uint64_t total = (uint64_t)tiles * n_walks;
+    eval_shape(L, n_lmt, (uint32_t)std::min<uint64_t>(total, 1u << 30), cand_tiles, k_splits);
+    return PSL_OK;
+}
+
+}  // extern "C"

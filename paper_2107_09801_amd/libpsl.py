@@ -1,0 +1,229 @@
+"""Thin ctypes binding of libpsl (include/psl.h).
+
+Argument marshalling only: every step of the search runs in the HIP kernels of
+``_build/libpsl.so``. PyTorch is used for device buffers and streams. There is
+no fallback: if the library is missing, importing this module fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "_build", "libpsl.so")
+
+OK, E_INVAL, E_NOMEM, E_HIP, E_STATE, E_AGAIN, E_FULL = 0, -1, -2, -3, -4, -5, -6
+STEP_BLOCKING = 1
+STEP_IMPROVED, STEP_WORSE, STEP_SWITCHED, STEP_PSL_IMPROVED = 1, 2, 4, 8
+L_MAX = 1048575
+
+EXPORTS = ["psl_ctx_create", "psl_ctx_destroy", "psl_last_error", "psl_sync", "psl_init_walks",
+           "psl_free_walks", "psl_eval_neighbourhood", "psl_apply_flip", "psl_step_batch",
+           "psl_read_walk", "psl_eval_shape", "psl_version"]
+
+
+class PslError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libpsl status {status}: {msg}")
+        self.status = status
+
+
+class WalkCfg(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_uint32), ("alpha1", ctypes.c_uint32), ("alpha2", ctypes.c_uint32),
+                ("n_lmt", ctypes.c_uint32), ("ls_lmt", ctypes.c_uint32),
+                ("flip_lmt", ctypes.c_uint32), ("switch_period", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("seed", ctypes.c_uint64)]
+
+
+class Choice(ctypes.Structure):
+    _fields_ = [("j_best", ctypes.c_uint32), ("i_best", ctypes.c_uint32),
+                ("F_best", ctypes.c_double), ("F_min", ctypes.c_double),
+                ("j_psl", ctypes.c_uint32), ("psl_min", ctypes.c_int32),
+                ("psl_k", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+    def as_dict(self) -> dict:
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class WalkState(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_uint32), ("alpha1", ctypes.c_uint32), ("alpha2", ctypes.c_uint32),
+                ("alpha", ctypes.c_uint32), ("n_lmt", ctypes.c_uint32), ("ls_lmt", ctypes.c_uint32),
+                ("flip_lmt", ctypes.c_uint32), ("switch_period", ctypes.c_uint32),
+                ("seed", ctypes.c_uint64), ("t", ctypes.c_uint64), ("q", ctypes.c_uint64),
+                ("value_local", ctypes.c_double), ("F_pivot", ctypes.c_double),
+                ("psl_pivot", ctypes.c_int32), ("psl_best", ctypes.c_int32),
+                ("unimproved", ctypes.c_uint32), ("last_k", ctypes.c_uint32),
+                ("last_value_step", ctypes.c_double), ("last_start", ctypes.c_uint32),
+                ("last_flags", ctypes.c_uint32)]
+
+    def as_dict(self) -> dict:
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The compiled library. Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libpsl is not built ({LIB_PATH} missing); run "
+                          "`python -c 'import __graft_entry__ as g; g.build()'`")
+    L = ctypes.CDLL(LIB_PATH)
+    P, u32, u64, i32, sz = (ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32,
+                            ctypes.c_size_t)
+    sig = {
+        "psl_ctx_create": (i32, [ctypes.c_int, P, P, sz, ctypes.POINTER(P)]),
+        "psl_ctx_destroy": (None, [P]),
+        "psl_last_error": (ctypes.c_char_p, [P]),
+        "psl_sync": (i32, [P]),
+        "psl_init_walks": (i32, [P, ctypes.POINTER(WalkCfg), u32, P, P]),
+        "psl_free_walks": (i32, [P, P, u32]),
+        "psl_eval_neighbourhood": (i32, [P, u32, u32, u32, P, P, ctypes.POINTER(Choice)]),
+        "psl_apply_flip": (i32, [P, u32, u32]),
+        "psl_step_batch": (i32, [P, P, u32, u32, u32]),
+        "psl_read_walk": (i32, [P, u32, ctypes.POINTER(WalkState), P, P, P, P]),
+        "psl_eval_shape": (i32, [P, u32, u32, u32, ctypes.POINTER(u32), ctypes.POINTER(u32)]),
+        "psl_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _ptr(a: np.ndarray) -> int:
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data
+
+
+def n_words(L: int) -> int:
+    return (L + 63) // 64
+
+
+class Context:
+    """A libpsl context on one HIP device (default: torch's current stream)."""
+
+    def __init__(self, device: int = 0, stream=None, arena=None):
+        import torch
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self._stream = stream
+        self._arena = arena          # a torch uint8 tensor kept alive by the context
+        h = ctypes.c_void_p()
+        arena_ptr = arena.data_ptr() if arena is not None else None
+        arena_bytes = arena.numel() * arena.element_size() if arena is not None else 0
+        st = lib().psl_ctx_create(device, ctypes.c_void_p(stream.cuda_stream), arena_ptr,
+                                  arena_bytes, ctypes.byref(h))
+        if st != OK:
+            raise PslError(st, "psl_ctx_create failed")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().psl_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, st: int):
+        if st != OK:
+            raise PslError(st, lib().psl_last_error(self._h).decode())
+
+    def last_error(self) -> str:
+        return lib().psl_last_error(self._h).decode()
+
+    def sync(self):
+        self._check(lib().psl_sync(self._h))
+
+    def init_walks(self, L: int, n: int, seed: int, alpha1: int = 4, alpha2: int = 13,
+                   n_lmt: int = 0, ls_lmt: int = 2000, flip_lmt: int = 10,
+                   switch_period: int = 0, init_bits=None) -> list[int]:
+        cfg = WalkCfg(L=L, alpha1=alpha1, alpha2=alpha2, n_lmt=n_lmt, ls_lmt=ls_lmt,
+                      flip_lmt=flip_lmt, switch_period=switch_period, reserved=0,
+                      seed=seed & (2**64 - 1))
+        ids = np.zeros(n, dtype=np.uint32)
+        arr = None
+        keep = []
+        if init_bits is not None:
+            arr = (ctypes.c_void_p * n)()
+            for w in range(n):
+                b = init_bits[w]
+                if b is None:
+                    arr[w] = None
+                else:
+                    b = np.ascontiguousarray(b, dtype=np.uint64)
+                    keep.append(b)
+                    arr[w] = b.ctypes.data
+        st = lib().psl_init_walks(self._h, ctypes.byref(cfg), n,
+                                  ctypes.cast(arr, ctypes.c_void_p) if arr is not None else None,
+                                  _ptr(ids))
+        self._check(st)
+        return [int(x) for x in ids]
+
+    def free_walks(self, ids):
+        a = np.ascontiguousarray(ids, dtype=np.uint32)
+        self._check(lib().psl_free_walks(self._h, _ptr(a), len(a)))
+
+    def eval_neighbourhood(self, walk: int, start: int, n_lmt: int, F_out=None, psl_out=None):
+        """F_out / psl_out: optional torch device tensors (float64 / int32, n_lmt)."""
+        ch = Choice()
+        fp = F_out.data_ptr() if F_out is not None else None
+        pp = psl_out.data_ptr() if psl_out is not None else None
+        if F_out is not None:
+            assert F_out.is_cuda and F_out.dtype.itemsize == 8 and F_out.numel() >= n_lmt
+        if psl_out is not None:
+            assert psl_out.is_cuda and psl_out.dtype.itemsize == 4 and psl_out.numel() >= n_lmt
+        self._check(lib().psl_eval_neighbourhood(self._h, walk, start, n_lmt, fp, pp,
+                                                 ctypes.byref(ch)))
+        return ch.as_dict()
+
+    def apply_flip(self, walk: int, j: int):
+        self._check(lib().psl_apply_flip(self._h, walk, j))
+
+    def step_batch(self, ids, steps: int, blocking: bool = True):
+        a = np.ascontiguousarray(ids, dtype=np.uint32)
+        self._check(lib().psl_step_batch(self._h, _ptr(a), len(a), steps,
+                                         STEP_BLOCKING if blocking else 0))
+
+    def read_walk(self, walk: int, bits: bool = True, C: bool = True) -> dict:
+        st = WalkState()
+        self._check(lib().psl_read_walk(self._h, walk, ctypes.byref(st), None, None, None, None))
+        d = st.as_dict()
+        if bits or C:
+            nw = n_words(d["L"])
+            piv = np.zeros(nw, np.uint64) if bits else None
+            lb = np.zeros(nw, np.uint64) if bits else None
+            best = np.zeros(nw, np.uint64) if bits else None
+            Cv = np.zeros(d["L"], np.int32) if C else None
+            self._check(lib().psl_read_walk(self._h, walk, None,
+                                            _ptr(piv) if bits else None,
+                                            _ptr(lb) if bits else None,
+                                            _ptr(best) if bits else None,
+                                            _ptr(Cv) if C else None))
+            d.update(pivot=piv, local_best=lb, best=best, C=Cv)
+        return d
+
+    def eval_shape(self, L: int, n_lmt: int, n_walks: int = 1):
+        t, k = ctypes.c_uint32(), ctypes.c_uint32()
+        self._check(lib().psl_eval_shape(self._h, L, n_lmt, n_walks, ctypes.byref(t),
+                                         ctypes.byref(k)))
+        return int(t.value), int(k.value)
+
+
+def version() -> str:
+    return lib().psl_version().decode()

@@ -1,0 +1,76 @@
+"""CPU checks of the C-ABI boundary: the library loads, exports every symbol
+include/psl.h declares, and the binding's structs match the header's layout."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "psl.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"PSL_API[^;(]*?\b(psl_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for want in ("psl_ctx_create", "psl_init_walks", "psl_eval_neighbourhood",
+                 "psl_apply_flip", "psl_step_batch", "psl_read_walk"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2107_09801_amd import libpsl
+    lib = libpsl.lib()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert sorted(libpsl.EXPORTS) == _declared()
+
+
+def test_struct_layouts_match_header(tmp_path):
+    from paper_2107_09801_amd import libpsl
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "psl.h"\n'
+                   'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(psl_walk_cfg),'
+                   ' sizeof(psl_choice), sizeof(psl_walk_state), offsetof(psl_walk_state, t),'
+                   ' offsetof(psl_choice, F_min));return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)],
+                   check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    want = [ctypes.sizeof(libpsl.WalkCfg), ctypes.sizeof(libpsl.Choice),
+            ctypes.sizeof(libpsl.WalkState), libpsl.WalkState.t.offset, libpsl.Choice.F_min.offset]
+    assert got == want
+
+
+def test_version_and_shape_without_gpu():
+    from paper_2107_09801_amd import libpsl
+    assert "gfx950" in libpsl.version()
+    lib = libpsl.lib()
+    t, k = ctypes.c_uint32(), ctypes.c_uint32()
+    assert lib.psl_eval_shape(None, 131071, 131071, 1024, ctypes.byref(t), ctypes.byref(k)) == 0
+    assert t.value == 512 and k.value == 1
+    assert lib.psl_eval_shape(None, 16383, 16383, 1, ctypes.byref(t), ctypes.byref(k)) == 0
+    assert t.value == 64 and k.value >= 8
+    assert lib.psl_eval_shape(None, 1, 1, 1, ctypes.byref(t), ctypes.byref(k)) == libpsl.E_INVAL
+
+
+def test_null_context_is_rejected_without_gpu():
+    from paper_2107_09801_amd import libpsl
+    lib = libpsl.lib()
+    assert lib.psl_sync(None) == libpsl.E_INVAL
+    assert lib.psl_step_batch(None, None, 0, 1, 0) == libpsl.E_INVAL
+    assert lib.psl_last_error(None) == b"null context"
+    out = ctypes.c_void_p()
+    # no device here: creation fails cleanly with an error status
+    st = lib.psl_ctx_create(0, None, None, 0, ctypes.byref(out))
+    if st != libpsl.OK:
+        assert st in (libpsl.E_INVAL, libpsl.E_HIP) and not out.value
+    else:
+        lib.psl_ctx_destroy(out)
+        pytest.skip("a device is present")

@@ -1,0 +1,227 @@
+"""GPU parity of libpsl against the CPU oracle (through the C-ABI).
+
+Bars: C, PSL, bits and moves bit-exact; F within a relative 1e-12; moves on
+steps the oracle flags as ambiguous (a value within 5e-13 relative of a band
+edge) are not compared.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import seeded_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+F_RTOL = 1e-12
+MARGIN = 5e-13
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2107_09801_amd import libpsl
+    assert torch.cuda.is_available()
+    c = libpsl.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(n, dtype):
+    import torch
+    return torch.empty(max(n, 1), dtype=dtype, device="cuda:0")
+
+
+def _oracle_state(L, seed=None, bits=None):
+    s = oracle.rand_pivot(seed, L) if bits is None else si.to_pm1(bits, L)
+    return s, oracle.corr(s)
+
+
+def _rel(a, b):
+    return np.max(np.abs(np.asarray(a) - np.asarray(b)) / np.maximum(np.abs(np.asarray(b)), 1e-300))
+
+
+# ------------------------------------------------------------------- init
+
+@pytest.mark.parametrize("L", [2, 3, 4, 5, 13, 31, 63, 64, 65, 127, 1001, 4097, 16383])
+def test_init_random_pivot_matches_oracle(ctx, L):
+    seed = si.BASE_SEED + L
+    (w,) = ctx.init_walks(L, 1, seed, alpha1=4, alpha2=13)
+    g = ctx.read_walk(w)
+    s, C = _oracle_state(L, seed)
+    assert np.array_equal(g["pivot"], oracle.seq_to_bits(s))
+    assert np.array_equal(g["C"], C)
+    assert np.array_equal(g["local_best"], g["pivot"]) and np.array_equal(g["best"], g["pivot"])
+    assert g["psl_best"] == oracle.psl(C) == g["psl_pivot"]
+    F = oracle.fitness(C, 4)
+    assert abs(g["value_local"] - F) <= F_RTOL * F and g["F_pivot"] == g["value_local"]
+    assert g["alpha"] == 4 and g["t"] == 0 and g["unimproved"] == 0
+    ctx.free_walks([w])
+
+
+@pytest.mark.parametrize("kind", ["plus", "alternating", "biased", "random"])
+@pytest.mark.parametrize("L", [2, 70, 3001])
+def test_init_given_bits(ctx, L, kind):
+    bits = {"plus": si.all_plus_bits(L), "alternating": si.alternating_bits(L),
+            "biased": si.biased_bits(L, 5, 0.2), "random": si.random_bits(L, 6)}[kind]
+    (w,) = ctx.init_walks(L, 1, 1, init_bits=[bits])
+    g = ctx.read_walk(w)
+    assert np.array_equal(g["pivot"], bits)
+    assert np.array_equal(g["C"], oracle.corr(si.to_pm1(bits, L)))
+    ctx.free_walks([w])
+
+
+# -------------------------------------------------------- neighbourhood
+
+EVAL_CASES = []
+for L in [2, 3, 4, 5, 13, 31, 63, 64, 65, 127, 1001, 4097, 16383]:
+    for start in sorted({0, L - 1, L // 2}):
+        for n_lmt in sorted({1, min(7, L), min(256, L), L}):
+            EVAL_CASES.append((L, start, n_lmt))
+
+
+@pytest.mark.parametrize("L,start,n_lmt", EVAL_CASES)
+def test_eval_neighbourhood_random_pivot(ctx, L, start, n_lmt):
+    import torch
+    seed = 77 + L
+    alpha = 4 if (L + start) % 2 else 13
+    (w,) = ctx.init_walks(L, 1, seed, alpha1=alpha, alpha2=4)
+    F, P = _dev(n_lmt, torch.float64), _dev(n_lmt, torch.int32)
+    ch = ctx.eval_neighbourhood(w, start, n_lmt, F, P)
+    s, C = _oracle_state(L, seed)
+    Fo, Po = oracle.eval_neighbourhood(s, C, alpha, start, n_lmt, nthreads=8)
+    Fg, Pg = F.cpu().numpy()[:n_lmt], P.cpu().numpy()[:n_lmt]
+    assert np.array_equal(Pg, Po)
+    assert _rel(Fg, Fo) <= F_RTOL
+    oc = oracle.select(Fo, Po, margin=MARGIN)
+    assert ch["psl_min"] == oc.psl_min and ch["j_psl"] == (start + oc.i_psl + 1) % L
+    if not oc.flags & oracle.AMBIG_ARGMIN:
+        assert ch["i_best"] == oc.i_best
+        assert ch["j_best"] == (start + oc.i_best + 1) % L
+    assert ch["F_best"] == Fg[ch["i_best"]] and ch["psl_k"] == Pg[ch["i_best"]]
+    assert ch["F_min"] == Fg.min()
+    # pure: the walk is unchanged
+    g = ctx.read_walk(w)
+    assert np.array_equal(g["C"], C) and g["t"] == 0
+    ctx.free_walks([w])
+
+
+@pytest.mark.parametrize("kind", ["plus", "alternating", "biased"])
+@pytest.mark.parametrize("alpha", [1, 2, 4, 10, 13, 16])
+@pytest.mark.parametrize("L", [2, 33, 300, 2049])
+def test_eval_structured_pivots(ctx, L, alpha, kind):
+    import torch
+    bits = {"plus": si.all_plus_bits(L), "alternating": si.alternating_bits(L),
+            "biased": si.biased_bits(L, 11, 0.25)}[kind]
+    (w,) = ctx.init_walks(L, 1, 1, alpha1=alpha, alpha2=4, init_bits=[bits])
+    start = (L * 7) // 11
+    F, P = _dev(L, torch.float64), _dev(L, torch.int32)
+    ctx.eval_neighbourhood(w, start, L, F, P)
+    s, C = _oracle_state(L, bits=bits)
+    Fo, Po = oracle.eval_neighbourhood(s, C, alpha, start, L, nthreads=8)
+    assert np.array_equal(P.cpu().numpy()[:L], Po)
+    assert _rel(F.cpu().numpy()[:L], Fo) <= F_RTOL
+    ctx.free_walks([w])
+
+
+# ------------------------------------------------------------------ flip
+
+@pytest.mark.parametrize("L", [2, 5, 64, 65, 1000, 16383])
+def test_apply_flip_matches_formula(ctx, L):
+    seed = 5 + L
+    (w,) = ctx.init_walks(L, 1, seed, alpha1=13, alpha2=4)
+    s, C = _oracle_state(L, seed)
+    for j in sorted({0, L - 1, L // 3, (2 * L) // 3}):
+        ctx.apply_flip(w, j)
+        C = oracle.flip_corr_formula(s, C, j)
+        s[j] = -s[j]
+        g = ctx.read_walk(w)
+        assert np.array_equal(g["C"], C)
+        assert np.array_equal(g["pivot"], oracle.seq_to_bits(s))
+        F = oracle.fitness(C, 13)
+        assert abs(g["F_pivot"] - F) <= F_RTOL * F and g["psl_pivot"] == oracle.psl(C)
+    assert np.array_equal(C, oracle.corr(s))
+    ctx.free_walks([w])
+
+
+# ------------------------------------------------------------ trajectories
+
+def _lockstep(ctx, w, ow, steps, check_every=1):
+    compared = 0
+    for t in range(steps):
+        ctx.step_batch([w], 1)
+        tr = ow.step()
+        if tr["flags"] & (oracle.AMBIG_ARGMIN | oracle.AMBIG_COMPARE):
+            break
+        g = ctx.read_walk(w, bits=(t % check_every == 0), C=(t % check_every == 0))
+        assert g["last_start"] == tr["start"], t
+        assert g["last_k"] == tr["k"], t
+        assert abs(g["last_value_step"] - tr["value_step"]) <= F_RTOL * tr["value_step"], t
+        assert g["psl_best"] == tr["psl_best"] and g["alpha"] == tr["alpha"], t
+        assert g["unimproved"] == tr["unimproved"] and g["t"] == t + 1, t
+        assert abs(g["value_local"] - tr["value_local"]) <= F_RTOL * tr["value_local"], t
+        if t % check_every == 0:
+            o = ow.read()
+            assert np.array_equal(g["pivot"], o["pivot"]), t
+            assert np.array_equal(g["C"], o["C"]), t
+            assert np.array_equal(g["local_best"], o["local_best"]), t
+            assert np.array_equal(g["best"], o["best"]), t
+        compared += 1
+    return compared
+
+
+@pytest.mark.parametrize("L,n_lmt,period,ls,steps", [
+    (257, 257, 5, 2000, 60), (1001, 1001, 50, 2000, 120), (1001, 300, 0, 3, 80),
+    (64, 64, 0, 2, 100), (2, 2, 3, 2000, 20), (5, 3, 0, 1, 40), (4097, 4097, 50, 2000, 60)])
+def test_step_lockstep_with_oracle(ctx, L, n_lmt, period, ls, steps):
+    seed = si.BASE_SEED + 3 * L + period
+    flip = min(10, L)
+    (w,) = ctx.init_walks(L, 1, seed, alpha1=4, alpha2=13, n_lmt=n_lmt, ls_lmt=ls,
+                          flip_lmt=flip, switch_period=period)
+    ow = oracle.Walk(oracle.WalkConfig(L=L, seed=seed, alpha1=4, alpha2=13, n_lmt=n_lmt,
+                                       ls_lmt=ls, flip_lmt=flip, switch_period=period),
+                     margin=MARGIN, nthreads=8)
+    n = _lockstep(ctx, w, ow, steps)
+    assert n >= steps * 0.9
+    ctx.free_walks([w])
+
+
+def test_batch_matches_single_walks(ctx):
+    Ls = [2, 65, 257, 1001, 3000]
+    solo, mixed = [], []
+    for L in Ls:
+        solo += ctx.init_walks(L, 1, 99 + L, n_lmt=0, switch_period=7, flip_lmt=min(3, L))
+    for L in Ls:
+        mixed += ctx.init_walks(L, 1, 99 + L, n_lmt=0, switch_period=7, flip_lmt=min(3, L))
+    for w in solo:
+        ctx.step_batch([w], 15)
+    ctx.step_batch(mixed, 15)
+    for a, b in zip(solo, mixed):
+        ga, gb = ctx.read_walk(a), ctx.read_walk(b)
+        for key in ("pivot", "C", "best", "local_best"):
+            assert np.array_equal(ga[key], gb[key]), key
+        for key in ("psl_best", "alpha", "unimproved", "t", "q", "last_k"):
+            assert ga[key] == gb[key], key
+        assert abs(ga["value_local"] - gb["value_local"]) <= F_RTOL * ga["value_local"]
+    ctx.free_walks(solo + mixed)
+
+
+def test_invalid_arguments(ctx):
+    from paper_2107_09801_amd import libpsl
+    with pytest.raises(libpsl.PslError):
+        ctx.init_walks(1, 1, 0)
+    with pytest.raises(libpsl.PslError):
+        ctx.init_walks(10, 1, 0, n_lmt=11)
+    with pytest.raises(libpsl.PslError):
+        ctx.init_walks(10, 1, 0, alpha1=0)
+    (w,) = ctx.init_walks(10, 1, 0)
+    with pytest.raises(libpsl.PslError):
+        ctx.eval_neighbourhood(w, 10, 5)
+    with pytest.raises(libpsl.PslError):
+        ctx.eval_neighbourhood(w, 0, 11)
+    with pytest.raises(libpsl.PslError):
+        ctx.apply_flip(w, 10)
+    with pytest.raises(libpsl.PslError):
+        ctx.step_batch([w, w], 1)
+    ctx.free_walks([w])
+    with pytest.raises(libpsl.PslError):
+        ctx.read_walk(w)

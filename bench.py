@@ -1,0 +1,178 @@
+"""Throughput of the two-phase PSL search's hot path on one MI355X.
+
+Workload (default): the batched uniform configuration, 1024 independent walks
+at L = 2^17 - 1 = 131071, each a random +-1 start from its own seed, full
+neighbourhood (N_lmt = L), alpha_1 = 4 / alpha_2 = 13, a phase switch every 50
+steps with FLIP_lmt = 10, FP64 fitness. One bench step is one iteration of the
+loop of Algorithm 1 on every walk of the batch: neighbourhood evaluation,
+selection, the O(L) flip, bookkeeping and (when due) the switch.
+
+Prints one JSON line: flip-evals/s (whole job) with the roofline of the
+dominant kernel (the neighbourhood evaluation, timed with HIP events on its
+own stream) and the CPU oracle timed on a bounded sample of the same work.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 64 lanes x 2.4 GHz of 32-bit / non-packed FP64 VALU issue.
+PEAK_LANE_OPS = 256 * 64 * 2.4e9
+# Algorithmic VALU lane-ops per C_k-update: form C' (1), fold |C'| into the
+# running max (1), select T(|C'|) (1), one FP64 add (1).
+OPS_PER_UPDATE = 4
+# Paper, Table 4 (A100 SXM4, N_lmt = 6912, one walk, alpha 4/10): context only.
+PAPER_A100_NSE = {16383: 4678451, 32767: 2577101, 65535: 1258873, 131071: 638043,
+                  262143: 326148, 524287: 167861, 1048575: 85062}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--walks", type=int, default=1024)
+    ap.add_argument("--L", type=int, default=131071)
+    ap.add_argument("--n-lmt", type=int, default=0, help="0 = full neighbourhood")
+    ap.add_argument("--switch-period", type=int, default=50)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target duration of the oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="before the run, one device-to-device copy of this many MiB "
+                         "(a known-size kernel to scale profiler byte counters)")
+    return ap.parse_args()
+
+
+def cpu_baseline(L: int, n_lmt: int, alpha: int, target_s: float, max_walks: int) -> dict:
+    """The oracle's Neighborhood for the first step of walks 0, 1, ... (their
+    own seeds and starts), in scan-order slices, until about target_s seconds
+    have passed. Only the evaluation is timed (the O(L^2) setup of each
+    walk's C is not)."""
+    import oracle
+    import seeded_inputs as si
+    threads = max(1, min(16, os.cpu_count() or 1))
+    done, walks, el = 0, 0, 0.0
+    chunk = max(threads * 4, 64)
+    for w in range(max_walks):
+        seed = si.walk_seed(w)
+        s = oracle.rand_pivot(seed, L)
+        C = oracle.corr(s)
+        start = oracle.draw(seed, 1 << 60) % L
+        pos = 0
+        while pos < n_lmt and el < target_s:
+            m = min(chunk, n_lmt - pos)
+            t0 = time.perf_counter()
+            oracle.eval_neighbourhood(s, C, alpha, (start + pos) % L, m, nthreads=threads)
+            el += time.perf_counter() - t0
+            pos += m
+            chunk = min(chunk * 2, n_lmt)
+        done += pos
+        walks += 1
+        if el >= target_s:
+            break
+    return {"value": done / el, "unit": "flip-evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{done} neighbour evaluations from the first step of {walks} walk(s) "
+                      f"at L={L} (alpha={alpha}), {el:.1f} s of evaluation, OpenMP over "
+                      f"candidates on {threads} threads",
+            "C_k_updates_per_s": done * (L - 1) / el}
+
+
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    import seeded_inputs as si
+    from paper_2107_09801_amd import libpsl
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    L, nw = args.L, args.walks
+    n_lmt = args.n_lmt or L
+    a2 = si.alpha2_for(L)
+    ctx = libpsl.Context(0)
+    ids = ctx.init_walks(L, nw, si.BASE_SEED, alpha1=4, alpha2=a2, n_lmt=n_lmt,
+                         ls_lmt=2000, flip_lmt=10, switch_period=args.switch_period)
+    log(f"{nw} walks of L={L} initialised")
+    if args.calib_copy_mb:
+        n = args.calib_copy_mb << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log(f"calibration copy of {args.calib_copy_mb} MiB done")
+    if args.warmup:
+        ctx.step_batch(ids, args.warmup, blocking=True)
+        log(f"{args.warmup} warmup step(s) done")
+    torch.cuda.synchronize()
+    ctx.timing_enable(True)
+    t0 = time.perf_counter()
+    ctx.step_batch(ids, args.steps, blocking=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    tm = ctx.timing_read()
+    log(f"{args.steps} timed step(s) in {el:.2f} s")
+    ctx.timing_enable(False)
+    st = ctx.read_walk(ids[0], bits=False, C=False)
+
+    evals_per_step = nw * n_lmt
+    updates_per_step = evals_per_step * (L - 1)
+    value = evals_per_step * args.steps / el
+    eval_avg_s = tm["eval_ms"] / max(1, tm["eval_launches"]) / 1e3
+    achieved = OPS_PER_UPDATE * updates_per_step / eval_avg_s
+    tiles, ks = ctx.eval_shape(L, n_lmt, nw)
+
+    out = {
+        "metric": "flip-evals/s",
+        "value": value,
+        "unit": "flip-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"batched uniform: {nw} walks, L={L}, N_lmt={n_lmt}, "
+                               f"alpha 4/{a2}, switch every {args.switch_period} steps, "
+                               f"FLIP_lmt 10, FP64 F",
+                   "walks": nw, "L": L, "n_lmt": n_lmt, "alpha1": 4, "alpha2": a2,
+                   "switch_period": args.switch_period, "eval_tiles": tiles,
+                   "eval_ksplit": ks},
+        "C_k_updates_per_s": value * (L - 1),
+        "eval_kernel": {"avg_ms": eval_avg_s * 1e3, "launches": tm["eval_launches"],
+                        "updates_per_s": updates_per_step / eval_avg_s,
+                        "rest_of_step_avg_ms": tm["rest_ms"] / max(1, tm["steps"])},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                     "unit": "Tlane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": None},
+        "walk0_after": {"t": st["t"], "psl_best": st["psl_best"], "alpha": st["alpha"]},
+    }
+    if L in PAPER_A100_NSE:
+        out["paper_context"] = {"A100_flip_evals_per_s": PAPER_A100_NSE[L],
+                                "note": "paper Table 4: one walk, N_lmt=6912, alpha 4/10"}
+    ctx.close()
+    if not args.no_cpu_baseline:
+        log("timing the oracle on a sample")
+        out["cpu_baseline"] = cpu_baseline(L, n_lmt, 4, args.cpu_seconds, nw)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -199,6 +199,23 @@ PSL_API psl_status psl_read_walk(psl_ctx *ctx, uint32_t walk, psl_walk_state *ou
                          uint64_t *pivot_bits, uint64_t *local_best_bits,
                          uint64_t *best_bits, int32_t *C);
 
+/* ------------------------------------------------------------ timing */
+
+/* Per-kernel device time of psl_step_batch, measured with HIP events recorded
+ * on the context's stream around each launch. */
+typedef struct {
+    double   eval_ms;        /* total time of the neighbourhood-evaluation kernel */
+    uint64_t eval_launches;
+    double   rest_ms;        /* total time of the rest of each step               */
+    uint64_t steps;
+} psl_timing;
+
+/* on != 0: start recording (counters reset); on == 0: stop. */
+PSL_API psl_status psl_timing_enable(psl_ctx *ctx, int on);
+
+/* Wait for the recorded work and report the totals since psl_timing_enable. */
+PSL_API psl_status psl_timing_read(psl_ctx *ctx, psl_timing *out);
+
 /* ----------------------------------------------------- introspection */
 
 /* Number of device work items, blocks per item and k-splits the evaluation

@@ -12,10 +12,17 @@ namespace psl {
 
 constexpr double kTau = 1e-12;       // relative band of the best-neighbour and
                                      // improvement comparisons
-constexpr int kEvalWaves = 4;        // wavefronts per evaluation block
+constexpr int kEvalWaves = 8;        // wavefronts per evaluation block
 constexpr int kEvalThreads = 64 * kEvalWaves;
 constexpr int kTileK = 256;          // shifts staged per LDS tile
+constexpr int kChunks = kTileK / 32; // 32-shift windows per tile
+constexpr int kPairs = kTileK / 2;   // shift pairs per tile
 constexpr int kRowStride = 5;        // T(|C_k + 2m|), m = -2..2
+
+// Guard words (64-bit) before and after the pivot's bits: every bit window
+// the evaluation reads (j +- k for j < L, k < L, plus one window) lies inside
+// [-(nw+2)*64, (2*nw+2)*64), and the guards read as zero.
+__host__ __device__ constexpr uint32_t guard_words(uint32_t nw) { return nw + 2; }
 
 struct WalkDev {
     // storage (slab)
@@ -62,6 +69,8 @@ struct BatchEntry {
     uint32_t *Mpart;        // ksplit * n_lmt partial maxima of hi32(T(|C'|))
     double *F;              // n_lmt: F per scan index
     int32_t *P;             // n_lmt: PSL per scan index
+    double *S0;             // L+1: S0[k] = sum_{k<=k'<L} T(|C_k'|), S0[L] = 0
+    uint32_t *M0;           // L+1: max_{k<=k'<L} hi32(T(|C_k'|)), M0[L] = 0
     uint32_t slot;          // walk slot
     uint32_t ksplit;        // k-splits of the evaluation
     uint32_t tiles;         // candidate tiles of the evaluation

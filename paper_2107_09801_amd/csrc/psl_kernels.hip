@@ -6,14 +6,8 @@
 // (Section 3, with Eq. (2)), and from the C'_k the kernel accumulates
 // F_j = sum_k |C'_k|^alpha (Eq. (5)) and PSL_j = max_k |C'_k| (Eq. (3)).
 //
-// Layout: one lane per candidate, 64 candidates per wavefront, four
-// wavefronts per block. Shifts are swept in tiles of kTileK; for each shift of
-// a tile the block stages in LDS the five values T(|C_k + 2m|), m = -2..2, that
-// C'_k can take, so the per-(j,k) work is: two bits of the packed sequence
-// (already XOR-ed with s_j), a row index, one LDS read, one FP64 add and one
-// 32-bit max of its high word. Bits come from 32-shift windows of the packed sequence, one funnel
-// shift per window, and the in-bounds masks of the window decide (uniformly
-// per wavefront, almost always) which of four branch-free forms applies.
+// Layout: one lane per candidate, 64 candidates per wavefront, eight
+// wavefronts per block; shifts are swept in LDS-staged tiles (see k_eval).
 #include "psl_device.h"
 #include "psl_launch.h"
 
@@ -211,12 +205,110 @@ __global__ __launch_bounds__(kFitThreads) void k_fitness(WalkDev *walks, const B
 
 // --------------------------------------------- neighbourhood evaluation
 
+// Suffix sums of the pivot's terms, S0[k] = sum_{k<=k'<L} T(|C_k'|) and
+// M0[k] = max hi32(T(|C_k'|)) over the same range, S0[L] = M0[L] = 0. A
+// candidate j leaves every C_k with k > max(j, L-1-j) unchanged (both
+// neighbours of the flipped element are out of bounds), so that part of its
+// F and PSL is read from these arrays. One block per walk, fixed blocking,
+// Neumaier sums.
+constexpr int kSufThreads = 1024;
+__global__ __launch_bounds__(kSufThreads) void k_suffix(const WalkDev *walks, const BatchEntry *batch,
+                                                        Tables tabs)
+{
+    const BatchEntry be = batch[blockIdx.x];
+    const WalkDev &w = walks[be.slot];
+    const int L = (int)w.L;
+    const double *T = tabs.T[w.alpha];
+    const int nk = L - 1;
+    const int seg = (nk + kSufThreads - 1) / kSufThreads;
+    const int lo = 1 + (int)threadIdx.x * seg;
+    const int hi = min(L, lo + seg);
+    double s = 0.0, c = 0.0;
+    uint32_t m = 0;
+    for (int k = hi - 1; k >= lo; --k) {
+        const int32_t x = w.C[k];
+        const double v = T[x < 0 ? -x : x];
+        nsum_add(s, c, v);
+        m = max(m, hi32(v));
+    }
+    __shared__ double s_sum[kSufThreads], s_comp[kSufThreads];
+    __shared__ uint32_t s_max[kSufThreads];
+    s_sum[threadIdx.x] = s;
+    s_comp[threadIdx.x] = c;
+    s_max[threadIdx.x] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // exclusive suffix scan over the segments, right to left
+        double rs = 0.0, rc = 0.0;
+        uint32_t rm = 0;
+        for (int i = kSufThreads - 1; i >= 0; --i) {
+            const double ts = s_sum[i], tc = s_comp[i];
+            const uint32_t tm = s_max[i];
+            s_sum[i] = rs;
+            s_comp[i] = rc;
+            s_max[i] = rm;
+            nsum_add(rs, rc, ts);
+            rc += tc;
+            rm = max(rm, tm);
+        }
+        be.S0[L] = 0.0;
+        be.M0[L] = 0;
+    }
+    __syncthreads();
+    s = s_sum[threadIdx.x];
+    c = s_comp[threadIdx.x];
+    m = s_max[threadIdx.x];
+    for (int k = hi - 1; k >= lo; --k) {
+        const int32_t x = w.C[k];
+        const double v = T[x < 0 ? -x : x];
+        nsum_add(s, c, v);
+        m = max(m, hi32(v));
+        be.S0[k] = s + c;
+        be.M0[k] = m;
+    }
+}
+
+struct PairEntry {
+    double sum;       // T(|C'_k|) + T(|C'_{k+1}|)
+    uint32_t maxhi;   // max of their hi32
+    uint32_t pad;
+};
+
+// Wave-wide minimum / maximum of an int (result uniform).
+__device__ __forceinline__ int wave_min(int v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+__device__ __forceinline__ int wave_max(int v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+// Neighborhood of Algorithm 1 for one (walk, 512 candidates, k-range) item.
+//
+// Per 256-shift tile the block stages (i) per shift the five values
+// T(|C_k + 2m|), m = -2..2, and (ii) per pair of shifts (k, k+1) two lookup
+// tables of pre-added terms with the 32-bit maximum of their high words: 16
+// entries indexed by the four bits (xr_k, xr_k+1, xl_k, xl_k+1) for shifts
+// where both neighbours of j exist (C' = C + 4(xr + xl - 1)), and 4 entries
+// indexed by (x_k, x_k+1) for shifts where one neighbour exists
+// (C' = C + 2(2x - 1)); x = 1 when s_j times that neighbour is -1. A lane
+// takes a 32-shift window of each side's bits with one funnel shift, and
+// per pair of shifts does two bit-field extracts, one LDS entry read, one
+// FP64 add and one 32-bit max. Which form a 32-shift window uses is decided
+// once per wavefront from the lanes' bounds. Shifts past every lane's
+// max(j, L-1-j) come from the suffix arrays.
 __global__ __launch_bounds__(kEvalThreads) void k_eval(const WalkDev *__restrict__ walks,
                                                        const BatchEntry *__restrict__ batch,
                                                        const EvalItem *__restrict__ items,
                                                        Tables tabs)
 {
     __shared__ double rows[kTileK * kRowStride];
+    __shared__ PairEntry both[kPairs * 16];
+    __shared__ PairEntry one[kPairs * 4];
+    __shared__ int s_kend[kEvalWaves];
 
     const EvalItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
     const BatchEntry be = batch[it.walk];
@@ -227,7 +319,6 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(const WalkDev *__restrict
     const double *__restrict__ T = tabs.T[w.alpha];
     const int32_t *__restrict__ C = w.C;
     const uint32_t *__restrict__ w32 = reinterpret_cast<const uint32_t *>(w.pivot);
-    const int nw32 = (int)w.nw * 2;
 
     // shifts of this split, in whole 32-shift chunks from k = 1
     const int nchunks = (L - 1 + 31) / 32;
@@ -244,12 +335,37 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(const WalkDev *__restrict
     const int j = (int)((start + 1u + ii) % (uint32_t)L);
     const uint32_t SJ = ((w32[j >> 5] >> (j & 31)) & 1u) ? 0xFFFFFFFFu : 0u;
 
+    // in-bounds limits: right neighbour for k <= jr, left for k <= jl
+    const int jl = j, jr = L - 1 - j;
+    const int jl_min = wave_min(jl), jl_max = wave_max(jl);
+    const int jr_min = wave_min(jr), jr_max = wave_max(jr);
+    const int both_max = min(jl_min, jr_min);             // all lanes: both exist
+    // first shift at which every lane of the wave has neither neighbour,
+    // rounded up to a chunk start; explicit shifts end there
+    const int k_none = max(jl_max, jr_max) + 1;
+    const int k_wend = min(k_hi, 1 + 32 * ((k_none - 1 + 31) / 32));
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) s_kend[wave] = k_wend;
+    __syncthreads();
+    int k_bend = s_kend[0];
+    for (int x = 1; x < kEvalWaves; ++x) k_bend = max(k_bend, s_kend[x]);
+
+    // bit-window cursors: right window of chunk c starts at element
+    // j + 1 + 32c (word (j+1)/32 + c, shift (j+1)%32); left window ends at
+    // element j - 1 - 32c and starts at j - 32 - 32c (word j/32 - 1 - c,
+    // shift j%32)
+    const uint32_t sh_r = (uint32_t)(j + 1) & 31u;
+    const uint32_t sh_l = (uint32_t)j & 31u;
+    const int wr0 = (j + 1) >> 5;
+    const int wl0 = (j >> 5) - 1;
+
     double sum = 0.0, comp = 0.0;
     uint32_t mx = 0;
-    for (int kt = k_lo; kt < k_hi; kt += kTileK) {
-        const int kt_end = min(k_hi, kt + kTileK);
+    for (int kt = k_lo; kt < k_bend; kt += kTileK) {
+        const int kt_end = min(k_bend, kt + kTileK);
+        const int nt = kt_end - kt;
         __syncthreads();
-        for (int t = threadIdx.x; t < kt_end - kt; t += kEvalThreads) {
+        for (int t = threadIdx.x; t < nt; t += kEvalThreads) {
             const int c = C[kt + t];
 #pragma unroll
             for (int m = 0; m < kRowStride; ++m) {
@@ -259,67 +375,92 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(const WalkDev *__restrict
             }
         }
         __syncthreads();
-
-        double acc = 0.0;
-        for (int k0 = kt; k0 < kt_end; k0 += 32) {
-            const int tcount = min(32, kt_end - k0);
-            const double *rb = rows + (k0 - kt) * kRowStride;
-            // xr bit t: s_j s_{j+k0+t} == -1; xl bit 31-t: s_j s_{j-k0-t} == -1
-            const uint32_t XR = bits32_at(w32, nw32, j + k0) ^ SJ;
-            const uint32_t XL = bits32_at(w32, nw32, j - k0 - 31) ^ SJ;
-            const int nR = L - j - k0;   // shifts k0.. with j+k < L
-            const int nL = j - k0 + 1;   // shifts k0.. with j-k >= 0
-            const uint32_t VR = nR >= 32 ? ~0u : (nR <= 0 ? 0u : ((1u << nR) - 1u));
-            const uint32_t VL = nL >= 32 ? ~0u : (nL <= 0 ? 0u : (~0u << (32 - nL)));
-            const bool full = tcount == 32;
-            if (full && __all(VR == ~0u && VL == ~0u)) {
-                // both neighbours in bounds: C' = C + 4(xr + xl - 1)
-#pragma unroll
-                for (int t = 0; t < 32; ++t) {
-                    const uint32_t xr = (XR >> t) & 1u;
-                    const uint32_t xl = (XL >> (31 - t)) & 1u;
-                    const double v = rb[t * kRowStride + 2 * (xr + xl)];
-                    acc += v;
-                    mx = max(mx, hi32(v));
-                }
-            } else if (full && __all(VR == ~0u && VL == 0u)) {
-                // right neighbour only: C' = C + 2(2 xr - 1)
-#pragma unroll
-                for (int t = 0; t < 32; ++t) {
-                    const uint32_t xr = (XR >> t) & 1u;
-                    const double v = rb[t * kRowStride + 1 + 2 * xr];
-                    acc += v;
-                    mx = max(mx, hi32(v));
-                }
-            } else if (full && __all(VR == 0u && VL == ~0u)) {
-                // left neighbour only
-#pragma unroll
-                for (int t = 0; t < 32; ++t) {
-                    const uint32_t xl = (XL >> (31 - t)) & 1u;
-                    const double v = rb[t * kRowStride + 1 + 2 * xl];
-                    acc += v;
-                    mx = max(mx, hi32(v));
-                }
-            } else if (full && __all(VR == 0u && VL == 0u)) {
-                // neither: C' = C
-#pragma unroll
-                for (int t = 0; t < 32; ++t) {
-                    const double v = rb[t * kRowStride + 2];
-                    acc += v;
-                    mx = max(mx, hi32(v));
+        for (int e = threadIdx.x; e < kPairs * 20; e += kEvalThreads) {
+            if (e < kPairs * 16) {
+                const int p = e >> 4, x = e & 15;
+                if (2 * p + 1 < nt) {
+                    const double a = rows[(2 * p) * kRowStride + 2 * ((x & 1) + ((x >> 2) & 1))];
+                    const double b = rows[(2 * p + 1) * kRowStride + 2 * (((x >> 1) & 1) + ((x >> 3) & 1))];
+                    PairEntry pe;
+                    pe.sum = a + b;
+                    pe.maxhi = max(hi32(a), hi32(b));
+                    pe.pad = 0;
+                    both[e] = pe;
                 }
             } else {
-                for (int t = 0; t < tcount; ++t) {
-                    int m = 2;
-                    if ((VR >> t) & 1u) m += ((XR >> t) & 1u) ? 1 : -1;
-                    if ((VL >> (31 - t)) & 1u) m += ((XL >> (31 - t)) & 1u) ? 1 : -1;
-                    const double v = rb[t * kRowStride + m];
-                    acc += v;
-                    mx = max(mx, hi32(v));
+                const int f = e - kPairs * 16;
+                const int p = f >> 2, x = f & 3;
+                if (2 * p + 1 < nt) {
+                    const double a = rows[(2 * p) * kRowStride + 1 + 2 * (x & 1)];
+                    const double b = rows[(2 * p + 1) * kRowStride + 1 + 2 * ((x >> 1) & 1)];
+                    PairEntry pe;
+                    pe.sum = a + b;
+                    pe.maxhi = max(hi32(a), hi32(b));
+                    pe.pad = 0;
+                    one[f] = pe;
+                }
+            }
+        }
+        __syncthreads();
+
+        double acc = 0.0;
+        const int cbase = (kt - 1) >> 5;                   // chunk index of kt
+#pragma unroll
+        for (int cc = 0; cc < kChunks; ++cc) {
+            const int k0 = kt + 32 * cc;
+            if (k0 < k_wend) {
+                const int c = cbase + cc;
+                const uint32_t XR = __builtin_amdgcn_alignbit(w32[wr0 + c + 1], w32[wr0 + c], sh_r) ^ SJ;
+                const uint32_t XL = __builtin_bitreverse32(
+                    __builtin_amdgcn_alignbit(w32[wl0 - c + 1], w32[wl0 - c], sh_l) ^ SJ);
+                const int tcount = min(32, kt_end - k0);
+                const PairEntry *bp = both + (16 * 16) * cc;
+                const PairEntry *op = one + (16 * 4) * cc;
+                if (tcount == 32 && k0 + 31 <= both_max) {
+#pragma unroll
+                    for (int p = 0; p < 16; ++p) {
+                        const uint32_t x = __builtin_amdgcn_ubfe(XR, 2 * p, 2) |
+                                           (__builtin_amdgcn_ubfe(XL, 2 * p, 2) << 2);
+                        const PairEntry *pe = bp + 16 * p + x;
+                        acc += pe->sum;
+                        mx = max(mx, pe->maxhi);
+                    }
+                } else if (tcount == 32 && k0 + 31 <= jr_min && k0 > jl_max) {
+#pragma unroll
+                    for (int p = 0; p < 16; ++p) {
+                        const PairEntry *pe = op + 4 * p + __builtin_amdgcn_ubfe(XR, 2 * p, 2);
+                        acc += pe->sum;
+                        mx = max(mx, pe->maxhi);
+                    }
+                } else if (tcount == 32 && k0 + 31 <= jl_min && k0 > jr_max) {
+#pragma unroll
+                    for (int p = 0; p < 16; ++p) {
+                        const PairEntry *pe = op + 4 * p + __builtin_amdgcn_ubfe(XL, 2 * p, 2);
+                        acc += pe->sum;
+                        mx = max(mx, pe->maxhi);
+                    }
+                } else {
+                    // mixed bounds or a partial chunk: per shift
+                    const double *rb = rows + (32 * cc) * kRowStride;
+                    for (int t = 0; t < tcount; ++t) {
+                        const int k = k0 + t;
+                        int m = 2;
+                        if (k <= jr) m += ((XR >> t) & 1u) ? 1 : -1;
+                        if (k <= jl) m += ((XL >> t) & 1u) ? 1 : -1;
+                        const double v = rb[t * kRowStride + m];
+                        acc += v;
+                        mx = max(mx, hi32(v));
+                    }
                 }
             }
         }
         nsum_add(sum, comp, acc);
+    }
+    // shifts where no lane of the wave has a neighbour in bounds
+    const int kn = max(k_lo, k_wend);
+    if (kn < k_hi) {
+        nsum_add(sum, comp, be.S0[kn] - be.S0[k_hi]);
+        mx = max(mx, be.M0[kn]);
     }
     if (active) {
         const size_t o = (size_t)it.ks * n_lmt + i;
@@ -587,6 +728,13 @@ hipError_t launch_eval(const WalkDev *walks, const BatchEntry *batch, const Eval
                        uint32_t n_items, const Tables &tabs, hipStream_t s)
 {
     k_eval<<<n_items, kEvalThreads, 0, s>>>(walks, batch, items, tabs);
+    return hipGetLastError();
+}
+
+hipError_t launch_suffix(const WalkDev *walks, const BatchEntry *batch, uint32_t nb, const Tables &tabs,
+                         hipStream_t s)
+{
+    k_suffix<<<nb, kSufThreads, 0, s>>>(walks, batch, tabs);
     return hipGetLastError();
 }
 

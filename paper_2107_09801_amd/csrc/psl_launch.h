@@ -14,6 +14,8 @@ hipError_t launch_fitness(WalkDev *walks, const BatchEntry *batch, uint32_t nb, 
                           int mode, hipStream_t s);
 hipError_t launch_eval(const WalkDev *walks, const BatchEntry *batch, const EvalItem *items,
                        uint32_t n_items, const Tables &tabs, hipStream_t s);
+hipError_t launch_suffix(const WalkDev *walks, const BatchEntry *batch, uint32_t nb, const Tables &tabs,
+                         hipStream_t s);
 hipError_t launch_select(WalkDev *walks, const BatchEntry *batch, uint32_t nb, const Tables &tabs,
                          int pure, void *out, hipStream_t s);
 size_t choice_dev_size();

@@ -87,8 +87,8 @@ struct BatchPlan {
     uint32_t n_items = 0;
     BatchEntry *d_batch = nullptr;
     EvalItem *d_items = nullptr;
-    double *d_fpart = nullptr, *d_f = nullptr;
-    uint32_t *d_mpart = nullptr;
+    double *d_fpart = nullptr, *d_f = nullptr, *d_s0 = nullptr;
+    uint32_t *d_mpart = nullptr, *d_m0 = nullptr;
     int32_t *d_p = nullptr;
 };
 
@@ -111,6 +111,11 @@ struct psl_ctx {
     BatchPlan pure;                   // single-walk plan of psl_eval_neighbourhood
     void *d_choice = nullptr;
     std::string err;
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev;       // 3 per recorded step: eval start, eval end, step end
+    double eval_ms = 0.0, rest_ms = 0.0;
+    uint64_t eval_launches = 0, steps_timed = 0;
 };
 
 namespace {
@@ -158,6 +163,37 @@ void dev_free(psl_ctx *ctx, void *p, bool from_arena)
     else (void)hipFree(p);
 }
 
+void timing_drop(psl_ctx *ctx)
+{
+    for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+    ctx->ev.clear();
+}
+
+// Folds recorded events into the totals (the stream must be idle).
+psl_status timing_collect(psl_ctx *ctx)
+{
+    for (size_t i = 0; i + 2 < ctx->ev.size(); i += 3) {
+        float a = 0.f, b = 0.f;
+        HIP_TRY(ctx, hipEventElapsedTime(&a, ctx->ev[i], ctx->ev[i + 1]));
+        HIP_TRY(ctx, hipEventElapsedTime(&b, ctx->ev[i + 1], ctx->ev[i + 2]));
+        ctx->eval_ms += a;
+        ctx->rest_ms += b;
+        ctx->eval_launches += 1;
+        ctx->steps_timed += 1;
+    }
+    timing_drop(ctx);
+    return PSL_OK;
+}
+
+psl_status timing_mark(psl_ctx *ctx)
+{
+    hipEvent_t e;
+    HIP_TRY(ctx, hipEventCreate(&e));
+    ctx->ev.push_back(e);
+    HIP_TRY(ctx, hipEventRecord(e, ctx->stream));
+    return PSL_OK;
+}
+
 void plan_free(psl_ctx *ctx, BatchPlan &pl)
 {
     dev_free(ctx, pl.d_batch, false);
@@ -166,6 +202,8 @@ void plan_free(psl_ctx *ctx, BatchPlan &pl)
     dev_free(ctx, pl.d_mpart, false);
     dev_free(ctx, pl.d_f, false);
     dev_free(ctx, pl.d_p, false);
+    dev_free(ctx, pl.d_s0, false);
+    dev_free(ctx, pl.d_m0, false);
     pl = BatchPlan();
 }
 
@@ -258,13 +296,14 @@ psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t 
         pl.max_L = std::max(pl.max_L, h.L);
         pl.max_nw = std::max(pl.max_nw, h.nw);
     }
-    size_t n_part = 0, n_cand = 0;
+    size_t n_part = 0, n_cand = 0, n_suf = 0;
     uint64_t n_items = 0;
     for (uint32_t b = 0; b < n; ++b) {
         eval_shape(ctx->walks[ids[b]].L, n_l[b], (uint32_t)std::min<uint64_t>(total_tiles, 1u << 30),
                    &tiles[b], &ks[b]);
         n_part += (size_t)ks[b] * n_l[b];
         n_cand += n_l[b];
+        n_suf += ctx->walks[ids[b]].L + 1;
         n_items += (uint64_t)tiles[b] * ks[b];
     }
     if (n_items >= (1ull << 31)) return fail(ctx, PSL_E_INVAL, "batch too large (%llu work items)",
@@ -279,10 +318,14 @@ psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t 
     pl.d_f = (double *)p;
     if ((st = dev_alloc(ctx, &p, sizeof(int32_t) * n_cand, false))) return st;
     pl.d_p = (int32_t *)p;
+    if ((st = dev_alloc(ctx, &p, sizeof(double) * n_suf, false))) return st;
+    pl.d_s0 = (double *)p;
+    if ((st = dev_alloc(ctx, &p, sizeof(uint32_t) * n_suf, false))) return st;
+    pl.d_m0 = (uint32_t *)p;
     std::vector<BatchEntry> be(n);
     std::vector<EvalItem> items;
     items.reserve(n_items);
-    size_t op = 0, oc = 0;
+    size_t op = 0, oc = 0, os = 0;
     for (uint32_t b = 0; b < n; ++b) {
         BatchEntry &e = be[b];
         memset(&e, 0, sizeof e);
@@ -290,6 +333,9 @@ psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t 
         e.Mpart = pl.d_mpart + op;
         e.F = pl.d_f + oc;
         e.P = pl.d_p + oc;
+        e.S0 = pl.d_s0 + os;
+        e.M0 = pl.d_m0 + os;
+        os += ctx->walks[ids[b]].L + 1;
         e.slot = ids[b];
         e.ksplit = ks[b];
         e.tiles = tiles[b];
@@ -385,6 +431,7 @@ void psl_ctx_destroy(psl_ctx *ctx)
     for (uint32_t a = 1; a <= PSL_ALPHA_MAX; ++a) dev_free(ctx, ctx->d_T[a], false);
     dev_free(ctx, ctx->d_walks, false);
     dev_free(ctx, ctx->d_choice, false);
+    timing_drop(ctx);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }
@@ -412,7 +459,9 @@ psl_status psl_init_walks(psl_ctx *ctx, const psl_walk_cfg *cfg, uint32_t n,
 
     const uint32_t L = cfg->L, nw = (L + 63) / 64;
     const size_t bits_bytes = align_up(sizeof(uint64_t) * nw, 256);
-    const size_t slab_bytes = 3 * bits_bytes + align_up(sizeof(int32_t) * L, 256);
+    const size_t guard_bytes = sizeof(uint64_t) * guard_words(nw);
+    const size_t pivot_bytes = align_up(2 * guard_bytes + sizeof(uint64_t) * nw, 256);
+    const size_t slab_bytes = pivot_bytes + 2 * bits_bytes + align_up(sizeof(int32_t) * L, 256);
 
     // slots
     std::vector<uint32_t> ids(n);
@@ -455,10 +504,12 @@ psl_status psl_init_walks(psl_ctx *ctx, const psl_walk_cfg *cfg, uint32_t n,
         WalkDev &w = wd[b];
         memset(&w, 0, sizeof w);
         char *base = (char *)slab;
-        w.pivot = (uint64_t *)base;
-        w.local_best = (uint64_t *)(base + bits_bytes);
-        w.best = (uint64_t *)(base + 2 * bits_bytes);
-        w.C = (int32_t *)(base + 3 * bits_bytes);
+        // the pivot sits between zeroed guard words (see guard_words)
+        HIP_TRY(ctx, hipMemsetAsync(slab, 0, slab_bytes, ctx->stream));
+        w.pivot = (uint64_t *)(base + guard_bytes);
+        w.local_best = (uint64_t *)(base + pivot_bytes);
+        w.best = (uint64_t *)(base + pivot_bytes + bits_bytes);
+        w.C = (int32_t *)(base + pivot_bytes + 2 * bits_bytes);
         w.seed = cfg->seed + b;
         w.L = L;
         w.nw = nw;
@@ -549,6 +600,7 @@ psl_status psl_eval_neighbourhood(psl_ctx *ctx, uint32_t walk, uint32_t start, u
     psl_status st = make_plan(ctx, ctx->pure, &walk, 1, n_lmt, start);
     if (st) return st;
     const Tables tabs = tables_of(ctx);
+    HIP_TRY(ctx, launch_suffix(ctx->d_walks, ctx->pure.d_batch, 1, tabs, ctx->stream));
     HIP_TRY(ctx, launch_eval(ctx->d_walks, ctx->pure.d_batch, ctx->pure.d_items, ctx->pure.n_items,
                              tabs, ctx->stream));
     HIP_TRY(ctx, launch_select(ctx->d_walks, ctx->pure.d_batch, 1, tabs, 1, ctx->d_choice, ctx->stream));
@@ -614,12 +666,16 @@ psl_status psl_step_batch(psl_ctx *ctx, const uint32_t *walk_ids, uint32_t n, ui
     const BatchPlan &pl = ctx->plan;
     const Tables tabs = tables_of(ctx);
     for (uint32_t s = 0; s < steps; ++s) {
+        HIP_TRY(ctx, launch_suffix(ctx->d_walks, pl.d_batch, n, tabs, ctx->stream));
+        if (ctx->timing && (st = timing_mark(ctx))) return st;
         HIP_TRY(ctx, launch_eval(ctx->d_walks, pl.d_batch, pl.d_items, pl.n_items, tabs, ctx->stream));
+        if (ctx->timing && (st = timing_mark(ctx))) return st;
         HIP_TRY(ctx, launch_select(ctx->d_walks, pl.d_batch, n, tabs, 0, nullptr, ctx->stream));
         HIP_TRY(ctx, launch_apply(ctx->d_walks, pl.d_batch, n, pl.max_L, -1, ctx->stream));
         HIP_TRY(ctx, launch_bookkeep(ctx->d_walks, pl.d_batch, n, ctx->stream));
         HIP_TRY(ctx, launch_corr(ctx->d_walks, pl.d_batch, n, pl.max_L, 1, ctx->stream));
         HIP_TRY(ctx, launch_fitness(ctx->d_walks, pl.d_batch, n, tabs, 1, ctx->stream));
+        if (ctx->timing && (st = timing_mark(ctx))) return st;
     }
     if (flags & PSL_STEP_BLOCKING) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     return PSL_OK;
@@ -662,6 +718,32 @@ psl_status psl_read_walk(psl_ctx *ctx, uint32_t walk, psl_walk_state *out, uint6
         out->last_start = w.start;
         out->last_flags = w.flags;
     }
+    return PSL_OK;
+}
+
+psl_status psl_timing_enable(psl_ctx *ctx, int on)
+{
+    if (!ctx) return PSL_E_INVAL;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    timing_drop(ctx);
+    ctx->timing = on != 0;
+    ctx->eval_ms = ctx->rest_ms = 0.0;
+    ctx->eval_launches = ctx->steps_timed = 0;
+    return PSL_OK;
+}
+
+psl_status psl_timing_read(psl_ctx *ctx, psl_timing *out)
+{
+    if (!ctx || !out) return PSL_E_INVAL;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    psl_status st = timing_collect(ctx);
+    if (st) return st;
+    out->eval_ms = ctx->eval_ms;
+    out->eval_launches = ctx->eval_launches;
+    out->rest_ms = ctx->rest_ms;
+    out->steps = ctx->steps_timed;
     return PSL_OK;
 }
 

@@ -21,7 +21,8 @@ L_MAX = 1048575
 
 EXPORTS = ["psl_ctx_create", "psl_ctx_destroy", "psl_last_error", "psl_sync", "psl_init_walks",
            "psl_free_walks", "psl_eval_neighbourhood", "psl_apply_flip", "psl_step_batch",
-           "psl_read_walk", "psl_eval_shape", "psl_version"]
+           "psl_read_walk", "psl_eval_shape", "psl_version", "psl_timing_enable",
+           "psl_timing_read"]
 
 
 class PslError(RuntimeError):
@@ -62,6 +63,14 @@ class WalkState(ctypes.Structure):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
+class Timing(ctypes.Structure):
+    _fields_ = [("eval_ms", ctypes.c_double), ("eval_launches", ctypes.c_uint64),
+                ("rest_ms", ctypes.c_double), ("steps", ctypes.c_uint64)]
+
+    def as_dict(self) -> dict:
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -89,6 +98,8 @@ def lib() -> ctypes.CDLL:
         "psl_read_walk": (i32, [P, u32, ctypes.POINTER(WalkState), P, P, P, P]),
         "psl_eval_shape": (i32, [P, u32, u32, u32, ctypes.POINTER(u32), ctypes.POINTER(u32)]),
         "psl_version": (ctypes.c_char_p, []),
+        "psl_timing_enable": (i32, [P, ctypes.c_int]),
+        "psl_timing_read": (i32, [P, ctypes.POINTER(Timing)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -151,8 +162,10 @@ class Context:
         self._check(lib().psl_sync(self._h))
 
     def init_walks(self, L: int, n: int, seed: int, alpha1: int = 4, alpha2: int = 13,
-                   n_lmt: int = 0, ls_lmt: int = 2000, flip_lmt: int = 10,
+                   n_lmt: int = 0, ls_lmt: int = 2000, flip_lmt: int | None = None,
                    switch_period: int = 0, init_bits=None) -> list[int]:
+        if flip_lmt is None:          # the paper's FLIP_lmt = 10, capped by L
+            flip_lmt = min(10, L)
         cfg = WalkCfg(L=L, alpha1=alpha1, alpha2=alpha2, n_lmt=n_lmt, ls_lmt=ls_lmt,
                       flip_lmt=flip_lmt, switch_period=switch_period, reserved=0,
                       seed=seed & (2**64 - 1))
@@ -223,6 +236,15 @@ class Context:
         self._check(lib().psl_eval_shape(self._h, L, n_lmt, n_walks, ctypes.byref(t),
                                          ctypes.byref(k)))
         return int(t.value), int(k.value)
+
+
+    def timing_enable(self, on: bool = True):
+        self._check(lib().psl_timing_enable(self._h, 1 if on else 0))
+
+    def timing_read(self) -> dict:
+        t = Timing()
+        self._check(lib().psl_timing_read(self._h, ctypes.byref(t)))
+        return t.as_dict()
 
 
 def version() -> str:

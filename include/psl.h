@@ -216,6 +216,17 @@ PSL_API psl_status psl_timing_enable(psl_ctx *ctx, int on);
 /* Wait for the recorded work and report the totals since psl_timing_enable. */
 PSL_API psl_status psl_timing_read(psl_ctx *ctx, psl_timing *out);
 
+/* ----------------------------------------------------------- options */
+
+/* PSL_OPT_NEAR_LIMIT: largest near-peak shift list (shifts k with |C_k|
+ * within 8 of the pivot's PSL, the only ones that can set a neighbour's PSL)
+ * for which the evaluation computes each neighbour's PSL from that list;
+ * above it the PSL maximum is kept in the main loop. -1 (default): automatic,
+ * min(4096, max(64, L/16)); 0 forces the in-loop maximum. Both give the same
+ * results. Errors: PSL_E_INVAL for an unknown option or value. */
+#define PSL_OPT_NEAR_LIMIT 1
+PSL_API psl_status psl_set_option(psl_ctx *ctx, int option, int64_t value);
+
 /* ----------------------------------------------------- introspection */
 
 /* Number of device work items, blocks per item and k-splits the evaluation

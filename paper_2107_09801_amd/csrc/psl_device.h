@@ -18,6 +18,7 @@ constexpr int kTileK = 256;          // shifts staged per LDS tile
 constexpr int kChunks = kTileK / 32; // 32-shift windows per tile
 constexpr int kPairs = kTileK / 2;   // shift pairs per tile
 constexpr int kRowStride = 5;        // T(|C_k + 2m|), m = -2..2
+constexpr int kNearCap = 4096;       // capacity of the near-peak shift list
 
 // Guard words (64-bit) before and after the pivot's bits: every bit window
 // the evaluation reads (j +- k for j < L, k < L, plus one window) lies inside
@@ -71,12 +72,15 @@ struct BatchEntry {
     int32_t *P;             // n_lmt: PSL per scan index
     double *S0;             // L+1: S0[k] = sum_{k<=k'<L} T(|C_k'|), S0[L] = 0
     uint32_t *M0;           // L+1: max_{k<=k'<L} hi32(T(|C_k'|)), M0[L] = 0
+    uint32_t *near;         // 1 + kNearCap: count, then the near-peak shifts
     uint32_t slot;          // walk slot
     uint32_t ksplit;        // k-splits of the evaluation
     uint32_t tiles;         // candidate tiles of the evaluation
     uint32_t n_lmt;         // candidates evaluated
     uint32_t start;         // start, when fixed by the caller
     uint32_t fixed;         // 1: start and n_lmt come from this entry
+    uint32_t near_lim;      // largest near-peak list handled sparsely
+    uint32_t pad;
 };
 
 // Eval work item: walk position in the batch, candidate tile, k-split index.

@@ -205,12 +205,17 @@ __global__ __launch_bounds__(kFitThreads) void k_fitness(WalkDev *walks, const B
 
 // --------------------------------------------- neighbourhood evaluation
 
-// Suffix sums of the pivot's terms, S0[k] = sum_{k<=k'<L} T(|C_k'|) and
-// M0[k] = max hi32(T(|C_k'|)) over the same range, S0[L] = M0[L] = 0. A
-// candidate j leaves every C_k with k > max(j, L-1-j) unchanged (both
-// neighbours of the flipped element are out of bounds), so that part of its
-// F and PSL is read from these arrays. One block per walk, fixed blocking,
-// Neumaier sums.
+// Per walk and step, from the pivot's C:
+//  * suffix sums S0[k] = sum_{k<=k'<L} T(|C_k'|) and M0[k] = max hi32(T(|C_k'|))
+//    over the same range (S0[L] = M0[L] = 0). A candidate j leaves every C_k
+//    with k > max(j, L-1-j) unchanged (both neighbours of the flipped element
+//    are out of bounds), so that part of its F (and PSL) is read from them;
+//  * the near-peak shift list: with P the pivot's PSL, every neighbour has
+//    PSL >= P - 4 (one flip moves each C_k by at most 4), and a shift with
+//    |C_k| <= P - 9 reaches at most P - 5, so a neighbour's PSL is the maximum
+//    of |C'_k| over the shifts with |C_k| >= P - 8 alone. near[0] = count,
+//    near[1..] = those shifts (any order), while the count fits kNearCap.
+// One block per walk, fixed blocking, Neumaier sums.
 constexpr int kSufThreads = 1024;
 __global__ __launch_bounds__(kSufThreads) void k_suffix(const WalkDev *walks, const BatchEntry *batch,
                                                         Tables tabs)
@@ -225,22 +230,29 @@ __global__ __launch_bounds__(kSufThreads) void k_suffix(const WalkDev *walks, co
     const int hi = min(L, lo + seg);
     double s = 0.0, c = 0.0;
     uint32_t m = 0;
+    int peak = 0;
     for (int k = hi - 1; k >= lo; --k) {
         const int32_t x = w.C[k];
-        const double v = T[x < 0 ? -x : x];
+        const int a = x < 0 ? -x : x;
+        const double v = T[a];
         nsum_add(s, c, v);
         m = max(m, hi32(v));
+        peak = max(peak, a);
     }
     __shared__ double s_sum[kSufThreads], s_comp[kSufThreads];
     __shared__ uint32_t s_max[kSufThreads];
+    __shared__ int s_peak[kSufThreads];
+    __shared__ uint32_t s_cnt;
     s_sum[threadIdx.x] = s;
     s_comp[threadIdx.x] = c;
     s_max[threadIdx.x] = m;
+    s_peak[threadIdx.x] = peak;
     __syncthreads();
     if (threadIdx.x == 0) {
         // exclusive suffix scan over the segments, right to left
         double rs = 0.0, rc = 0.0;
         uint32_t rm = 0;
+        int pk = 0;
         for (int i = kSufThreads - 1; i >= 0; --i) {
             const double ts = s_sum[i], tc = s_comp[i];
             const uint32_t tm = s_max[i];
@@ -250,29 +262,34 @@ __global__ __launch_bounds__(kSufThreads) void k_suffix(const WalkDev *walks, co
             nsum_add(rs, rc, ts);
             rc += tc;
             rm = max(rm, tm);
+            pk = max(pk, s_peak[i]);
         }
         be.S0[L] = 0.0;
         be.M0[L] = 0;
+        s_peak[0] = pk;
+        s_cnt = 0;
     }
     __syncthreads();
+    const int cut = s_peak[0] - 8;
     s = s_sum[threadIdx.x];
     c = s_comp[threadIdx.x];
     m = s_max[threadIdx.x];
     for (int k = hi - 1; k >= lo; --k) {
         const int32_t x = w.C[k];
-        const double v = T[x < 0 ? -x : x];
+        const int a = x < 0 ? -x : x;
+        const double v = T[a];
         nsum_add(s, c, v);
         m = max(m, hi32(v));
         be.S0[k] = s + c;
         be.M0[k] = m;
+        if (a >= cut) {
+            const uint32_t q = atomicAdd(&s_cnt, 1u);
+            if (q < (uint32_t)kNearCap) be.near[1 + q] = (uint32_t)k;
+        }
     }
+    __syncthreads();
+    if (threadIdx.x == 0) be.near[0] = s_cnt;
 }
-
-struct PairEntry {
-    double sum;       // T(|C'_k|) + T(|C'_{k+1}|)
-    uint32_t maxhi;   // max of their hi32
-    uint32_t pad;
-};
 
 // Wave-wide minimum / maximum of an int (result uniform).
 __device__ __forceinline__ int wave_min(int v)
@@ -286,69 +303,53 @@ __device__ __forceinline__ int wave_max(int v)
     return __builtin_amdgcn_readfirstlane(v);
 }
 
-// Neighborhood of Algorithm 1 for one (walk, 512 candidates, k-range) item.
-//
-// Per 256-shift tile the block stages (i) per shift the five values
-// T(|C_k + 2m|), m = -2..2, and (ii) per pair of shifts (k, k+1) two lookup
-// tables of pre-added terms with the 32-bit maximum of their high words: 16
-// entries indexed by the four bits (xr_k, xr_k+1, xl_k, xl_k+1) for shifts
-// where both neighbours of j exist (C' = C + 4(xr + xl - 1)), and 4 entries
-// indexed by (x_k, x_k+1) for shifts where one neighbour exists
-// (C' = C + 2(2x - 1)); x = 1 when s_j times that neighbour is -1. A lane
-// takes a 32-shift window of each side's bits with one funnel shift, and
-// per pair of shifts does two bit-field extracts, one LDS entry read, one
-// FP64 add and one 32-bit max. Which form a 32-shift window uses is decided
-// once per wavefront from the lanes' bounds. Shifts past every lane's
-// max(j, L-1-j) come from the suffix arrays.
-__global__ __launch_bounds__(kEvalThreads) void k_eval(const WalkDev *__restrict__ walks,
-                                                       const BatchEntry *__restrict__ batch,
-                                                       const EvalItem *__restrict__ items,
-                                                       Tables tabs)
-{
-    __shared__ double rows[kTileK * kRowStride];
-    __shared__ PairEntry both[kPairs * 16];
-    __shared__ PairEntry one[kPairs * 4];
-    __shared__ int s_kend[kEvalWaves];
+// LDS of one evaluation block.
+struct EvalLds {
+    double rows[kTileK * kRowStride];   // T(|C_k + 2m|), m = -2..2, per shift
+    double both[kPairs * 16];           // pair sums, both neighbours
+    double one[kPairs * 4];             // pair sums, one neighbour
+    uint32_t both_max[kPairs * 16];     // max hi32 of the pair (dense PSL only)
+    uint32_t one_max[kPairs * 4];
+    int kend[kEvalWaves];
+    int bmax[kEvalWaves];
+    int omax[kEvalWaves];
+};
 
-    const EvalItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
-    const BatchEntry be = batch[it.walk];
-    const WalkDev &w = walks[be.slot];
+// The sweep of one item. kMax: keep the PSL maximum in the main loop (dense
+// form); otherwise the near-peak pass supplies it.
+template <bool kMax>
+__device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const BatchEntry &be,
+                                           const EvalItem &it, const double *__restrict__ T,
+                                           uint32_t n_lmt, int j, uint32_t SJ, int k_lo, int k_hi,
+                                           double &sum, double &comp, uint32_t &mx)
+{
     const int L = (int)w.L;
-    const uint32_t n_lmt = be.fixed ? be.n_lmt : w.n_lmt;
-    const uint32_t start = be.fixed ? be.start : step_start(w);
-    const double *__restrict__ T = tabs.T[w.alpha];
     const int32_t *__restrict__ C = w.C;
     const uint32_t *__restrict__ w32 = reinterpret_cast<const uint32_t *>(w.pivot);
-
-    // shifts of this split, in whole 32-shift chunks from k = 1
-    const int nchunks = (L - 1 + 31) / 32;
-    const int per = (nchunks + (int)be.ksplit - 1) / (int)be.ksplit;
-    const int c_lo = (int)it.ks * per;
-    const int c_hi = min(nchunks, c_lo + per);
-    const int k_lo = 1 + 32 * c_lo;
-    const int k_hi = min(L, 1 + 32 * c_hi);
-
-    // this lane's candidate; inactive lanes keep a valid j and store nothing
-    const uint32_t i = it.tile * kEvalThreads + threadIdx.x;
-    const bool active = i < n_lmt;
-    const uint32_t ii = active ? i : n_lmt - 1;
-    const int j = (int)((start + 1u + ii) % (uint32_t)L);
-    const uint32_t SJ = ((w32[j >> 5] >> (j & 31)) & 1u) ? 0xFFFFFFFFu : 0u;
 
     // in-bounds limits: right neighbour for k <= jr, left for k <= jl
     const int jl = j, jr = L - 1 - j;
     const int jl_min = wave_min(jl), jl_max = wave_max(jl);
     const int jr_min = wave_min(jr), jr_max = wave_max(jr);
     const int both_max = min(jl_min, jr_min);             // all lanes: both exist
+    const int one_max = max(jl_min, jr_min);              // all lanes: one exists
     // first shift at which every lane of the wave has neither neighbour,
     // rounded up to a chunk start; explicit shifts end there
     const int k_none = max(jl_max, jr_max) + 1;
     const int k_wend = min(k_hi, 1 + 32 * ((k_none - 1 + 31) / 32));
     const int wave = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) s_kend[wave] = k_wend;
+    if ((threadIdx.x & 63) == 0) {
+        sh.kend[wave] = k_wend;
+        sh.bmax[wave] = both_max;
+        sh.omax[wave] = one_max;
+    }
     __syncthreads();
-    int k_bend = s_kend[0];
-    for (int x = 1; x < kEvalWaves; ++x) k_bend = max(k_bend, s_kend[x]);
+    int k_bend = sh.kend[0], b_bmax = sh.bmax[0], b_omax = sh.omax[0];
+    for (int x = 1; x < kEvalWaves; ++x) {
+        k_bend = max(k_bend, sh.kend[x]);
+        b_bmax = max(b_bmax, sh.bmax[x]);
+        b_omax = max(b_omax, sh.omax[x]);
+    }
 
     // bit-window cursors: right window of chunk c starts at element
     // j + 1 + 32c (word (j+1)/32 + c, shift (j+1)%32); left window ends at
@@ -359,11 +360,12 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(const WalkDev *__restrict
     const int wr0 = (j + 1) >> 5;
     const int wl0 = (j >> 5) - 1;
 
-    double sum = 0.0, comp = 0.0;
-    uint32_t mx = 0;
     for (int kt = k_lo; kt < k_bend; kt += kTileK) {
         const int kt_end = min(k_bend, kt + kTileK);
         const int nt = kt_end - kt;
+        // which pair tables some wave of the block can use in this tile
+        const bool need_both = kt + 31 <= b_bmax;
+        const bool need_one = kt + 31 <= b_omax;
         __syncthreads();
         for (int t = threadIdx.x; t < nt; t += kEvalThreads) {
             const int c = C[kt + t];
@@ -371,33 +373,29 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(const WalkDev *__restrict
             for (int m = 0; m < kRowStride; ++m) {
                 int a = c + 2 * m - 4;
                 a = a < 0 ? -a : a;
-                rows[t * kRowStride + m] = T[a];
+                sh.rows[t * kRowStride + m] = T[a];
             }
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < kPairs * 20; e += kEvalThreads) {
-            if (e < kPairs * 16) {
+        if (need_both) {
+            for (int e = threadIdx.x; e < kPairs * 16; e += kEvalThreads) {
                 const int p = e >> 4, x = e & 15;
                 if (2 * p + 1 < nt) {
-                    const double a = rows[(2 * p) * kRowStride + 2 * ((x & 1) + ((x >> 2) & 1))];
-                    const double b = rows[(2 * p + 1) * kRowStride + 2 * (((x >> 1) & 1) + ((x >> 3) & 1))];
-                    PairEntry pe;
-                    pe.sum = a + b;
-                    pe.maxhi = max(hi32(a), hi32(b));
-                    pe.pad = 0;
-                    both[e] = pe;
+                    const double a = sh.rows[(2 * p) * kRowStride + 2 * ((x & 1) + ((x >> 2) & 1))];
+                    const double b = sh.rows[(2 * p + 1) * kRowStride + 2 * (((x >> 1) & 1) + ((x >> 3) & 1))];
+                    sh.both[e] = a + b;
+                    if (kMax) sh.both_max[e] = max(hi32(a), hi32(b));
                 }
-            } else {
-                const int f = e - kPairs * 16;
+            }
+        }
+        if (need_one) {
+            for (int f = threadIdx.x; f < kPairs * 4; f += kEvalThreads) {
                 const int p = f >> 2, x = f & 3;
                 if (2 * p + 1 < nt) {
-                    const double a = rows[(2 * p) * kRowStride + 1 + 2 * (x & 1)];
-                    const double b = rows[(2 * p + 1) * kRowStride + 1 + 2 * ((x >> 1) & 1)];
-                    PairEntry pe;
-                    pe.sum = a + b;
-                    pe.maxhi = max(hi32(a), hi32(b));
-                    pe.pad = 0;
-                    one[f] = pe;
+                    const double a = sh.rows[(2 * p) * kRowStride + 1 + 2 * (x & 1)];
+                    const double b = sh.rows[(2 * p + 1) * kRowStride + 1 + 2 * ((x >> 1) & 1)];
+                    sh.one[f] = a + b;
+                    if (kMax) sh.one_max[f] = max(hi32(a), hi32(b));
                 }
             }
         }
@@ -414,34 +412,35 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(const WalkDev *__restrict
                 const uint32_t XL = __builtin_bitreverse32(
                     __builtin_amdgcn_alignbit(w32[wl0 - c + 1], w32[wl0 - c], sh_l) ^ SJ);
                 const int tcount = min(32, kt_end - k0);
-                const PairEntry *bp = both + (16 * 16) * cc;
-                const PairEntry *op = one + (16 * 4) * cc;
+                const double *bp = sh.both + (16 * 16) * cc;
+                const double *op = sh.one + (16 * 4) * cc;
+                const uint32_t *bq = sh.both_max + (16 * 16) * cc;
+                const uint32_t *oq = sh.one_max + (16 * 4) * cc;
                 if (tcount == 32 && k0 + 31 <= both_max) {
 #pragma unroll
                     for (int p = 0; p < 16; ++p) {
                         const uint32_t x = __builtin_amdgcn_ubfe(XR, 2 * p, 2) |
                                            (__builtin_amdgcn_ubfe(XL, 2 * p, 2) << 2);
-                        const PairEntry *pe = bp + 16 * p + x;
-                        acc += pe->sum;
-                        mx = max(mx, pe->maxhi);
+                        acc += bp[16 * p + x];
+                        if (kMax) mx = max(mx, bq[16 * p + x]);
                     }
                 } else if (tcount == 32 && k0 + 31 <= jr_min && k0 > jl_max) {
 #pragma unroll
                     for (int p = 0; p < 16; ++p) {
-                        const PairEntry *pe = op + 4 * p + __builtin_amdgcn_ubfe(XR, 2 * p, 2);
-                        acc += pe->sum;
-                        mx = max(mx, pe->maxhi);
+                        const uint32_t x = __builtin_amdgcn_ubfe(XR, 2 * p, 2);
+                        acc += op[4 * p + x];
+                        if (kMax) mx = max(mx, oq[4 * p + x]);
                     }
                 } else if (tcount == 32 && k0 + 31 <= jl_min && k0 > jr_max) {
 #pragma unroll
                     for (int p = 0; p < 16; ++p) {
-                        const PairEntry *pe = op + 4 * p + __builtin_amdgcn_ubfe(XL, 2 * p, 2);
-                        acc += pe->sum;
-                        mx = max(mx, pe->maxhi);
+                        const uint32_t x = __builtin_amdgcn_ubfe(XL, 2 * p, 2);
+                        acc += op[4 * p + x];
+                        if (kMax) mx = max(mx, oq[4 * p + x]);
                     }
                 } else {
                     // mixed bounds or a partial chunk: per shift
-                    const double *rb = rows + (32 * cc) * kRowStride;
+                    const double *rb = sh.rows + (32 * cc) * kRowStride;
                     for (int t = 0; t < tcount; ++t) {
                         const int k = k0 + t;
                         int m = 2;
@@ -449,7 +448,7 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(const WalkDev *__restrict
                         if (k <= jl) m += ((XL >> t) & 1u) ? 1 : -1;
                         const double v = rb[t * kRowStride + m];
                         acc += v;
-                        mx = max(mx, hi32(v));
+                        if (kMax) mx = max(mx, hi32(v));
                     }
                 }
             }
@@ -460,7 +459,83 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(const WalkDev *__restrict
     const int kn = max(k_lo, k_wend);
     if (kn < k_hi) {
         nsum_add(sum, comp, be.S0[kn] - be.S0[k_hi]);
-        mx = max(mx, be.M0[kn]);
+        if (kMax) mx = max(mx, be.M0[kn]);
+    }
+}
+
+// Neighborhood of Algorithm 1 for one (walk, 512 candidates, k-range) item.
+//
+// Per 256-shift tile the block stages (i) per shift the five values
+// T(|C_k + 2m|), m = -2..2, and (ii) per pair of shifts (k, k+1) two tables
+// of pre-added terms: 16 entries indexed by the four bits (xr_k, xr_k+1,
+// xl_k, xl_k+1) for shifts where both neighbours of j exist
+// (C' = C + 4(xr + xl - 1)), and 4 entries indexed by (x_k, x_k+1) for shifts
+// where one neighbour exists (C' = C + 2(2x - 1)); x = 1 when s_j times that
+// neighbour is -1. A lane takes a 32-shift window of each side's bits with
+// one funnel shift, and per pair of shifts does two bit-field extracts, one
+// LDS read and one FP64 add. Which form a 32-shift window uses is decided
+// once per wavefront from the lanes' bounds. Shifts past every lane's
+// max(j, L-1-j) come from the suffix sums. The PSL comes from the near-peak
+// shifts (split 0 only), or, for pivots with many near-peak shifts, from
+// 32-bit maxima kept in the main loop.
+__global__ __launch_bounds__(kEvalThreads) void k_eval(const WalkDev *__restrict__ walks,
+                                                       const BatchEntry *__restrict__ batch,
+                                                       const EvalItem *__restrict__ items,
+                                                       Tables tabs)
+{
+    __shared__ EvalLds sh;
+
+    const EvalItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
+    const BatchEntry be = batch[it.walk];
+    const WalkDev &w = walks[be.slot];
+    const int L = (int)w.L;
+    const uint32_t n_lmt = be.fixed ? be.n_lmt : w.n_lmt;
+    const uint32_t start = be.fixed ? be.start : step_start(w);
+    const double *__restrict__ T = tabs.T[w.alpha];
+    const uint32_t *__restrict__ w32 = reinterpret_cast<const uint32_t *>(w.pivot);
+
+    // shifts of this split, in whole 32-shift chunks from k = 1
+    const int nchunks = (L - 1 + 31) / 32;
+    const int per = (nchunks + (int)be.ksplit - 1) / (int)be.ksplit;
+    const int c_lo = (int)it.ks * per;
+    const int c_hi = min(nchunks, c_lo + per);
+    const int k_lo = 1 + 32 * c_lo;
+    const int k_hi = min(L, 1 + 32 * c_hi);
+
+    // this lane's candidate; inactive lanes keep a valid j and store nothing
+    const uint32_t i = it.tile * kEvalThreads + threadIdx.x;
+    const bool active = i < n_lmt;
+    const uint32_t ii = active ? i : n_lmt - 1;
+    const int j = (int)((start + 1u + ii) % (uint32_t)L);
+    const uint32_t sjbit = (w32[j >> 5] >> (j & 31)) & 1u;
+    const uint32_t SJ = sjbit ? 0xFFFFFFFFu : 0u;
+
+    double sum = 0.0, comp = 0.0;
+    uint32_t mx = 0;
+    const uint32_t n_near = be.near[0];
+    if (n_near > be.near_lim) {
+        eval_sweep<true>(sh, w, be, it, T, n_lmt, j, SJ, k_lo, k_hi, sum, comp, mx);
+    } else {
+        eval_sweep<false>(sh, w, be, it, T, n_lmt, j, SJ, k_lo, k_hi, sum, comp, mx);
+        if (it.ks == 0) {
+            // PSL over the near-peak shifts, every candidate, all bounds cases
+            const int jl = j, jr = L - 1 - j;
+            int peak = 0;
+            for (uint32_t q = 0; q < n_near; ++q) {
+                const int k = (int)be.near[1 + q];
+                int c = w.C[k];
+                if (k <= jr) {
+                    const int p = j + k;
+                    c += (((w32[p >> 5] >> (p & 31)) & 1u) ^ sjbit) ? 2 : -2;
+                }
+                if (k <= jl) {
+                    const int p = j - k;
+                    c += (((w32[p >> 5] >> (p & 31)) & 1u) ^ sjbit) ? 2 : -2;
+                }
+                peak = max(peak, c < 0 ? -c : c);
+            }
+            mx = hi32(T[peak]);
+        }
     }
     if (active) {
         const size_t o = (size_t)it.ks * n_lmt + i;

@@ -88,7 +88,7 @@ struct BatchPlan {
     BatchEntry *d_batch = nullptr;
     EvalItem *d_items = nullptr;
     double *d_fpart = nullptr, *d_f = nullptr, *d_s0 = nullptr;
-    uint32_t *d_mpart = nullptr, *d_m0 = nullptr;
+    uint32_t *d_mpart = nullptr, *d_m0 = nullptr, *d_near = nullptr;
     int32_t *d_p = nullptr;
 };
 
@@ -111,6 +111,7 @@ struct psl_ctx {
     BatchPlan pure;                   // single-walk plan of psl_eval_neighbourhood
     void *d_choice = nullptr;
     std::string err;
+    int64_t near_limit = -1;          // PSL_OPT_NEAR_LIMIT
     // timing
     bool timing = false;
     std::vector<hipEvent_t> ev;       // 3 per recorded step: eval start, eval end, step end
@@ -204,6 +205,7 @@ void plan_free(psl_ctx *ctx, BatchPlan &pl)
     dev_free(ctx, pl.d_p, false);
     dev_free(ctx, pl.d_s0, false);
     dev_free(ctx, pl.d_m0, false);
+    dev_free(ctx, pl.d_near, false);
     pl = BatchPlan();
 }
 
@@ -322,6 +324,8 @@ psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t 
     pl.d_s0 = (double *)p;
     if ((st = dev_alloc(ctx, &p, sizeof(uint32_t) * n_suf, false))) return st;
     pl.d_m0 = (uint32_t *)p;
+    if ((st = dev_alloc(ctx, &p, sizeof(uint32_t) * (kNearCap + 1) * n, false))) return st;
+    pl.d_near = (uint32_t *)p;
     std::vector<BatchEntry> be(n);
     std::vector<EvalItem> items;
     items.reserve(n_items);
@@ -335,12 +339,19 @@ psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t 
         e.P = pl.d_p + oc;
         e.S0 = pl.d_s0 + os;
         e.M0 = pl.d_m0 + os;
+        e.near = pl.d_near + (size_t)(kNearCap + 1) * b;
         os += ctx->walks[ids[b]].L + 1;
         e.slot = ids[b];
         e.ksplit = ks[b];
         e.tiles = tiles[b];
         e.n_lmt = n_l[b];
         e.start = fixed ? start_fixed : 0;
+        {
+            const uint32_t Lb = ctx->walks[ids[b]].L;
+            const uint32_t autol = std::min<uint32_t>(kNearCap, std::max<uint32_t>(64, Lb / 16));
+            e.near_lim = ctx->near_limit < 0 ? autol
+                                             : (uint32_t)std::min<int64_t>(ctx->near_limit, kNearCap);
+        }
         e.fixed = fixed ? 1 : 0;
         op += (size_t)ks[b] * n_l[b];
         oc += n_l[b];
@@ -744,6 +755,19 @@ psl_status psl_timing_read(psl_ctx *ctx, psl_timing *out)
     out->eval_launches = ctx->eval_launches;
     out->rest_ms = ctx->rest_ms;
     out->steps = ctx->steps_timed;
+    return PSL_OK;
+}
+
+psl_status psl_set_option(psl_ctx *ctx, int option, int64_t value)
+{
+    if (!ctx) return PSL_E_INVAL;
+    if (option != PSL_OPT_NEAR_LIMIT || value < -1)
+        return fail(ctx, PSL_E_INVAL, "option %d value %lld", option, (long long)value);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->near_limit = value;
+    plan_free(ctx, ctx->plan);   // cached layouts carry the old value
+    plan_free(ctx, ctx->pure);
     return PSL_OK;
 }
 

@@ -22,7 +22,8 @@ L_MAX = 1048575
 EXPORTS = ["psl_ctx_create", "psl_ctx_destroy", "psl_last_error", "psl_sync", "psl_init_walks",
            "psl_free_walks", "psl_eval_neighbourhood", "psl_apply_flip", "psl_step_batch",
            "psl_read_walk", "psl_eval_shape", "psl_version", "psl_timing_enable",
-           "psl_timing_read"]
+           "psl_timing_read", "psl_set_option"]
+OPT_NEAR_LIMIT = 1
 
 
 class PslError(RuntimeError):
@@ -100,6 +101,7 @@ def lib() -> ctypes.CDLL:
         "psl_version": (ctypes.c_char_p, []),
         "psl_timing_enable": (i32, [P, ctypes.c_int]),
         "psl_timing_read": (i32, [P, ctypes.POINTER(Timing)]),
+        "psl_set_option": (i32, [P, ctypes.c_int, ctypes.c_int64]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -237,6 +239,9 @@ class Context:
                                          ctypes.byref(k)))
         return int(t.value), int(k.value)
 
+
+    def set_option(self, option: int, value: int):
+        self._check(lib().psl_set_option(self._h, option, value))
 
     def timing_enable(self, on: bool = True):
         self._check(lib().psl_timing_enable(self._h, 1 if on else 0))

@@ -16,12 +16,15 @@ F_RTOL = 1e-12
 MARGIN = 5e-13
 
 
-@pytest.fixture(scope="module")
-def ctx():
+@pytest.fixture(scope="module", params=["auto", "dense"])
+def ctx(request):
+    """Two contexts: automatic PSL mode (near-peak list) and the in-loop max."""
     import torch
     from paper_2107_09801_amd import libpsl
     assert torch.cuda.is_available()
     c = libpsl.Context(0)
+    if request.param == "dense":
+        c.set_option(libpsl.OPT_NEAR_LIMIT, 0)
     yield c
     c.close()
 

@@ -188,6 +188,9 @@ PSL_API psl_status psl_apply_flip(psl_ctx *ctx, uint32_t walk, uint32_t j);
  * with PSL_STEP_BLOCKING the call waits for it. Walks of different L may be
  * mixed. Errors: PSL_E_INVAL, PSL_E_STATE, PSL_E_NOMEM, PSL_E_HIP. */
 #define PSL_STEP_BLOCKING 1u
+#define PSL_STEP_GRAPH    2u   /* replay one captured hipGraph per step (the
+                                  capture is cached with the batch; ignored
+                                  while timing is enabled) */
 PSL_API psl_status psl_step_batch(psl_ctx *ctx, const uint32_t *walk_ids, uint32_t n,
                           uint32_t steps, uint32_t flags);
 

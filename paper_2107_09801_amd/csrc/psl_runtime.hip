@@ -87,12 +87,16 @@ struct BatchPlan {
     uint32_t n_items = 0;
     BatchEntry *d_batch = nullptr;
     EvalItem *d_items = nullptr;
+    hipGraph_t graph = nullptr;       // one captured step of this plan
+    hipGraphExec_t gexec = nullptr;
     double *d_fpart = nullptr, *d_f = nullptr, *d_s0 = nullptr;
     uint32_t *d_mpart = nullptr, *d_m0 = nullptr, *d_near = nullptr;
     int32_t *d_p = nullptr;
 };
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+constexpr size_t kPlanCache = 8;   // step batches whose layout (and graph) is kept
 
 }  // namespace
 
@@ -107,7 +111,7 @@ struct psl_ctx {
     uint32_t walk_cap = 0;
     double *d_T[PSL_ALPHA_MAX + 1] = {};
     uint32_t T_n = 0;                 // entries per power table
-    BatchPlan plan;                   // last step batch
+    std::vector<BatchPlan> plans;     // recent step batches, most recent last
     BatchPlan pure;                   // single-walk plan of psl_eval_neighbourhood
     void *d_choice = nullptr;
     std::string err;
@@ -197,6 +201,8 @@ psl_status timing_mark(psl_ctx *ctx)
 
 void plan_free(psl_ctx *ctx, BatchPlan &pl)
 {
+    if (pl.gexec) (void)hipGraphExecDestroy(pl.gexec);
+    if (pl.graph) (void)hipGraphDestroy(pl.graph);
     dev_free(ctx, pl.d_batch, false);
     dev_free(ctx, pl.d_items, false);
     dev_free(ctx, pl.d_fpart, false);
@@ -209,6 +215,13 @@ void plan_free(psl_ctx *ctx, BatchPlan &pl)
     pl = BatchPlan();
 }
 
+void plans_clear(psl_ctx *ctx)
+{
+    for (auto &pl : ctx->plans) plan_free(ctx, pl);
+    ctx->plans.clear();
+    plan_free(ctx, ctx->pure);
+}
+
 // Power tables for every exponent, |c| up to L_max + 4.
 psl_status ensure_tables(psl_ctx *ctx, uint32_t L)
 {
@@ -216,6 +229,7 @@ psl_status ensure_tables(psl_ctx *ctx, uint32_t L)
     if (need <= ctx->T_n) return PSL_OK;
     uint32_t n = std::max<uint32_t>(need, 1024);
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    plans_clear(ctx);            // captured launches name the old tables
     for (uint32_t a = 1; a <= PSL_ALPHA_MAX; ++a) {
         dev_free(ctx, ctx->d_T[a], false);
         ctx->d_T[a] = nullptr;
@@ -250,6 +264,7 @@ psl_status ensure_walk_cap(psl_ctx *ctx, uint32_t cap)
     psl_status st = dev_alloc(ctx, &p, sizeof(WalkDev) * ncap, false);
     if (st) return st;
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    plans_clear(ctx);            // captured launches name the old walk array
     if (ctx->d_walks) {
         HIP_TRY(ctx, hipMemcpy(p, ctx->d_walks, sizeof(WalkDev) * ctx->walk_cap,
                                hipMemcpyDeviceToDevice));
@@ -284,8 +299,6 @@ psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t 
                      uint32_t start_fixed)
 {
     const bool fixed = n_fixed != UINT32_MAX;
-    if (!fixed && pl.d_batch && pl.ids.size() == n && std::equal(ids, ids + n, pl.ids.begin()))
-        return PSL_OK;
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     plan_free(ctx, pl);
     pl.ids.assign(ids, ids + n);
@@ -382,6 +395,46 @@ psl_status check_cfg(psl_ctx *ctx, const psl_walk_cfg *c)
     return PSL_OK;
 }
 
+// The launches of one iteration of Algorithm 1 for every walk of a plan.
+psl_status launch_step(psl_ctx *ctx, const BatchPlan &pl, const Tables &tabs, uint32_t n, bool timed)
+{
+    psl_status st;
+    HIP_TRY(ctx, launch_suffix(ctx->d_walks, pl.d_batch, n, tabs, ctx->stream));
+    if (timed && (st = timing_mark(ctx))) return st;
+    HIP_TRY(ctx, launch_eval(ctx->d_walks, pl.d_batch, pl.d_items, pl.n_items, tabs, ctx->stream));
+    if (timed && (st = timing_mark(ctx))) return st;
+    HIP_TRY(ctx, launch_select(ctx->d_walks, pl.d_batch, n, tabs, 0, nullptr, ctx->stream));
+    HIP_TRY(ctx, launch_apply(ctx->d_walks, pl.d_batch, n, pl.max_L, -1, ctx->stream));
+    HIP_TRY(ctx, launch_bookkeep(ctx->d_walks, pl.d_batch, n, ctx->stream));
+    HIP_TRY(ctx, launch_corr(ctx->d_walks, pl.d_batch, n, pl.max_L, 1, ctx->stream));
+    HIP_TRY(ctx, launch_fitness(ctx->d_walks, pl.d_batch, n, tabs, 1, ctx->stream));
+    if (timed && (st = timing_mark(ctx))) return st;
+    return PSL_OK;
+}
+
+// Captures one step of the plan into a graph (every per-step quantity lives
+// in device memory, so one capture serves every later step).
+psl_status capture_step(psl_ctx *ctx, BatchPlan &pl, const Tables &tabs, uint32_t n)
+{
+    HIP_TRY(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+    psl_status st = launch_step(ctx, pl, tabs, n, false);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(ctx->stream, &g);
+    if (st) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(ctx, PSL_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&pl.gexec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        pl.gexec = nullptr;
+        return fail(ctx, PSL_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    pl.graph = g;
+    return PSL_OK;
+}
+
 psl_status single_plan(psl_ctx *ctx, uint32_t walk, BatchPlan &pl)
 {
     // a one-walk plan with the walk's own n_lmt (used by psl_apply_flip)
@@ -437,8 +490,7 @@ void psl_ctx_destroy(psl_ctx *ctx)
     (void)hipStreamSynchronize(ctx->stream);
     for (auto &h : ctx->walks)
         if (h.active) dev_free(ctx, h.slab, true);
-    plan_free(ctx, ctx->plan);
-    plan_free(ctx, ctx->pure);
+    plans_clear(ctx);
     for (uint32_t a = 1; a <= PSL_ALPHA_MAX; ++a) dev_free(ctx, ctx->d_T[a], false);
     dev_free(ctx, ctx->d_walks, false);
     dev_free(ctx, ctx->d_choice, false);
@@ -594,8 +646,7 @@ psl_status psl_free_walks(psl_ctx *ctx, const uint32_t *walk_ids, uint32_t n)
         h = WalkHost();
         ctx->free_slots.push_back(id);
     }
-    plan_free(ctx, ctx->plan);   // cached layouts may name freed walks
-    plan_free(ctx, ctx->pure);
+    plans_clear(ctx);            // cached layouts may name freed walks
     return st;
 }
 
@@ -672,21 +723,35 @@ psl_status psl_step_batch(psl_ctx *ctx, const uint32_t *walk_ids, uint32_t n, ui
         if (b && sorted[b] == sorted[b - 1]) return fail(ctx, PSL_E_INVAL, "walk %u repeated", sorted[b]);
     }
     HIP_TRY(ctx, hipSetDevice(ctx->device));
-    psl_status st = make_plan(ctx, ctx->plan, walk_ids, n, UINT32_MAX, 0);
-    if (st) return st;
-    const BatchPlan &pl = ctx->plan;
+    psl_status st = PSL_OK;
+    size_t hit = ctx->plans.size();
+    for (size_t x = 0; x < ctx->plans.size(); ++x) {
+        const BatchPlan &c = ctx->plans[x];
+        if (c.ids.size() == n && std::equal(walk_ids, walk_ids + n, c.ids.begin())) hit = x;
+    }
+    if (hit == ctx->plans.size()) {
+        if (ctx->plans.size() >= kPlanCache) {
+            HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+            plan_free(ctx, ctx->plans.front());
+            ctx->plans.erase(ctx->plans.begin());
+        }
+        ctx->plans.emplace_back();
+        if ((st = make_plan(ctx, ctx->plans.back(), walk_ids, n, UINT32_MAX, 0))) {
+            plan_free(ctx, ctx->plans.back());
+            ctx->plans.pop_back();
+            return st;
+        }
+    } else if (hit + 1 != ctx->plans.size()) {
+        std::rotate(ctx->plans.begin() + hit, ctx->plans.begin() + hit + 1, ctx->plans.end());
+    }
+    BatchPlan &pl = ctx->plans.back();
     const Tables tabs = tables_of(ctx);
-    for (uint32_t s = 0; s < steps; ++s) {
-        HIP_TRY(ctx, launch_suffix(ctx->d_walks, pl.d_batch, n, tabs, ctx->stream));
-        if (ctx->timing && (st = timing_mark(ctx))) return st;
-        HIP_TRY(ctx, launch_eval(ctx->d_walks, pl.d_batch, pl.d_items, pl.n_items, tabs, ctx->stream));
-        if (ctx->timing && (st = timing_mark(ctx))) return st;
-        HIP_TRY(ctx, launch_select(ctx->d_walks, pl.d_batch, n, tabs, 0, nullptr, ctx->stream));
-        HIP_TRY(ctx, launch_apply(ctx->d_walks, pl.d_batch, n, pl.max_L, -1, ctx->stream));
-        HIP_TRY(ctx, launch_bookkeep(ctx->d_walks, pl.d_batch, n, ctx->stream));
-        HIP_TRY(ctx, launch_corr(ctx->d_walks, pl.d_batch, n, pl.max_L, 1, ctx->stream));
-        HIP_TRY(ctx, launch_fitness(ctx->d_walks, pl.d_batch, n, tabs, 1, ctx->stream));
-        if (ctx->timing && (st = timing_mark(ctx))) return st;
+    if ((flags & PSL_STEP_GRAPH) && !ctx->timing) {
+        if (!pl.gexec && (st = capture_step(ctx, pl, tabs, n))) return st;
+        for (uint32_t s = 0; s < steps; ++s) HIP_TRY(ctx, hipGraphLaunch(pl.gexec, ctx->stream));
+    } else {
+        for (uint32_t s = 0; s < steps; ++s)
+            if ((st = launch_step(ctx, pl, tabs, n, ctx->timing))) return st;
     }
     if (flags & PSL_STEP_BLOCKING) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     return PSL_OK;
@@ -766,8 +831,7 @@ psl_status psl_set_option(psl_ctx *ctx, int option, int64_t value)
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     ctx->near_limit = value;
-    plan_free(ctx, ctx->plan);   // cached layouts carry the old value
-    plan_free(ctx, ctx->pure);
+    plans_clear(ctx);            // cached layouts carry the old value
     return PSL_OK;
 }
 

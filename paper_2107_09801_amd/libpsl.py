@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(PKG, "_build", "libpsl.so")
 
 OK, E_INVAL, E_NOMEM, E_HIP, E_STATE, E_AGAIN, E_FULL = 0, -1, -2, -3, -4, -5, -6
 STEP_BLOCKING = 1
+STEP_GRAPH = 2
 STEP_IMPROVED, STEP_WORSE, STEP_SWITCHED, STEP_PSL_IMPROVED = 1, 2, 4, 8
 L_MAX = 1048575
 
@@ -210,10 +211,10 @@ class Context:
     def apply_flip(self, walk: int, j: int):
         self._check(lib().psl_apply_flip(self._h, walk, j))
 
-    def step_batch(self, ids, steps: int, blocking: bool = True):
+    def step_batch(self, ids, steps: int, blocking: bool = True, graph: bool = False):
         a = np.ascontiguousarray(ids, dtype=np.uint32)
-        self._check(lib().psl_step_batch(self._h, _ptr(a), len(a), steps,
-                                         STEP_BLOCKING if blocking else 0))
+        flags = (STEP_BLOCKING if blocking else 0) | (STEP_GRAPH if graph else 0)
+        self._check(lib().psl_step_batch(self._h, _ptr(a), len(a), steps, flags))
 
     def read_walk(self, walk: int, bits: bool = True, C: bool = True) -> dict:
         st = WalkState()

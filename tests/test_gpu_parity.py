@@ -228,3 +228,30 @@ def test_invalid_arguments(ctx):
     ctx.free_walks([w])
     with pytest.raises(libpsl.PslError):
         ctx.read_walk(w)
+
+
+def test_graph_replays_match_eager(ctx):
+    """One captured step replayed many times, with eager work and syncs between
+    replays, equals the eager path after every replay."""
+    Ls = [2, 257, 1001, 5000]
+    eager, graph = [], []
+    for L in Ls:
+        eager += ctx.init_walks(L, 1, 4242 + L, n_lmt=0, switch_period=4, flip_lmt=min(3, L))
+    for L in Ls:
+        graph += ctx.init_walks(L, 1, 4242 + L, n_lmt=0, switch_period=4, flip_lmt=min(3, L))
+    other = ctx.init_walks(300, 2, 7, n_lmt=0)
+    for r in range(9):
+        ctx.step_batch(eager, 1)
+        ctx.step_batch(graph, 1 + (r % 2), graph=True)
+        if r % 2 == 1:
+            ctx.step_batch(eager, 1)
+        ctx.step_batch(other, 1)          # eager work between replays
+        ctx.sync()
+        for a, b in zip(eager, graph):
+            ga, gb = ctx.read_walk(a), ctx.read_walk(b)
+            assert ga["t"] == gb["t"]
+            for key in ("pivot", "C", "best", "local_best"):
+                assert np.array_equal(ga[key], gb[key]), (r, key)
+            for key in ("psl_best", "alpha", "unimproved", "q", "last_k", "value_local"):
+                assert ga[key] == gb[key], (r, key)
+    ctx.free_walks(eager + graph + other)

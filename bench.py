@@ -10,6 +10,10 @@ selection, the O(L) flip, bookkeeping and (when due) the switch.
 Prints one JSON line: flip-evals/s (whole job) with the roofline of the
 dominant kernel (the neighbourhood evaluation, timed with HIP events on its
 own stream) and the CPU oracle timed on a bounded sample of the same work.
+Two secondary measurements ride along: the request loop under Poisson
+arrivals of the serving workload's job mixture (p50/p99 time-to-budget and
+aggregate flip-evals/s), and the same jobs served together against one walk
+per launch sequence.
 """
 from __future__ import annotations
 
@@ -45,6 +49,13 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="arrival window of the serving run (0: skip it)")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrivals per second")
+    ap.add_argument("--serve-nlmt", type=int, default=256,
+                    help="N_lmt of served jobs (min(L, this))")
+    ap.add_argument("--compare-jobs", type=int, default=48,
+                    help="jobs in the served vs one-walk-per-launch comparison (0: skip)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before the run, one device-to-device copy of this many MiB "
                          "(a known-size kernel to scale profiler byte counters)")
@@ -83,6 +94,115 @@ def cpu_baseline(L: int, n_lmt: int, alpha: int, target_s: float, max_walks: int
                       f"at L={L} (alpha={alpha}), {el:.1f} s of evaluation, OpenMP over "
                       f"candidates on {threads} threads",
             "C_k_updates_per_s": done * (L - 1) / el}
+
+
+def serve_jobs(n: int, seed: int, nlmt_cap: int):
+    """The serving workload's job mixture: half L = 2^m - 1 (m = 14..20
+    uniform), half odd L uniform in [1001, 1048575]; step budget uniform in
+    [50, 500]; N_lmt = min(L, nlmt_cap); job i has seed BASE_SEED + i."""
+    import numpy as np
+
+    import seeded_inputs as si
+    rng = np.random.Generator(np.random.PCG64(seed))
+    jobs = []
+    for i in range(n):
+        if rng.random() < 0.5:
+            L = 2 ** int(rng.integers(14, 21)) - 1
+        else:
+            L = 2 * int(rng.integers(500, 524288)) + 1
+        budget = int(rng.integers(50, 501))
+        jobs.append({"L": L, "budget": budget, "n_lmt": min(L, nlmt_cap),
+                     "alpha2": si.alpha2_for(L), "seed": si.BASE_SEED + i})
+    return jobs
+
+
+def run_serving(libpsl, seconds: float, rate: float, nlmt_cap: int) -> dict:
+    """Poisson arrivals into the request loop; time-to-budget per job."""
+    import numpy as np
+
+    import seeded_inputs as si
+    rng = np.random.Generator(np.random.PCG64(si.BASE_SEED))
+    n = int(rng.poisson(rate * seconds))
+    arrivals = np.sort(rng.uniform(0.0, seconds, size=n))
+    jobs = serve_jobs(n, si.BASE_SEED + 1, nlmt_cap)
+    ctx = libpsl.Context(0)
+    ctx.serve_start(hbm_budget=200 << 30, max_slots=4096)
+    outstanding, results = set(), {}
+    t0 = time.perf_counter()
+    nxt = 0
+    last_log = t0
+    while nxt < n or len(results) < n:
+        now = time.perf_counter() - t0
+        while nxt < n and arrivals[nxt] <= now:
+            j = jobs[nxt]
+            outstanding.add(ctx.serve_submit(j["L"], j["seed"], j["budget"], alpha2=j["alpha2"],
+                                             n_lmt=j["n_lmt"], switch_period=50, want_best=False))
+            nxt += 1
+        for t in list(outstanding):
+            r = ctx.serve_poll(t)
+            if r is not None:
+                results[t] = r
+                outstanding.discard(t)
+        if time.perf_counter() - last_log > 5:
+            last_log = time.perf_counter()
+            log(f"serving: {nxt}/{n} submitted, {len(results)} done")
+        time.sleep(0.0005)
+    wall = time.perf_counter() - t0
+    st = ctx.serve_stats()
+    ctx.serve_stop(drain=True)
+    ctx.close()
+    ttb = np.array([(r["t_done_ns"] - r["t_arrive_ns"]) * 1e-9 for r in results.values()])
+    queue = np.array([(r["t_admit_ns"] - r["t_arrive_ns"]) * 1e-9 for r in results.values()])
+    offered = sum(j["budget"] * j["n_lmt"] * (j["L"] - 1) for j in jobs) / seconds
+    return {"jobs": n, "arrival_rate": rate, "arrival_window_s": seconds, "wall_s": wall,
+            "n_lmt": f"min(L, {nlmt_cap})",
+            "time_to_budget_p50_s": float(np.percentile(ttb, 50)),
+            "time_to_budget_p99_s": float(np.percentile(ttb, 99)),
+            "queue_wait_p99_s": float(np.percentile(queue, 99)),
+            "flip_evals_per_s": st["flip_evals"] / wall,
+            "C_k_updates_per_s": st["ck_updates"] / wall,
+            "offered_C_k_updates_per_s": offered,
+            "failed": st["failed"], "peak_active": st["peak_active"],
+            "iterations": st["iterations"]}
+
+
+def run_compare(libpsl, n: int, nlmt_cap: int) -> dict:
+    """The same jobs served together (all submitted at once) and run one walk
+    per launch sequence, one job after the other (captured-graph steps)."""
+    import seeded_inputs as si
+    jobs = serve_jobs(n, si.BASE_SEED + 2, nlmt_cap)
+    evals = sum(j["budget"] * j["n_lmt"] for j in jobs)
+    ctx = libpsl.Context(0)
+    ctx.serve_start(hbm_budget=200 << 30, max_slots=4096)
+    t0 = time.perf_counter()
+    tickets = [ctx.serve_submit(j["L"], j["seed"], j["budget"], alpha2=j["alpha2"],
+                                n_lmt=j["n_lmt"], switch_period=50, want_best=False) for j in jobs]
+    served, outstanding = {}, set(tickets)
+    while outstanding:
+        for t in list(outstanding):
+            r = ctx.serve_poll(t)
+            if r is not None:
+                served[t] = r
+                outstanding.discard(t)
+        time.sleep(0.0005)
+    t_served = time.perf_counter() - t0
+    ctx.serve_stop(drain=True)
+    solo = []
+    t0 = time.perf_counter()
+    for j in jobs:
+        (w,) = ctx.init_walks(j["L"], 1, j["seed"], alpha2=j["alpha2"], n_lmt=j["n_lmt"],
+                              switch_period=50)
+        ctx.step_batch([w], j["budget"], graph=True)
+        solo.append(ctx.read_walk(w, bits=False, C=False))
+        ctx.free_walks([w])
+    t_solo = time.perf_counter() - t0
+    same = all(served[t]["psl_best"] == g["psl_best"] and served[t]["psl_final"] == g["psl_pivot"]
+               for t, g in zip(tickets, solo))
+    ctx.close()
+    return {"jobs": n, "flip_evals": evals,
+            "served_flip_evals_per_s": evals / t_served,
+            "one_walk_per_launch_flip_evals_per_s": evals / t_solo,
+            "speedup": t_solo / t_served, "results_identical": same}
 
 
 def log(msg: str):
@@ -168,6 +288,12 @@ def main():
         out["paper_context"] = {"A100_flip_evals_per_s": PAPER_A100_NSE[L],
                                 "note": "paper Table 4: one walk, N_lmt=6912, alpha 4/10"}
     ctx.close()
+    if args.serve_seconds > 0:
+        log(f"serving run: {args.serve_rate:g} jobs/s for {args.serve_seconds:g} s")
+        out["serving"] = run_serving(libpsl, args.serve_seconds, args.serve_rate, args.serve_nlmt)
+    if args.compare_jobs > 0:
+        log(f"served vs one-walk-per-launch on {args.compare_jobs} jobs")
+        out["served_vs_single"] = run_compare(libpsl, args.compare_jobs, args.serve_nlmt)
     if not args.no_cpu_baseline:
         log("timing the oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(L, n_lmt, 4, args.cpu_seconds, nw)

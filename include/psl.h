@@ -202,6 +202,73 @@ PSL_API psl_status psl_read_walk(psl_ctx *ctx, uint32_t walk, psl_walk_state *ou
                          uint64_t *pivot_bits, uint64_t *local_best_bits,
                          uint64_t *best_bits, int32_t *C);
 
+/* ----------------------------------------------------------- serving */
+
+/* A request loop on its own host thread: jobs (one walk each, any L, their
+ * own step budget) are admitted in arrival order as device memory and slots
+ * allow, their walks stay resident in HBM, and every iteration advances every
+ * admitted walk by one step of Algorithm 1 in one batched launch sequence
+ * (continuous batching: jobs that arrive while others run join the next
+ * iteration). While serving, the context's other calls return PSL_E_STATE. */
+typedef struct {
+    uint64_t hbm_budget;     /* bytes jobs may occupy: walk slabs and their scratch */
+    uint32_t max_slots;      /* most jobs admitted at once (>= 1)                  */
+    uint32_t flags;          /* reserved, 0                                         */
+} psl_serve_cfg;
+
+typedef struct {
+    psl_walk_cfg cfg;        /* the job's walk (cfg.seed is its SEED)              */
+    uint64_t step_budget;    /* iterations of Algorithm 1 to run, >= 1              */
+    uint64_t *best_bits_out; /* host, ceil(L/64) words, or NULL: receives the best-
+                                PSL sequence; must stay valid until the job is
+                                polled done                                        */
+} psl_job;
+
+typedef struct {
+    int32_t  status;         /* PSL_OK; PSL_E_HIP if a device error ended it;
+                                PSL_E_STATE if it was cancelled by psl_serve_stop  */
+    int32_t  psl_best;       /* best PSL seen                                       */
+    int32_t  psl_final;      /* PSL of the final pivot                              */
+    uint32_t alpha_final;    /* exponent at the end                                 */
+    double   F_final;        /* F of the final pivot in that exponent               */
+    uint64_t steps;          /* steps run                                           */
+    uint64_t t_arrive_ns;    /* steady-clock times: submit, admit, done             */
+    uint64_t t_admit_ns;
+    uint64_t t_done_ns;
+} psl_job_result;
+
+typedef struct {
+    uint64_t submitted, completed, failed, active, queued;
+    uint64_t iterations;     /* batched steps launched                              */
+    uint64_t flip_evals;     /* neighbour evaluations done                          */
+    uint64_t ck_updates;     /* flip_evals x (L-1), nominal                         */
+    double   busy_s;         /* wall time with at least one job admitted            */
+    uint64_t peak_active;    /* most jobs admitted at once                          */
+    uint64_t peak_used;      /* most budget bytes held at once                      */
+} psl_serve_stats;
+
+/* Start the loop on this context. Errors: PSL_E_INVAL (cfg), PSL_E_STATE
+ * (already serving), PSL_E_NOMEM, PSL_E_HIP. */
+PSL_API psl_status psl_serve_start(psl_ctx *ctx, const psl_serve_cfg *cfg);
+
+/* Queue a job; thread-safe and non-blocking. *ticket names it.
+ * Errors: PSL_E_INVAL (bad job), PSL_E_FULL (its footprint exceeds the whole
+ * budget), PSL_E_STATE (not serving). */
+PSL_API psl_status psl_serve_submit(psl_ctx *ctx, const psl_job *job, uint64_t *ticket);
+
+/* Thread-safe. PSL_OK: the job is finished, *out holds its result and the
+ * ticket is retired. PSL_E_AGAIN: queued or running. PSL_E_STATE: unknown
+ * (or already retired) ticket. */
+PSL_API psl_status psl_serve_poll(psl_ctx *ctx, uint64_t ticket, psl_job_result *out);
+
+/* Thread-safe counters of the loop. */
+PSL_API psl_status psl_serve_stats_read(psl_ctx *ctx, psl_serve_stats *out);
+
+/* Stop the loop. drain != 0: finish every submitted job first; drain == 0:
+ * cancel queued and running jobs. Results stay pollable until the next
+ * psl_serve_start or psl_ctx_destroy. */
+PSL_API psl_status psl_serve_stop(psl_ctx *ctx, int drain);
+
 /* ------------------------------------------------------------ timing */
 
 /* Per-kernel device time of psl_step_batch, measured with HIP events recorded

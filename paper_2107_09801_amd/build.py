@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT_DIR = os.path.join(PKG, "_build")
 LIB = os.path.join(OUT_DIR, "libpsl.so")
-SOURCES = ["psl_runtime.hip", "psl_kernels.hip"]
+SOURCES = ["psl_runtime.hip", "psl_serve.hip", "psl_kernels.hip"]
 ARCH = "gfx950"
 
 
@@ -30,7 +30,7 @@ def build(verbose: bool = False) -> str:
            # packed FP32 instructions are kept out of every kernel
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           "-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
+           "-pthread", "-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

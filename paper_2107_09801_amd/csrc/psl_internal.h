@@ -1,0 +1,174 @@
+// psl_internal.h -- host-side structures shared by the libpsl runtime and
+// its serving loop (internal; not part of the C-ABI).
+#pragma once
+
+#include "psl.h"
+#include "psl_device.h"
+#include "psl_launch.h"
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+namespace psl_rt {
+
+using namespace psl;
+
+// ------------------------------------------------------------ arena
+
+// First-fit allocator over a caller-provided device buffer. Offsets are
+// 256-byte aligned; freed ranges merge with their neighbours.
+class Arena {
+public:
+    void reset(char *base, size_t bytes)
+    {
+        base_ = base;
+        free_.clear();
+        if (base && bytes >= kAlign) free_[0] = bytes & ~(kAlign - 1);
+    }
+    bool active() const { return base_ != nullptr; }
+    void *alloc(size_t bytes)
+    {
+        bytes = (bytes + kAlign - 1) & ~(kAlign - 1);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                size_t off = it->first, len = it->second;
+                free_.erase(it);
+                if (len > bytes) free_[off + bytes] = len - bytes;
+                used_[off] = bytes;
+                return base_ + off;
+            }
+        }
+        return nullptr;
+    }
+    void release(void *p)
+    {
+        size_t off = (size_t)((char *)p - base_);
+        auto u = used_.find(off);
+        if (u == used_.end()) return;
+        size_t len = u->second;
+        used_.erase(u);
+        auto nx = free_.lower_bound(off);
+        if (nx != free_.end() && off + len == nx->first) {
+            len += nx->second;
+            nx = free_.erase(nx);
+        }
+        if (nx != free_.begin()) {
+            auto pv = std::prev(nx);
+            if (pv->first + pv->second == off) {
+                pv->second += len;
+                return;
+            }
+        }
+        free_[off] = len;
+    }
+
+private:
+    static constexpr size_t kAlign = 256;
+    char *base_ = nullptr;
+    std::map<size_t, size_t> free_, used_;
+};
+
+// Host record of a walk slot.
+struct WalkHost {
+    bool active = false;
+    uint32_t L = 0, nw = 0, n_lmt = 0;
+    void *slab = nullptr;
+    size_t slab_bytes = 0;
+};
+
+// A batch as laid out on the device; cached by its walk list.
+struct BatchPlan {
+    std::vector<uint32_t> ids;
+    uint32_t max_L = 0, max_nw = 0;
+    uint32_t n_items = 0;
+    BatchEntry *d_batch = nullptr;
+    EvalItem *d_items = nullptr;
+    hipGraph_t graph = nullptr;       // one captured step of this plan
+    hipGraphExec_t gexec = nullptr;
+    double *d_fpart = nullptr, *d_f = nullptr, *d_s0 = nullptr;
+    uint32_t *d_mpart = nullptr, *d_m0 = nullptr, *d_near = nullptr;
+    int32_t *d_p = nullptr;
+};
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+constexpr size_t kPlanCache = 8;   // step batches whose layout (and graph) is kept
+
+
+struct Server;   // serving loop (psl_serve.hip)
+
+}  // namespace psl_rt
+
+struct psl_ctx {
+    using Arena = psl_rt::Arena;
+    using WalkHost = psl_rt::WalkHost;
+    using BatchPlan = psl_rt::BatchPlan;
+    using WalkDev = psl::WalkDev;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    Arena arena;
+    std::vector<WalkHost> walks;
+    std::vector<uint32_t> free_slots;
+    WalkDev *d_walks = nullptr;
+    uint32_t walk_cap = 0;
+    double *d_T[PSL_ALPHA_MAX + 1] = {};
+    uint32_t T_n = 0;                 // entries per power table
+    std::vector<BatchPlan> plans;     // recent step batches, most recent last
+    BatchPlan pure;                   // single-walk plan of psl_eval_neighbourhood
+    void *d_choice = nullptr;
+    std::string err;
+    int64_t near_limit = -1;          // PSL_OPT_NEAR_LIMIT
+    psl_rt::Server *server = nullptr; // serving loop, when started
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev;       // 3 per recorded step: eval start, eval end, step end
+    double eval_ms = 0.0, rest_ms = 0.0;
+    uint64_t eval_launches = 0, steps_timed = 0;
+};
+
+namespace psl_rt {
+
+psl_status fail(psl_ctx *ctx, psl_status st, const char *fmt, ...);
+
+#define HIP_TRY(ctx, expr)                                                              \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return ::psl_rt::fail((ctx), PSL_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+psl_status dev_alloc(psl_ctx *ctx, void **p, size_t bytes, bool from_arena);
+void dev_free(psl_ctx *ctx, void *p, bool from_arena);
+void plan_free(psl_ctx *ctx, BatchPlan &pl);
+void plans_clear(psl_ctx *ctx);
+psl_status ensure_tables(psl_ctx *ctx, uint32_t L);
+Tables tables_of(const psl_ctx *ctx);
+psl_status ensure_walk_cap(psl_ctx *ctx, uint32_t cap);
+bool walk_ok(const psl_ctx *ctx, uint32_t id);
+void eval_shape(uint32_t L, uint32_t n_lmt, uint32_t total_tiles, uint32_t *tiles, uint32_t *ksplit);
+psl_status check_cfg(psl_ctx *ctx, const psl_walk_cfg *c);
+uint32_t near_limit_for(const psl_ctx *ctx, uint32_t L);
+
+// Slab layout of one walk of length L: the pivot between guard words, then
+// local_best, best and C.
+struct SlabLayout {
+    size_t guard_bytes, pivot_bytes, bits_bytes, slab_bytes;
+};
+SlabLayout slab_layout(uint32_t L);
+// Fills a WalkDev for cfg (seed already chosen) over a slab.
+void fill_walk(WalkDev &w, const psl_walk_cfg &cfg, uint64_t seed, void *slab, const SlabLayout &lay);
+
+// Stops the serving loop (if any) and releases it.
+void serve_shutdown(psl_ctx *ctx);
+// True while the serving loop owns the context.
+bool serve_active(psl_ctx *ctx);
+
+}  // namespace psl_rt

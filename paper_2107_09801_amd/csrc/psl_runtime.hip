@@ -1,129 +1,11 @@
 // psl_runtime.hip -- host runtime of libpsl: contexts, device memory, walks,
 // batches and the C-ABI entry points declared in include/psl.h.
-#include "psl.h"
-#include "psl_device.h"
-#include "psl_launch.h"
-
-#include <algorithm>
-#include <cstdarg>
-#include <cstdio>
-#include <cstring>
-#include <map>
-#include <mutex>
-#include <string>
-#include <vector>
+#include "psl_internal.h"
 
 using namespace psl;
+using namespace psl_rt;
 
-namespace {
-
-// ------------------------------------------------------------ arena
-
-// First-fit allocator over a caller-provided device buffer. Offsets are
-// 256-byte aligned; freed ranges merge with their neighbours.
-class Arena {
-public:
-    void reset(char *base, size_t bytes)
-    {
-        base_ = base;
-        free_.clear();
-        if (base && bytes >= kAlign) free_[0] = bytes & ~(kAlign - 1);
-    }
-    bool active() const { return base_ != nullptr; }
-    void *alloc(size_t bytes)
-    {
-        bytes = (bytes + kAlign - 1) & ~(kAlign - 1);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= bytes) {
-                size_t off = it->first, len = it->second;
-                free_.erase(it);
-                if (len > bytes) free_[off + bytes] = len - bytes;
-                used_[off] = bytes;
-                return base_ + off;
-            }
-        }
-        return nullptr;
-    }
-    void release(void *p)
-    {
-        size_t off = (size_t)((char *)p - base_);
-        auto u = used_.find(off);
-        if (u == used_.end()) return;
-        size_t len = u->second;
-        used_.erase(u);
-        auto nx = free_.lower_bound(off);
-        if (nx != free_.end() && off + len == nx->first) {
-            len += nx->second;
-            nx = free_.erase(nx);
-        }
-        if (nx != free_.begin()) {
-            auto pv = std::prev(nx);
-            if (pv->first + pv->second == off) {
-                pv->second += len;
-                return;
-            }
-        }
-        free_[off] = len;
-    }
-
-private:
-    static constexpr size_t kAlign = 256;
-    char *base_ = nullptr;
-    std::map<size_t, size_t> free_, used_;
-};
-
-// Host record of a walk slot.
-struct WalkHost {
-    bool active = false;
-    uint32_t L = 0, nw = 0, n_lmt = 0;
-    void *slab = nullptr;
-    size_t slab_bytes = 0;
-};
-
-// A batch as laid out on the device; cached by its walk list.
-struct BatchPlan {
-    std::vector<uint32_t> ids;
-    uint32_t max_L = 0, max_nw = 0;
-    uint32_t n_items = 0;
-    BatchEntry *d_batch = nullptr;
-    EvalItem *d_items = nullptr;
-    hipGraph_t graph = nullptr;       // one captured step of this plan
-    hipGraphExec_t gexec = nullptr;
-    double *d_fpart = nullptr, *d_f = nullptr, *d_s0 = nullptr;
-    uint32_t *d_mpart = nullptr, *d_m0 = nullptr, *d_near = nullptr;
-    int32_t *d_p = nullptr;
-};
-
-size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
-
-constexpr size_t kPlanCache = 8;   // step batches whose layout (and graph) is kept
-
-}  // namespace
-
-struct psl_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    Arena arena;
-    std::vector<WalkHost> walks;
-    std::vector<uint32_t> free_slots;
-    WalkDev *d_walks = nullptr;
-    uint32_t walk_cap = 0;
-    double *d_T[PSL_ALPHA_MAX + 1] = {};
-    uint32_t T_n = 0;                 // entries per power table
-    std::vector<BatchPlan> plans;     // recent step batches, most recent last
-    BatchPlan pure;                   // single-walk plan of psl_eval_neighbourhood
-    void *d_choice = nullptr;
-    std::string err;
-    int64_t near_limit = -1;          // PSL_OPT_NEAR_LIMIT
-    // timing
-    bool timing = false;
-    std::vector<hipEvent_t> ev;       // 3 per recorded step: eval start, eval end, step end
-    double eval_ms = 0.0, rest_ms = 0.0;
-    uint64_t eval_launches = 0, steps_timed = 0;
-};
-
-namespace {
+namespace psl_rt {
 
 psl_status fail(psl_ctx *ctx, psl_status st, const char *fmt, ...)
 {
@@ -136,12 +18,7 @@ psl_status fail(psl_ctx *ctx, psl_status st, const char *fmt, ...)
     return st;
 }
 
-#define HIP_TRY(ctx, expr)                                                              \
-    do {                                                                                \
-        hipError_t e_ = (expr);                                                         \
-        if (e_ != hipSuccess)                                                           \
-            return fail((ctx), PSL_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));      \
-    } while (0)
+
 
 psl_status dev_alloc(psl_ctx *ctx, void **p, size_t bytes, bool from_arena)
 {
@@ -359,12 +236,7 @@ psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t 
         e.tiles = tiles[b];
         e.n_lmt = n_l[b];
         e.start = fixed ? start_fixed : 0;
-        {
-            const uint32_t Lb = ctx->walks[ids[b]].L;
-            const uint32_t autol = std::min<uint32_t>(kNearCap, std::max<uint32_t>(64, Lb / 16));
-            e.near_lim = ctx->near_limit < 0 ? autol
-                                             : (uint32_t)std::min<int64_t>(ctx->near_limit, kNearCap);
-        }
+        e.near_lim = near_limit_for(ctx, ctx->walks[ids[b]].L);
         e.fixed = fixed ? 1 : 0;
         op += (size_t)ks[b] * n_l[b];
         oc += n_l[b];
@@ -380,6 +252,43 @@ psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t 
                            hipMemcpyHostToDevice));
     pl.n_items = (uint32_t)items.size();
     return PSL_OK;
+}
+
+SlabLayout slab_layout(uint32_t L)
+{
+    const uint32_t nw = (L + 63) / 64;
+    SlabLayout s;
+    s.bits_bytes = align_up(sizeof(uint64_t) * nw, 256);
+    s.guard_bytes = sizeof(uint64_t) * guard_words(nw);
+    s.pivot_bytes = align_up(2 * s.guard_bytes + sizeof(uint64_t) * nw, 256);
+    s.slab_bytes = s.pivot_bytes + 2 * s.bits_bytes + align_up(sizeof(int32_t) * L, 256);
+    return s;
+}
+
+void fill_walk(WalkDev &w, const psl_walk_cfg &cfg, uint64_t seed, void *slab, const SlabLayout &lay)
+{
+    memset(&w, 0, sizeof w);
+    char *base = (char *)slab;
+    w.pivot = (uint64_t *)(base + lay.guard_bytes);
+    w.local_best = (uint64_t *)(base + lay.pivot_bytes);
+    w.best = (uint64_t *)(base + lay.pivot_bytes + lay.bits_bytes);
+    w.C = (int32_t *)(base + lay.pivot_bytes + 2 * lay.bits_bytes);
+    w.seed = seed;
+    w.L = cfg.L;
+    w.nw = (cfg.L + 63) / 64;
+    w.alpha1 = cfg.alpha1;
+    w.alpha2 = cfg.alpha2;
+    w.alpha = cfg.alpha1;
+    w.n_lmt = cfg.n_lmt ? cfg.n_lmt : cfg.L;
+    w.ls_lmt = cfg.ls_lmt;
+    w.flip_lmt = cfg.flip_lmt;
+    w.switch_period = cfg.switch_period;
+}
+
+uint32_t near_limit_for(const psl_ctx *ctx, uint32_t L)
+{
+    const uint32_t autol = std::min<uint32_t>(kNearCap, std::max<uint32_t>(64, L / 16));
+    return ctx->near_limit < 0 ? autol : (uint32_t)std::min<int64_t>(ctx->near_limit, kNearCap);
 }
 
 psl_status check_cfg(psl_ctx *ctx, const psl_walk_cfg *c)
@@ -441,7 +350,7 @@ psl_status single_plan(psl_ctx *ctx, uint32_t walk, BatchPlan &pl)
     return make_plan(ctx, pl, &walk, 1, UINT32_MAX, 0);
 }
 
-}  // namespace
+}  // namespace psl_rt
 
 // ================================================================= C-ABI
 
@@ -486,6 +395,7 @@ psl_status psl_ctx_create(int device, void *hip_stream, void *arena, size_t aren
 void psl_ctx_destroy(psl_ctx *ctx)
 {
     if (!ctx) return;
+    serve_shutdown(ctx);
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     for (auto &h : ctx->walks)
@@ -513,6 +423,7 @@ psl_status psl_init_walks(psl_ctx *ctx, const psl_walk_cfg *cfg, uint32_t n,
                           const uint64_t *const *init_bits, uint32_t *walk_ids_out)
 {
     if (!ctx) return PSL_E_INVAL;
+    if (serve_active(ctx)) return fail(ctx, PSL_E_STATE, "the context is serving");
     psl_status st = check_cfg(ctx, cfg);
     if (st) return st;
     if (n == 0) return PSL_OK;
@@ -521,10 +432,8 @@ psl_status psl_init_walks(psl_ctx *ctx, const psl_walk_cfg *cfg, uint32_t n,
     if ((st = ensure_tables(ctx, cfg->L))) return st;
 
     const uint32_t L = cfg->L, nw = (L + 63) / 64;
-    const size_t bits_bytes = align_up(sizeof(uint64_t) * nw, 256);
-    const size_t guard_bytes = sizeof(uint64_t) * guard_words(nw);
-    const size_t pivot_bytes = align_up(2 * guard_bytes + sizeof(uint64_t) * nw, 256);
-    const size_t slab_bytes = pivot_bytes + 2 * bits_bytes + align_up(sizeof(int32_t) * L, 256);
+    const SlabLayout lay = slab_layout(L);
+    const size_t slab_bytes = lay.slab_bytes;
 
     // slots
     std::vector<uint32_t> ids(n);
@@ -565,24 +474,9 @@ psl_status psl_init_walks(psl_ctx *ctx, const psl_walk_cfg *cfg, uint32_t n,
         h.slab = slab;
         h.slab_bytes = slab_bytes;
         WalkDev &w = wd[b];
-        memset(&w, 0, sizeof w);
-        char *base = (char *)slab;
         // the pivot sits between zeroed guard words (see guard_words)
         HIP_TRY(ctx, hipMemsetAsync(slab, 0, slab_bytes, ctx->stream));
-        w.pivot = (uint64_t *)(base + guard_bytes);
-        w.local_best = (uint64_t *)(base + pivot_bytes);
-        w.best = (uint64_t *)(base + pivot_bytes + bits_bytes);
-        w.C = (int32_t *)(base + pivot_bytes + 2 * bits_bytes);
-        w.seed = cfg->seed + b;
-        w.L = L;
-        w.nw = nw;
-        w.alpha1 = cfg->alpha1;
-        w.alpha2 = cfg->alpha2;
-        w.alpha = cfg->alpha1;
-        w.n_lmt = h.n_lmt;
-        w.ls_lmt = cfg->ls_lmt;
-        w.flip_lmt = cfg->flip_lmt;
-        w.switch_period = cfg->switch_period;
+        fill_walk(w, *cfg, cfg->seed + b, slab, lay);
         const uint64_t *given = init_bits ? init_bits[b] : nullptr;
         want[b] = given ? 0u : 1u;
         if (given) {
@@ -632,6 +526,7 @@ psl_status psl_init_walks(psl_ctx *ctx, const psl_walk_cfg *cfg, uint32_t n,
 psl_status psl_free_walks(psl_ctx *ctx, const uint32_t *walk_ids, uint32_t n)
 {
     if (!ctx || (n && !walk_ids)) return PSL_E_INVAL;
+    if (serve_active(ctx)) return fail(ctx, PSL_E_STATE, "the context is serving");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     psl_status st = PSL_OK;
@@ -654,6 +549,7 @@ psl_status psl_eval_neighbourhood(psl_ctx *ctx, uint32_t walk, uint32_t start, u
                                   double *F_dev, int32_t *psl_dev, psl_choice *out)
 {
     if (!ctx) return PSL_E_INVAL;
+    if (serve_active(ctx)) return fail(ctx, PSL_E_STATE, "the context is serving");
     if (!walk_ok(ctx, walk)) return fail(ctx, PSL_E_STATE, "unknown walk %u", walk);
     const WalkHost &h = ctx->walks[walk];
     if (n_lmt < 1 || n_lmt > h.L || start >= h.L)
@@ -687,6 +583,7 @@ psl_status psl_eval_neighbourhood(psl_ctx *ctx, uint32_t walk, uint32_t start, u
 psl_status psl_apply_flip(psl_ctx *ctx, uint32_t walk, uint32_t j)
 {
     if (!ctx) return PSL_E_INVAL;
+    if (serve_active(ctx)) return fail(ctx, PSL_E_STATE, "the context is serving");
     if (!walk_ok(ctx, walk)) return fail(ctx, PSL_E_STATE, "unknown walk %u", walk);
     const WalkHost &h = ctx->walks[walk];
     if (j >= h.L) return fail(ctx, PSL_E_INVAL, "j=%u >= L=%u", j, h.L);
@@ -714,6 +611,7 @@ psl_status psl_step_batch(psl_ctx *ctx, const uint32_t *walk_ids, uint32_t n, ui
                           uint32_t flags)
 {
     if (!ctx) return PSL_E_INVAL;
+    if (serve_active(ctx)) return fail(ctx, PSL_E_STATE, "the context is serving");
     if (n == 0 || steps == 0) return PSL_OK;
     if (!walk_ids) return fail(ctx, PSL_E_INVAL, "walk_ids is NULL");
     std::vector<uint32_t> sorted(walk_ids, walk_ids + n);
@@ -761,6 +659,7 @@ psl_status psl_read_walk(psl_ctx *ctx, uint32_t walk, psl_walk_state *out, uint6
                          uint64_t *local_best_bits, uint64_t *best_bits, int32_t *C)
 {
     if (!ctx) return PSL_E_INVAL;
+    if (serve_active(ctx)) return fail(ctx, PSL_E_STATE, "the context is serving");
     if (!walk_ok(ctx, walk)) return fail(ctx, PSL_E_STATE, "unknown walk %u", walk);
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
@@ -800,6 +699,7 @@ psl_status psl_read_walk(psl_ctx *ctx, uint32_t walk, psl_walk_state *out, uint6
 psl_status psl_timing_enable(psl_ctx *ctx, int on)
 {
     if (!ctx) return PSL_E_INVAL;
+    if (serve_active(ctx)) return fail(ctx, PSL_E_STATE, "the context is serving");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     timing_drop(ctx);
@@ -826,6 +726,7 @@ psl_status psl_timing_read(psl_ctx *ctx, psl_timing *out)
 psl_status psl_set_option(psl_ctx *ctx, int option, int64_t value)
 {
     if (!ctx) return PSL_E_INVAL;
+    if (serve_active(ctx)) return fail(ctx, PSL_E_STATE, "the context is serving");
     if (option != PSL_OPT_NEAR_LIMIT || value < -1)
         return fail(ctx, PSL_E_INVAL, "option %d value %lld", option, (long long)value);
     HIP_TRY(ctx, hipSetDevice(ctx->device));

@@ -1,0 +1,705 @@
+// psl_serve.hip -- the request loop of libpsl (psl_serve_* in include/psl.h).
+//
+// One host thread owns the context's stream while serving. Each iteration it
+//   1. takes submitted jobs into a FIFO,
+//   2. finishes retiring jobs whose read-back has landed,
+//   3. admits jobs from the FIFO head while the HBM budget and slots allow
+//      (zeroed slab, walk record, then one batched init launch),
+//   4. advances every admitted walk by one step of Algorithm 1 with the same
+//      launch sequence psl_step_batch uses (the batch is whatever is admitted:
+//      continuous batching), and
+//   5. retires the walks that reached their budget: their record and best
+//      sequence are copied to pinned host memory behind an event, and their
+//      slab and slot are released (later reuse is ordered after the copy on
+//      the same stream).
+// No step waits on the host: at most two iterations are in flight, and the
+// host only waits for the iteration two back before reusing its staging.
+#include "psl_internal.h"
+
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <thread>
+
+using namespace psl;
+
+namespace psl_rt {
+
+namespace {
+
+uint64_t now_ns()
+{
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Upper bound of the evaluation scratch one walk can need in a batch (the
+// number of k-splits grows only while the batch has few candidate tiles).
+size_t scratch_bound(uint32_t L, uint32_t n_lmt)
+{
+    const uint64_t tiles = (n_lmt + kEvalThreads - 1) / kEvalThreads;
+    const uint64_t ks_max = std::max<uint64_t>(1, ((L - 1 + 31) / 32) / (kTileK / 32));
+    const uint64_t ks = std::min<uint64_t>(ks_max, (4096 + tiles - 1) / tiles);
+    return (size_t)(12ull * ks * n_lmt + 12ull * n_lmt + 12ull * (L + 1) +
+                    4ull * (kNearCap + 1) + sizeof(BatchEntry) + sizeof(EvalItem) * ks * tiles);
+}
+
+size_t job_footprint(const psl_walk_cfg &c)
+{
+    return slab_layout(c.L).slab_bytes + scratch_bound(c.L, c.n_lmt ? c.n_lmt : c.L);
+}
+
+struct Job {
+    uint64_t ticket = 0;
+    psl_walk_cfg cfg{};
+    uint64_t budget = 0;
+    uint64_t *best_out = nullptr;
+    uint64_t t_arrive = 0, t_admit = 0;
+    size_t foot = 0;
+    uint32_t slot = UINT32_MAX;
+    void *slab = nullptr;
+    WalkDev dev{};            // device pointers of the walk
+    uint64_t steps = 0;
+    char *host = nullptr;     // pinned read-back: WalkDev, then best bits
+    size_t host_bytes = 0;
+    hipEvent_t ev = nullptr;
+};
+
+// Grow-only device buffer.
+template <class T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t cap = 0;
+};
+
+}  // namespace
+
+struct Server {
+    psl_serve_cfg cfg{};
+    psl_ctx *ctx = nullptr;
+    std::thread th;
+    // shared with submitters (mu)
+    std::mutex mu;
+    std::condition_variable cv;
+    bool stop = false, drain = false, running = false;
+    std::deque<Job> incoming;
+    std::map<uint64_t, psl_job_result> done;
+    std::map<uint64_t, int> live;               // tickets queued, running or retiring
+    uint64_t next_ticket = 1;
+    psl_serve_stats stats{};
+    // scheduler-owned
+    std::deque<Job> pending;
+    std::vector<Job> active, retiring;
+    size_t used = 0;
+    char *arena_mem = nullptr;
+    Arena arena;
+    DevBuf<BatchEntry> d_batch, d_admit;
+    DevBuf<EvalItem> d_items;
+    DevBuf<double> d_fpart, d_f, d_s0;
+    DevBuf<uint32_t> d_mpart, d_m0, d_near, d_want;
+    DevBuf<int32_t> d_p;
+    uint32_t n_items = 0, max_L = 0;
+    bool dirty = true;
+    // pinned staging, two halves used by alternate iterations
+    char *stage[2] = {nullptr, nullptr};
+    size_t stage_cap[2] = {0, 0};
+    hipEvent_t stage_ev[2] = {nullptr, nullptr};
+    bool stage_used[2] = {false, false};
+    int cur = 0;
+    std::multimap<size_t, char *> pinned_free;  // read-back buffers by size
+    uint64_t busy_from = 0;
+
+    void run();
+    psl_status ensure_stage(size_t need);
+    psl_status iterate();
+    psl_status upload_layout(char *&sp, char *stage_end);
+    psl_status admit(char *&sp, char *stage_end);
+    void retire_finished();
+    void fail_all(int32_t status);
+    void finish(Job &j, int32_t status);
+};
+
+namespace {
+
+template <class T>
+psl_status grow(psl_ctx *ctx, DevBuf<T> &b, size_t n)
+{
+    if (n <= b.cap) return PSL_OK;
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    dev_free(ctx, b.p, false);
+    b.p = nullptr;
+    b.cap = 0;
+    size_t c = std::max<size_t>(n + n / 2, 1024);
+    void *p;
+    psl_status st = dev_alloc(ctx, &p, sizeof(T) * c, false);
+    if (st) return st;
+    b.p = (T *)p;
+    b.cap = c;
+    return PSL_OK;
+}
+
+template <class T>
+void release(psl_ctx *ctx, DevBuf<T> &b)
+{
+    dev_free(ctx, b.p, false);
+    b = DevBuf<T>();
+}
+
+psl_status pinned(psl_ctx *ctx, Server &s, size_t bytes, char **out)
+{
+    auto it = s.pinned_free.lower_bound(bytes);
+    if (it != s.pinned_free.end() && it->first <= 2 * bytes) {
+        *out = it->second;
+        s.pinned_free.erase(it);
+        return PSL_OK;
+    }
+    void *p = nullptr;
+    HIP_TRY(ctx, hipHostMalloc(&p, bytes, hipHostMallocDefault));
+    *out = (char *)p;
+    return PSL_OK;
+}
+
+}  // namespace
+
+void Server::finish(Job &j, int32_t status)
+{
+    psl_job_result r;
+    memset(&r, 0, sizeof r);
+    r.status = status;
+    r.t_arrive_ns = j.t_arrive;
+    r.t_admit_ns = j.t_admit;
+    r.t_done_ns = now_ns();
+    r.steps = j.steps;
+    if (status == PSL_OK && j.host) {
+        WalkDev w;
+        memcpy(&w, j.host, sizeof w);
+        r.psl_best = w.psl_best;
+        r.psl_final = w.psl_pivot;
+        r.alpha_final = w.alpha;
+        r.F_final = w.F_pivot;
+        r.steps = w.t;
+        if (j.best_out) memcpy(j.best_out, j.host + sizeof(WalkDev), 8ull * w.nw);
+    }
+    if (j.host) pinned_free.emplace(j.host_bytes, j.host);
+    if (j.ev) (void)hipEventDestroy(j.ev);
+    j.host = nullptr;
+    j.ev = nullptr;
+    std::lock_guard<std::mutex> g(mu);
+    done[j.ticket] = r;
+    live.erase(j.ticket);
+    if (status == PSL_OK) stats.completed++;
+    else stats.failed++;
+}
+
+void Server::fail_all(int32_t status)
+{
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipGetLastError();
+    for (auto &j : retiring) finish(j, status);
+    retiring.clear();
+    for (auto &j : active) {
+        if (j.slab) arena.release(j.slab);
+        if (j.slot != UINT32_MAX) {
+            ctx->walks[j.slot] = WalkHost();
+            ctx->free_slots.push_back(j.slot);
+        }
+        finish(j, status);
+    }
+    active.clear();
+    used = 0;
+    dirty = true;
+}
+
+void Server::retire_finished()
+{
+    for (size_t x = 0; x < retiring.size();) {
+        if (hipEventQuery(retiring[x].ev) == hipSuccess) {
+            finish(retiring[x], PSL_OK);
+            retiring.erase(retiring.begin() + x);
+        } else {
+            ++x;
+        }
+    }
+}
+
+// Admits jobs from the FIFO head; their walk records and the batched init
+// arrays go through the staging buffer.
+psl_status Server::admit(char *&sp, char *stage_end)
+{
+    std::vector<Job> adm;
+    while (!pending.empty()) {
+        Job &j = pending.front();
+        if (active.size() + adm.size() >= cfg.max_slots) break;
+        if (used + j.foot > cfg.hbm_budget) break;      // strict FIFO: no overtaking
+        const SlabLayout lay = slab_layout(j.cfg.L);
+        void *slab = arena.alloc(lay.slab_bytes);
+        if (!slab) break;
+        j.slab = slab;
+        used += j.foot;
+        adm.push_back(std::move(j));
+        pending.pop_front();
+    }
+    if (adm.empty()) return PSL_OK;
+    const size_t need = adm.size() * (sizeof(WalkDev) + sizeof(BatchEntry) + sizeof(uint32_t)) + 64;
+    if ((size_t)(stage_end - sp) < need) {
+        // put them back in order; admitted next iteration
+        for (auto it = adm.rbegin(); it != adm.rend(); ++it) {
+            arena.release(it->slab);
+            used -= it->foot;
+            it->slab = nullptr;
+            pending.push_front(std::move(*it));
+        }
+        return PSL_OK;
+    }
+    psl_status st;
+    if ((st = grow(ctx, d_admit, adm.size()))) return st;
+    if ((st = grow(ctx, d_want, adm.size()))) return st;
+    uint32_t maxL = 0, maxnw = 0;
+    BatchEntry *be = (BatchEntry *)sp;
+    sp += sizeof(BatchEntry) * adm.size();
+    uint32_t *want = (uint32_t *)sp;
+    sp += sizeof(uint32_t) * adm.size();
+    sp = (char *)(((uintptr_t)sp + 63) & ~(uintptr_t)63);
+    const uint64_t t = now_ns();
+    for (size_t b = 0; b < adm.size(); ++b) {
+        Job &j = adm[b];
+        uint32_t slot;
+        if (!ctx->free_slots.empty()) {
+            slot = ctx->free_slots.back();
+            ctx->free_slots.pop_back();
+        } else {
+            slot = (uint32_t)ctx->walks.size();
+            ctx->walks.push_back(WalkHost());
+        }
+        if (slot >= ctx->walk_cap) return fail(ctx, PSL_E_STATE, "walk capacity exceeded");
+        j.slot = slot;
+        const SlabLayout lay = slab_layout(j.cfg.L);
+        WalkHost &h = ctx->walks[slot];
+        h.active = true;
+        h.L = j.cfg.L;
+        h.nw = (j.cfg.L + 63) / 64;
+        h.n_lmt = j.cfg.n_lmt ? j.cfg.n_lmt : j.cfg.L;
+        h.slab = j.slab;
+        h.slab_bytes = lay.slab_bytes;
+        WalkDev *wd = (WalkDev *)sp;
+        sp += sizeof(WalkDev);
+        fill_walk(*wd, j.cfg, j.cfg.seed, j.slab, lay);
+        j.dev = *wd;
+        HIP_TRY(ctx, hipMemsetAsync(j.slab, 0, lay.slab_bytes, ctx->stream));
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->d_walks + slot, wd, sizeof(WalkDev), hipMemcpyHostToDevice,
+                                    ctx->stream));
+        memset(&be[b], 0, sizeof(BatchEntry));
+        be[b].slot = slot;
+        want[b] = 1;
+        maxL = std::max(maxL, j.cfg.L);
+        maxnw = std::max(maxnw, h.nw);
+        j.t_admit = t;
+    }
+    const uint32_t n = (uint32_t)adm.size();
+    HIP_TRY(ctx, hipMemcpyAsync(d_admit.p, be, sizeof(BatchEntry) * n, hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(d_want.p, want, sizeof(uint32_t) * n, hipMemcpyHostToDevice, ctx->stream));
+    const Tables tabs = tables_of(ctx);
+    HIP_TRY(ctx, launch_init_bits(ctx->d_walks, d_admit.p, d_want.p, n, maxnw, ctx->stream));
+    HIP_TRY(ctx, launch_corr(ctx->d_walks, d_admit.p, n, maxL, 0, ctx->stream));
+    HIP_TRY(ctx, launch_fitness(ctx->d_walks, d_admit.p, n, tabs, 0, ctx->stream));
+    for (auto &j : adm) active.push_back(std::move(j));
+    dirty = true;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        stats.peak_active = std::max<uint64_t>(stats.peak_active, active.size());
+        stats.peak_used = std::max<uint64_t>(stats.peak_used, used);
+    }
+    return PSL_OK;
+}
+
+// Lays out the admitted batch: entries, eval work items and scratch.
+psl_status Server::upload_layout(char *&sp, char *stage_end)
+{
+    const uint32_t n = (uint32_t)active.size();
+    uint64_t total_tiles = 0;
+    max_L = 0;
+    for (auto &j : active) {
+        const uint32_t nl = j.cfg.n_lmt ? j.cfg.n_lmt : j.cfg.L;
+        total_tiles += (nl + kEvalThreads - 1) / kEvalThreads;
+        max_L = std::max(max_L, j.cfg.L);
+    }
+    std::vector<uint32_t> tiles(n), ks(n);
+    size_t n_part = 0, n_cand = 0, n_suf = 0, items = 0;
+    for (uint32_t b = 0; b < n; ++b) {
+        const Job &j = active[b];
+        const uint32_t nl = j.cfg.n_lmt ? j.cfg.n_lmt : j.cfg.L;
+        eval_shape(j.cfg.L, nl, (uint32_t)std::min<uint64_t>(total_tiles, 1u << 30), &tiles[b], &ks[b]);
+        n_part += (size_t)ks[b] * nl;
+        n_cand += nl;
+        n_suf += j.cfg.L + 1;
+        items += (size_t)tiles[b] * ks[b];
+    }
+    const size_t need = sizeof(BatchEntry) * n + sizeof(EvalItem) * items + 128;
+    if ((size_t)(stage_end - sp) < need) return fail(ctx, PSL_E_NOMEM, "serving staging too small");
+    psl_status st;
+    if ((st = grow(ctx, d_batch, n)) || (st = grow(ctx, d_items, items)) ||
+        (st = grow(ctx, d_fpart, n_part)) || (st = grow(ctx, d_mpart, n_part)) ||
+        (st = grow(ctx, d_f, n_cand)) || (st = grow(ctx, d_p, n_cand)) ||
+        (st = grow(ctx, d_s0, n_suf)) || (st = grow(ctx, d_m0, n_suf)) ||
+        (st = grow(ctx, d_near, (size_t)(kNearCap + 1) * n)))
+        return st;
+    BatchEntry *be = (BatchEntry *)sp;
+    sp += sizeof(BatchEntry) * n;
+    sp = (char *)(((uintptr_t)sp + 15) & ~(uintptr_t)15);
+    EvalItem *it = (EvalItem *)sp;
+    sp += sizeof(EvalItem) * items;
+    sp = (char *)(((uintptr_t)sp + 63) & ~(uintptr_t)63);
+    size_t op = 0, oc = 0, os = 0, oi = 0;
+    for (uint32_t b = 0; b < n; ++b) {
+        const Job &j = active[b];
+        const uint32_t nl = j.cfg.n_lmt ? j.cfg.n_lmt : j.cfg.L;
+        BatchEntry &e = be[b];
+        memset(&e, 0, sizeof e);
+        e.Fpart = d_fpart.p + op;
+        e.Mpart = d_mpart.p + op;
+        e.F = d_f.p + oc;
+        e.P = d_p.p + oc;
+        e.S0 = d_s0.p + os;
+        e.M0 = d_m0.p + os;
+        e.near = d_near.p + (size_t)(kNearCap + 1) * b;
+        e.slot = j.slot;
+        e.ksplit = ks[b];
+        e.tiles = tiles[b];
+        e.n_lmt = nl;
+        e.near_lim = near_limit_for(ctx, j.cfg.L);
+        op += (size_t)ks[b] * nl;
+        oc += nl;
+        os += j.cfg.L + 1;
+        for (uint32_t t = 0; t < tiles[b]; ++t)
+            for (uint32_t s = 0; s < ks[b]; ++s) it[oi++] = EvalItem{b, t, s, 0};
+    }
+    HIP_TRY(ctx, hipMemcpyAsync(d_batch.p, be, sizeof(BatchEntry) * n, hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(d_items.p, it, sizeof(EvalItem) * items, hipMemcpyHostToDevice,
+                                ctx->stream));
+    n_items = (uint32_t)items;
+    dirty = false;
+    return PSL_OK;
+}
+
+// Both staging halves hold at least `need` bytes (growing waits for the
+// stream, so no copy still reads the old buffers).
+psl_status Server::ensure_stage(size_t need)
+{
+    if (need <= stage_cap[0] && need <= stage_cap[1]) return PSL_OK;
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    const size_t bytes = need + need / 2;
+    for (int h = 0; h < 2; ++h) {
+        if (stage[h]) (void)hipHostFree(stage[h]);
+        stage[h] = nullptr;
+        stage_cap[h] = 0;
+        stage_used[h] = false;
+        HIP_TRY(ctx, hipHostMalloc((void **)&stage[h], bytes, hipHostMallocDefault));
+        stage_cap[h] = bytes;
+    }
+    return PSL_OK;
+}
+
+psl_status Server::iterate()
+{
+    psl_status st;
+    // staging half of this iteration: wait for its use two iterations back
+    if (stage_used[cur]) {
+        HIP_TRY(ctx, hipEventSynchronize(stage_ev[cur]));
+        stage_used[cur] = false;
+    }
+    retire_finished();
+    {
+        // worst case of this iteration's uploads: admissions, then the layout
+        // (work items <= 4096 + candidate tiles, see eval_shape)
+        const size_t n_adm = std::min<size_t>(pending.size(), cfg.max_slots);
+        uint64_t tiles = 0;
+        for (auto &j : active) tiles += ((j.cfg.n_lmt ? j.cfg.n_lmt : j.cfg.L) + kEvalThreads - 1) / kEvalThreads;
+        for (size_t x = 0; x < n_adm; ++x) {
+            const Job &j = pending[x];
+            tiles += ((j.cfg.n_lmt ? j.cfg.n_lmt : j.cfg.L) + kEvalThreads - 1) / kEvalThreads;
+        }
+        const size_t need = (n_adm + active.size()) * (sizeof(WalkDev) + 2 * sizeof(BatchEntry) + 8) +
+                            sizeof(EvalItem) * (4096 + tiles) + 4096;
+        if ((st = ensure_stage(need))) return st;
+    }
+    char *sp = stage[cur];
+    char *se = stage[cur] + stage_cap[cur];
+    if ((st = admit(sp, se))) return st;
+    if (active.empty()) return PSL_OK;
+    if (dirty && (st = upload_layout(sp, se))) return st;
+    const uint32_t n = (uint32_t)active.size();
+    const Tables tabs = tables_of(ctx);
+    HIP_TRY(ctx, launch_suffix(ctx->d_walks, d_batch.p, n, tabs, ctx->stream));
+    HIP_TRY(ctx, launch_eval(ctx->d_walks, d_batch.p, d_items.p, n_items, tabs, ctx->stream));
+    HIP_TRY(ctx, launch_select(ctx->d_walks, d_batch.p, n, tabs, 0, nullptr, ctx->stream));
+    HIP_TRY(ctx, launch_apply(ctx->d_walks, d_batch.p, n, max_L, -1, ctx->stream));
+    HIP_TRY(ctx, launch_bookkeep(ctx->d_walks, d_batch.p, n, ctx->stream));
+    HIP_TRY(ctx, launch_corr(ctx->d_walks, d_batch.p, n, max_L, 1, ctx->stream));
+    HIP_TRY(ctx, launch_fitness(ctx->d_walks, d_batch.p, n, tabs, 1, ctx->stream));
+    uint64_t evals = 0, upd = 0;
+    for (auto &j : active) {
+        const uint64_t nl = j.cfg.n_lmt ? j.cfg.n_lmt : j.cfg.L;
+        evals += nl;
+        upd += nl * (j.cfg.L - 1);
+        j.steps++;
+    }
+    // retire walks that reached their budget
+    for (size_t x = 0; x < active.size();) {
+        Job &j = active[x];
+        if (j.steps < j.budget) {
+            ++x;
+            continue;
+        }
+        const size_t bytes = sizeof(WalkDev) + 8ull * ((j.cfg.L + 63) / 64);
+        if ((st = pinned(ctx, *this, bytes, &j.host))) return st;
+        j.host_bytes = bytes;
+        HIP_TRY(ctx, hipMemcpyAsync(j.host, ctx->d_walks + j.slot, sizeof(WalkDev), hipMemcpyDeviceToHost,
+                                    ctx->stream));
+        HIP_TRY(ctx, hipMemcpyAsync(j.host + sizeof(WalkDev), j.dev.best, 8ull * ((j.cfg.L + 63) / 64),
+                                    hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(ctx, hipEventCreateWithFlags(&j.ev, hipEventDisableTiming));
+        HIP_TRY(ctx, hipEventRecord(j.ev, ctx->stream));
+        arena.release(j.slab);
+        used -= j.foot;
+        j.slab = nullptr;
+        ctx->walks[j.slot] = WalkHost();
+        ctx->free_slots.push_back(j.slot);
+        retiring.push_back(std::move(j));
+        active.erase(active.begin() + x);
+        dirty = true;
+    }
+    HIP_TRY(ctx, hipEventRecord(stage_ev[cur], ctx->stream));
+    stage_used[cur] = true;
+    cur ^= 1;
+    std::lock_guard<std::mutex> g(mu);
+    stats.iterations++;
+    stats.flip_evals += evals;
+    stats.ck_updates += upd;
+    return PSL_OK;
+}
+
+void Server::run()
+{
+    (void)hipSetDevice(ctx->device);
+    for (;;) {
+        bool idle;
+        {
+            std::unique_lock<std::mutex> g(mu);
+            while (!incoming.empty()) {
+                pending.push_back(std::move(incoming.front()));
+                incoming.pop_front();
+            }
+            if (stop && !drain) break;
+            idle = pending.empty() && active.empty();
+            if (stop && idle && retiring.empty()) break;
+            if (idle && retiring.empty()) {
+                if (busy_from) {
+                    stats.busy_s += (now_ns() - busy_from) * 1e-9;
+                    busy_from = 0;
+                }
+                cv.wait_for(g, std::chrono::milliseconds(2));
+                continue;
+            }
+            if (!idle && !busy_from) busy_from = now_ns();
+            stats.active = active.size();
+            stats.queued = pending.size();
+        }
+        if (idle) {
+            // only read-backs in flight
+            retire_finished();
+            std::this_thread::sleep_for(std::chrono::microseconds(200));
+            continue;
+        }
+        if (iterate() != PSL_OK) fail_all(PSL_E_HIP);
+    }
+    // cancel what is left (drain == 0) and settle read-backs
+    (void)hipStreamSynchronize(ctx->stream);
+    retire_finished();
+    for (auto &j : retiring) finish(j, PSL_OK);
+    retiring.clear();
+    for (auto &j : active) {
+        if (j.slab) arena.release(j.slab);
+        ctx->walks[j.slot] = WalkHost();
+        ctx->free_slots.push_back(j.slot);
+        finish(j, PSL_E_STATE);
+    }
+    active.clear();
+    for (auto &j : pending) finish(j, PSL_E_STATE);
+    pending.clear();
+    std::lock_guard<std::mutex> g(mu);
+    if (busy_from) stats.busy_s += (now_ns() - busy_from) * 1e-9;
+    busy_from = 0;
+    stats.active = stats.queued = 0;
+    running = false;
+}
+
+bool serve_active(psl_ctx *ctx)
+{
+    Server *s = ctx->server;
+    if (!s) return false;
+    std::lock_guard<std::mutex> g(s->mu);
+    return s->running;
+}
+
+void serve_shutdown(psl_ctx *ctx)
+{
+    Server *s = ctx->server;
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->stop = true;
+        s->drain = false;
+    }
+    s->cv.notify_all();
+    if (s->th.joinable()) s->th.join();
+    (void)hipStreamSynchronize(ctx->stream);
+    release(ctx, s->d_batch);
+    release(ctx, s->d_admit);
+    release(ctx, s->d_items);
+    release(ctx, s->d_fpart);
+    release(ctx, s->d_f);
+    release(ctx, s->d_s0);
+    release(ctx, s->d_mpart);
+    release(ctx, s->d_m0);
+    release(ctx, s->d_near);
+    release(ctx, s->d_want);
+    release(ctx, s->d_p);
+    for (int h = 0; h < 2; ++h) {
+        if (s->stage[h]) (void)hipHostFree(s->stage[h]);
+        if (s->stage_ev[h]) (void)hipEventDestroy(s->stage_ev[h]);
+    }
+    for (auto &kv : s->pinned_free) (void)hipHostFree(kv.second);
+    if (s->arena_mem) (void)hipFree(s->arena_mem);
+    delete s;
+    ctx->server = nullptr;
+}
+
+}  // namespace psl_rt
+
+using namespace psl_rt;
+
+extern "C" {
+
+psl_status psl_serve_start(psl_ctx *ctx, const psl_serve_cfg *cfg)
+{
+    if (!ctx || !cfg) return PSL_E_INVAL;
+    if (cfg->max_slots < 1 || cfg->hbm_budget < 4096 || cfg->flags != 0)
+        return fail(ctx, PSL_E_INVAL, "serve cfg: max_slots=%u hbm_budget=%llu", cfg->max_slots,
+                    (unsigned long long)cfg->hbm_budget);
+    if (ctx->server) {
+        bool running;
+        {
+            std::lock_guard<std::mutex> g(ctx->server->mu);
+            running = ctx->server->running;
+        }
+        if (running) return fail(ctx, PSL_E_STATE, "already serving");
+        serve_shutdown(ctx);   // a stopped loop: drop its results
+    }
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    psl_status st;
+    if ((st = ensure_tables(ctx, PSL_L_MAX))) return st;
+    if ((st = ensure_walk_cap(ctx, (uint32_t)ctx->walks.size() + cfg->max_slots))) return st;
+    Server *s = new Server();
+    s->cfg = *cfg;
+    s->ctx = ctx;
+    // slabs come from one device region of the budget's size
+    if (hipMalloc((void **)&s->arena_mem, cfg->hbm_budget) != hipSuccess) {
+        (void)hipGetLastError();
+        delete s;
+        return fail(ctx, PSL_E_NOMEM, "serving arena of %llu bytes", (unsigned long long)cfg->hbm_budget);
+    }
+    s->arena.reset(s->arena_mem, cfg->hbm_budget);
+    const size_t stage_bytes = ((size_t)4 << 20) + (size_t)cfg->max_slots * 256;
+    for (int h = 0; h < 2; ++h) {
+        if (hipHostMalloc((void **)&s->stage[h], stage_bytes, hipHostMallocDefault) != hipSuccess ||
+            hipEventCreateWithFlags(&s->stage_ev[h], hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->server = s;
+            serve_shutdown(ctx);
+            return fail(ctx, PSL_E_HIP, "serving staging");
+        }
+        s->stage_cap[h] = stage_bytes;
+    }
+    s->running = true;
+    ctx->server = s;
+    s->th = std::thread([s] { s->run(); });
+    return PSL_OK;
+}
+
+psl_status psl_serve_submit(psl_ctx *ctx, const psl_job *job, uint64_t *ticket)
+{
+    if (!ctx || !job || !ticket) return PSL_E_INVAL;
+    Server *s = ctx->server;
+    if (!s) return PSL_E_STATE;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        if (!s->running || s->stop) return PSL_E_STATE;
+    }
+    const psl_walk_cfg &c = job->cfg;
+    if (c.L < 2 || c.L > PSL_L_MAX || c.alpha1 < 1 || c.alpha1 > PSL_ALPHA_MAX || c.alpha2 < 1 ||
+        c.alpha2 > PSL_ALPHA_MAX || c.n_lmt > c.L || c.flip_lmt > c.L || c.flip_lmt > PSL_FLIP_LMT_MAX ||
+        c.reserved != 0 || job->step_budget < 1)
+        return PSL_E_INVAL;
+    Job j;
+    j.cfg = c;
+    j.budget = job->step_budget;
+    j.best_out = job->best_bits_out;
+    j.t_arrive = now_ns();
+    j.foot = job_footprint(c);
+    if (j.foot > s->cfg.hbm_budget) return PSL_E_FULL;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        if (!s->running || s->stop) return PSL_E_STATE;
+        j.ticket = s->next_ticket++;
+        *ticket = j.ticket;
+        s->live[j.ticket] = 1;
+        s->incoming.push_back(std::move(j));
+        s->stats.submitted++;
+    }
+    s->cv.notify_one();
+    return PSL_OK;
+}
+
+psl_status psl_serve_poll(psl_ctx *ctx, uint64_t ticket, psl_job_result *out)
+{
+    if (!ctx || !out) return PSL_E_INVAL;
+    Server *s = ctx->server;
+    if (!s) return PSL_E_STATE;
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->done.find(ticket);
+    if (it != s->done.end()) {
+        *out = it->second;
+        s->done.erase(it);
+        return PSL_OK;
+    }
+    return s->live.count(ticket) ? PSL_E_AGAIN : PSL_E_STATE;
+}
+
+psl_status psl_serve_stats_read(psl_ctx *ctx, psl_serve_stats *out)
+{
+    if (!ctx || !out) return PSL_E_INVAL;
+    Server *s = ctx->server;
+    if (!s) return PSL_E_STATE;
+    std::lock_guard<std::mutex> g(s->mu);
+    *out = s->stats;
+    if (s->busy_from) out->busy_s += (now_ns() - s->busy_from) * 1e-9;
+    return PSL_OK;
+}
+
+psl_status psl_serve_stop(psl_ctx *ctx, int drain)
+{
+    if (!ctx) return PSL_E_INVAL;
+    Server *s = ctx->server;
+    if (!s) return PSL_E_STATE;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        if (!s->running && !s->th.joinable()) return PSL_OK;
+        s->stop = true;
+        s->drain = drain != 0;
+    }
+    s->cv.notify_all();
+    if (s->th.joinable()) s->th.join();
+    return PSL_OK;
+}
+
+}  // extern "C"

@@ -23,7 +23,8 @@ L_MAX = 1048575
 EXPORTS = ["psl_ctx_create", "psl_ctx_destroy", "psl_last_error", "psl_sync", "psl_init_walks",
            "psl_free_walks", "psl_eval_neighbourhood", "psl_apply_flip", "psl_step_batch",
            "psl_read_walk", "psl_eval_shape", "psl_version", "psl_timing_enable",
-           "psl_timing_read", "psl_set_option"]
+           "psl_timing_read", "psl_set_option", "psl_serve_start", "psl_serve_submit",
+           "psl_serve_poll", "psl_serve_stats_read", "psl_serve_stop"]
 OPT_NEAR_LIMIT = 1
 
 
@@ -60,6 +61,39 @@ class WalkState(ctypes.Structure):
                 ("unimproved", ctypes.c_uint32), ("last_k", ctypes.c_uint32),
                 ("last_value_step", ctypes.c_double), ("last_start", ctypes.c_uint32),
                 ("last_flags", ctypes.c_uint32)]
+
+    def as_dict(self) -> dict:
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class ServeCfg(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_uint64), ("max_slots", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32)]
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("cfg", WalkCfg), ("step_budget", ctypes.c_uint64),
+                ("best_bits_out", ctypes.c_void_p)]
+
+
+class JobResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("psl_best", ctypes.c_int32),
+                ("psl_final", ctypes.c_int32), ("alpha_final", ctypes.c_uint32),
+                ("F_final", ctypes.c_double), ("steps", ctypes.c_uint64),
+                ("t_arrive_ns", ctypes.c_uint64), ("t_admit_ns", ctypes.c_uint64),
+                ("t_done_ns", ctypes.c_uint64)]
+
+    def as_dict(self) -> dict:
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("failed", ctypes.c_uint64), ("active", ctypes.c_uint64),
+                ("queued", ctypes.c_uint64), ("iterations", ctypes.c_uint64),
+                ("flip_evals", ctypes.c_uint64), ("ck_updates", ctypes.c_uint64),
+                ("busy_s", ctypes.c_double), ("peak_active", ctypes.c_uint64),
+                ("peak_used", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -103,6 +137,11 @@ def lib() -> ctypes.CDLL:
         "psl_timing_enable": (i32, [P, ctypes.c_int]),
         "psl_timing_read": (i32, [P, ctypes.POINTER(Timing)]),
         "psl_set_option": (i32, [P, ctypes.c_int, ctypes.c_int64]),
+        "psl_serve_start": (i32, [P, ctypes.POINTER(ServeCfg)]),
+        "psl_serve_submit": (i32, [P, ctypes.POINTER(Job), ctypes.POINTER(u64)]),
+        "psl_serve_poll": (i32, [P, u64, ctypes.POINTER(JobResult)]),
+        "psl_serve_stats_read": (i32, [P, ctypes.POINTER(ServeStats)]),
+        "psl_serve_stop": (i32, [P, ctypes.c_int]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -240,6 +279,52 @@ class Context:
                                          ctypes.byref(k)))
         return int(t.value), int(k.value)
 
+
+    # ------------------------------------------------------------ serving
+
+    def serve_start(self, hbm_budget: int, max_slots: int):
+        self._served = {}
+        cfg = ServeCfg(hbm_budget=hbm_budget, max_slots=max_slots, flags=0)
+        self._check(lib().psl_serve_start(self._h, ctypes.byref(cfg)))
+
+    def serve_submit(self, L: int, seed: int, step_budget: int, alpha1: int = 4,
+                     alpha2: int = 13, n_lmt: int = 0, ls_lmt: int = 2000,
+                     flip_lmt: int | None = None, switch_period: int = 0,
+                     want_best: bool = True) -> int:
+        """Queue a job; returns its ticket. Raises PslError on a non-OK status."""
+        if flip_lmt is None:
+            flip_lmt = min(10, L)
+        best = np.zeros(n_words(L), np.uint64) if want_best else None
+        job = Job(cfg=WalkCfg(L=L, alpha1=alpha1, alpha2=alpha2, n_lmt=n_lmt, ls_lmt=ls_lmt,
+                              flip_lmt=flip_lmt, switch_period=switch_period, reserved=0,
+                              seed=seed & (2**64 - 1)),
+                  step_budget=step_budget, best_bits_out=best.ctypes.data if want_best else None)
+        t = ctypes.c_uint64()
+        st = lib().psl_serve_submit(self._h, ctypes.byref(job), ctypes.byref(t))
+        if st != OK:
+            raise PslError(st, "psl_serve_submit")
+        self._served[int(t.value)] = best      # the buffer lives until polled
+        return int(t.value)
+
+    def serve_poll(self, ticket: int):
+        """The job's result dict (with 'best' bits) when done, else None."""
+        r = JobResult()
+        st = lib().psl_serve_poll(self._h, ticket, ctypes.byref(r))
+        if st == E_AGAIN:
+            return None
+        if st != OK:
+            raise PslError(st, "psl_serve_poll")
+        d = r.as_dict()
+        d["best"] = self._served.pop(ticket, None)
+        return d
+
+    def serve_stats(self) -> dict:
+        s = ServeStats()
+        self._check(lib().psl_serve_stats_read(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def serve_stop(self, drain: bool = True):
+        self._check(lib().psl_serve_stop(self._h, 1 if drain else 0))
 
     def set_option(self, option: int, value: int):
         self._check(lib().psl_set_option(self._h, option, value))

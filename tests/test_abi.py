@@ -35,16 +35,21 @@ def test_struct_layouts_match_header(tmp_path):
     from paper_2107_09801_amd import libpsl
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "psl.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(psl_walk_cfg),'
-                   ' sizeof(psl_choice), sizeof(psl_walk_state), offsetof(psl_walk_state, t),'
-                   ' offsetof(psl_choice, F_min));return 0;}\n')
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n",'
+                   ' sizeof(psl_walk_cfg), sizeof(psl_choice), sizeof(psl_walk_state),'
+                   ' offsetof(psl_walk_state, t), offsetof(psl_choice, F_min), sizeof(psl_serve_cfg),'
+                   ' sizeof(psl_job), sizeof(psl_job_result), sizeof(psl_serve_stats),'
+                   ' sizeof(psl_timing));return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)],
                    check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
                                           check=True).stdout.split()]
     want = [ctypes.sizeof(libpsl.WalkCfg), ctypes.sizeof(libpsl.Choice),
-            ctypes.sizeof(libpsl.WalkState), libpsl.WalkState.t.offset, libpsl.Choice.F_min.offset]
+            ctypes.sizeof(libpsl.WalkState), libpsl.WalkState.t.offset, libpsl.Choice.F_min.offset,
+            ctypes.sizeof(libpsl.ServeCfg), ctypes.sizeof(libpsl.Job),
+            ctypes.sizeof(libpsl.JobResult), ctypes.sizeof(libpsl.ServeStats),
+            ctypes.sizeof(libpsl.Timing)]
     assert got == want
 
 

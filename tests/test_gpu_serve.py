@@ -1,0 +1,133 @@
+"""The request loop (psl_serve_*): continuous batching of jobs of different L
+and budgets. Each job's result equals the same walk run alone, small jobs
+equal the oracle, admission follows arrival order within the HBM budget, and
+the status codes follow the header."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import seeded_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+F_RTOL = 1e-12
+
+
+@pytest.fixture()
+def ctx():
+    import torch
+    from paper_2107_09801_amd import libpsl
+    assert torch.cuda.is_available()
+    c = libpsl.Context(0)
+    yield c
+    c.close()
+
+
+def _wait(ctx, tickets, timeout_s=120.0):
+    out, t0 = {}, time.time()
+    while len(out) < len(tickets):
+        for t in tickets:
+            if t not in out:
+                r = ctx.serve_poll(t)
+                if r is not None:
+                    out[t] = r
+        assert time.time() - t0 < timeout_s, "jobs did not finish"
+        time.sleep(0.002)
+    return out
+
+
+JOBS = [  # (L, seed, budget, n_lmt, alpha2, period)
+    (1001, 11, 30, 0, 13, 7), (63, 12, 45, 0, 13, 5), (16383, 13, 12, 256, 13, 50),
+    (4097, 14, 25, 1000, 11, 0), (2, 15, 9, 0, 4, 3), (131071, 16, 5, 256, 13, 50),
+    (777, 17, 60, 300, 10, 0), (65, 18, 33, 65, 13, 4), (30001, 19, 8, 0, 13, 50),
+]
+
+
+def test_served_results_equal_alone_and_oracle(ctx):
+    ctx.serve_start(hbm_budget=1 << 30, max_slots=64)
+    tickets = []
+    for i, (L, seed, budget, n_lmt, a2, period) in enumerate(JOBS):
+        tickets.append(ctx.serve_submit(L, seed, budget, alpha2=a2, n_lmt=n_lmt, ls_lmt=3,
+                                        switch_period=period))
+        if i % 3 == 2:
+            time.sleep(0.01)          # later jobs arrive while earlier ones run
+    res = _wait(ctx, tickets)
+    ctx.serve_stop(drain=True)
+    st = ctx.serve_stats()
+    assert st["completed"] == len(JOBS) and st["failed"] == 0
+    for t, (L, seed, budget, n_lmt, a2, period) in zip(tickets, JOBS):
+        r = res[t]
+        assert r["status"] == 0 and r["steps"] == budget
+        assert r["t_arrive_ns"] <= r["t_admit_ns"] <= r["t_done_ns"]
+        # the same walk alone, through the batched step
+        (w,) = ctx.init_walks(L, 1, seed, alpha2=a2, n_lmt=n_lmt, ls_lmt=3, switch_period=period)
+        ctx.step_batch([w], budget)
+        g = ctx.read_walk(w)
+        assert r["psl_best"] == g["psl_best"] and r["psl_final"] == g["psl_pivot"]
+        assert r["alpha_final"] == g["alpha"]
+        assert abs(r["F_final"] - g["F_pivot"]) <= F_RTOL * g["F_pivot"]
+        assert np.array_equal(r["best"], g["best"])
+        ctx.free_walks([w])
+        if L <= 4097:
+            ow = oracle.Walk(oracle.WalkConfig(L=L, seed=seed, alpha1=4, alpha2=a2, n_lmt=n_lmt or L,
+                                               ls_lmt=3, flip_lmt=min(10, L), switch_period=period),
+                             margin=5e-13, nthreads=8)
+            flagged = False
+            for _ in range(budget):
+                tr = ow.step()
+                flagged |= bool(tr["flags"] & (oracle.AMBIG_ARGMIN | oracle.AMBIG_COMPARE))
+            if not flagged:
+                o = ow.read()
+                assert r["psl_best"] == o["psl_best"] and np.array_equal(r["best"], o["best"])
+                assert r["psl_final"] == o["psl_pivot"]
+
+
+def test_admission_fifo_within_budget(ctx):
+    # room for three L=30001, N_lmt=256 jobs at a time (about 0.88 MB each:
+    # slab plus the evaluation scratch bound)
+    from paper_2107_09801_amd import libpsl
+    ctx.serve_start(hbm_budget=2_700_000, max_slots=64)
+    tickets = [ctx.serve_submit(30001, 100 + i, 6, n_lmt=256, switch_period=50) for i in range(10)]
+    res = _wait(ctx, tickets)
+    ctx.serve_stop(drain=True)
+    admits = [res[t]["t_admit_ns"] for t in tickets]
+    assert admits == sorted(admits)
+    st = ctx.serve_stats()
+    assert st["completed"] == 10
+    assert st["peak_used"] <= 2_700_000 and st["peak_active"] == 3
+    with pytest.raises(libpsl.PslError) as e:
+        ctx.serve_submit(30001, 1, 5)          # not serving any more
+    assert e.value.status == libpsl.E_STATE
+
+
+def test_status_codes_and_cancel(ctx):
+    from paper_2107_09801_amd import libpsl
+    ctx.serve_start(hbm_budget=32 << 20, max_slots=8)
+    with pytest.raises(libpsl.PslError) as e:
+        ctx.serve_submit(1048575, 1, 5)        # full neighbourhood of 2^20-1 needs more
+    assert e.value.status == libpsl.E_FULL
+    with pytest.raises(libpsl.PslError) as e:
+        ctx.serve_submit(1, 1, 5)
+    assert e.value.status == libpsl.E_INVAL
+    with pytest.raises(libpsl.PslError) as e:
+        ctx.serve_submit(100, 1, 0)
+    assert e.value.status == libpsl.E_INVAL
+    with pytest.raises(libpsl.PslError) as e:
+        ctx.serve_poll(987654)
+    assert e.value.status == libpsl.E_STATE
+    with pytest.raises(libpsl.PslError) as e:
+        ctx.init_walks(100, 1, 1)              # the loop owns the context
+    assert e.value.status == libpsl.E_STATE
+    long_jobs = [ctx.serve_submit(131071, 5 + i, 100000, n_lmt=512) for i in range(8)]
+    time.sleep(0.3)
+    ctx.serve_stop(drain=False)
+    res = [ctx.serve_poll(t) for t in long_jobs]
+    assert all(r is not None and r["status"] == libpsl.E_STATE for r in res)
+    with pytest.raises(libpsl.PslError):
+        ctx.serve_poll(long_jobs[0])            # retired
+    # the context is usable again
+    (w,) = ctx.init_walks(100, 1, 1)
+    ctx.step_batch([w], 2)
+    ctx.free_walks([w])

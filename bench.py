@@ -42,10 +42,17 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--walks", type=int, default=1024)
-    ap.add_argument("--L", type=int, default=131071)
+    ap.add_argument("--workload", default="batched",
+                    choices=["batched", "single", "large", "uneven", "paper"],
+                    help="batched: 1024 walks at L=131071 (the headline); single: one walk at "
+                         "L=16383; large: one walk at L=1048575; uneven: L=2^m-1, m=14..20 with "
+                         "512..8 walks; paper: Table 4 settings (N_lmt=6912, alpha 4/10, "
+                         "LS_lmt=2000) at --L with --walks walks")
+    ap.add_argument("--walks", type=int, default=0, help="override the walk count")
+    ap.add_argument("--L", type=int, default=0, help="override L")
     ap.add_argument("--n-lmt", type=int, default=0, help="0 = full neighbourhood")
     ap.add_argument("--switch-period", type=int, default=50)
+    ap.add_argument("--graph", action="store_true", help="replay a captured step per step")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -221,13 +228,33 @@ def main():
     from paper_2107_09801_amd import libpsl
 
     assert torch.cuda.is_available(), "bench needs a GPU"
-    L, nw = args.L, args.walks
-    n_lmt = args.n_lmt or L
-    a2 = si.alpha2_for(L)
+    UNEVEN = [(14, 512), (15, 256), (16, 128), (17, 64), (18, 32), (19, 16), (20, 8)]
+    wl = args.workload
+    period, ls_lmt = args.switch_period, 2000
+    if wl == "batched":
+        groups = [(args.L or 131071, args.walks or 1024)]
+    elif wl == "single":
+        groups = [(args.L or 16383, args.walks or 1)]
+    elif wl == "large":
+        groups = [(args.L or 1048575, args.walks or 1)]
+    elif wl == "uneven":
+        groups = [(2 ** m - 1, c) for m, c in UNEVEN]
+    else:  # paper: Table 4 settings
+        groups = [(args.L or 131071, args.walks or 64)]
+        period = 0
     ctx = libpsl.Context(0)
-    ids = ctx.init_walks(L, nw, si.BASE_SEED, alpha1=4, alpha2=a2, n_lmt=n_lmt,
-                         ls_lmt=2000, flip_lmt=10, switch_period=args.switch_period)
-    log(f"{nw} walks of L={L} initialised")
+    ids, evals_per_step, updates_per_step = [], 0, 0
+    for L, count in groups:
+        a2 = 10 if wl == "paper" else si.alpha2_for(L)
+        n_lmt = min(L, 6912) if wl == "paper" else min(L, args.n_lmt or L)
+        ids += ctx.init_walks(L, count, si.BASE_SEED + len(ids), alpha1=4, alpha2=a2, n_lmt=n_lmt,
+                              ls_lmt=ls_lmt, flip_lmt=10, switch_period=period)
+        evals_per_step += count * n_lmt
+        updates_per_step += count * n_lmt * (L - 1)
+    nw = len(ids)
+    L, n_lmt = groups[0][0], (min(groups[0][0], 6912) if wl == "paper" else min(groups[0][0], args.n_lmt or groups[0][0]))
+    a2 = 10 if wl == "paper" else si.alpha2_for(L)
+    log(f"{nw} walks initialised ({wl})")
     if args.calib_copy_mb:
         n = args.calib_copy_mb << 20
         src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
@@ -237,25 +264,41 @@ def main():
         del src, dst
         log(f"calibration copy of {args.calib_copy_mb} MiB done")
     if args.warmup:
-        ctx.step_batch(ids, args.warmup, blocking=True)
+        ctx.step_batch(ids, args.warmup, blocking=True, graph=args.graph)
         log(f"{args.warmup} warmup step(s) done")
     torch.cuda.synchronize()
-    ctx.timing_enable(True)
-    t0 = time.perf_counter()
-    ctx.step_batch(ids, args.steps, blocking=True)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    tm = ctx.timing_read()
-    log(f"{args.steps} timed step(s) in {el:.2f} s")
-    ctx.timing_enable(False)
+    tm = None
+    if args.graph:
+        t0 = time.perf_counter()
+        ctx.step_batch(ids, args.steps, blocking=True, graph=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ctx.timing_enable(True)          # one eager pass for the kernel's duration
+        ctx.step_batch(ids, min(args.steps, 8), blocking=True)
+        tm = ctx.timing_read()
+        ctx.timing_enable(False)
+    else:
+        ctx.timing_enable(True)
+        t0 = time.perf_counter()
+        ctx.step_batch(ids, args.steps, blocking=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        tm = ctx.timing_read()
+        ctx.timing_enable(False)
+    log(f"{args.steps} timed step(s) in {el:.3f} s")
     st = ctx.read_walk(ids[0], bits=False, C=False)
 
-    evals_per_step = nw * n_lmt
-    updates_per_step = evals_per_step * (L - 1)
     value = evals_per_step * args.steps / el
     eval_avg_s = tm["eval_ms"] / max(1, tm["eval_launches"]) / 1e3
     achieved = OPS_PER_UPDATE * updates_per_step / eval_avg_s
     tiles, ks = ctx.eval_shape(L, n_lmt, nw)
+    names = {"batched": "batched uniform", "single": "single walk", "large": "large single instance",
+             "uneven": "uneven batch", "paper": "paper settings (Table 4)"}
+    desc = (f"{names[wl]}: {nw} walks, L={'/'.join(str(g[0]) for g in groups)}, "
+            f"N_lmt={'min(L,6912)' if wl == 'paper' else ('L' if not args.n_lmt else args.n_lmt)}, "
+            f"alpha 4/{'10' if wl == 'paper' else 'by L'}, "
+            f"{'paper switch rule LS_lmt=2000' if period == 0 else f'switch every {period} steps'}, "
+            f"FLIP_lmt 10, FP64 F{', graph replay' if args.graph else ''}")
 
     out = {
         "metric": "flip-evals/s",
@@ -270,13 +313,10 @@ def main():
         "vs_baseline": None,
         "dtype": "i32+f64",
         "data": "synthetic",
-        "config": {"workload": f"batched uniform: {nw} walks, L={L}, N_lmt={n_lmt}, "
-                               f"alpha 4/{a2}, switch every {args.switch_period} steps, "
-                               f"FLIP_lmt 10, FP64 F",
-                   "walks": nw, "L": L, "n_lmt": n_lmt, "alpha1": 4, "alpha2": a2,
-                   "switch_period": args.switch_period, "eval_tiles": tiles,
-                   "eval_ksplit": ks},
-        "C_k_updates_per_s": value * (L - 1),
+        "config": {"workload": desc, "walks": nw, "L": [g[0] for g in groups],
+                   "walks_per_L": [g[1] for g in groups], "n_lmt": n_lmt, "alpha1": 4,
+                   "alpha2": a2, "switch_period": period, "eval_tiles": tiles, "eval_ksplit": ks},
+        "C_k_updates_per_s": updates_per_step * args.steps / el,
         "eval_kernel": {"avg_ms": eval_avg_s * 1e3, "launches": tm["eval_launches"],
                         "updates_per_s": updates_per_step / eval_avg_s,
                         "rest_of_step_avg_ms": tm["rest_ms"] / max(1, tm["steps"])},
@@ -284,10 +324,14 @@ def main():
                      "unit": "Tlane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": None},
         "walk0_after": {"t": st["t"], "psl_best": st["psl_best"], "alpha": st["alpha"]},
     }
-    if L in PAPER_A100_NSE:
+    if L in PAPER_A100_NSE and len(groups) == 1:
         out["paper_context"] = {"A100_flip_evals_per_s": PAPER_A100_NSE[L],
                                 "note": "paper Table 4: one walk, N_lmt=6912, alpha 4/10"}
+        if wl == "paper":
+            out["vs_paper_table4"] = value / PAPER_A100_NSE[L]
     ctx.close()
+    if wl != "batched":
+        args.serve_seconds, args.compare_jobs = 0, 0
     if args.serve_seconds > 0:
         log(f"serving run: {args.serve_rate:g} jobs/s for {args.serve_seconds:g} s")
         out["serving"] = run_serving(libpsl, args.serve_seconds, args.serve_rate, args.serve_nlmt)

@@ -261,6 +261,11 @@ PSL_API psl_status psl_serve_submit(psl_ctx *ctx, const psl_job *job, uint64_t *
  * (or already retired) ticket. */
 PSL_API psl_status psl_serve_poll(psl_ctx *ctx, uint64_t ticket, psl_job_result *out);
 
+/* Device bytes a job with this configuration counts against hbm_budget
+ * (its walk slab plus an upper bound of its evaluation scratch). Needs no
+ * context or device. Errors: PSL_E_INVAL. */
+PSL_API psl_status psl_serve_footprint(const psl_walk_cfg *cfg, uint64_t *bytes);
+
 /* Thread-safe counters of the loop. */
 PSL_API psl_status psl_serve_stats_read(psl_ctx *ctx, psl_serve_stats *out);
 

@@ -12,13 +12,15 @@ namespace psl {
 
 constexpr double kTau = 1e-12;       // relative band of the best-neighbour and
                                      // improvement comparisons
-constexpr int kEvalWaves = 8;        // wavefronts per evaluation block
+constexpr int kEvalWaves = 8;        // wavefronts per evaluation block (largest)
 constexpr int kEvalThreads = 64 * kEvalWaves;
+constexpr int kEvalWavesSmall = 4;   // blocks for batches of small neighbourhoods
 constexpr int kTileK = 256;          // shifts staged per LDS tile
 constexpr int kChunks = kTileK / 32; // 32-shift windows per tile
 constexpr int kPairs = kTileK / 2;   // shift pairs per tile
 constexpr int kRowStride = 5;        // T(|C_k + 2m|), m = -2..2
 constexpr int kNearCap = 4096;       // capacity of the near-peak shift list
+constexpr uint32_t kFlipIncremental = 64;  // Rand_flip sizes rebuilt by one-flip updates
 
 // Guard words (64-bit) before and after the pivot's bits: every bit window
 // the evaluation reads (j +- k for j < L, k < L, plus one window) lies inside
@@ -31,6 +33,8 @@ struct WalkDev {
     uint64_t *local_best;   // nw words
     uint64_t *best;         // nw words (solution_best)
     int32_t *C;             // L entries, C[0] = L
+    int32_t *C_lb;          // L entries: C of local_best
+    uint32_t *flips;        // the positions of the last Rand_flip (<= flip_lmt)
     // control parameters
     uint64_t seed;
     uint32_t L, nw;
@@ -56,6 +60,7 @@ struct WalkDev {
     int32_t psl_min;
     uint32_t flags;
     uint32_t pending;       // 1: C, F and PSL of the pivot must be rebuilt
+    uint32_t n_flips;       // entries of flips[] for the pending rebuild
 };
 
 struct Tables {
@@ -82,6 +87,8 @@ struct BatchEntry {
     uint32_t near_lim;      // largest near-peak list handled sparsely
     uint32_t pad;
 };
+
+constexpr uint32_t kNoItem = 0xFFFFFFFFu;  // padding work item (no work)
 
 // Eval work item: walk position in the batch, candidate tile, k-split index.
 struct EvalItem {

@@ -78,7 +78,7 @@ private:
 // Host record of a walk slot.
 struct WalkHost {
     bool active = false;
-    uint32_t L = 0, nw = 0, n_lmt = 0;
+    uint32_t L = 0, nw = 0, n_lmt = 0, flip_lmt = 0;
     void *slab = nullptr;
     size_t slab_bytes = 0;
 };
@@ -87,7 +87,9 @@ struct WalkHost {
 struct BatchPlan {
     std::vector<uint32_t> ids;
     uint32_t max_L = 0, max_nw = 0;
+    bool big_flips = false;           // some walk's Rand_flip exceeds the one-flip rebuild
     uint32_t n_items = 0;
+    int waves = kEvalWaves;           // wavefronts per evaluation block
     BatchEntry *d_batch = nullptr;
     EvalItem *d_items = nullptr;
     hipGraph_t graph = nullptr;       // one captured step of this plan
@@ -153,14 +155,23 @@ psl_status ensure_tables(psl_ctx *ctx, uint32_t L);
 Tables tables_of(const psl_ctx *ctx);
 psl_status ensure_walk_cap(psl_ctx *ctx, uint32_t cap);
 bool walk_ok(const psl_ctx *ctx, uint32_t id);
-void eval_shape(uint32_t L, uint32_t n_lmt, uint32_t total_tiles, uint32_t *tiles, uint32_t *ksplit);
+// Launch layout of a batch's evaluation: candidate tiles and k-splits per
+// walk, and the work items in XCD-balanced order (see eval_layout).
+struct EvalLayout {
+    int waves = kEvalWaves;           // wavefronts per evaluation block
+    std::vector<uint32_t> tiles, ks;
+    std::vector<EvalItem> items;
+};
+void eval_layout(const uint32_t *Ls, const uint32_t *n_lmt, uint32_t n, EvalLayout &out);
+void eval_shape_k(uint32_t L, uint32_t n_lmt, uint32_t K, uint32_t tile, uint32_t *tiles, uint32_t *ksplit);
+int eval_waves(const uint32_t *n_lmt, uint32_t n);
 psl_status check_cfg(psl_ctx *ctx, const psl_walk_cfg *c);
 uint32_t near_limit_for(const psl_ctx *ctx, uint32_t L);
 
 // Slab layout of one walk of length L: the pivot between guard words, then
-// local_best, best and C.
+// local_best, best, C, C of local_best and the Rand_flip positions.
 struct SlabLayout {
-    size_t guard_bytes, pivot_bytes, bits_bytes, slab_bytes;
+    size_t guard_bytes, pivot_bytes, bits_bytes, c_bytes, slab_bytes;
 };
 SlabLayout slab_layout(uint32_t L);
 // Fills a WalkDev for cfg (seed already chosen) over a slab.

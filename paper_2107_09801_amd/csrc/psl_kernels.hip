@@ -11,6 +11,7 @@
 #include "psl_device.h"
 #include "psl_launch.h"
 
+#include <algorithm>
 #include <climits>
 
 namespace psl {
@@ -123,30 +124,90 @@ __global__ void k_init_bits(WalkDev *walks, const BatchEntry *batch, const uint3
 }
 
 // Eq. (2) from the packed pivot: C_k = (L-k) - 2 * #(s_i != s_{i+k}).
-// only_pending: skip walks without a pending rebuild.
-__global__ void k_corr(WalkDev *walks, const BatchEntry *batch, int only_pending)
+// A block owns 256 consecutive shifts k0..k0+255 and sweeps the sequence in
+// LDS-staged segments of 32-bit words: word x of the sequence and the word at
+// bit offset 32x + k (one funnel shift of two staged words) give 32 products
+// per XOR and popcount.
+// only_pending == 0: every walk (init; C of local_best = C as well);
+// only_pending == 1: walks left pending by a switch whose Rand_flip is too
+// large for the one-flip rebuild (k_switch_corr).
+constexpr int kCorrThreads = 256;
+constexpr int kCorrSeg = 1024;        // staged 32-bit words per segment
+__global__ __launch_bounds__(kCorrThreads) void k_corr(WalkDev *walks, const BatchEntry *batch,
+                                                       int only_pending)
 {
     WalkDev &w = walks[batch[blockIdx.y].slot];
-    if (only_pending && !w.pending) return;
+    if (only_pending && !(w.pending && w.n_flips > kFlipIncremental)) return;
     const uint32_t L = w.L;
-    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= L) return;
-    const uint64_t *b = w.pivot;
-    const uint32_t n = L - k;
-    int32_t diff = 0;
-    for (uint32_t i = 0; i < n; i += 64) {
-        uint64_t a = b[i >> 6];
-        uint32_t p = i + k;
-        uint32_t wi = p >> 6, sh = p & 63u;
-        uint64_t lo = b[wi];
-        uint64_t hi = (wi + 1 < w.nw) ? b[wi + 1] : 0ull;
-        uint64_t c = sh ? ((lo >> sh) | (hi << (64u - sh))) : lo;
-        uint64_t x = a ^ c;
-        uint32_t rem = n - i;
-        if (rem < 64) x &= (1ull << rem) - 1ull;
-        diff += __popcll(x);
+    const uint32_t k0 = blockIdx.x * kCorrThreads;
+    if (k0 >= L) return;
+    __shared__ uint32_t A[kCorrSeg];
+    __shared__ uint32_t B[kCorrSeg + 16];
+    const uint32_t *s32 = reinterpret_cast<const uint32_t *>(w.pivot);
+    const uint32_t n32 = (L + 31) / 32;
+    const uint32_t k = k0 + threadIdx.x;
+    const uint32_t d = threadIdx.x, dq = d >> 5, dr = d & 31u;
+    const uint32_t nprod = k < L ? L - k : 0;          // products of this shift
+    const uint32_t nwb = (L - k0 + 31) / 32;           // words the block needs
+    const uint32_t kq = k0 / 32;
+    uint32_t diff = 0;
+    for (uint32_t w0 = 0; w0 < nwb; w0 += kCorrSeg) {
+        __syncthreads();
+        for (uint32_t t = threadIdx.x; t < kCorrSeg; t += kCorrThreads)
+            A[t] = (w0 + t < n32) ? s32[w0 + t] : 0u;
+        for (uint32_t t = threadIdx.x; t < kCorrSeg + 16; t += kCorrThreads)
+            B[t] = (w0 + kq + t < n32) ? s32[w0 + kq + t] : 0u;
+        __syncthreads();
+        // this shift's products in the segment: bits 32*w0 .. nprod
+        const uint32_t have = nprod > 32 * w0 ? nprod - 32 * w0 : 0;
+        const uint32_t full = min((uint32_t)kCorrSeg, have / 32);
+        for (uint32_t x = 0; x < full; ++x)
+            diff += __popc(A[x] ^ __builtin_amdgcn_alignbit(B[x + dq + 1], B[x + dq], dr));
+        if (full < (uint32_t)kCorrSeg && (have & 31u)) {
+            const uint32_t x = full;
+            const uint32_t v = A[x] ^ __builtin_amdgcn_alignbit(B[x + dq + 1], B[x + dq], dr);
+            diff += __popc(v & ((1u << (have & 31u)) - 1u));
+        }
     }
-    w.C[k] = (int32_t)n - 2 * diff;
+    if (k < L) {
+        const int32_t c = (int32_t)nprod - 2 * (int32_t)diff;
+        w.C[k] = c;
+        if (!only_pending) w.C_lb[k] = c;
+    }
+}
+
+// After a switch: C of (local_best with the Rand_flip positions flipped),
+// from C of local_best by one one-element flip per position, in draw order.
+// Flip f sees the elements of local_best with positions 0..f-1 flipped.
+__global__ void k_switch_corr(WalkDev *walks, const BatchEntry *batch)
+{
+    WalkDev &w = walks[batch[blockIdx.y].slot];
+    if (!w.pending || w.n_flips > kFlipIncremental) return;
+    const uint32_t L = w.L;
+    const uint32_t nf = w.n_flips;
+    const uint64_t *lb = w.local_best;
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < L; k += gridDim.x * blockDim.x) {
+    if (k == 0) {
+        w.C[0] = (int32_t)L;
+        continue;
+    }
+    int32_t c = w.C_lb[k];
+    for (uint32_t f = 0; f < nf; ++f) {
+        const uint32_t p = w.flips[f];
+        // element x of the sequence after flips 0..f-1: -1 iff bit set
+        auto bit = [&](uint32_t x) {
+            uint32_t b = get_bit(lb, x);
+            for (uint32_t g = 0; g < f; ++g) b ^= (w.flips[g] == x) ? 1u : 0u;
+            return b;
+        };
+        const int sp = bit(p) ? -1 : 1;
+        int d = 0;
+        if (p + k < L) d += bit(p + k) ? -1 : 1;
+        if (k <= p) d += bit(p - k) ? -1 : 1;
+        c -= 2 * sp * d;
+    }
+    w.C[k] = c;
+    }
 }
 
 // F of the pivot (Eq. (5)) and its PSL (Eq. (3)) from C, one block per walk,
@@ -310,14 +371,14 @@ struct EvalLds {
     double one[kPairs * 4];             // pair sums, one neighbour
     uint32_t both_max[kPairs * 16];     // max hi32 of the pair (dense PSL only)
     uint32_t one_max[kPairs * 4];
-    int kend[kEvalWaves];
+    int kend[kEvalWaves];               // per wavefront (up to kEvalWaves)
     int bmax[kEvalWaves];
     int omax[kEvalWaves];
 };
 
 // The sweep of one item. kMax: keep the PSL maximum in the main loop (dense
 // form); otherwise the near-peak pass supplies it.
-template <bool kMax>
+template <int WAVES, bool kMax>
 __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const BatchEntry &be,
                                            const EvalItem &it, const double *__restrict__ T,
                                            uint32_t n_lmt, int j, uint32_t SJ, int k_lo, int k_hi,
@@ -345,7 +406,7 @@ __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const 
     }
     __syncthreads();
     int k_bend = sh.kend[0], b_bmax = sh.bmax[0], b_omax = sh.omax[0];
-    for (int x = 1; x < kEvalWaves; ++x) {
+    for (int x = 1; x < WAVES; ++x) {
         k_bend = max(k_bend, sh.kend[x]);
         b_bmax = max(b_bmax, sh.bmax[x]);
         b_omax = max(b_omax, sh.omax[x]);
@@ -367,7 +428,7 @@ __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const 
         const bool need_both = kt + 31 <= b_bmax;
         const bool need_one = kt + 31 <= b_omax;
         __syncthreads();
-        for (int t = threadIdx.x; t < nt; t += kEvalThreads) {
+        for (int t = threadIdx.x; t < nt; t += 64 * WAVES) {
             const int c = C[kt + t];
 #pragma unroll
             for (int m = 0; m < kRowStride; ++m) {
@@ -378,7 +439,7 @@ __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const 
         }
         __syncthreads();
         if (need_both) {
-            for (int e = threadIdx.x; e < kPairs * 16; e += kEvalThreads) {
+            for (int e = threadIdx.x; e < kPairs * 16; e += 64 * WAVES) {
                 const int p = e >> 4, x = e & 15;
                 if (2 * p + 1 < nt) {
                     const double a = sh.rows[(2 * p) * kRowStride + 2 * ((x & 1) + ((x >> 2) & 1))];
@@ -389,7 +450,7 @@ __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const 
             }
         }
         if (need_one) {
-            for (int f = threadIdx.x; f < kPairs * 4; f += kEvalThreads) {
+            for (int f = threadIdx.x; f < kPairs * 4; f += 64 * WAVES) {
                 const int p = f >> 2, x = f & 3;
                 if (2 * p + 1 < nt) {
                     const double a = sh.rows[(2 * p) * kRowStride + 1 + 2 * (x & 1)];
@@ -463,7 +524,7 @@ __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const 
     }
 }
 
-// Neighborhood of Algorithm 1 for one (walk, 512 candidates, k-range) item.
+// Neighborhood of Algorithm 1 for one (walk, 64*WAVES candidates, k-range) item.
 //
 // Per 256-shift tile the block stages (i) per shift the five values
 // T(|C_k + 2m|), m = -2..2, and (ii) per pair of shifts (k, k+1) two tables
@@ -478,7 +539,8 @@ __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const 
 // max(j, L-1-j) come from the suffix sums. The PSL comes from the near-peak
 // shifts (split 0 only), or, for pivots with many near-peak shifts, from
 // 32-bit maxima kept in the main loop.
-__global__ __launch_bounds__(kEvalThreads) void k_eval(const WalkDev *__restrict__ walks,
+template <int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_eval(const WalkDev *__restrict__ walks,
                                                        const BatchEntry *__restrict__ batch,
                                                        const EvalItem *__restrict__ items,
                                                        Tables tabs)
@@ -486,6 +548,7 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(const WalkDev *__restrict
     __shared__ EvalLds sh;
 
     const EvalItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
+    if (it.walk == kNoItem) return;     // padding of an XCD's range
     const BatchEntry be = batch[it.walk];
     const WalkDev &w = walks[be.slot];
     const int L = (int)w.L;
@@ -503,7 +566,7 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(const WalkDev *__restrict
     const int k_hi = min(L, 1 + 32 * c_hi);
 
     // this lane's candidate; inactive lanes keep a valid j and store nothing
-    const uint32_t i = it.tile * kEvalThreads + threadIdx.x;
+    const uint32_t i = it.tile * (64 * WAVES) + threadIdx.x;
     const bool active = i < n_lmt;
     const uint32_t ii = active ? i : n_lmt - 1;
     const int j = (int)((start + 1u + ii) % (uint32_t)L);
@@ -514,9 +577,9 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(const WalkDev *__restrict
     uint32_t mx = 0;
     const uint32_t n_near = be.near[0];
     if (n_near > be.near_lim) {
-        eval_sweep<true>(sh, w, be, it, T, n_lmt, j, SJ, k_lo, k_hi, sum, comp, mx);
+        eval_sweep<WAVES, true>(sh, w, be, it, T, n_lmt, j, SJ, k_lo, k_hi, sum, comp, mx);
     } else {
-        eval_sweep<false>(sh, w, be, it, T, n_lmt, j, SJ, k_lo, k_hi, sum, comp, mx);
+        eval_sweep<WAVES, false>(sh, w, be, it, T, n_lmt, j, SJ, k_lo, k_hi, sum, comp, mx);
         if (it.ks == 0) {
             // PSL over the near-peak shifts, every candidate, all bounds cases
             const int jl = j, jr = L - 1 - j;
@@ -659,11 +722,15 @@ __global__ __launch_bounds__(kSelThreads) void k_select(WalkDev *walks, const Ba
             w.psl_k = Pb;
             w.j_psl = jp;
             w.psl_min = Pmin;
-            w.flags = 0;
+            // three-way comparison of the move with v_local (Algorithm 1)
+            uint32_t fl = 0;
+            if (Fb < w.value_local * (1.0 - kTau)) fl = STEP_IMPROVED;
+            else if (Fb > w.value_local * (1.0 + kTau)) fl = STEP_WORSE;
+            w.flags = fl;
             s_improve = Pmin < w.psl_best;
             if (s_improve) {
                 w.psl_best = Pmin;
-                w.flags = STEP_PSL_IMPROVED;
+                w.flags |= STEP_PSL_IMPROVED;
             }
         }
     }
@@ -686,15 +753,19 @@ __global__ void k_apply(WalkDev *walks, const BatchEntry *batch, int64_t j_fixed
 {
     WalkDev &w = walks[batch[blockIdx.y].slot];
     const uint32_t L = w.L;
-    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x + 1u;
-    if (k >= L) return;
     const uint32_t j = j_fixed >= 0 ? (uint32_t)j_fixed : w.k;
     const uint64_t *b = w.pivot;
     const int sj = get_bit(b, j) ? -1 : 1;
-    int d = 0;
-    if (j + k < L) d += get_bit(b, j + k) ? -1 : 1;
-    if (k <= j) d += get_bit(b, j - k) ? -1 : 1;
-    w.C[k] -= 2 * sj * d;
+    // the move improves on v_local: the new pivot becomes local_best
+    const bool lb = j_fixed < 0 && (w.flags & STEP_IMPROVED);
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x + 1u; k < L; k += gridDim.x * blockDim.x) {
+        int d = 0;
+        if (j + k < L) d += get_bit(b, j + k) ? -1 : 1;
+        if (k <= j) d += get_bit(b, j - k) ? -1 : 1;
+        const int32_t c = w.C[k] - 2 * sj * d;
+        w.C[k] = c;
+        if (lb) w.C_lb[k] = c;
+    }
 }
 
 // Flip(pivot, j), part 2, for a forced flip: the bit itself.
@@ -721,19 +792,15 @@ __global__ __launch_bounds__(kBookThreads) void k_bookkeep(WalkDev *walks, const
         w.pivot[k >> 6] ^= 1ull << (k & 63u);
         w.F_pivot = w.value_step;
         w.psl_pivot = w.psl_k;
-        const double v = w.value_step;
-        const double lo = w.value_local * (1.0 - kTau);
-        const double hi = w.value_local * (1.0 + kTau);
+        // the comparison with v_local was taken by k_select
         int improved = 0, sw = 0;
         uint32_t flags = w.flags;
-        if (v < lo) {
+        if (flags & STEP_IMPROVED) {
             improved = 1;
             w.unimproved = 0;
-            w.value_local = v;
-            flags |= STEP_IMPROVED;
-        } else if (v > hi) {
+            w.value_local = w.value_step;
+        } else if (flags & STEP_WORSE) {
             w.unimproved += 1;
-            flags |= STEP_WORSE;
             if (w.switch_period == 0 && w.unimproved > w.ls_lmt) sw = 1;
         }
         if (w.switch_period > 0 && ((w.t + 1u) % w.switch_period) == 0) sw = 1;
@@ -760,9 +827,12 @@ __global__ __launch_bounds__(kBookThreads) void k_bookkeep(WalkDev *walks, const
                 bool dup = false;
                 for (uint32_t x = 0; x < cnt; ++x) dup |= (s_pos[x] == pos);
                 if (dup) continue;
-                s_pos[cnt++] = pos;
+                s_pos[cnt] = pos;
+                w.flips[cnt] = pos;
+                ++cnt;
                 w.pivot[pos >> 6] ^= 1ull << (pos & 63u);
             }
+            w.n_flips = cnt;
             w.alpha = (w.alpha == w.alpha1) ? w.alpha2 : w.alpha1;
             w.q += 1;
             w.pending = 1;
@@ -771,6 +841,15 @@ __global__ __launch_bounds__(kBookThreads) void k_bookkeep(WalkDev *walks, const
 }
 
 // ------------------------------------------------------------ launches
+
+// O(L) kernels stride over k with at most max(32, 2048 / walks) blocks per
+// walk, so a batch of many walks of very different L launches no
+// mostly-empty grid while a single walk still spreads over the GPU.
+static uint32_t lin_blocks(uint32_t max_L, uint32_t nb)
+{
+    const uint32_t cap = std::max<uint32_t>(32, 2048 / std::max<uint32_t>(nb, 1));
+    return std::min<uint32_t>(std::max<uint32_t>((max_L + 255) / 256, 1), cap);
+}
 
 hipError_t launch_power_table(double *T, uint32_t n, uint32_t alpha, hipStream_t s)
 {
@@ -788,7 +867,15 @@ hipError_t launch_init_bits(WalkDev *walks, const BatchEntry *batch, const uint3
 hipError_t launch_corr(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t max_L,
                        int only_pending, hipStream_t s)
 {
-    k_corr<<<dim3((max_L + 255) / 256, nb), 256, 0, s>>>(walks, batch, only_pending);
+    k_corr<<<dim3((max_L + kCorrThreads - 1) / kCorrThreads, nb), kCorrThreads, 0, s>>>(walks, batch,
+                                                                                       only_pending);
+    return hipGetLastError();
+}
+
+hipError_t launch_switch_corr(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t max_L,
+                              hipStream_t s)
+{
+    k_switch_corr<<<dim3(lin_blocks(max_L, nb), nb), 256, 0, s>>>(walks, batch);
     return hipGetLastError();
 }
 
@@ -800,9 +887,12 @@ hipError_t launch_fitness(WalkDev *walks, const BatchEntry *batch, uint32_t nb, 
 }
 
 hipError_t launch_eval(const WalkDev *walks, const BatchEntry *batch, const EvalItem *items,
-                       uint32_t n_items, const Tables &tabs, hipStream_t s)
+                       uint32_t n_items, const Tables &tabs, int waves, hipStream_t s)
 {
-    k_eval<<<n_items, kEvalThreads, 0, s>>>(walks, batch, items, tabs);
+    if (waves == kEvalWavesSmall)
+        k_eval<kEvalWavesSmall><<<n_items, 64 * kEvalWavesSmall, 0, s>>>(walks, batch, items, tabs);
+    else
+        k_eval<kEvalWaves><<<n_items, kEvalThreads, 0, s>>>(walks, batch, items, tabs);
     return hipGetLastError();
 }
 
@@ -834,7 +924,7 @@ hipError_t launch_apply(WalkDev *walks, const BatchEntry *batch, uint32_t nb, ui
                         int64_t j_fixed, hipStream_t s)
 {
     if (max_L < 2) return hipSuccess;
-    k_apply<<<dim3((max_L - 1 + 255) / 256, nb), 256, 0, s>>>(walks, batch, j_fixed);
+    k_apply<<<dim3(lin_blocks(max_L, nb), nb), 256, 0, s>>>(walks, batch, j_fixed);
     return hipGetLastError();
 }
 

@@ -10,10 +10,12 @@ hipError_t launch_init_bits(WalkDev *walks, const BatchEntry *batch, const uint3
                             uint32_t nb, uint32_t max_nw, hipStream_t s);
 hipError_t launch_corr(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t max_L,
                        int only_pending, hipStream_t s);
+hipError_t launch_switch_corr(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t max_L,
+                              hipStream_t s);
 hipError_t launch_fitness(WalkDev *walks, const BatchEntry *batch, uint32_t nb, const Tables &tabs,
                           int mode, hipStream_t s);
 hipError_t launch_eval(const WalkDev *walks, const BatchEntry *batch, const EvalItem *items,
-                       uint32_t n_items, const Tables &tabs, hipStream_t s);
+                       uint32_t n_items, const Tables &tabs, int waves, hipStream_t s);
 hipError_t launch_suffix(const WalkDev *walks, const BatchEntry *batch, uint32_t nb, const Tables &tabs,
                          hipStream_t s);
 hipError_t launch_select(WalkDev *walks, const BatchEntry *batch, uint32_t nb, const Tables &tabs,

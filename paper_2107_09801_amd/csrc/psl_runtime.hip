@@ -157,17 +157,81 @@ bool walk_ok(const psl_ctx *ctx, uint32_t id)
     return id < ctx->walks.size() && ctx->walks[id].active;
 }
 
-// Evaluation shape: candidate tiles of kEvalThreads and k-splits so that a
-// batch offers enough blocks to fill 256 CUs.
-void eval_shape(uint32_t L, uint32_t n_lmt, uint32_t total_tiles, uint32_t *tiles, uint32_t *ksplit)
+// Evaluation shape of a batch. Candidates go in tiles of one block (64 lanes
+// per wavefront; 4 wavefronts when most walks evaluate at most 256
+// candidates, else 8); the shifts of a walk split into pieces of about
+// K = max(kTileK, W / 4096) shifts, where W is the batch's total
+// (tile x shift) work, so a batch offers at least about 4096 work items and
+// no item is much longer than the batch's average.
+int eval_waves(const uint32_t *nl, uint32_t n)
 {
-    *tiles = (n_lmt + kEvalThreads - 1) / kEvalThreads;
-    const uint32_t target = 4096;
-    uint32_t nchunks = (L - 1 + 31) / 32;
-    uint32_t ks = 1;
-    if (total_tiles < target) ks = (target + total_tiles - 1) / total_tiles;
-    uint32_t ks_max = std::max<uint32_t>(1, nchunks / (kTileK / 32));
-    *ksplit = std::min(ks, ks_max);
+    uint32_t small = 0;
+    for (uint32_t b = 0; b < n; ++b) small += nl[b] <= 64u * kEvalWavesSmall;
+    return 2 * small > n ? kEvalWavesSmall : kEvalWaves;
+}
+
+static uint32_t item_shifts(const uint32_t *Ls, const uint32_t *nl, uint32_t n, uint32_t tile)
+{
+    uint64_t W = 0;
+    for (uint32_t b = 0; b < n; ++b) W += (uint64_t)((nl[b] + tile - 1) / tile) * (Ls[b] - 1);
+    return (uint32_t)std::max<uint64_t>(kTileK, (W + 4095) / 4096);
+}
+
+void eval_shape_k(uint32_t L, uint32_t n_lmt, uint32_t K, uint32_t tile, uint32_t *tiles, uint32_t *ksplit)
+{
+    *tiles = (n_lmt + tile - 1) / tile;
+    const uint32_t nchunks = (L - 1 + 31) / 32;
+    const uint32_t ks_max = std::max<uint32_t>(1, nchunks / (kTileK / 32));
+    const uint32_t ks = (L - 1 + K - 1) / K;
+    *ksplit = std::min(std::max<uint32_t>(ks, 1), ks_max);
+}
+
+void eval_layout(const uint32_t *Ls, const uint32_t *nl, uint32_t n, EvalLayout &out)
+{
+    out.tiles.assign(n, 0);
+    out.ks.assign(n, 0);
+    out.items.clear();
+    out.waves = eval_waves(nl, n);
+    const uint32_t tile = 64u * out.waves;
+    const uint32_t K = item_shifts(Ls, nl, n, tile);
+    struct C { EvalItem it; double cost; };
+    std::vector<C> all;
+    double total = 0.0;
+    for (uint32_t b = 0; b < n; ++b) {
+        eval_shape_k(Ls[b], nl[b], K, tile, &out.tiles[b], &out.ks[b]);
+        const uint32_t nchunks = (Ls[b] - 1 + 31) / 32;
+        const uint32_t per = (nchunks + out.ks[b] - 1) / out.ks[b];
+        for (uint32_t t = 0; t < out.tiles[b]; ++t) {
+            const uint32_t cand = std::min<uint32_t>(tile, nl[b] - t * tile);
+            for (uint32_t s = 0; s < out.ks[b]; ++s) {
+                const uint32_t clo = s * per, chi = std::min(nchunks, clo + per);
+                const double cost = (double)(chi > clo ? chi - clo : 0) * 32.0 * cand + 1.0;
+                all.push_back(C{EvalItem{b, t, s, 0}, cost});
+                total += cost;
+            }
+        }
+    }
+    // 8 contiguous segments of equal cost (one per XCD, so a walk's items
+    // mostly share an L2), each in longest-first order, padded with no-op
+    // items to equal length (blocks map to XCDs round-robin).
+    std::vector<std::vector<C>> seg(8);
+    double acc = 0.0;
+    size_t x = 0;
+    for (auto &c : all) {
+        while (x < 7 && acc >= total * (double)(x + 1) / 8.0) ++x;
+        seg[x].push_back(c);
+        acc += c.cost;
+    }
+    size_t cmax = 0;
+    for (auto &sg : seg) {
+        std::stable_sort(sg.begin(), sg.end(), [](const C &a, const C &b) { return a.cost > b.cost; });
+        cmax = std::max(cmax, sg.size());
+    }
+    out.items.reserve(8 * cmax);
+    for (auto &sg : seg) {
+        for (auto &c : sg) out.items.push_back(c.it);
+        for (size_t k = sg.size(); k < cmax; ++k) out.items.push_back(EvalItem{kNoItem, 0, 0, 0});
+    }
 }
 
 // Builds (or reuses) the device layout of a batch: entries, eval work items
@@ -179,25 +243,27 @@ psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t 
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     plan_free(ctx, pl);
     pl.ids.assign(ids, ids + n);
-    std::vector<uint32_t> n_l(n), tiles(n), ks(n);
-    uint64_t total_tiles = 0;
+    std::vector<uint32_t> n_l(n), Ls(n);
     for (uint32_t b = 0; b < n; ++b) {
         const WalkHost &h = ctx->walks[ids[b]];
         n_l[b] = fixed ? n_fixed : h.n_lmt;
-        total_tiles += (n_l[b] + kEvalThreads - 1) / kEvalThreads;
+        Ls[b] = h.L;
+        pl.big_flips |= h.flip_lmt > kFlipIncremental;
         pl.max_L = std::max(pl.max_L, h.L);
         pl.max_nw = std::max(pl.max_nw, h.nw);
     }
+    EvalLayout lay;
+    eval_layout(Ls.data(), n_l.data(), n, lay);
+    const std::vector<uint32_t> &tiles = lay.tiles, &ks = lay.ks;
+    std::vector<EvalItem> &items = lay.items;
+    pl.waves = lay.waves;
     size_t n_part = 0, n_cand = 0, n_suf = 0;
-    uint64_t n_items = 0;
     for (uint32_t b = 0; b < n; ++b) {
-        eval_shape(ctx->walks[ids[b]].L, n_l[b], (uint32_t)std::min<uint64_t>(total_tiles, 1u << 30),
-                   &tiles[b], &ks[b]);
         n_part += (size_t)ks[b] * n_l[b];
         n_cand += n_l[b];
-        n_suf += ctx->walks[ids[b]].L + 1;
-        n_items += (uint64_t)tiles[b] * ks[b];
+        n_suf += Ls[b] + 1;
     }
+    const uint64_t n_items = items.size();
     if (n_items >= (1ull << 31)) return fail(ctx, PSL_E_INVAL, "batch too large (%llu work items)",
                                              (unsigned long long)n_items);
     void *p;
@@ -217,8 +283,6 @@ psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t 
     if ((st = dev_alloc(ctx, &p, sizeof(uint32_t) * (kNearCap + 1) * n, false))) return st;
     pl.d_near = (uint32_t *)p;
     std::vector<BatchEntry> be(n);
-    std::vector<EvalItem> items;
-    items.reserve(n_items);
     size_t op = 0, oc = 0, os = 0;
     for (uint32_t b = 0; b < n; ++b) {
         BatchEntry &e = be[b];
@@ -240,8 +304,6 @@ psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t 
         e.fixed = fixed ? 1 : 0;
         op += (size_t)ks[b] * n_l[b];
         oc += n_l[b];
-        for (uint32_t t = 0; t < tiles[b]; ++t)
-            for (uint32_t s = 0; s < ks[b]; ++s) items.push_back(EvalItem{b, t, s, 0});
     }
     if ((st = dev_alloc(ctx, &p, sizeof(BatchEntry) * n, false))) return st;
     pl.d_batch = (BatchEntry *)p;
@@ -261,7 +323,8 @@ SlabLayout slab_layout(uint32_t L)
     s.bits_bytes = align_up(sizeof(uint64_t) * nw, 256);
     s.guard_bytes = sizeof(uint64_t) * guard_words(nw);
     s.pivot_bytes = align_up(2 * s.guard_bytes + sizeof(uint64_t) * nw, 256);
-    s.slab_bytes = s.pivot_bytes + 2 * s.bits_bytes + align_up(sizeof(int32_t) * L, 256);
+    s.c_bytes = align_up(sizeof(int32_t) * L, 256);
+    s.slab_bytes = s.pivot_bytes + 2 * s.bits_bytes + 2 * s.c_bytes + align_up(4 * PSL_FLIP_LMT_MAX, 256);
     return s;
 }
 
@@ -273,6 +336,8 @@ void fill_walk(WalkDev &w, const psl_walk_cfg &cfg, uint64_t seed, void *slab, c
     w.local_best = (uint64_t *)(base + lay.pivot_bytes);
     w.best = (uint64_t *)(base + lay.pivot_bytes + lay.bits_bytes);
     w.C = (int32_t *)(base + lay.pivot_bytes + 2 * lay.bits_bytes);
+    w.C_lb = (int32_t *)(base + lay.pivot_bytes + 2 * lay.bits_bytes + lay.c_bytes);
+    w.flips = (uint32_t *)(base + lay.pivot_bytes + 2 * lay.bits_bytes + 2 * lay.c_bytes);
     w.seed = seed;
     w.L = cfg.L;
     w.nw = (cfg.L + 63) / 64;
@@ -310,12 +375,13 @@ psl_status launch_step(psl_ctx *ctx, const BatchPlan &pl, const Tables &tabs, ui
     psl_status st;
     HIP_TRY(ctx, launch_suffix(ctx->d_walks, pl.d_batch, n, tabs, ctx->stream));
     if (timed && (st = timing_mark(ctx))) return st;
-    HIP_TRY(ctx, launch_eval(ctx->d_walks, pl.d_batch, pl.d_items, pl.n_items, tabs, ctx->stream));
+    HIP_TRY(ctx, launch_eval(ctx->d_walks, pl.d_batch, pl.d_items, pl.n_items, tabs, pl.waves, ctx->stream));
     if (timed && (st = timing_mark(ctx))) return st;
     HIP_TRY(ctx, launch_select(ctx->d_walks, pl.d_batch, n, tabs, 0, nullptr, ctx->stream));
     HIP_TRY(ctx, launch_apply(ctx->d_walks, pl.d_batch, n, pl.max_L, -1, ctx->stream));
     HIP_TRY(ctx, launch_bookkeep(ctx->d_walks, pl.d_batch, n, ctx->stream));
-    HIP_TRY(ctx, launch_corr(ctx->d_walks, pl.d_batch, n, pl.max_L, 1, ctx->stream));
+    HIP_TRY(ctx, launch_switch_corr(ctx->d_walks, pl.d_batch, n, pl.max_L, ctx->stream));
+    if (pl.big_flips) HIP_TRY(ctx, launch_corr(ctx->d_walks, pl.d_batch, n, pl.max_L, 1, ctx->stream));
     HIP_TRY(ctx, launch_fitness(ctx->d_walks, pl.d_batch, n, tabs, 1, ctx->stream));
     if (timed && (st = timing_mark(ctx))) return st;
     return PSL_OK;
@@ -471,6 +537,7 @@ psl_status psl_init_walks(psl_ctx *ctx, const psl_walk_cfg *cfg, uint32_t n,
         h.L = L;
         h.nw = nw;
         h.n_lmt = cfg->n_lmt ? cfg->n_lmt : L;
+        h.flip_lmt = cfg->flip_lmt;
         h.slab = slab;
         h.slab_bytes = slab_bytes;
         WalkDev &w = wd[b];
@@ -560,7 +627,7 @@ psl_status psl_eval_neighbourhood(psl_ctx *ctx, uint32_t walk, uint32_t start, u
     const Tables tabs = tables_of(ctx);
     HIP_TRY(ctx, launch_suffix(ctx->d_walks, ctx->pure.d_batch, 1, tabs, ctx->stream));
     HIP_TRY(ctx, launch_eval(ctx->d_walks, ctx->pure.d_batch, ctx->pure.d_items, ctx->pure.n_items,
-                             tabs, ctx->stream));
+                             tabs, ctx->pure.waves, ctx->stream));
     HIP_TRY(ctx, launch_select(ctx->d_walks, ctx->pure.d_batch, 1, tabs, 1, ctx->d_choice, ctx->stream));
     if (F_dev)
         HIP_TRY(ctx, hipMemcpyAsync(F_dev, ctx->pure.d_f, sizeof(double) * n_lmt,
@@ -742,9 +809,11 @@ psl_status psl_eval_shape(psl_ctx *ctx, uint32_t L, uint32_t n_lmt, uint32_t n_w
     (void)ctx;
     if (L < 2 || L > PSL_L_MAX || n_lmt < 1 || n_lmt > L || n_walks < 1 || !cand_tiles || !k_splits)
         return PSL_E_INVAL;
-    uint32_t tiles = (n_lmt + kEvalThreads - 1) / kEvalThreads;
-    uint64_t total = (uint64_t)tiles * n_walks;
-    eval_shape(L, n_lmt, (uint32_t)std::min<uint64_t>(total, 1u << 30), cand_tiles, k_splits);
+    const uint32_t tile = 64u * eval_waves(&n_lmt, 1);
+    const uint32_t tiles = (n_lmt + tile - 1) / tile;
+    const uint64_t W = (uint64_t)tiles * (L - 1) * n_walks;
+    const uint32_t K = (uint32_t)std::max<uint64_t>(kTileK, (W + 4095) / 4096);
+    eval_shape_k(L, n_lmt, K, tile, cand_tiles, k_splits);
     return PSL_OK;
 }
 

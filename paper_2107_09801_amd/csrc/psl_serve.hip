@@ -37,7 +37,7 @@ uint64_t now_ns()
 // number of k-splits grows only while the batch has few candidate tiles).
 size_t scratch_bound(uint32_t L, uint32_t n_lmt)
 {
-    const uint64_t tiles = (n_lmt + kEvalThreads - 1) / kEvalThreads;
+    const uint64_t tiles = (n_lmt + 64 * kEvalWavesSmall - 1) / (64 * kEvalWavesSmall);
     const uint64_t ks_max = std::max<uint64_t>(1, ((L - 1 + 31) / 32) / (kTileK / 32));
     const uint64_t ks = std::min<uint64_t>(ks_max, (4096 + tiles - 1) / tiles);
     return (size_t)(12ull * ks * n_lmt + 12ull * n_lmt + 12ull * (L + 1) +
@@ -99,6 +99,7 @@ struct Server {
     DevBuf<uint32_t> d_mpart, d_m0, d_near, d_want;
     DevBuf<int32_t> d_p;
     uint32_t n_items = 0, max_L = 0;
+    int waves = kEvalWaves;
     bool dirty = true;
     // pinned staging, two halves used by alternate iterations
     char *stage[2] = {nullptr, nullptr};
@@ -316,24 +317,24 @@ psl_status Server::admit(char *&sp, char *stage_end)
 psl_status Server::upload_layout(char *&sp, char *stage_end)
 {
     const uint32_t n = (uint32_t)active.size();
-    uint64_t total_tiles = 0;
+    std::vector<uint32_t> Ls(n), nls(n);
     max_L = 0;
-    for (auto &j : active) {
-        const uint32_t nl = j.cfg.n_lmt ? j.cfg.n_lmt : j.cfg.L;
-        total_tiles += (nl + kEvalThreads - 1) / kEvalThreads;
-        max_L = std::max(max_L, j.cfg.L);
-    }
-    std::vector<uint32_t> tiles(n), ks(n);
-    size_t n_part = 0, n_cand = 0, n_suf = 0, items = 0;
     for (uint32_t b = 0; b < n; ++b) {
-        const Job &j = active[b];
-        const uint32_t nl = j.cfg.n_lmt ? j.cfg.n_lmt : j.cfg.L;
-        eval_shape(j.cfg.L, nl, (uint32_t)std::min<uint64_t>(total_tiles, 1u << 30), &tiles[b], &ks[b]);
-        n_part += (size_t)ks[b] * nl;
-        n_cand += nl;
-        n_suf += j.cfg.L + 1;
-        items += (size_t)tiles[b] * ks[b];
+        Ls[b] = active[b].cfg.L;
+        nls[b] = active[b].cfg.n_lmt ? active[b].cfg.n_lmt : active[b].cfg.L;
+        max_L = std::max(max_L, Ls[b]);
     }
+    EvalLayout lay;
+    eval_layout(Ls.data(), nls.data(), n, lay);
+    const std::vector<uint32_t> &tiles = lay.tiles, &ks = lay.ks;
+    size_t n_part = 0, n_cand = 0, n_suf = 0;
+    for (uint32_t b = 0; b < n; ++b) {
+        n_part += (size_t)ks[b] * nls[b];
+        n_cand += nls[b];
+        n_suf += Ls[b] + 1;
+    }
+    const size_t items = lay.items.size();
+    waves = lay.waves;
     const size_t need = sizeof(BatchEntry) * n + sizeof(EvalItem) * items + 128;
     if ((size_t)(stage_end - sp) < need) return fail(ctx, PSL_E_NOMEM, "serving staging too small");
     psl_status st;
@@ -349,7 +350,7 @@ psl_status Server::upload_layout(char *&sp, char *stage_end)
     EvalItem *it = (EvalItem *)sp;
     sp += sizeof(EvalItem) * items;
     sp = (char *)(((uintptr_t)sp + 63) & ~(uintptr_t)63);
-    size_t op = 0, oc = 0, os = 0, oi = 0;
+    size_t op = 0, oc = 0, os = 0;
     for (uint32_t b = 0; b < n; ++b) {
         const Job &j = active[b];
         const uint32_t nl = j.cfg.n_lmt ? j.cfg.n_lmt : j.cfg.L;
@@ -370,9 +371,8 @@ psl_status Server::upload_layout(char *&sp, char *stage_end)
         op += (size_t)ks[b] * nl;
         oc += nl;
         os += j.cfg.L + 1;
-        for (uint32_t t = 0; t < tiles[b]; ++t)
-            for (uint32_t s = 0; s < ks[b]; ++s) it[oi++] = EvalItem{b, t, s, 0};
     }
+    memcpy(it, lay.items.data(), sizeof(EvalItem) * items);
     HIP_TRY(ctx, hipMemcpyAsync(d_batch.p, be, sizeof(BatchEntry) * n, hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(ctx, hipMemcpyAsync(d_items.p, it, sizeof(EvalItem) * items, hipMemcpyHostToDevice,
                                 ctx->stream));
@@ -410,16 +410,17 @@ psl_status Server::iterate()
     retire_finished();
     {
         // worst case of this iteration's uploads: admissions, then the layout
-        // (work items <= 4096 + candidate tiles, see eval_shape)
+        // (work items <= 8 x (4096 + candidate tiles) with padding, see eval_layout)
         const size_t n_adm = std::min<size_t>(pending.size(), cfg.max_slots);
         uint64_t tiles = 0;
-        for (auto &j : active) tiles += ((j.cfg.n_lmt ? j.cfg.n_lmt : j.cfg.L) + kEvalThreads - 1) / kEvalThreads;
+        const uint32_t tl = 64 * kEvalWavesSmall;
+        for (auto &j : active) tiles += ((j.cfg.n_lmt ? j.cfg.n_lmt : j.cfg.L) + tl - 1) / tl;
         for (size_t x = 0; x < n_adm; ++x) {
             const Job &j = pending[x];
-            tiles += ((j.cfg.n_lmt ? j.cfg.n_lmt : j.cfg.L) + kEvalThreads - 1) / kEvalThreads;
+            tiles += ((j.cfg.n_lmt ? j.cfg.n_lmt : j.cfg.L) + tl - 1) / tl;
         }
         const size_t need = (n_adm + active.size()) * (sizeof(WalkDev) + 2 * sizeof(BatchEntry) + 8) +
-                            sizeof(EvalItem) * (4096 + tiles) + 4096;
+                            sizeof(EvalItem) * 8 * (4096 + tiles) + 4096;
         if ((st = ensure_stage(need))) return st;
     }
     char *sp = stage[cur];
@@ -430,11 +431,14 @@ psl_status Server::iterate()
     const uint32_t n = (uint32_t)active.size();
     const Tables tabs = tables_of(ctx);
     HIP_TRY(ctx, launch_suffix(ctx->d_walks, d_batch.p, n, tabs, ctx->stream));
-    HIP_TRY(ctx, launch_eval(ctx->d_walks, d_batch.p, d_items.p, n_items, tabs, ctx->stream));
+    HIP_TRY(ctx, launch_eval(ctx->d_walks, d_batch.p, d_items.p, n_items, tabs, waves, ctx->stream));
     HIP_TRY(ctx, launch_select(ctx->d_walks, d_batch.p, n, tabs, 0, nullptr, ctx->stream));
     HIP_TRY(ctx, launch_apply(ctx->d_walks, d_batch.p, n, max_L, -1, ctx->stream));
     HIP_TRY(ctx, launch_bookkeep(ctx->d_walks, d_batch.p, n, ctx->stream));
-    HIP_TRY(ctx, launch_corr(ctx->d_walks, d_batch.p, n, max_L, 1, ctx->stream));
+    HIP_TRY(ctx, launch_switch_corr(ctx->d_walks, d_batch.p, n, max_L, ctx->stream));
+    bool big = false;
+    for (auto &j : active) big |= j.cfg.flip_lmt > kFlipIncremental;
+    if (big) HIP_TRY(ctx, launch_corr(ctx->d_walks, d_batch.p, n, max_L, 1, ctx->stream));
     HIP_TRY(ctx, launch_fitness(ctx->d_walks, d_batch.p, n, tabs, 1, ctx->stream));
     uint64_t evals = 0, upd = 0;
     for (auto &j : active) {
@@ -673,6 +677,13 @@ psl_status psl_serve_poll(psl_ctx *ctx, uint64_t ticket, psl_job_result *out)
         return PSL_OK;
     }
     return s->live.count(ticket) ? PSL_E_AGAIN : PSL_E_STATE;
+}
+
+psl_status psl_serve_footprint(const psl_walk_cfg *cfg, uint64_t *bytes)
+{
+    if (!cfg || !bytes || cfg->L < 2 || cfg->L > PSL_L_MAX || cfg->n_lmt > cfg->L) return PSL_E_INVAL;
+    *bytes = job_footprint(*cfg);
+    return PSL_OK;
 }
 
 psl_status psl_serve_stats_read(psl_ctx *ctx, psl_serve_stats *out)

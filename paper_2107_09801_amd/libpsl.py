@@ -24,7 +24,7 @@ EXPORTS = ["psl_ctx_create", "psl_ctx_destroy", "psl_last_error", "psl_sync", "p
            "psl_free_walks", "psl_eval_neighbourhood", "psl_apply_flip", "psl_step_batch",
            "psl_read_walk", "psl_eval_shape", "psl_version", "psl_timing_enable",
            "psl_timing_read", "psl_set_option", "psl_serve_start", "psl_serve_submit",
-           "psl_serve_poll", "psl_serve_stats_read", "psl_serve_stop"]
+           "psl_serve_poll", "psl_serve_stats_read", "psl_serve_stop", "psl_serve_footprint"]
 OPT_NEAR_LIMIT = 1
 
 
@@ -142,6 +142,7 @@ def lib() -> ctypes.CDLL:
         "psl_serve_poll": (i32, [P, u64, ctypes.POINTER(JobResult)]),
         "psl_serve_stats_read": (i32, [P, ctypes.POINTER(ServeStats)]),
         "psl_serve_stop": (i32, [P, ctypes.c_int]),
+        "psl_serve_footprint": (i32, [ctypes.POINTER(WalkCfg), ctypes.POINTER(u64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -336,6 +337,17 @@ class Context:
         t = Timing()
         self._check(lib().psl_timing_read(self._h, ctypes.byref(t)))
         return t.as_dict()
+
+
+def serve_footprint(L: int, n_lmt: int = 0) -> int:
+    """Bytes a served job of length L (and N_lmt) counts against the budget."""
+    cfg = WalkCfg(L=L, alpha1=4, alpha2=13, n_lmt=n_lmt, ls_lmt=0, flip_lmt=0, switch_period=0,
+                  reserved=0, seed=0)
+    out = ctypes.c_uint64()
+    st = lib().psl_serve_footprint(ctypes.byref(cfg), ctypes.byref(out))
+    if st != OK:
+        raise PslError(st, "psl_serve_footprint")
+    return int(out.value)
 
 
 def version() -> str:

@@ -65,6 +65,17 @@ def test_version_and_shape_without_gpu():
     assert lib.psl_eval_shape(None, 1, 1, 1, ctypes.byref(t), ctypes.byref(k)) == libpsl.E_INVAL
 
 
+def test_serve_footprint_without_gpu():
+    from paper_2107_09801_amd import libpsl
+    a = libpsl.serve_footprint(30001, 256)
+    b = libpsl.serve_footprint(30001, 0)
+    c = libpsl.serve_footprint(1048575, 0)
+    assert 0 < a < b < c
+    assert c > 4 * 1048575 * 2           # at least C and C of local_best
+    with pytest.raises(libpsl.PslError):
+        libpsl.serve_footprint(1, 0)
+
+
 def test_null_context_is_rejected_without_gpu():
     from paper_2107_09801_amd import libpsl
     lib = libpsl.lib()

@@ -85,10 +85,11 @@ def test_served_results_equal_alone_and_oracle(ctx):
 
 
 def test_admission_fifo_within_budget(ctx):
-    # room for three L=30001, N_lmt=256 jobs at a time (about 0.88 MB each:
-    # slab plus the evaluation scratch bound)
+    # room for three L=30001, N_lmt=256 jobs at a time
     from paper_2107_09801_amd import libpsl
-    ctx.serve_start(hbm_budget=2_700_000, max_slots=64)
+    fp = libpsl.serve_footprint(30001, 256)
+    budget = 3 * fp + fp // 2
+    ctx.serve_start(hbm_budget=budget, max_slots=64)
     tickets = [ctx.serve_submit(30001, 100 + i, 6, n_lmt=256, switch_period=50) for i in range(10)]
     res = _wait(ctx, tickets)
     ctx.serve_stop(drain=True)
@@ -96,7 +97,7 @@ def test_admission_fifo_within_budget(ctx):
     assert admits == sorted(admits)
     st = ctx.serve_stats()
     assert st["completed"] == 10
-    assert st["peak_used"] <= 2_700_000 and st["peak_active"] == 3
+    assert st["peak_used"] <= budget and st["peak_active"] == 3
     with pytest.raises(libpsl.PslError) as e:
         ctx.serve_submit(30001, 1, 5)          # not serving any more
     assert e.value.status == libpsl.E_STATE

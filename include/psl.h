@@ -291,6 +291,32 @@ PSL_API psl_status psl_timing_enable(psl_ctx *ctx, int on);
 /* Wait for the recorded work and report the totals since psl_timing_enable. */
 PSL_API psl_status psl_timing_read(psl_ctx *ctx, psl_timing *out);
 
+/* --------------------------------------------------------- autotuner */
+
+/* Launch shape of the neighbourhood evaluation for a batch. */
+typedef struct {
+    int32_t waves;          /* wavefronts per block: 4 (256 candidates) or 8 (512)   */
+    int32_t persistent;     /* 1: a fixed grid of blocks_per_cu x CUs takes work
+                               items from per-XCD queues; 0: one block per item     */
+    int32_t blocks_per_cu;  /* resident blocks per CU of the persistent grid (1..3) */
+    int32_t reserved;
+    double  eval_ms;        /* measured mean launch time of this shape              */
+    double  default_ms;     /* measured mean launch time of the untuned default     */
+} psl_tune_choice;
+
+/* Time every candidate launch shape of the evaluation on these walks (their
+ * state is not changed), keep the fastest for every later batch with the same
+ * key (log2 of the largest L, of the median N_lmt and of the walk count, and
+ * whether the L differ by more than 4x), and report it. Blocking.
+ * Errors: PSL_E_INVAL, PSL_E_STATE, PSL_E_NOMEM, PSL_E_HIP. */
+PSL_API psl_status psl_autotune(psl_ctx *ctx, const uint32_t *walk_ids, uint32_t n,
+                                psl_tune_choice *out);
+
+/* Write / read the context's tuned shapes as text (one "key waves persistent
+ * blocks_per_cu" line each). Errors: PSL_E_INVAL (I/O or format). */
+PSL_API psl_status psl_tune_save(psl_ctx *ctx, const char *path);
+PSL_API psl_status psl_tune_load(psl_ctx *ctx, const char *path);
+
 /* ----------------------------------------------------------- options */
 
 /* PSL_OPT_NEAR_LIMIT: largest near-peak shift list (shifts k with |C_k|

@@ -98,6 +98,21 @@ struct EvalItem {
     uint32_t pad;
 };
 
+// Per-XCD work queues of the persistent evaluation: queue x holds the items
+// base[x] .. base[x]+count[x]-1; next[x] is its cursor (reset per launch).
+struct EvalQueues {
+    uint32_t base[8];
+    uint32_t count[8];
+    uint32_t next[8];
+};
+
+// Launch shape of the evaluation kernel.
+struct EvalShape {
+    int waves = kEvalWaves;     // wavefronts per block
+    int persistent = 0;         // 1: fixed grid over the per-XCD queues
+    uint32_t grid = 0;          // blocks of the persistent form
+};
+
 enum : uint32_t {
     STEP_IMPROVED = 1u,
     STEP_WORSE = 2u,

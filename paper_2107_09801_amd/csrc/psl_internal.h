@@ -19,6 +19,8 @@
 namespace psl_rt {
 
 using namespace psl;
+using psl::EvalShape;
+using psl::EvalQueues;
 
 // ------------------------------------------------------------ arena
 
@@ -89,7 +91,8 @@ struct BatchPlan {
     uint32_t max_L = 0, max_nw = 0;
     bool big_flips = false;           // some walk's Rand_flip exceeds the one-flip rebuild
     uint32_t n_items = 0;
-    int waves = kEvalWaves;           // wavefronts per evaluation block
+    EvalShape shape;                  // evaluation launch shape
+    EvalQueues *d_queues = nullptr;   // persistent evaluation: work queues
     BatchEntry *d_batch = nullptr;
     EvalItem *d_items = nullptr;
     hipGraph_t graph = nullptr;       // one captured step of this plan
@@ -129,6 +132,8 @@ struct psl_ctx {
     std::string err;
     int64_t near_limit = -1;          // PSL_OPT_NEAR_LIMIT
     psl_rt::Server *server = nullptr; // serving loop, when started
+    uint32_t n_cu = 256;              // compute units of the device
+    std::map<uint32_t, psl::EvalShape> tuned;  // autotuner choices by tune_key
     // timing
     bool timing = false;
     std::vector<hipEvent_t> ev;       // 3 per recorded step: eval start, eval end, step end
@@ -158,14 +163,23 @@ bool walk_ok(const psl_ctx *ctx, uint32_t id);
 // Launch layout of a batch's evaluation: candidate tiles and k-splits per
 // walk, and the work items in XCD-balanced order (see eval_layout).
 struct EvalLayout {
-    int waves = kEvalWaves;           // wavefronts per evaluation block
+    EvalShape shape;                  // launch shape the items are laid out for
     std::vector<uint32_t> tiles, ks;
-    std::vector<EvalItem> items;
+    std::vector<EvalItem> items;      // flat: padded XCD ranges; persistent: queues
+    EvalQueues queues{};              // persistent: queue ranges
 };
-void eval_layout(const uint32_t *Ls, const uint32_t *n_lmt, uint32_t n, EvalLayout &out);
+// Tuning key of a batch: (log2 of max L, log2 of the median N_lmt, log2 of
+// the walk count, uneven flag).
+uint32_t tune_key(const uint32_t *Ls, const uint32_t *n_lmt, uint32_t n);
+// The evaluation shape for a batch: the tuned one for its key, else defaults.
+EvalShape pick_shape(const psl_ctx *ctx, const uint32_t *Ls, const uint32_t *n_lmt, uint32_t n);
+void eval_layout(const uint32_t *Ls, const uint32_t *n_lmt, uint32_t n, const EvalShape &shape,
+                 EvalLayout &out);
 void eval_shape_k(uint32_t L, uint32_t n_lmt, uint32_t K, uint32_t tile, uint32_t *tiles, uint32_t *ksplit);
 int eval_waves(const uint32_t *n_lmt, uint32_t n);
 psl_status check_cfg(psl_ctx *ctx, const psl_walk_cfg *c);
+psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t n, uint32_t n_fixed,
+                     uint32_t start_fixed, const EvalShape *force = nullptr);
 uint32_t near_limit_for(const psl_ctx *ctx, uint32_t L);
 
 // Slab layout of one walk of length L: the pivot between guard words, then

@@ -540,15 +540,10 @@ __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const 
 // shifts (split 0 only), or, for pivots with many near-peak shifts, from
 // 32-bit maxima kept in the main loop.
 template <int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_eval(const WalkDev *__restrict__ walks,
-                                                       const BatchEntry *__restrict__ batch,
-                                                       const EvalItem *__restrict__ items,
-                                                       Tables tabs)
+__device__ __forceinline__ void eval_item(EvalLds &sh, const WalkDev *__restrict__ walks,
+                                          const BatchEntry *__restrict__ batch, const EvalItem it,
+                                          const Tables &tabs)
 {
-    __shared__ EvalLds sh;
-
-    const EvalItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
-    if (it.walk == kNoItem) return;     // padding of an XCD's range
     const BatchEntry be = batch[it.walk];
     const WalkDev &w = walks[be.slot];
     const int L = (int)w.L;
@@ -605,6 +600,53 @@ __global__ __launch_bounds__(64 * WAVES) void k_eval(const WalkDev *__restrict__
         be.Fpart[o] = sum + comp;
         be.Mpart[o] = mx;
     }
+}
+
+// One block per work item; items are laid out as 8 equal-cost XCD ranges
+// padded to equal length.
+template <int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_eval(const WalkDev *__restrict__ walks,
+                                                     const BatchEntry *__restrict__ batch,
+                                                     const EvalItem *__restrict__ items, Tables tabs)
+{
+    __shared__ EvalLds sh;
+    const EvalItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
+    if (it.walk == kNoItem) return;     // padding of an XCD's range
+    eval_item<WAVES>(sh, walks, batch, it, tabs);
+}
+
+// Persistent form: a fixed grid (blocks per CU x CUs) takes items from 8
+// per-XCD queues, its own XCD's first (longest items first), then the
+// others'. Every block leaves once all 8 queues are drained.
+template <int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_eval_persistent(const WalkDev *__restrict__ walks,
+                                                                const BatchEntry *__restrict__ batch,
+                                                                const EvalItem *__restrict__ items,
+                                                                Tables tabs, EvalQueues *queues)
+{
+    __shared__ EvalLds sh;
+    __shared__ uint32_t s_item;
+    uint32_t q = blockIdx.x % 8, dry = 0;
+    while (dry < 8) {
+        __syncthreads();                // the previous item is done with LDS
+        if (threadIdx.x == 0) {
+            const uint32_t idx = atomicAdd(&queues->next[q], 1u);
+            s_item = idx < queues->count[q] ? queues->base[q] + idx : kNoItem;
+        }
+        __syncthreads();
+        const uint32_t item = s_item;
+        if (item == kNoItem) {
+            q = (q + 1) % 8;
+            ++dry;
+            continue;
+        }
+        eval_item<WAVES>(sh, walks, batch, items[item], tabs);
+    }
+}
+
+__global__ void k_queue_reset(EvalQueues *queues)
+{
+    if (threadIdx.x < 8) queues->next[threadIdx.x] = 0;
 }
 
 // ------------------------------------------------------- selection
@@ -887,12 +929,22 @@ hipError_t launch_fitness(WalkDev *walks, const BatchEntry *batch, uint32_t nb, 
 }
 
 hipError_t launch_eval(const WalkDev *walks, const BatchEntry *batch, const EvalItem *items,
-                       uint32_t n_items, const Tables &tabs, int waves, hipStream_t s)
+                       uint32_t n_items, const Tables &tabs, const EvalShape &shape,
+                       EvalQueues *queues, hipStream_t s)
 {
-    if (waves == kEvalWavesSmall)
+    if (shape.persistent) {
+        k_queue_reset<<<1, 64, 0, s>>>(queues);
+        const uint32_t grid = shape.grid;
+        if (shape.waves == kEvalWavesSmall)
+            k_eval_persistent<kEvalWavesSmall><<<grid, 64 * kEvalWavesSmall, 0, s>>>(walks, batch, items,
+                                                                                    tabs, queues);
+        else
+            k_eval_persistent<kEvalWaves><<<grid, kEvalThreads, 0, s>>>(walks, batch, items, tabs, queues);
+    } else if (shape.waves == kEvalWavesSmall) {
         k_eval<kEvalWavesSmall><<<n_items, 64 * kEvalWavesSmall, 0, s>>>(walks, batch, items, tabs);
-    else
+    } else {
         k_eval<kEvalWaves><<<n_items, kEvalThreads, 0, s>>>(walks, batch, items, tabs);
+    }
     return hipGetLastError();
 }
 

@@ -15,7 +15,8 @@ hipError_t launch_switch_corr(WalkDev *walks, const BatchEntry *batch, uint32_t 
 hipError_t launch_fitness(WalkDev *walks, const BatchEntry *batch, uint32_t nb, const Tables &tabs,
                           int mode, hipStream_t s);
 hipError_t launch_eval(const WalkDev *walks, const BatchEntry *batch, const EvalItem *items,
-                       uint32_t n_items, const Tables &tabs, int waves, hipStream_t s);
+                       uint32_t n_items, const Tables &tabs, const EvalShape &shape,
+                       EvalQueues *queues, hipStream_t s);
 hipError_t launch_suffix(const WalkDev *walks, const BatchEntry *batch, uint32_t nb, const Tables &tabs,
                          hipStream_t s);
 hipError_t launch_select(WalkDev *walks, const BatchEntry *batch, uint32_t nb, const Tables &tabs,

@@ -89,6 +89,7 @@ void plan_free(psl_ctx *ctx, BatchPlan &pl)
     dev_free(ctx, pl.d_s0, false);
     dev_free(ctx, pl.d_m0, false);
     dev_free(ctx, pl.d_near, false);
+    dev_free(ctx, pl.d_queues, false);
     pl = BatchPlan();
 }
 
@@ -186,13 +187,45 @@ void eval_shape_k(uint32_t L, uint32_t n_lmt, uint32_t K, uint32_t tile, uint32_
     *ksplit = std::min(std::max<uint32_t>(ks, 1), ks_max);
 }
 
-void eval_layout(const uint32_t *Ls, const uint32_t *nl, uint32_t n, EvalLayout &out)
+uint32_t tune_key(const uint32_t *Ls, const uint32_t *nl, uint32_t n)
 {
+    uint32_t lmax = 0, lmin = UINT32_MAX;
+    std::vector<uint32_t> v(nl, nl + n);
+    for (uint32_t b = 0; b < n; ++b) {
+        lmax = std::max(lmax, Ls[b]);
+        lmin = std::min(lmin, Ls[b]);
+    }
+    std::nth_element(v.begin(), v.begin() + n / 2, v.end());
+    auto lg = [](uint64_t x) { uint32_t r = 0; while (x > 1) { x >>= 1; ++r; } return r; };
+    const uint32_t uneven = lmax > 4ull * lmin ? 1u : 0u;
+    return lg(lmax) << 24 | lg(v[n / 2]) << 16 | lg(n) << 8 | uneven;
+}
+
+EvalShape pick_shape(const psl_ctx *ctx, const uint32_t *Ls, const uint32_t *nl, uint32_t n)
+{
+    auto it = ctx->tuned.find(tune_key(Ls, nl, n));
+    if (it != ctx->tuned.end()) return it->second;
+    EvalShape sh;
+    sh.waves = eval_waves(nl, n);
+    // batches of very different L: dynamic per-XCD queues
+    uint32_t lmax = 0, lmin = UINT32_MAX;
+    for (uint32_t b = 0; b < n; ++b) {
+        lmax = std::max(lmax, Ls[b]);
+        lmin = std::min(lmin, Ls[b]);
+    }
+    sh.persistent = lmax > 4ull * lmin ? 1 : 0;
+    sh.grid = sh.persistent ? 3 * ctx->n_cu : 0;
+    return sh;
+}
+
+void eval_layout(const uint32_t *Ls, const uint32_t *nl, uint32_t n, const EvalShape &shape,
+                 EvalLayout &out)
+{
+    out.shape = shape;
     out.tiles.assign(n, 0);
     out.ks.assign(n, 0);
     out.items.clear();
-    out.waves = eval_waves(nl, n);
-    const uint32_t tile = 64u * out.waves;
+    const uint32_t tile = 64u * shape.waves;
     const uint32_t K = item_shifts(Ls, nl, n, tile);
     struct C { EvalItem it; double cost; };
     std::vector<C> all;
@@ -212,8 +245,9 @@ void eval_layout(const uint32_t *Ls, const uint32_t *nl, uint32_t n, EvalLayout 
         }
     }
     // 8 contiguous segments of equal cost (one per XCD, so a walk's items
-    // mostly share an L2), each in longest-first order, padded with no-op
-    // items to equal length (blocks map to XCDs round-robin).
+    // mostly share an L2), each in longest-first order. The one-block-per-
+    // item form pads them to equal length (blocks map to XCDs round-robin);
+    // the persistent form uses them as queues.
     std::vector<std::vector<C>> seg(8);
     double acc = 0.0;
     size_t x = 0;
@@ -227,17 +261,22 @@ void eval_layout(const uint32_t *Ls, const uint32_t *nl, uint32_t n, EvalLayout 
         std::stable_sort(sg.begin(), sg.end(), [](const C &a, const C &b) { return a.cost > b.cost; });
         cmax = std::max(cmax, sg.size());
     }
-    out.items.reserve(8 * cmax);
-    for (auto &sg : seg) {
+    out.items.reserve(shape.persistent ? all.size() : 8 * cmax);
+    for (int q = 0; q < 8; ++q) {
+        auto &sg = seg[q];
+        out.queues.base[q] = (uint32_t)out.items.size();
+        out.queues.count[q] = (uint32_t)sg.size();
+        out.queues.next[q] = 0;
         for (auto &c : sg) out.items.push_back(c.it);
-        for (size_t k = sg.size(); k < cmax; ++k) out.items.push_back(EvalItem{kNoItem, 0, 0, 0});
+        if (!shape.persistent)
+            for (size_t k = sg.size(); k < cmax; ++k) out.items.push_back(EvalItem{kNoItem, 0, 0, 0});
     }
 }
 
 // Builds (or reuses) the device layout of a batch: entries, eval work items
 // and scratch. n_fixed / start_fixed != UINT32_MAX: a pure single evaluation.
 psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t n, uint32_t n_fixed,
-                     uint32_t start_fixed)
+                     uint32_t start_fixed, const EvalShape *force)
 {
     const bool fixed = n_fixed != UINT32_MAX;
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
@@ -253,10 +292,11 @@ psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t 
         pl.max_nw = std::max(pl.max_nw, h.nw);
     }
     EvalLayout lay;
-    eval_layout(Ls.data(), n_l.data(), n, lay);
+    const EvalShape shape = force ? *force : pick_shape(ctx, Ls.data(), n_l.data(), n);
+    eval_layout(Ls.data(), n_l.data(), n, shape, lay);
     const std::vector<uint32_t> &tiles = lay.tiles, &ks = lay.ks;
     std::vector<EvalItem> &items = lay.items;
-    pl.waves = lay.waves;
+    pl.shape = lay.shape;
     size_t n_part = 0, n_cand = 0, n_suf = 0;
     for (uint32_t b = 0; b < n; ++b) {
         n_part += (size_t)ks[b] * n_l[b];
@@ -307,8 +347,11 @@ psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t 
     }
     if ((st = dev_alloc(ctx, &p, sizeof(BatchEntry) * n, false))) return st;
     pl.d_batch = (BatchEntry *)p;
-    if ((st = dev_alloc(ctx, &p, sizeof(EvalItem) * items.size(), false))) return st;
+    if ((st = dev_alloc(ctx, &p, sizeof(EvalItem) * std::max<size_t>(items.size(), 1), false))) return st;
     pl.d_items = (EvalItem *)p;
+    if ((st = dev_alloc(ctx, &p, sizeof(EvalQueues), false))) return st;
+    pl.d_queues = (EvalQueues *)p;
+    HIP_TRY(ctx, hipMemcpy(pl.d_queues, &lay.queues, sizeof(EvalQueues), hipMemcpyHostToDevice));
     HIP_TRY(ctx, hipMemcpy(pl.d_batch, be.data(), sizeof(BatchEntry) * n, hipMemcpyHostToDevice));
     HIP_TRY(ctx, hipMemcpy(pl.d_items, items.data(), sizeof(EvalItem) * items.size(),
                            hipMemcpyHostToDevice));
@@ -375,7 +418,8 @@ psl_status launch_step(psl_ctx *ctx, const BatchPlan &pl, const Tables &tabs, ui
     psl_status st;
     HIP_TRY(ctx, launch_suffix(ctx->d_walks, pl.d_batch, n, tabs, ctx->stream));
     if (timed && (st = timing_mark(ctx))) return st;
-    HIP_TRY(ctx, launch_eval(ctx->d_walks, pl.d_batch, pl.d_items, pl.n_items, tabs, pl.waves, ctx->stream));
+    HIP_TRY(ctx, launch_eval(ctx->d_walks, pl.d_batch, pl.d_items, pl.n_items, tabs, pl.shape, pl.d_queues,
+                             ctx->stream));
     if (timed && (st = timing_mark(ctx))) return st;
     HIP_TRY(ctx, launch_select(ctx->d_walks, pl.d_batch, n, tabs, 0, nullptr, ctx->stream));
     HIP_TRY(ctx, launch_apply(ctx->d_walks, pl.d_batch, n, pl.max_L, -1, ctx->stream));
@@ -449,6 +493,12 @@ psl_status psl_ctx_create(int device, void *hip_stream, void *arena, size_t aren
         ctx->own_stream = true;
     }
     if (arena) ctx->arena.reset((char *)arena, arena_bytes);
+    {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+            ctx->n_cu = (uint32_t)cus;
+        (void)hipGetLastError();
+    }
     if (hipMalloc(&ctx->d_choice, 256) != hipSuccess) {
         if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
         delete ctx;
@@ -627,7 +677,7 @@ psl_status psl_eval_neighbourhood(psl_ctx *ctx, uint32_t walk, uint32_t start, u
     const Tables tabs = tables_of(ctx);
     HIP_TRY(ctx, launch_suffix(ctx->d_walks, ctx->pure.d_batch, 1, tabs, ctx->stream));
     HIP_TRY(ctx, launch_eval(ctx->d_walks, ctx->pure.d_batch, ctx->pure.d_items, ctx->pure.n_items,
-                             tabs, ctx->pure.waves, ctx->stream));
+                             tabs, ctx->pure.shape, ctx->pure.d_queues, ctx->stream));
     HIP_TRY(ctx, launch_select(ctx->d_walks, ctx->pure.d_batch, 1, tabs, 1, ctx->d_choice, ctx->stream));
     if (F_dev)
         HIP_TRY(ctx, hipMemcpyAsync(F_dev, ctx->pure.d_f, sizeof(double) * n_lmt,
@@ -790,6 +840,129 @@ psl_status psl_timing_read(psl_ctx *ctx, psl_timing *out)
     return PSL_OK;
 }
 
+psl_status psl_autotune(psl_ctx *ctx, const uint32_t *walk_ids, uint32_t n, psl_tune_choice *out)
+{
+    if (!ctx) return PSL_E_INVAL;
+    if (serve_active(ctx)) return fail(ctx, PSL_E_STATE, "the context is serving");
+    if (n == 0 || !walk_ids) return fail(ctx, PSL_E_INVAL, "empty batch");
+    for (uint32_t b = 0; b < n; ++b)
+        if (!walk_ok(ctx, walk_ids[b])) return fail(ctx, PSL_E_STATE, "unknown walk %u", walk_ids[b]);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    std::vector<uint32_t> Ls(n), nl(n);
+    for (uint32_t b = 0; b < n; ++b) {
+        Ls[b] = ctx->walks[walk_ids[b]].L;
+        nl[b] = ctx->walks[walk_ids[b]].n_lmt;
+    }
+    const uint32_t key = tune_key(Ls.data(), nl.data(), n);
+    ctx->tuned.erase(key);
+    const EvalShape def = pick_shape(ctx, Ls.data(), nl.data(), n);
+    std::vector<EvalShape> cands;
+    for (int waves : {kEvalWaves, kEvalWavesSmall}) {
+        EvalShape f;
+        f.waves = waves;
+        cands.push_back(f);
+        for (uint32_t bpc = 1; bpc <= 3; ++bpc) {
+            EvalShape q;
+            q.waves = waves;
+            q.persistent = 1;
+            q.grid = bpc * ctx->n_cu;
+            cands.push_back(q);
+        }
+    }
+    const Tables tabs = tables_of(ctx);
+    hipEvent_t e0, e1;
+    HIP_TRY(ctx, hipEventCreate(&e0));
+    HIP_TRY(ctx, hipEventCreate(&e1));
+    double best_ms = 1e300, def_ms = 0.0;
+    EvalShape best = def;
+    psl_status st = PSL_OK;
+    for (const EvalShape &c : cands) {
+        BatchPlan tmp;
+        if ((st = make_plan(ctx, tmp, walk_ids, n, UINT32_MAX, 0, &c))) break;
+        hipError_t e = launch_suffix(ctx->d_walks, tmp.d_batch, n, tabs, ctx->stream);
+        if (e == hipSuccess)   // warm-up
+            e = launch_eval(ctx->d_walks, tmp.d_batch, tmp.d_items, tmp.n_items, tabs, tmp.shape,
+                            tmp.d_queues, ctx->stream);
+        const int reps = 2;
+        if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
+        for (int r = 0; r < reps && e == hipSuccess; ++r)
+            e = launch_eval(ctx->d_walks, tmp.d_batch, tmp.d_items, tmp.n_items, tabs, tmp.shape,
+                            tmp.d_queues, ctx->stream);
+        if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        plan_free(ctx, tmp);
+        if (e != hipSuccess) {
+            st = fail(ctx, PSL_E_HIP, "autotune: %s", hipGetErrorString(e));
+            break;
+        }
+        const double avg = ms / reps;
+        if (c.waves == def.waves && c.persistent == def.persistent && c.grid == def.grid) def_ms = avg;
+        if (avg < best_ms) {
+            best_ms = avg;
+            best = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st) return st;
+    ctx->tuned[key] = best;
+    plans_clear(ctx);            // later plans pick up the choice
+    if (out) {
+        memset(out, 0, sizeof *out);
+        out->waves = best.waves;
+        out->persistent = best.persistent;
+        out->blocks_per_cu = best.persistent ? (int32_t)(best.grid / ctx->n_cu) : 0;
+        out->eval_ms = best_ms;
+        out->default_ms = def_ms;
+    }
+    return PSL_OK;
+}
+
+psl_status psl_tune_save(psl_ctx *ctx, const char *path)
+{
+    if (!ctx || !path) return PSL_E_INVAL;
+    FILE *f = fopen(path, "w");
+    if (!f) return fail(ctx, PSL_E_INVAL, "cannot write %s", path);
+    for (const auto &kv : ctx->tuned)
+        fprintf(f, "%u %d %d %u\n", kv.first, kv.second.waves, kv.second.persistent,
+                kv.second.persistent ? kv.second.grid / ctx->n_cu : 0u);
+    fclose(f);
+    return PSL_OK;
+}
+
+psl_status psl_tune_load(psl_ctx *ctx, const char *path)
+{
+    if (!ctx || !path) return PSL_E_INVAL;
+    if (serve_active(ctx)) return fail(ctx, PSL_E_STATE, "the context is serving");
+    FILE *f = fopen(path, "r");
+    if (!f) return fail(ctx, PSL_E_INVAL, "cannot read %s", path);
+    std::map<uint32_t, EvalShape> got;
+    unsigned key, bpc;
+    int waves, pers;
+    int r;
+    while ((r = fscanf(f, "%u %d %d %u", &key, &waves, &pers, &bpc)) == 4) {
+        if ((waves != kEvalWaves && waves != kEvalWavesSmall) || (pers != 0 && pers != 1) ||
+            (pers && (bpc < 1 || bpc > 3))) {
+            fclose(f);
+            return fail(ctx, PSL_E_INVAL, "bad tuning line in %s", path);
+        }
+        EvalShape sh;
+        sh.waves = waves;
+        sh.persistent = pers;
+        sh.grid = pers ? bpc * ctx->n_cu : 0;
+        got[key] = sh;
+    }
+    fclose(f);
+    if (r != EOF) return fail(ctx, PSL_E_INVAL, "bad tuning file %s", path);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    for (auto &kv : got) ctx->tuned[kv.first] = kv.second;
+    plans_clear(ctx);
+    return PSL_OK;
+}
+
 psl_status psl_set_option(psl_ctx *ctx, int option, int64_t value)
 {
     if (!ctx) return PSL_E_INVAL;
@@ -809,7 +982,7 @@ psl_status psl_eval_shape(psl_ctx *ctx, uint32_t L, uint32_t n_lmt, uint32_t n_w
     (void)ctx;
     if (L < 2 || L > PSL_L_MAX || n_lmt < 1 || n_lmt > L || n_walks < 1 || !cand_tiles || !k_splits)
         return PSL_E_INVAL;
-    const uint32_t tile = 64u * eval_waves(&n_lmt, 1);
+    const uint32_t tile = 64u * (ctx ? pick_shape(ctx, &L, &n_lmt, 1).waves : eval_waves(&n_lmt, 1));
     const uint32_t tiles = (n_lmt + tile - 1) / tile;
     const uint64_t W = (uint64_t)tiles * (L - 1) * n_walks;
     const uint32_t K = (uint32_t)std::max<uint64_t>(kTileK, (W + 4095) / 4096);

@@ -99,7 +99,8 @@ struct Server {
     DevBuf<uint32_t> d_mpart, d_m0, d_near, d_want;
     DevBuf<int32_t> d_p;
     uint32_t n_items = 0, max_L = 0;
-    int waves = kEvalWaves;
+    EvalShape shape;
+    DevBuf<EvalQueues> d_queues;
     bool dirty = true;
     // pinned staging, two halves used by alternate iterations
     char *stage[2] = {nullptr, nullptr};
@@ -325,7 +326,7 @@ psl_status Server::upload_layout(char *&sp, char *stage_end)
         max_L = std::max(max_L, Ls[b]);
     }
     EvalLayout lay;
-    eval_layout(Ls.data(), nls.data(), n, lay);
+    eval_layout(Ls.data(), nls.data(), n, pick_shape(ctx, Ls.data(), nls.data(), n), lay);
     const std::vector<uint32_t> &tiles = lay.tiles, &ks = lay.ks;
     size_t n_part = 0, n_cand = 0, n_suf = 0;
     for (uint32_t b = 0; b < n; ++b) {
@@ -334,15 +335,15 @@ psl_status Server::upload_layout(char *&sp, char *stage_end)
         n_suf += Ls[b] + 1;
     }
     const size_t items = lay.items.size();
-    waves = lay.waves;
-    const size_t need = sizeof(BatchEntry) * n + sizeof(EvalItem) * items + 128;
+    shape = lay.shape;
+    const size_t need = sizeof(BatchEntry) * n + sizeof(EvalItem) * items + sizeof(EvalQueues) + 256;
     if ((size_t)(stage_end - sp) < need) return fail(ctx, PSL_E_NOMEM, "serving staging too small");
     psl_status st;
     if ((st = grow(ctx, d_batch, n)) || (st = grow(ctx, d_items, items)) ||
         (st = grow(ctx, d_fpart, n_part)) || (st = grow(ctx, d_mpart, n_part)) ||
         (st = grow(ctx, d_f, n_cand)) || (st = grow(ctx, d_p, n_cand)) ||
         (st = grow(ctx, d_s0, n_suf)) || (st = grow(ctx, d_m0, n_suf)) ||
-        (st = grow(ctx, d_near, (size_t)(kNearCap + 1) * n)))
+        (st = grow(ctx, d_near, (size_t)(kNearCap + 1) * n)) || (st = grow(ctx, d_queues, 1)))
         return st;
     BatchEntry *be = (BatchEntry *)sp;
     sp += sizeof(BatchEntry) * n;
@@ -376,6 +377,10 @@ psl_status Server::upload_layout(char *&sp, char *stage_end)
     HIP_TRY(ctx, hipMemcpyAsync(d_batch.p, be, sizeof(BatchEntry) * n, hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(ctx, hipMemcpyAsync(d_items.p, it, sizeof(EvalItem) * items, hipMemcpyHostToDevice,
                                 ctx->stream));
+    EvalQueues *qs = (EvalQueues *)sp;
+    sp += sizeof(EvalQueues);
+    *qs = lay.queues;
+    HIP_TRY(ctx, hipMemcpyAsync(d_queues.p, qs, sizeof(EvalQueues), hipMemcpyHostToDevice, ctx->stream));
     n_items = (uint32_t)items;
     dirty = false;
     return PSL_OK;
@@ -431,7 +436,7 @@ psl_status Server::iterate()
     const uint32_t n = (uint32_t)active.size();
     const Tables tabs = tables_of(ctx);
     HIP_TRY(ctx, launch_suffix(ctx->d_walks, d_batch.p, n, tabs, ctx->stream));
-    HIP_TRY(ctx, launch_eval(ctx->d_walks, d_batch.p, d_items.p, n_items, tabs, waves, ctx->stream));
+    HIP_TRY(ctx, launch_eval(ctx->d_walks, d_batch.p, d_items.p, n_items, tabs, shape, d_queues.p, ctx->stream));
     HIP_TRY(ctx, launch_select(ctx->d_walks, d_batch.p, n, tabs, 0, nullptr, ctx->stream));
     HIP_TRY(ctx, launch_apply(ctx->d_walks, d_batch.p, n, max_L, -1, ctx->stream));
     HIP_TRY(ctx, launch_bookkeep(ctx->d_walks, d_batch.p, n, ctx->stream));
@@ -568,6 +573,7 @@ void serve_shutdown(psl_ctx *ctx)
     release(ctx, s->d_near);
     release(ctx, s->d_want);
     release(ctx, s->d_p);
+    release(ctx, s->d_queues);
     for (int h = 0; h < 2; ++h) {
         if (s->stage[h]) (void)hipHostFree(s->stage[h]);
         if (s->stage_ev[h]) (void)hipEventDestroy(s->stage_ev[h]);

@@ -24,7 +24,8 @@ EXPORTS = ["psl_ctx_create", "psl_ctx_destroy", "psl_last_error", "psl_sync", "p
            "psl_free_walks", "psl_eval_neighbourhood", "psl_apply_flip", "psl_step_batch",
            "psl_read_walk", "psl_eval_shape", "psl_version", "psl_timing_enable",
            "psl_timing_read", "psl_set_option", "psl_serve_start", "psl_serve_submit",
-           "psl_serve_poll", "psl_serve_stats_read", "psl_serve_stop", "psl_serve_footprint"]
+           "psl_serve_poll", "psl_serve_stats_read", "psl_serve_stop", "psl_serve_footprint",
+           "psl_autotune", "psl_tune_save", "psl_tune_load"]
 OPT_NEAR_LIMIT = 1
 
 
@@ -99,6 +100,15 @@ class ServeStats(ctypes.Structure):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
+class TuneChoice(ctypes.Structure):
+    _fields_ = [("waves", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("eval_ms", ctypes.c_double), ("default_ms", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {n: getattr(self, n) for n, _ in self._fields_ if n != "reserved"}
+
+
 class Timing(ctypes.Structure):
     _fields_ = [("eval_ms", ctypes.c_double), ("eval_launches", ctypes.c_uint64),
                 ("rest_ms", ctypes.c_double), ("steps", ctypes.c_uint64)]
@@ -143,6 +153,9 @@ def lib() -> ctypes.CDLL:
         "psl_serve_stats_read": (i32, [P, ctypes.POINTER(ServeStats)]),
         "psl_serve_stop": (i32, [P, ctypes.c_int]),
         "psl_serve_footprint": (i32, [ctypes.POINTER(WalkCfg), ctypes.POINTER(u64)]),
+        "psl_autotune": (i32, [P, P, u32, ctypes.POINTER(TuneChoice)]),
+        "psl_tune_save": (i32, [P, ctypes.c_char_p]),
+        "psl_tune_load": (i32, [P, ctypes.c_char_p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -326,6 +339,18 @@ class Context:
 
     def serve_stop(self, drain: bool = True):
         self._check(lib().psl_serve_stop(self._h, 1 if drain else 0))
+
+    def autotune(self, ids) -> dict:
+        a = np.ascontiguousarray(ids, dtype=np.uint32)
+        c = TuneChoice()
+        self._check(lib().psl_autotune(self._h, _ptr(a), len(a), ctypes.byref(c)))
+        return c.as_dict()
+
+    def tune_save(self, path: str):
+        self._check(lib().psl_tune_save(self._h, path.encode()))
+
+    def tune_load(self, path: str):
+        self._check(lib().psl_tune_load(self._h, path.encode()))
 
     def set_option(self, option: int, value: int):
         self._check(lib().psl_set_option(self._h, option, value))

@@ -255,3 +255,37 @@ def test_graph_replays_match_eager(ctx):
             for key in ("psl_best", "alpha", "unimproved", "q", "last_k", "value_local"):
                 assert ga[key] == gb[key], (r, key)
     ctx.free_walks(eager + graph + other)
+
+
+def test_autotune_shapes_keep_results(ctx, tmp_path):
+    """Every launch shape the autotuner may pick gives the same walks: a batch
+    stepped under the tuned shape equals the same batch under the defaults
+    (fresh context), and the tuning file round-trips."""
+    from paper_2107_09801_amd import libpsl
+    Ls = [64, 513, 2000, 4097, 9000]
+
+    def batch(c):
+        ids = []
+        for L in Ls:
+            ids += c.init_walks(L, 2, 31 + L, n_lmt=0, switch_period=6, flip_lmt=min(5, L))
+        return ids
+
+    ids = batch(ctx)
+    choice = ctx.autotune(ids)
+    assert choice["waves"] in (4, 8) and choice["persistent"] in (0, 1)
+    assert choice["eval_ms"] > 0 and choice["eval_ms"] <= choice["default_ms"] * 1.0001
+    ctx.step_batch(ids, 12)
+    path = str(tmp_path / "tune.txt")
+    ctx.tune_save(path)
+    other = libpsl.Context(0)
+    ref = batch(other)
+    other.step_batch(ref, 12)
+    for a, b in zip(ids, ref):
+        ga, gb = ctx.read_walk(a), other.read_walk(b)
+        for key in ("pivot", "C", "best", "local_best"):
+            assert np.array_equal(ga[key], gb[key]), key
+        assert abs(ga["value_local"] - gb["value_local"]) <= F_RTOL * ga["value_local"]
+    other.tune_load(path)
+    assert other.autotune(ref)["waves"] in (4, 8)
+    other.close()
+    ctx.free_walks(ids)

@@ -328,6 +328,40 @@ PSL_API psl_status psl_tune_load(psl_ctx *ctx, const char *path);
 #define PSL_OPT_NEAR_LIMIT 1
 PSL_API psl_status psl_set_option(psl_ctx *ctx, int option, int64_t value);
 
+/* --------------------------------------------------- trace, checkpoint */
+
+/* One step of a walk as recorded by the trace ring. */
+typedef struct {
+    uint64_t t;             /* step number (0-based)                              */
+    uint32_t start;         /* start of the limited neighbourhood                 */
+    uint32_t k;             /* the move                                           */
+    double   value_step;    /* F of the move                                      */
+    int32_t  psl_k;         /* PSL of the move                                    */
+    int32_t  psl_best;      /* best PSL after the step                            */
+    uint32_t alpha;         /* exponent after the step                            */
+    uint32_t flags;         /* PSL_STEP_* bits                                    */
+} psl_trace_entry;
+
+/* Record every later step of `walk` into a device ring of `capacity` entries
+ * (0 stops recording and frees the ring). Errors: PSL_E_STATE, PSL_E_NOMEM. */
+PSL_API psl_status psl_trace_enable(psl_ctx *ctx, uint32_t walk, uint32_t capacity);
+
+/* Copy the most recent min(max_entries, recorded, capacity) entries, oldest
+ * first, to host memory; *n_out receives the count. Waits for queued work.
+ * Errors: PSL_E_STATE (unknown walk or no ring), PSL_E_HIP. */
+PSL_API psl_status psl_trace_read(psl_ctx *ctx, uint32_t walk, psl_trace_entry *out,
+                                  uint32_t max_entries, uint32_t *n_out);
+
+/* Checkpoint restore: overwrite `walk` (same L) with a state read earlier by
+ * psl_read_walk -- its scalars (exponent, v_local, psl_best, unimproved, t, q,
+ * seed and control parameters) and its pivot, local_best and best bits (host,
+ * ceil(L/64) words each). C, C of local_best and the pivot's F and PSL are
+ * recomputed from the bits, so run N steps + read + restore + run M steps
+ * equals N + M steps. Blocking. Errors: PSL_E_INVAL, PSL_E_STATE, PSL_E_HIP. */
+PSL_API psl_status psl_restore_walk(psl_ctx *ctx, uint32_t walk, const psl_walk_state *state,
+                                    const uint64_t *pivot_bits, const uint64_t *local_best_bits,
+                                    const uint64_t *best_bits);
+
 /* ----------------------------------------------------- introspection */
 
 /* Number of device work items, blocks per item and k-splits the evaluation

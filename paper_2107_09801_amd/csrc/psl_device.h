@@ -61,6 +61,17 @@ struct WalkDev {
     uint32_t flags;
     uint32_t pending;       // 1: C, F and PSL of the pivot must be rebuilt
     uint32_t n_flips;       // entries of flips[] for the pending rebuild
+    uint32_t trace_cap;     // entries of the trace ring (0: no trace)
+    struct TraceEntry *trace;   // ring, entry t % trace_cap for step t
+};
+
+// One step of the trace ring (layout of psl_trace_entry).
+struct TraceEntry {
+    uint64_t t;
+    uint32_t start, k;
+    double value_step;
+    int32_t psl_k, psl_best;
+    uint32_t alpha, flags;
 };
 
 struct Tables {

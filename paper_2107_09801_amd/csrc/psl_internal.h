@@ -81,6 +81,7 @@ private:
 struct WalkHost {
     bool active = false;
     uint32_t L = 0, nw = 0, n_lmt = 0, flip_lmt = 0;
+    void *trace = nullptr;            // trace ring (hipMalloc), if enabled
     void *slab = nullptr;
     size_t slab_bytes = 0;
 };

@@ -130,14 +130,15 @@ __global__ void k_init_bits(WalkDev *walks, const BatchEntry *batch, const uint3
 // per XOR and popcount.
 // only_pending == 0: every walk (init; C of local_best = C as well);
 // only_pending == 1: walks left pending by a switch whose Rand_flip is too
-// large for the one-flip rebuild (k_switch_corr).
+// large for the one-flip rebuild (k_switch_corr);
+// only_pending == 2: every walk, C only (checkpoint restore).
 constexpr int kCorrThreads = 256;
 constexpr int kCorrSeg = 1024;        // staged 32-bit words per segment
 __global__ __launch_bounds__(kCorrThreads) void k_corr(WalkDev *walks, const BatchEntry *batch,
                                                        int only_pending)
 {
     WalkDev &w = walks[batch[blockIdx.y].slot];
-    if (only_pending && !(w.pending && w.n_flips > kFlipIncremental)) return;
+    if (only_pending == 1 && !(w.pending && w.n_flips > kFlipIncremental)) return;
     const uint32_t L = w.L;
     const uint32_t k0 = blockIdx.x * kCorrThreads;
     if (k0 >= L) return;
@@ -172,7 +173,7 @@ __global__ __launch_bounds__(kCorrThreads) void k_corr(WalkDev *walks, const Bat
     if (k < L) {
         const int32_t c = (int32_t)nprod - 2 * (int32_t)diff;
         w.C[k] = c;
-        if (!only_pending) w.C_lb[k] = c;
+        if (only_pending == 0) w.C_lb[k] = c;
     }
 }
 
@@ -846,9 +847,21 @@ __global__ __launch_bounds__(kBookThreads) void k_bookkeep(WalkDev *walks, const
             if (w.switch_period == 0 && w.unimproved > w.ls_lmt) sw = 1;
         }
         if (w.switch_period > 0 && ((w.t + 1u) % w.switch_period) == 0) sw = 1;
-        w.t += 1;
         if (sw) flags |= STEP_SWITCHED;
         w.flags = flags;
+        if (w.trace_cap) {
+            TraceEntry e;
+            e.t = w.t;
+            e.start = w.start;
+            e.k = w.k;
+            e.value_step = w.value_step;
+            e.psl_k = w.psl_k;
+            e.psl_best = w.psl_best;
+            e.alpha = sw ? (w.alpha == w.alpha1 ? w.alpha2 : w.alpha1) : w.alpha;
+            e.flags = flags;
+            w.trace[w.t % w.trace_cap] = e;
+        }
+        w.t += 1;
         s_improved = improved;
         s_switch = sw;
     }

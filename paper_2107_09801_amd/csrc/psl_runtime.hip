@@ -514,8 +514,10 @@ void psl_ctx_destroy(psl_ctx *ctx)
     serve_shutdown(ctx);
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
-    for (auto &h : ctx->walks)
+    for (auto &h : ctx->walks) {
         if (h.active) dev_free(ctx, h.slab, true);
+        dev_free(ctx, h.trace, false);
+    }
     plans_clear(ctx);
     for (uint32_t a = 1; a <= PSL_ALPHA_MAX; ++a) dev_free(ctx, ctx->d_T[a], false);
     dev_free(ctx, ctx->d_walks, false);
@@ -655,6 +657,7 @@ psl_status psl_free_walks(psl_ctx *ctx, const uint32_t *walk_ids, uint32_t n)
         }
         WalkHost &h = ctx->walks[id];
         dev_free(ctx, h.slab, true);
+        dev_free(ctx, h.trace, false);
         h = WalkHost();
         ctx->free_slots.push_back(id);
     }
@@ -973,6 +976,135 @@ psl_status psl_set_option(psl_ctx *ctx, int option, int64_t value)
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     ctx->near_limit = value;
     plans_clear(ctx);            // cached layouts carry the old value
+    return PSL_OK;
+}
+
+psl_status psl_trace_enable(psl_ctx *ctx, uint32_t walk, uint32_t capacity)
+{
+    if (!ctx) return PSL_E_INVAL;
+    if (serve_active(ctx)) return fail(ctx, PSL_E_STATE, "the context is serving");
+    if (!walk_ok(ctx, walk)) return fail(ctx, PSL_E_STATE, "unknown walk %u", walk);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    WalkHost &h = ctx->walks[walk];
+    void *ring = nullptr;
+    if (capacity) {
+        psl_status st = dev_alloc(ctx, &ring, sizeof(TraceEntry) * capacity, false);
+        if (st) return st;
+    }
+    WalkDev w;
+    HIP_TRY(ctx, hipMemcpy(&w, ctx->d_walks + walk, sizeof w, hipMemcpyDeviceToHost));
+    w.trace = (TraceEntry *)ring;
+    w.trace_cap = capacity;
+    HIP_TRY(ctx, hipMemcpy(ctx->d_walks + walk, &w, sizeof w, hipMemcpyHostToDevice));
+    dev_free(ctx, h.trace, false);
+    h.trace = ring;
+    return PSL_OK;
+}
+
+psl_status psl_trace_read(psl_ctx *ctx, uint32_t walk, psl_trace_entry *out, uint32_t max_entries,
+                          uint32_t *n_out)
+{
+    if (!ctx || !n_out || (max_entries && !out)) return PSL_E_INVAL;
+    if (serve_active(ctx)) return fail(ctx, PSL_E_STATE, "the context is serving");
+    if (!walk_ok(ctx, walk)) return fail(ctx, PSL_E_STATE, "unknown walk %u", walk);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    WalkDev w;
+    HIP_TRY(ctx, hipMemcpy(&w, ctx->d_walks + walk, sizeof w, hipMemcpyDeviceToHost));
+    if (!w.trace_cap) return fail(ctx, PSL_E_STATE, "walk %u has no trace", walk);
+    std::vector<TraceEntry> ring(w.trace_cap);
+    HIP_TRY(ctx, hipMemcpy(ring.data(), w.trace, sizeof(TraceEntry) * w.trace_cap, hipMemcpyDeviceToHost));
+    const uint64_t have = std::min<uint64_t>(w.t, w.trace_cap);
+    const uint64_t n = std::min<uint64_t>(have, max_entries);
+    for (uint64_t x = 0; x < n; ++x) {
+        const uint64_t t = w.t - n + x;
+        const TraceEntry &e = ring[t % w.trace_cap];
+        psl_trace_entry &o = out[x];
+        o.t = e.t;
+        o.start = e.start;
+        o.k = e.k;
+        o.value_step = e.value_step;
+        o.psl_k = e.psl_k;
+        o.psl_best = e.psl_best;
+        o.alpha = e.alpha;
+        o.flags = e.flags;
+    }
+    *n_out = (uint32_t)n;
+    return PSL_OK;
+}
+
+psl_status psl_restore_walk(psl_ctx *ctx, uint32_t walk, const psl_walk_state *st, const uint64_t *pivot,
+                            const uint64_t *local_best, const uint64_t *best)
+{
+    if (!ctx) return PSL_E_INVAL;
+    if (serve_active(ctx)) return fail(ctx, PSL_E_STATE, "the context is serving");
+    if (!walk_ok(ctx, walk)) return fail(ctx, PSL_E_STATE, "unknown walk %u", walk);
+    if (!st || !pivot || !local_best || !best) return fail(ctx, PSL_E_INVAL, "null argument");
+    WalkHost &h = ctx->walks[walk];
+    psl_walk_cfg c;
+    memset(&c, 0, sizeof c);
+    c.L = st->L;
+    c.alpha1 = st->alpha1;
+    c.alpha2 = st->alpha2;
+    c.n_lmt = st->n_lmt;
+    c.ls_lmt = st->ls_lmt;
+    c.flip_lmt = st->flip_lmt;
+    c.switch_period = st->switch_period;
+    c.seed = st->seed;
+    psl_status s2 = check_cfg(ctx, &c);
+    if (s2) return s2;
+    if (st->L != h.L) return fail(ctx, PSL_E_INVAL, "state of L=%u for a walk of L=%u", st->L, h.L);
+    if (st->alpha != st->alpha1 && st->alpha != st->alpha2) return fail(ctx, PSL_E_INVAL, "alpha");
+    const uint32_t nw = h.nw, L = h.L;
+    if ((L & 63u) && ((pivot[nw - 1] | local_best[nw - 1] | best[nw - 1]) >> (L & 63u)))
+        return fail(ctx, PSL_E_INVAL, "bits set at or beyond L");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    WalkDev w;
+    HIP_TRY(ctx, hipMemcpy(&w, ctx->d_walks + walk, sizeof w, hipMemcpyDeviceToHost));
+    w.seed = st->seed;
+    w.alpha1 = st->alpha1;
+    w.alpha2 = st->alpha2;
+    w.alpha = st->alpha;
+    w.n_lmt = st->n_lmt ? st->n_lmt : L;
+    w.ls_lmt = st->ls_lmt;
+    w.flip_lmt = st->flip_lmt;
+    w.switch_period = st->switch_period;
+    w.t = st->t;
+    w.q = st->q;
+    w.value_local = st->value_local;
+    w.psl_best = st->psl_best;
+    w.unimproved = st->unimproved;
+    w.pending = 0;
+    w.n_flips = 0;
+    w.flags = 0;
+    HIP_TRY(ctx, hipMemcpy(ctx->d_walks + walk, &w, sizeof w, hipMemcpyHostToDevice));
+    h.n_lmt = w.n_lmt;
+    h.flip_lmt = w.flip_lmt;
+    plans_clear(ctx);            // N_lmt may differ
+    // C of local_best (and C) from local_best's bits, then C from the pivot's
+    BatchPlan one;
+    void *p;
+    psl_status rs = dev_alloc(ctx, &p, sizeof(BatchEntry), false);
+    if (rs) return rs;
+    one.d_batch = (BatchEntry *)p;
+    BatchEntry e;
+    memset(&e, 0, sizeof e);
+    e.slot = walk;
+    hipError_t r = hipMemcpy(one.d_batch, &e, sizeof e, hipMemcpyHostToDevice);
+    const Tables tabs = tables_of(ctx);
+    if (r == hipSuccess) r = hipMemcpy(w.pivot, local_best, 8ull * nw, hipMemcpyHostToDevice);
+    if (r == hipSuccess) r = launch_corr(ctx->d_walks, one.d_batch, 1, L, 0, ctx->stream);
+    if (r == hipSuccess) r = hipStreamSynchronize(ctx->stream);
+    if (r == hipSuccess) r = hipMemcpy(w.pivot, pivot, 8ull * nw, hipMemcpyHostToDevice);
+    if (r == hipSuccess) r = hipMemcpy(w.local_best, local_best, 8ull * nw, hipMemcpyHostToDevice);
+    if (r == hipSuccess) r = hipMemcpy(w.best, best, 8ull * nw, hipMemcpyHostToDevice);
+    if (r == hipSuccess) r = launch_corr(ctx->d_walks, one.d_batch, 1, L, 2, ctx->stream);
+    if (r == hipSuccess) r = launch_fitness(ctx->d_walks, one.d_batch, 1, tabs, 2, ctx->stream);
+    if (r == hipSuccess) r = hipStreamSynchronize(ctx->stream);
+    plan_free(ctx, one);
+    if (r != hipSuccess) return fail(ctx, PSL_E_HIP, "restore: %s", hipGetErrorString(r));
     return PSL_OK;
 }
 

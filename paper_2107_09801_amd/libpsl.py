@@ -25,7 +25,8 @@ EXPORTS = ["psl_ctx_create", "psl_ctx_destroy", "psl_last_error", "psl_sync", "p
            "psl_read_walk", "psl_eval_shape", "psl_version", "psl_timing_enable",
            "psl_timing_read", "psl_set_option", "psl_serve_start", "psl_serve_submit",
            "psl_serve_poll", "psl_serve_stats_read", "psl_serve_stop", "psl_serve_footprint",
-           "psl_autotune", "psl_tune_save", "psl_tune_load"]
+           "psl_autotune", "psl_tune_save", "psl_tune_load", "psl_trace_enable",
+           "psl_trace_read", "psl_restore_walk"]
 OPT_NEAR_LIMIT = 1
 
 
@@ -100,6 +101,15 @@ class ServeStats(ctypes.Structure):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
+class TraceEntry(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_uint64), ("start", ctypes.c_uint32), ("k", ctypes.c_uint32),
+                ("value_step", ctypes.c_double), ("psl_k", ctypes.c_int32),
+                ("psl_best", ctypes.c_int32), ("alpha", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+    def as_dict(self) -> dict:
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
 class TuneChoice(ctypes.Structure):
     _fields_ = [("waves", ctypes.c_int32), ("persistent", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32),
@@ -156,6 +166,9 @@ def lib() -> ctypes.CDLL:
         "psl_autotune": (i32, [P, P, u32, ctypes.POINTER(TuneChoice)]),
         "psl_tune_save": (i32, [P, ctypes.c_char_p]),
         "psl_tune_load": (i32, [P, ctypes.c_char_p]),
+        "psl_trace_enable": (i32, [P, u32, u32]),
+        "psl_trace_read": (i32, [P, u32, ctypes.POINTER(TraceEntry), u32, ctypes.POINTER(u32)]),
+        "psl_restore_walk": (i32, [P, u32, ctypes.POINTER(WalkState), P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -339,6 +352,29 @@ class Context:
 
     def serve_stop(self, drain: bool = True):
         self._check(lib().psl_serve_stop(self._h, 1 if drain else 0))
+
+    def trace_enable(self, walk: int, capacity: int):
+        self._check(lib().psl_trace_enable(self._h, walk, capacity))
+
+    def trace_read(self, walk: int, max_entries: int) -> list[dict]:
+        buf = (TraceEntry * max(max_entries, 1))()
+        n = ctypes.c_uint32()
+        self._check(lib().psl_trace_read(self._h, walk, buf, max_entries, ctypes.byref(n)))
+        return [buf[i].as_dict() for i in range(n.value)]
+
+    def checkpoint(self, walk: int) -> dict:
+        """Everything psl_restore_walk needs: the state struct and the three bit sets."""
+        st = WalkState()
+        self._check(lib().psl_read_walk(self._h, walk, ctypes.byref(st), None, None, None, None))
+        nw = n_words(st.L)
+        piv, lb, best = (np.zeros(nw, np.uint64) for _ in range(3))
+        self._check(lib().psl_read_walk(self._h, walk, None, _ptr(piv), _ptr(lb), _ptr(best), None))
+        return {"state": st, "pivot": piv, "local_best": lb, "best": best}
+
+    def restore(self, walk: int, ck: dict):
+        self._check(lib().psl_restore_walk(self._h, walk, ctypes.byref(ck["state"]),
+                                           _ptr(ck["pivot"]), _ptr(ck["local_best"]),
+                                           _ptr(ck["best"])))
 
     def autotune(self, ids) -> dict:
         a = np.ascontiguousarray(ids, dtype=np.uint32)

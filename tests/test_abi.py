@@ -39,7 +39,7 @@ def test_struct_layouts_match_header(tmp_path):
                    ' sizeof(psl_walk_cfg), sizeof(psl_choice), sizeof(psl_walk_state),'
                    ' offsetof(psl_walk_state, t), offsetof(psl_choice, F_min), sizeof(psl_serve_cfg),'
                    ' sizeof(psl_job), sizeof(psl_job_result), sizeof(psl_serve_stats),'
-                   ' sizeof(psl_timing)); printf("%zu\\n", sizeof(psl_tune_choice)); return 0;}\n')
+                   ' sizeof(psl_timing)); printf("%zu %zu\\n", sizeof(psl_tune_choice), sizeof(psl_trace_entry)); return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)],
                    check=True)
@@ -49,7 +49,8 @@ def test_struct_layouts_match_header(tmp_path):
             ctypes.sizeof(libpsl.WalkState), libpsl.WalkState.t.offset, libpsl.Choice.F_min.offset,
             ctypes.sizeof(libpsl.ServeCfg), ctypes.sizeof(libpsl.Job),
             ctypes.sizeof(libpsl.JobResult), ctypes.sizeof(libpsl.ServeStats),
-            ctypes.sizeof(libpsl.Timing), ctypes.sizeof(libpsl.TuneChoice)]
+            ctypes.sizeof(libpsl.Timing), ctypes.sizeof(libpsl.TuneChoice),
+            ctypes.sizeof(libpsl.TraceEntry)]
     assert got == want
 
 

@@ -289,3 +289,45 @@ def test_autotune_shapes_keep_results(ctx, tmp_path):
     assert other.autotune(ref)["waves"] in (4, 8)
     other.close()
     ctx.free_walks(ids)
+
+
+def test_checkpoint_restore_continues_exactly(ctx):
+    """N steps, checkpoint, restore into another walk, M steps == N + M steps."""
+    L, seed, N, M = 2000, 77, 17, 13
+    kw = dict(alpha1=4, alpha2=11, n_lmt=0, ls_lmt=4, flip_lmt=7, switch_period=0)
+    (a,) = ctx.init_walks(L, 1, seed, **kw)
+    (b,) = ctx.init_walks(L, 1, seed, **kw)
+    ctx.step_batch([a], N + M)
+    ctx.step_batch([b], N)
+    ck = ctx.checkpoint(b)
+    ctx.free_walks([b])
+    (c,) = ctx.init_walks(L, 1, 999, alpha1=13, alpha2=13, n_lmt=100, switch_period=3)
+    ctx.restore(c, ck)
+    ctx.step_batch([c], M)
+    ga, gc = ctx.read_walk(a), ctx.read_walk(c)
+    for key in ("pivot", "C", "local_best", "best"):
+        assert np.array_equal(ga[key], gc[key]), key
+    for key in ("t", "q", "alpha", "psl_best", "unimproved", "psl_pivot", "last_k", "value_local"):
+        assert ga[key] == gc[key], key
+    ctx.free_walks([a, c])
+
+
+def test_trace_ring_matches_oracle(ctx):
+    L, seed, steps, cap = 1001, 4321, 40, 16
+    (w,) = ctx.init_walks(L, 1, seed, alpha1=4, alpha2=13, n_lmt=0, flip_lmt=10, switch_period=9)
+    ctx.trace_enable(w, cap)
+    ow = oracle.Walk(oracle.WalkConfig(L=L, seed=seed, alpha1=4, alpha2=13, n_lmt=L, flip_lmt=10,
+                                       switch_period=9), margin=MARGIN, nthreads=8)
+    ctx.step_batch([w], steps)
+    trs = [ow.step() for _ in range(steps)]
+    got = ctx.trace_read(w, 100)
+    assert [e["t"] for e in got] == list(range(steps - cap, steps))
+    for e in got:
+        tr = trs[e["t"]]
+        assert e["start"] == tr["start"] and e["k"] == tr["k"]
+        assert abs(e["value_step"] - tr["value_step"]) <= F_RTOL * tr["value_step"]
+        assert e["psl_k"] == tr["psl_k"] and e["psl_best"] == tr["psl_best"]
+        assert e["alpha"] == tr["alpha"]
+        assert bool(e["flags"] & 4) == bool(tr["flags"] & oracle.SWITCHED)
+    ctx.trace_enable(w, 0)
+    ctx.free_walks([w])

@@ -68,6 +68,15 @@ def test_walk_step_properties(L, n_lmt, period, ls):
         want_best = min(prev["psl_best"], min(Px))
         assert st["psl_best"] == want_best
         assert _exact_psl_of_bits(st["best"], L) == want_best
+        if min(Px) < prev["psl_best"]:
+            # the first best-PSL neighbour in scan order replaces solution_best
+            jb = cand[Px.index(min(Px))]
+            nb = prev["pivot"].copy()
+            nb[jb // 64] ^= np.uint64(1) << np.uint64(jb % 64)
+            assert np.array_equal(st["best"], nb)
+        else:
+            # ties and worse leave solution_best as it was
+            assert np.array_equal(st["best"], prev["best"])
         switched = bool(tr["flags"] & oracle.SWITCHED)
         improved = tr["value_step"] < prev["value_local"] * (1 - oracle.TAU)
         worse = tr["value_step"] > prev["value_local"] * (1 + oracle.TAU)

@@ -27,6 +27,10 @@ constexpr uint32_t kFlipIncremental = 64;  // Rand_flip sizes rebuilt by one-fli
 // [-(nw+2)*64, (2*nw+2)*64), and the guards read as zero.
 __host__ __device__ constexpr uint32_t guard_words(uint32_t nw) { return nw + 2; }
 
+// Entries of the per-step chunk suffix arrays: one per 32-shift chunk of
+// k = 1..L-1, plus a terminating zero.
+__host__ __device__ constexpr uint32_t suffix_len(uint32_t L) { return (L - 1 + 31) / 32 + 1; }
+
 struct WalkDev {
     // storage (slab)
     uint64_t *pivot;        // nw words
@@ -86,9 +90,10 @@ struct BatchEntry {
     uint32_t *Mpart;        // ksplit * n_lmt partial maxima of hi32(T(|C'|))
     double *F;              // n_lmt: F per scan index
     int32_t *P;             // n_lmt: PSL per scan index
-    double *S0;             // L+1: S0[k] = sum_{k<=k'<L} T(|C_k'|), S0[L] = 0
-    uint32_t *M0;           // L+1: max_{k<=k'<L} hi32(T(|C_k'|)), M0[L] = 0
+    double *S0;             // suffix_len(L): S0[x] = sum_{1+32x<=k'<L} T(|C_k'|), last = 0
+    uint32_t *M0;           // suffix_len(L): max of hi32(T(|C_k'|)) over the same range
     uint32_t *near;         // 1 + kNearCap: count, then the near-peak shifts
+    struct SelPart *red;    // combine blocks: per block minimum F and first minimum PSL
     uint32_t slot;          // walk slot
     uint32_t ksplit;        // k-splits of the evaluation
     uint32_t tiles;         // candidate tiles of the evaluation
@@ -98,6 +103,15 @@ struct BatchEntry {
     uint32_t near_lim;      // largest near-peak list handled sparsely
     uint32_t pad;
 };
+
+// Per combine block: the smallest F, and the smallest PSL with its first scan
+// index, over the candidates the block combined.
+struct SelPart {
+    double f;
+    int32_t p;
+    uint32_t i;
+};
+constexpr uint32_t kCombMaxBlocks = 256;   // combine blocks per walk, at most
 
 constexpr uint32_t kNoItem = 0xFFFFFFFFu;  // padding work item (no work)
 

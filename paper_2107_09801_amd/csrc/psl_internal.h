@@ -93,6 +93,7 @@ struct BatchPlan {
     bool big_flips = false;           // some walk's Rand_flip exceeds the one-flip rebuild
     uint32_t n_items = 0;
     EvalShape shape;                  // evaluation launch shape
+    uint32_t comb_blocks = 1;         // combine blocks per walk (selection)
     EvalQueues *d_queues = nullptr;   // persistent evaluation: work queues
     BatchEntry *d_batch = nullptr;
     EvalItem *d_items = nullptr;
@@ -101,6 +102,7 @@ struct BatchPlan {
     double *d_fpart = nullptr, *d_f = nullptr, *d_s0 = nullptr;
     uint32_t *d_mpart = nullptr, *d_m0 = nullptr, *d_near = nullptr;
     int32_t *d_p = nullptr;
+    SelPart *d_red = nullptr;
 };
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -168,6 +170,7 @@ struct EvalLayout {
     std::vector<uint32_t> tiles, ks;
     std::vector<EvalItem> items;      // flat: padded XCD ranges; persistent: queues
     EvalQueues queues{};              // persistent: queue ranges
+    uint32_t comb_blocks = 1;         // combine blocks per walk (selection)
 };
 // Tuning key of a batch: (log2 of max L, log2 of the median N_lmt, log2 of
 // the walk count, uneven flag).

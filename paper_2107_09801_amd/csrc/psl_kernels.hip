@@ -268,16 +268,19 @@ __global__ __launch_bounds__(kFitThreads) void k_fitness(WalkDev *walks, const B
 // --------------------------------------------- neighbourhood evaluation
 
 // Per walk and step, from the pivot's C:
-//  * suffix sums S0[k] = sum_{k<=k'<L} T(|C_k'|) and M0[k] = max hi32(T(|C_k'|))
-//    over the same range (S0[L] = M0[L] = 0). A candidate j leaves every C_k
-//    with k > max(j, L-1-j) unchanged (both neighbours of the flipped element
-//    are out of bounds), so that part of its F (and PSL) is read from them;
+//  * chunk suffix sums S0c[x] = sum_{k' >= 1+32x, k' < L} T(|C_k'|) and
+//    M0c[x] = max hi32(T(|C_k'|)) over the same range, x = 0..nchunks
+//    (S0c[nchunks] = M0c[nchunks] = 0). A candidate j leaves every C_k with
+//    k > max(j, L-1-j) unchanged (both neighbours of the flipped element are
+//    out of bounds), so that part of its F (and PSL) is read from them; the
+//    evaluation only needs them at 32-shift chunk starts;
 //  * the near-peak shift list: with P the pivot's PSL, every neighbour has
 //    PSL >= P - 4 (one flip moves each C_k by at most 4), and a shift with
 //    |C_k| <= P - 9 reaches at most P - 5, so a neighbour's PSL is the maximum
 //    of |C'_k| over the shifts with |C_k| >= P - 8 alone. near[0] = count,
 //    near[1..] = those shifts (any order), while the count fits kNearCap.
-// One block per walk, fixed blocking, Neumaier sums.
+// One block of 16 wavefronts per walk; fixed blocking: a 32-lane tree per
+// chunk, then Neumaier sums over chunks.
 constexpr int kSufThreads = 1024;
 __global__ __launch_bounds__(kSufThreads) void k_suffix(const WalkDev *walks, const BatchEntry *batch,
                                                         Tables tabs)
@@ -286,67 +289,123 @@ __global__ __launch_bounds__(kSufThreads) void k_suffix(const WalkDev *walks, co
     const WalkDev &w = walks[be.slot];
     const int L = (int)w.L;
     const double *T = tabs.T[w.alpha];
-    const int nk = L - 1;
-    const int seg = (nk + kSufThreads - 1) / kSufThreads;
-    const int lo = 1 + (int)threadIdx.x * seg;
-    const int hi = min(L, lo + seg);
-    double s = 0.0, c = 0.0;
-    uint32_t m = 0;
-    int peak = 0;
-    for (int k = hi - 1; k >= lo; --k) {
-        const int32_t x = w.C[k];
-        const int a = x < 0 ? -x : x;
-        const double v = T[a];
-        nsum_add(s, c, v);
-        m = max(m, hi32(v));
-        peak = max(peak, a);
-    }
-    __shared__ double s_sum[kSufThreads], s_comp[kSufThreads];
-    __shared__ uint32_t s_max[kSufThreads];
-    __shared__ int s_peak[kSufThreads];
+    const int nchunks = (L - 1 + 31) / 32;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __shared__ int s_peak[kSufThreads / 64];
+    __shared__ double s_ts[kSufThreads], s_tc[kSufThreads];
+    __shared__ uint32_t s_tm[kSufThreads];
     __shared__ uint32_t s_cnt;
-    s_sum[threadIdx.x] = s;
-    s_comp[threadIdx.x] = c;
-    s_max[threadIdx.x] = m;
-    s_peak[threadIdx.x] = peak;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        // exclusive suffix scan over the segments, right to left
-        double rs = 0.0, rc = 0.0;
-        uint32_t rm = 0;
-        int pk = 0;
-        for (int i = kSufThreads - 1; i >= 0; --i) {
-            const double ts = s_sum[i], tc = s_comp[i];
-            const uint32_t tm = s_max[i];
-            s_sum[i] = rs;
-            s_comp[i] = rc;
-            s_max[i] = rm;
-            nsum_add(rs, rc, ts);
-            rc += tc;
-            rm = max(rm, tm);
-            pk = max(pk, s_peak[i]);
+
+    // 1. per-chunk sums and maxima; a wavefront covers two chunks per pass
+    int peak = 0;
+    for (int p = wave; 2 * p < nchunks; p += kSufThreads / 64) {
+        const int k = 1 + 64 * p + lane;
+        double v = 0.0;
+        int a = 0;
+        if (k < L) {
+            const int32_t x = w.C[k];
+            a = x < 0 ? -x : x;
+            v = T[a];
         }
-        be.S0[L] = 0.0;
-        be.M0[L] = 0;
-        s_peak[0] = pk;
-        s_cnt = 0;
+        uint32_t h = hi32(v);
+        peak = max(peak, a);
+        for (int o = 16; o > 0; o >>= 1) {
+            v += __shfl_xor(v, o);
+            h = max(h, (uint32_t)__shfl_xor((int)h, o));
+        }
+        const int c = 2 * p + (lane >> 5);
+        if ((lane & 31) == 0 && c < nchunks) {
+            be.S0[c] = v;
+            be.M0[c] = h;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) peak = max(peak, __shfl_xor(peak, o));
+    if (lane == 0) s_peak[wave] = peak;
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
+
+    // 2. suffix scan over the chunk sums: each thread a contiguous segment
+    //    (right to left, Neumaier), then an exclusive suffix scan of the
+    //    segment totals (one wave, 16 totals per lane), then the offsets
+    const int seg = (nchunks + kSufThreads - 1) / kSufThreads;
+    const int lo = (int)threadIdx.x * seg, hi = min(nchunks, lo + seg);
+    double ts = 0.0, tc = 0.0;
+    uint32_t tm = 0;
+    for (int c = hi - 1; c >= lo; --c) {
+        nsum_add(ts, tc, be.S0[c]);
+        tm = max(tm, be.M0[c]);
+    }
+    s_ts[threadIdx.x] = ts;
+    s_tc[threadIdx.x] = tc;
+    s_tm[threadIdx.x] = tm;
+    __syncthreads();
+    if (wave == 0) {
+        // lane l owns segment totals 16l .. 16l+15
+        double ls = 0.0, lc = 0.0;
+        uint32_t lm = 0;
+        for (int x = 15; x >= 0; --x) {
+            const int t = 16 * lane + x;
+            nsum_add(ls, lc, s_ts[t]);
+            lc += s_tc[t];
+            lm = max(lm, s_tm[t]);
+        }
+        // exclusive suffix over lanes (lanes above l), in lane order
+        double es = 0.0, ec = 0.0;
+        uint32_t em = 0;
+        for (int o = 63; o > 0; --o) {
+            const double os = __shfl(ls, o), oc = __shfl(lc, o);
+            const uint32_t om = (uint32_t)__shfl((int)lm, o);
+            if (o > lane) {
+                nsum_add(es, ec, os);
+                ec += oc;
+                em = max(em, om);
+            }
+        }
+        for (int x = 15; x >= 0; --x) {
+            const int t = 16 * lane + x;
+            const double ns = s_ts[t], nc = s_tc[t];
+            const uint32_t nm = s_tm[t];
+            s_ts[t] = es;
+            s_tc[t] = ec;
+            s_tm[t] = em;
+            nsum_add(es, ec, ns);
+            ec += nc;
+            em = max(em, nm);
+        }
     }
     __syncthreads();
-    const int cut = s_peak[0] - 8;
-    s = s_sum[threadIdx.x];
-    c = s_comp[threadIdx.x];
-    m = s_max[threadIdx.x];
-    for (int k = hi - 1; k >= lo; --k) {
-        const int32_t x = w.C[k];
-        const int a = x < 0 ? -x : x;
-        const double v = T[a];
-        nsum_add(s, c, v);
-        m = max(m, hi32(v));
-        be.S0[k] = s + c;
-        be.M0[k] = m;
-        if (a >= cut) {
-            const uint32_t q = atomicAdd(&s_cnt, 1u);
-            if (q < (uint32_t)kNearCap) be.near[1 + q] = (uint32_t)k;
+    ts = s_ts[threadIdx.x];
+    tc = s_tc[threadIdx.x];
+    tm = s_tm[threadIdx.x];
+    for (int c = hi - 1; c >= lo; --c) {
+        nsum_add(ts, tc, be.S0[c]);
+        tm = max(tm, be.M0[c]);
+        be.S0[c] = ts + tc;
+        be.M0[c] = tm;
+    }
+    if (threadIdx.x == 0) {
+        be.S0[nchunks] = 0.0;
+        be.M0[nchunks] = 0;
+    }
+
+    // 3. the near-peak list, one ballot per wavefront pass
+    int pk = 0;
+    for (int x = 0; x < kSufThreads / 64; ++x) pk = max(pk, s_peak[x]);
+    const int cut = pk - 8;
+    for (int k0 = 1 + 64 * wave; k0 < L; k0 += kSufThreads) {
+        const int k = k0 + lane;
+        bool take = false;
+        if (k < L) {
+            const int32_t x = w.C[k];
+            take = (x < 0 ? -x : x) >= cut;
+        }
+        const uint64_t bal = __ballot(take);
+        if (bal) {
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(&s_cnt, (uint32_t)__popcll(bal));
+            base = (uint32_t)__shfl((int)base, 0);
+            const uint32_t q = base + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+            if (take && q < (uint32_t)kNearCap) be.near[1 + q] = (uint32_t)k;
         }
     }
     __syncthreads();
@@ -517,11 +576,15 @@ __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const 
         }
         nsum_add(sum, comp, acc);
     }
-    // shifts where no lane of the wave has a neighbour in bounds
+    // shifts where no lane of the wave has a neighbour in bounds (kn is a
+    // chunk start; k_hi a chunk start or L, the chunk arrays' last entry)
     const int kn = max(k_lo, k_wend);
     if (kn < k_hi) {
-        nsum_add(sum, comp, be.S0[kn] - be.S0[k_hi]);
-        if (kMax) mx = max(mx, be.M0[kn]);
+        const int nchunks = (L - 1 + 31) / 32;
+        const int xa = (kn - 1) >> 5;
+        const int xb = k_hi >= L ? nchunks : (k_hi - 1) >> 5;
+        nsum_add(sum, comp, be.S0[xa] - be.S0[xb]);
+        if (kMax) mx = max(mx, be.M0[xa]);
     }
 }
 
@@ -593,7 +656,7 @@ __device__ __forceinline__ void eval_item(EvalLds &sh, const WalkDev *__restrict
                 }
                 peak = max(peak, c < 0 ? -c : c);
             }
-            mx = hi32(T[peak]);
+            mx = (uint32_t)peak;          // the PSL itself (< L, far below 0x3FF00000)
         }
     }
     if (active) {
@@ -662,39 +725,89 @@ struct ChoiceDev {
 };
 
 constexpr int kSelThreads = 1024;
+constexpr int kCombThreads = 256;
 
-// Combines the k-split partials into F and PSL per candidate, then the scan
-// of Algorithm 1: the move is the first candidate in scan order within
-// F_min*(1+tau); the best-PSL neighbour is the first with the minimum PSL.
-// pure != 0: write the choice to out[b] and leave the walk unchanged.
-// Otherwise record the choice in the walk and, on a strict PSL improvement,
-// update psl_best and solution_best = pivot with j_psl flipped.
-__global__ __launch_bounds__(kSelThreads) void k_select(WalkDev *walks, const BatchEntry *batch,
-                                                        Tables tabs, int pure, ChoiceDev *out)
+__device__ __forceinline__ void sel_merge(double &f, int32_t &p, uint32_t &i, double of, int32_t op,
+                                          uint32_t oi)
 {
-    const BatchEntry be = batch[blockIdx.x];
-    WalkDev &w = walks[be.slot];
+    f = of < f ? of : f;
+    if (op < p || (op == p && oi < i)) {
+        p = op;
+        i = oi;
+    }
+}
+
+// F and PSL per candidate from the k-split partials (splits added in order),
+// spread over gridDim.x blocks per walk (blockIdx.y = batch position); each
+// block leaves its smallest F and its first smallest PSL in be.red.
+__global__ __launch_bounds__(kCombThreads) void k_combine(const WalkDev *walks, const BatchEntry *batch,
+                                                          Tables tabs)
+{
+    const BatchEntry be = batch[blockIdx.y];
+    const WalkDev &w = walks[be.slot];
     const uint32_t n = be.fixed ? be.n_lmt : w.n_lmt;
-    const uint32_t start = be.fixed ? be.start : step_start(w);
-    const uint32_t L = w.L;
     const uint32_t ks = be.ksplit;
     const double *T = tabs.T[w.alpha];
 
     double fmin = INFINITY;
     int32_t pmin = INT_MAX;
     uint32_t ipmin = UINT_MAX;
-    for (uint32_t i = threadIdx.x; i < n; i += kSelThreads) {
+    for (uint32_t i = blockIdx.x * kCombThreads + threadIdx.x; i < n; i += gridDim.x * kCombThreads) {
         double f = 0.0;
         uint32_t m = 0;
-        for (uint32_t s = 0; s < ks; ++s) {
-            f += be.Fpart[(size_t)s * n + i];
-            m = max(m, be.Mpart[(size_t)s * n + i]);
+        for (uint32_t x = 0; x < ks; ++x) {
+            f += be.Fpart[(size_t)x * n + i];
+            m = max(m, be.Mpart[(size_t)x * n + i]);
         }
-        const int32_t p = table_inverse(T, tabs.n, m);
+        // the near-peak path stores the PSL itself; the dense path the high
+        // word of T(PSL), which is at least hi32(T(1)) = 0x3FF00000 because
+        // |C'_{L-1}| = 1 for every sequence
+        const int32_t p = m < 0x3FF00000u ? (int32_t)m : table_inverse(T, tabs.n, m);
         be.F[i] = f;
         be.P[i] = p;
         fmin = f < fmin ? f : fmin;
         if (p < pmin) { pmin = p; ipmin = i; }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const double of = __shfl_xor(fmin, o);
+        const int32_t op = __shfl_xor(pmin, o);
+        const uint32_t oi = (uint32_t)__shfl_xor((int)ipmin, o);
+        sel_merge(fmin, pmin, ipmin, of, op, oi);
+    }
+    __shared__ SelPart s_r[kCombThreads / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) s_r[wave] = SelPart{fmin, pmin, ipmin};
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        SelPart r = s_r[0];
+        for (int x = 1; x < kCombThreads / 64; ++x) sel_merge(r.f, r.p, r.i, s_r[x].f, s_r[x].p, s_r[x].i);
+        be.red[blockIdx.x] = r;
+    }
+}
+
+// The scan of Algorithm 1 over the combined F and PSL: the move is the first
+// candidate in scan order within F_min*(1+tau); the best-PSL neighbour is the
+// first with the minimum PSL.
+// pure != 0: write the choice to out[b] and leave the walk unchanged.
+// Otherwise record the choice in the walk and, on a strict PSL improvement,
+// update psl_best and solution_best = pivot with j_psl flipped.
+__global__ __launch_bounds__(kSelThreads) void k_select(WalkDev *walks, const BatchEntry *batch,
+                                                        uint32_t comb_blocks, int pure, ChoiceDev *out)
+{
+    const BatchEntry be = batch[blockIdx.x];
+    WalkDev &w = walks[be.slot];
+    const uint32_t n = be.fixed ? be.n_lmt : w.n_lmt;
+    const uint32_t start = be.fixed ? be.start : step_start(w);
+    const uint32_t L = w.L;
+
+    double fmin = INFINITY;
+    int32_t pmin = INT_MAX;
+    uint32_t ipmin = UINT_MAX;
+    if (threadIdx.x < comb_blocks) {
+        const SelPart r = be.red[threadIdx.x];
+        fmin = r.f;
+        pmin = r.p;
+        ipmin = r.i;
     }
     __shared__ double s_f[kSelThreads];
     __shared__ int32_t s_p[kSelThreads];
@@ -720,7 +833,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select(WalkDev *walks, const Ba
     const double thr = Fmin * (1.0 + kTau);
     __syncthreads();
 
-    // first scan index inside the band (each thread re-reads its own writes)
+    // first scan index inside the band
     uint32_t ifirst = UINT_MAX;
     for (uint32_t i = threadIdx.x; i < n; i += kSelThreads) {
         if (be.F[i] <= thr) { ifirst = i; break; }
@@ -738,18 +851,10 @@ __global__ __launch_bounds__(kSelThreads) void k_select(WalkDev *walks, const Ba
     const uint32_t kb = (uint32_t)(((uint64_t)start + 1u + ib) % L);
     const uint32_t jp = (uint32_t)(((uint64_t)start + 1u + iPmin) % L);
 
-    // thread ib % kSelThreads wrote F[ib] and P[ib]; it hands them over
-    __shared__ double s_Fb;
-    __shared__ int32_t s_Pb;
     __shared__ int s_improve;
-    if (threadIdx.x == ib % kSelThreads) {
-        s_Fb = be.F[ib];
-        s_Pb = be.P[ib];
-    }
-    __syncthreads();
     if (threadIdx.x == 0) {
-        const double Fb = s_Fb;
-        const int32_t Pb = s_Pb;
+        const double Fb = be.F[ib];
+        const int32_t Pb = be.P[ib];
         if (pure) {
             ChoiceDev c;
             c.i_best = ib; c.j_best = kb; c.F_best = Fb; c.F_min = Fmin;
@@ -968,10 +1073,14 @@ hipError_t launch_suffix(const WalkDev *walks, const BatchEntry *batch, uint32_t
     return hipGetLastError();
 }
 
-hipError_t launch_select(WalkDev *walks, const BatchEntry *batch, uint32_t nb, const Tables &tabs,
-                         int pure, void *out, hipStream_t s)
+hipError_t launch_select(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t comb_blocks,
+                         const Tables &tabs, int pure, void *out, hipStream_t s)
 {
-    k_select<<<nb, kSelThreads, 0, s>>>(walks, batch, tabs, pure, (ChoiceDev *)out);
+    if (comb_blocks < 1 || comb_blocks > kCombMaxBlocks) return hipErrorInvalidValue;
+    k_combine<<<dim3(comb_blocks, nb), kCombThreads, 0, s>>>(walks, batch, tabs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_select<<<nb, kSelThreads, 0, s>>>(walks, batch, comb_blocks, pure, (ChoiceDev *)out);
     return hipGetLastError();
 }
 

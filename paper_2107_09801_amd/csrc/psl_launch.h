@@ -19,8 +19,8 @@ hipError_t launch_eval(const WalkDev *walks, const BatchEntry *batch, const Eval
                        EvalQueues *queues, hipStream_t s);
 hipError_t launch_suffix(const WalkDev *walks, const BatchEntry *batch, uint32_t nb, const Tables &tabs,
                          hipStream_t s);
-hipError_t launch_select(WalkDev *walks, const BatchEntry *batch, uint32_t nb, const Tables &tabs,
-                         int pure, void *out, hipStream_t s);
+hipError_t launch_select(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t comb_blocks,
+                         const Tables &tabs, int pure, void *out, hipStream_t s);
 size_t choice_dev_size();
 void choice_dev_unpack(const void *p, uint32_t *i_best, uint32_t *j_best, double *F_best,
                        double *F_min, uint32_t *j_psl, int32_t *psl_min, int32_t *psl_k);

@@ -88,6 +88,7 @@ void plan_free(psl_ctx *ctx, BatchPlan &pl)
     dev_free(ctx, pl.d_p, false);
     dev_free(ctx, pl.d_s0, false);
     dev_free(ctx, pl.d_m0, false);
+    dev_free(ctx, pl.d_red, false);
     dev_free(ctx, pl.d_near, false);
     dev_free(ctx, pl.d_queues, false);
     pl = BatchPlan();
@@ -261,6 +262,15 @@ void eval_layout(const uint32_t *Ls, const uint32_t *nl, uint32_t n, const EvalS
         std::stable_sort(sg.begin(), sg.end(), [](const C &a, const C &b) { return a.cost > b.cost; });
         cmax = std::max(cmax, sg.size());
     }
+    // selection: about 8192 partials per combine block, at most one block
+    // per 256 candidates
+    uint64_t work = 0, nmax = 0;
+    for (uint32_t b = 0; b < n; ++b) {
+        work = std::max<uint64_t>(work, (uint64_t)out.ks[b] * nl[b]);
+        nmax = std::max<uint64_t>(nmax, nl[b]);
+    }
+    out.comb_blocks = (uint32_t)std::max<uint64_t>(
+        1, std::min<uint64_t>({(work + 8191) / 8192, (nmax + 255) / 256, (uint64_t)kCombMaxBlocks}));
     out.items.reserve(shape.persistent ? all.size() : 8 * cmax);
     for (int q = 0; q < 8; ++q) {
         auto &sg = seg[q];
@@ -297,11 +307,12 @@ psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t 
     const std::vector<uint32_t> &tiles = lay.tiles, &ks = lay.ks;
     std::vector<EvalItem> &items = lay.items;
     pl.shape = lay.shape;
+    pl.comb_blocks = lay.comb_blocks;
     size_t n_part = 0, n_cand = 0, n_suf = 0;
     for (uint32_t b = 0; b < n; ++b) {
         n_part += (size_t)ks[b] * n_l[b];
         n_cand += n_l[b];
-        n_suf += Ls[b] + 1;
+        n_suf += suffix_len(Ls[b]);
     }
     const uint64_t n_items = items.size();
     if (n_items >= (1ull << 31)) return fail(ctx, PSL_E_INVAL, "batch too large (%llu work items)",
@@ -322,6 +333,8 @@ psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t 
     pl.d_m0 = (uint32_t *)p;
     if ((st = dev_alloc(ctx, &p, sizeof(uint32_t) * (kNearCap + 1) * n, false))) return st;
     pl.d_near = (uint32_t *)p;
+    if ((st = dev_alloc(ctx, &p, sizeof(SelPart) * pl.comb_blocks * n, false))) return st;
+    pl.d_red = (SelPart *)p;
     std::vector<BatchEntry> be(n);
     size_t op = 0, oc = 0, os = 0;
     for (uint32_t b = 0; b < n; ++b) {
@@ -334,7 +347,8 @@ psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t 
         e.S0 = pl.d_s0 + os;
         e.M0 = pl.d_m0 + os;
         e.near = pl.d_near + (size_t)(kNearCap + 1) * b;
-        os += ctx->walks[ids[b]].L + 1;
+        e.red = pl.d_red + (size_t)pl.comb_blocks * b;
+        os += suffix_len(ctx->walks[ids[b]].L);
         e.slot = ids[b];
         e.ksplit = ks[b];
         e.tiles = tiles[b];
@@ -421,7 +435,7 @@ psl_status launch_step(psl_ctx *ctx, const BatchPlan &pl, const Tables &tabs, ui
     HIP_TRY(ctx, launch_eval(ctx->d_walks, pl.d_batch, pl.d_items, pl.n_items, tabs, pl.shape, pl.d_queues,
                              ctx->stream));
     if (timed && (st = timing_mark(ctx))) return st;
-    HIP_TRY(ctx, launch_select(ctx->d_walks, pl.d_batch, n, tabs, 0, nullptr, ctx->stream));
+    HIP_TRY(ctx, launch_select(ctx->d_walks, pl.d_batch, n, pl.comb_blocks, tabs, 0, nullptr, ctx->stream));
     HIP_TRY(ctx, launch_apply(ctx->d_walks, pl.d_batch, n, pl.max_L, -1, ctx->stream));
     HIP_TRY(ctx, launch_bookkeep(ctx->d_walks, pl.d_batch, n, ctx->stream));
     HIP_TRY(ctx, launch_switch_corr(ctx->d_walks, pl.d_batch, n, pl.max_L, ctx->stream));
@@ -681,7 +695,8 @@ psl_status psl_eval_neighbourhood(psl_ctx *ctx, uint32_t walk, uint32_t start, u
     HIP_TRY(ctx, launch_suffix(ctx->d_walks, ctx->pure.d_batch, 1, tabs, ctx->stream));
     HIP_TRY(ctx, launch_eval(ctx->d_walks, ctx->pure.d_batch, ctx->pure.d_items, ctx->pure.n_items,
                              tabs, ctx->pure.shape, ctx->pure.d_queues, ctx->stream));
-    HIP_TRY(ctx, launch_select(ctx->d_walks, ctx->pure.d_batch, 1, tabs, 1, ctx->d_choice, ctx->stream));
+    HIP_TRY(ctx, launch_select(ctx->d_walks, ctx->pure.d_batch, 1, ctx->pure.comb_blocks, tabs, 1, ctx->d_choice,
+                               ctx->stream));
     if (F_dev)
         HIP_TRY(ctx, hipMemcpyAsync(F_dev, ctx->pure.d_f, sizeof(double) * n_lmt,
                                     hipMemcpyDeviceToDevice, ctx->stream));

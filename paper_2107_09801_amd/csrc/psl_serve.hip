@@ -40,8 +40,9 @@ size_t scratch_bound(uint32_t L, uint32_t n_lmt)
     const uint64_t tiles = (n_lmt + 64 * kEvalWavesSmall - 1) / (64 * kEvalWavesSmall);
     const uint64_t ks_max = std::max<uint64_t>(1, ((L - 1 + 31) / 32) / (kTileK / 32));
     const uint64_t ks = std::min<uint64_t>(ks_max, (4096 + tiles - 1) / tiles);
-    return (size_t)(12ull * ks * n_lmt + 12ull * n_lmt + 12ull * (L + 1) +
-                    4ull * (kNearCap + 1) + sizeof(BatchEntry) + sizeof(EvalItem) * ks * tiles);
+    return (size_t)(12ull * ks * n_lmt + 12ull * n_lmt + 12ull * suffix_len(L) +
+                    4ull * (kNearCap + 1) + sizeof(SelPart) * kCombMaxBlocks + sizeof(BatchEntry) +
+                    sizeof(EvalItem) * ks * tiles);
 }
 
 size_t job_footprint(const psl_walk_cfg &c)
@@ -97,6 +98,8 @@ struct Server {
     DevBuf<EvalItem> d_items;
     DevBuf<double> d_fpart, d_f, d_s0;
     DevBuf<uint32_t> d_mpart, d_m0, d_near, d_want;
+    DevBuf<SelPart> d_red;
+    uint32_t comb_blocks = 1;
     DevBuf<int32_t> d_p;
     uint32_t n_items = 0, max_L = 0;
     EvalShape shape;
@@ -332,10 +335,11 @@ psl_status Server::upload_layout(char *&sp, char *stage_end)
     for (uint32_t b = 0; b < n; ++b) {
         n_part += (size_t)ks[b] * nls[b];
         n_cand += nls[b];
-        n_suf += Ls[b] + 1;
+        n_suf += suffix_len(Ls[b]);
     }
     const size_t items = lay.items.size();
     shape = lay.shape;
+    comb_blocks = lay.comb_blocks;
     const size_t need = sizeof(BatchEntry) * n + sizeof(EvalItem) * items + sizeof(EvalQueues) + 256;
     if ((size_t)(stage_end - sp) < need) return fail(ctx, PSL_E_NOMEM, "serving staging too small");
     psl_status st;
@@ -343,7 +347,8 @@ psl_status Server::upload_layout(char *&sp, char *stage_end)
         (st = grow(ctx, d_fpart, n_part)) || (st = grow(ctx, d_mpart, n_part)) ||
         (st = grow(ctx, d_f, n_cand)) || (st = grow(ctx, d_p, n_cand)) ||
         (st = grow(ctx, d_s0, n_suf)) || (st = grow(ctx, d_m0, n_suf)) ||
-        (st = grow(ctx, d_near, (size_t)(kNearCap + 1) * n)) || (st = grow(ctx, d_queues, 1)))
+        (st = grow(ctx, d_near, (size_t)(kNearCap + 1) * n)) || (st = grow(ctx, d_queues, 1)) ||
+        (st = grow(ctx, d_red, (size_t)comb_blocks * n)))
         return st;
     BatchEntry *be = (BatchEntry *)sp;
     sp += sizeof(BatchEntry) * n;
@@ -364,6 +369,7 @@ psl_status Server::upload_layout(char *&sp, char *stage_end)
         e.S0 = d_s0.p + os;
         e.M0 = d_m0.p + os;
         e.near = d_near.p + (size_t)(kNearCap + 1) * b;
+        e.red = d_red.p + (size_t)comb_blocks * b;
         e.slot = j.slot;
         e.ksplit = ks[b];
         e.tiles = tiles[b];
@@ -371,7 +377,7 @@ psl_status Server::upload_layout(char *&sp, char *stage_end)
         e.near_lim = near_limit_for(ctx, j.cfg.L);
         op += (size_t)ks[b] * nl;
         oc += nl;
-        os += j.cfg.L + 1;
+        os += suffix_len(j.cfg.L);
     }
     memcpy(it, lay.items.data(), sizeof(EvalItem) * items);
     HIP_TRY(ctx, hipMemcpyAsync(d_batch.p, be, sizeof(BatchEntry) * n, hipMemcpyHostToDevice, ctx->stream));
@@ -437,7 +443,7 @@ psl_status Server::iterate()
     const Tables tabs = tables_of(ctx);
     HIP_TRY(ctx, launch_suffix(ctx->d_walks, d_batch.p, n, tabs, ctx->stream));
     HIP_TRY(ctx, launch_eval(ctx->d_walks, d_batch.p, d_items.p, n_items, tabs, shape, d_queues.p, ctx->stream));
-    HIP_TRY(ctx, launch_select(ctx->d_walks, d_batch.p, n, tabs, 0, nullptr, ctx->stream));
+    HIP_TRY(ctx, launch_select(ctx->d_walks, d_batch.p, n, comb_blocks, tabs, 0, nullptr, ctx->stream));
     HIP_TRY(ctx, launch_apply(ctx->d_walks, d_batch.p, n, max_L, -1, ctx->stream));
     HIP_TRY(ctx, launch_bookkeep(ctx->d_walks, d_batch.p, n, ctx->stream));
     HIP_TRY(ctx, launch_switch_corr(ctx->d_walks, d_batch.p, n, max_L, ctx->stream));
@@ -571,6 +577,7 @@ void serve_shutdown(psl_ctx *ctx)
     release(ctx, s->d_mpart);
     release(ctx, s->d_m0);
     release(ctx, s->d_near);
+    release(ctx, s->d_red);
     release(ctx, s->d_want);
     release(ctx, s->d_p);
     release(ctx, s->d_queues);

@@ -18,6 +18,7 @@ per launch sequence.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -35,6 +36,40 @@ OPS_PER_UPDATE = 4
 # Paper, Table 4 (A100 SXM4, N_lmt = 6912, one walk, alpha 4/10): context only.
 PAPER_A100_NSE = {16383: 4678451, 32767: 2577101, 65535: 1258873, 131071: 638043,
                   262143: 326148, 524287: 167861, 1048575: 85062}
+
+
+# Sources that define the evaluation kernel: a counter record is valid only for
+# the exact text it was taken from.
+KERNEL_SOURCES = ("paper_2107_09801_amd/csrc/psl_kernels.hip", "paper_2107_09801_amd/csrc/psl_device.h")
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(tag: str):
+    """HBM bytes per launch of the evaluation kernel for workload `tag`, from the
+    `traffic-record:` line of a committed rocprofv3 counter summary (FETCH_SIZE
+    and WRITE_SIZE, each scaled by what the counter reads for a copy of known
+    size). None when there is no record or the kernel's sources changed since."""
+    pdir = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(pdir):
+        return None
+    digest = kernel_source_digest()
+    for name in sorted(os.listdir(pdir)):
+        with open(os.path.join(pdir, name), encoding="utf-8", errors="replace") as f:
+            for line in f:
+                line = line.strip().strip("`")
+                if not line.startswith("traffic-record:"):
+                    continue
+                kv = dict(t.split("=", 1) for t in line.split()[1:] if "=" in t)
+                if kv.get("workload") == tag and kv.get("source_sha256") == digest:
+                    return int(kv["fetch_bytes_per_launch"]) + int(kv["write_bytes_per_launch"])
+    return None
 
 
 def parse():
@@ -321,7 +356,9 @@ def main():
                         "updates_per_s": updates_per_step / eval_avg_s,
                         "rest_of_step_avg_ms": tm["rest_ms"] / max(1, tm["steps"])},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                     "unit": "Tlane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": None},
+                     "unit": "Tlane-op/s", "frac": achieved / PEAK_LANE_OPS,
+                     "traffic": measured_traffic(f"{wl}_L{'-'.join(str(g[0]) for g in groups)}_w{nw}"),
+                     "traffic_unit": "B/launch"},
         "walk0_after": {"t": st["t"], "psl_best": st["psl_best"], "alpha": st["alpha"]},
     }
     if L in PAPER_A100_NSE and len(groups) == 1:

@@ -94,6 +94,7 @@ struct BatchPlan {
     uint32_t n_items = 0;
     EvalShape shape;                  // evaluation launch shape
     uint32_t comb_blocks = 1;         // combine blocks per walk (selection)
+    uint32_t comb_group = 1;          // lanes per candidate in the combine
     EvalQueues *d_queues = nullptr;   // persistent evaluation: work queues
     BatchEntry *d_batch = nullptr;
     EvalItem *d_items = nullptr;
@@ -171,6 +172,7 @@ struct EvalLayout {
     std::vector<EvalItem> items;      // flat: padded XCD ranges; persistent: queues
     EvalQueues queues{};              // persistent: queue ranges
     uint32_t comb_blocks = 1;         // combine blocks per walk (selection)
+    uint32_t comb_group = 1;          // lanes per candidate in the combine
 };
 // Tuning key of a batch: (log2 of max L, log2 of the median N_lmt, log2 of
 // the walk count, uneven flag).

@@ -214,15 +214,12 @@ __global__ void k_switch_corr(WalkDev *walks, const BatchEntry *batch)
 // F of the pivot (Eq. (5)) and its PSL (Eq. (3)) from C, one block per walk,
 // fixed blocking so a given C always gives the same F bits.
 // mode 0: initial (value_local, F_pivot, psl_pivot, psl_best);
-// mode 1: after a switch, pending walks only (value_local, F_pivot,
-//         psl_pivot, unimproved = 0, pending = 0);
-// mode 2: after a forced flip (F_pivot, psl_pivot).
+// mode 2: after a forced flip or a restore (F_pivot, psl_pivot).
 constexpr int kFitThreads = 256;
 __global__ __launch_bounds__(kFitThreads) void k_fitness(WalkDev *walks, const BatchEntry *batch,
                                                          Tables tabs, int mode)
 {
     WalkDev &w = walks[batch[blockIdx.x].slot];
-    if (mode == 1 && !w.pending) return;
     const double *T = tabs.T[w.alpha];
     double sum = 0.0, comp = 0.0;
     int32_t peak = 0;
@@ -257,10 +254,6 @@ __global__ __launch_bounds__(kFitThreads) void k_fitness(WalkDev *walks, const B
         if (mode == 0) {
             w.value_local = F;
             w.psl_best = p;
-        } else if (mode == 1) {
-            w.value_local = F;
-            w.unimproved = 0;
-            w.pending = 0;
         }
     }
 }
@@ -268,37 +261,40 @@ __global__ __launch_bounds__(kFitThreads) void k_fitness(WalkDev *walks, const B
 // --------------------------------------------- neighbourhood evaluation
 
 // Per walk and step, from the pivot's C:
-//  * chunk suffix sums S0c[x] = sum_{k' >= 1+32x, k' < L} T(|C_k'|) and
-//    M0c[x] = max hi32(T(|C_k'|)) over the same range, x = 0..nchunks
-//    (S0c[nchunks] = M0c[nchunks] = 0). A candidate j leaves every C_k with
-//    k > max(j, L-1-j) unchanged (both neighbours of the flipped element are
-//    out of bounds), so that part of its F (and PSL) is read from them; the
-//    evaluation only needs them at 32-shift chunk starts;
+//  * chunk suffix sums S0[x] = sum_{1+32x <= k' < L} T(|C_k'|) and
+//    M0[x] = max |C_k'| over the same range, x = 0..nchunks (the last entry
+//    0). A candidate j leaves every C_k with k > max(j, L-1-j) unchanged
+//    (both neighbours of the flipped element are out of bounds), so that
+//    part of its F (and PSL) is read from them; the evaluation only needs
+//    them at 32-shift chunk starts;
 //  * the near-peak shift list: with P the pivot's PSL, every neighbour has
 //    PSL >= P - 4 (one flip moves each C_k by at most 4), and a shift with
 //    |C_k| <= P - 9 reaches at most P - 5, so a neighbour's PSL is the maximum
 //    of |C'_k| over the shifts with |C_k| >= P - 8 alone. near[0] = count,
 //    near[1..] = those shifts (any order), while the count fits kNearCap.
-// One block of 16 wavefronts per walk; fixed blocking: a 32-lane tree per
-// chunk, then Neumaier sums over chunks.
-constexpr int kSufThreads = 1024;
-__global__ __launch_bounds__(kSufThreads) void k_suffix(const WalkDev *walks, const BatchEntry *batch,
-                                                        Tables tabs)
+// Two kernels: k_chunks (several blocks per walk) writes per-chunk sums (a
+// fixed 32-lane tree) and maxima and appends to the near list; k_scan (one
+// block per walk) turns the chunk values into suffix values in a fixed order.
+// The same pair, in mode 1, is the fitness of a walk after a phase switch:
+// S0[0] = F and M0[0] = PSL of the new pivot under the new alpha.
+constexpr int kChunkThreads = 256;
+constexpr uint32_t kMaxGridY = 65535;      // walks per launch of the 2-D grids
+__global__ __launch_bounds__(kChunkThreads) void k_chunks(const WalkDev *walks, const BatchEntry *batch,
+                                                          Tables tabs, int mode)
 {
-    const BatchEntry be = batch[blockIdx.x];
+    const BatchEntry be = batch[blockIdx.y];
     const WalkDev &w = walks[be.slot];
+    if (mode == 1 && !w.pending) return;
     const int L = (int)w.L;
     const double *T = tabs.T[w.alpha];
     const int nchunks = (L - 1 + 31) / 32;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    __shared__ int s_peak[kSufThreads / 64];
-    __shared__ double s_ts[kSufThreads], s_tc[kSufThreads];
-    __shared__ uint32_t s_tm[kSufThreads];
-    __shared__ uint32_t s_cnt;
-
-    // 1. per-chunk sums and maxima; a wavefront covers two chunks per pass
-    int peak = 0;
-    for (int p = wave; 2 * p < nchunks; p += kSufThreads / 64) {
+    const int lane = threadIdx.x & 63;
+    const int gw = (int)blockIdx.x * (kChunkThreads / 64) + ((int)threadIdx.x >> 6);
+    const int nwaves = (int)gridDim.x * (kChunkThreads / 64);
+    // the near-peak cut (the pivot's PSL is kept current by every step)
+    const int cut = mode == 0 ? w.psl_pivot - 8 : INT_MAX;
+    // a wavefront covers two chunks per pass
+    for (int p = gw; 2 * p < nchunks; p += nwaves) {
         const int k = 1 + 64 * p + lane;
         double v = 0.0;
         int a = 0;
@@ -307,27 +303,46 @@ __global__ __launch_bounds__(kSufThreads) void k_suffix(const WalkDev *walks, co
             a = x < 0 ? -x : x;
             v = T[a];
         }
-        uint32_t h = hi32(v);
-        peak = max(peak, a);
+        const bool take = k < L && a >= cut;
+        int m = a;
         for (int o = 16; o > 0; o >>= 1) {
             v += __shfl_xor(v, o);
-            h = max(h, (uint32_t)__shfl_xor((int)h, o));
+            m = max(m, __shfl_xor(m, o));
         }
         const int c = 2 * p + (lane >> 5);
         if ((lane & 31) == 0 && c < nchunks) {
             be.S0[c] = v;
-            be.M0[c] = h;
+            be.M0[c] = (uint32_t)m;
+        }
+        if (mode == 0) {
+            const uint64_t bal = __ballot(take);
+            if (bal) {
+                uint32_t base = 0;
+                if (lane == 0) base = atomicAdd(&be.near[0], (uint32_t)__popcll(bal));
+                base = (uint32_t)__shfl((int)base, 0);
+                const uint32_t q = base + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+                if (take && q < (uint32_t)kNearCap) be.near[1 + q] = (uint32_t)k;
+            }
         }
     }
-    for (int o = 32; o > 0; o >>= 1) peak = max(peak, __shfl_xor(peak, o));
-    if (lane == 0) s_peak[wave] = peak;
-    if (threadIdx.x == 0) s_cnt = 0;
-    __syncthreads();
+}
 
-    // 2. suffix scan over the chunk sums: each thread a contiguous segment
-    //    (right to left, Neumaier), then an exclusive suffix scan of the
-    //    segment totals (one wave, 16 totals per lane), then the offsets
-    const int seg = (nchunks + kSufThreads - 1) / kSufThreads;
+constexpr int kScanThreads = 1024;
+__global__ __launch_bounds__(kScanThreads) void k_scan(WalkDev *walks, const BatchEntry *batch, int mode)
+{
+    const BatchEntry be = batch[blockIdx.x];
+    WalkDev &w = walks[be.slot];
+    if (mode == 1 && !w.pending) return;
+    const int L = (int)w.L;
+    const int nchunks = (L - 1 + 31) / 32;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __shared__ double s_ts[kScanThreads], s_tc[kScanThreads];
+    __shared__ uint32_t s_tm[kScanThreads];
+
+    // each thread a contiguous segment (right to left, Neumaier), then an
+    // exclusive suffix scan of the segment totals (one wave, 16 per lane),
+    // then the offsets
+    const int seg = (nchunks + kScanThreads - 1) / kScanThreads;
     const int lo = (int)threadIdx.x * seg, hi = min(nchunks, lo + seg);
     double ts = 0.0, tc = 0.0;
     uint32_t tm = 0;
@@ -386,30 +401,16 @@ __global__ __launch_bounds__(kSufThreads) void k_suffix(const WalkDev *walks, co
     if (threadIdx.x == 0) {
         be.S0[nchunks] = 0.0;
         be.M0[nchunks] = 0;
-    }
-
-    // 3. the near-peak list, one ballot per wavefront pass
-    int pk = 0;
-    for (int x = 0; x < kSufThreads / 64; ++x) pk = max(pk, s_peak[x]);
-    const int cut = pk - 8;
-    for (int k0 = 1 + 64 * wave; k0 < L; k0 += kSufThreads) {
-        const int k = k0 + lane;
-        bool take = false;
-        if (k < L) {
-            const int32_t x = w.C[k];
-            take = (x < 0 ? -x : x) >= cut;
-        }
-        const uint64_t bal = __ballot(take);
-        if (bal) {
-            uint32_t base = 0;
-            if (lane == 0) base = atomicAdd(&s_cnt, (uint32_t)__popcll(bal));
-            base = (uint32_t)__shfl((int)base, 0);
-            const uint32_t q = base + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
-            if (take && q < (uint32_t)kNearCap) be.near[1 + q] = (uint32_t)k;
+        if (mode == 1) {
+            // thread 0's segment starts at chunk 0: the totals over k >= 1
+            const double F = ts + tc;
+            w.F_pivot = F;
+            w.psl_pivot = (int32_t)tm;
+            w.value_local = F;
+            w.unimproved = 0;
+            w.pending = 0;
         }
     }
-    __syncthreads();
-    if (threadIdx.x == 0) be.near[0] = s_cnt;
 }
 
 // Wave-wide minimum / maximum of an int (result uniform).
@@ -424,13 +425,20 @@ __device__ __forceinline__ int wave_max(int v)
     return __builtin_amdgcn_readfirstlane(v);
 }
 
+// One-neighbour tables of a 32-shift window: ten triples of shifts (8
+// entries each, indexed by the three bits) and the last pair (4 entries).
+constexpr int kOneTriples = 10;
+constexpr int kOneWin = 8 * kOneTriples + 4;
+constexpr int kOneItems = 4 * kOneTriples + 2;   // table-building items per window
+
 // LDS of one evaluation block.
 struct EvalLds {
     double rows[kTileK * kRowStride];   // T(|C_k + 2m|), m = -2..2, per shift
     double both[kPairs * 16];           // pair sums, both neighbours
-    double one[kPairs * 4];             // pair sums, one neighbour
+    double one[kChunks * kOneWin];      // triple / pair sums, one neighbour
     uint32_t both_max[kPairs * 16];     // max hi32 of the pair (dense PSL only)
-    uint32_t one_max[kPairs * 4];
+    uint32_t one_max[kChunks * kOneWin];
+    uint32_t bits[kEvalWaves * 64];     // per wavefront: its pivot words of the tile
     int kend[kEvalWaves];               // per wavefront (up to kEvalWaves)
     int bmax[kEvalWaves];
     int omax[kEvalWaves];
@@ -472,14 +480,30 @@ __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const 
         b_omax = max(b_omax, sh.omax[x]);
     }
 
-    // bit-window cursors: right window of chunk c starts at element
-    // j + 1 + 32c (word (j+1)/32 + c, shift (j+1)%32); left window ends at
-    // element j - 1 - 32c and starts at j - 32 - 32c (word j/32 - 1 - c,
-    // shift j%32)
+    // bit windows: the right window of chunk c starts at element
+    // j + 1 + 32c (words (j+1)/32 + c and the next, shift (j+1)%32); the
+    // left window ends at element j - 1 - 32c and starts at j - 32 - 32c
+    // (words j/32 - 1 - c and the next, shift j%32). Per tile each
+    // wavefront stages the words its windows read in LDS: the lanes of a
+    // wavefront hold consecutive scan indices, so their j form at most two
+    // runs of consecutive values (two when the scan wraps past L-1); per run
+    // g, 16 slots of right words in increasing order and 16 slots of left
+    // words in decreasing order.
     const uint32_t sh_r = (uint32_t)(j + 1) & 31u;
     const uint32_t sh_l = (uint32_t)j & 31u;
-    const int wr0 = (j + 1) >> 5;
-    const int wl0 = (j >> 5) - 1;
+    const int lane = threadIdx.x & 63;
+    const int j_first = __shfl(j, 0);
+    const int grp = j < j_first ? 1 : 0;
+    constexpr int kNone = 1 << 30;                        // empty run: min > max
+    const int jmn0 = wave_min(grp ? kNone : j), jmx0 = wave_max(grp ? -kNone : j);
+    const int jmn1 = wave_min(grp ? j : kNone), jmx1 = wave_max(grp ? j : -kNone);
+    const int jmn = grp ? jmn1 : jmn0, jmx = grp ? jmx1 : jmx0;
+    const uint32_t *rbits = sh.bits + 64 * wave + 32 * grp + (((j + 1) >> 5) - ((jmn + 1) >> 5));
+    const uint32_t *lbits = sh.bits + 64 * wave + 32 * grp + 16 + ((jmx >> 5) - (j >> 5));
+    // the slots this lane stages: run lane/32, side (lane/16)%2, slot lane%16
+    const int s_grp = lane >> 5, s_side = (lane >> 4) & 1, s_idx = lane & 15;
+    const int s_mn = s_grp ? jmn1 : jmn0, s_mx = s_grp ? jmx1 : jmx0;
+    const int s_span = s_side ? (s_mx >> 5) - (s_mn >> 5) : ((s_mx + 1) >> 5) - ((s_mn + 1) >> 5);
 
     for (int kt = k_lo; kt < k_bend; kt += kTileK) {
         const int kt_end = min(k_bend, kt + kTileK);
@@ -488,6 +512,16 @@ __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const 
         const bool need_both = kt + 31 <= b_bmax;
         const bool need_one = kt + 31 <= b_omax;
         __syncthreads();
+        {
+            // this wavefront's words for its windows of the tile (chunks
+            // cb .. cb + cc_last)
+            const int cb = (kt - 1) >> 5;
+            const int cc_last = kt < k_wend ? min(kChunks - 1, (k_wend - 1 - kt) >> 5) : -1;
+            if (s_mn <= s_mx && s_idx < s_span + cc_last + 2) {
+                const int word = s_side ? (s_mx >> 5) - cb - s_idx : ((s_mn + 1) >> 5) + cb + s_idx;
+                sh.bits[64 * wave + lane] = w32[word];
+            }
+        }
         for (int t = threadIdx.x; t < nt; t += 64 * WAVES) {
             const int c = C[kt + t];
 #pragma unroll
@@ -499,66 +533,116 @@ __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const 
         }
         __syncthreads();
         if (need_both) {
-            for (int e = threadIdx.x; e < kPairs * 16; e += 64 * WAVES) {
-                const int p = e >> 4, x = e & 15;
+            // both neighbours: C' = C + 4(xr + xl - 1), row entry 2(xr + xl).
+            // Entry x of pair p: low two bits the left pair (xl_k, xl_k+1),
+            // high two the right pair; one thread per (pair, right bits)
+            // writes its four consecutive entries.
+            for (int e = threadIdx.x; e < kPairs * 4; e += 64 * WAVES) {
+                const int p = e >> 2, r0 = e & 1, r1 = (e >> 1) & 1;
                 if (2 * p + 1 < nt) {
-                    const double a = sh.rows[(2 * p) * kRowStride + 2 * ((x & 1) + ((x >> 2) & 1))];
-                    const double b = sh.rows[(2 * p + 1) * kRowStride + 2 * (((x >> 1) & 1) + ((x >> 3) & 1))];
-                    sh.both[e] = a + b;
-                    if (kMax) sh.both_max[e] = max(hi32(a), hi32(b));
+                    const double *ra = sh.rows + (2 * p) * kRowStride + 2 * r0;
+                    const double *rb = sh.rows + (2 * p + 1) * kRowStride + 2 * r1;
+                    const double a0 = ra[0], a1 = ra[2], b0 = rb[0], b1 = rb[2];
+                    double2 *dst = reinterpret_cast<double2 *>(sh.both + 4 * e);
+                    dst[0] = make_double2(a0 + b0, a1 + b0);
+                    dst[1] = make_double2(a0 + b1, a1 + b1);
+                    if (kMax) {
+                        const uint32_t ha0 = hi32(a0), ha1 = hi32(a1), hb0 = hi32(b0), hb1 = hi32(b1);
+                        *reinterpret_cast<uint4 *>(sh.both_max + 4 * e) =
+                            make_uint4(max(ha0, hb0), max(ha1, hb0), max(ha0, hb1), max(ha1, hb1));
+                    }
                 }
             }
         }
         if (need_one) {
-            for (int f = threadIdx.x; f < kPairs * 4; f += 64 * WAVES) {
-                const int p = f >> 2, x = f & 3;
-                if (2 * p + 1 < nt) {
-                    const double a = sh.rows[(2 * p) * kRowStride + 1 + 2 * (x & 1)];
-                    const double b = sh.rows[(2 * p + 1) * kRowStride + 1 + 2 * ((x >> 1) & 1)];
-                    sh.one[f] = a + b;
-                    if (kMax) sh.one_max[f] = max(hi32(a), hi32(b));
+            // one neighbour: C' = C + 2(2x - 1), row entry 1 + 2x. Per
+            // window, item (t, b) for t < 10 writes the two entries of
+            // triple t whose first two bits are b; items 40, 41 write the
+            // two entries of the last pair whose first bit is 0, 1.
+            for (int f = threadIdx.x; f < kChunks * kOneItems; f += 64 * WAVES) {
+                const int cc = f / kOneItems, r = f - cc * kOneItems;
+                double *dst = sh.one + kOneWin * cc;
+                uint32_t *dmx = sh.one_max + kOneWin * cc;
+                if (r < 4 * kOneTriples) {
+                    const int t = r >> 2, b = r & 3;
+                    const int t0 = 32 * cc + 3 * t;
+                    if (t0 + 2 < nt) {
+                        const double a = sh.rows[t0 * kRowStride + 1 + 2 * (b & 1)];
+                        const double bb = sh.rows[(t0 + 1) * kRowStride + 1 + 2 * (b >> 1)];
+                        const double c0 = sh.rows[(t0 + 2) * kRowStride + 1];
+                        const double c1 = sh.rows[(t0 + 2) * kRowStride + 3];
+                        const double ab = a + bb;
+                        dst[8 * t + b] = ab + c0;
+                        dst[8 * t + 4 + b] = ab + c1;
+                        if (kMax) {
+                            const uint32_t h = max(hi32(a), hi32(bb));
+                            dmx[8 * t + b] = max(h, hi32(c0));
+                            dmx[8 * t + 4 + b] = max(h, hi32(c1));
+                        }
+                    }
+                } else {
+                    const int b = r - 4 * kOneTriples;
+                    const int t0 = 32 * cc + 30;
+                    if (t0 + 1 < nt) {
+                        const double a = sh.rows[t0 * kRowStride + 1 + 2 * b];
+                        const double c0 = sh.rows[(t0 + 1) * kRowStride + 1];
+                        const double c1 = sh.rows[(t0 + 1) * kRowStride + 3];
+                        dst[8 * kOneTriples + b] = a + c0;
+                        dst[8 * kOneTriples + 2 + b] = a + c1;
+                        if (kMax) {
+                            dmx[8 * kOneTriples + b] = max(hi32(a), hi32(c0));
+                            dmx[8 * kOneTriples + 2 + b] = max(hi32(a), hi32(c1));
+                        }
+                    }
                 }
             }
         }
         __syncthreads();
 
         double acc = 0.0;
-        const int cbase = (kt - 1) >> 5;                   // chunk index of kt
 #pragma unroll
         for (int cc = 0; cc < kChunks; ++cc) {
             const int k0 = kt + 32 * cc;
             if (k0 < k_wend) {
-                const int c = cbase + cc;
-                const uint32_t XR = __builtin_amdgcn_alignbit(w32[wr0 + c + 1], w32[wr0 + c], sh_r) ^ SJ;
+                const uint32_t XR = __builtin_amdgcn_alignbit(rbits[cc + 1], rbits[cc], sh_r) ^ SJ;
                 const uint32_t XL = __builtin_bitreverse32(
-                    __builtin_amdgcn_alignbit(w32[wl0 - c + 1], w32[wl0 - c], sh_l) ^ SJ);
+                    __builtin_amdgcn_alignbit(lbits[cc], lbits[cc + 1], sh_l) ^ SJ);
                 const int tcount = min(32, kt_end - k0);
                 const double *bp = sh.both + (16 * 16) * cc;
-                const double *op = sh.one + (16 * 4) * cc;
+                const double *op = sh.one + kOneWin * cc;
                 const uint32_t *bq = sh.both_max + (16 * 16) * cc;
-                const uint32_t *oq = sh.one_max + (16 * 4) * cc;
+                const uint32_t *oq = sh.one_max + kOneWin * cc;
                 if (tcount == 32 && k0 + 31 <= both_max) {
+                    // nibble q of W0 (W1) is the table index of pair 2q
+                    // (2q+1): its two left bits below its two right bits
+                    const uint32_t W0 = (XL & 0x33333333u) | ((XR << 2) & 0xCCCCCCCCu);
+                    const uint32_t W1 = ((XL >> 2) & 0x33333333u) | (XR & 0xCCCCCCCCu);
 #pragma unroll
                     for (int p = 0; p < 16; ++p) {
-                        const uint32_t x = __builtin_amdgcn_ubfe(XR, 2 * p, 2) |
-                                           (__builtin_amdgcn_ubfe(XL, 2 * p, 2) << 2);
+                        const uint32_t x = ((p & 1 ? W1 : W0) >> (4 * (p >> 1))) & 15u;
                         acc += bp[16 * p + x];
                         if (kMax) mx = max(mx, bq[16 * p + x]);
                     }
                 } else if (tcount == 32 && k0 + 31 <= jr_min && k0 > jl_max) {
 #pragma unroll
-                    for (int p = 0; p < 16; ++p) {
-                        const uint32_t x = __builtin_amdgcn_ubfe(XR, 2 * p, 2);
-                        acc += op[4 * p + x];
-                        if (kMax) mx = max(mx, oq[4 * p + x]);
+                    for (int t = 0; t < kOneTriples; ++t) {
+                        const uint32_t x = __builtin_amdgcn_ubfe(XR, 3 * t, 3);
+                        acc += op[8 * t + x];
+                        if (kMax) mx = max(mx, oq[8 * t + x]);
                     }
+                    const uint32_t x = XR >> 30;
+                    acc += op[8 * kOneTriples + x];
+                    if (kMax) mx = max(mx, oq[8 * kOneTriples + x]);
                 } else if (tcount == 32 && k0 + 31 <= jl_min && k0 > jr_max) {
 #pragma unroll
-                    for (int p = 0; p < 16; ++p) {
-                        const uint32_t x = __builtin_amdgcn_ubfe(XL, 2 * p, 2);
-                        acc += op[4 * p + x];
-                        if (kMax) mx = max(mx, oq[4 * p + x]);
+                    for (int t = 0; t < kOneTriples; ++t) {
+                        const uint32_t x = __builtin_amdgcn_ubfe(XL, 3 * t, 3);
+                        acc += op[8 * t + x];
+                        if (kMax) mx = max(mx, oq[8 * t + x]);
                     }
+                    const uint32_t x = XL >> 30;
+                    acc += op[8 * kOneTriples + x];
+                    if (kMax) mx = max(mx, oq[8 * kOneTriples + x]);
                 } else {
                     // mixed bounds or a partial chunk: per shift
                     const double *rb = sh.rows + (32 * cc) * kRowStride;
@@ -584,22 +668,24 @@ __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const 
         const int xa = (kn - 1) >> 5;
         const int xb = k_hi >= L ? nchunks : (k_hi - 1) >> 5;
         nsum_add(sum, comp, be.S0[xa] - be.S0[xb]);
-        if (kMax) mx = max(mx, be.M0[xa]);
+        if (kMax) mx = max(mx, hi32(T[be.M0[xa]]));
     }
 }
 
 // Neighborhood of Algorithm 1 for one (walk, 64*WAVES candidates, k-range) item.
 //
 // Per 256-shift tile the block stages (i) per shift the five values
-// T(|C_k + 2m|), m = -2..2, and (ii) per pair of shifts (k, k+1) two tables
-// of pre-added terms: 16 entries indexed by the four bits (xr_k, xr_k+1,
-// xl_k, xl_k+1) for shifts where both neighbours of j exist
-// (C' = C + 4(xr + xl - 1)), and 4 entries indexed by (x_k, x_k+1) for shifts
-// where one neighbour exists (C' = C + 2(2x - 1)); x = 1 when s_j times that
+// T(|C_k + 2m|), m = -2..2, and (ii) tables of pre-added terms: for shifts
+// where both neighbours of j exist (C' = C + 4(xr + xl - 1)), 16 entries per
+// pair of shifts (k, k+1) indexed by the four bits (xl_k, xl_k+1, xr_k,
+// xr_k+1); for shifts where one neighbour exists (C' = C + 2(2x - 1)), 8
+// entries per triple of shifts indexed by its three bits (ten triples and a
+// final 4-entry pair per 32-shift window); x = 1 when s_j times that
 // neighbour is -1. A lane takes a 32-shift window of each side's bits with
-// one funnel shift, and per pair of shifts does two bit-field extracts, one
-// LDS read and one FP64 add. Which form a 32-shift window uses is decided
-// once per wavefront from the lanes' bounds. Shifts past every lane's
+// one funnel shift; per table entry it does a shift and a mask (the two
+// sides' bits are first merged nibble-wise with bit-field inserts), one LDS
+// read and one FP64 add. Which form a 32-shift window uses is decided once
+// per wavefront from the lanes' bounds. Shifts past every lane's
 // max(j, L-1-j) come from the suffix sums. The PSL comes from the near-peak
 // shifts (split 0 only), or, for pivots with many near-peak shifts, from
 // 32-bit maxima kept in the main loop.
@@ -666,10 +752,17 @@ __device__ __forceinline__ void eval_item(EvalLds &sh, const WalkDev *__restrict
     }
 }
 
+// Register budget of the evaluation kernels: the LDS of a block admits three
+// blocks per CU, i.e. 3 * WAVES / 4 wavefronts per SIMD; ask the compiler to
+// keep the VGPR count low enough for that.
+template <int WAVES>
+constexpr int kEvalWavesPerEU = WAVES * 3 / 4 > 0 ? WAVES * 3 / 4 : 1;
+
 // One block per work item; items are laid out as 8 equal-cost XCD ranges
 // padded to equal length.
 template <int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_eval(const WalkDev *__restrict__ walks,
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(kEvalWavesPerEU<WAVES>)))
+void k_eval(const WalkDev *__restrict__ walks,
                                                      const BatchEntry *__restrict__ batch,
                                                      const EvalItem *__restrict__ items, Tables tabs)
 {
@@ -683,7 +776,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_eval(const WalkDev *__restrict__
 // per-XCD queues, its own XCD's first (longest items first), then the
 // others'. Every block leaves once all 8 queues are drained.
 template <int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_eval_persistent(const WalkDev *__restrict__ walks,
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(kEvalWavesPerEU<WAVES>)))
+void k_eval_persistent(const WalkDev *__restrict__ walks,
                                                                 const BatchEntry *__restrict__ batch,
                                                                 const EvalItem *__restrict__ items,
                                                                 Tables tabs, EvalQueues *queues)
@@ -737,36 +831,51 @@ __device__ __forceinline__ void sel_merge(double &f, int32_t &p, uint32_t &i, do
     }
 }
 
-// F and PSL per candidate from the k-split partials (splits added in order),
-// spread over gridDim.x blocks per walk (blockIdx.y = batch position); each
-// block leaves its smallest F and its first smallest PSL in be.red.
+// F and PSL per candidate from the k-split partials, spread over gridDim.x
+// blocks per walk (blockIdx.y = batch position); each block leaves its
+// smallest F and its first smallest PSL in be.red. A group of G lanes
+// (a power of two, at most 64) shares a candidate: lane g adds splits g,
+// g+G, ... in order, then the group adds its lanes' sums with a butterfly
+// (a fixed order for a given split count and G; G = 1 adds the splits in
+// order).
 __global__ __launch_bounds__(kCombThreads) void k_combine(const WalkDev *walks, const BatchEntry *batch,
-                                                          Tables tabs)
+                                                          Tables tabs, int G)
 {
     const BatchEntry be = batch[blockIdx.y];
     const WalkDev &w = walks[be.slot];
     const uint32_t n = be.fixed ? be.n_lmt : w.n_lmt;
     const uint32_t ks = be.ksplit;
     const double *T = tabs.T[w.alpha];
+    const uint32_t g = threadIdx.x & (uint32_t)(G - 1);
+    const uint32_t cpb = kCombThreads / (uint32_t)G;      // candidates per block pass
 
     double fmin = INFINITY;
     int32_t pmin = INT_MAX;
     uint32_t ipmin = UINT_MAX;
-    for (uint32_t i = blockIdx.x * kCombThreads + threadIdx.x; i < n; i += gridDim.x * kCombThreads) {
+    for (uint32_t i0 = blockIdx.x * cpb; i0 < n; i0 += gridDim.x * cpb) {
+        const uint32_t i = i0 + threadIdx.x / (uint32_t)G;
         double f = 0.0;
         uint32_t m = 0;
-        for (uint32_t x = 0; x < ks; ++x) {
-            f += be.Fpart[(size_t)x * n + i];
-            m = max(m, be.Mpart[(size_t)x * n + i]);
+        if (i < n) {
+            for (uint32_t x = g; x < ks; x += (uint32_t)G) {
+                f += be.Fpart[(size_t)x * n + i];
+                m = max(m, be.Mpart[(size_t)x * n + i]);
+            }
         }
-        // the near-peak path stores the PSL itself; the dense path the high
-        // word of T(PSL), which is at least hi32(T(1)) = 0x3FF00000 because
-        // |C'_{L-1}| = 1 for every sequence
-        const int32_t p = m < 0x3FF00000u ? (int32_t)m : table_inverse(T, tabs.n, m);
-        be.F[i] = f;
-        be.P[i] = p;
-        fmin = f < fmin ? f : fmin;
-        if (p < pmin) { pmin = p; ipmin = i; }
+        for (int o = G >> 1; o > 0; o >>= 1) {
+            f += __shfl_xor(f, o);
+            m = max(m, (uint32_t)__shfl_xor((int)m, o));
+        }
+        if (g == 0 && i < n) {
+            // the near-peak path stores the PSL itself; the dense path the
+            // high word of T(PSL), which is at least hi32(T(1)) = 0x3FF00000
+            // because |C'_{L-1}| = 1 for every sequence
+            const int32_t p = m < 0x3FF00000u ? (int32_t)m : table_inverse(T, tabs.n, m);
+            be.F[i] = f;
+            be.P[i] = p;
+            fmin = f < fmin ? f : fmin;
+            if (p < pmin) { pmin = p; ipmin = i; }
+        }
     }
     for (int o = 32; o > 0; o >>= 1) {
         const double of = __shfl_xor(fmin, o);
@@ -853,6 +962,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select(WalkDev *walks, const Ba
 
     __shared__ int s_improve;
     if (threadIdx.x == 0) {
+        be.near[0] = 0;           // the evaluation has read it; k_chunks appends to it
         const double Fb = be.F[ib];
         const int32_t Pb = be.P[ib];
         if (pure) {
@@ -1066,20 +1176,46 @@ hipError_t launch_eval(const WalkDev *walks, const BatchEntry *batch, const Eval
     return hipGetLastError();
 }
 
-hipError_t launch_suffix(const WalkDev *walks, const BatchEntry *batch, uint32_t nb, const Tables &tabs,
-                         hipStream_t s)
+hipError_t launch_suffix(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t max_L,
+                         const Tables &tabs, int mode, hipStream_t s)
 {
-    k_suffix<<<nb, kSufThreads, 0, s>>>(walks, batch, tabs);
+    // about 2048 blocks over the batch, at most one per 8 chunks of the
+    // longest walk
+    const uint32_t nchunks = (max_L - 1 + 31) / 32;
+    const uint32_t per_walk = std::max<uint32_t>(1, (2048 + nb - 1) / nb);
+    const uint32_t bx = std::max<uint32_t>(1, std::min(per_walk, (nchunks + 7) / 8));
+    for (uint32_t b0 = 0; b0 < nb; b0 += kMaxGridY) {
+        k_chunks<<<dim3(bx, std::min(kMaxGridY, nb - b0)), kChunkThreads, 0, s>>>(walks, batch + b0, tabs, mode);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    k_scan<<<nb, kScanThreads, 0, s>>>(walks, batch, mode);
+    return hipGetLastError();
+}
+
+__global__ void k_near_reset(const BatchEntry *batch, uint32_t nb)
+{
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < nb) batch[b].near[0] = 0;
+}
+
+hipError_t launch_near_reset(const BatchEntry *batch, uint32_t nb, hipStream_t s)
+{
+    k_near_reset<<<(nb + 255) / 256, 256, 0, s>>>(batch, nb);
     return hipGetLastError();
 }
 
 hipError_t launch_select(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t comb_blocks,
-                         const Tables &tabs, int pure, void *out, hipStream_t s)
+                         uint32_t comb_group, const Tables &tabs, int pure, void *out, hipStream_t s)
 {
     if (comb_blocks < 1 || comb_blocks > kCombMaxBlocks) return hipErrorInvalidValue;
-    k_combine<<<dim3(comb_blocks, nb), kCombThreads, 0, s>>>(walks, batch, tabs);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (comb_group < 1 || comb_group > 64 || (comb_group & (comb_group - 1))) return hipErrorInvalidValue;
+    for (uint32_t b0 = 0; b0 < nb; b0 += kMaxGridY) {
+        k_combine<<<dim3(comb_blocks, std::min(kMaxGridY, nb - b0)), kCombThreads, 0, s>>>(
+            walks, batch + b0, tabs, (int)comb_group);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     k_select<<<nb, kSelThreads, 0, s>>>(walks, batch, comb_blocks, pure, (ChoiceDev *)out);
     return hipGetLastError();
 }

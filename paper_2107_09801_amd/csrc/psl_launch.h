@@ -17,10 +17,14 @@ hipError_t launch_fitness(WalkDev *walks, const BatchEntry *batch, uint32_t nb, 
 hipError_t launch_eval(const WalkDev *walks, const BatchEntry *batch, const EvalItem *items,
                        uint32_t n_items, const Tables &tabs, const EvalShape &shape,
                        EvalQueues *queues, hipStream_t s);
-hipError_t launch_suffix(const WalkDev *walks, const BatchEntry *batch, uint32_t nb, const Tables &tabs,
-                         hipStream_t s);
+// mode 0: the step's chunk suffix arrays and near-peak list; mode 1: the
+// fitness of pending walks after a phase switch.
+hipError_t launch_suffix(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t max_L,
+                         const Tables &tabs, int mode, hipStream_t s);
+// Zero the near-peak counts of a batch (after its scratch is allocated).
+hipError_t launch_near_reset(const BatchEntry *batch, uint32_t nb, hipStream_t s);
 hipError_t launch_select(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t comb_blocks,
-                         const Tables &tabs, int pure, void *out, hipStream_t s);
+                         uint32_t comb_group, const Tables &tabs, int pure, void *out, hipStream_t s);
 size_t choice_dev_size();
 void choice_dev_unpack(const void *p, uint32_t *i_best, uint32_t *j_best, double *F_best,
                        double *F_min, uint32_t *j_psl, int32_t *psl_min, int32_t *psl_k);

@@ -262,15 +262,21 @@ void eval_layout(const uint32_t *Ls, const uint32_t *nl, uint32_t n, const EvalS
         std::stable_sort(sg.begin(), sg.end(), [](const C &a, const C &b) { return a.cost > b.cost; });
         cmax = std::max(cmax, sg.size());
     }
-    // selection: about 8192 partials per combine block, at most one block
-    // per 256 candidates
-    uint64_t work = 0, nmax = 0;
+    // selection: a group of G lanes per candidate with about 16 splits per
+    // lane, about 8192 partials per combine block, at most one block per
+    // block-pass of candidates
+    uint64_t work = 0, nmax = 0, ksmax = 1;
     for (uint32_t b = 0; b < n; ++b) {
         work = std::max<uint64_t>(work, (uint64_t)out.ks[b] * nl[b]);
         nmax = std::max<uint64_t>(nmax, nl[b]);
+        ksmax = std::max<uint64_t>(ksmax, out.ks[b]);
     }
+    uint32_t G = 1;
+    while (G < 64 && (uint64_t)G * 16 < ksmax) G <<= 1;
+    out.comb_group = G;
+    const uint64_t cpb = 256 / G;
     out.comb_blocks = (uint32_t)std::max<uint64_t>(
-        1, std::min<uint64_t>({(work + 8191) / 8192, (nmax + 255) / 256, (uint64_t)kCombMaxBlocks}));
+        1, std::min<uint64_t>({(work + 8191) / 8192, (nmax + cpb - 1) / cpb, (uint64_t)kCombMaxBlocks}));
     out.items.reserve(shape.persistent ? all.size() : 8 * cmax);
     for (int q = 0; q < 8; ++q) {
         auto &sg = seg[q];
@@ -308,6 +314,7 @@ psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t 
     std::vector<EvalItem> &items = lay.items;
     pl.shape = lay.shape;
     pl.comb_blocks = lay.comb_blocks;
+    pl.comb_group = lay.comb_group;
     size_t n_part = 0, n_cand = 0, n_suf = 0;
     for (uint32_t b = 0; b < n; ++b) {
         n_part += (size_t)ks[b] * n_l[b];
@@ -369,6 +376,7 @@ psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t 
     HIP_TRY(ctx, hipMemcpy(pl.d_batch, be.data(), sizeof(BatchEntry) * n, hipMemcpyHostToDevice));
     HIP_TRY(ctx, hipMemcpy(pl.d_items, items.data(), sizeof(EvalItem) * items.size(),
                            hipMemcpyHostToDevice));
+    HIP_TRY(ctx, launch_near_reset(pl.d_batch, n, ctx->stream));
     pl.n_items = (uint32_t)items.size();
     return PSL_OK;
 }
@@ -430,17 +438,18 @@ psl_status check_cfg(psl_ctx *ctx, const psl_walk_cfg *c)
 psl_status launch_step(psl_ctx *ctx, const BatchPlan &pl, const Tables &tabs, uint32_t n, bool timed)
 {
     psl_status st;
-    HIP_TRY(ctx, launch_suffix(ctx->d_walks, pl.d_batch, n, tabs, ctx->stream));
+    HIP_TRY(ctx, launch_suffix(ctx->d_walks, pl.d_batch, n, pl.max_L, tabs, 0, ctx->stream));
     if (timed && (st = timing_mark(ctx))) return st;
     HIP_TRY(ctx, launch_eval(ctx->d_walks, pl.d_batch, pl.d_items, pl.n_items, tabs, pl.shape, pl.d_queues,
                              ctx->stream));
     if (timed && (st = timing_mark(ctx))) return st;
-    HIP_TRY(ctx, launch_select(ctx->d_walks, pl.d_batch, n, pl.comb_blocks, tabs, 0, nullptr, ctx->stream));
+    HIP_TRY(ctx, launch_select(ctx->d_walks, pl.d_batch, n, pl.comb_blocks, pl.comb_group, tabs, 0, nullptr,
+                               ctx->stream));
     HIP_TRY(ctx, launch_apply(ctx->d_walks, pl.d_batch, n, pl.max_L, -1, ctx->stream));
     HIP_TRY(ctx, launch_bookkeep(ctx->d_walks, pl.d_batch, n, ctx->stream));
     HIP_TRY(ctx, launch_switch_corr(ctx->d_walks, pl.d_batch, n, pl.max_L, ctx->stream));
     if (pl.big_flips) HIP_TRY(ctx, launch_corr(ctx->d_walks, pl.d_batch, n, pl.max_L, 1, ctx->stream));
-    HIP_TRY(ctx, launch_fitness(ctx->d_walks, pl.d_batch, n, tabs, 1, ctx->stream));
+    HIP_TRY(ctx, launch_suffix(ctx->d_walks, pl.d_batch, n, pl.max_L, tabs, 1, ctx->stream));
     if (timed && (st = timing_mark(ctx))) return st;
     return PSL_OK;
 }
@@ -692,10 +701,11 @@ psl_status psl_eval_neighbourhood(psl_ctx *ctx, uint32_t walk, uint32_t start, u
     psl_status st = make_plan(ctx, ctx->pure, &walk, 1, n_lmt, start);
     if (st) return st;
     const Tables tabs = tables_of(ctx);
-    HIP_TRY(ctx, launch_suffix(ctx->d_walks, ctx->pure.d_batch, 1, tabs, ctx->stream));
+    HIP_TRY(ctx, launch_suffix(ctx->d_walks, ctx->pure.d_batch, 1, h.L, tabs, 0, ctx->stream));
     HIP_TRY(ctx, launch_eval(ctx->d_walks, ctx->pure.d_batch, ctx->pure.d_items, ctx->pure.n_items,
                              tabs, ctx->pure.shape, ctx->pure.d_queues, ctx->stream));
-    HIP_TRY(ctx, launch_select(ctx->d_walks, ctx->pure.d_batch, 1, ctx->pure.comb_blocks, tabs, 1, ctx->d_choice,
+    HIP_TRY(ctx, launch_select(ctx->d_walks, ctx->pure.d_batch, 1, ctx->pure.comb_blocks, ctx->pure.comb_group, tabs, 1,
+                               ctx->d_choice,
                                ctx->stream));
     if (F_dev)
         HIP_TRY(ctx, hipMemcpyAsync(F_dev, ctx->pure.d_f, sizeof(double) * n_lmt,
@@ -897,7 +907,7 @@ psl_status psl_autotune(psl_ctx *ctx, const uint32_t *walk_ids, uint32_t n, psl_
     for (const EvalShape &c : cands) {
         BatchPlan tmp;
         if ((st = make_plan(ctx, tmp, walk_ids, n, UINT32_MAX, 0, &c))) break;
-        hipError_t e = launch_suffix(ctx->d_walks, tmp.d_batch, n, tabs, ctx->stream);
+        hipError_t e = launch_suffix(ctx->d_walks, tmp.d_batch, n, tmp.max_L, tabs, 0, ctx->stream);
         if (e == hipSuccess)   // warm-up
             e = launch_eval(ctx->d_walks, tmp.d_batch, tmp.d_items, tmp.n_items, tabs, tmp.shape,
                             tmp.d_queues, ctx->stream);

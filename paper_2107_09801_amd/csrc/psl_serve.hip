@@ -99,7 +99,7 @@ struct Server {
     DevBuf<double> d_fpart, d_f, d_s0;
     DevBuf<uint32_t> d_mpart, d_m0, d_near, d_want;
     DevBuf<SelPart> d_red;
-    uint32_t comb_blocks = 1;
+    uint32_t comb_blocks = 1, comb_group = 1;
     DevBuf<int32_t> d_p;
     uint32_t n_items = 0, max_L = 0;
     EvalShape shape;
@@ -340,6 +340,7 @@ psl_status Server::upload_layout(char *&sp, char *stage_end)
     const size_t items = lay.items.size();
     shape = lay.shape;
     comb_blocks = lay.comb_blocks;
+    comb_group = lay.comb_group;
     const size_t need = sizeof(BatchEntry) * n + sizeof(EvalItem) * items + sizeof(EvalQueues) + 256;
     if ((size_t)(stage_end - sp) < need) return fail(ctx, PSL_E_NOMEM, "serving staging too small");
     psl_status st;
@@ -387,6 +388,7 @@ psl_status Server::upload_layout(char *&sp, char *stage_end)
     sp += sizeof(EvalQueues);
     *qs = lay.queues;
     HIP_TRY(ctx, hipMemcpyAsync(d_queues.p, qs, sizeof(EvalQueues), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, launch_near_reset(d_batch.p, n, ctx->stream));
     n_items = (uint32_t)items;
     dirty = false;
     return PSL_OK;
@@ -441,16 +443,16 @@ psl_status Server::iterate()
     if (dirty && (st = upload_layout(sp, se))) return st;
     const uint32_t n = (uint32_t)active.size();
     const Tables tabs = tables_of(ctx);
-    HIP_TRY(ctx, launch_suffix(ctx->d_walks, d_batch.p, n, tabs, ctx->stream));
+    HIP_TRY(ctx, launch_suffix(ctx->d_walks, d_batch.p, n, max_L, tabs, 0, ctx->stream));
     HIP_TRY(ctx, launch_eval(ctx->d_walks, d_batch.p, d_items.p, n_items, tabs, shape, d_queues.p, ctx->stream));
-    HIP_TRY(ctx, launch_select(ctx->d_walks, d_batch.p, n, comb_blocks, tabs, 0, nullptr, ctx->stream));
+    HIP_TRY(ctx, launch_select(ctx->d_walks, d_batch.p, n, comb_blocks, comb_group, tabs, 0, nullptr, ctx->stream));
     HIP_TRY(ctx, launch_apply(ctx->d_walks, d_batch.p, n, max_L, -1, ctx->stream));
     HIP_TRY(ctx, launch_bookkeep(ctx->d_walks, d_batch.p, n, ctx->stream));
     HIP_TRY(ctx, launch_switch_corr(ctx->d_walks, d_batch.p, n, max_L, ctx->stream));
     bool big = false;
     for (auto &j : active) big |= j.cfg.flip_lmt > kFlipIncremental;
     if (big) HIP_TRY(ctx, launch_corr(ctx->d_walks, d_batch.p, n, max_L, 1, ctx->stream));
-    HIP_TRY(ctx, launch_fitness(ctx->d_walks, d_batch.p, n, tabs, 1, ctx->stream));
+    HIP_TRY(ctx, launch_suffix(ctx->d_walks, d_batch.p, n, max_L, tabs, 1, ctx->stream));
     uint64_t evals = 0, upd = 0;
     for (auto &j : active) {
         const uint64_t nl = j.cfg.n_lmt ? j.cfg.n_lmt : j.cfg.L;

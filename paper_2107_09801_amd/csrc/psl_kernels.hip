@@ -425,17 +425,17 @@ __device__ __forceinline__ int wave_max(int v)
     return __builtin_amdgcn_readfirstlane(v);
 }
 
-// One-neighbour tables of a 32-shift window: ten triples of shifts (8
-// entries each, indexed by the three bits) and the last pair (4 entries).
-constexpr int kOneTriples = 10;
-constexpr int kOneWin = 8 * kOneTriples + 4;
-constexpr int kOneItems = 4 * kOneTriples + 2;   // table-building items per window
+// One-neighbour tables of a 32-shift window: eight quads of shifts, 16
+// entries each, indexed by the quad's four bits.
+constexpr int kOneQuads = 8;
+constexpr int kOneWin = 16 * kOneQuads;
+constexpr int kOneItems = 4 * kOneQuads;   // table-building items per window
 
 // LDS of one evaluation block.
 struct EvalLds {
     double rows[kTileK * kRowStride];   // T(|C_k + 2m|), m = -2..2, per shift
     double both[kPairs * 16];           // pair sums, both neighbours
-    double one[kChunks * kOneWin];      // triple / pair sums, one neighbour
+    double one[kChunks * kOneWin];      // quad sums, one neighbour
     uint32_t both_max[kPairs * 16];     // max hi32 of the pair (dense PSL only)
     uint32_t one_max[kChunks * kOneWin];
     uint32_t bits[kEvalWaves * 64];     // per wavefront: its pivot words of the tile
@@ -555,44 +555,29 @@ __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const 
             }
         }
         if (need_one) {
-            // one neighbour: C' = C + 2(2x - 1), row entry 1 + 2x. Per
-            // window, item (t, b) for t < 10 writes the two entries of
-            // triple t whose first two bits are b; items 40, 41 write the
-            // two entries of the last pair whose first bit is 0, 1.
+            // one neighbour: C' = C + 2(2x - 1), row entry 1 + 2x. Entry x of
+            // quad q: bit i of x is the bit of shift 4q + i. Item (q, h) of a
+            // window writes the four consecutive entries whose two high bits
+            // are h: (a + b) + (c + d).
             for (int f = threadIdx.x; f < kChunks * kOneItems; f += 64 * WAVES) {
                 const int cc = f / kOneItems, r = f - cc * kOneItems;
-                double *dst = sh.one + kOneWin * cc;
-                uint32_t *dmx = sh.one_max + kOneWin * cc;
-                if (r < 4 * kOneTriples) {
-                    const int t = r >> 2, b = r & 3;
-                    const int t0 = 32 * cc + 3 * t;
-                    if (t0 + 2 < nt) {
-                        const double a = sh.rows[t0 * kRowStride + 1 + 2 * (b & 1)];
-                        const double bb = sh.rows[(t0 + 1) * kRowStride + 1 + 2 * (b >> 1)];
-                        const double c0 = sh.rows[(t0 + 2) * kRowStride + 1];
-                        const double c1 = sh.rows[(t0 + 2) * kRowStride + 3];
-                        const double ab = a + bb;
-                        dst[8 * t + b] = ab + c0;
-                        dst[8 * t + 4 + b] = ab + c1;
-                        if (kMax) {
-                            const uint32_t h = max(hi32(a), hi32(bb));
-                            dmx[8 * t + b] = max(h, hi32(c0));
-                            dmx[8 * t + 4 + b] = max(h, hi32(c1));
-                        }
-                    }
-                } else {
-                    const int b = r - 4 * kOneTriples;
-                    const int t0 = 32 * cc + 30;
-                    if (t0 + 1 < nt) {
-                        const double a = sh.rows[t0 * kRowStride + 1 + 2 * b];
-                        const double c0 = sh.rows[(t0 + 1) * kRowStride + 1];
-                        const double c1 = sh.rows[(t0 + 1) * kRowStride + 3];
-                        dst[8 * kOneTriples + b] = a + c0;
-                        dst[8 * kOneTriples + 2 + b] = a + c1;
-                        if (kMax) {
-                            dmx[8 * kOneTriples + b] = max(hi32(a), hi32(c0));
-                            dmx[8 * kOneTriples + 2 + b] = max(hi32(a), hi32(c1));
-                        }
+                const int q = r >> 2, h0 = r & 1, h1 = (r >> 1) & 1;
+                const int t0 = 32 * cc + 4 * q;
+                if (t0 + 3 < nt) {
+                    const double *ra = sh.rows + t0 * kRowStride + 1;
+                    const double a0 = ra[0], a1 = ra[2];
+                    const double b0 = ra[kRowStride], b1 = ra[kRowStride + 2];
+                    const double c = ra[2 * kRowStride + 2 * h0], d = ra[3 * kRowStride + 2 * h1];
+                    const double cd = c + d;
+                    double2 *dst = reinterpret_cast<double2 *>(sh.one + kOneWin * cc + 16 * q + 4 * (r & 3));
+                    dst[0] = make_double2((a0 + b0) + cd, (a1 + b0) + cd);
+                    dst[1] = make_double2((a0 + b1) + cd, (a1 + b1) + cd);
+                    if (kMax) {
+                        const uint32_t hcd = max(hi32(c), hi32(d));
+                        const uint32_t ha0 = max(hi32(a0), hcd), ha1 = max(hi32(a1), hcd);
+                        const uint32_t hb0 = hi32(b0), hb1 = hi32(b1);
+                        *reinterpret_cast<uint4 *>(sh.one_max + kOneWin * cc + 16 * q + 4 * (r & 3)) =
+                            make_uint4(max(ha0, hb0), max(ha1, hb0), max(ha0, hb1), max(ha1, hb1));
                     }
                 }
             }
@@ -625,24 +610,18 @@ __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const 
                     }
                 } else if (tcount == 32 && k0 + 31 <= jr_min && k0 > jl_max) {
 #pragma unroll
-                    for (int t = 0; t < kOneTriples; ++t) {
-                        const uint32_t x = __builtin_amdgcn_ubfe(XR, 3 * t, 3);
-                        acc += op[8 * t + x];
-                        if (kMax) mx = max(mx, oq[8 * t + x]);
+                    for (int q = 0; q < kOneQuads; ++q) {
+                        const uint32_t x = (XR >> (4 * q)) & 15u;
+                        acc += op[16 * q + x];
+                        if (kMax) mx = max(mx, oq[16 * q + x]);
                     }
-                    const uint32_t x = XR >> 30;
-                    acc += op[8 * kOneTriples + x];
-                    if (kMax) mx = max(mx, oq[8 * kOneTriples + x]);
                 } else if (tcount == 32 && k0 + 31 <= jl_min && k0 > jr_max) {
 #pragma unroll
-                    for (int t = 0; t < kOneTriples; ++t) {
-                        const uint32_t x = __builtin_amdgcn_ubfe(XL, 3 * t, 3);
-                        acc += op[8 * t + x];
-                        if (kMax) mx = max(mx, oq[8 * t + x]);
+                    for (int q = 0; q < kOneQuads; ++q) {
+                        const uint32_t x = (XL >> (4 * q)) & 15u;
+                        acc += op[16 * q + x];
+                        if (kMax) mx = max(mx, oq[16 * q + x]);
                     }
-                    const uint32_t x = XL >> 30;
-                    acc += op[8 * kOneTriples + x];
-                    if (kMax) mx = max(mx, oq[8 * kOneTriples + x]);
                 } else {
                     // mixed bounds or a partial chunk: per shift
                     const double *rb = sh.rows + (32 * cc) * kRowStride;
@@ -678,10 +657,9 @@ __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const 
 // T(|C_k + 2m|), m = -2..2, and (ii) tables of pre-added terms: for shifts
 // where both neighbours of j exist (C' = C + 4(xr + xl - 1)), 16 entries per
 // pair of shifts (k, k+1) indexed by the four bits (xl_k, xl_k+1, xr_k,
-// xr_k+1); for shifts where one neighbour exists (C' = C + 2(2x - 1)), 8
-// entries per triple of shifts indexed by its three bits (ten triples and a
-// final 4-entry pair per 32-shift window); x = 1 when s_j times that
-// neighbour is -1. A lane takes a 32-shift window of each side's bits with
+// xr_k+1); for shifts where one neighbour exists (C' = C + 2(2x - 1)), 16
+// entries per quad of shifts indexed by its four bits; x = 1 when s_j times
+// that neighbour is -1. A lane takes a 32-shift window of each side's bits with
 // one funnel shift; per table entry it does a shift and a mask (the two
 // sides' bits are first merged nibble-wise with bit-field inserts), one LDS
 // read and one FP64 add. Which form a 32-shift window uses is decided once
@@ -857,6 +835,7 @@ __global__ __launch_bounds__(kCombThreads) void k_combine(const WalkDev *walks, 
         double f = 0.0;
         uint32_t m = 0;
         if (i < n) {
+#pragma unroll 4
             for (uint32_t x = g; x < ks; x += (uint32_t)G) {
                 f += be.Fpart[(size_t)x * n + i];
                 m = max(m, be.Mpart[(size_t)x * n + i]);
@@ -942,10 +921,21 @@ __global__ __launch_bounds__(kSelThreads) void k_select(WalkDev *walks, const Ba
     const double thr = Fmin * (1.0 + kTau);
     __syncthreads();
 
-    // first scan index inside the band
+    // first scan index inside the band: rounds of 8 * kSelThreads indices,
+    // each thread's eight loads issued together; the first round with a hit
+    // holds the answer
     uint32_t ifirst = UINT_MAX;
-    for (uint32_t i = threadIdx.x; i < n; i += kSelThreads) {
-        if (be.F[i] <= thr) { ifirst = i; break; }
+    for (uint32_t i0 = 0; i0 < n; i0 += 8 * kSelThreads) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t i = i0 + u * kSelThreads + threadIdx.x;
+            v[u] = i < n ? be.F[i] : INFINITY;
+        }
+#pragma unroll
+        for (int u = 7; u >= 0; --u)
+            if (v[u] <= thr) ifirst = i0 + u * kSelThreads + threadIdx.x;
+        if (__syncthreads_or(ifirst != UINT_MAX)) break;
     }
     s_i[threadIdx.x] = ifirst;
     __syncthreads();

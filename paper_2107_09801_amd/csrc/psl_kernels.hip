@@ -275,8 +275,9 @@ __global__ __launch_bounds__(kFitThreads) void k_fitness(WalkDev *walks, const B
 // Two kernels: k_chunks (several blocks per walk) writes per-chunk sums (a
 // fixed 32-lane tree) and maxima and appends to the near list; k_scan (one
 // block per walk) turns the chunk values into suffix values in a fixed order.
-// The same pair, in mode 1, is the fitness of a walk after a phase switch:
-// S0[0] = F and M0[0] = PSL of the new pivot under the new alpha.
+// The same pair is also the fitness of a pivot: S0[0] = F and M0[0] = PSL.
+// Mode 1: after a phase switch (pending walks: the new pivot under the new
+// alpha); mode 2: at init (every walk).
 constexpr int kChunkThreads = 256;
 constexpr uint32_t kMaxGridY = 65535;      // walks per launch of the 2-D grids
 __global__ __launch_bounds__(kChunkThreads) void k_chunks(const WalkDev *walks, const BatchEntry *batch,
@@ -292,7 +293,7 @@ __global__ __launch_bounds__(kChunkThreads) void k_chunks(const WalkDev *walks, 
     const int gw = (int)blockIdx.x * (kChunkThreads / 64) + ((int)threadIdx.x >> 6);
     const int nwaves = (int)gridDim.x * (kChunkThreads / 64);
     // the near-peak cut (the pivot's PSL is kept current by every step)
-    const int cut = mode == 0 ? w.psl_pivot - 8 : INT_MAX;
+    const int cut = mode == 0 ? w.psl_pivot - 8 : INT_MAX;   // unused in modes 1, 2
     // a wavefront covers two chunks per pass
     for (int p = gw; 2 * p < nchunks; p += nwaves) {
         const int k = 1 + 64 * p + lane;
@@ -401,14 +402,18 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(WalkDev *walks, const Bat
     if (threadIdx.x == 0) {
         be.S0[nchunks] = 0.0;
         be.M0[nchunks] = 0;
-        if (mode == 1) {
+        if (mode != 0) {
             // thread 0's segment starts at chunk 0: the totals over k >= 1
             const double F = ts + tc;
             w.F_pivot = F;
             w.psl_pivot = (int32_t)tm;
             w.value_local = F;
-            w.unimproved = 0;
-            w.pending = 0;
+            if (mode == 1) {
+                w.unimproved = 0;
+                w.pending = 0;
+            } else {
+                w.psl_best = (int32_t)tm;
+            }
         }
     }
 }

@@ -18,7 +18,8 @@ hipError_t launch_eval(const WalkDev *walks, const BatchEntry *batch, const Eval
                        uint32_t n_items, const Tables &tabs, const EvalShape &shape,
                        EvalQueues *queues, hipStream_t s);
 // mode 0: the step's chunk suffix arrays and near-peak list; mode 1: the
-// fitness of pending walks after a phase switch.
+// fitness of pending walks after a phase switch; mode 2: the initial fitness
+// (value_local, F_pivot, psl_pivot, psl_best) of every walk.
 hipError_t launch_suffix(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t max_L,
                          const Tables &tabs, int mode, hipStream_t s);
 // Zero the near-peak counts of a batch (after its scratch is allocated).

@@ -634,16 +634,30 @@ psl_status psl_init_walks(psl_ctx *ctx, const psl_walk_cfg *cfg, uint32_t n,
                                     hipMemcpyHostToDevice, ctx->stream));
     }
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    // init plan: entries only (no eval scratch needed), on a temporary plan
+    // init plan: entries and the chunk arrays of the fitness pass, on a
+    // temporary plan
     BatchPlan tmp;
     {
         void *p;
         if ((st = dev_alloc(ctx, &p, sizeof(BatchEntry) * n, false))) return st;
         tmp.d_batch = (BatchEntry *)p;
+        const size_t ns = suffix_len(L);
+        if ((st = dev_alloc(ctx, &p, sizeof(double) * ns * n, false))) {
+            plan_free(ctx, tmp);
+            return st;
+        }
+        tmp.d_s0 = (double *)p;
+        if ((st = dev_alloc(ctx, &p, sizeof(uint32_t) * ns * n, false))) {
+            plan_free(ctx, tmp);
+            return st;
+        }
+        tmp.d_m0 = (uint32_t *)p;
         std::vector<BatchEntry> be(n);
         for (uint32_t b = 0; b < n; ++b) {
             memset(&be[b], 0, sizeof(BatchEntry));
             be[b].slot = ids[b];
+            be[b].S0 = tmp.d_s0 + ns * b;
+            be[b].M0 = tmp.d_m0 + ns * b;
         }
         void *dw;
         if ((st = dev_alloc(ctx, &dw, sizeof(uint32_t) * n, false))) {
@@ -655,7 +669,7 @@ psl_status psl_init_walks(psl_ctx *ctx, const psl_walk_cfg *cfg, uint32_t n,
         const Tables tabs = tables_of(ctx);
         hipError_t e = launch_init_bits(ctx->d_walks, tmp.d_batch, (const uint32_t *)dw, n, nw, ctx->stream);
         if (e == hipSuccess) e = launch_corr(ctx->d_walks, tmp.d_batch, n, L, 0, ctx->stream);
-        if (e == hipSuccess) e = launch_fitness(ctx->d_walks, tmp.d_batch, n, tabs, 0, ctx->stream);
+        if (e == hipSuccess) e = launch_suffix(ctx->d_walks, tmp.d_batch, n, L, tabs, 2, ctx->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
         dev_free(ctx, dw, false);
         plan_free(ctx, tmp);

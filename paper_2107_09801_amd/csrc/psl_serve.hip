@@ -40,7 +40,7 @@ size_t scratch_bound(uint32_t L, uint32_t n_lmt)
     const uint64_t tiles = (n_lmt + 64 * kEvalWavesSmall - 1) / (64 * kEvalWavesSmall);
     const uint64_t ks_max = std::max<uint64_t>(1, ((L - 1 + 31) / 32) / (kTileK / 32));
     const uint64_t ks = std::min<uint64_t>(ks_max, (4096 + tiles - 1) / tiles);
-    return (size_t)(12ull * ks * n_lmt + 12ull * n_lmt + 12ull * suffix_len(L) +
+    return (size_t)(12ull * ks * n_lmt + 12ull * n_lmt + 24ull * suffix_len(L) +
                     4ull * (kNearCap + 1) + sizeof(SelPart) * kCombMaxBlocks + sizeof(BatchEntry) +
                     sizeof(EvalItem) * ks * tiles);
 }
@@ -99,6 +99,8 @@ struct Server {
     DevBuf<double> d_fpart, d_f, d_s0;
     DevBuf<uint32_t> d_mpart, d_m0, d_near, d_want;
     DevBuf<SelPart> d_red;
+    DevBuf<double> d_adm_s0;      // chunk arrays of the admitted walks' fitness pass
+    DevBuf<uint32_t> d_adm_m0;
     uint32_t comb_blocks = 1, comb_group = 1;
     DevBuf<int32_t> d_p;
     uint32_t n_items = 0, max_L = 0;
@@ -259,6 +261,10 @@ psl_status Server::admit(char *&sp, char *stage_end)
     psl_status st;
     if ((st = grow(ctx, d_admit, adm.size()))) return st;
     if ((st = grow(ctx, d_want, adm.size()))) return st;
+    size_t n_suf = 0;
+    for (const Job &j : adm) n_suf += suffix_len(j.cfg.L);
+    if ((st = grow(ctx, d_adm_s0, n_suf)) || (st = grow(ctx, d_adm_m0, n_suf))) return st;
+    size_t os = 0;
     uint32_t maxL = 0, maxnw = 0;
     BatchEntry *be = (BatchEntry *)sp;
     sp += sizeof(BatchEntry) * adm.size();
@@ -295,6 +301,9 @@ psl_status Server::admit(char *&sp, char *stage_end)
                                     ctx->stream));
         memset(&be[b], 0, sizeof(BatchEntry));
         be[b].slot = slot;
+        be[b].S0 = d_adm_s0.p + os;
+        be[b].M0 = d_adm_m0.p + os;
+        os += suffix_len(j.cfg.L);
         want[b] = 1;
         maxL = std::max(maxL, j.cfg.L);
         maxnw = std::max(maxnw, h.nw);
@@ -306,7 +315,7 @@ psl_status Server::admit(char *&sp, char *stage_end)
     const Tables tabs = tables_of(ctx);
     HIP_TRY(ctx, launch_init_bits(ctx->d_walks, d_admit.p, d_want.p, n, maxnw, ctx->stream));
     HIP_TRY(ctx, launch_corr(ctx->d_walks, d_admit.p, n, maxL, 0, ctx->stream));
-    HIP_TRY(ctx, launch_fitness(ctx->d_walks, d_admit.p, n, tabs, 0, ctx->stream));
+    HIP_TRY(ctx, launch_suffix(ctx->d_walks, d_admit.p, n, maxL, tabs, 2, ctx->stream));
     for (auto &j : adm) active.push_back(std::move(j));
     dirty = true;
     {
@@ -580,6 +589,8 @@ void serve_shutdown(psl_ctx *ctx)
     release(ctx, s->d_m0);
     release(ctx, s->d_near);
     release(ctx, s->d_red);
+    release(ctx, s->d_adm_s0);
+    release(ctx, s->d_adm_m0);
     release(ctx, s->d_want);
     release(ctx, s->d_p);
     release(ctx, s->d_queues);

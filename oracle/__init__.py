@@ -30,6 +30,7 @@ IMPROVED = 4
 WORSE = 8
 SWITCHED = 16
 PSL_IMPROVED = 32
+SELFCHECK_FAILED = 64
 
 
 def build(verbose: bool = False) -> str:
@@ -83,6 +84,7 @@ def lib() -> ctypes.CDLL:
         "oc_bits_to_seq": (None, [P, cint, P]),
         "oc_seq_to_bits": (None, [P, cint, P]),
         "oc_corr": (None, [P, cint, P]),
+        "oc_check_corr": (cint, [P, P, cint, cint]),
         "oc_psl": (i32, [P, cint]),
         "oc_power_table": (None, [cint, cint, P]),
         "oc_fitness": (dbl, [P, cint, P]),
@@ -146,6 +148,14 @@ def corr(s: np.ndarray) -> np.ndarray:
     C = np.empty(len(s), dtype=np.int32)
     lib().oc_corr(_p(s), len(s), _p(C))
     return C
+
+
+def check_corr(s: np.ndarray, C: np.ndarray, full: bool = False) -> bool:
+    """The identities of Eq. (2) that every C satisfies (and, with full, C
+    equal to Eq. (2) recomputed): the walk's per-step self-check."""
+    s = np.ascontiguousarray(s, dtype=np.int8)
+    C = np.ascontiguousarray(C, dtype=np.int32)
+    return bool(lib().oc_check_corr(_p(s), _p(C), len(s), 1 if full else 0))
 
 
 def psl(C: np.ndarray) -> int:
@@ -257,7 +267,10 @@ class Walk:
         tr = Trace()
         lib().oc_walk_step(self._w, self.tau, self.margin, self.nthreads, force_k,
                            ctypes.byref(tr))
-        return tr.as_dict()
+        d = tr.as_dict()
+        if d["flags"] & SELFCHECK_FAILED:
+            raise RuntimeError(f"oracle walk: C fails its Eq. (2) self-check after step {self.read()['t']}")
+        return d
 
     def read(self) -> dict:
         nw = n_words(self.L)

@@ -227,6 +227,8 @@ enum {
     OC_WORSE = 8,
     OC_SWITCHED = 16,
     OC_PSL_IMPROVED = 32,
+    OC_SELFCHECK_FAILED = 64,  /* C broke an identity of Eq. (2), or differs
+                                  from a from-scratch recomputation */
 };
 
 typedef struct {
@@ -378,8 +380,42 @@ static void walk_switch(oc_walk *w)
     w->q += 1;
 }
 
+/* Identities every C of Eq. (2) satisfies: C_0 = L; C_{L-1} = s_0 s_{L-1};
+ * C_k has the parity of L-k and |C_k| <= L-k; (sum s)^2 = L + 2 sum_{k>=1} C_k
+ * (square the sum and group the products by their distance). With `full`,
+ * C is also compared with Eq. (2) recomputed from the sequence. Returns 1 if
+ * all hold. */
+OC_API int oc_check_corr(const int8_t *s, const int32_t *C, int L, int full)
+{
+    if (C[0] != L || C[L - 1] != (int32_t)s[0] * (int32_t)s[L - 1]) return 0;
+    int64_t sum_s = 0, sum_c = 0;
+    for (int i = 0; i < L; ++i) sum_s += s[i];
+    for (int k = 1; k < L; ++k) {
+        int64_t c = C[k], room = L - k;
+        if (c > room || c < -room || ((c - room) % 2) != 0) return 0;
+        sum_c += c;
+    }
+    if (sum_s * sum_s != (int64_t)L + 2 * sum_c) return 0;
+    if (full) {
+        int32_t *R = (int32_t *)malloc(sizeof(int32_t) * (size_t)L);
+        oc_corr(s, L, R);
+        int same = memcmp(R, C, sizeof(int32_t) * (size_t)L) == 0;
+        free(R);
+        if (!same) return 0;
+    }
+    return 1;
+}
+
+static int walk_check_corr(const oc_walk *w, int full)
+{
+    return oc_check_corr(w->pivot, w->C, w->L, full);
+}
+
 /* One iteration of the while loop of Algorithm 1. `force_k` >= 0 replaces
- * the chosen move (used only to follow a decision taken elsewhere). */
+ * the chosen move (used only to follow a decision taken elsewhere). After the
+ * step the walk checks its C against the identities of Eq. (2), and every
+ * 64 steps against a from-scratch recomputation; a failure sets
+ * OC_SELFCHECK_FAILED. */
 OC_API void oc_walk_step(oc_walk *w, double tau, double margin, int nthreads,
                          int32_t force_k, oc_trace *tr)
 {
@@ -444,6 +480,7 @@ OC_API void oc_walk_step(oc_walk *w, double tau, double margin, int nthreads,
         flags |= OC_SWITCHED;
     }
     w->t += 1;
+    if (!walk_check_corr(w, (w->t % 64) == 0)) flags |= OC_SELFCHECK_FAILED;
 
     if (tr) {
         tr->start = start;

@@ -154,3 +154,39 @@ def test_walk_rejects_bad_config():
         oracle.Walk(oracle.WalkConfig(L=10, seed=0, n_lmt=11))
     with pytest.raises(ValueError):
         oracle.Walk(oracle.WalkConfig(L=10, seed=0, alpha1=17))
+
+
+def test_corr_self_check_catches_planted_errors():
+    """The walk's per-step check of C (identities of Eq. (2), plus the full
+    recomputation) accepts a true C and rejects planted mistakes."""
+    rng = np.random.default_rng(11)
+    for L in (2, 3, 17, 64, 101):
+        s = (1 - 2 * rng.integers(0, 2, L)).astype(np.int8)
+        C = np.array(oracle.corr_exact(s), dtype=np.int32)
+        assert oracle.check_corr(s, C) and oracle.check_corr(s, C, full=True)
+        if L < 4:
+            continue
+        bad = C.copy(); bad[0] += 2                 # C_0 != L
+        assert not oracle.check_corr(s, bad)
+        bad = C.copy(); bad[L - 1] = -bad[L - 1]    # wrong end term
+        assert not oracle.check_corr(s, bad)
+        bad = C.copy(); bad[2] += 1                 # parity of L-k broken
+        assert not oracle.check_corr(s, bad)
+        bad = C.copy(); bad[1] += 2                 # sum identity broken
+        if abs(bad[1]) <= L - 1:
+            assert not oracle.check_corr(s, bad)
+        # a change the identities cannot see: +2 at one shift, -2 at another
+        bad = C.copy(); k1, k2 = 1, 3
+        if abs(C[k1] + 2) <= L - k1 and abs(C[k2] - 2) <= L - k2:
+            bad[k1] += 2; bad[k2] -= 2
+            assert oracle.check_corr(s, bad)
+            assert not oracle.check_corr(s, bad, full=True)
+
+
+def test_walk_runs_its_self_check_past_64_steps():
+    L = 40
+    w = oracle.Walk(oracle.WalkConfig(L=L, seed=5, alpha1=4, alpha2=13, n_lmt=L, flip_lmt=3,
+                                      switch_period=7))
+    for _ in range(130):
+        tr = w.step()
+        assert not tr["flags"] & oracle.SELFCHECK_FAILED

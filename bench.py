@@ -98,6 +98,8 @@ def parse():
                     help="N_lmt of served jobs (min(L, this))")
     ap.add_argument("--compare-jobs", type=int, default=48,
                     help="jobs in the served vs one-walk-per-launch comparison (0: skip)")
+    ap.add_argument("--compare-uneven-steps", type=int, default=2,
+                    help="uneven workload: steps of the batch-vs-one-walk-per-launch comparison (0 = off)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before the run, one device-to-device copy of this many MiB "
                          "(a known-size kernel to scale profiler byte counters)")
@@ -247,6 +249,58 @@ def run_compare(libpsl, n: int, nlmt_cap: int) -> dict:
             "speedup": t_solo / t_served, "results_identical": same}
 
 
+def run_uneven_compare(libpsl, groups, steps: int, period: int) -> dict:
+    """The uneven batch stepped in one launch sequence per step against every
+    walk stepped alone (one launch sequence per walk), from the same seeds:
+    wall time of `steps` steps each way, and whether every walk ends in the
+    same state."""
+    import torch
+
+    import seeded_inputs as si
+    ctx = libpsl.Context(0)
+    batch, alone, base = [], [], 0
+    for L, count in groups:
+        kw = dict(alpha1=4, alpha2=si.alpha2_for(L), n_lmt=L, ls_lmt=2000, flip_lmt=10,
+                  switch_period=period)
+        batch += ctx.init_walks(L, count, si.BASE_SEED + 7 + base, **kw)
+        for b in range(count):
+            alone += ctx.init_walks(L, 1, si.BASE_SEED + 7 + base + b, **kw)
+        base += count
+    # warm single-walk timing per L: one more walk per L (same seed as the
+    # first of its group), stepped alone with a captured graph
+    warm, base = 0.0, 0
+    for L, count in groups:
+        (r,) = ctx.init_walks(L, 1, si.BASE_SEED + 7 + base, alpha1=4, alpha2=si.alpha2_for(L), n_lmt=L,
+                              ls_lmt=2000, flip_lmt=10, switch_period=period)
+        ctx.step_batch([r], 1, blocking=True, graph=True)
+        t0 = time.perf_counter()
+        ctx.step_batch([r], steps, blocking=True, graph=True)
+        warm += count * (time.perf_counter() - t0)
+        ctx.free_walks([r])
+        base += count
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step_batch(batch, steps, blocking=True)
+    t_batch = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for w in alone:
+        ctx.step_batch([w], steps)
+    ctx.sync()
+    t_alone = time.perf_counter() - t0
+    same = True
+    for a, b in zip(alone, batch):
+        ga, gb = ctx.read_walk(a, bits=False, C=False), ctx.read_walk(b, bits=False, C=False)
+        same &= all(ga[k] == gb[k] for k in ("t", "last_k", "psl_best", "psl_pivot", "alpha",
+                                               "unimproved"))
+    ctx.close()
+    return {"walks": len(batch), "steps": steps, "batch_s": t_batch,
+            "one_walk_per_launch_s": t_alone, "speedup": t_alone / t_batch,
+            "one_walk_per_launch_warm_graph_s": warm, "speedup_vs_warm_graph": warm / t_batch,
+            "note": "one_walk_per_launch_s: every walk stepped alone, including its per-walk launch "
+                    "set-up; warm_graph: per L, one walk's captured-graph step time times the walk count",
+            "results_identical": bool(same)}
+
+
 def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -290,6 +344,8 @@ def main():
     L, n_lmt = groups[0][0], (min(groups[0][0], 6912) if wl == "paper" else min(groups[0][0], args.n_lmt or groups[0][0]))
     a2 = 10 if wl == "paper" else si.alpha2_for(L)
     log(f"{nw} walks initialised ({wl})")
+    if wl == "large":   # per-step PSL and psl_best of the walk (trace ring)
+        ctx.trace_enable(ids[0], args.warmup + args.steps)
     if args.calib_copy_mb:
         n = args.calib_copy_mb << 20
         src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
@@ -361,6 +417,9 @@ def main():
                      "traffic_unit": "B/launch"},
         "walk0_after": {"t": st["t"], "psl_best": st["psl_best"], "alpha": st["alpha"]},
     }
+    if wl == "large":
+        out["walk0_trace"] = [{k: e[k] for k in ("t", "psl_k", "psl_best", "value_step", "alpha")}
+                              for e in ctx.trace_read(ids[0], args.warmup + args.steps)]
     if L in PAPER_A100_NSE and len(groups) == 1:
         out["paper_context"] = {"A100_flip_evals_per_s": PAPER_A100_NSE[L],
                                 "note": "paper Table 4: one walk, N_lmt=6912, alpha 4/10"}
@@ -375,6 +434,9 @@ def main():
     if args.compare_jobs > 0:
         log(f"served vs one-walk-per-launch on {args.compare_jobs} jobs")
         out["served_vs_single"] = run_compare(libpsl, args.compare_jobs, args.serve_nlmt)
+    if wl == "uneven" and args.compare_uneven_steps > 0:
+        log(f"uneven batch vs one-walk-per-launch, {args.compare_uneven_steps} step(s)")
+        out["uneven_vs_single"] = run_uneven_compare(libpsl, groups, args.compare_uneven_steps, period)
     if not args.no_cpu_baseline:
         log("timing the oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(L, n_lmt, 4, args.cpu_seconds, nw)

@@ -295,10 +295,11 @@ PSL_API psl_status psl_timing_read(psl_ctx *ctx, psl_timing *out);
 
 /* Launch shape of the neighbourhood evaluation for a batch. */
 typedef struct {
-    int32_t waves;          /* wavefronts per block: 4 (256 candidates) or 8 (512)   */
+    int32_t waves;          /* wavefronts per block: 4, 8 or 16 (64 candidates each) */
     int32_t persistent;     /* 1: a fixed grid of blocks_per_cu x CUs takes work
                                items from per-XCD queues; 0: one block per item     */
-    int32_t blocks_per_cu;  /* resident blocks per CU of the persistent grid (1..3) */
+    int32_t blocks_per_cu;  /* resident blocks per CU of the persistent grid: 1..3
+                               (1..2 for 16 wavefronts)                            */
     int32_t reserved;
     double  eval_ms;        /* measured mean launch time of this shape              */
     double  default_ms;     /* measured mean launch time of the untuned default     */

@@ -12,8 +12,8 @@ namespace psl {
 
 constexpr double kTau = 1e-12;       // relative band of the best-neighbour and
                                      // improvement comparisons
-constexpr int kEvalWaves = 8;        // wavefronts per evaluation block (largest)
-constexpr int kEvalThreads = 64 * kEvalWaves;
+constexpr int kEvalWavesMax = 16;    // wavefronts per evaluation block: 16, 8 or 4
+constexpr int kEvalWaves = 8;        // the default for large neighbourhoods
 constexpr int kEvalWavesSmall = 4;   // blocks for batches of small neighbourhoods
 constexpr int kTileK = 256;          // shifts staged per LDS tile
 constexpr int kChunks = kTileK / 32; // 32-shift windows per tile

@@ -182,6 +182,7 @@ EvalShape pick_shape(const psl_ctx *ctx, const uint32_t *Ls, const uint32_t *n_l
 void eval_layout(const uint32_t *Ls, const uint32_t *n_lmt, uint32_t n, const EvalShape &shape,
                  EvalLayout &out);
 void eval_shape_k(uint32_t L, uint32_t n_lmt, uint32_t K, uint32_t tile, uint32_t *tiles, uint32_t *ksplit);
+uint32_t max_blocks_per_cu(int waves);
 int eval_waves(const uint32_t *n_lmt, uint32_t n);
 psl_status check_cfg(psl_ctx *ctx, const psl_walk_cfg *c);
 psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t n, uint32_t n_fixed,

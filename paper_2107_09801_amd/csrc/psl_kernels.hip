@@ -443,10 +443,10 @@ struct EvalLds {
     double one[kChunks * kOneWin];      // quad sums, one neighbour
     uint32_t both_max[kPairs * 16];     // max hi32 of the pair (dense PSL only)
     uint32_t one_max[kChunks * kOneWin];
-    uint32_t bits[kEvalWaves * 64];     // per wavefront: its pivot words of the tile
-    int kend[kEvalWaves];               // per wavefront (up to kEvalWaves)
-    int bmax[kEvalWaves];
-    int omax[kEvalWaves];
+    uint32_t bits[kEvalWavesMax * 64];  // per wavefront: its pivot words of the tile
+    int kend[kEvalWavesMax];            // per wavefront
+    int bmax[kEvalWavesMax];
+    int omax[kEvalWavesMax];
 };
 
 // The sweep of one item. kMax: keep the PSL maximum in the main loop (dense
@@ -739,7 +739,7 @@ __device__ __forceinline__ void eval_item(EvalLds &sh, const WalkDev *__restrict
 // blocks per CU, i.e. 3 * WAVES / 4 wavefronts per SIMD; ask the compiler to
 // keep the VGPR count low enough for that.
 template <int WAVES>
-constexpr int kEvalWavesPerEU = WAVES * 3 / 4 > 0 ? WAVES * 3 / 4 : 1;
+constexpr int kEvalWavesPerEU = WAVES * 3 / 4 < 1 ? 1 : WAVES * 3 / 4 > 8 ? 8 : WAVES * 3 / 4;
 
 // One block per work item; items are laid out as 8 equal-cost XCD ranges
 // padded to equal length.
@@ -1155,18 +1155,22 @@ hipError_t launch_eval(const WalkDev *walks, const BatchEntry *batch, const Eval
                        uint32_t n_items, const Tables &tabs, const EvalShape &shape,
                        EvalQueues *queues, hipStream_t s)
 {
+    if (shape.waves != 4 && shape.waves != 8 && shape.waves != 16) return hipErrorInvalidValue;
     if (shape.persistent) {
         k_queue_reset<<<1, 64, 0, s>>>(queues);
         const uint32_t grid = shape.grid;
-        if (shape.waves == kEvalWavesSmall)
-            k_eval_persistent<kEvalWavesSmall><<<grid, 64 * kEvalWavesSmall, 0, s>>>(walks, batch, items,
-                                                                                    tabs, queues);
+        if (shape.waves == 4)
+            k_eval_persistent<4><<<grid, 64 * 4, 0, s>>>(walks, batch, items, tabs, queues);
+        else if (shape.waves == 8)
+            k_eval_persistent<8><<<grid, 64 * 8, 0, s>>>(walks, batch, items, tabs, queues);
         else
-            k_eval_persistent<kEvalWaves><<<grid, kEvalThreads, 0, s>>>(walks, batch, items, tabs, queues);
-    } else if (shape.waves == kEvalWavesSmall) {
-        k_eval<kEvalWavesSmall><<<n_items, 64 * kEvalWavesSmall, 0, s>>>(walks, batch, items, tabs);
+            k_eval_persistent<16><<<grid, 64 * 16, 0, s>>>(walks, batch, items, tabs, queues);
+    } else if (shape.waves == 4) {
+        k_eval<4><<<n_items, 64 * 4, 0, s>>>(walks, batch, items, tabs);
+    } else if (shape.waves == 8) {
+        k_eval<8><<<n_items, 64 * 8, 0, s>>>(walks, batch, items, tabs);
     } else {
-        k_eval<kEvalWaves><<<n_items, kEvalThreads, 0, s>>>(walks, batch, items, tabs);
+        k_eval<16><<<n_items, 64 * 16, 0, s>>>(walks, batch, items, tabs);
     }
     return hipGetLastError();
 }

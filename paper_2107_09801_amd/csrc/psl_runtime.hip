@@ -161,15 +161,29 @@ bool walk_ok(const psl_ctx *ctx, uint32_t id)
 
 // Evaluation shape of a batch. Candidates go in tiles of one block (64 lanes
 // per wavefront; 4 wavefronts when most walks evaluate at most 256
-// candidates, else 8); the shifts of a walk split into pieces of about
+// candidates, 16 for batches of at least 256 x 1024 candidates, else 8); the shifts of a walk split into pieces of about
 // K = max(kTileK, W / 4096) shifts, where W is the batch's total
 // (tile x shift) work, so a batch offers at least about 4096 work items and
 // no item is much longer than the batch's average.
+// Evaluation blocks resident per CU: the LDS of a block admits three; 16
+// wavefronts per block are limited to two by the CU's wavefront slots.
+uint32_t max_blocks_per_cu(int waves)
+{
+    return waves >= kEvalWavesMax ? 2u : 3u;
+}
+
 int eval_waves(const uint32_t *nl, uint32_t n)
 {
     uint32_t small = 0;
-    for (uint32_t b = 0; b < n; ++b) small += nl[b] <= 64u * kEvalWavesSmall;
-    return 2 * small > n ? kEvalWavesSmall : kEvalWaves;
+    uint64_t total = 0;
+    for (uint32_t b = 0; b < n; ++b) {
+        small += nl[b] <= 64u * kEvalWavesSmall;
+        total += nl[b];
+    }
+    if (2 * small > n) return kEvalWavesSmall;
+    // 16 wavefronts halve the per-candidate cost of building the LDS tables
+    // once a batch has candidates for at least 256 such blocks
+    return total >= 256ull * 64 * kEvalWavesMax ? kEvalWavesMax : kEvalWaves;
 }
 
 static uint32_t item_shifts(const uint32_t *Ls, const uint32_t *nl, uint32_t n, uint32_t tile)
@@ -215,7 +229,7 @@ EvalShape pick_shape(const psl_ctx *ctx, const uint32_t *Ls, const uint32_t *nl,
         lmin = std::min(lmin, Ls[b]);
     }
     sh.persistent = lmax > 4ull * lmin ? 1 : 0;
-    sh.grid = sh.persistent ? 3 * ctx->n_cu : 0;
+    sh.grid = sh.persistent ? max_blocks_per_cu(sh.waves) * ctx->n_cu : 0;
     return sh;
 }
 
@@ -899,11 +913,11 @@ psl_status psl_autotune(psl_ctx *ctx, const uint32_t *walk_ids, uint32_t n, psl_
     ctx->tuned.erase(key);
     const EvalShape def = pick_shape(ctx, Ls.data(), nl.data(), n);
     std::vector<EvalShape> cands;
-    for (int waves : {kEvalWaves, kEvalWavesSmall}) {
+    for (int waves : {kEvalWavesMax, kEvalWaves, kEvalWavesSmall}) {
         EvalShape f;
         f.waves = waves;
         cands.push_back(f);
-        for (uint32_t bpc = 1; bpc <= 3; ++bpc) {
+        for (uint32_t bpc = 1; bpc <= max_blocks_per_cu(waves); ++bpc) {
             EvalShape q;
             q.waves = waves;
             q.persistent = 1;
@@ -985,8 +999,8 @@ psl_status psl_tune_load(psl_ctx *ctx, const char *path)
     int waves, pers;
     int r;
     while ((r = fscanf(f, "%u %d %d %u", &key, &waves, &pers, &bpc)) == 4) {
-        if ((waves != kEvalWaves && waves != kEvalWavesSmall) || (pers != 0 && pers != 1) ||
-            (pers && (bpc < 1 || bpc > 3))) {
+        if ((waves != kEvalWavesMax && waves != kEvalWaves && waves != kEvalWavesSmall) ||
+            (pers != 0 && pers != 1) || (pers && (bpc < 1 || bpc > max_blocks_per_cu(waves)))) {
             fclose(f);
             return fail(ctx, PSL_E_INVAL, "bad tuning line in %s", path);
         }

@@ -104,6 +104,7 @@ struct BatchPlan {
     uint32_t *d_mpart = nullptr, *d_m0 = nullptr, *d_near = nullptr;
     int32_t *d_p = nullptr;
     SelPart *d_red = nullptr;
+    uint32_t *d_pend = nullptr;       // pending list: count, then batch positions
 };
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }

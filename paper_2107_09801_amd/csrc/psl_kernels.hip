@@ -177,37 +177,88 @@ __global__ __launch_bounds__(kCorrThreads) void k_corr(WalkDev *walks, const Bat
     }
 }
 
-// After a switch: C of (local_best with the Rand_flip positions flipped),
-// from C of local_best by one one-element flip per position, in draw order.
-// Flip f sees the elements of local_best with positions 0..f-1 flipped.
-__global__ void k_switch_corr(WalkDev *walks, const BatchEntry *batch)
+// The pending list of a batch: pend[0] = count, pend[1..] = batch positions
+// of the walks whose step ended in a phase switch (k_bookkeep appends,
+// k_select of the next step clears the count).
+//
+// C of a switched pivot from C of local_best: the FLIP_lmt one-element flips
+// in draw order, where flip f sees local_best with flips 0..f-1 applied.
+// Element x of that sequence differs from local_best only if x is an earlier
+// flip position, and flip f reads elements p_f and p_f +- k; so for every k
+// outside D = {|p_f - p_g| : g < f} the update can read local_best's bits
+// directly. k_switch_corr does that for all k (all blocks work through the
+// pending walks in turn); k_switch_fix then recomputes the shifts in D with
+// the sequential bits (one block per pending walk, one thread per pair).
+__device__ __forceinline__ int32_t switch_flip_delta(const uint64_t *lb, uint32_t L, uint32_t k, uint32_t p)
 {
-    WalkDev &w = walks[batch[blockIdx.y].slot];
-    if (!w.pending || w.n_flips > kFlipIncremental) return;
-    const uint32_t L = w.L;
-    const uint32_t nf = w.n_flips;
-    const uint64_t *lb = w.local_best;
-    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < L; k += gridDim.x * blockDim.x) {
-    if (k == 0) {
-        w.C[0] = (int32_t)L;
-        continue;
+    const int sp = get_bit(lb, p) ? -1 : 1;
+    int d = 0;
+    if (p + k < L) d += get_bit(lb, p + k) ? -1 : 1;
+    if (k <= p) d += get_bit(lb, p - k) ? -1 : 1;
+    return -2 * sp * d;
+}
+
+__global__ __launch_bounds__(256) void k_switch_corr(WalkDev *walks, const BatchEntry *batch,
+                                                     const uint32_t *pend)
+{
+    __shared__ uint32_t s_fl[kFlipIncremental];
+    const uint32_t np = pend[0];
+    for (uint32_t q = 0; q < np; ++q) {
+        WalkDev &w = walks[batch[pend[1 + q]].slot];
+        const uint32_t nf = w.n_flips;
+        if (nf > kFlipIncremental) continue;      // rebuilt by k_corr
+        __syncthreads();
+        if (threadIdx.x < nf) s_fl[threadIdx.x] = w.flips[threadIdx.x];
+        __syncthreads();
+        const uint32_t L = w.L;
+        const uint64_t *lb = w.local_best;
+        for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < L; k += gridDim.x * blockDim.x) {
+            if (k == 0) {
+                w.C[0] = (int32_t)L;
+                continue;
+            }
+            int32_t c = w.C_lb[k];
+            for (uint32_t f = 0; f < nf; ++f) c += switch_flip_delta(lb, L, k, s_fl[f]);
+            w.C[k] = c;
+        }
     }
-    int32_t c = w.C_lb[k];
-    for (uint32_t f = 0; f < nf; ++f) {
-        const uint32_t p = w.flips[f];
-        // element x of the sequence after flips 0..f-1: -1 iff bit set
-        auto bit = [&](uint32_t x) {
-            uint32_t b = get_bit(lb, x);
-            for (uint32_t g = 0; g < f; ++g) b ^= (w.flips[g] == x) ? 1u : 0u;
-            return b;
-        };
-        const int sp = bit(p) ? -1 : 1;
-        int d = 0;
-        if (p + k < L) d += bit(p + k) ? -1 : 1;
-        if (k <= p) d += bit(p - k) ? -1 : 1;
-        c -= 2 * sp * d;
-    }
-    w.C[k] = c;
+}
+
+__global__ __launch_bounds__(256) void k_switch_fix(WalkDev *walks, const BatchEntry *batch,
+                                                    const uint32_t *pend)
+{
+    __shared__ uint32_t s_fl[kFlipIncremental];
+    const uint32_t np = pend[0];
+    for (uint32_t q = blockIdx.x; q < np; q += gridDim.x) {
+        WalkDev &w = walks[batch[pend[1 + q]].slot];
+        const uint32_t nf = w.n_flips;
+        if (nf > kFlipIncremental) continue;
+        __syncthreads();
+        if (threadIdx.x < nf) s_fl[threadIdx.x] = w.flips[threadIdx.x];
+        __syncthreads();
+        const uint32_t L = w.L;
+        const uint64_t *lb = w.local_best;
+        for (uint32_t pr = threadIdx.x; pr < nf * nf; pr += blockDim.x) {
+            const uint32_t f = pr / nf, g = pr - f * nf;
+            if (g >= f) continue;
+            const uint32_t k = s_fl[f] > s_fl[g] ? s_fl[f] - s_fl[g] : s_fl[g] - s_fl[f];
+            // element x after flips 0..h-1
+            auto bit = [&](uint32_t x, uint32_t h) {
+                uint32_t v = get_bit(lb, x);
+                for (uint32_t e = 0; e < h; ++e) v ^= (s_fl[e] == x) ? 1u : 0u;
+                return v;
+            };
+            int32_t c = w.C_lb[k];
+            for (uint32_t h = 0; h < nf; ++h) {
+                const uint32_t p = s_fl[h];
+                const int sp = bit(p, h) ? -1 : 1;
+                int d = 0;
+                if (p + k < L) d += bit(p + k, h) ? -1 : 1;
+                if (k <= p) d += bit(p - k, h) ? -1 : 1;
+                c -= 2 * sp * d;
+            }
+            w.C[k] = c;
+        }
     }
 }
 
@@ -281,11 +332,14 @@ __global__ __launch_bounds__(kFitThreads) void k_fitness(WalkDev *walks, const B
 constexpr int kChunkThreads = 256;
 constexpr uint32_t kMaxGridY = 65535;      // walks per launch of the 2-D grids
 __global__ __launch_bounds__(kChunkThreads) void k_chunks(const WalkDev *walks, const BatchEntry *batch,
-                                                          Tables tabs, int mode)
+                                                          Tables tabs, int mode, const uint32_t *pend)
 {
-    const BatchEntry be = batch[blockIdx.y];
+    // mode 1: the whole grid works through the pending walks in turn;
+    // otherwise blockIdx.y is the walk
+    const uint32_t nq = mode == 1 ? pend[0] : 1;
+    for (uint32_t qi = 0; qi < nq; ++qi) {
+    const BatchEntry be = batch[mode == 1 ? pend[1 + qi] : blockIdx.y];
     const WalkDev &w = walks[be.slot];
-    if (mode == 1 && !w.pending) return;
     const int L = (int)w.L;
     const double *T = tabs.T[w.alpha];
     const int nchunks = (L - 1 + 31) / 32;
@@ -326,14 +380,20 @@ __global__ __launch_bounds__(kChunkThreads) void k_chunks(const WalkDev *walks, 
             }
         }
     }
+    }
 }
 
 constexpr int kScanThreads = 1024;
-__global__ __launch_bounds__(kScanThreads) void k_scan(WalkDev *walks, const BatchEntry *batch, int mode)
+__global__ __launch_bounds__(kScanThreads) void k_scan(WalkDev *walks, const BatchEntry *batch, int mode,
+                                                      const uint32_t *pend)
 {
-    const BatchEntry be = batch[blockIdx.x];
+    // mode 1: block g takes pending walks g, g + gridDim.x, ...; otherwise
+    // blockIdx.x is the walk
+    const uint32_t nq = mode == 1 ? pend[0] : blockIdx.x + 1;
+    for (uint32_t qi = blockIdx.x; qi < nq; qi += gridDim.x) {
+    __syncthreads();
+    const BatchEntry be = batch[mode == 1 ? pend[1 + qi] : qi];
     WalkDev &w = walks[be.slot];
-    if (mode == 1 && !w.pending) return;
     const int L = (int)w.L;
     const int nchunks = (L - 1 + 31) / 32;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -415,6 +475,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(WalkDev *walks, const Bat
                 w.psl_best = (int32_t)tm;
             }
         }
+    }
     }
 }
 
@@ -885,8 +946,12 @@ __global__ __launch_bounds__(kCombThreads) void k_combine(const WalkDev *walks, 
 // Otherwise record the choice in the walk and, on a strict PSL improvement,
 // update psl_best and solution_best = pivot with j_psl flipped.
 __global__ __launch_bounds__(kSelThreads) void k_select(WalkDev *walks, const BatchEntry *batch,
-                                                        uint32_t comb_blocks, int pure, ChoiceDev *out)
+                                                        uint32_t comb_blocks, int pure, ChoiceDev *out,
+                                                        uint32_t *pend)
 {
+    // the previous step's pending list has been consumed; this step's
+    // bookkeeping refills it
+    if (pend && blockIdx.x == 0 && threadIdx.x == 0) pend[0] = 0;
     const BatchEntry be = batch[blockIdx.x];
     WalkDev &w = walks[be.slot];
     const uint32_t n = be.fixed ? be.n_lmt : w.n_lmt;
@@ -1035,7 +1100,8 @@ constexpr int kBookThreads = 256;
 // the local best, and the phase switch (Rand_flip of the local best and the
 // exponent swap; C, F and PSL of the new pivot are rebuilt by k_corr and
 // k_fitness on walks left pending).
-__global__ __launch_bounds__(kBookThreads) void k_bookkeep(WalkDev *walks, const BatchEntry *batch)
+__global__ __launch_bounds__(kBookThreads) void k_bookkeep(WalkDev *walks, const BatchEntry *batch,
+                                                           uint32_t *pend)
 {
     WalkDev &w = walks[batch[blockIdx.x].slot];
     __shared__ int s_improved, s_switch;
@@ -1101,6 +1167,7 @@ __global__ __launch_bounds__(kBookThreads) void k_bookkeep(WalkDev *walks, const
             w.alpha = (w.alpha == w.alpha1) ? w.alpha2 : w.alpha1;
             w.q += 1;
             w.pending = 1;
+            pend[1 + atomicAdd(&pend[0], 1u)] = blockIdx.x;
         }
     }
 }
@@ -1138,9 +1205,15 @@ hipError_t launch_corr(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uin
 }
 
 hipError_t launch_switch_corr(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t max_L,
-                              hipStream_t s)
+                              const uint32_t *pend, hipStream_t s)
 {
-    k_switch_corr<<<dim3(lin_blocks(max_L, nb), nb), 256, 0, s>>>(walks, batch);
+    // the pending walks one after another over about 2048 blocks, then the
+    // shifts whose bits an earlier flip of the same switch changed
+    const uint32_t bx = std::max<uint32_t>(1, std::min<uint32_t>(2048, (max_L + 255) / 256));
+    k_switch_corr<<<bx, 256, 0, s>>>(walks, batch, pend);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_switch_fix<<<std::min<uint32_t>(nb, 256), 256, 0, s>>>(walks, batch, pend);
     return hipGetLastError();
 }
 
@@ -1176,36 +1249,49 @@ hipError_t launch_eval(const WalkDev *walks, const BatchEntry *batch, const Eval
 }
 
 hipError_t launch_suffix(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t max_L,
-                         const Tables &tabs, int mode, hipStream_t s)
+                         const Tables &tabs, int mode, const uint32_t *pend, hipStream_t s)
 {
+    const uint32_t nchunks = (max_L - 1 + 31) / 32;
+    if (mode == 1) {
+        // the pending walks of the batch, one after another over the grid
+        if (!pend) return hipErrorInvalidValue;
+        const uint32_t bx = std::max<uint32_t>(1, std::min<uint32_t>(1024, (nchunks + 7) / 8));
+        k_chunks<<<dim3(bx, 1), kChunkThreads, 0, s>>>(walks, batch, tabs, mode, pend);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        k_scan<<<std::min<uint32_t>(nb, 256), kScanThreads, 0, s>>>(walks, batch, mode, pend);
+        return hipGetLastError();
+    }
     // about 2048 blocks over the batch, at most one per 8 chunks of the
     // longest walk
-    const uint32_t nchunks = (max_L - 1 + 31) / 32;
     const uint32_t per_walk = std::max<uint32_t>(1, (2048 + nb - 1) / nb);
     const uint32_t bx = std::max<uint32_t>(1, std::min(per_walk, (nchunks + 7) / 8));
     for (uint32_t b0 = 0; b0 < nb; b0 += kMaxGridY) {
-        k_chunks<<<dim3(bx, std::min(kMaxGridY, nb - b0)), kChunkThreads, 0, s>>>(walks, batch + b0, tabs, mode);
+        k_chunks<<<dim3(bx, std::min(kMaxGridY, nb - b0)), kChunkThreads, 0, s>>>(walks, batch + b0, tabs, mode,
+                                                                                  nullptr);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    k_scan<<<nb, kScanThreads, 0, s>>>(walks, batch, mode);
+    k_scan<<<nb, kScanThreads, 0, s>>>(walks, batch, mode, nullptr);
     return hipGetLastError();
 }
 
-__global__ void k_near_reset(const BatchEntry *batch, uint32_t nb)
+__global__ void k_near_reset(const BatchEntry *batch, uint32_t nb, uint32_t *pend)
 {
     const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b < nb) batch[b].near[0] = 0;
+    if (b == 0 && pend) pend[0] = 0;
 }
 
-hipError_t launch_near_reset(const BatchEntry *batch, uint32_t nb, hipStream_t s)
+hipError_t launch_near_reset(const BatchEntry *batch, uint32_t nb, uint32_t *pend, hipStream_t s)
 {
-    k_near_reset<<<(nb + 255) / 256, 256, 0, s>>>(batch, nb);
+    k_near_reset<<<(nb + 255) / 256, 256, 0, s>>>(batch, nb, pend);
     return hipGetLastError();
 }
 
 hipError_t launch_select(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t comb_blocks,
-                         uint32_t comb_group, const Tables &tabs, int pure, void *out, hipStream_t s)
+                         uint32_t comb_group, const Tables &tabs, int pure, void *out, uint32_t *pend,
+                         hipStream_t s)
 {
     if (comb_blocks < 1 || comb_blocks > kCombMaxBlocks) return hipErrorInvalidValue;
     if (comb_group < 1 || comb_group > 64 || (comb_group & (comb_group - 1))) return hipErrorInvalidValue;
@@ -1215,7 +1301,7 @@ hipError_t launch_select(WalkDev *walks, const BatchEntry *batch, uint32_t nb, u
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    k_select<<<nb, kSelThreads, 0, s>>>(walks, batch, comb_blocks, pure, (ChoiceDev *)out);
+    k_select<<<nb, kSelThreads, 0, s>>>(walks, batch, comb_blocks, pure, (ChoiceDev *)out, pend);
     return hipGetLastError();
 }
 
@@ -1243,9 +1329,10 @@ hipError_t launch_flip_bit(WalkDev *walks, const BatchEntry *batch, uint32_t j, 
     return hipGetLastError();
 }
 
-hipError_t launch_bookkeep(WalkDev *walks, const BatchEntry *batch, uint32_t nb, hipStream_t s)
+hipError_t launch_bookkeep(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t *pend, hipStream_t s)
 {
-    k_bookkeep<<<nb, kBookThreads, 0, s>>>(walks, batch);
+    if (!pend) return hipErrorInvalidValue;
+    k_bookkeep<<<nb, kBookThreads, 0, s>>>(walks, batch, pend);
     return hipGetLastError();
 }
 

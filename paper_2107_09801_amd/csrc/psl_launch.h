@@ -10,8 +10,9 @@ hipError_t launch_init_bits(WalkDev *walks, const BatchEntry *batch, const uint3
                             uint32_t nb, uint32_t max_nw, hipStream_t s);
 hipError_t launch_corr(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t max_L,
                        int only_pending, hipStream_t s);
+// pend: the batch's pending list (count, then batch positions).
 hipError_t launch_switch_corr(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t max_L,
-                              hipStream_t s);
+                              const uint32_t *pend, hipStream_t s);
 hipError_t launch_fitness(WalkDev *walks, const BatchEntry *batch, uint32_t nb, const Tables &tabs,
                           int mode, hipStream_t s);
 hipError_t launch_eval(const WalkDev *walks, const BatchEntry *batch, const EvalItem *items,
@@ -21,17 +22,19 @@ hipError_t launch_eval(const WalkDev *walks, const BatchEntry *batch, const Eval
 // fitness of pending walks after a phase switch; mode 2: the initial fitness
 // (value_local, F_pivot, psl_pivot, psl_best) of every walk.
 hipError_t launch_suffix(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t max_L,
-                         const Tables &tabs, int mode, hipStream_t s);
-// Zero the near-peak counts of a batch (after its scratch is allocated).
-hipError_t launch_near_reset(const BatchEntry *batch, uint32_t nb, hipStream_t s);
+                         const Tables &tabs, int mode, const uint32_t *pend, hipStream_t s);
+// Zero the near-peak counts of a batch and its pending count (after its
+// scratch is allocated).
+hipError_t launch_near_reset(const BatchEntry *batch, uint32_t nb, uint32_t *pend, hipStream_t s);
 hipError_t launch_select(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t comb_blocks,
-                         uint32_t comb_group, const Tables &tabs, int pure, void *out, hipStream_t s);
+                         uint32_t comb_group, const Tables &tabs, int pure, void *out, uint32_t *pend,
+                         hipStream_t s);
 size_t choice_dev_size();
 void choice_dev_unpack(const void *p, uint32_t *i_best, uint32_t *j_best, double *F_best,
                        double *F_min, uint32_t *j_psl, int32_t *psl_min, int32_t *psl_k);
 hipError_t launch_apply(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t max_L,
                         int64_t j_fixed, hipStream_t s);
 hipError_t launch_flip_bit(WalkDev *walks, const BatchEntry *batch, uint32_t j, hipStream_t s);
-hipError_t launch_bookkeep(WalkDev *walks, const BatchEntry *batch, uint32_t nb, hipStream_t s);
+hipError_t launch_bookkeep(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t *pend, hipStream_t s);
 
 }  // namespace psl

@@ -89,6 +89,7 @@ void plan_free(psl_ctx *ctx, BatchPlan &pl)
     dev_free(ctx, pl.d_s0, false);
     dev_free(ctx, pl.d_m0, false);
     dev_free(ctx, pl.d_red, false);
+    dev_free(ctx, pl.d_pend, false);
     dev_free(ctx, pl.d_near, false);
     dev_free(ctx, pl.d_queues, false);
     pl = BatchPlan();
@@ -356,6 +357,8 @@ psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t 
     pl.d_near = (uint32_t *)p;
     if ((st = dev_alloc(ctx, &p, sizeof(SelPart) * pl.comb_blocks * n, false))) return st;
     pl.d_red = (SelPart *)p;
+    if ((st = dev_alloc(ctx, &p, sizeof(uint32_t) * (n + 1), false))) return st;
+    pl.d_pend = (uint32_t *)p;
     std::vector<BatchEntry> be(n);
     size_t op = 0, oc = 0, os = 0;
     for (uint32_t b = 0; b < n; ++b) {
@@ -390,7 +393,7 @@ psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t 
     HIP_TRY(ctx, hipMemcpy(pl.d_batch, be.data(), sizeof(BatchEntry) * n, hipMemcpyHostToDevice));
     HIP_TRY(ctx, hipMemcpy(pl.d_items, items.data(), sizeof(EvalItem) * items.size(),
                            hipMemcpyHostToDevice));
-    HIP_TRY(ctx, launch_near_reset(pl.d_batch, n, ctx->stream));
+    HIP_TRY(ctx, launch_near_reset(pl.d_batch, n, pl.d_pend, ctx->stream));
     pl.n_items = (uint32_t)items.size();
     return PSL_OK;
 }
@@ -452,18 +455,18 @@ psl_status check_cfg(psl_ctx *ctx, const psl_walk_cfg *c)
 psl_status launch_step(psl_ctx *ctx, const BatchPlan &pl, const Tables &tabs, uint32_t n, bool timed)
 {
     psl_status st;
-    HIP_TRY(ctx, launch_suffix(ctx->d_walks, pl.d_batch, n, pl.max_L, tabs, 0, ctx->stream));
+    HIP_TRY(ctx, launch_suffix(ctx->d_walks, pl.d_batch, n, pl.max_L, tabs, 0, nullptr, ctx->stream));
     if (timed && (st = timing_mark(ctx))) return st;
     HIP_TRY(ctx, launch_eval(ctx->d_walks, pl.d_batch, pl.d_items, pl.n_items, tabs, pl.shape, pl.d_queues,
                              ctx->stream));
     if (timed && (st = timing_mark(ctx))) return st;
     HIP_TRY(ctx, launch_select(ctx->d_walks, pl.d_batch, n, pl.comb_blocks, pl.comb_group, tabs, 0, nullptr,
-                               ctx->stream));
+                               pl.d_pend, ctx->stream));
     HIP_TRY(ctx, launch_apply(ctx->d_walks, pl.d_batch, n, pl.max_L, -1, ctx->stream));
-    HIP_TRY(ctx, launch_bookkeep(ctx->d_walks, pl.d_batch, n, ctx->stream));
-    HIP_TRY(ctx, launch_switch_corr(ctx->d_walks, pl.d_batch, n, pl.max_L, ctx->stream));
+    HIP_TRY(ctx, launch_bookkeep(ctx->d_walks, pl.d_batch, n, pl.d_pend, ctx->stream));
+    HIP_TRY(ctx, launch_switch_corr(ctx->d_walks, pl.d_batch, n, pl.max_L, pl.d_pend, ctx->stream));
     if (pl.big_flips) HIP_TRY(ctx, launch_corr(ctx->d_walks, pl.d_batch, n, pl.max_L, 1, ctx->stream));
-    HIP_TRY(ctx, launch_suffix(ctx->d_walks, pl.d_batch, n, pl.max_L, tabs, 1, ctx->stream));
+    HIP_TRY(ctx, launch_suffix(ctx->d_walks, pl.d_batch, n, pl.max_L, tabs, 1, pl.d_pend, ctx->stream));
     if (timed && (st = timing_mark(ctx))) return st;
     return PSL_OK;
 }
@@ -683,7 +686,7 @@ psl_status psl_init_walks(psl_ctx *ctx, const psl_walk_cfg *cfg, uint32_t n,
         const Tables tabs = tables_of(ctx);
         hipError_t e = launch_init_bits(ctx->d_walks, tmp.d_batch, (const uint32_t *)dw, n, nw, ctx->stream);
         if (e == hipSuccess) e = launch_corr(ctx->d_walks, tmp.d_batch, n, L, 0, ctx->stream);
-        if (e == hipSuccess) e = launch_suffix(ctx->d_walks, tmp.d_batch, n, L, tabs, 2, ctx->stream);
+        if (e == hipSuccess) e = launch_suffix(ctx->d_walks, tmp.d_batch, n, L, tabs, 2, nullptr, ctx->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
         dev_free(ctx, dw, false);
         plan_free(ctx, tmp);
@@ -729,11 +732,11 @@ psl_status psl_eval_neighbourhood(psl_ctx *ctx, uint32_t walk, uint32_t start, u
     psl_status st = make_plan(ctx, ctx->pure, &walk, 1, n_lmt, start);
     if (st) return st;
     const Tables tabs = tables_of(ctx);
-    HIP_TRY(ctx, launch_suffix(ctx->d_walks, ctx->pure.d_batch, 1, h.L, tabs, 0, ctx->stream));
+    HIP_TRY(ctx, launch_suffix(ctx->d_walks, ctx->pure.d_batch, 1, h.L, tabs, 0, nullptr, ctx->stream));
     HIP_TRY(ctx, launch_eval(ctx->d_walks, ctx->pure.d_batch, ctx->pure.d_items, ctx->pure.n_items,
                              tabs, ctx->pure.shape, ctx->pure.d_queues, ctx->stream));
     HIP_TRY(ctx, launch_select(ctx->d_walks, ctx->pure.d_batch, 1, ctx->pure.comb_blocks, ctx->pure.comb_group, tabs, 1,
-                               ctx->d_choice,
+                               ctx->d_choice, nullptr,
                                ctx->stream));
     if (F_dev)
         HIP_TRY(ctx, hipMemcpyAsync(F_dev, ctx->pure.d_f, sizeof(double) * n_lmt,
@@ -935,7 +938,7 @@ psl_status psl_autotune(psl_ctx *ctx, const uint32_t *walk_ids, uint32_t n, psl_
     for (const EvalShape &c : cands) {
         BatchPlan tmp;
         if ((st = make_plan(ctx, tmp, walk_ids, n, UINT32_MAX, 0, &c))) break;
-        hipError_t e = launch_suffix(ctx->d_walks, tmp.d_batch, n, tmp.max_L, tabs, 0, ctx->stream);
+        hipError_t e = launch_suffix(ctx->d_walks, tmp.d_batch, n, tmp.max_L, tabs, 0, nullptr, ctx->stream);
         if (e == hipSuccess)   // warm-up
             e = launch_eval(ctx->d_walks, tmp.d_batch, tmp.d_items, tmp.n_items, tabs, tmp.shape,
                             tmp.d_queues, ctx->stream);

@@ -99,6 +99,7 @@ struct Server {
     DevBuf<double> d_fpart, d_f, d_s0;
     DevBuf<uint32_t> d_mpart, d_m0, d_near, d_want;
     DevBuf<SelPart> d_red;
+    DevBuf<uint32_t> d_pend;      // pending list of the iteration's batch
     DevBuf<double> d_adm_s0;      // chunk arrays of the admitted walks' fitness pass
     DevBuf<uint32_t> d_adm_m0;
     uint32_t comb_blocks = 1, comb_group = 1;
@@ -315,7 +316,7 @@ psl_status Server::admit(char *&sp, char *stage_end)
     const Tables tabs = tables_of(ctx);
     HIP_TRY(ctx, launch_init_bits(ctx->d_walks, d_admit.p, d_want.p, n, maxnw, ctx->stream));
     HIP_TRY(ctx, launch_corr(ctx->d_walks, d_admit.p, n, maxL, 0, ctx->stream));
-    HIP_TRY(ctx, launch_suffix(ctx->d_walks, d_admit.p, n, maxL, tabs, 2, ctx->stream));
+    HIP_TRY(ctx, launch_suffix(ctx->d_walks, d_admit.p, n, maxL, tabs, 2, nullptr, ctx->stream));
     for (auto &j : adm) active.push_back(std::move(j));
     dirty = true;
     {
@@ -358,7 +359,7 @@ psl_status Server::upload_layout(char *&sp, char *stage_end)
         (st = grow(ctx, d_f, n_cand)) || (st = grow(ctx, d_p, n_cand)) ||
         (st = grow(ctx, d_s0, n_suf)) || (st = grow(ctx, d_m0, n_suf)) ||
         (st = grow(ctx, d_near, (size_t)(kNearCap + 1) * n)) || (st = grow(ctx, d_queues, 1)) ||
-        (st = grow(ctx, d_red, (size_t)comb_blocks * n)))
+        (st = grow(ctx, d_red, (size_t)comb_blocks * n)) || (st = grow(ctx, d_pend, (size_t)n + 1)))
         return st;
     BatchEntry *be = (BatchEntry *)sp;
     sp += sizeof(BatchEntry) * n;
@@ -397,7 +398,7 @@ psl_status Server::upload_layout(char *&sp, char *stage_end)
     sp += sizeof(EvalQueues);
     *qs = lay.queues;
     HIP_TRY(ctx, hipMemcpyAsync(d_queues.p, qs, sizeof(EvalQueues), hipMemcpyHostToDevice, ctx->stream));
-    HIP_TRY(ctx, launch_near_reset(d_batch.p, n, ctx->stream));
+    HIP_TRY(ctx, launch_near_reset(d_batch.p, n, d_pend.p, ctx->stream));
     n_items = (uint32_t)items;
     dirty = false;
     return PSL_OK;
@@ -452,16 +453,17 @@ psl_status Server::iterate()
     if (dirty && (st = upload_layout(sp, se))) return st;
     const uint32_t n = (uint32_t)active.size();
     const Tables tabs = tables_of(ctx);
-    HIP_TRY(ctx, launch_suffix(ctx->d_walks, d_batch.p, n, max_L, tabs, 0, ctx->stream));
+    HIP_TRY(ctx, launch_suffix(ctx->d_walks, d_batch.p, n, max_L, tabs, 0, nullptr, ctx->stream));
     HIP_TRY(ctx, launch_eval(ctx->d_walks, d_batch.p, d_items.p, n_items, tabs, shape, d_queues.p, ctx->stream));
-    HIP_TRY(ctx, launch_select(ctx->d_walks, d_batch.p, n, comb_blocks, comb_group, tabs, 0, nullptr, ctx->stream));
+    HIP_TRY(ctx, launch_select(ctx->d_walks, d_batch.p, n, comb_blocks, comb_group, tabs, 0, nullptr, d_pend.p,
+                               ctx->stream));
     HIP_TRY(ctx, launch_apply(ctx->d_walks, d_batch.p, n, max_L, -1, ctx->stream));
-    HIP_TRY(ctx, launch_bookkeep(ctx->d_walks, d_batch.p, n, ctx->stream));
-    HIP_TRY(ctx, launch_switch_corr(ctx->d_walks, d_batch.p, n, max_L, ctx->stream));
+    HIP_TRY(ctx, launch_bookkeep(ctx->d_walks, d_batch.p, n, d_pend.p, ctx->stream));
+    HIP_TRY(ctx, launch_switch_corr(ctx->d_walks, d_batch.p, n, max_L, d_pend.p, ctx->stream));
     bool big = false;
     for (auto &j : active) big |= j.cfg.flip_lmt > kFlipIncremental;
     if (big) HIP_TRY(ctx, launch_corr(ctx->d_walks, d_batch.p, n, max_L, 1, ctx->stream));
-    HIP_TRY(ctx, launch_suffix(ctx->d_walks, d_batch.p, n, max_L, tabs, 1, ctx->stream));
+    HIP_TRY(ctx, launch_suffix(ctx->d_walks, d_batch.p, n, max_L, tabs, 1, d_pend.p, ctx->stream));
     uint64_t evals = 0, upd = 0;
     for (auto &j : active) {
         const uint64_t nl = j.cfg.n_lmt ? j.cfg.n_lmt : j.cfg.L;
@@ -589,6 +591,7 @@ void serve_shutdown(psl_ctx *ctx)
     release(ctx, s->d_m0);
     release(ctx, s->d_near);
     release(ctx, s->d_red);
+    release(ctx, s->d_pend);
     release(ctx, s->d_adm_s0);
     release(ctx, s->d_adm_m0);
     release(ctx, s->d_want);

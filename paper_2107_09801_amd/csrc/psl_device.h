@@ -113,6 +113,25 @@ struct SelPart {
 };
 constexpr uint32_t kCombMaxBlocks = 256;   // combine blocks per walk, at most
 
+// Blocks of an O(L) pass over a batch: a walk's shifts k = 1..L-1 are cut
+// into segments of 2^shift (256 .. 4096, chosen per batch so that the pass
+// has a few thousand blocks); block i of the pass covers segment s of walk
+// b. With off != nullptr, off[b] (b = 0..nb) are the prefix sums of the
+// walks' segment counts (device memory); otherwise every walk has spw
+// segments. total = the number of blocks.
+constexpr uint32_t kSegShiftMin = 8, kSegShiftMax = 12;
+__host__ __device__ constexpr uint32_t seg_count(uint32_t L, uint32_t shift)
+{
+    return (L - 1 + (1u << shift) - 1) >> shift;
+}
+struct SegMap {
+    const uint32_t *off;
+    uint32_t nb;
+    uint32_t spw;
+    uint32_t total;
+    uint32_t shift;
+};
+
 constexpr uint32_t kNoItem = 0xFFFFFFFFu;  // padding work item (no work)
 
 // Eval work item: walk position in the batch, candidate tile, k-split index.

@@ -105,6 +105,8 @@ struct BatchPlan {
     int32_t *d_p = nullptr;
     SelPart *d_red = nullptr;
     uint32_t *d_pend = nullptr;       // pending list: count, then batch positions
+    uint32_t *d_seg = nullptr;        // segment map of the O(L) passes
+    SegMap seg{};
 };
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -184,6 +186,11 @@ void eval_layout(const uint32_t *Ls, const uint32_t *n_lmt, uint32_t n, const Ev
                  EvalLayout &out);
 void eval_shape_k(uint32_t L, uint32_t n_lmt, uint32_t K, uint32_t tile, uint32_t *tiles, uint32_t *ksplit);
 uint32_t max_blocks_per_cu(int waves);
+// Segment maps of the O(L) passes: every walk of length L; or off[0..n] =
+// prefix sums of the walks' segment counts (the returned map's off is left
+// null for the caller to point at the device copy).
+SegMap seg_uniform(uint32_t nb, uint32_t L);
+SegMap seg_prefix(const uint32_t *Ls, uint32_t n, uint32_t *off);
 int eval_waves(const uint32_t *n_lmt, uint32_t n);
 psl_status check_cfg(psl_ctx *ctx, const psl_walk_cfg *c);
 psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t n, uint32_t n_fixed,

@@ -331,25 +331,33 @@ __global__ __launch_bounds__(kFitThreads) void k_fitness(WalkDev *walks, const B
 // alpha); mode 2: at init (every walk).
 constexpr int kChunkThreads = 256;
 constexpr uint32_t kMaxGridY = 65535;      // walks per launch of the 2-D grids
-__global__ __launch_bounds__(kChunkThreads) void k_chunks(const WalkDev *walks, const BatchEntry *batch,
-                                                          Tables tabs, int mode, const uint32_t *pend)
+// (walk, segment) of block i of an O(L) pass.
+__device__ __forceinline__ void seg_of(const SegMap &m, uint32_t i, uint32_t &b, uint32_t &seg)
 {
-    // mode 1: the whole grid works through the pending walks in turn;
-    // otherwise blockIdx.y is the walk
-    const uint32_t nq = mode == 1 ? pend[0] : 1;
-    for (uint32_t qi = 0; qi < nq; ++qi) {
-    const BatchEntry be = batch[mode == 1 ? pend[1 + qi] : blockIdx.y];
-    const WalkDev &w = walks[be.slot];
+    if (!m.off) {
+        b = i / m.spw;
+        seg = i - b * m.spw;
+        return;
+    }
+    uint32_t lo = 0, hi = m.nb - 1;      // the largest b with off[b] <= i
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (m.off[mid] <= i) lo = mid;
+        else                 hi = mid - 1;
+    }
+    b = lo;
+    seg = i - m.off[lo];
+}
+
+// Chunk pairs p0, p0 + step, ... below p1 of one walk, for the calling
+// wavefront (a pair is 64 consecutive shifts, two chunks).
+__device__ __forceinline__ void chunk_pairs(const BatchEntry &be, const WalkDev &w, const double *T, int cut,
+                                            bool near, int p0, int p1, int step)
+{
     const int L = (int)w.L;
-    const double *T = tabs.T[w.alpha];
     const int nchunks = (L - 1 + 31) / 32;
     const int lane = threadIdx.x & 63;
-    const int gw = (int)blockIdx.x * (kChunkThreads / 64) + ((int)threadIdx.x >> 6);
-    const int nwaves = (int)gridDim.x * (kChunkThreads / 64);
-    // the near-peak cut (the pivot's PSL is kept current by every step)
-    const int cut = mode == 0 ? w.psl_pivot - 8 : INT_MAX;   // unused in modes 1, 2
-    // a wavefront covers two chunks per pass
-    for (int p = gw; 2 * p < nchunks; p += nwaves) {
+    for (int p = p0; p < p1; p += step) {
         const int k = 1 + 64 * p + lane;
         double v = 0.0;
         int a = 0;
@@ -369,7 +377,7 @@ __global__ __launch_bounds__(kChunkThreads) void k_chunks(const WalkDev *walks, 
             be.S0[c] = v;
             be.M0[c] = (uint32_t)m;
         }
-        if (mode == 0) {
+        if (near) {
             const uint64_t bal = __ballot(take);
             if (bal) {
                 uint32_t base = 0;
@@ -380,7 +388,38 @@ __global__ __launch_bounds__(kChunkThreads) void k_chunks(const WalkDev *walks, 
             }
         }
     }
+}
+
+// Mode 0 (step, with the near list) and 2 (init): one block per segment of
+// the map. Mode 1: the whole grid works through the pending walks in turn.
+__global__ __launch_bounds__(kChunkThreads) void k_chunks(const WalkDev *walks, const BatchEntry *batch,
+                                                          Tables tabs, int mode, const uint32_t *pend,
+                                                          SegMap map)
+{
+    const int wave = (int)threadIdx.x >> 6;
+    constexpr int kWaves = kChunkThreads / 64;
+    if (mode == 1) {
+        const int gw = (int)blockIdx.x * kWaves + wave;
+        const int nwaves = (int)gridDim.x * kWaves;
+        const uint32_t nq = pend[0];
+        for (uint32_t qi = 0; qi < nq; ++qi) {
+            const BatchEntry be = batch[pend[1 + qi]];
+            const WalkDev &w = walks[be.slot];
+            const int npairs = ((int)w.L - 1 + 63) / 64;
+            chunk_pairs(be, w, tabs.T[w.alpha], INT_MAX, false, gw, npairs, nwaves);
+        }
+        return;
     }
+    uint32_t b, seg;
+    seg_of(map, blockIdx.x, b, seg);
+    const BatchEntry be = batch[b];
+    const WalkDev &w = walks[be.slot];
+    const int npairs = ((int)w.L - 1 + 63) / 64;
+    const int pairs_per_seg = 1 << (map.shift - 6);
+    const int p0 = (int)seg * pairs_per_seg;
+    const int p1 = min(npairs, p0 + pairs_per_seg);
+    // the near-peak cut (the pivot's PSL is kept current by every step)
+    chunk_pairs(be, w, tabs.T[w.alpha], w.psl_pivot - 8, mode == 0, p0 + wave, p1, kWaves);
 }
 
 constexpr int kScanThreads = 1024;
@@ -407,6 +446,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(WalkDev *walks, const Bat
     const int lo = (int)threadIdx.x * seg, hi = min(nchunks, lo + seg);
     double ts = 0.0, tc = 0.0;
     uint32_t tm = 0;
+#pragma unroll 4
     for (int c = hi - 1; c >= lo; --c) {
         nsum_add(ts, tc, be.S0[c]);
         tm = max(tm, be.M0[c]);
@@ -425,17 +465,23 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(WalkDev *walks, const Bat
             lc += s_tc[t];
             lm = max(lm, s_tm[t]);
         }
-        // exclusive suffix over lanes (lanes above l), in lane order
-        double es = 0.0, ec = 0.0;
-        uint32_t em = 0;
-        for (int o = 63; o > 0; --o) {
-            const double os = __shfl(ls, o), oc = __shfl(lc, o);
-            const uint32_t om = (uint32_t)__shfl((int)lm, o);
-            if (o > lane) {
-                nsum_add(es, ec, os);
-                ec += oc;
-                em = max(em, om);
+        // inclusive suffix over lanes in six doubling steps, then shifted
+        // down one lane: the totals of the lanes above l
+        for (int d = 1; d < 64; d <<= 1) {
+            const double os = __shfl_down(ls, d), oc = __shfl_down(lc, d);
+            const uint32_t om = (uint32_t)__shfl_down((int)lm, d);
+            if (lane + d < 64) {
+                nsum_add(ls, lc, os);
+                lc += oc;
+                lm = max(lm, om);
             }
+        }
+        double es = __shfl_down(ls, 1), ec = __shfl_down(lc, 1);
+        uint32_t em = (uint32_t)__shfl_down((int)lm, 1);
+        if (lane == 63) {
+            es = 0.0;
+            ec = 0.0;
+            em = 0;
         }
         for (int x = 15; x >= 0; --x) {
             const int t = 16 * lane + x;
@@ -1067,16 +1113,23 @@ __global__ __launch_bounds__(kSelThreads) void k_select(WalkDev *walks, const Ba
 // Flip(pivot, j), part 1: C_k += -2 s_j (s_{j+k} + s_{j-k}) over the terms in
 // bounds, read from the pivot before its bit changes. j_fixed < 0: the walk's
 // recorded move.
-__global__ void k_apply(WalkDev *walks, const BatchEntry *batch, int64_t j_fixed)
+constexpr int kApplyThreads = 256;
+__global__ __launch_bounds__(kApplyThreads) void k_apply(WalkDev *walks, const BatchEntry *batch,
+                                                         int64_t j_fixed, SegMap map)
 {
-    WalkDev &w = walks[batch[blockIdx.y].slot];
+    uint32_t bi, seg;
+    seg_of(map, blockIdx.x, bi, seg);
+    WalkDev &w = walks[batch[bi].slot];
     const uint32_t L = w.L;
     const uint32_t j = j_fixed >= 0 ? (uint32_t)j_fixed : w.k;
     const uint64_t *b = w.pivot;
     const int sj = get_bit(b, j) ? -1 : 1;
     // the move improves on v_local: the new pivot becomes local_best
     const bool lb = j_fixed < 0 && (w.flags & STEP_IMPROVED);
-    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x + 1u; k < L; k += gridDim.x * blockDim.x) {
+    const uint32_t k0 = 1u + (seg << map.shift);
+    const uint32_t k1 = min(L, k0 + (1u << map.shift));
+#pragma unroll 4
+    for (uint32_t k = k0 + threadIdx.x; k < k1; k += kApplyThreads) {
         int d = 0;
         if (j + k < L) d += get_bit(b, j + k) ? -1 : 1;
         if (k <= j) d += get_bit(b, j - k) ? -1 : 1;
@@ -1098,8 +1151,8 @@ constexpr int kBookThreads = 256;
 // The rest of one loop iteration of Algorithm 1 after the C update: the
 // move's bit, the three-way comparison with v_local, the unimproved counter,
 // the local best, and the phase switch (Rand_flip of the local best and the
-// exponent swap; C, F and PSL of the new pivot are rebuilt by k_corr and
-// k_fitness on walks left pending).
+// exponent swap; the walk joins the batch's pending list, whose C, F and PSL
+// the switch kernels and the chunk pass in mode 1 then rebuild).
 __global__ __launch_bounds__(kBookThreads) void k_bookkeep(WalkDev *walks, const BatchEntry *batch,
                                                            uint32_t *pend)
 {
@@ -1249,29 +1302,24 @@ hipError_t launch_eval(const WalkDev *walks, const BatchEntry *batch, const Eval
 }
 
 hipError_t launch_suffix(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t max_L,
-                         const Tables &tabs, int mode, const uint32_t *pend, hipStream_t s)
+                         const Tables &tabs, int mode, const uint32_t *pend, const SegMap *map, hipStream_t s)
 {
-    const uint32_t nchunks = (max_L - 1 + 31) / 32;
     if (mode == 1) {
         // the pending walks of the batch, one after another over the grid
         if (!pend) return hipErrorInvalidValue;
+        const uint32_t nchunks = (max_L - 1 + 31) / 32;
         const uint32_t bx = std::max<uint32_t>(1, std::min<uint32_t>(1024, (nchunks + 7) / 8));
-        k_chunks<<<dim3(bx, 1), kChunkThreads, 0, s>>>(walks, batch, tabs, mode, pend);
+        k_chunks<<<bx, kChunkThreads, 0, s>>>(walks, batch, tabs, mode, pend, SegMap{nullptr, 1, 1, 1, 12});
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         k_scan<<<std::min<uint32_t>(nb, 256), kScanThreads, 0, s>>>(walks, batch, mode, pend);
         return hipGetLastError();
     }
-    // about 2048 blocks over the batch, at most one per 8 chunks of the
-    // longest walk
-    const uint32_t per_walk = std::max<uint32_t>(1, (2048 + nb - 1) / nb);
-    const uint32_t bx = std::max<uint32_t>(1, std::min(per_walk, (nchunks + 7) / 8));
-    for (uint32_t b0 = 0; b0 < nb; b0 += kMaxGridY) {
-        k_chunks<<<dim3(bx, std::min(kMaxGridY, nb - b0)), kChunkThreads, 0, s>>>(walks, batch + b0, tabs, mode,
-                                                                                  nullptr);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
+    if (!map || map->total == 0 || map->nb != nb || map->shift < kSegShiftMin || map->shift > kSegShiftMax)
+        return hipErrorInvalidValue;
+    k_chunks<<<map->total, kChunkThreads, 0, s>>>(walks, batch, tabs, mode, nullptr, *map);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     k_scan<<<nb, kScanThreads, 0, s>>>(walks, batch, mode, nullptr);
     return hipGetLastError();
 }
@@ -1315,11 +1363,12 @@ void choice_dev_unpack(const void *p, uint32_t *i_best, uint32_t *j_best, double
     *j_psl = c->j_psl; *psl_min = c->psl_min; *psl_k = c->psl_k;
 }
 
-hipError_t launch_apply(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t max_L,
-                        int64_t j_fixed, hipStream_t s)
+hipError_t launch_apply(WalkDev *walks, const BatchEntry *batch, const SegMap &map, int64_t j_fixed,
+                        hipStream_t s)
 {
-    if (max_L < 2) return hipSuccess;
-    k_apply<<<dim3(lin_blocks(max_L, nb), nb), 256, 0, s>>>(walks, batch, j_fixed);
+    if (map.shift < kSegShiftMin || map.shift > kSegShiftMax) return hipErrorInvalidValue;
+    if (map.total == 0) return hipSuccess;       // L = 1 has no shift to update
+    k_apply<<<map.total, kApplyThreads, 0, s>>>(walks, batch, j_fixed, map);
     return hipGetLastError();
 }
 

@@ -22,7 +22,7 @@ hipError_t launch_eval(const WalkDev *walks, const BatchEntry *batch, const Eval
 // fitness of pending walks after a phase switch; mode 2: the initial fitness
 // (value_local, F_pivot, psl_pivot, psl_best) of every walk.
 hipError_t launch_suffix(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t max_L,
-                         const Tables &tabs, int mode, const uint32_t *pend, hipStream_t s);
+                         const Tables &tabs, int mode, const uint32_t *pend, const SegMap *map, hipStream_t s);
 // Zero the near-peak counts of a batch and its pending count (after its
 // scratch is allocated).
 hipError_t launch_near_reset(const BatchEntry *batch, uint32_t nb, uint32_t *pend, hipStream_t s);
@@ -32,8 +32,8 @@ hipError_t launch_select(WalkDev *walks, const BatchEntry *batch, uint32_t nb, u
 size_t choice_dev_size();
 void choice_dev_unpack(const void *p, uint32_t *i_best, uint32_t *j_best, double *F_best,
                        double *F_min, uint32_t *j_psl, int32_t *psl_min, int32_t *psl_k);
-hipError_t launch_apply(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t max_L,
-                        int64_t j_fixed, hipStream_t s);
+hipError_t launch_apply(WalkDev *walks, const BatchEntry *batch, const SegMap &map, int64_t j_fixed,
+                        hipStream_t s);
 hipError_t launch_flip_bit(WalkDev *walks, const BatchEntry *batch, uint32_t j, hipStream_t s);
 hipError_t launch_bookkeep(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t *pend, hipStream_t s);
 

@@ -90,6 +90,7 @@ void plan_free(psl_ctx *ctx, BatchPlan &pl)
     dev_free(ctx, pl.d_m0, false);
     dev_free(ctx, pl.d_red, false);
     dev_free(ctx, pl.d_pend, false);
+    dev_free(ctx, pl.d_seg, false);
     dev_free(ctx, pl.d_near, false);
     dev_free(ctx, pl.d_queues, false);
     pl = BatchPlan();
@@ -168,6 +169,32 @@ bool walk_ok(const psl_ctx *ctx, uint32_t id)
 // no item is much longer than the batch's average.
 // Evaluation blocks resident per CU: the LDS of a block admits three; 16
 // wavefronts per block are limited to two by the CU's wavefront slots.
+// The largest segment (256 .. 4096 shifts) that still gives the pass about
+// 2048 blocks.
+static uint32_t seg_shift(uint64_t shifts)
+{
+    uint32_t sh = kSegShiftMax;
+    while (sh > kSegShiftMin && (shifts >> sh) < 2048) --sh;
+    return sh;
+}
+
+SegMap seg_uniform(uint32_t nb, uint32_t L)
+{
+    const uint32_t sh = seg_shift((uint64_t)nb * (L - 1));
+    const uint32_t spw = seg_count(L, sh);
+    return SegMap{nullptr, nb, spw, nb * spw, sh};
+}
+
+SegMap seg_prefix(const uint32_t *Ls, uint32_t n, uint32_t *off)
+{
+    uint64_t shifts = 0;
+    for (uint32_t b = 0; b < n; ++b) shifts += Ls[b] - 1;
+    const uint32_t sh = seg_shift(shifts);
+    off[0] = 0;
+    for (uint32_t b = 0; b < n; ++b) off[b + 1] = off[b] + seg_count(Ls[b], sh);
+    return SegMap{nullptr, n, 0, off[n], sh};
+}
+
 uint32_t max_blocks_per_cu(int waves)
 {
     return waves >= kEvalWavesMax ? 2u : 3u;
@@ -359,6 +386,14 @@ psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t 
     pl.d_red = (SelPart *)p;
     if ((st = dev_alloc(ctx, &p, sizeof(uint32_t) * (n + 1), false))) return st;
     pl.d_pend = (uint32_t *)p;
+    {
+        std::vector<uint32_t> off(n + 1);
+        pl.seg = seg_prefix(Ls.data(), n, off.data());
+        if ((st = dev_alloc(ctx, &p, sizeof(uint32_t) * (n + 1), false))) return st;
+        pl.d_seg = (uint32_t *)p;
+        pl.seg.off = pl.d_seg;
+        HIP_TRY(ctx, hipMemcpy(pl.d_seg, off.data(), sizeof(uint32_t) * (n + 1), hipMemcpyHostToDevice));
+    }
     std::vector<BatchEntry> be(n);
     size_t op = 0, oc = 0, os = 0;
     for (uint32_t b = 0; b < n; ++b) {
@@ -455,18 +490,18 @@ psl_status check_cfg(psl_ctx *ctx, const psl_walk_cfg *c)
 psl_status launch_step(psl_ctx *ctx, const BatchPlan &pl, const Tables &tabs, uint32_t n, bool timed)
 {
     psl_status st;
-    HIP_TRY(ctx, launch_suffix(ctx->d_walks, pl.d_batch, n, pl.max_L, tabs, 0, nullptr, ctx->stream));
+    HIP_TRY(ctx, launch_suffix(ctx->d_walks, pl.d_batch, n, pl.max_L, tabs, 0, nullptr, &pl.seg, ctx->stream));
     if (timed && (st = timing_mark(ctx))) return st;
     HIP_TRY(ctx, launch_eval(ctx->d_walks, pl.d_batch, pl.d_items, pl.n_items, tabs, pl.shape, pl.d_queues,
                              ctx->stream));
     if (timed && (st = timing_mark(ctx))) return st;
     HIP_TRY(ctx, launch_select(ctx->d_walks, pl.d_batch, n, pl.comb_blocks, pl.comb_group, tabs, 0, nullptr,
                                pl.d_pend, ctx->stream));
-    HIP_TRY(ctx, launch_apply(ctx->d_walks, pl.d_batch, n, pl.max_L, -1, ctx->stream));
+    HIP_TRY(ctx, launch_apply(ctx->d_walks, pl.d_batch, pl.seg, -1, ctx->stream));
     HIP_TRY(ctx, launch_bookkeep(ctx->d_walks, pl.d_batch, n, pl.d_pend, ctx->stream));
     HIP_TRY(ctx, launch_switch_corr(ctx->d_walks, pl.d_batch, n, pl.max_L, pl.d_pend, ctx->stream));
     if (pl.big_flips) HIP_TRY(ctx, launch_corr(ctx->d_walks, pl.d_batch, n, pl.max_L, 1, ctx->stream));
-    HIP_TRY(ctx, launch_suffix(ctx->d_walks, pl.d_batch, n, pl.max_L, tabs, 1, pl.d_pend, ctx->stream));
+    HIP_TRY(ctx, launch_suffix(ctx->d_walks, pl.d_batch, n, pl.max_L, tabs, 1, pl.d_pend, nullptr, ctx->stream));
     if (timed && (st = timing_mark(ctx))) return st;
     return PSL_OK;
 }
@@ -686,7 +721,8 @@ psl_status psl_init_walks(psl_ctx *ctx, const psl_walk_cfg *cfg, uint32_t n,
         const Tables tabs = tables_of(ctx);
         hipError_t e = launch_init_bits(ctx->d_walks, tmp.d_batch, (const uint32_t *)dw, n, nw, ctx->stream);
         if (e == hipSuccess) e = launch_corr(ctx->d_walks, tmp.d_batch, n, L, 0, ctx->stream);
-        if (e == hipSuccess) e = launch_suffix(ctx->d_walks, tmp.d_batch, n, L, tabs, 2, nullptr, ctx->stream);
+        const SegMap sm = seg_uniform(n, L);
+        if (e == hipSuccess) e = launch_suffix(ctx->d_walks, tmp.d_batch, n, L, tabs, 2, nullptr, &sm, ctx->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
         dev_free(ctx, dw, false);
         plan_free(ctx, tmp);
@@ -732,7 +768,8 @@ psl_status psl_eval_neighbourhood(psl_ctx *ctx, uint32_t walk, uint32_t start, u
     psl_status st = make_plan(ctx, ctx->pure, &walk, 1, n_lmt, start);
     if (st) return st;
     const Tables tabs = tables_of(ctx);
-    HIP_TRY(ctx, launch_suffix(ctx->d_walks, ctx->pure.d_batch, 1, h.L, tabs, 0, nullptr, ctx->stream));
+    HIP_TRY(ctx, launch_suffix(ctx->d_walks, ctx->pure.d_batch, 1, h.L, tabs, 0, nullptr, &ctx->pure.seg,
+                               ctx->stream));
     HIP_TRY(ctx, launch_eval(ctx->d_walks, ctx->pure.d_batch, ctx->pure.d_items, ctx->pure.n_items,
                              tabs, ctx->pure.shape, ctx->pure.d_queues, ctx->stream));
     HIP_TRY(ctx, launch_select(ctx->d_walks, ctx->pure.d_batch, 1, ctx->pure.comb_blocks, ctx->pure.comb_group, tabs, 1,
@@ -774,7 +811,7 @@ psl_status psl_apply_flip(psl_ctx *ctx, uint32_t walk, uint32_t j)
     e.slot = walk;
     hipError_t r = hipMemcpy(one.d_batch, &e, sizeof e, hipMemcpyHostToDevice);
     const Tables tabs = tables_of(ctx);
-    if (r == hipSuccess) r = launch_apply(ctx->d_walks, one.d_batch, 1, h.L, (int64_t)j, ctx->stream);
+    if (r == hipSuccess) r = launch_apply(ctx->d_walks, one.d_batch, seg_uniform(1, h.L), (int64_t)j, ctx->stream);
     if (r == hipSuccess) r = launch_flip_bit(ctx->d_walks, one.d_batch, j, ctx->stream);
     if (r == hipSuccess) r = launch_fitness(ctx->d_walks, one.d_batch, 1, tabs, 2, ctx->stream);
     if (r == hipSuccess) r = hipStreamSynchronize(ctx->stream);
@@ -938,7 +975,8 @@ psl_status psl_autotune(psl_ctx *ctx, const uint32_t *walk_ids, uint32_t n, psl_
     for (const EvalShape &c : cands) {
         BatchPlan tmp;
         if ((st = make_plan(ctx, tmp, walk_ids, n, UINT32_MAX, 0, &c))) break;
-        hipError_t e = launch_suffix(ctx->d_walks, tmp.d_batch, n, tmp.max_L, tabs, 0, nullptr, ctx->stream);
+        hipError_t e = launch_suffix(ctx->d_walks, tmp.d_batch, n, tmp.max_L, tabs, 0, nullptr, &tmp.seg,
+                                     ctx->stream);
         if (e == hipSuccess)   // warm-up
             e = launch_eval(ctx->d_walks, tmp.d_batch, tmp.d_items, tmp.n_items, tabs, tmp.shape,
                             tmp.d_queues, ctx->stream);

@@ -100,6 +100,8 @@ struct Server {
     DevBuf<uint32_t> d_mpart, d_m0, d_near, d_want;
     DevBuf<SelPart> d_red;
     DevBuf<uint32_t> d_pend;      // pending list of the iteration's batch
+    DevBuf<uint32_t> d_seg, d_adm_seg;   // segment maps (batch, admitted walks)
+    SegMap seg{};
     DevBuf<double> d_adm_s0;      // chunk arrays of the admitted walks' fitness pass
     DevBuf<uint32_t> d_adm_m0;
     uint32_t comb_blocks = 1, comb_group = 1;
@@ -248,7 +250,7 @@ psl_status Server::admit(char *&sp, char *stage_end)
         pending.pop_front();
     }
     if (adm.empty()) return PSL_OK;
-    const size_t need = adm.size() * (sizeof(WalkDev) + sizeof(BatchEntry) + sizeof(uint32_t)) + 64;
+    const size_t need = adm.size() * (sizeof(WalkDev) + sizeof(BatchEntry) + 2 * sizeof(uint32_t)) + 192;
     if ((size_t)(stage_end - sp) < need) {
         // put them back in order; admitted next iteration
         for (auto it = adm.rbegin(); it != adm.rend(); ++it) {
@@ -271,7 +273,17 @@ psl_status Server::admit(char *&sp, char *stage_end)
     sp += sizeof(BatchEntry) * adm.size();
     uint32_t *want = (uint32_t *)sp;
     sp += sizeof(uint32_t) * adm.size();
+    uint32_t *adm_off = (uint32_t *)sp;
+    sp += sizeof(uint32_t) * (adm.size() + 1);
     sp = (char *)(((uintptr_t)sp + 63) & ~(uintptr_t)63);
+    if ((st = grow(ctx, d_adm_seg, adm.size() + 1))) return st;
+    SegMap adm_map{};
+    {
+        std::vector<uint32_t> aL(adm.size());
+        for (size_t b = 0; b < adm.size(); ++b) aL[b] = adm[b].cfg.L;
+        adm_map = seg_prefix(aL.data(), (uint32_t)adm.size(), adm_off);
+        adm_map.off = d_adm_seg.p;
+    }
     const uint64_t t = now_ns();
     for (size_t b = 0; b < adm.size(); ++b) {
         Job &j = adm[b];
@@ -316,7 +328,9 @@ psl_status Server::admit(char *&sp, char *stage_end)
     const Tables tabs = tables_of(ctx);
     HIP_TRY(ctx, launch_init_bits(ctx->d_walks, d_admit.p, d_want.p, n, maxnw, ctx->stream));
     HIP_TRY(ctx, launch_corr(ctx->d_walks, d_admit.p, n, maxL, 0, ctx->stream));
-    HIP_TRY(ctx, launch_suffix(ctx->d_walks, d_admit.p, n, maxL, tabs, 2, nullptr, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(d_adm_seg.p, adm_off, sizeof(uint32_t) * (n + 1), hipMemcpyHostToDevice,
+                                ctx->stream));
+    HIP_TRY(ctx, launch_suffix(ctx->d_walks, d_admit.p, n, maxL, tabs, 2, nullptr, &adm_map, ctx->stream));
     for (auto &j : adm) active.push_back(std::move(j));
     dirty = true;
     {
@@ -351,7 +365,8 @@ psl_status Server::upload_layout(char *&sp, char *stage_end)
     shape = lay.shape;
     comb_blocks = lay.comb_blocks;
     comb_group = lay.comb_group;
-    const size_t need = sizeof(BatchEntry) * n + sizeof(EvalItem) * items + sizeof(EvalQueues) + 256;
+    const size_t need = sizeof(BatchEntry) * n + sizeof(EvalItem) * items + sizeof(EvalQueues) +
+                        sizeof(uint32_t) * (n + 1) + 512;
     if ((size_t)(stage_end - sp) < need) return fail(ctx, PSL_E_NOMEM, "serving staging too small");
     psl_status st;
     if ((st = grow(ctx, d_batch, n)) || (st = grow(ctx, d_items, items)) ||
@@ -359,7 +374,8 @@ psl_status Server::upload_layout(char *&sp, char *stage_end)
         (st = grow(ctx, d_f, n_cand)) || (st = grow(ctx, d_p, n_cand)) ||
         (st = grow(ctx, d_s0, n_suf)) || (st = grow(ctx, d_m0, n_suf)) ||
         (st = grow(ctx, d_near, (size_t)(kNearCap + 1) * n)) || (st = grow(ctx, d_queues, 1)) ||
-        (st = grow(ctx, d_red, (size_t)comb_blocks * n)) || (st = grow(ctx, d_pend, (size_t)n + 1)))
+        (st = grow(ctx, d_red, (size_t)comb_blocks * n)) || (st = grow(ctx, d_pend, (size_t)n + 1)) ||
+        (st = grow(ctx, d_seg, (size_t)n + 1)))
         return st;
     BatchEntry *be = (BatchEntry *)sp;
     sp += sizeof(BatchEntry) * n;
@@ -398,6 +414,12 @@ psl_status Server::upload_layout(char *&sp, char *stage_end)
     sp += sizeof(EvalQueues);
     *qs = lay.queues;
     HIP_TRY(ctx, hipMemcpyAsync(d_queues.p, qs, sizeof(EvalQueues), hipMemcpyHostToDevice, ctx->stream));
+    sp = (char *)(((uintptr_t)sp + 63) & ~(uintptr_t)63);
+    uint32_t *off = (uint32_t *)sp;
+    sp += sizeof(uint32_t) * (n + 1);
+    seg = seg_prefix(Ls.data(), n, off);
+    seg.off = d_seg.p;
+    HIP_TRY(ctx, hipMemcpyAsync(d_seg.p, off, sizeof(uint32_t) * (n + 1), hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(ctx, launch_near_reset(d_batch.p, n, d_pend.p, ctx->stream));
     n_items = (uint32_t)items;
     dirty = false;
@@ -442,8 +464,8 @@ psl_status Server::iterate()
             const Job &j = pending[x];
             tiles += ((j.cfg.n_lmt ? j.cfg.n_lmt : j.cfg.L) + tl - 1) / tl;
         }
-        const size_t need = (n_adm + active.size()) * (sizeof(WalkDev) + 2 * sizeof(BatchEntry) + 8) +
-                            sizeof(EvalItem) * 8 * (4096 + tiles) + 4096;
+        const size_t need = (n_adm + active.size()) * (sizeof(WalkDev) + 2 * sizeof(BatchEntry) + 16) +
+                            sizeof(EvalItem) * 8 * (4096 + tiles) + 8192;
         if ((st = ensure_stage(need))) return st;
     }
     char *sp = stage[cur];
@@ -453,17 +475,17 @@ psl_status Server::iterate()
     if (dirty && (st = upload_layout(sp, se))) return st;
     const uint32_t n = (uint32_t)active.size();
     const Tables tabs = tables_of(ctx);
-    HIP_TRY(ctx, launch_suffix(ctx->d_walks, d_batch.p, n, max_L, tabs, 0, nullptr, ctx->stream));
+    HIP_TRY(ctx, launch_suffix(ctx->d_walks, d_batch.p, n, max_L, tabs, 0, nullptr, &seg, ctx->stream));
     HIP_TRY(ctx, launch_eval(ctx->d_walks, d_batch.p, d_items.p, n_items, tabs, shape, d_queues.p, ctx->stream));
     HIP_TRY(ctx, launch_select(ctx->d_walks, d_batch.p, n, comb_blocks, comb_group, tabs, 0, nullptr, d_pend.p,
                                ctx->stream));
-    HIP_TRY(ctx, launch_apply(ctx->d_walks, d_batch.p, n, max_L, -1, ctx->stream));
+    HIP_TRY(ctx, launch_apply(ctx->d_walks, d_batch.p, seg, -1, ctx->stream));
     HIP_TRY(ctx, launch_bookkeep(ctx->d_walks, d_batch.p, n, d_pend.p, ctx->stream));
     HIP_TRY(ctx, launch_switch_corr(ctx->d_walks, d_batch.p, n, max_L, d_pend.p, ctx->stream));
     bool big = false;
     for (auto &j : active) big |= j.cfg.flip_lmt > kFlipIncremental;
     if (big) HIP_TRY(ctx, launch_corr(ctx->d_walks, d_batch.p, n, max_L, 1, ctx->stream));
-    HIP_TRY(ctx, launch_suffix(ctx->d_walks, d_batch.p, n, max_L, tabs, 1, d_pend.p, ctx->stream));
+    HIP_TRY(ctx, launch_suffix(ctx->d_walks, d_batch.p, n, max_L, tabs, 1, d_pend.p, nullptr, ctx->stream));
     uint64_t evals = 0, upd = 0;
     for (auto &j : active) {
         const uint64_t nl = j.cfg.n_lmt ? j.cfg.n_lmt : j.cfg.L;
@@ -592,6 +614,8 @@ void serve_shutdown(psl_ctx *ctx)
     release(ctx, s->d_near);
     release(ctx, s->d_red);
     release(ctx, s->d_pend);
+    release(ctx, s->d_seg);
+    release(ctx, s->d_adm_seg);
     release(ctx, s->d_adm_s0);
     release(ctx, s->d_adm_m0);
     release(ctx, s->d_want);

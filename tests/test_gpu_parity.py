@@ -208,6 +208,35 @@ def test_batch_matches_single_walks(ctx):
     ctx.free_walks(solo + mixed)
 
 
+@pytest.mark.parametrize("flip", [1, 10, 40, 64, 65, 90])
+def test_switch_every_step_against_oracle(ctx, flip):
+    """Every walk of a mixed batch switches after every step, so every step
+    rebuilds C from local_best's C through the pending list (FLIP_lmt <= 64:
+    one-flip updates plus the fix-up of the shifts earlier flips touched;
+    above 64: the full correlation). Each walk follows its oracle walk."""
+    Ls = [70, 129, 500, 1200]
+    ids, ows = [], []
+    for L in Ls:
+        seed = si.BASE_SEED + 11 * L + flip
+        fl = min(flip, L)
+        ids += ctx.init_walks(L, 1, seed, alpha1=4, alpha2=13, n_lmt=0, flip_lmt=fl, switch_period=1)
+        ows.append(oracle.Walk(oracle.WalkConfig(L=L, seed=seed, alpha1=4, alpha2=13, n_lmt=L,
+                                                 flip_lmt=fl, switch_period=1), margin=MARGIN, nthreads=8))
+    for t in range(8):
+        ctx.step_batch(ids, 1)
+        for w, ow in zip(ids, ows):
+            tr = ow.step()
+            if tr["flags"] & (oracle.AMBIG_ARGMIN | oracle.AMBIG_COMPARE):
+                pytest.skip("the oracle flags an ambiguous decision")
+            assert tr["flags"] & oracle.SWITCHED
+            g, o = ctx.read_walk(w), ow.read()
+            for key in ("pivot", "C", "local_best", "best"):
+                assert np.array_equal(g[key], o[key]), (t, key)
+            assert g["alpha"] == o["alpha"] and g["psl_pivot"] == o["psl_pivot"], t
+            assert abs(g["value_local"] - o["value_local"]) <= F_RTOL * o["value_local"], t
+    ctx.free_walks(ids)
+
+
 def test_invalid_arguments(ctx):
     from paper_2107_09801_amd import libpsl
     with pytest.raises(libpsl.PslError):

@@ -130,6 +130,8 @@ struct SegMap {
     uint32_t spw;
     uint32_t total;
     uint32_t shift;
+    double *tot;            // per block: sum over its segment's chunks (or nullptr)
+    uint32_t *tmax;         // per block: maximum |C_k| over its segment
 };
 
 constexpr uint32_t kNoItem = 0xFFFFFFFFu;  // padding work item (no work)

@@ -352,7 +352,8 @@ __device__ __forceinline__ void seg_of(const SegMap &m, uint32_t i, uint32_t &b,
 // Chunk pairs p0, p0 + step, ... below p1 of one walk, for the calling
 // wavefront (a pair is 64 consecutive shifts, two chunks).
 __device__ __forceinline__ void chunk_pairs(const BatchEntry &be, const WalkDev &w, const double *T, int cut,
-                                            bool near, int p0, int p1, int step)
+                                            bool near, int p0, int p1, int step, double &ws, double &wc,
+                                            uint32_t &wm)
 {
     const int L = (int)w.L;
     const int nchunks = (L - 1 + 31) / 32;
@@ -377,6 +378,11 @@ __device__ __forceinline__ void chunk_pairs(const BatchEntry &be, const WalkDev 
             be.S0[c] = v;
             be.M0[c] = (uint32_t)m;
         }
+        // the pair's two chunk sums, in chunk order, into the wave's total
+        const double v2 = __shfl(v, 32);
+        nsum_add(ws, wc, __shfl(v, 0));
+        nsum_add(ws, wc, v2);
+        wm = max(wm, (uint32_t)max(__shfl(m, 0), __shfl(m, 32)));
         if (near) {
             const uint64_t bal = __ballot(take);
             if (bal) {
@@ -406,7 +412,9 @@ __global__ __launch_bounds__(kChunkThreads) void k_chunks(const WalkDev *walks, 
             const BatchEntry be = batch[pend[1 + qi]];
             const WalkDev &w = walks[be.slot];
             const int npairs = ((int)w.L - 1 + 63) / 64;
-            chunk_pairs(be, w, tabs.T[w.alpha], INT_MAX, false, gw, npairs, nwaves);
+            double ws = 0.0, wc = 0.0;
+            uint32_t wm = 0;
+            chunk_pairs(be, w, tabs.T[w.alpha], INT_MAX, false, gw, npairs, nwaves, ws, wc, wm);
         }
         return;
     }
@@ -419,7 +427,113 @@ __global__ __launch_bounds__(kChunkThreads) void k_chunks(const WalkDev *walks, 
     const int p0 = (int)seg * pairs_per_seg;
     const int p1 = min(npairs, p0 + pairs_per_seg);
     // the near-peak cut (the pivot's PSL is kept current by every step)
-    chunk_pairs(be, w, tabs.T[w.alpha], w.psl_pivot - 8, mode == 0, p0 + wave, p1, kWaves);
+    double ws = 0.0, wc = 0.0;
+    uint32_t wm = 0;
+    chunk_pairs(be, w, tabs.T[w.alpha], w.psl_pivot - 8, mode == 0, p0 + wave, p1, kWaves, ws, wc, wm);
+    if (map.tot) {
+        // the segment's total (waves in order) for the segment-parallel scan
+        __shared__ double s_s[kWaves], s_c[kWaves];
+        __shared__ uint32_t s_m[kWaves];
+        if ((threadIdx.x & 63) == 0) {
+            s_s[wave] = ws;
+            s_c[wave] = wc;
+            s_m[wave] = wm;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double ts = 0.0, tc = 0.0;
+            uint32_t tm = 0;
+            for (int x = 0; x < kWaves; ++x) {
+                nsum_add(ts, tc, s_s[x]);
+                tc += s_c[x];
+                tm = max(tm, s_m[x]);
+            }
+            map.tot[blockIdx.x] = ts + tc;
+            map.tmax[blockIdx.x] = tm;
+        }
+    }
+}
+
+// Suffix values of the step's chunk arrays, one wavefront per segment of the
+// map: the segment's chunks (at most 128, two per lane) are scanned from the
+// right with doubling steps, and the offset is the sum of the totals of the
+// walk's later segments (a fixed butterfly over lanes). Each entry is a sum
+// of the same chunk values, each in a fixed order.
+constexpr int kSegScanThreads = 256;
+__global__ __launch_bounds__(kSegScanThreads) void k_seg_scan(const WalkDev *walks, const BatchEntry *batch,
+                                                              SegMap map)
+{
+    const uint32_t i = blockIdx.x * (kSegScanThreads / 64) + (threadIdx.x >> 6);
+    if (i >= map.total) return;              // wave-uniform
+    const int lane = threadIdx.x & 63;
+    uint32_t b, seg;
+    seg_of(map, i, b, seg);
+    const BatchEntry be = batch[b];
+    const WalkDev &w = walks[be.slot];
+    const int nchunks = ((int)w.L - 1 + 31) / 32;
+    const int cps = 1 << (map.shift - 5);    // chunks per segment
+    const int c0 = (int)seg * cps;
+    const int c1 = min(nchunks, c0 + cps);
+    // totals of the later segments of this walk
+    const uint32_t last = map.off ? map.off[b + 1] : (b + 1) * map.spw;
+    double os = 0.0, oc = 0.0;
+    uint32_t om = 0;
+    for (uint32_t x = i + 1 + lane; x < last; x += 64) {
+        nsum_add(os, oc, map.tot[x]);
+        om = max(om, map.tmax[x]);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const double ps = __shfl_xor(os, o), pc = __shfl_xor(oc, o);
+        const uint32_t pm = (uint32_t)__shfl_xor((int)om, o);
+        nsum_add(os, oc, ps);
+        oc += pc;
+        om = max(om, pm);
+    }
+    // lane l holds chunks c0 + 2l, c0 + 2l + 1
+    const int ca = c0 + 2 * lane, cb = ca + 1;
+    const double va = ca < c1 ? be.S0[ca] : 0.0, vb = cb < c1 ? be.S0[cb] : 0.0;
+    const uint32_t ma = ca < c1 ? be.M0[ca] : 0u, mb = cb < c1 ? be.M0[cb] : 0u;
+    double ls = 0.0, lc = 0.0;
+    nsum_add(ls, lc, vb);
+    nsum_add(ls, lc, va);
+    uint32_t lm = max(ma, mb);
+    // inclusive suffix over lanes, then exclusive by one lane
+    for (int d = 1; d < 64; d <<= 1) {
+        const double ps = __shfl_down(ls, d), pc = __shfl_down(lc, d);
+        const uint32_t pm = (uint32_t)__shfl_down((int)lm, d);
+        if (lane + d < 64) {
+            nsum_add(ls, lc, ps);
+            lc += pc;
+            lm = max(lm, pm);
+        }
+    }
+    double es = __shfl_down(ls, 1), ec = __shfl_down(lc, 1);
+    uint32_t em = (uint32_t)__shfl_down((int)lm, 1);
+    if (lane == 63) {
+        es = 0.0;
+        ec = 0.0;
+        em = 0;
+    }
+    // add the later segments, then this lane's chunks from the right
+    nsum_add(es, ec, os);
+    ec += oc;
+    em = max(em, om);
+    if (cb < c1) {
+        nsum_add(es, ec, vb);
+        em = max(em, mb);
+        be.S0[cb] = es + ec;
+        be.M0[cb] = em;
+    }
+    if (ca < c1) {
+        nsum_add(es, ec, va);
+        em = max(em, ma);
+        be.S0[ca] = es + ec;
+        be.M0[ca] = em;
+    }
+    if (c1 == nchunks && lane == 0) {
+        be.S0[nchunks] = 0.0;
+        be.M0[nchunks] = 0;
+    }
 }
 
 constexpr int kScanThreads = 1024;
@@ -1309,7 +1423,8 @@ hipError_t launch_suffix(WalkDev *walks, const BatchEntry *batch, uint32_t nb, u
         if (!pend) return hipErrorInvalidValue;
         const uint32_t nchunks = (max_L - 1 + 31) / 32;
         const uint32_t bx = std::max<uint32_t>(1, std::min<uint32_t>(1024, (nchunks + 7) / 8));
-        k_chunks<<<bx, kChunkThreads, 0, s>>>(walks, batch, tabs, mode, pend, SegMap{nullptr, 1, 1, 1, 12});
+        k_chunks<<<bx, kChunkThreads, 0, s>>>(walks, batch, tabs, mode, pend,
+                                              SegMap{nullptr, 1, 1, 1, 12, nullptr, nullptr});
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         k_scan<<<std::min<uint32_t>(nb, 256), kScanThreads, 0, s>>>(walks, batch, mode, pend);
@@ -1317,10 +1432,20 @@ hipError_t launch_suffix(WalkDev *walks, const BatchEntry *batch, uint32_t nb, u
     }
     if (!map || map->total == 0 || map->nb != nb || map->shift < kSegShiftMin || map->shift > kSegShiftMax)
         return hipErrorInvalidValue;
-    k_chunks<<<map->total, kChunkThreads, 0, s>>>(walks, batch, tabs, mode, nullptr, *map);
+    if (mode == 0 && (!map->tot || !map->tmax)) return hipErrorInvalidValue;
+    SegMap m = *map;
+    if (mode != 0) m.tot = nullptr, m.tmax = nullptr;
+    k_chunks<<<m.total, kChunkThreads, 0, s>>>(walks, batch, tabs, mode, nullptr, m);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_scan<<<nb, kScanThreads, 0, s>>>(walks, batch, mode, nullptr);
+    if (mode == 0) {
+        // the step: suffix values segment by segment
+        constexpr uint32_t per = kSegScanThreads / 64;
+        k_seg_scan<<<(m.total + per - 1) / per, kSegScanThreads, 0, s>>>(walks, batch, m);
+    } else {
+        // the initial fitness: totals per walk
+        k_scan<<<nb, kScanThreads, 0, s>>>(walks, batch, mode, nullptr);
+    }
     return hipGetLastError();
 }
 

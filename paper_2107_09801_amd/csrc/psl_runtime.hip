@@ -91,6 +91,8 @@ void plan_free(psl_ctx *ctx, BatchPlan &pl)
     dev_free(ctx, pl.d_red, false);
     dev_free(ctx, pl.d_pend, false);
     dev_free(ctx, pl.d_seg, false);
+    dev_free(ctx, pl.d_segtot, false);
+    dev_free(ctx, pl.d_segmax, false);
     dev_free(ctx, pl.d_near, false);
     dev_free(ctx, pl.d_queues, false);
     pl = BatchPlan();
@@ -182,7 +184,7 @@ SegMap seg_uniform(uint32_t nb, uint32_t L)
 {
     const uint32_t sh = seg_shift((uint64_t)nb * (L - 1));
     const uint32_t spw = seg_count(L, sh);
-    return SegMap{nullptr, nb, spw, nb * spw, sh};
+    return SegMap{nullptr, nb, spw, nb * spw, sh, nullptr, nullptr};
 }
 
 SegMap seg_prefix(const uint32_t *Ls, uint32_t n, uint32_t *off)
@@ -192,7 +194,7 @@ SegMap seg_prefix(const uint32_t *Ls, uint32_t n, uint32_t *off)
     const uint32_t sh = seg_shift(shifts);
     off[0] = 0;
     for (uint32_t b = 0; b < n; ++b) off[b + 1] = off[b] + seg_count(Ls[b], sh);
-    return SegMap{nullptr, n, 0, off[n], sh};
+    return SegMap{nullptr, n, 0, off[n], sh, nullptr, nullptr};
 }
 
 uint32_t max_blocks_per_cu(int waves)
@@ -393,6 +395,12 @@ psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t 
         pl.d_seg = (uint32_t *)p;
         pl.seg.off = pl.d_seg;
         HIP_TRY(ctx, hipMemcpy(pl.d_seg, off.data(), sizeof(uint32_t) * (n + 1), hipMemcpyHostToDevice));
+        if ((st = dev_alloc(ctx, &p, sizeof(double) * pl.seg.total, false))) return st;
+        pl.d_segtot = (double *)p;
+        if ((st = dev_alloc(ctx, &p, sizeof(uint32_t) * pl.seg.total, false))) return st;
+        pl.d_segmax = (uint32_t *)p;
+        pl.seg.tot = pl.d_segtot;
+        pl.seg.tmax = pl.d_segmax;
     }
     std::vector<BatchEntry> be(n);
     size_t op = 0, oc = 0, os = 0;

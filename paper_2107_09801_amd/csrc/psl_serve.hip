@@ -101,6 +101,8 @@ struct Server {
     DevBuf<SelPart> d_red;
     DevBuf<uint32_t> d_pend;      // pending list of the iteration's batch
     DevBuf<uint32_t> d_seg, d_adm_seg;   // segment maps (batch, admitted walks)
+    DevBuf<double> d_segtot;             // per segment of the batch map: chunk-sum total
+    DevBuf<uint32_t> d_segmax;
     SegMap seg{};
     DevBuf<double> d_adm_s0;      // chunk arrays of the admitted walks' fitness pass
     DevBuf<uint32_t> d_adm_m0;
@@ -418,7 +420,10 @@ psl_status Server::upload_layout(char *&sp, char *stage_end)
     uint32_t *off = (uint32_t *)sp;
     sp += sizeof(uint32_t) * (n + 1);
     seg = seg_prefix(Ls.data(), n, off);
+    if ((st = grow(ctx, d_segtot, seg.total)) || (st = grow(ctx, d_segmax, seg.total))) return st;
     seg.off = d_seg.p;
+    seg.tot = d_segtot.p;
+    seg.tmax = d_segmax.p;
     HIP_TRY(ctx, hipMemcpyAsync(d_seg.p, off, sizeof(uint32_t) * (n + 1), hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(ctx, launch_near_reset(d_batch.p, n, d_pend.p, ctx->stream));
     n_items = (uint32_t)items;
@@ -616,6 +621,8 @@ void serve_shutdown(psl_ctx *ctx)
     release(ctx, s->d_pend);
     release(ctx, s->d_seg);
     release(ctx, s->d_adm_seg);
+    release(ctx, s->d_segtot);
+    release(ctx, s->d_segmax);
     release(ctx, s->d_adm_s0);
     release(ctx, s->d_adm_m0);
     release(ctx, s->d_want);

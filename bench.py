@@ -100,6 +100,11 @@ def parse():
                     help="jobs in the served vs one-walk-per-launch comparison (0: skip)")
     ap.add_argument("--compare-uneven-steps", type=int, default=2,
                     help="uneven workload: steps of the batch-vs-one-walk-per-launch comparison (0 = off)")
+    ap.add_argument("--study", default="", choices=["", "paper-sweep", "alpha-ablation"],
+                    help="instead of the benchmark: the paper-settings speed sweep over L, or the alpha ablation")
+    ap.add_argument("--nse", type=float, default=1e9, help="alpha ablation: sequence evaluations per run")
+    ap.add_argument("--runs", type=int, default=30, help="alpha ablation: runs per alpha pair")
+    ap.add_argument("--sweep-seconds", type=float, default=4.0, help="paper sweep: seconds per L and mode")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before the run, one device-to-device copy of this many MiB "
                          "(a known-size kernel to scale profiler byte counters)")
@@ -301,6 +306,82 @@ def run_uneven_compare(libpsl, groups, steps: int, period: int) -> dict:
             "results_identical": bool(same)}
 
 
+# Paper, Table 2 (L = 65535, 30 runs, NSE = 1e10, N_lmt = 6912): mean PSL.
+PAPER_ALPHA_MEAN_PSL = {"4/13": 212.700, "4/4": 232.833, "13/13": 238.967}
+
+
+def run_paper_sweep(libpsl, seconds: float) -> dict:
+    """The paper's speed settings (N_lmt = 6912, alpha 4/10, LS_lmt = 2000,
+    FLIP_lmt = 10, the switch rule of Algorithm 1) for every L = 2^m - 1,
+    m = 14..20: one walk alone (captured-graph steps), and a batch of walks
+    that fills the GPU; flip-evals/s against Table 4's A100 figure."""
+    import seeded_inputs as si
+    ctx = libpsl.Context(0)
+    rows = []
+    for m in range(14, 21):
+        L = 2 ** m - 1
+        kw = dict(alpha1=4, alpha2=10, n_lmt=6912, ls_lmt=2000, flip_lmt=10, switch_period=0)
+        row = {"L": L, "A100_flip_evals_per_s": PAPER_A100_NSE[L]}
+        for label, count in (("one_walk", 1), ("batch", 64 if m <= 18 else 16)):
+            ids = ctx.init_walks(L, count, si.BASE_SEED + 500 * m, **kw)
+            ctx.step_batch(ids, 3, blocking=True, graph=True)
+            t0 = time.perf_counter()
+            ctx.step_batch(ids, 3, blocking=True, graph=True)
+            per = (time.perf_counter() - t0) / 3
+            steps = max(3, int(seconds / 2 / max(per, 1e-6)))
+            t0 = time.perf_counter()
+            ctx.step_batch(ids, steps, blocking=True, graph=True)
+            el = time.perf_counter() - t0
+            rate = count * 6912 * steps / el
+            row[label] = {"walks": count, "steps": steps, "flip_evals_per_s": rate,
+                          "vs_A100": rate / PAPER_A100_NSE[L]}
+            ctx.free_walks(ids)
+        log(f"paper sweep L={L}: one walk {row['one_walk']['flip_evals_per_s']:.3g}, "
+            f"batch {row['batch']['flip_evals_per_s']:.3g} flip-evals/s")
+        rows.append(row)
+    ctx.close()
+    return {"study": "paper-settings speed sweep (Table 4 settings)", "rows": rows}
+
+
+def run_alpha_ablation(libpsl, nse: float, runs: int) -> dict:
+    """Table 2's alpha study at a reduced budget: L = 65535, N_lmt = 6912,
+    LS_lmt = 2000, FLIP_lmt = 10, the switch rule of Algorithm 1; alpha_1 /
+    alpha_2 = 4/13, 4/4 and 13/13, `runs` walks each (all stepped as one
+    batch), each stopped after `nse` sequence evaluations. Reports the best
+    PSL found per walk."""
+    import numpy as np
+
+    import seeded_inputs as si
+    L, n_lmt = 65535, 6912
+    configs = [(4, 13), (4, 4), (13, 13)]
+    ctx = libpsl.Context(0)
+    ids = {}
+    for c, (a1, a2) in enumerate(configs):
+        ids[(a1, a2)] = ctx.init_walks(L, runs, si.BASE_SEED + 10000 * (c + 1), alpha1=a1, alpha2=a2,
+                                       n_lmt=n_lmt, ls_lmt=2000, flip_lmt=10, switch_period=0)
+    every = [w for v in ids.values() for w in v]
+    steps = int(nse // n_lmt)
+    done, chunk = 0, 2000
+    t0 = time.perf_counter()
+    while done < steps:
+        k = min(chunk, steps - done)
+        ctx.step_batch(every, k, blocking=True, graph=True)
+        done += k
+        log(f"alpha ablation: {done}/{steps} steps, {time.perf_counter() - t0:.0f} s")
+    el = time.perf_counter() - t0
+    out = {"study": "alpha ablation (Table 2 settings, reduced budget)", "L": L, "n_lmt": n_lmt,
+           "runs_per_config": runs, "nse_per_run": steps * n_lmt, "wall_s": el,
+           "flip_evals_per_s": len(every) * n_lmt * steps / el, "configs": {}}
+    for (a1, a2), ws in ids.items():
+        p = np.array([ctx.read_walk(w, bits=False, C=False)["psl_best"] for w in ws])
+        key = f"{a1}/{a2}"
+        out["configs"][key] = {"psl_mean": float(p.mean()), "psl_std": float(p.std(ddof=1)) if len(p) > 1 else 0.0,
+                               "psl_min": int(p.min()), "psl_max": int(p.max()),
+                               "paper_psl_mean_at_1e10": PAPER_ALPHA_MEAN_PSL[key]}
+    ctx.close()
+    return out
+
+
 def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -317,6 +398,12 @@ def main():
     from paper_2107_09801_amd import libpsl
 
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.study == "paper-sweep":
+        print(json.dumps(run_paper_sweep(libpsl, args.sweep_seconds)), flush=True)
+        return
+    if args.study == "alpha-ablation":
+        print(json.dumps(run_alpha_ablation(libpsl, args.nse, args.runs)), flush=True)
+        return
     UNEVEN = [(14, 512), (15, 256), (16, 128), (17, 64), (18, 32), (19, 16), (20, 8)]
     wl = args.workload
     period, ls_lmt = args.switch_period, 2000

@@ -659,12 +659,14 @@ constexpr int kOneItems = 4 * kOneQuads;   // table-building items per window
 
 // LDS of one evaluation block.
 struct EvalLds {
+    // first, so that a window's two-word read needs no base offset (the
+    // offsets of ds_read2_b32 are 8-bit dword counts)
+    uint32_t bits[kEvalWavesMax * 64];  // per wavefront: its pivot words of the tile
     double rows[kTileK * kRowStride];   // T(|C_k + 2m|), m = -2..2, per shift
     double both[kPairs * 16];           // pair sums, both neighbours
     double one[kChunks * kOneWin];      // quad sums, one neighbour
     uint32_t both_max[kPairs * 16];     // max hi32 of the pair (dense PSL only)
     uint32_t one_max[kChunks * kOneWin];
-    uint32_t bits[kEvalWavesMax * 64];  // per wavefront: its pivot words of the tile
     int kend[kEvalWavesMax];            // per wavefront
     int bmax[kEvalWavesMax];
     int omax[kEvalWavesMax];

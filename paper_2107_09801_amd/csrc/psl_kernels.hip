@@ -830,26 +830,39 @@ __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const 
                     // (2q+1): its two left bits below its two right bits
                     const uint32_t W0 = (XL & 0x33333333u) | ((XR << 2) & 0xCCCCCCCCu);
                     const uint32_t W1 = ((XL >> 2) & 0x33333333u) | (XR & 0xCCCCCCCCu);
+                    // the reads go out in groups of eight before their adds
 #pragma unroll
-                    for (int p = 0; p < 16; ++p) {
-                        const uint32_t x = ((p & 1 ? W1 : W0) >> (4 * (p >> 1))) & 15u;
-                        acc += bp[16 * p + x];
-                        if (kMax) mx = max(mx, bq[16 * p + x]);
+                    for (int h = 0; h < 16; h += 8) {
+                        double v[8];
+#pragma unroll
+                        for (int p = h; p < h + 8; ++p) {
+                            const uint32_t x = ((p & 1 ? W1 : W0) >> (4 * (p >> 1))) & 15u;
+                            v[p - h] = bp[16 * p + x];
+                            if (kMax) mx = max(mx, bq[16 * p + x]);
+                        }
+#pragma unroll
+                        for (int p = 0; p < 8; ++p) acc += v[p];
                     }
                 } else if (tcount == 32 && k0 + 31 <= jr_min && k0 > jl_max) {
+                    double v[kOneQuads];
 #pragma unroll
                     for (int q = 0; q < kOneQuads; ++q) {
                         const uint32_t x = (XR >> (4 * q)) & 15u;
-                        acc += op[16 * q + x];
+                        v[q] = op[16 * q + x];
                         if (kMax) mx = max(mx, oq[16 * q + x]);
                     }
+#pragma unroll
+                    for (int q = 0; q < kOneQuads; ++q) acc += v[q];
                 } else if (tcount == 32 && k0 + 31 <= jl_min && k0 > jr_max) {
+                    double v[kOneQuads];
 #pragma unroll
                     for (int q = 0; q < kOneQuads; ++q) {
                         const uint32_t x = (XL >> (4 * q)) & 15u;
-                        acc += op[16 * q + x];
+                        v[q] = op[16 * q + x];
                         if (kMax) mx = max(mx, oq[16 * q + x]);
                     }
+#pragma unroll
+                    for (int q = 0; q < kOneQuads; ++q) acc += v[q];
                 } else {
                     // mixed bounds or a partial chunk: per shift
                     const double *rb = sh.rows + (32 * cc) * kRowStride;

@@ -813,13 +813,22 @@ __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const 
         __syncthreads();
 
         double acc = 0.0;
+        // the next window's words are read one window ahead (slots past
+        // the staged ones hold stale words that are never used)
+        uint32_t r0 = rbits[0], r1 = rbits[1], l0 = lbits[0], l1 = lbits[1];
 #pragma unroll
         for (int cc = 0; cc < kChunks; ++cc) {
             const int k0 = kt + 32 * cc;
+            const uint32_t cr0 = r0, cr1 = r1, cl0 = l0, cl1 = l1;
+            if (cc + 1 < kChunks) {
+                r0 = rbits[cc + 1];
+                r1 = rbits[cc + 2];
+                l0 = lbits[cc + 1];
+                l1 = lbits[cc + 2];
+            }
             if (k0 < k_wend) {
-                const uint32_t XR = __builtin_amdgcn_alignbit(rbits[cc + 1], rbits[cc], sh_r) ^ SJ;
-                const uint32_t XL = __builtin_bitreverse32(
-                    __builtin_amdgcn_alignbit(lbits[cc], lbits[cc + 1], sh_l) ^ SJ);
+                const uint32_t XR = __builtin_amdgcn_alignbit(cr1, cr0, sh_r) ^ SJ;
+                const uint32_t XL = __builtin_bitreverse32(__builtin_amdgcn_alignbit(cl0, cl1, sh_l) ^ SJ);
                 const int tcount = min(32, kt_end - k0);
                 const double *bp = sh.both + (16 * 16) * cc;
                 const double *op = sh.one + kOneWin * cc;

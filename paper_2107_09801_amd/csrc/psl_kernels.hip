@@ -1365,15 +1365,6 @@ __global__ __launch_bounds__(kBookThreads) void k_bookkeep(WalkDev *walks, const
 
 // ------------------------------------------------------------ launches
 
-// O(L) kernels stride over k with at most max(32, 2048 / walks) blocks per
-// walk, so a batch of many walks of very different L launches no
-// mostly-empty grid while a single walk still spreads over the GPU.
-static uint32_t lin_blocks(uint32_t max_L, uint32_t nb)
-{
-    const uint32_t cap = std::max<uint32_t>(32, 2048 / std::max<uint32_t>(nb, 1));
-    return std::min<uint32_t>(std::max<uint32_t>((max_L + 255) / 256, 1), cap);
-}
-
 hipError_t launch_power_table(double *T, uint32_t n, uint32_t alpha, hipStream_t s)
 {
     k_power_table<<<(n + 255) / 256, 256, 0, s>>>(T, n, alpha);
@@ -1383,16 +1374,25 @@ hipError_t launch_power_table(double *T, uint32_t n, uint32_t alpha, hipStream_t
 hipError_t launch_init_bits(WalkDev *walks, const BatchEntry *batch, const uint32_t *want,
                             uint32_t nb, uint32_t max_nw, hipStream_t s)
 {
-    k_init_bits<<<dim3((max_nw + 255) / 256, nb), 256, 0, s>>>(walks, batch, want);
-    return hipGetLastError();
+    for (uint32_t b0 = 0; b0 < nb; b0 += kMaxGridY) {
+        k_init_bits<<<dim3((max_nw + 255) / 256, std::min(kMaxGridY, nb - b0)), 256, 0, s>>>(walks, batch + b0,
+                                                                                             want + b0);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_corr(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t max_L,
                        int only_pending, hipStream_t s)
 {
-    k_corr<<<dim3((max_L + kCorrThreads - 1) / kCorrThreads, nb), kCorrThreads, 0, s>>>(walks, batch,
-                                                                                       only_pending);
-    return hipGetLastError();
+    for (uint32_t b0 = 0; b0 < nb; b0 += kMaxGridY) {
+        k_corr<<<dim3((max_L + kCorrThreads - 1) / kCorrThreads, std::min(kMaxGridY, nb - b0)), kCorrThreads, 0,
+                 s>>>(walks, batch + b0, only_pending);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_switch_corr(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t max_L,

@@ -208,7 +208,7 @@ def test_batch_matches_single_walks(ctx):
     ctx.free_walks(solo + mixed)
 
 
-@pytest.mark.parametrize("flip", [1, 10, 40, 64, 65, 90])
+@pytest.mark.parametrize("flip", [0, 1, 10, 40, 64, 65, 90])
 def test_switch_every_step_against_oracle(ctx, flip):
     """Every walk of a mixed batch switches after every step, so every step
     rebuilds C from local_best's C through the pending list (FLIP_lmt <= 64:

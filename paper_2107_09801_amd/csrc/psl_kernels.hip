@@ -827,14 +827,19 @@ __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const 
                 l1 = lbits[cc + 2];
             }
             if (k0 < k_wend) {
-                const uint32_t XR = __builtin_amdgcn_alignbit(cr1, cr0, sh_r) ^ SJ;
-                const uint32_t XL = __builtin_bitreverse32(__builtin_amdgcn_alignbit(cl0, cl1, sh_l) ^ SJ);
+                // a side's window bits, x = 1 where s_j times the neighbour is
+                // -1 (formed only in the forms that use that side)
+                auto win_r = [&]() { return __builtin_amdgcn_alignbit(cr1, cr0, sh_r) ^ SJ; };
+                auto win_l = [&]() {
+                    return __builtin_bitreverse32(__builtin_amdgcn_alignbit(cl0, cl1, sh_l) ^ SJ);
+                };
                 const int tcount = min(32, kt_end - k0);
                 const double *bp = sh.both + (16 * 16) * cc;
                 const double *op = sh.one + kOneWin * cc;
                 const uint32_t *bq = sh.both_max + (16 * 16) * cc;
                 const uint32_t *oq = sh.one_max + kOneWin * cc;
                 if (tcount == 32 && k0 + 31 <= both_max) {
+                    const uint32_t XR = win_r(), XL = win_l();
                     // nibble q of W0 (W1) is the table index of pair 2q
                     // (2q+1): its two left bits below its two right bits
                     const uint32_t W0 = (XL & 0x33333333u) | ((XR << 2) & 0xCCCCCCCCu);
@@ -853,6 +858,7 @@ __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const 
                         for (int p = 0; p < 8; ++p) acc += v[p];
                     }
                 } else if (tcount == 32 && k0 + 31 <= jr_min && k0 > jl_max) {
+                    const uint32_t XR = win_r();
                     double v[kOneQuads];
 #pragma unroll
                     for (int q = 0; q < kOneQuads; ++q) {
@@ -863,6 +869,7 @@ __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const 
 #pragma unroll
                     for (int q = 0; q < kOneQuads; ++q) acc += v[q];
                 } else if (tcount == 32 && k0 + 31 <= jl_min && k0 > jr_max) {
+                    const uint32_t XL = win_l();
                     double v[kOneQuads];
 #pragma unroll
                     for (int q = 0; q < kOneQuads; ++q) {
@@ -874,6 +881,7 @@ __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const 
                     for (int q = 0; q < kOneQuads; ++q) acc += v[q];
                 } else {
                     // mixed bounds or a partial chunk: per shift
+                    const uint32_t XR = win_r(), XL = win_l();
                     const double *rb = sh.rows + (32 * cc) * kRowStride;
                     for (int t = 0; t < tcount; ++t) {
                         const int k = k0 + t;

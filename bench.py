@@ -389,7 +389,7 @@ def log(msg: str):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "libpsl runs walks on one GPU (walks shard across GPUs with no communication, but that is not built); --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch

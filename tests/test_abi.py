@@ -91,3 +91,15 @@ def test_null_context_is_rejected_without_gpu():
     else:
         lib.psl_ctx_destroy(out)
         pytest.skip("a device is present")
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # walks run on one GPU: any other count exits with a message and status 2
+    # before the device is touched
+    import json
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert msg["n_gpus"] == 2 and "--gpus must be 1" in msg["error"]

@@ -88,6 +88,8 @@ def parse():
     ap.add_argument("--n-lmt", type=int, default=0, help="0 = full neighbourhood")
     ap.add_argument("--switch-period", type=int, default=50)
     ap.add_argument("--graph", action="store_true", help="replay a captured step per step")
+    ap.add_argument("--eval-items", type=int, default=0,
+                    help="minimum work items per evaluation launch (0 = the library default)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -419,6 +421,8 @@ def main():
         groups = [(args.L or 131071, args.walks or 64)]
         period = 0
     ctx = libpsl.Context(0)
+    if args.eval_items:
+        ctx.set_option(libpsl.OPT_EVAL_ITEMS, args.eval_items)
     ids, evals_per_step, updates_per_step = [], 0, 0
     for L, count in groups:
         a2 = 10 if wl == "paper" else si.alpha2_for(L)
@@ -493,7 +497,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "walks": nw, "L": [g[0] for g in groups],
                    "walks_per_L": [g[1] for g in groups], "n_lmt": n_lmt, "alpha1": 4,
-                   "alpha2": a2, "switch_period": period, "eval_tiles": tiles, "eval_ksplit": ks},
+                   "alpha2": a2, "switch_period": period, "eval_tiles": tiles, "eval_ksplit": ks,
+                   **({"eval_items": args.eval_items} if args.eval_items else {})},
         "C_k_updates_per_s": updates_per_step * args.steps / el,
         "eval_kernel": {"avg_ms": eval_avg_s * 1e3, "launches": tm["eval_launches"],
                         "updates_per_s": updates_per_step / eval_avg_s,

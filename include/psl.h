@@ -327,6 +327,16 @@ PSL_API psl_status psl_tune_load(psl_ctx *ctx, const char *path);
  * min(4096, max(64, L/16)); 0 forces the in-loop maximum. Both give the same
  * results. Errors: PSL_E_INVAL for an unknown option or value. */
 #define PSL_OPT_NEAR_LIMIT 1
+/* PSL_OPT_EVAL_ITEMS: the number of work items (candidate tile x piece of
+ * the shift range) an evaluation launch offers at least: a walk's shifts are
+ * cut into pieces of about W / value shifts (at least 256), W being the
+ * batch's total (candidate tile x shift) work. More items shorten the tail of
+ * a launch over few long walks, at the cost of more partial sums to combine.
+ * -1: the default, 4096; otherwise 1 .. 262144. It changes the grouping of
+ * the FP64 F sums, so F only by rounding; PSL values are unaffected, and so
+ * are the moves wherever the tolerance band decides them. Errors:
+ * PSL_E_INVAL outside that range. */
+#define PSL_OPT_EVAL_ITEMS 2
 PSL_API psl_status psl_set_option(psl_ctx *ctx, int option, int64_t value);
 
 /* --------------------------------------------------- trace, checkpoint */

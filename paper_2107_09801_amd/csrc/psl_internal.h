@@ -114,6 +114,8 @@ struct BatchPlan {
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 constexpr size_t kPlanCache = 8;   // step batches whose layout (and graph) is kept
+constexpr uint32_t kEvalItemsDefault = 4096;    // PSL_OPT_EVAL_ITEMS default
+constexpr uint32_t kEvalItemsMax = 1u << 18;    // and its largest value
 
 
 struct Server;   // serving loop (psl_serve.hip)
@@ -140,6 +142,7 @@ struct psl_ctx {
     void *d_choice = nullptr;
     std::string err;
     int64_t near_limit = -1;          // PSL_OPT_NEAR_LIMIT
+    uint32_t eval_items = psl_rt::kEvalItemsDefault;  // PSL_OPT_EVAL_ITEMS
     psl_rt::Server *server = nullptr; // serving loop, when started
     uint32_t n_cu = 256;              // compute units of the device
     std::map<uint32_t, psl::EvalShape> tuned;  // autotuner choices by tune_key
@@ -184,9 +187,13 @@ struct EvalLayout {
 uint32_t tune_key(const uint32_t *Ls, const uint32_t *n_lmt, uint32_t n);
 // The evaluation shape for a batch: the tuned one for its key, else defaults.
 EvalShape pick_shape(const psl_ctx *ctx, const uint32_t *Ls, const uint32_t *n_lmt, uint32_t n);
+// min_items: the work items the launch should offer at least (the shifts of
+// a walk split into pieces of about W / min_items, W the batch's total
+// (candidate tile x shift) work).
 void eval_layout(const uint32_t *Ls, const uint32_t *n_lmt, uint32_t n, const EvalShape &shape,
-                 EvalLayout &out);
+                 uint32_t min_items, EvalLayout &out);
 void eval_shape_k(uint32_t L, uint32_t n_lmt, uint32_t K, uint32_t tile, uint32_t *tiles, uint32_t *ksplit);
+uint32_t item_shifts_for(uint64_t W, uint32_t tile, uint32_t min_items);
 uint32_t max_blocks_per_cu(int waves);
 // Segment maps of the O(L) passes: every walk of length L; or off[0..n] =
 // prefix sums of the walks' segment counts (the returned map's off is left

@@ -165,10 +165,10 @@ bool walk_ok(const psl_ctx *ctx, uint32_t id)
 
 // Evaluation shape of a batch. Candidates go in tiles of one block (64 lanes
 // per wavefront; 4 wavefronts when most walks evaluate at most 256
-// candidates, 16 for batches of at least 256 x 1024 candidates, else 8); the shifts of a walk split into pieces of about
-// K = max(kTileK, W / 4096) shifts, where W is the batch's total
-// (tile x shift) work, so a batch offers at least about 4096 work items and
-// no item is much longer than the batch's average.
+// candidates, 16 for batches of at least 256 x 1024 candidates, else 8); the
+// shifts of a walk split into pieces of K shifts (item_shifts_for), so a
+// batch offers at least about 4096 work items (PSL_OPT_EVAL_ITEMS) and no
+// item is much longer than the batch's average.
 // Evaluation blocks resident per CU: the LDS of a block admits three; 16
 // wavefronts per block are limited to two by the CU's wavefront slots.
 // The largest segment (256 .. 4096 shifts) that still gives the pass about
@@ -216,11 +216,28 @@ int eval_waves(const uint32_t *nl, uint32_t n)
     return total >= 256ull * 64 * kEvalWavesMax ? kEvalWavesMax : kEvalWaves;
 }
 
-static uint32_t item_shifts(const uint32_t *Ls, const uint32_t *nl, uint32_t n, uint32_t tile)
+// Shifts per work item for W (candidate tile x shift) units of work: about
+// W / min_items, but an item of more than 2^24 updates (K_big shifts of a
+// tile) is cut down to K_big while the launch stays within max(65536,
+// min_items) items. A launch over one or a few long walks otherwise has a
+// few thousand items of several milliseconds each, whose different costs
+// (both, one or no neighbour per shift) leave CUs idle at its end; batches
+// of many walks keep one item per candidate tile.
+uint32_t item_shifts_for(uint64_t W, uint32_t tile, uint32_t min_items)
+{
+    const uint64_t n_max = std::max<uint64_t>(65536, min_items);
+    const uint64_t k_big = std::max<uint64_t>(kTileK, (1ull << 24) / tile);
+    const uint64_t k = std::max<uint64_t>((W + n_max - 1) / n_max,
+                                          std::min<uint64_t>(k_big, (W + min_items - 1) / min_items));
+    return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(kTileK, k), UINT32_MAX);
+}
+
+static uint32_t item_shifts(const uint32_t *Ls, const uint32_t *nl, uint32_t n, uint32_t tile,
+                            uint32_t min_items)
 {
     uint64_t W = 0;
     for (uint32_t b = 0; b < n; ++b) W += (uint64_t)((nl[b] + tile - 1) / tile) * (Ls[b] - 1);
-    return (uint32_t)std::max<uint64_t>(kTileK, (W + 4095) / 4096);
+    return item_shifts_for(W, tile, min_items);
 }
 
 void eval_shape_k(uint32_t L, uint32_t n_lmt, uint32_t K, uint32_t tile, uint32_t *tiles, uint32_t *ksplit)
@@ -264,14 +281,14 @@ EvalShape pick_shape(const psl_ctx *ctx, const uint32_t *Ls, const uint32_t *nl,
 }
 
 void eval_layout(const uint32_t *Ls, const uint32_t *nl, uint32_t n, const EvalShape &shape,
-                 EvalLayout &out)
+                 uint32_t min_items, EvalLayout &out)
 {
     out.shape = shape;
     out.tiles.assign(n, 0);
     out.ks.assign(n, 0);
     out.items.clear();
     const uint32_t tile = 64u * shape.waves;
-    const uint32_t K = item_shifts(Ls, nl, n, tile);
+    const uint32_t K = item_shifts(Ls, nl, n, tile, min_items);
     struct C { EvalItem it; double cost; };
     std::vector<C> all;
     double total = 0.0;
@@ -353,7 +370,7 @@ psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t 
     }
     EvalLayout lay;
     const EvalShape shape = force ? *force : pick_shape(ctx, Ls.data(), n_l.data(), n);
-    eval_layout(Ls.data(), n_l.data(), n, shape, lay);
+    eval_layout(Ls.data(), n_l.data(), n, shape, ctx->eval_items, lay);
     const std::vector<uint32_t> &tiles = lay.tiles, &ks = lay.ks;
     std::vector<EvalItem> &items = lay.items;
     pl.shape = lay.shape;
@@ -1072,11 +1089,15 @@ psl_status psl_set_option(psl_ctx *ctx, int option, int64_t value)
 {
     if (!ctx) return PSL_E_INVAL;
     if (serve_active(ctx)) return fail(ctx, PSL_E_STATE, "the context is serving");
-    if (option != PSL_OPT_NEAR_LIMIT || value < -1)
-        return fail(ctx, PSL_E_INVAL, "option %d value %lld", option, (long long)value);
+    const bool ok = (option == PSL_OPT_NEAR_LIMIT && value >= -1) ||
+                    (option == PSL_OPT_EVAL_ITEMS && (value == -1 || (value >= 1 && value <= kEvalItemsMax)));
+    if (!ok) return fail(ctx, PSL_E_INVAL, "option %d value %lld", option, (long long)value);
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    ctx->near_limit = value;
+    if (option == PSL_OPT_NEAR_LIMIT)
+        ctx->near_limit = value;
+    else
+        ctx->eval_items = value < 0 ? kEvalItemsDefault : (uint32_t)value;
     plans_clear(ctx);            // cached layouts carry the old value
     return PSL_OK;
 }
@@ -1219,7 +1240,7 @@ psl_status psl_eval_shape(psl_ctx *ctx, uint32_t L, uint32_t n_lmt, uint32_t n_w
     const uint32_t tile = 64u * (ctx ? pick_shape(ctx, &L, &n_lmt, 1).waves : eval_waves(&n_lmt, 1));
     const uint32_t tiles = (n_lmt + tile - 1) / tile;
     const uint64_t W = (uint64_t)tiles * (L - 1) * n_walks;
-    const uint32_t K = (uint32_t)std::max<uint64_t>(kTileK, (W + 4095) / 4096);
+    const uint32_t K = item_shifts_for(W, tile, ctx ? ctx->eval_items : kEvalItemsDefault);
     eval_shape_k(L, n_lmt, K, tile, cand_tiles, k_splits);
     return PSL_OK;
 }

@@ -355,7 +355,7 @@ psl_status Server::upload_layout(char *&sp, char *stage_end)
         max_L = std::max(max_L, Ls[b]);
     }
     EvalLayout lay;
-    eval_layout(Ls.data(), nls.data(), n, pick_shape(ctx, Ls.data(), nls.data(), n), lay);
+    eval_layout(Ls.data(), nls.data(), n, pick_shape(ctx, Ls.data(), nls.data(), n), ctx->eval_items, lay);
     const std::vector<uint32_t> &tiles = lay.tiles, &ks = lay.ks;
     size_t n_part = 0, n_cand = 0, n_suf = 0;
     for (uint32_t b = 0; b < n; ++b) {
@@ -460,7 +460,7 @@ psl_status Server::iterate()
     retire_finished();
     {
         // worst case of this iteration's uploads: admissions, then the layout
-        // (work items <= 8 x (4096 + candidate tiles) with padding, see eval_layout)
+        // (work items <= 8 x (eval_items + candidate tiles) with padding, see eval_layout)
         const size_t n_adm = std::min<size_t>(pending.size(), cfg.max_slots);
         uint64_t tiles = 0;
         const uint32_t tl = 64 * kEvalWavesSmall;
@@ -470,7 +470,7 @@ psl_status Server::iterate()
             tiles += ((j.cfg.n_lmt ? j.cfg.n_lmt : j.cfg.L) + tl - 1) / tl;
         }
         const size_t need = (n_adm + active.size()) * (sizeof(WalkDev) + 2 * sizeof(BatchEntry) + 16) +
-                            sizeof(EvalItem) * 8 * (4096 + tiles) + 8192;
+                            sizeof(EvalItem) * 8 * ((uint64_t)ctx->eval_items + tiles) + 8192;
         if ((st = ensure_stage(need))) return st;
     }
     char *sp = stage[cur];

@@ -28,6 +28,7 @@ EXPORTS = ["psl_ctx_create", "psl_ctx_destroy", "psl_last_error", "psl_sync", "p
            "psl_autotune", "psl_tune_save", "psl_tune_load", "psl_trace_enable",
            "psl_trace_read", "psl_restore_walk"]
 OPT_NEAR_LIMIT = 1
+OPT_EVAL_ITEMS = 2
 
 
 class PslError(RuntimeError):

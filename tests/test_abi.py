@@ -64,6 +64,13 @@ def test_version_and_shape_without_gpu():
     assert lib.psl_eval_shape(None, 16383, 16383, 1, ctypes.byref(t), ctypes.byref(k)) == 0
     assert t.value == 32 and k.value >= 8
     assert lib.psl_eval_shape(None, 1, 1, 1, ctypes.byref(t), ctypes.byref(k)) == libpsl.E_INVAL
+    # one long walk: items of at most 2^24 updates (16384 shifts of a
+    # 1024-candidate tile), 65536 of them
+    assert lib.psl_eval_shape(None, 1048575, 1048575, 1, ctypes.byref(t), ctypes.byref(k)) == 0
+    assert t.value == 1024 and k.value == 64
+    # short items are not cut further: about 4096 items
+    assert lib.psl_eval_shape(None, 1048575, 6912, 1, ctypes.byref(t), ctypes.byref(k)) == 0
+    assert t.value == 14 and 4096 <= t.value * k.value < 4200
 
 
 def test_serve_footprint_without_gpu():

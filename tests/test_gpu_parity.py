@@ -259,6 +259,64 @@ def test_invalid_arguments(ctx):
         ctx.read_walk(w)
 
 
+def test_empty_batches_and_range_edges(ctx):
+    """Empty inputs are no-ops; configuration limits are enforced on the host."""
+    from paper_2107_09801_amd import libpsl
+    assert ctx.init_walks(1001, 0, 5) == []
+    ctx.step_batch([], 3)
+    (w,) = ctx.init_walks(1001, 1, 5)
+    before = ctx.read_walk(w)
+    ctx.step_batch([w], 0)
+    after = ctx.read_walk(w)
+    assert after["t"] == 0 and np.array_equal(after["C"], before["C"])
+    assert np.array_equal(after["pivot"], before["pivot"])
+    for bad in (dict(L=libpsl.L_MAX + 1), dict(L=1001, alpha1=17), dict(L=1001, alpha2=0),
+                dict(L=1001, flip_lmt=1002), dict(L=3000, flip_lmt=1025)):
+        L = bad.pop("L")
+        with pytest.raises(libpsl.PslError):
+            ctx.init_walks(L, 1, 5, **bad)
+    # the limits themselves are accepted
+    ids = ctx.init_walks(2, 1, 5, flip_lmt=2, alpha1=16, alpha2=1)
+    ids += ctx.init_walks(3000, 1, 5, flip_lmt=1024)
+    ctx.step_batch(ids, 2)
+    for x in ids:
+        g = ctx.read_walk(x)
+        assert g["t"] == 2
+        assert np.array_equal(g["C"], oracle.corr(si.to_pm1(g["pivot"], g["L"])))
+    ctx.free_walks(ids + [w])
+
+
+def test_eval_items_option_keeps_results(ctx):
+    """More or fewer evaluation work items change only how the shifts are cut
+    (the k-splits) and so F by rounding: PSL and the chosen move stay."""
+    import torch
+    from paper_2107_09801_amd import libpsl
+    L, n_lmt, start = 20001, 20001, 777
+    (w,) = ctx.init_walks(L, 1, 4242, alpha1=13, alpha2=4)
+    s, C = _oracle_state(L, 4242)
+    Fo, Po = oracle.eval_neighbourhood(s, C, 13, start, n_lmt, nthreads=8)
+    oc = oracle.select(Fo, Po, margin=MARGIN)
+    splits = set()
+    try:
+        for v in (1, 64, 4096, 65536, 262144):
+            ctx.set_option(libpsl.OPT_EVAL_ITEMS, v)
+            splits.add(ctx.eval_shape(L, n_lmt, 1)[1])
+            F, P = _dev(n_lmt, torch.float64), _dev(n_lmt, torch.int32)
+            ch = ctx.eval_neighbourhood(w, start, n_lmt, F, P)
+            assert np.array_equal(P.cpu().numpy(), Po), v
+            assert _rel(F.cpu().numpy(), Fo) <= F_RTOL, v
+            assert ch["psl_min"] == oc.psl_min
+            if not oc.flags & oracle.AMBIG_ARGMIN:
+                assert ch["i_best"] == oc.i_best, v
+        for bad in (0, -2, 262145):
+            with pytest.raises(libpsl.PslError):
+                ctx.set_option(libpsl.OPT_EVAL_ITEMS, bad)
+    finally:
+        ctx.set_option(libpsl.OPT_EVAL_ITEMS, -1)
+    assert len(splits) >= 3          # the option reached the layout
+    ctx.free_walks([w])
+
+
 def test_graph_replays_match_eager(ctx):
     """One captured step replayed many times, with eager work and syncs between
     replays, equals the eager path after every replay."""

@@ -639,15 +639,17 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(WalkDev *walks, const Bat
     }
 }
 
-// Wave-wide minimum / maximum of an int (result uniform).
-__device__ __forceinline__ int wave_min(int v)
+// Wave-wide minimum / maximum of an int (result uniform; every lane of the
+// wavefront active). lane = this lane's index in its wavefront, passed in
+// so that the permute addresses derive from the caller's value.
+__device__ __forceinline__ int wave_min(int v, int lane)
 {
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __builtin_amdgcn_ds_bpermute((lane ^ o) << 2, v));
     return __builtin_amdgcn_readfirstlane(v);
 }
-__device__ __forceinline__ int wave_max(int v)
+__device__ __forceinline__ int wave_max(int v, int lane)
 {
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __builtin_amdgcn_ds_bpermute((lane ^ o) << 2, v));
     return __builtin_amdgcn_readfirstlane(v);
 }
 
@@ -678,7 +680,7 @@ template <int WAVES, bool kMax>
 __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const BatchEntry &be,
                                            const EvalItem &it, const double *__restrict__ T,
                                            uint32_t n_lmt, int j, uint32_t SJ, int k_lo, int k_hi,
-                                           double &sum, double &comp, uint32_t &mx)
+                                           int tid, double &sum, double &comp, uint32_t &mx)
 {
     const int L = (int)w.L;
     const int32_t *__restrict__ C = w.C;
@@ -686,16 +688,17 @@ __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const 
 
     // in-bounds limits: right neighbour for k <= jr, left for k <= jl
     const int jl = j, jr = L - 1 - j;
-    const int jl_min = wave_min(jl), jl_max = wave_max(jl);
-    const int jr_min = wave_min(jr), jr_max = wave_max(jr);
+    const int lane = tid & 63;
+    const int jl_min = wave_min(jl, lane), jl_max = wave_max(jl, lane);
+    const int jr_min = wave_min(jr, lane), jr_max = wave_max(jr, lane);
     const int both_max = min(jl_min, jr_min);             // all lanes: both exist
     const int one_max = max(jl_min, jr_min);              // all lanes: one exists
     // first shift at which every lane of the wave has neither neighbour,
     // rounded up to a chunk start; explicit shifts end there
     const int k_none = max(jl_max, jr_max) + 1;
     const int k_wend = min(k_hi, 1 + 32 * ((k_none - 1 + 31) / 32));
-    const int wave = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
+    const int wave = tid >> 6;
+    if ((tid & 63) == 0) {
         sh.kend[wave] = k_wend;
         sh.bmax[wave] = both_max;
         sh.omax[wave] = one_max;
@@ -719,12 +722,11 @@ __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const 
     // words in decreasing order.
     const uint32_t sh_r = (uint32_t)(j + 1) & 31u;
     const uint32_t sh_l = (uint32_t)j & 31u;
-    const int lane = threadIdx.x & 63;
-    const int j_first = __shfl(j, 0);
+    const int j_first = __builtin_amdgcn_readlane(j, 0);
     const int grp = j < j_first ? 1 : 0;
     constexpr int kNone = 1 << 30;                        // empty run: min > max
-    const int jmn0 = wave_min(grp ? kNone : j), jmx0 = wave_max(grp ? -kNone : j);
-    const int jmn1 = wave_min(grp ? j : kNone), jmx1 = wave_max(grp ? j : -kNone);
+    const int jmn0 = wave_min(grp ? kNone : j, lane), jmx0 = wave_max(grp ? -kNone : j, lane);
+    const int jmn1 = wave_min(grp ? j : kNone, lane), jmx1 = wave_max(grp ? j : -kNone, lane);
     const int jmn = grp ? jmn1 : jmn0, jmx = grp ? jmx1 : jmx0;
     const uint32_t *rbits = sh.bits + 64 * wave + 32 * grp + (((j + 1) >> 5) - ((jmn + 1) >> 5));
     const uint32_t *lbits = sh.bits + 64 * wave + 32 * grp + 16 + ((jmx >> 5) - (j >> 5));
@@ -750,7 +752,7 @@ __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const 
                 sh.bits[64 * wave + lane] = w32[word];
             }
         }
-        for (int t = threadIdx.x; t < nt; t += 64 * WAVES) {
+        for (int t = tid; t < nt; t += 64 * WAVES) {
             const int c = C[kt + t];
 #pragma unroll
             for (int m = 0; m < kRowStride; ++m) {
@@ -765,7 +767,7 @@ __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const 
             // Entry x of pair p: low two bits the left pair (xl_k, xl_k+1),
             // high two the right pair; one thread per (pair, right bits)
             // writes its four consecutive entries.
-            for (int e = threadIdx.x; e < kPairs * 4; e += 64 * WAVES) {
+            for (int e = tid; e < kPairs * 4; e += 64 * WAVES) {
                 const int p = e >> 2, r0 = e & 1, r1 = (e >> 1) & 1;
                 if (2 * p + 1 < nt) {
                     const double *ra = sh.rows + (2 * p) * kRowStride + 2 * r0;
@@ -787,7 +789,7 @@ __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const 
             // quad q: bit i of x is the bit of shift 4q + i. Item (q, h) of a
             // window writes the four consecutive entries whose two high bits
             // are h: (a + b) + (c + d).
-            for (int f = threadIdx.x; f < kChunks * kOneItems; f += 64 * WAVES) {
+            for (int f = tid; f < kChunks * kOneItems; f += 64 * WAVES) {
                 const int cc = f / kOneItems, r = f - cc * kOneItems;
                 const int q = r >> 2, h0 = r & 1, h1 = (r >> 1) & 1;
                 const int t0 = 32 * cc + 4 * q;
@@ -928,7 +930,7 @@ __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const 
 template <int WAVES>
 __device__ __forceinline__ void eval_item(EvalLds &sh, const WalkDev *__restrict__ walks,
                                           const BatchEntry *__restrict__ batch, const EvalItem it,
-                                          const Tables &tabs)
+                                          const Tables &tabs, int tid)
 {
     const BatchEntry be = batch[it.walk];
     const WalkDev &w = walks[be.slot];
@@ -947,7 +949,7 @@ __device__ __forceinline__ void eval_item(EvalLds &sh, const WalkDev *__restrict
     const int k_hi = min(L, 1 + 32 * c_hi);
 
     // this lane's candidate; inactive lanes keep a valid j and store nothing
-    const uint32_t i = it.tile * (64 * WAVES) + threadIdx.x;
+    const uint32_t i = it.tile * (64 * WAVES) + (uint32_t)tid;
     const bool active = i < n_lmt;
     const uint32_t ii = active ? i : n_lmt - 1;
     const int j = (int)((start + 1u + ii) % (uint32_t)L);
@@ -958,9 +960,9 @@ __device__ __forceinline__ void eval_item(EvalLds &sh, const WalkDev *__restrict
     uint32_t mx = 0;
     const uint32_t n_near = be.near[0];
     if (n_near > be.near_lim) {
-        eval_sweep<WAVES, true>(sh, w, be, it, T, n_lmt, j, SJ, k_lo, k_hi, sum, comp, mx);
+        eval_sweep<WAVES, true>(sh, w, be, it, T, n_lmt, j, SJ, k_lo, k_hi, tid, sum, comp, mx);
     } else {
-        eval_sweep<WAVES, false>(sh, w, be, it, T, n_lmt, j, SJ, k_lo, k_hi, sum, comp, mx);
+        eval_sweep<WAVES, false>(sh, w, be, it, T, n_lmt, j, SJ, k_lo, k_hi, tid, sum, comp, mx);
         if (it.ks == 0) {
             // PSL over the near-peak shifts, every candidate, all bounds cases
             const int jl = j, jr = L - 1 - j;
@@ -1005,7 +1007,7 @@ void k_eval(const WalkDev *__restrict__ walks,
     __shared__ EvalLds sh;
     const EvalItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
     if (it.walk == kNoItem) return;     // padding of an XCD's range
-    eval_item<WAVES>(sh, walks, batch, it, tabs);
+    eval_item<WAVES>(sh, walks, batch, it, tabs, (int)threadIdx.x);
 }
 
 // Persistent form: a fixed grid (blocks per CU x CUs) takes items from 8
@@ -1034,7 +1036,13 @@ void k_eval_persistent(const WalkDev *__restrict__ walks,
             ++dry;
             continue;
         }
-        eval_item<WAVES>(sh, walks, batch, items[item], tabs);
+        // the thread index, opaque to the compiler once per item: values
+        // derived from it are computed per item instead of being hoisted
+        // out of this loop, where they would outlive every item in scratch
+        int tid = (int)threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        __builtin_assume(tid >= 0 && tid < 64 * WAVES);
+        eval_item<WAVES>(sh, walks, batch, items[item], tabs, tid);
     }
 }
 

@@ -269,13 +269,13 @@ EvalShape pick_shape(const psl_ctx *ctx, const uint32_t *Ls, const uint32_t *nl,
     if (it != ctx->tuned.end()) return it->second;
     EvalShape sh;
     sh.waves = eval_waves(nl, n);
-    // batches of very different L: dynamic per-XCD queues
-    uint32_t lmax = 0, lmin = UINT32_MAX;
-    for (uint32_t b = 0; b < n; ++b) {
-        lmax = std::max(lmax, Ls[b]);
-        lmin = std::min(lmin, Ls[b]);
-    }
-    sh.persistent = lmax > 4ull * lmin ? 1 : 0;
+    // launches of at least 2^38 nominal updates (about 10 ms): a fixed grid
+    // over the per-XCD queues, which evens out items of different cost and
+    // XCDs of different load; shorter launches pay more for the queues than
+    // they gain and stay one block per item
+    uint64_t updates = 0;
+    for (uint32_t b = 0; b < n; ++b) updates += (uint64_t)nl[b] * (Ls[b] - 1);
+    sh.persistent = updates >= (1ull << 38) ? 1 : 0;
     sh.grid = sh.persistent ? max_blocks_per_cu(sh.waves) * ctx->n_cu : 0;
     return sh;
 }

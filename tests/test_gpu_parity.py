@@ -25,6 +25,7 @@ def ctx(request):
     c = libpsl.Context(0)
     if request.param == "dense":
         c.set_option(libpsl.OPT_NEAR_LIMIT, 0)
+        c._dense = True
     yield c
     c.close()
 
@@ -376,6 +377,57 @@ def test_autotune_shapes_keep_results(ctx, tmp_path):
     assert other.autotune(ref)["waves"] in (4, 8, 16)
     other.close()
     ctx.free_walks(ids)
+
+
+def test_every_launch_shape_gives_the_same_walks(ctx, tmp_path):
+    """Each evaluation launch shape (4, 8 or 16 wavefronts; one block per
+    item, or a persistent grid of 1..3 blocks per CU over the per-XCD
+    queues), forced through a tuning file, steps a mixed batch (ragged
+    tiles, L from 2 to 9000, several k-splits) to the same walks as the
+    untuned default, which the oracle pins elsewhere."""
+    from paper_2107_09801_amd import libpsl
+    Ls = [2, 65, 257, 1001, 3000, 9000]
+
+    def batch(c):
+        ids = []
+        for L in Ls:
+            ids += c.init_walks(L, 2, 57 + L, n_lmt=0, switch_period=4, flip_lmt=min(5, L))
+        return ids
+
+    ref_ctx = libpsl.Context(0)
+    ref = batch(ref_ctx)
+    ref_ctx.step_batch(ref, 9)
+    want = [ref_ctx.read_walk(w) for w in ref]
+    ref_ctx.close()
+    # the batch's tuning key, as the library writes it
+    probe = libpsl.Context(0)
+    pids = batch(probe)
+    probe.autotune(pids)
+    probe.tune_save(str(tmp_path / "key.txt"))
+    key = open(tmp_path / "key.txt").read().split()[0]
+    probe.close()
+    shapes = [(16, 0, 0), (16, 1, 1), (16, 1, 2), (8, 0, 0), (8, 1, 1), (8, 1, 2), (8, 1, 3),
+              (4, 0, 0), (4, 1, 1), (4, 1, 3)]
+    for waves, pers, bpc in shapes:
+        c = libpsl.Context(0)
+        if ctx_is_dense(ctx):
+            c.set_option(libpsl.OPT_NEAR_LIMIT, 0)
+        f = tmp_path / "shape.txt"
+        f.write_text(f"{key} {waves} {pers} {bpc}\n")
+        c.tune_load(str(f))
+        ids = batch(c)
+        c.step_batch(ids, 9)
+        for w, o in zip(ids, want):
+            g = c.read_walk(w)
+            for k in ("pivot", "C", "best", "local_best"):
+                assert np.array_equal(g[k], o[k]), (waves, pers, bpc, k)
+            assert g["psl_best"] == o["psl_best"] and g["t"] == o["t"]
+            assert abs(g["value_local"] - o["value_local"]) <= F_RTOL * o["value_local"]
+        c.close()
+
+
+def ctx_is_dense(ctx):
+    return getattr(ctx, "_dense", False)
 
 
 def test_checkpoint_restore_continues_exactly(ctx):

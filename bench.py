@@ -102,10 +102,14 @@ def parse():
                     help="jobs in the served vs one-walk-per-launch comparison (0: skip)")
     ap.add_argument("--compare-uneven-steps", type=int, default=2,
                     help="uneven workload: steps of the batch-vs-one-walk-per-launch comparison (0 = off)")
-    ap.add_argument("--study", default="", choices=["", "paper-sweep", "alpha-ablation"],
-                    help="instead of the benchmark: the paper-settings speed sweep over L, or the alpha ablation")
+    ap.add_argument("--study", default="", choices=["", "paper-sweep", "alpha-ablation", "restart"],
+                    help="instead of the benchmark: the paper-settings speed sweep over L, the alpha ablation, "
+                         "or the restart protocol")
     ap.add_argument("--nse", type=float, default=1e9, help="alpha ablation: sequence evaluations per run")
     ap.add_argument("--runs", type=int, default=30, help="alpha ablation: runs per alpha pair")
+    ap.add_argument("--rounds", type=int, default=4, help="restart study: rounds")
+    ap.add_argument("--restart-nse", type=float, default=1e8,
+                    help="restart study: sequence evaluations per walk and round")
     ap.add_argument("--sweep-seconds", type=float, default=4.0, help="paper sweep: seconds per L and mode")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before the run, one device-to-device copy of this many MiB "
@@ -384,6 +388,71 @@ def run_alpha_ablation(libpsl, nse: float, runs: int) -> dict:
     return out
 
 
+def run_restart_study(libpsl, L: int, rounds: int, walks: int, nse: float) -> dict:
+    """The restart protocol of Section 4 (the Table 5 runs), scaled down:
+    Table 4's settings (N_lmt = 6912, alpha 4 / alpha2 by L, LS_lmt = 2000,
+    FLIP_lmt = 10, the switch rule of Algorithm 1); round 0 starts `walks`
+    walks from random sequences, every later round starts `walks` walks (new
+    seeds) from the best sequence the previous round found. Each walk of a
+    round is stopped after `nse` sequence evaluations."""
+    import numpy as np
+
+    import seeded_inputs as si
+    n_lmt = min(L, 6912)
+    steps = int(nse // n_lmt)
+    ctx = libpsl.Context(0)
+    out = {"study": "restart from the best sequence (Section 4 protocol, reduced budget)", "L": L,
+           "n_lmt": n_lmt, "alpha1": 4, "alpha2": si.alpha2_for(L), "walks_per_round": walks,
+           "nse_per_walk_per_round": steps * n_lmt, "rounds": []}
+    best_bits, best_psl = None, None
+    t_all = time.perf_counter()
+    for r in range(rounds):
+        init = None if best_bits is None else [best_bits] * walks
+        ids = ctx.init_walks(L, walks, si.BASE_SEED + 20000 + 1000 * r, alpha1=4, alpha2=si.alpha2_for(L),
+                             n_lmt=n_lmt, ls_lmt=2000, flip_lmt=10, switch_period=0, init_bits=init)
+        start_psl = [ctx.read_walk(w, bits=False, C=False)["psl_best"] for w in ids]
+        if best_psl is not None:
+            # every walk of the round starts at the sequence it was given
+            assert all(p == best_psl for p in start_psl), (best_psl, set(start_psl))
+        t0 = time.perf_counter()
+        done = 0
+        while done < steps:
+            k = min(2000, steps - done)
+            ctx.step_batch(ids, k, blocking=True, graph=True)
+            done += k
+        el = time.perf_counter() - t0
+        got = [ctx.read_walk(w, C=False) for w in ids]
+        p = np.array([g["psl_best"] for g in got])
+        b = int(np.argmin(p))
+        best_psl, best_bits = int(p[b]), np.array(got[b]["best"], dtype=np.uint64)
+        out["rounds"].append({"round": r, "start_psl": int(min(start_psl)), "psl_best": best_psl,
+                              "psl_mean": float(p.mean()), "psl_max": int(p.max()), "wall_s": el})
+        log(f"restart round {r}: start {min(start_psl)}, best {best_psl}, mean {p.mean():.1f} ({el:.0f} s)")
+        ctx.free_walks(ids)
+    out["wall_s"] = time.perf_counter() - t_all
+    ctx.close()
+    return out
+
+
+def explicit_updates(groups, wl, n_lmt_arg, nominal_per_step, steps, el):
+    """The nominal C_k-updates counted by `value`'s companion figure include
+    the shifts k > max(j, L-1-j), where neither neighbour of j exists and C'_k
+    = C_k: the evaluation takes them from suffix sums instead of visiting
+    them. For full neighbourhoods (every j once) the remaining, explicitly
+    evaluated (j, k) pairs number L(L-1) - sum_j min(j, L-1-j) per walk; with
+    a limited neighbourhood the count depends on each step's start, and None
+    is returned."""
+    if wl == "paper" or n_lmt_arg:
+        return None
+    def skipped(L):
+        m = L // 2
+        return m * m if L % 2 else m * (m - 1)
+    explicit = sum(c * (L * (L - 1) - skipped(L)) for L, c in groups)
+    return {"per_step": explicit, "per_s": explicit * steps / el,
+            "fraction_of_nominal": explicit / nominal_per_step,
+            "note": "shifts with at least one neighbour of j in bounds; the rest come from suffix sums"}
+
+
 def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -405,6 +474,10 @@ def main():
         return
     if args.study == "alpha-ablation":
         print(json.dumps(run_alpha_ablation(libpsl, args.nse, args.runs)), flush=True)
+        return
+    if args.study == "restart":
+        print(json.dumps(run_restart_study(libpsl, args.L or 65535, args.rounds, args.walks or 64,
+                                           args.restart_nse)), flush=True)
         return
     UNEVEN = [(14, 512), (15, 256), (16, 128), (17, 64), (18, 32), (19, 16), (20, 8)]
     wl = args.workload
@@ -500,6 +573,7 @@ def main():
                    "alpha2": a2, "switch_period": period, "eval_tiles": tiles, "eval_ksplit": ks,
                    **({"eval_items": args.eval_items} if args.eval_items else {})},
         "C_k_updates_per_s": updates_per_step * args.steps / el,
+        "C_k_updates_explicit": explicit_updates(groups, wl, args.n_lmt, updates_per_step, args.steps, el),
         "eval_kernel": {"avg_ms": eval_avg_s * 1e3, "launches": tm["eval_launches"],
                         "updates_per_s": updates_per_step / eval_avg_s,
                         "rest_of_step_avg_ms": tm["rest_ms"] / max(1, tm["steps"])},

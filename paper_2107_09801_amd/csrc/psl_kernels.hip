@@ -1064,6 +1064,7 @@ struct ChoiceDev {
 
 constexpr int kSelThreads = 1024;
 constexpr int kCombThreads = 256;
+constexpr int kCombBatch = 16;      // split loads a combine lane keeps in flight
 
 __device__ __forceinline__ void sel_merge(double &f, int32_t &p, uint32_t &i, double of, int32_t op,
                                           uint32_t oi)
@@ -1101,10 +1102,26 @@ __global__ __launch_bounds__(kCombThreads) void k_combine(const WalkDev *walks, 
         double f = 0.0;
         uint32_t m = 0;
         if (i < n) {
-#pragma unroll 4
-            for (uint32_t x = g; x < ks; x += (uint32_t)G) {
-                f += be.Fpart[(size_t)x * n + i];
-                m = max(m, be.Mpart[(size_t)x * n + i]);
+            // up to kCombBatch of this lane's splits are loaded before they
+            // are added (in split order)
+            for (uint32_t x0 = g; x0 < ks; x0 += (uint32_t)G * kCombBatch) {
+                double v[kCombBatch];
+                uint32_t mv[kCombBatch];
+#pragma unroll
+                for (int u = 0; u < kCombBatch; ++u) {
+                    const uint32_t x = x0 + (uint32_t)u * (uint32_t)G;
+                    if (x < ks) {
+                        v[u] = be.Fpart[(size_t)x * n + i];
+                        mv[u] = be.Mpart[(size_t)x * n + i];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kCombBatch; ++u) {
+                    if (x0 + (uint32_t)u * (uint32_t)G < ks) {
+                        f += v[u];
+                        m = max(m, mv[u]);
+                    }
+                }
             }
         }
         for (int o = G >> 1; o > 0; o >>= 1) {
@@ -1167,29 +1184,26 @@ __global__ __launch_bounds__(kSelThreads) void k_select(WalkDev *walks, const Ba
         pmin = r.p;
         ipmin = r.i;
     }
-    __shared__ double s_f[kSelThreads];
-    __shared__ int32_t s_p[kSelThreads];
-    __shared__ uint32_t s_i[kSelThreads];
-    s_f[threadIdx.x] = fmin;
-    s_p[threadIdx.x] = pmin;
-    s_i[threadIdx.x] = ipmin;
-    __syncthreads();
-    for (int h = kSelThreads / 2; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) {
-            const int o = threadIdx.x + h;
-            if (s_f[o] < s_f[threadIdx.x]) s_f[threadIdx.x] = s_f[o];
-            if (s_p[o] < s_p[threadIdx.x] || (s_p[o] == s_p[threadIdx.x] && s_i[o] < s_i[threadIdx.x])) {
-                s_p[threadIdx.x] = s_p[o];
-                s_i[threadIdx.x] = s_i[o];
-            }
-        }
-        __syncthreads();
+    // block minima: within each wavefront, then across the wavefronts (the
+    // minimum F and the first minimum (PSL, index) do not depend on the order)
+    constexpr int kSelWaves = kSelThreads / 64;
+    __shared__ SelPart s_w[kSelWaves];
+    __shared__ uint32_t s_first[kSelWaves];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int o = 32; o > 0; o >>= 1) {
+        const double of = __shfl_xor(fmin, o);
+        const int32_t op = __shfl_xor(pmin, o);
+        const uint32_t oi = (uint32_t)__shfl_xor((int)ipmin, o);
+        sel_merge(fmin, pmin, ipmin, of, op, oi);
     }
-    const double Fmin = s_f[0];
-    const int32_t Pmin = s_p[0];
-    const uint32_t iPmin = s_i[0];
-    const double thr = Fmin * (1.0 + kTau);
+    if (lane == 0) s_w[wave] = SelPart{fmin, pmin, ipmin};
     __syncthreads();
+    SelPart r = s_w[0];
+    for (int x = 1; x < kSelWaves; ++x) sel_merge(r.f, r.p, r.i, s_w[x].f, s_w[x].p, s_w[x].i);
+    const double Fmin = r.f;
+    const int32_t Pmin = r.p;
+    const uint32_t iPmin = r.i;
+    const double thr = Fmin * (1.0 + kTau);
 
     // first scan index inside the band: rounds of 8 * kSelThreads indices,
     // each thread's eight loads issued together; the first round with a hit
@@ -1207,16 +1221,11 @@ __global__ __launch_bounds__(kSelThreads) void k_select(WalkDev *walks, const Ba
             if (v[u] <= thr) ifirst = i0 + u * kSelThreads + threadIdx.x;
         if (__syncthreads_or(ifirst != UINT_MAX)) break;
     }
-    s_i[threadIdx.x] = ifirst;
+    for (int o = 32; o > 0; o >>= 1) ifirst = min(ifirst, (uint32_t)__shfl_xor((int)ifirst, o));
+    if (lane == 0) s_first[wave] = ifirst;
     __syncthreads();
-    for (int h = kSelThreads / 2; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) {
-            const uint32_t o = s_i[threadIdx.x + h];
-            if (o < s_i[threadIdx.x]) s_i[threadIdx.x] = o;
-        }
-        __syncthreads();
-    }
-    const uint32_t ib = s_i[0];
+    uint32_t ib = s_first[0];
+    for (int x = 1; x < kSelWaves; ++x) ib = min(ib, s_first[x]);
     const uint32_t kb = (uint32_t)(((uint64_t)start + 1u + ib) % L);
     const uint32_t jp = (uint32_t)(((uint64_t)start + 1u + iPmin) % L);
 

@@ -1066,6 +1066,18 @@ constexpr int kSelThreads = 1024;
 constexpr int kCombThreads = 256;
 constexpr int kCombBatch = 16;      // split loads a combine lane keeps in flight
 
+// Candidates [lo, hi) of combine block b of `blocks`: contiguous ranges in
+// scan order, a multiple of the block's candidates per pass (kCombThreads / G)
+// long, so a block's minimum covers a contiguous run of scan indices.
+__device__ __forceinline__ void comb_range(uint32_t n, uint32_t blocks, uint32_t G, uint32_t b, uint32_t &lo,
+                                           uint32_t &hi)
+{
+    const uint32_t cpb = kCombThreads / G;
+    const uint32_t chunk = ((n + blocks - 1) / blocks + cpb - 1) / cpb * cpb;
+    lo = min(n, b * chunk);
+    hi = min(n, lo + chunk);
+}
+
 __device__ __forceinline__ void sel_merge(double &f, int32_t &p, uint32_t &i, double of, int32_t op,
                                           uint32_t oi)
 {
@@ -1097,11 +1109,13 @@ __global__ __launch_bounds__(kCombThreads) void k_combine(const WalkDev *walks, 
     double fmin = INFINITY;
     int32_t pmin = INT_MAX;
     uint32_t ipmin = UINT_MAX;
-    for (uint32_t i0 = blockIdx.x * cpb; i0 < n; i0 += gridDim.x * cpb) {
+    uint32_t lo, hi;
+    comb_range(n, gridDim.x, (uint32_t)G, blockIdx.x, lo, hi);
+    for (uint32_t i0 = lo; i0 < hi; i0 += cpb) {
         const uint32_t i = i0 + threadIdx.x / (uint32_t)G;
         double f = 0.0;
         uint32_t m = 0;
-        if (i < n) {
+        if (i < hi) {
             // up to kCombBatch of this lane's splits are loaded before they
             // are added (in split order)
             for (uint32_t x0 = g; x0 < ks; x0 += (uint32_t)G * kCombBatch) {
@@ -1128,7 +1142,7 @@ __global__ __launch_bounds__(kCombThreads) void k_combine(const WalkDev *walks, 
             f += __shfl_xor(f, o);
             m = max(m, (uint32_t)__shfl_xor((int)m, o));
         }
-        if (g == 0 && i < n) {
+        if (g == 0 && i < hi) {
             // the near-peak path stores the PSL itself; the dense path the
             // high word of T(PSL), which is at least hi32(T(1)) = 0x3FF00000
             // because |C'_{L-1}| = 1 for every sequence
@@ -1163,8 +1177,8 @@ __global__ __launch_bounds__(kCombThreads) void k_combine(const WalkDev *walks, 
 // Otherwise record the choice in the walk and, on a strict PSL improvement,
 // update psl_best and solution_best = pivot with j_psl flipped.
 __global__ __launch_bounds__(kSelThreads) void k_select(WalkDev *walks, const BatchEntry *batch,
-                                                        uint32_t comb_blocks, int pure, ChoiceDev *out,
-                                                        uint32_t *pend)
+                                                        uint32_t comb_blocks, uint32_t comb_group, int pure,
+                                                        ChoiceDev *out, uint32_t *pend)
 {
     // the previous step's pending list has been consumed; this step's
     // bookkeeping refills it
@@ -1184,6 +1198,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select(WalkDev *walks, const Ba
         pmin = r.p;
         ipmin = r.i;
     }
+    const double my_f = fmin;           // this thread's combine block minimum
     // block minima: within each wavefront, then across the wavefronts (the
     // minimum F and the first minimum (PSL, index) do not depend on the order)
     constexpr int kSelWaves = kSelThreads / 64;
@@ -1205,16 +1220,27 @@ __global__ __launch_bounds__(kSelThreads) void k_select(WalkDev *walks, const Ba
     const uint32_t iPmin = r.i;
     const double thr = Fmin * (1.0 + kTau);
 
-    // first scan index inside the band: rounds of 8 * kSelThreads indices,
-    // each thread's eight loads issued together; the first round with a hit
-    // holds the answer
+    // the first band member lies in the first combine block (they cover
+    // contiguous runs of scan indices in order) whose minimum is in the band
+    uint32_t bfirst = my_f <= thr ? (uint32_t)threadIdx.x : UINT_MAX;
+    for (int o = 32; o > 0; o >>= 1) bfirst = min(bfirst, (uint32_t)__shfl_xor((int)bfirst, o));
+    if (lane == 0) s_first[wave] = bfirst;
+    __syncthreads();
+    for (int x = 0; x < kSelWaves; ++x) bfirst = min(bfirst, s_first[x]);
+    uint32_t lo, hi;
+    comb_range(n, comb_blocks, comb_group, bfirst, lo, hi);
+    __syncthreads();                    // s_first is reused below
+
+    // first scan index inside the band within [lo, hi): rounds of
+    // 8 * kSelThreads indices, each thread's eight loads issued together;
+    // the first round with a hit holds the answer
     uint32_t ifirst = UINT_MAX;
-    for (uint32_t i0 = 0; i0 < n; i0 += 8 * kSelThreads) {
+    for (uint32_t i0 = lo; i0 < hi; i0 += 8 * kSelThreads) {
         double v[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const uint32_t i = i0 + u * kSelThreads + threadIdx.x;
-            v[u] = i < n ? be.F[i] : INFINITY;
+            v[u] = i < hi ? be.F[i] : INFINITY;
         }
 #pragma unroll
         for (int u = 7; u >= 0; --u)
@@ -1226,6 +1252,9 @@ __global__ __launch_bounds__(kSelThreads) void k_select(WalkDev *walks, const Ba
     __syncthreads();
     uint32_t ib = s_first[0];
     for (int x = 1; x < kSelWaves; ++x) ib = min(ib, s_first[x]);
+    // with finite F the block holding F_min is in the band, so a member was
+    // found; the clamp only keeps the reads below in bounds otherwise
+    ib = ib < n ? ib : iPmin < n ? iPmin : 0u;
     const uint32_t kb = (uint32_t)(((uint64_t)start + 1u + ib) % L);
     const uint32_t jp = (uint32_t)(((uint64_t)start + 1u + iPmin) % L);
 
@@ -1523,7 +1552,7 @@ hipError_t launch_select(WalkDev *walks, const BatchEntry *batch, uint32_t nb, u
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    k_select<<<nb, kSelThreads, 0, s>>>(walks, batch, comb_blocks, pure, (ChoiceDev *)out, pend);
+    k_select<<<nb, kSelThreads, 0, s>>>(walks, batch, comb_blocks, comb_group, pure, (ChoiceDev *)out, pend);
     return hipGetLastError();
 }
 

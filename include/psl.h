@@ -375,8 +375,11 @@ PSL_API psl_status psl_restore_walk(psl_ctx *ctx, uint32_t walk, const psl_walk_
 
 /* ----------------------------------------------------- introspection */
 
-/* Number of device work items, blocks per item and k-splits the evaluation
- * of one walk of length L with n_lmt candidates uses (for tests and bench). */
+/* Candidate tiles (blocks of candidates) and k-splits the evaluation of one
+ * walk of length L with n_lmt candidates uses when it is stepped in a batch
+ * of n_walks such walks (1 <= n_walks <= 2^20), with the context's tuned
+ * shapes and options when ctx is not NULL (for tests and bench). Errors:
+ * PSL_E_INVAL. */
 PSL_API psl_status psl_eval_shape(psl_ctx *ctx, uint32_t L, uint32_t n_lmt, uint32_t n_walks,
                           uint32_t *cand_tiles, uint32_t *k_splits);
 

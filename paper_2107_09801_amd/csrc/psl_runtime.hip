@@ -217,7 +217,7 @@ int eval_waves(const uint32_t *nl, uint32_t n)
 }
 
 // Shifts per work item for W (candidate tile x shift) units of work: about
-// W / min_items, but an item of more than 2^24 updates (K_big shifts of a
+// W / min_items, but an item of more than 2^23 updates (K_big shifts of a
 // tile) is cut down to K_big while the launch stays within max(65536,
 // min_items) items. A launch over one or a few long walks otherwise has a
 // few thousand items of several milliseconds each, whose different costs
@@ -226,7 +226,7 @@ int eval_waves(const uint32_t *nl, uint32_t n)
 uint32_t item_shifts_for(uint64_t W, uint32_t tile, uint32_t min_items)
 {
     const uint64_t n_max = std::max<uint64_t>(65536, min_items);
-    const uint64_t k_big = std::max<uint64_t>(kTileK, (1ull << 24) / tile);
+    const uint64_t k_big = std::max<uint64_t>(kTileK, (1ull << 23) / tile);
     const uint64_t k = std::max<uint64_t>((W + n_max - 1) / n_max,
                                           std::min<uint64_t>(k_big, (W + min_items - 1) / min_items));
     return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(kTileK, k), UINT32_MAX);
@@ -1235,9 +1235,13 @@ psl_status psl_eval_shape(psl_ctx *ctx, uint32_t L, uint32_t n_lmt, uint32_t n_w
                           uint32_t *cand_tiles, uint32_t *k_splits)
 {
     (void)ctx;
-    if (L < 2 || L > PSL_L_MAX || n_lmt < 1 || n_lmt > L || n_walks < 1 || !cand_tiles || !k_splits)
+    if (L < 2 || L > PSL_L_MAX || n_lmt < 1 || n_lmt > L || n_walks < 1 || n_walks > (1u << 20) || !cand_tiles ||
+        !k_splits)
         return PSL_E_INVAL;
-    const uint32_t tile = 64u * (ctx ? pick_shape(ctx, &L, &n_lmt, 1).waves : eval_waves(&n_lmt, 1));
+    // the shape a batch of n_walks such walks is launched with
+    const std::vector<uint32_t> Ls(n_walks, L), nl(n_walks, n_lmt);
+    const uint32_t tile = 64u * (ctx ? pick_shape(ctx, Ls.data(), nl.data(), n_walks).waves
+                                     : eval_waves(nl.data(), n_walks));
     const uint32_t tiles = (n_lmt + tile - 1) / tile;
     const uint64_t W = (uint64_t)tiles * (L - 1) * n_walks;
     const uint32_t K = item_shifts_for(W, tile, ctx ? ctx->eval_items : kEvalItemsDefault);

@@ -59,8 +59,13 @@ def test_version_and_shape_without_gpu():
     assert "gfx950" in libpsl.version()
     lib = libpsl.lib()
     t, k = ctypes.c_uint32(), ctypes.c_uint32()
+    # 1024 walks: 16-wavefront blocks of 1024 candidates, one k-split
     assert lib.psl_eval_shape(None, 131071, 131071, 1024, ctypes.byref(t), ctypes.byref(k)) == 0
-    assert t.value == 256 and k.value == 1
+    assert t.value == 128 and k.value == 1
+    # 64 walks at Table 4's N_lmt = 6912: 16-wavefront blocks, items cut to 2^23 updates
+    assert lib.psl_eval_shape(None, 131071, 6912, 64, ctypes.byref(t), ctypes.byref(k)) == 0
+    assert t.value == 7 and k.value == 16
+    assert lib.psl_eval_shape(None, 131071, 6912, (1 << 20) + 1, ctypes.byref(t), ctypes.byref(k)) == libpsl.E_INVAL
     assert lib.psl_eval_shape(None, 16383, 16383, 1, ctypes.byref(t), ctypes.byref(k)) == 0
     assert t.value == 32 and k.value >= 8
     assert lib.psl_eval_shape(None, 1, 1, 1, ctypes.byref(t), ctypes.byref(k)) == libpsl.E_INVAL

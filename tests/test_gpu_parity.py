@@ -299,7 +299,7 @@ def test_eval_items_option_keeps_results(ctx):
     oc = oracle.select(Fo, Po, margin=MARGIN)
     splits = set()
     try:
-        for v in (1, 64, 4096, 65536, 262144):
+        for v in (1, 128, 4096, 65536, 262144):
             ctx.set_option(libpsl.OPT_EVAL_ITEMS, v)
             splits.add(ctx.eval_shape(L, n_lmt, 1)[1])
             F, P = _dev(n_lmt, torch.float64), _dev(n_lmt, torch.int32)

@@ -38,6 +38,28 @@ __device__ __forceinline__ uint32_t get_bit(const uint64_t *b, uint32_t i)
     return (uint32_t)((b[i >> 6] >> (i & 63u)) & 1u);
 }
 
+// dst[x] = src[x] for x < n (word flip_word also XORed with flip_mask), the
+// threads of a block striding by nthreads. The two arrays never overlap;
+// each thread issues eight loads before their stores instead of waiting on
+// one load per word.
+__device__ __forceinline__ void copy_words(uint64_t *__restrict__ dst, const uint64_t *__restrict__ src,
+                                           uint32_t n, uint32_t tid, uint32_t nthreads, uint32_t flip_word,
+                                           uint64_t flip_mask)
+{
+    uint32_t x = tid;
+    for (; x + 7u * nthreads < n; x += 8u * nthreads) {
+        uint64_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = src[x + (uint32_t)u * nthreads];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t y = x + (uint32_t)u * nthreads;
+            dst[y] = y == flip_word ? v[u] ^ flip_mask : v[u];
+        }
+    }
+    for (; x < n; x += nthreads) dst[x] = x == flip_word ? src[x] ^ flip_mask : src[x];
+}
+
 // Bits [pos, pos+32) of a packed sequence held as nw32 32-bit words; bits
 // outside the words read as 0.
 __device__ __forceinline__ uint32_t bits32_at(const uint32_t *__restrict__ w32, int nw32,
@@ -198,6 +220,27 @@ __device__ __forceinline__ int32_t switch_flip_delta(const uint64_t *lb, uint32_
     return -2 * sp * d;
 }
 
+// C[k] for k = k_first, k_first + stride, ... < L from C of local_best. C and
+// C_lb are separate arrays: each thread computes two shifts before it stores
+// either.
+__device__ __forceinline__ void switch_corr_range(int32_t *__restrict__ C, const int32_t *__restrict__ C_lb,
+                                                  const uint64_t *__restrict__ lb, uint32_t L,
+                                                  const uint32_t *fl, uint32_t nf, uint32_t k_first,
+                                                  uint32_t stride)
+{
+    for (uint32_t k = k_first; k < L; k += 2 * stride) {
+        const uint32_t k2 = k + stride;
+        int32_t c = k == 0 ? (int32_t)L : C_lb[k];
+        int32_t c2 = k2 < L ? C_lb[k2] : 0;
+        for (uint32_t f = 0; f < nf; ++f) {
+            if (k != 0) c += switch_flip_delta(lb, L, k, fl[f]);
+            if (k2 < L) c2 += switch_flip_delta(lb, L, k2, fl[f]);
+        }
+        C[k] = c;
+        if (k2 < L) C[k2] = c2;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_switch_corr(WalkDev *walks, const BatchEntry *batch,
                                                      const uint32_t *pend)
 {
@@ -210,17 +253,8 @@ __global__ __launch_bounds__(256) void k_switch_corr(WalkDev *walks, const Batch
         __syncthreads();
         if (threadIdx.x < nf) s_fl[threadIdx.x] = w.flips[threadIdx.x];
         __syncthreads();
-        const uint32_t L = w.L;
-        const uint64_t *lb = w.local_best;
-        for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < L; k += gridDim.x * blockDim.x) {
-            if (k == 0) {
-                w.C[0] = (int32_t)L;
-                continue;
-            }
-            int32_t c = w.C_lb[k];
-            for (uint32_t f = 0; f < nf; ++f) c += switch_flip_delta(lb, L, k, s_fl[f]);
-            w.C[k] = c;
-        }
+        switch_corr_range(w.C, w.C_lb, w.local_best, w.L, s_fl, nf, blockIdx.x * blockDim.x + threadIdx.x,
+                          gridDim.x * blockDim.x);
     }
 }
 
@@ -1291,13 +1325,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select(WalkDev *walks, const Ba
         }
     }
     __syncthreads();
-    if (s_improve) {
-        for (uint32_t x = threadIdx.x; x < w.nw; x += kSelThreads) {
-            uint64_t v = w.pivot[x];
-            if (x == (jp >> 6)) v ^= 1ull << (jp & 63u);
-            w.best[x] = v;
-        }
-    }
+    if (s_improve) copy_words(w.best, w.pivot, w.nw, threadIdx.x, kSelThreads, jp >> 6, 1ull << (jp & 63u));
 }
 
 // ------------------------------------------------------------ flip
@@ -1306,6 +1334,44 @@ __global__ __launch_bounds__(kSelThreads) void k_select(WalkDev *walks, const Ba
 // bounds, read from the pivot before its bit changes. j_fixed < 0: the walk's
 // recorded move.
 constexpr int kApplyThreads = 256;
+
+// The C update of shifts k0 + tid, k0 + tid + kApplyThreads, ... < k1. C and
+// C_lb are separate arrays: each thread loads four shifts' C values and bit
+// words before it stores any of them. The bit words of j + k and j - k are
+// read whether or not those elements exist: the pivot's zero guard words
+// (nw + 2 on each side) hold every index from -(L-1) to 2L-2.
+constexpr int kApplyBatch = 4;
+__device__ __forceinline__ void apply_range(int32_t *__restrict__ C, int32_t *__restrict__ C_lb,
+                                            const uint64_t *__restrict__ b, uint32_t L, uint32_t j, int sj,
+                                            bool lb, uint32_t k0, uint32_t k1)
+{
+    for (uint32_t k = k0 + threadIdx.x; k < k1; k += kApplyBatch * kApplyThreads) {
+        int32_t cv[kApplyBatch];
+        uint64_t wr[kApplyBatch], wl[kApplyBatch];
+#pragma unroll
+        for (int u = 0; u < kApplyBatch; ++u) {
+            uint32_t kk = k + (uint32_t)u * kApplyThreads;
+            kk = kk < k1 ? kk : k;                  // past the end: a valid shift, not stored
+            const int32_t pl = (int32_t)j - (int32_t)kk;
+            cv[u] = C[kk];
+            wr[u] = b[(j + kk) >> 6];
+            wl[u] = b[pl >> 6];                     // arithmetic shift: a guard word when pl < 0
+        }
+#pragma unroll
+        for (int u = 0; u < kApplyBatch; ++u) {
+            const uint32_t kk = k + (uint32_t)u * kApplyThreads;
+            if (kk < k1) {
+                int d = 0;
+                if (j + kk < L) d += ((wr[u] >> ((j + kk) & 63u)) & 1u) ? -1 : 1;
+                if (kk <= j) d += ((wl[u] >> ((j - kk) & 63u)) & 1u) ? -1 : 1;
+                const int32_t c = cv[u] - 2 * sj * d;
+                C[kk] = c;
+                if (lb) C_lb[kk] = c;
+            }
+        }
+    }
+}
+
 __global__ __launch_bounds__(kApplyThreads) void k_apply(WalkDev *walks, const BatchEntry *batch,
                                                          int64_t j_fixed, SegMap map)
 {
@@ -1320,15 +1386,7 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply(WalkDev *walks, const B
     const bool lb = j_fixed < 0 && (w.flags & STEP_IMPROVED);
     const uint32_t k0 = 1u + (seg << map.shift);
     const uint32_t k1 = min(L, k0 + (1u << map.shift));
-#pragma unroll 4
-    for (uint32_t k = k0 + threadIdx.x; k < k1; k += kApplyThreads) {
-        int d = 0;
-        if (j + k < L) d += get_bit(b, j + k) ? -1 : 1;
-        if (k <= j) d += get_bit(b, j - k) ? -1 : 1;
-        const int32_t c = w.C[k] - 2 * sj * d;
-        w.C[k] = c;
-        if (lb) w.C_lb[k] = c;
-    }
+    apply_range(w.C, w.C_lb, b, L, j, sj, lb, k0, k1);
 }
 
 // Flip(pivot, j), part 2, for a forced flip: the bit itself.
@@ -1387,12 +1445,10 @@ __global__ __launch_bounds__(kBookThreads) void k_bookkeep(WalkDev *walks, const
         s_switch = sw;
     }
     __syncthreads();
-    if (s_improved) {
-        for (uint32_t x = threadIdx.x; x < w.nw; x += kBookThreads) w.local_best[x] = w.pivot[x];
-    }
+    if (s_improved) copy_words(w.local_best, w.pivot, w.nw, threadIdx.x, kBookThreads, UINT32_MAX, 0);
     __syncthreads();
     if (s_switch) {
-        for (uint32_t x = threadIdx.x; x < w.nw; x += kBookThreads) w.pivot[x] = w.local_best[x];
+        copy_words(w.pivot, w.local_best, w.nw, threadIdx.x, kBookThreads, UINT32_MAX, 0);
         __syncthreads();
         if (threadIdx.x == 0) {
             const uint32_t L = w.L;

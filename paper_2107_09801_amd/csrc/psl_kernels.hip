@@ -959,7 +959,7 @@ __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const 
 // read and one FP64 add. Which form a 32-shift window uses is decided once
 // per wavefront from the lanes' bounds. Shifts past every lane's
 // max(j, L-1-j) come from the suffix sums. The PSL comes from the near-peak
-// shifts (split 0 only), or, for pivots with many near-peak shifts, from
+// shifts (spread over the k-splits), or, for pivots with many near-peak shifts, from
 // 32-bit maxima kept in the main loop.
 template <int WAVES>
 __device__ __forceinline__ void eval_item(EvalLds &sh, const WalkDev *__restrict__ walks,
@@ -997,11 +997,13 @@ __device__ __forceinline__ void eval_item(EvalLds &sh, const WalkDev *__restrict
         eval_sweep<WAVES, true>(sh, w, be, it, T, n_lmt, j, SJ, k_lo, k_hi, tid, sum, comp, mx);
     } else {
         eval_sweep<WAVES, false>(sh, w, be, it, T, n_lmt, j, SJ, k_lo, k_hi, tid, sum, comp, mx);
-        if (it.ks == 0) {
-            // PSL over the near-peak shifts, every candidate, all bounds cases
+        {
+            // PSL over the near-peak shifts, every candidate, all bounds
+            // cases; split s takes entries s, s + ksplit, ... (the combine
+            // takes the maximum over the splits)
             const int jl = j, jr = L - 1 - j;
             int peak = 0;
-            for (uint32_t q = 0; q < n_near; ++q) {
+            for (uint32_t q = it.ks; q < n_near; q += be.ksplit) {
                 const int k = (int)be.near[1 + q];
                 int c = w.C[k];
                 if (k <= jr) {
@@ -1014,7 +1016,7 @@ __device__ __forceinline__ void eval_item(EvalLds &sh, const WalkDev *__restrict
                 }
                 peak = max(peak, c < 0 ? -c : c);
             }
-            mx = (uint32_t)peak;          // the PSL itself (< L, far below 0x3FF00000)
+            mx = (uint32_t)peak;          // its part of the PSL (< L, far below 0x3FF00000)
         }
     }
     if (active) {

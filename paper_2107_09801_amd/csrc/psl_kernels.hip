@@ -1124,6 +1124,129 @@ __device__ __forceinline__ void sel_merge(double &f, int32_t &p, uint32_t &i, do
     }
 }
 
+// The scan of Algorithm 1 over the combined F and PSL: the move is the first
+// candidate in scan order within F_min*(1+tau); the best-PSL neighbour is the
+// first with the minimum PSL.
+// pure != 0: write the choice to out[b] and leave the walk unchanged.
+// Otherwise record the choice in the walk and, on a strict PSL improvement,
+// update psl_best and solution_best = pivot with j_psl flipped.
+// The selection of walk w (batch position bi) by a block of NT threads.
+template <int NT>
+__device__ __forceinline__ void select_walk(WalkDev &w, const BatchEntry &be, uint32_t bi, uint32_t comb_blocks,
+                                            uint32_t comb_group, int pure, ChoiceDev *out, uint32_t *pend)
+{
+    // the previous step's pending list has been consumed; this step's
+    // bookkeeping refills it
+    if (pend && bi == 0 && threadIdx.x == 0) pend[0] = 0;
+    const uint32_t n = be.fixed ? be.n_lmt : w.n_lmt;
+    const uint32_t start = be.fixed ? be.start : step_start(w);
+    const uint32_t L = w.L;
+
+    double fmin = INFINITY;
+    int32_t pmin = INT_MAX;
+    uint32_t ipmin = UINT_MAX;
+    if (threadIdx.x < comb_blocks) {
+        const SelPart r = be.red[threadIdx.x];
+        fmin = r.f;
+        pmin = r.p;
+        ipmin = r.i;
+    }
+    const double my_f = fmin;           // this thread's combine block minimum
+    // block minima: within each wavefront, then across the wavefronts (the
+    // minimum F and the first minimum (PSL, index) do not depend on the order)
+    constexpr int kSelWaves = NT / 64;
+    __shared__ SelPart s_w[kSelWaves];
+    __shared__ uint32_t s_first[kSelWaves];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int o = 32; o > 0; o >>= 1) {
+        const double of = __shfl_xor(fmin, o);
+        const int32_t op = __shfl_xor(pmin, o);
+        const uint32_t oi = (uint32_t)__shfl_xor((int)ipmin, o);
+        sel_merge(fmin, pmin, ipmin, of, op, oi);
+    }
+    if (lane == 0) s_w[wave] = SelPart{fmin, pmin, ipmin};
+    __syncthreads();
+    SelPart r = s_w[0];
+    for (int x = 1; x < kSelWaves; ++x) sel_merge(r.f, r.p, r.i, s_w[x].f, s_w[x].p, s_w[x].i);
+    const double Fmin = r.f;
+    const int32_t Pmin = r.p;
+    const uint32_t iPmin = r.i;
+    const double thr = Fmin * (1.0 + kTau);
+
+    // the first band member lies in the first combine block (they cover
+    // contiguous runs of scan indices in order) whose minimum is in the band
+    uint32_t bfirst = my_f <= thr ? (uint32_t)threadIdx.x : UINT_MAX;
+    for (int o = 32; o > 0; o >>= 1) bfirst = min(bfirst, (uint32_t)__shfl_xor((int)bfirst, o));
+    if (lane == 0) s_first[wave] = bfirst;
+    __syncthreads();
+    for (int x = 0; x < kSelWaves; ++x) bfirst = min(bfirst, s_first[x]);
+    uint32_t lo, hi;
+    comb_range(n, comb_blocks, comb_group, bfirst, lo, hi);
+    __syncthreads();                    // s_first is reused below
+
+    // first scan index inside the band within [lo, hi): rounds of
+    // 8 * NT indices, each thread's eight loads issued together;
+    // the first round with a hit holds the answer
+    uint32_t ifirst = UINT_MAX;
+    for (uint32_t i0 = lo; i0 < hi; i0 += 8 * NT) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t i = i0 + u * NT + threadIdx.x;
+            v[u] = i < hi ? be.F[i] : INFINITY;
+        }
+#pragma unroll
+        for (int u = 7; u >= 0; --u)
+            if (v[u] <= thr) ifirst = i0 + u * NT + threadIdx.x;
+        if (__syncthreads_or(ifirst != UINT_MAX)) break;
+    }
+    for (int o = 32; o > 0; o >>= 1) ifirst = min(ifirst, (uint32_t)__shfl_xor((int)ifirst, o));
+    if (lane == 0) s_first[wave] = ifirst;
+    __syncthreads();
+    uint32_t ib = s_first[0];
+    for (int x = 1; x < kSelWaves; ++x) ib = min(ib, s_first[x]);
+    // with finite F the block holding F_min is in the band, so a member was
+    // found; the clamp only keeps the reads below in bounds otherwise
+    ib = ib < n ? ib : iPmin < n ? iPmin : 0u;
+    const uint32_t kb = (uint32_t)(((uint64_t)start + 1u + ib) % L);
+    const uint32_t jp = (uint32_t)(((uint64_t)start + 1u + iPmin) % L);
+
+    __shared__ int s_improve;
+    if (threadIdx.x == 0) {
+        be.near[0] = 0;           // the evaluation has read it; k_chunks appends to it
+        const double Fb = be.F[ib];
+        const int32_t Pb = be.P[ib];
+        if (pure) {
+            ChoiceDev c;
+            c.i_best = ib; c.j_best = kb; c.F_best = Fb; c.F_min = Fmin;
+            c.j_psl = jp; c.psl_min = Pmin; c.psl_k = Pb; c.pad = 0;
+            out[bi] = c;
+            s_improve = 0;
+        } else {
+            w.start = start;
+            w.k = kb;
+            w.i_best = ib;
+            w.value_step = Fb;
+            w.F_min = Fmin;
+            w.psl_k = Pb;
+            w.j_psl = jp;
+            w.psl_min = Pmin;
+            // three-way comparison of the move with v_local (Algorithm 1)
+            uint32_t fl = 0;
+            if (Fb < w.value_local * (1.0 - kTau)) fl = STEP_IMPROVED;
+            else if (Fb > w.value_local * (1.0 + kTau)) fl = STEP_WORSE;
+            w.flags = fl;
+            s_improve = Pmin < w.psl_best;
+            if (s_improve) {
+                w.psl_best = Pmin;
+                w.flags |= STEP_PSL_IMPROVED;
+            }
+        }
+    }
+    __syncthreads();
+    if (s_improve) copy_words(w.best, w.pivot, w.nw, threadIdx.x, NT, jp >> 6, 1ull << (jp & 63u));
+}
+
 // F and PSL per candidate from the k-split partials, spread over gridDim.x
 // blocks per walk (blockIdx.y = batch position); each block leaves its
 // smallest F and its first smallest PSL in be.red. A group of G lanes
@@ -1131,11 +1254,15 @@ __device__ __forceinline__ void sel_merge(double &f, int32_t &p, uint32_t &i, do
 // g+G, ... in order, then the group adds its lanes' sums with a butterfly
 // (a fixed order for a given split count and G; G = 1 adds the splits in
 // order).
-__global__ __launch_bounds__(kCombThreads) void k_combine(const WalkDev *walks, const BatchEntry *batch,
-                                                          Tables tabs, int G)
+// fuse != 0 (one block per walk): the block then makes the walk's selection
+// itself (select_walk), in place of k_select; b0 = the batch position of
+// blockIdx.y = 0.
+__global__ __launch_bounds__(kCombThreads) void k_combine(WalkDev *walks, const BatchEntry *batch, Tables tabs,
+                                                          int G, int fuse, int pure, ChoiceDev *out,
+                                                          uint32_t *pend, uint32_t b0)
 {
     const BatchEntry be = batch[blockIdx.y];
-    const WalkDev &w = walks[be.slot];
+    WalkDev &w = walks[be.slot];
     const uint32_t n = be.fixed ? be.n_lmt : w.n_lmt;
     const uint32_t ks = be.ksplit;
     const double *T = tabs.T[w.alpha];
@@ -1204,130 +1331,18 @@ __global__ __launch_bounds__(kCombThreads) void k_combine(const WalkDev *walks, 
         for (int x = 1; x < kCombThreads / 64; ++x) sel_merge(r.f, r.p, r.i, s_r[x].f, s_r[x].p, s_r[x].i);
         be.red[blockIdx.x] = r;
     }
+    if (fuse) {
+        __syncthreads();        // this block's F, P and block minimum are visible to it
+        select_walk<kCombThreads>(w, be, b0 + blockIdx.y, 1, (uint32_t)G, pure, out, pend);
+    }
 }
 
-// The scan of Algorithm 1 over the combined F and PSL: the move is the first
-// candidate in scan order within F_min*(1+tau); the best-PSL neighbour is the
-// first with the minimum PSL.
-// pure != 0: write the choice to out[b] and leave the walk unchanged.
-// Otherwise record the choice in the walk and, on a strict PSL improvement,
-// update psl_best and solution_best = pivot with j_psl flipped.
 __global__ __launch_bounds__(kSelThreads) void k_select(WalkDev *walks, const BatchEntry *batch,
                                                         uint32_t comb_blocks, uint32_t comb_group, int pure,
                                                         ChoiceDev *out, uint32_t *pend)
 {
-    // the previous step's pending list has been consumed; this step's
-    // bookkeeping refills it
-    if (pend && blockIdx.x == 0 && threadIdx.x == 0) pend[0] = 0;
     const BatchEntry be = batch[blockIdx.x];
-    WalkDev &w = walks[be.slot];
-    const uint32_t n = be.fixed ? be.n_lmt : w.n_lmt;
-    const uint32_t start = be.fixed ? be.start : step_start(w);
-    const uint32_t L = w.L;
-
-    double fmin = INFINITY;
-    int32_t pmin = INT_MAX;
-    uint32_t ipmin = UINT_MAX;
-    if (threadIdx.x < comb_blocks) {
-        const SelPart r = be.red[threadIdx.x];
-        fmin = r.f;
-        pmin = r.p;
-        ipmin = r.i;
-    }
-    const double my_f = fmin;           // this thread's combine block minimum
-    // block minima: within each wavefront, then across the wavefronts (the
-    // minimum F and the first minimum (PSL, index) do not depend on the order)
-    constexpr int kSelWaves = kSelThreads / 64;
-    __shared__ SelPart s_w[kSelWaves];
-    __shared__ uint32_t s_first[kSelWaves];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int o = 32; o > 0; o >>= 1) {
-        const double of = __shfl_xor(fmin, o);
-        const int32_t op = __shfl_xor(pmin, o);
-        const uint32_t oi = (uint32_t)__shfl_xor((int)ipmin, o);
-        sel_merge(fmin, pmin, ipmin, of, op, oi);
-    }
-    if (lane == 0) s_w[wave] = SelPart{fmin, pmin, ipmin};
-    __syncthreads();
-    SelPart r = s_w[0];
-    for (int x = 1; x < kSelWaves; ++x) sel_merge(r.f, r.p, r.i, s_w[x].f, s_w[x].p, s_w[x].i);
-    const double Fmin = r.f;
-    const int32_t Pmin = r.p;
-    const uint32_t iPmin = r.i;
-    const double thr = Fmin * (1.0 + kTau);
-
-    // the first band member lies in the first combine block (they cover
-    // contiguous runs of scan indices in order) whose minimum is in the band
-    uint32_t bfirst = my_f <= thr ? (uint32_t)threadIdx.x : UINT_MAX;
-    for (int o = 32; o > 0; o >>= 1) bfirst = min(bfirst, (uint32_t)__shfl_xor((int)bfirst, o));
-    if (lane == 0) s_first[wave] = bfirst;
-    __syncthreads();
-    for (int x = 0; x < kSelWaves; ++x) bfirst = min(bfirst, s_first[x]);
-    uint32_t lo, hi;
-    comb_range(n, comb_blocks, comb_group, bfirst, lo, hi);
-    __syncthreads();                    // s_first is reused below
-
-    // first scan index inside the band within [lo, hi): rounds of
-    // 8 * kSelThreads indices, each thread's eight loads issued together;
-    // the first round with a hit holds the answer
-    uint32_t ifirst = UINT_MAX;
-    for (uint32_t i0 = lo; i0 < hi; i0 += 8 * kSelThreads) {
-        double v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const uint32_t i = i0 + u * kSelThreads + threadIdx.x;
-            v[u] = i < hi ? be.F[i] : INFINITY;
-        }
-#pragma unroll
-        for (int u = 7; u >= 0; --u)
-            if (v[u] <= thr) ifirst = i0 + u * kSelThreads + threadIdx.x;
-        if (__syncthreads_or(ifirst != UINT_MAX)) break;
-    }
-    for (int o = 32; o > 0; o >>= 1) ifirst = min(ifirst, (uint32_t)__shfl_xor((int)ifirst, o));
-    if (lane == 0) s_first[wave] = ifirst;
-    __syncthreads();
-    uint32_t ib = s_first[0];
-    for (int x = 1; x < kSelWaves; ++x) ib = min(ib, s_first[x]);
-    // with finite F the block holding F_min is in the band, so a member was
-    // found; the clamp only keeps the reads below in bounds otherwise
-    ib = ib < n ? ib : iPmin < n ? iPmin : 0u;
-    const uint32_t kb = (uint32_t)(((uint64_t)start + 1u + ib) % L);
-    const uint32_t jp = (uint32_t)(((uint64_t)start + 1u + iPmin) % L);
-
-    __shared__ int s_improve;
-    if (threadIdx.x == 0) {
-        be.near[0] = 0;           // the evaluation has read it; k_chunks appends to it
-        const double Fb = be.F[ib];
-        const int32_t Pb = be.P[ib];
-        if (pure) {
-            ChoiceDev c;
-            c.i_best = ib; c.j_best = kb; c.F_best = Fb; c.F_min = Fmin;
-            c.j_psl = jp; c.psl_min = Pmin; c.psl_k = Pb; c.pad = 0;
-            out[blockIdx.x] = c;
-            s_improve = 0;
-        } else {
-            w.start = start;
-            w.k = kb;
-            w.i_best = ib;
-            w.value_step = Fb;
-            w.F_min = Fmin;
-            w.psl_k = Pb;
-            w.j_psl = jp;
-            w.psl_min = Pmin;
-            // three-way comparison of the move with v_local (Algorithm 1)
-            uint32_t fl = 0;
-            if (Fb < w.value_local * (1.0 - kTau)) fl = STEP_IMPROVED;
-            else if (Fb > w.value_local * (1.0 + kTau)) fl = STEP_WORSE;
-            w.flags = fl;
-            s_improve = Pmin < w.psl_best;
-            if (s_improve) {
-                w.psl_best = Pmin;
-                w.flags |= STEP_PSL_IMPROVED;
-            }
-        }
-    }
-    __syncthreads();
-    if (s_improve) copy_words(w.best, w.pivot, w.nw, threadIdx.x, kSelThreads, jp >> 6, 1ull << (jp & 63u));
+    select_walk<kSelThreads>(walks[be.slot], be, blockIdx.x, comb_blocks, comb_group, pure, out, pend);
 }
 
 // ------------------------------------------------------------ flip
@@ -1604,12 +1619,15 @@ hipError_t launch_select(WalkDev *walks, const BatchEntry *batch, uint32_t nb, u
 {
     if (comb_blocks < 1 || comb_blocks > kCombMaxBlocks) return hipErrorInvalidValue;
     if (comb_group < 1 || comb_group > 64 || (comb_group & (comb_group - 1))) return hipErrorInvalidValue;
+    // one combine block per walk: it makes the selection too
+    const int fuse = comb_blocks == 1 ? 1 : 0;
     for (uint32_t b0 = 0; b0 < nb; b0 += kMaxGridY) {
         k_combine<<<dim3(comb_blocks, std::min(kMaxGridY, nb - b0)), kCombThreads, 0, s>>>(
-            walks, batch + b0, tabs, (int)comb_group);
+            walks, batch + b0, tabs, (int)comb_group, fuse, pure, (ChoiceDev *)out, pend, b0);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
+    if (fuse) return hipSuccess;
     k_select<<<nb, kSelThreads, 0, s>>>(walks, batch, comb_blocks, comb_group, pure, (ChoiceDev *)out, pend);
     return hipGetLastError();
 }

@@ -336,8 +336,12 @@ void eval_layout(const uint32_t *Ls, const uint32_t *nl, uint32_t n, const EvalS
     while (G < 64 && (uint64_t)G * 16 < ksmax) G <<= 1;
     out.comb_group = G;
     const uint64_t cpb = 256 / G;
-    out.comb_blocks = (uint32_t)std::max<uint64_t>(
-        1, std::min<uint64_t>({(work + 8191) / 8192, (nmax + cpb - 1) / cpb, (uint64_t)kCombMaxBlocks}));
+    // up to two blocks' worth of partials per walk: one block, which then
+    // also makes the selection (no separate selection launch)
+    out.comb_blocks = work <= 16384 ? 1u
+                                    : (uint32_t)std::max<uint64_t>(
+                                          1, std::min<uint64_t>({(work + 8191) / 8192, (nmax + cpb - 1) / cpb,
+                                                                 (uint64_t)kCombMaxBlocks}));
     out.items.reserve(shape.persistent ? all.size() : 8 * cmax);
     for (int q = 0; q < 8; ++q) {
         auto &sg = seg[q];

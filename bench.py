@@ -102,9 +102,9 @@ def parse():
                     help="jobs in the served vs one-walk-per-launch comparison (0: skip)")
     ap.add_argument("--compare-uneven-steps", type=int, default=2,
                     help="uneven workload: steps of the batch-vs-one-walk-per-launch comparison (0 = off)")
-    ap.add_argument("--study", default="", choices=["", "paper-sweep", "alpha-ablation", "restart"],
+    ap.add_argument("--study", default="", choices=["", "paper-sweep", "alpha-ablation", "restart", "serve"],
                     help="instead of the benchmark: the paper-settings speed sweep over L, the alpha ablation, "
-                         "or the restart protocol")
+                         "the restart protocol, or the serving run alone")
     ap.add_argument("--nse", type=float, default=1e9, help="alpha ablation: sequence evaluations per run")
     ap.add_argument("--runs", type=int, default=30, help="alpha ablation: runs per alpha pair")
     ap.add_argument("--rounds", type=int, default=4, help="restart study: rounds")
@@ -474,6 +474,9 @@ def main():
         return
     if args.study == "alpha-ablation":
         print(json.dumps(run_alpha_ablation(libpsl, args.nse, args.runs)), flush=True)
+        return
+    if args.study == "serve":
+        print(json.dumps(run_serving(libpsl, args.serve_seconds, args.serve_rate, args.serve_nlmt)), flush=True)
         return
     if args.study == "restart":
         print(json.dumps(run_restart_study(libpsl, args.L or 65535, args.rounds, args.walks or 64,

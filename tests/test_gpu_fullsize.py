@@ -5,6 +5,8 @@ size.
 * L = 16383, one walk, full neighbourhood, alpha 4/13, switch every 50 steps:
   the 200-step trajectory in lockstep with the oracle.
 * L = 131071, 1024 walks: walks 0, 511 and 1023 after steps 1, 2 and 3.
+* L = 131071, 64 walks at Table 4's settings (N_lmt = 6912, alpha 4/10, the
+  switch rule of Algorithm 1): walks 0 and 63 after steps 1, 2 and 3.
 * L = 1048575, one walk, alpha 4/10: sampled neighbours of step 1 against the
   oracle, the choice against the full F/PSL arrays, the O(L) flip against the
   oracle's formula tier, and the correlation invariants.
@@ -78,6 +80,25 @@ def test_batch_1024_L131071_sampled_walks(ctx):
         g = ctx.read_walk(ids[b])
         o = ows[b].read()
         assert np.array_equal(g["pivot"], o["pivot"]) and np.array_equal(g["C"], o["C"])
+    for t in range(3):
+        ctx.step_batch(ids, 1)
+        for b in sample:
+            tr = ows[b].step()
+            assert not tr["flags"] & (oracle.AMBIG_ARGMIN | oracle.AMBIG_COMPARE)
+            _check_against_oracle(ctx.read_walk(ids[b]), ows[b].read(), tr, (b, t))
+    ctx.free_walks(ids)
+
+
+def test_paper_settings_64_walks_L131071_sampled(ctx):
+    """The limited neighbourhood at full size: 6912 candidates from a random
+    start, 16-wavefront blocks and many k-splits per walk."""
+    L, nw, n_lmt = 131071, 64, 6912
+    ids = ctx.init_walks(L, nw, si.BASE_SEED, alpha1=4, alpha2=10, n_lmt=n_lmt, ls_lmt=2000, flip_lmt=10,
+                         switch_period=0)
+    sample = [0, 63]
+    ows = {b: oracle.Walk(oracle.WalkConfig(L=L, seed=si.walk_seed(b), alpha1=4, alpha2=10, n_lmt=n_lmt,
+                                            ls_lmt=2000, flip_lmt=10, switch_period=0),
+                          margin=MARGIN, nthreads=THREADS) for b in sample}
     for t in range(3):
         ctx.step_batch(ids, 1)
         for b in sample:

@@ -1,7 +1,7 @@
 /*
  * psl.h -- libpsl: MI355X (gfx950) engine for the data-parallel hot path of
  * the two-phase stochastic search for +-1 sequences with a low peak sidelobe
- * level (Bosković & Brest, arXiv 2107.09801).
+ * level (Boskovic & Brest, arXiv 2107.09801).
  *
  * Problem statement followed by every call:
  *   Eq. (1)  a sequence S_L of L elements, each +1 or -1;

@@ -13,7 +13,7 @@ namespace psl {
 constexpr double kTau = 1e-12;       // relative band of the best-neighbour and
                                      // improvement comparisons
 constexpr int kEvalWavesMax = 16;    // wavefronts per evaluation block: 16, 8 or 4
-constexpr int kEvalWaves = 8;        // the default for large neighbourhoods
+constexpr int kEvalWaves = 8;        // the default below 256 x 1024 candidates per batch
 constexpr int kEvalWavesSmall = 4;   // blocks for batches of small neighbourhoods
 constexpr int kTileK = 256;          // shifts staged per LDS tile
 constexpr int kChunks = kTileK / 32; // 32-shift windows per tile

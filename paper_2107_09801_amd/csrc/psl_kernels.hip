@@ -6,8 +6,9 @@
 // (Section 3, with Eq. (2)), and from the C'_k the kernel accumulates
 // F_j = sum_k |C'_k|^alpha (Eq. (5)) and PSL_j = max_k |C'_k| (Eq. (3)).
 //
-// Layout: one lane per candidate, 64 candidates per wavefront, eight
-// wavefronts per block; shifts are swept in LDS-staged tiles (see k_eval).
+// Layout: one lane per candidate, 64 candidates per wavefront, 4, 8 or 16
+// wavefronts per block; shifts are swept in LDS-staged tiles (see eval_item),
+// one block per work item or a persistent grid over per-XCD queues.
 #include "psl_device.h"
 #include "psl_launch.h"
 

@@ -88,6 +88,8 @@ def parse():
     ap.add_argument("--n-lmt", type=int, default=0, help="0 = full neighbourhood")
     ap.add_argument("--switch-period", type=int, default=50)
     ap.add_argument("--graph", action="store_true", help="replay a captured step per step")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time every evaluation launch shape on the batch first and keep the fastest")
     ap.add_argument("--eval-items", type=int, default=0,
                     help="minimum work items per evaluation launch (0 = the library default)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -521,6 +523,9 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         log(f"calibration copy of {args.calib_copy_mb} MiB done")
+    tuned = ctx.autotune(ids) if args.autotune else None
+    if tuned is not None:
+        log(f"autotuned: {tuned}")
     if args.warmup:
         ctx.step_batch(ids, args.warmup, blocking=True, graph=args.graph)
         log(f"{args.warmup} warmup step(s) done")
@@ -586,6 +591,8 @@ def main():
                      "traffic_unit": "B/launch"},
         "walk0_after": {"t": st["t"], "psl_best": st["psl_best"], "alpha": st["alpha"]},
     }
+    if tuned is not None:
+        out["autotune"] = tuned
     if wl == "large":
         out["walk0_trace"] = [{k: e[k] for k in ("t", "psl_k", "psl_best", "value_step", "alpha")}
                               for e in ctx.trace_read(ids[0], args.warmup + args.steps)]

@@ -84,6 +84,41 @@ def test_served_results_equal_alone_and_oracle(ctx):
                 assert r["psl_final"] == o["psl_pivot"]
 
 
+def test_serving_mixture_50_jobs_equal_alone(ctx):
+    """50 jobs of the serving workload's mixture (L = 2^m - 1 or any odd L up
+    to 2^20 - 1, N_lmt = min(L, 256), a switch every 50 steps), submitted in
+    waves while earlier ones run; budgets cut to 5..60 steps so the check
+    stays short. Each result equals the same job stepped alone."""
+    import os
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    rng = np.random.default_rng(2107)
+    jobs = bench.serve_jobs(50, si.BASE_SEED + 7, 256)
+    for j in jobs:
+        j["budget"] = int(rng.integers(5, 61))
+    ctx.serve_start(hbm_budget=40 << 30, max_slots=4096)
+    tickets = []
+    for i, j in enumerate(jobs):
+        tickets.append(ctx.serve_submit(j["L"], j["seed"], j["budget"], alpha2=j["alpha2"], n_lmt=j["n_lmt"],
+                                        switch_period=50))
+        if i % 10 == 9:
+            time.sleep(0.02)
+    res = _wait(ctx, tickets, timeout_s=100.0)
+    ctx.serve_stop(drain=True)
+    for t, j in zip(tickets, jobs):
+        r = res[t]
+        assert r["status"] == 0 and r["steps"] == j["budget"]
+        (w,) = ctx.init_walks(j["L"], 1, j["seed"], alpha2=j["alpha2"], n_lmt=j["n_lmt"], switch_period=50)
+        ctx.step_batch([w], j["budget"])
+        g = ctx.read_walk(w, C=False)
+        assert r["psl_best"] == g["psl_best"] and r["psl_final"] == g["psl_pivot"], j
+        assert r["alpha_final"] == g["alpha"], j
+        assert abs(r["F_final"] - g["F_pivot"]) <= F_RTOL * g["F_pivot"], j
+        assert np.array_equal(r["best"], g["best"]), j
+        ctx.free_walks([w])
+
+
 def test_admission_fifo_within_budget(ctx):
     # room for three L=30001, N_lmt=256 jobs at a time
     from paper_2107_09801_amd import libpsl

@@ -300,21 +300,24 @@ typedef struct {
                                items from per-XCD queues; 0: one block per item     */
     int32_t blocks_per_cu;  /* resident blocks per CU of the persistent grid: 1..3
                                (1..2 for 16 wavefronts)                            */
-    int32_t reserved;
+    int32_t eval_items;     /* work-item target kept with it (PSL_OPT_EVAL_ITEMS)   */
     double  eval_ms;        /* measured mean launch time of this shape              */
     double  default_ms;     /* measured mean launch time of the untuned default     */
 } psl_tune_choice;
 
 /* Time every candidate launch shape of the evaluation on these walks (their
- * state is not changed), keep the fastest for every later batch with the same
- * key (log2 of the largest L, of the median N_lmt and of the walk count, and
- * whether the L differ by more than 4x), and report it. Blocking.
+ * state is not changed), then, in the fastest shape, the work-item targets
+ * half, twice and four times PSL_OPT_EVAL_ITEMS; keep the fastest pair for
+ * every later batch with the same key (log2 of the largest L, of the median
+ * N_lmt and of the walk count, and whether the L differ by more than 4x),
+ * and report it. Blocking.
  * Errors: PSL_E_INVAL, PSL_E_STATE, PSL_E_NOMEM, PSL_E_HIP. */
 PSL_API psl_status psl_autotune(psl_ctx *ctx, const uint32_t *walk_ids, uint32_t n,
                                 psl_tune_choice *out);
 
 /* Write / read the context's tuned shapes as text (one "key waves persistent
- * blocks_per_cu" line each). Errors: PSL_E_INVAL (I/O or format). */
+ * blocks_per_cu eval_items" line each; a line without eval_items keeps the
+ * context's value). Errors: PSL_E_INVAL (I/O or format). */
 PSL_API psl_status psl_tune_save(psl_ctx *ctx, const char *path);
 PSL_API psl_status psl_tune_load(psl_ctx *ctx, const char *path);
 

@@ -146,6 +146,7 @@ struct psl_ctx {
     psl_rt::Server *server = nullptr; // serving loop, when started
     uint32_t n_cu = 256;              // compute units of the device
     std::map<uint32_t, psl::EvalShape> tuned;  // autotuner choices by tune_key
+    std::map<uint32_t, uint32_t> tuned_items;  // autotuned work-item targets by tune_key
     // timing
     bool timing = false;
     std::vector<hipEvent_t> ev;       // 3 per recorded step: eval start, eval end, step end
@@ -203,7 +204,11 @@ SegMap seg_prefix(const uint32_t *Ls, uint32_t n, uint32_t *off);
 int eval_waves(const uint32_t *n_lmt, uint32_t n);
 psl_status check_cfg(psl_ctx *ctx, const psl_walk_cfg *c);
 psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t n, uint32_t n_fixed,
-                     uint32_t start_fixed, const EvalShape *force = nullptr);
+                     uint32_t start_fixed, const EvalShape *force = nullptr, uint32_t force_items = 0);
+// The work-item target of a batch: the autotuned one for its key, else the
+// context's PSL_OPT_EVAL_ITEMS; and the largest target any batch can get.
+uint32_t items_for(const psl_ctx *ctx, const uint32_t *Ls, const uint32_t *n_lmt, uint32_t n);
+uint32_t items_max(const psl_ctx *ctx);
 uint32_t near_limit_for(const psl_ctx *ctx, uint32_t L);
 
 // Slab layout of one walk of length L: the pivot between guard words, then

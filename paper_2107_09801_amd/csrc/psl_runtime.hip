@@ -356,8 +356,21 @@ void eval_layout(const uint32_t *Ls, const uint32_t *nl, uint32_t n, const EvalS
 
 // Builds (or reuses) the device layout of a batch: entries, eval work items
 // and scratch. n_fixed / start_fixed != UINT32_MAX: a pure single evaluation.
+uint32_t items_for(const psl_ctx *ctx, const uint32_t *Ls, const uint32_t *nl, uint32_t n)
+{
+    auto it = ctx->tuned_items.find(tune_key(Ls, nl, n));
+    return it != ctx->tuned_items.end() ? it->second : ctx->eval_items;
+}
+
+uint32_t items_max(const psl_ctx *ctx)
+{
+    uint32_t m = ctx->eval_items;
+    for (const auto &kv : ctx->tuned_items) m = std::max(m, kv.second);
+    return m;
+}
+
 psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t n, uint32_t n_fixed,
-                     uint32_t start_fixed, const EvalShape *force)
+                     uint32_t start_fixed, const EvalShape *force, uint32_t force_items)
 {
     const bool fixed = n_fixed != UINT32_MAX;
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
@@ -374,7 +387,8 @@ psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t 
     }
     EvalLayout lay;
     const EvalShape shape = force ? *force : pick_shape(ctx, Ls.data(), n_l.data(), n);
-    eval_layout(Ls.data(), n_l.data(), n, shape, ctx->eval_items, lay);
+    eval_layout(Ls.data(), n_l.data(), n, shape,
+                force_items ? force_items : items_for(ctx, Ls.data(), n_l.data(), n), lay);
     const std::vector<uint32_t> &tiles = lay.tiles, &ks = lay.ks;
     std::vector<EvalItem> &items = lay.items;
     pl.shape = lay.shape;
@@ -980,6 +994,7 @@ psl_status psl_autotune(psl_ctx *ctx, const uint32_t *walk_ids, uint32_t n, psl_
     }
     const uint32_t key = tune_key(Ls.data(), nl.data(), n);
     ctx->tuned.erase(key);
+    ctx->tuned_items.erase(key);
     const EvalShape def = pick_shape(ctx, Ls.data(), nl.data(), n);
     std::vector<EvalShape> cands;
     for (int waves : {kEvalWavesMax, kEvalWaves, kEvalWavesSmall}) {
@@ -998,12 +1013,11 @@ psl_status psl_autotune(psl_ctx *ctx, const uint32_t *walk_ids, uint32_t n, psl_
     hipEvent_t e0, e1;
     HIP_TRY(ctx, hipEventCreate(&e0));
     HIP_TRY(ctx, hipEventCreate(&e1));
-    double best_ms = 1e300, def_ms = 0.0;
-    EvalShape best = def;
-    psl_status st = PSL_OK;
-    for (const EvalShape &c : cands) {
+    // mean time of one evaluation launch in a given shape and work-item target
+    auto time_eval = [&](const EvalShape &c, uint32_t items, double &avg) -> psl_status {
         BatchPlan tmp;
-        if ((st = make_plan(ctx, tmp, walk_ids, n, UINT32_MAX, 0, &c))) break;
+        psl_status s2 = make_plan(ctx, tmp, walk_ids, n, UINT32_MAX, 0, &c, items);
+        if (s2) return s2;
         hipError_t e = launch_suffix(ctx->d_walks, tmp.d_batch, n, tmp.max_L, tabs, 0, nullptr, &tmp.seg,
                                      ctx->stream);
         if (e == hipSuccess)   // warm-up
@@ -1019,27 +1033,50 @@ psl_status psl_autotune(psl_ctx *ctx, const uint32_t *walk_ids, uint32_t n, psl_
         float ms = 0.f;
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
         plan_free(ctx, tmp);
-        if (e != hipSuccess) {
-            st = fail(ctx, PSL_E_HIP, "autotune: %s", hipGetErrorString(e));
-            break;
-        }
-        const double avg = ms / reps;
+        if (e != hipSuccess) return fail(ctx, PSL_E_HIP, "autotune: %s", hipGetErrorString(e));
+        avg = ms / reps;
+        return PSL_OK;
+    };
+    double best_ms = 1e300, def_ms = 0.0;
+    EvalShape best = def;
+    uint32_t best_items = ctx->eval_items;
+    psl_status st = PSL_OK;
+    for (const EvalShape &c : cands) {
+        double avg = 0.0;
+        if ((st = time_eval(c, ctx->eval_items, avg))) break;
         if (c.waves == def.waves && c.persistent == def.persistent && c.grid == def.grid) def_ms = avg;
         if (avg < best_ms) {
             best_ms = avg;
             best = c;
         }
     }
+    // then the work-item target for that shape: half, twice and four times
+    // the context's value
+    if (!st) {
+        for (const uint64_t f : {1ull, 4ull, 8ull}) {       // x/2, 2x, 4x of the value
+            const uint32_t items = (uint32_t)std::min<uint64_t>(
+                kEvalItemsMax, std::max<uint64_t>(1, (uint64_t)ctx->eval_items * f / 2));
+            if (items == ctx->eval_items) continue;
+            double avg = 0.0;
+            if ((st = time_eval(best, items, avg))) break;
+            if (avg < best_ms) {
+                best_ms = avg;
+                best_items = items;
+            }
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st) return st;
     ctx->tuned[key] = best;
+    ctx->tuned_items[key] = best_items;
     plans_clear(ctx);            // later plans pick up the choice
     if (out) {
         memset(out, 0, sizeof *out);
         out->waves = best.waves;
         out->persistent = best.persistent;
         out->blocks_per_cu = best.persistent ? (int32_t)(best.grid / ctx->n_cu) : 0;
+        out->eval_items = (int32_t)best_items;
         out->eval_ms = best_ms;
         out->default_ms = def_ms;
     }
@@ -1051,9 +1088,12 @@ psl_status psl_tune_save(psl_ctx *ctx, const char *path)
     if (!ctx || !path) return PSL_E_INVAL;
     FILE *f = fopen(path, "w");
     if (!f) return fail(ctx, PSL_E_INVAL, "cannot write %s", path);
-    for (const auto &kv : ctx->tuned)
-        fprintf(f, "%u %d %d %u\n", kv.first, kv.second.waves, kv.second.persistent,
-                kv.second.persistent ? kv.second.grid / ctx->n_cu : 0u);
+    for (const auto &kv : ctx->tuned) {
+        auto it = ctx->tuned_items.find(kv.first);
+        fprintf(f, "%u %d %d %u %u\n", kv.first, kv.second.waves, kv.second.persistent,
+                kv.second.persistent ? kv.second.grid / ctx->n_cu : 0u,
+                it != ctx->tuned_items.end() ? it->second : ctx->eval_items);
+    }
     fclose(f);
     return PSL_OK;
 }
@@ -1065,12 +1105,17 @@ psl_status psl_tune_load(psl_ctx *ctx, const char *path)
     FILE *f = fopen(path, "r");
     if (!f) return fail(ctx, PSL_E_INVAL, "cannot read %s", path);
     std::map<uint32_t, EvalShape> got;
-    unsigned key, bpc;
-    int waves, pers;
-    int r;
-    while ((r = fscanf(f, "%u %d %d %u", &key, &waves, &pers, &bpc)) == 4) {
-        if ((waves != kEvalWavesMax && waves != kEvalWaves && waves != kEvalWavesSmall) ||
-            (pers != 0 && pers != 1) || (pers && (bpc < 1 || bpc > max_blocks_per_cu(waves)))) {
+    std::map<uint32_t, uint32_t> got_items;
+    char line[256];
+    while (fgets(line, sizeof line, f)) {
+        unsigned key, bpc, items = 0;
+        int waves, pers;
+        char extra;
+        const int r = sscanf(line, "%u %d %d %u %u %c", &key, &waves, &pers, &bpc, &items, &extra);
+        if (r <= 0) continue;                   // blank line
+        if ((r != 4 && r != 5) || (waves != kEvalWavesMax && waves != kEvalWaves && waves != kEvalWavesSmall) ||
+            (pers != 0 && pers != 1) || (pers && (bpc < 1 || bpc > max_blocks_per_cu(waves))) ||
+            (r == 5 && (items < 1 || items > kEvalItemsMax))) {
             fclose(f);
             return fail(ctx, PSL_E_INVAL, "bad tuning line in %s", path);
         }
@@ -1079,12 +1124,13 @@ psl_status psl_tune_load(psl_ctx *ctx, const char *path)
         sh.persistent = pers;
         sh.grid = pers ? bpc * ctx->n_cu : 0;
         got[key] = sh;
+        if (r == 5) got_items[key] = items;
     }
     fclose(f);
-    if (r != EOF) return fail(ctx, PSL_E_INVAL, "bad tuning file %s", path);
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     for (auto &kv : got) ctx->tuned[kv.first] = kv.second;
+    for (auto &kv : got_items) ctx->tuned_items[kv.first] = kv.second;
     plans_clear(ctx);
     return PSL_OK;
 }

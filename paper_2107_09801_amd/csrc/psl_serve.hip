@@ -355,7 +355,8 @@ psl_status Server::upload_layout(char *&sp, char *stage_end)
         max_L = std::max(max_L, Ls[b]);
     }
     EvalLayout lay;
-    eval_layout(Ls.data(), nls.data(), n, pick_shape(ctx, Ls.data(), nls.data(), n), ctx->eval_items, lay);
+    eval_layout(Ls.data(), nls.data(), n, pick_shape(ctx, Ls.data(), nls.data(), n),
+                items_for(ctx, Ls.data(), nls.data(), n), lay);
     const std::vector<uint32_t> &tiles = lay.tiles, &ks = lay.ks;
     size_t n_part = 0, n_cand = 0, n_suf = 0;
     for (uint32_t b = 0; b < n; ++b) {
@@ -470,7 +471,7 @@ psl_status Server::iterate()
             tiles += ((j.cfg.n_lmt ? j.cfg.n_lmt : j.cfg.L) + tl - 1) / tl;
         }
         const size_t need = (n_adm + active.size()) * (sizeof(WalkDev) + 2 * sizeof(BatchEntry) + 16) +
-                            sizeof(EvalItem) * 8 * ((uint64_t)ctx->eval_items + tiles) + 8192;
+                            sizeof(EvalItem) * 8 * ((uint64_t)items_max(ctx) + tiles) + 8192;
         if ((st = ensure_stage(need))) return st;
     }
     char *sp = stage[cur];

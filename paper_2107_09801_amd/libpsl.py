@@ -113,11 +113,11 @@ class TraceEntry(ctypes.Structure):
 
 class TuneChoice(ctypes.Structure):
     _fields_ = [("waves", ctypes.c_int32), ("persistent", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32), ("eval_items", ctypes.c_int32),
                 ("eval_ms", ctypes.c_double), ("default_ms", ctypes.c_double)]
 
     def as_dict(self) -> dict:
-        return {n: getattr(self, n) for n, _ in self._fields_ if n != "reserved"}
+        return {n: getattr(self, n) for n, _ in self._fields_}
 
 
 class Timing(ctypes.Structure):

@@ -361,10 +361,13 @@ def test_autotune_shapes_keep_results(ctx, tmp_path):
     ids = batch(ctx)
     choice = ctx.autotune(ids)
     assert choice["waves"] in (4, 8, 16) and choice["persistent"] in (0, 1)
+    assert choice["eval_items"] in (2048, 4096, 8192, 16384)     # x/2 .. 4x of the default
     assert choice["eval_ms"] > 0 and choice["eval_ms"] <= choice["default_ms"] * 1.0001
     ctx.step_batch(ids, 12)
     path = str(tmp_path / "tune.txt")
     ctx.tune_save(path)
+    fields = open(path).read().split()
+    assert len(fields) % 5 == 0 and int(fields[4]) == choice["eval_items"]
     other = libpsl.Context(0)
     ref = batch(other)
     other.step_batch(ref, 12)

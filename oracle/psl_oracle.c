@@ -99,9 +99,14 @@ OC_API void oc_seq_to_bits(const int8_t *s, int L, uint64_t *bits)
 
 /* ------------------------------------------------------- Eq. (2), Eq. (3) */
 
-/* Aperiodic autocorrelation by its definition, O(L^2). */
+/* Aperiodic autocorrelation by its definition, O(L^2). Long sequences spread
+ * the shifts k over threads; each C_k is an integer sum, so its value does
+ * not depend on how the shifts are divided. */
 OC_API void oc_corr(const int8_t *s, int L, int32_t *C)
 {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 256) if (L >= 8192)
+#endif
     for (int k = 0; k < L; ++k) {
         int32_t acc = 0;
         for (int i = 0; i + k < L; ++i)

@@ -86,3 +86,30 @@ def alpha2_for(L: int) -> int:
     if L <= 262143:
         return 11
     return 10
+
+
+def serve_jobs(n: int, seed: int, nlmt_cap: int) -> list[dict]:
+    """The serving workload's job mixture: half L = 2^m - 1 (m = 14..20
+    uniform), half odd L uniform in [1001, 1048575]; step budget uniform in
+    [50, 500]; N_lmt = min(L, nlmt_cap); job i has seed BASE_SEED + i."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    jobs = []
+    for i in range(n):
+        if rng.random() < 0.5:
+            L = 2 ** int(rng.integers(14, 21)) - 1
+        else:
+            L = 2 * int(rng.integers(500, 524288)) + 1
+        budget = int(rng.integers(50, 501))
+        jobs.append({"L": L, "budget": budget, "n_lmt": min(L, nlmt_cap),
+                     "alpha2": alpha2_for(L), "seed": BASE_SEED + i})
+    return jobs
+
+
+def serve_mixture_50() -> list[dict]:
+    """The 50-job sample of the serving mixture that the serving parity test
+    submits in waves: budgets cut to 5..60 steps so the check stays short."""
+    rng = np.random.default_rng(2107)
+    jobs = serve_jobs(50, BASE_SEED + 7, 256)
+    for j in jobs:
+        j["budget"] = int(rng.integers(5, 61))
+    return jobs

@@ -28,11 +28,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs x 64 lanes x 2.4 GHz of 32-bit / non-packed FP64 VALU issue.
+# MI355X: 256 CUs x 64 lanes x 2.4 GHz of 32-bit / non-packed FP64 VALU issue
+# (each CU issues one 64-lane VALU instruction per clock: 4 SIMDs, 4 clocks each).
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
-# Algorithmic VALU lane-ops per C_k-update: form C' (1), fold |C'| into the
-# running max (1), select T(|C'|) (1), one FP64 add (1).
-OPS_PER_UPDATE = 4
+# VALU lane-ops per C_k-update of the direct form of the one-element flip: form
+# C' (1), fold |C'| into the running max (1), select T(|C'|) (1), one FP64 add
+# (1). The evaluation kernel needs fewer (it skips the unchanged shifts and
+# resolves two or four shifts per table lookup), so this figure is reported
+# beside the roofline, not as it.
+OPS_PER_UPDATE_DIRECT = 4
+# cfg2 (the batched uniform configuration) runs 100 steps per walk.
+BATCHED_STEPS = 100
 # Paper, Table 4 (A100 SXM4, N_lmt = 6912, one walk, alpha 4/10): context only.
 PAPER_A100_NSE = {16383: 4678451, 32767: 2577101, 65535: 1258873, 131071: 638043,
                   262143: 326148, 524287: 167861, 1048575: 85062}
@@ -40,7 +46,8 @@ PAPER_A100_NSE = {16383: 4678451, 32767: 2577101, 65535: 1258873, 131071: 638043
 
 # Sources that define the evaluation kernel: a counter record is valid only for
 # the exact text it was taken from.
-KERNEL_SOURCES = ("paper_2107_09801_amd/csrc/psl_kernels.hip", "paper_2107_09801_amd/csrc/psl_device.h")
+KERNEL_SOURCES = ("paper_2107_09801_amd/csrc/psl_eval.hip", "paper_2107_09801_amd/csrc/psl_dev_util.h",
+                  "paper_2107_09801_amd/csrc/psl_device.h")
 
 
 def kernel_source_digest() -> str:
@@ -51,11 +58,11 @@ def kernel_source_digest() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(tag: str):
-    """HBM bytes per launch of the evaluation kernel for workload `tag`, from the
-    `traffic-record:` line of a committed rocprofv3 counter summary (FETCH_SIZE
-    and WRITE_SIZE, each scaled by what the counter reads for a copy of known
-    size). None when there is no record or the kernel's sources changed since."""
+def counter_record(kind: str, tag: str):
+    """The `<kind>-record:` line of a committed rocprofv3 counter summary under
+    profiles/ for workload `tag` (a dict of its key=value fields), or None when
+    there is none or the evaluation kernel's sources changed since it was
+    taken."""
     pdir = os.path.join(ROOT, "profiles")
     if not os.path.isdir(pdir):
         return None
@@ -64,19 +71,36 @@ def measured_traffic(tag: str):
         with open(os.path.join(pdir, name), encoding="utf-8", errors="replace") as f:
             for line in f:
                 line = line.strip().strip("`")
-                if not line.startswith("traffic-record:"):
+                if not line.startswith(f"{kind}-record:"):
                     continue
                 kv = dict(t.split("=", 1) for t in line.split()[1:] if "=" in t)
                 if kv.get("workload") == tag and kv.get("source_sha256") == digest:
-                    return int(kv["fetch_bytes_per_launch"]) + int(kv["write_bytes_per_launch"])
+                    return kv
     return None
+
+
+def measured_traffic(tag: str):
+    """HBM bytes per launch of the evaluation kernel for workload `tag`, from the
+    `traffic-record:` line (FETCH_SIZE and WRITE_SIZE, each scaled by what the
+    counter reads for a copy of known size)."""
+    kv = counter_record("traffic", tag)
+    return None if kv is None else int(kv["fetch_bytes_per_launch"]) + int(kv["write_bytes_per_launch"])
+
+
+def measured_valu(tag: str):
+    """VALU instructions (64-lane wavefront instructions, SQ_INSTS_VALU) per
+    launch of the evaluation kernel for workload `tag`, from the
+    `valu-record:` line."""
+    kv = counter_record("valu", tag)
+    return None if kv is None else float(kv["sq_insts_valu_per_launch"])
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=BATCHED_STEPS,
+                    help="timed steps (default: the batched configuration's 100 steps per walk)")
+    ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--workload", default="batched",
                     choices=["batched", "single", "large", "uneven", "paper"],
                     help="batched: 1024 walks at L=131071 (the headline); single: one walk at "
@@ -92,10 +116,10 @@ def parse():
                     help="time every evaluation launch shape on the batch first and keep the fastest")
     ap.add_argument("--eval-items", type=int, default=0,
                     help="minimum work items per evaluation launch (0 = the library default)")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="target duration of the oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="target duration of the oracle sample, per mode (one thread; all cores)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=10.0,
+    ap.add_argument("--serve-seconds", type=float, default=120.0,
                     help="arrival window of the serving run (0: skip it)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrivals per second")
     ap.add_argument("--serve-nlmt", type=int, default=256,
@@ -119,16 +143,45 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(L: int, n_lmt: int, alpha: int, target_s: float, max_walks: int) -> dict:
+def host_info() -> dict:
+    """The host the oracle runs on: CPU model, logical CPUs, the CPUs this
+    process may run on, and the OpenMP thread setting of the environment."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = os.cpu_count() or 1
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity_cpus": affinity,
+            "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS")}
+
+
+def all_core_threads(info: dict) -> int:
+    """Every CPU this process may use, limited by OMP_NUM_THREADS when the
+    environment sets it (the share of the host's cores given to one GPU)."""
+    n = info["affinity_cpus"]
+    omp = info["OMP_NUM_THREADS"]
+    if omp and omp.isdigit() and int(omp) > 0:
+        n = min(n, int(omp))
+    return max(1, n)
+
+
+def oracle_rate(L: int, n_lmt: int, alpha: int, target_s: float, max_walks: int, threads: int):
     """The oracle's Neighborhood for the first step of walks 0, 1, ... (their
     own seeds and starts), in scan-order slices, until about target_s seconds
-    have passed. Only the evaluation is timed (the O(L^2) setup of each
-    walk's C is not)."""
+    have passed. Only the evaluation is timed (the O(L^2) setup of each walk's
+    C is not). Returns (neighbour evaluations, seconds, walks)."""
     import oracle
     import seeded_inputs as si
-    threads = max(1, min(16, os.cpu_count() or 1))
     done, walks, el = 0, 0, 0.0
-    chunk = max(threads * 4, 64)
+    chunk = max(threads * 4, 16)
     for w in range(max_walks):
         seed = si.walk_seed(w)
         s = oracle.rand_pivot(seed, L)
@@ -146,31 +199,27 @@ def cpu_baseline(L: int, n_lmt: int, alpha: int, target_s: float, max_walks: int
         walks += 1
         if el >= target_s:
             break
-    return {"value": done / el, "unit": "flip-evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"{done} neighbour evaluations from the first step of {walks} walk(s) "
-                      f"at L={L} (alpha={alpha}), {el:.1f} s of evaluation, OpenMP over "
-                      f"candidates on {threads} threads",
-            "C_k_updates_per_s": done * (L - 1) / el}
+    return done, el, walks
 
 
-def serve_jobs(n: int, seed: int, nlmt_cap: int):
-    """The serving workload's job mixture: half L = 2^m - 1 (m = 14..20
-    uniform), half odd L uniform in [1001, 1048575]; step budget uniform in
-    [50, 500]; N_lmt = min(L, nlmt_cap); job i has seed BASE_SEED + i."""
-    import numpy as np
-
-    import seeded_inputs as si
-    rng = np.random.Generator(np.random.PCG64(seed))
-    jobs = []
-    for i in range(n):
-        if rng.random() < 0.5:
-            L = 2 ** int(rng.integers(14, 21)) - 1
-        else:
-            L = 2 * int(rng.integers(500, 524288)) + 1
-        budget = int(rng.integers(50, 501))
-        jobs.append({"L": L, "budget": budget, "n_lmt": min(L, nlmt_cap),
-                     "alpha2": si.alpha2_for(L), "seed": si.BASE_SEED + i})
-    return jobs
+def cpu_baseline(L: int, n_lmt: int, alpha: int, target_s: float, max_walks: int) -> dict:
+    """The oracle timed in two modes on the host: one thread, and OpenMP over
+    candidates on every core this process may use (see all_core_threads)."""
+    info = host_info()
+    threads = all_core_threads(info)
+    d1, e1, w1 = oracle_rate(L, n_lmt, alpha, target_s, max_walks, 1)
+    dn, en, wn = oracle_rate(L, n_lmt, alpha, target_s, max_walks, threads)
+    return {"value": dn / en, "unit": "flip-evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{dn} neighbour evaluations from the first step of {wn} walk(s) at L={L} "
+                      f"(alpha={alpha}), {en:.1f} s of evaluation, OpenMP over candidates on {threads} "
+                      f"threads ({info['cpu_model']}, nproc {info['nproc']}, "
+                      f"{info['affinity_cpus']} CPUs in this process's affinity, "
+                      f"OMP_NUM_THREADS={info['OMP_NUM_THREADS']})",
+            "C_k_updates_per_s": dn * (L - 1) / en,
+            "single_thread": {"value": d1 / e1, "unit": "flip-evals/s", "cores": 1,
+                              "C_k_updates_per_s": d1 * (L - 1) / e1,
+                              "sample": f"{d1} neighbour evaluations from {w1} walk(s), {e1:.1f} s"},
+            "host": info}
 
 
 def run_serving(libpsl, seconds: float, rate: float, nlmt_cap: int) -> dict:
@@ -181,7 +230,7 @@ def run_serving(libpsl, seconds: float, rate: float, nlmt_cap: int) -> dict:
     rng = np.random.Generator(np.random.PCG64(si.BASE_SEED))
     n = int(rng.poisson(rate * seconds))
     arrivals = np.sort(rng.uniform(0.0, seconds, size=n))
-    jobs = serve_jobs(n, si.BASE_SEED + 1, nlmt_cap)
+    jobs = si.serve_jobs(n, si.BASE_SEED + 1, nlmt_cap)
     ctx = libpsl.Context(0)
     ctx.serve_start(hbm_budget=200 << 30, max_slots=4096)
     outstanding, results = set(), {}
@@ -227,7 +276,7 @@ def run_compare(libpsl, n: int, nlmt_cap: int) -> dict:
     """The same jobs served together (all submitted at once) and run one walk
     per launch sequence, one job after the other (captured-graph steps)."""
     import seeded_inputs as si
-    jobs = serve_jobs(n, si.BASE_SEED + 2, nlmt_cap)
+    jobs = si.serve_jobs(n, si.BASE_SEED + 2, nlmt_cap)
     evals = sum(j["budget"] * j["n_lmt"] for j in jobs)
     ctx = libpsl.Context(0)
     ctx.serve_start(hbm_budget=200 << 30, max_slots=4096)
@@ -526,8 +575,11 @@ def main():
     tuned = ctx.autotune(ids) if args.autotune else None
     if tuned is not None:
         log(f"autotuned: {tuned}")
+    warm_s = 0.0
     if args.warmup:
+        t0 = time.perf_counter()
         ctx.step_batch(ids, args.warmup, blocking=True, graph=args.graph)
+        warm_s = time.perf_counter() - t0
         log(f"{args.warmup} warmup step(s) done")
     torch.cuda.synchronize()
     tm = None
@@ -550,10 +602,41 @@ def main():
         ctx.timing_enable(False)
     log(f"{args.steps} timed step(s) in {el:.3f} s")
     st = ctx.read_walk(ids[0], bits=False, C=False)
+    whole = None
+    if wl == "batched" and args.warmup + args.steps < BATCHED_STEPS:
+        # the rest of the configuration's 100 steps (a phase switch after
+        # steps 50 and 100), so its whole run is timed too
+        rest = BATCHED_STEPS - args.warmup - args.steps
+        t0 = time.perf_counter()
+        ctx.step_batch(ids, rest, blocking=True, graph=args.graph)
+        torch.cuda.synchronize()
+        rest_s = time.perf_counter() - t0
+        st_end = ctx.read_walk(ids[0], bits=False, C=False)
+        total_s = warm_s + el + rest_s
+        whole = {"steps": BATCHED_STEPS, "s": total_s, "ms_per_step": total_s / BATCHED_STEPS * 1e3,
+                 "flip_evals_per_s": evals_per_step * BATCHED_STEPS / total_s,
+                 "switches_after_steps": [t for t in range(1, BATCHED_STEPS + 1) if period and t % period == 0],
+                 "walk0_after": {"t": st_end["t"], "q": st_end["q"], "psl_best": st_end["psl_best"],
+                                 "alpha": st_end["alpha"]},
+                 "note": "warmup, timed and remaining steps of the configuration's 100 steps, each "
+                         "bracketed by a device sync (wall clock)"}
+        log(f"whole run: {BATCHED_STEPS} steps in {total_s:.3f} s")
 
     value = evals_per_step * args.steps / el
     eval_avg_s = tm["eval_ms"] / max(1, tm["eval_launches"]) / 1e3
-    achieved = OPS_PER_UPDATE * updates_per_step / eval_avg_s
+    tag = f"{wl}_L{'-'.join(str(g[0]) for g in groups)}_w{nw}"
+    valu = measured_valu(tag)
+    if valu is not None:
+        roofline = {"bound": "alu", "achieved": valu * 64 / eval_avg_s / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                    "unit": "Tlane-op/s", "frac": valu * 64 / eval_avg_s / PEAK_LANE_OPS,
+                    "traffic": measured_traffic(tag), "traffic_unit": "B/launch",
+                    "basis": "VALU lane-ops per launch (SQ_INSTS_VALU x 64, the valu-record of the "
+                             "kernel's committed counter profile) / the launch time measured here"}
+    else:
+        roofline = {"bound": "alu", "achieved": None, "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-op/s",
+                    "frac": None, "traffic": measured_traffic(tag), "traffic_unit": "B/launch",
+                    "basis": "no SQ_INSTS_VALU record for these kernel sources and this workload"}
+    direct = OPS_PER_UPDATE_DIRECT * updates_per_step / eval_avg_s
     tiles, ks = ctx.eval_shape(L, n_lmt, nw)
     names = {"batched": "batched uniform", "single": "single walk", "large": "large single instance",
              "uneven": "uneven batch", "paper": "paper settings (Table 4)"}
@@ -585,12 +668,19 @@ def main():
         "eval_kernel": {"avg_ms": eval_avg_s * 1e3, "launches": tm["eval_launches"],
                         "updates_per_s": updates_per_step / eval_avg_s,
                         "rest_of_step_avg_ms": tm["rest_ms"] / max(1, tm["steps"])},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                     "unit": "Tlane-op/s", "frac": achieved / PEAK_LANE_OPS,
-                     "traffic": measured_traffic(f"{wl}_L{'-'.join(str(g[0]) for g in groups)}_w{nw}"),
-                     "traffic_unit": "B/launch"},
+        "roofline": roofline,
+        "vs_direct_form": {"direct_lane_ops_per_update": OPS_PER_UPDATE_DIRECT,
+                           "nominal_updates_per_s": updates_per_step / eval_avg_s,
+                           "ceiling_updates_per_s": PEAK_LANE_OPS / OPS_PER_UPDATE_DIRECT,
+                           "ratio": direct / PEAK_LANE_OPS,
+                           "lane_ops_per_nominal_update": (valu * 64 / updates_per_step) if valu else None,
+                           "note": "nominal C_k-updates/s of the evaluation against the ceiling of the "
+                                   "direct form (4 VALU lane-ops per update); above 1 because the kernel "
+                                   "skips the unchanged shifts and resolves 2 or 4 shifts per table lookup"},
         "walk0_after": {"t": st["t"], "psl_best": st["psl_best"], "alpha": st["alpha"]},
     }
+    if whole is not None:
+        out["whole_run"] = whole
     if tuned is not None:
         out["autotune"] = tuned
     if wl == "large":

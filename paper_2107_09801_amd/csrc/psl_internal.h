@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -35,10 +36,13 @@ public:
         if (base && bytes >= kAlign) free_[0] = bytes & ~(kAlign - 1);
     }
     bool active() const { return base_ != nullptr; }
-    void *alloc(size_t bytes)
+    // First fit; with a limit, only a block that ends at or below offset
+    // `limit` is taken.
+    void *alloc(size_t bytes, size_t limit = SIZE_MAX)
     {
         bytes = (bytes + kAlign - 1) & ~(kAlign - 1);
         for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->first + bytes > limit) break;          // offsets only grow from here
             if (it->second >= bytes) {
                 size_t off = it->first, len = it->second;
                 free_.erase(it);
@@ -48,6 +52,11 @@ public:
             }
         }
         return nullptr;
+    }
+    // End offset of the highest block in use (0 when none is).
+    size_t used_end() const
+    {
+        return used_.empty() ? 0 : used_.rbegin()->first + used_.rbegin()->second;
     }
     void release(void *p)
     {
@@ -116,6 +125,7 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 constexpr size_t kPlanCache = 8;   // step batches whose layout (and graph) is kept
 constexpr uint32_t kEvalItemsDefault = 4096;    // PSL_OPT_EVAL_ITEMS default
 constexpr uint32_t kEvalItemsMax = 1u << 18;    // and its largest value
+constexpr int64_t kAmbigMarginMax = 1000000000000000ll;  // PSL_OPT_AMBIG_MARGIN: 1.0 in units of 1e-15
 
 
 struct Server;   // serving loop (psl_serve.hip)
@@ -143,6 +153,8 @@ struct psl_ctx {
     std::string err;
     int64_t near_limit = -1;          // PSL_OPT_NEAR_LIMIT
     uint32_t eval_items = psl_rt::kEvalItemsDefault;  // PSL_OPT_EVAL_ITEMS
+    double amb_margin = psl::kAmbigMarginDefault;     // PSL_OPT_AMBIG_MARGIN (relative)
+    uint64_t test_fail_admit = 0;     // PSL_OPT_TEST_FAIL_ADMIT
     psl_rt::Server *server = nullptr; // serving loop, when started
     uint32_t n_cu = 256;              // compute units of the device
     std::map<uint32_t, psl::EvalShape> tuned;  // autotuner choices by tune_key

@@ -1,14 +1,9 @@
-// psl_kernels.hip -- gfx950 kernels of libpsl.
-//
-// The hot path is the limited-neighbourhood evaluation of Algorithm 1 (the
-// Neighborhood call): for every candidate flip j and every shift k the
-// one-element flip gives C'_k = C_k - 2 s_j (s_{j+k}[j+k<L] + s_{j-k}[j-k>=0])
-// (Section 3, with Eq. (2)), and from the C'_k the kernel accumulates
-// F_j = sum_k |C'_k|^alpha (Eq. (5)) and PSL_j = max_k |C'_k| (Eq. (3)).
-//
-// Layout: one lane per candidate, 64 candidates per wavefront, 4, 8 or 16
-// wavefronts per block; shifts are swept in LDS-staged tiles (see eval_item),
-// one block per work item or a persistent grid over per-XCD queues.
+// psl_kernels.hip -- gfx950 kernels of libpsl around the neighbourhood
+// evaluation (which lives in psl_eval.hip): power tables, init and the
+// correlations of Eq. (2), the phase-switch rebuild, the per-step chunk sums
+// and near-peak list the evaluation reads, the selection of Algorithm 1's
+// scan, the O(L) flip of Section 3 and the step's bookkeeping.
+#include "psl_dev_util.h"
 #include "psl_device.h"
 #include "psl_launch.h"
 
@@ -16,105 +11,6 @@
 #include <climits>
 
 namespace psl {
-
-// ------------------------------------------------------------ helpers
-
-// Counter-based SplitMix64 (Steele, Lea & Flood 2014): output ctr+1 of the
-// stream whose state starts at seed.
-__device__ __forceinline__ uint64_t draw(uint64_t seed, uint64_t ctr)
-{
-    uint64_t z = seed + (ctr + 1u) * 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-
-__device__ __forceinline__ uint32_t step_start(const WalkDev &w)
-{
-    return (uint32_t)(draw(w.seed, (1ull << 60) | w.t) % (uint64_t)w.L);
-}
-
-__device__ __forceinline__ uint32_t get_bit(const uint64_t *b, uint32_t i)
-{
-    return (uint32_t)((b[i >> 6] >> (i & 63u)) & 1u);
-}
-
-// dst[x] = src[x] for x < n (word flip_word also XORed with flip_mask), the
-// threads of a block striding by nthreads. The two arrays never overlap;
-// each thread issues eight loads before their stores instead of waiting on
-// one load per word.
-__device__ __forceinline__ void copy_words(uint64_t *__restrict__ dst, const uint64_t *__restrict__ src,
-                                           uint32_t n, uint32_t tid, uint32_t nthreads, uint32_t flip_word,
-                                           uint64_t flip_mask)
-{
-    uint32_t x = tid;
-    for (; x + 7u * nthreads < n; x += 8u * nthreads) {
-        uint64_t v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = src[x + (uint32_t)u * nthreads];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const uint32_t y = x + (uint32_t)u * nthreads;
-            dst[y] = y == flip_word ? v[u] ^ flip_mask : v[u];
-        }
-    }
-    for (; x < n; x += nthreads) dst[x] = x == flip_word ? src[x] ^ flip_mask : src[x];
-}
-
-// Bits [pos, pos+32) of a packed sequence held as nw32 32-bit words; bits
-// outside the words read as 0.
-__device__ __forceinline__ uint32_t bits32_at(const uint32_t *__restrict__ w32, int nw32,
-                                              int pos)
-{
-    int wi = pos >> 5;
-    uint32_t sh = (uint32_t)pos & 31u;
-    uint32_t lo = (wi >= 0 && wi < nw32) ? w32[wi] : 0u;
-    uint32_t hi = (wi + 1 >= 0 && wi + 1 < nw32) ? w32[wi + 1] : 0u;
-    return __builtin_amdgcn_alignbit(hi, lo, sh);
-}
-
-__device__ __forceinline__ double dmax(double a, double b) { return a > b ? a : b; }
-
-// High 32 bits of a non-negative double. Over the power table they are
-// strictly increasing in |c| (consecutive entries differ by a factor of at
-// least 1 + 2^-19 for alpha >= 2 and |c| <= 2^20 + 8; for alpha = 1 the
-// entries are integers below 2^21, exact in 20 fraction bits), so the
-// running maximum of T(|C'|) can be kept as a 32-bit unsigned maximum.
-__device__ __forceinline__ uint32_t hi32(double v)
-{
-    return (uint32_t)((uint64_t)__double_as_longlong(v) >> 32);
-}
-
-// Neumaier's compensated addition.
-__device__ __forceinline__ void nsum_add(double &sum, double &comp, double x)
-{
-    double t = sum + x;
-    if (fabs(sum) >= fabs(x)) comp += (sum - t) + x;
-    else                      comp += (x - t) + sum;
-    sum = t;
-}
-
-// Smallest c with hi32(T[c]) >= h: |c| from the high word of T(|c|).
-__device__ __forceinline__ int32_t table_inverse(const double *T, uint32_t n, uint32_t h)
-{
-    uint32_t lo = 0, hi = n - 1;
-    while (lo < hi) {
-        uint32_t mid = (lo + hi) >> 1;
-        if (hi32(T[mid]) < h) lo = mid + 1;
-        else                  hi = mid;
-    }
-    return (int32_t)lo;
-}
-
-// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
-// contiguous range of work items so that the blocks of one walk share an L2.
-__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t nb)
-{
-    const uint32_t nx = 8;
-    uint32_t q = nb / nx, r = nb % nx;
-    uint32_t x = b % nx, local = b / nx;
-    return x * q + (x < r ? x : r) + local;
-}
 
 // ------------------------------------------------------- power tables
 
@@ -674,420 +570,6 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(WalkDev *walks, const Bat
     }
 }
 
-// Wave-wide minimum / maximum of an int (result uniform; every lane of the
-// wavefront active). lane = this lane's index in its wavefront, passed in
-// so that the permute addresses derive from the caller's value.
-__device__ __forceinline__ int wave_min(int v, int lane)
-{
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __builtin_amdgcn_ds_bpermute((lane ^ o) << 2, v));
-    return __builtin_amdgcn_readfirstlane(v);
-}
-__device__ __forceinline__ int wave_max(int v, int lane)
-{
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __builtin_amdgcn_ds_bpermute((lane ^ o) << 2, v));
-    return __builtin_amdgcn_readfirstlane(v);
-}
-
-// One-neighbour tables of a 32-shift window: eight quads of shifts, 16
-// entries each, indexed by the quad's four bits.
-constexpr int kOneQuads = 8;
-constexpr int kOneWin = 16 * kOneQuads;
-constexpr int kOneItems = 4 * kOneQuads;   // table-building items per window
-
-// LDS of one evaluation block.
-struct EvalLds {
-    // first, so that a window's two-word read needs no base offset (the
-    // offsets of ds_read2_b32 are 8-bit dword counts)
-    uint32_t bits[kEvalWavesMax * 64];  // per wavefront: its pivot words of the tile
-    double rows[kTileK * kRowStride];   // T(|C_k + 2m|), m = -2..2, per shift
-    double both[kPairs * 16];           // pair sums, both neighbours
-    double one[kChunks * kOneWin];      // quad sums, one neighbour
-    uint32_t both_max[kPairs * 16];     // max hi32 of the pair (dense PSL only)
-    uint32_t one_max[kChunks * kOneWin];
-    int kend[kEvalWavesMax];            // per wavefront
-    int bmax[kEvalWavesMax];
-    int omax[kEvalWavesMax];
-};
-
-// The sweep of one item. kMax: keep the PSL maximum in the main loop (dense
-// form); otherwise the near-peak pass supplies it.
-template <int WAVES, bool kMax>
-__device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const BatchEntry &be,
-                                           const EvalItem &it, const double *__restrict__ T,
-                                           uint32_t n_lmt, int j, uint32_t SJ, int k_lo, int k_hi,
-                                           int tid, double &sum, double &comp, uint32_t &mx)
-{
-    const int L = (int)w.L;
-    const int32_t *__restrict__ C = w.C;
-    const uint32_t *__restrict__ w32 = reinterpret_cast<const uint32_t *>(w.pivot);
-
-    // in-bounds limits: right neighbour for k <= jr, left for k <= jl
-    const int jl = j, jr = L - 1 - j;
-    const int lane = tid & 63;
-    const int jl_min = wave_min(jl, lane), jl_max = wave_max(jl, lane);
-    const int jr_min = wave_min(jr, lane), jr_max = wave_max(jr, lane);
-    const int both_max = min(jl_min, jr_min);             // all lanes: both exist
-    const int one_max = max(jl_min, jr_min);              // all lanes: one exists
-    // first shift at which every lane of the wave has neither neighbour,
-    // rounded up to a chunk start; explicit shifts end there
-    const int k_none = max(jl_max, jr_max) + 1;
-    const int k_wend = min(k_hi, 1 + 32 * ((k_none - 1 + 31) / 32));
-    const int wave = tid >> 6;
-    if ((tid & 63) == 0) {
-        sh.kend[wave] = k_wend;
-        sh.bmax[wave] = both_max;
-        sh.omax[wave] = one_max;
-    }
-    __syncthreads();
-    int k_bend = sh.kend[0], b_bmax = sh.bmax[0], b_omax = sh.omax[0];
-    for (int x = 1; x < WAVES; ++x) {
-        k_bend = max(k_bend, sh.kend[x]);
-        b_bmax = max(b_bmax, sh.bmax[x]);
-        b_omax = max(b_omax, sh.omax[x]);
-    }
-
-    // bit windows: the right window of chunk c starts at element
-    // j + 1 + 32c (words (j+1)/32 + c and the next, shift (j+1)%32); the
-    // left window ends at element j - 1 - 32c and starts at j - 32 - 32c
-    // (words j/32 - 1 - c and the next, shift j%32). Per tile each
-    // wavefront stages the words its windows read in LDS: the lanes of a
-    // wavefront hold consecutive scan indices, so their j form at most two
-    // runs of consecutive values (two when the scan wraps past L-1); per run
-    // g, 16 slots of right words in increasing order and 16 slots of left
-    // words in decreasing order.
-    const uint32_t sh_r = (uint32_t)(j + 1) & 31u;
-    const uint32_t sh_l = (uint32_t)j & 31u;
-    const int j_first = __builtin_amdgcn_readlane(j, 0);
-    const int grp = j < j_first ? 1 : 0;
-    constexpr int kNone = 1 << 30;                        // empty run: min > max
-    const int jmn0 = wave_min(grp ? kNone : j, lane), jmx0 = wave_max(grp ? -kNone : j, lane);
-    const int jmn1 = wave_min(grp ? j : kNone, lane), jmx1 = wave_max(grp ? j : -kNone, lane);
-    const int jmn = grp ? jmn1 : jmn0, jmx = grp ? jmx1 : jmx0;
-    const uint32_t *rbits = sh.bits + 64 * wave + 32 * grp + (((j + 1) >> 5) - ((jmn + 1) >> 5));
-    const uint32_t *lbits = sh.bits + 64 * wave + 32 * grp + 16 + ((jmx >> 5) - (j >> 5));
-    // the slots this lane stages: run lane/32, side (lane/16)%2, slot lane%16
-    const int s_grp = lane >> 5, s_side = (lane >> 4) & 1, s_idx = lane & 15;
-    const int s_mn = s_grp ? jmn1 : jmn0, s_mx = s_grp ? jmx1 : jmx0;
-    const int s_span = s_side ? (s_mx >> 5) - (s_mn >> 5) : ((s_mx + 1) >> 5) - ((s_mn + 1) >> 5);
-
-    for (int kt = k_lo; kt < k_bend; kt += kTileK) {
-        const int kt_end = min(k_bend, kt + kTileK);
-        const int nt = kt_end - kt;
-        // which pair tables some wave of the block can use in this tile
-        const bool need_both = kt + 31 <= b_bmax;
-        const bool need_one = kt + 31 <= b_omax;
-        __syncthreads();
-        {
-            // this wavefront's words for its windows of the tile (chunks
-            // cb .. cb + cc_last)
-            const int cb = (kt - 1) >> 5;
-            const int cc_last = kt < k_wend ? min(kChunks - 1, (k_wend - 1 - kt) >> 5) : -1;
-            if (s_mn <= s_mx && s_idx < s_span + cc_last + 2) {
-                const int word = s_side ? (s_mx >> 5) - cb - s_idx : ((s_mn + 1) >> 5) + cb + s_idx;
-                sh.bits[64 * wave + lane] = w32[word];
-            }
-        }
-        for (int t = tid; t < nt; t += 64 * WAVES) {
-            const int c = C[kt + t];
-#pragma unroll
-            for (int m = 0; m < kRowStride; ++m) {
-                int a = c + 2 * m - 4;
-                a = a < 0 ? -a : a;
-                sh.rows[t * kRowStride + m] = T[a];
-            }
-        }
-        __syncthreads();
-        if (need_both) {
-            // both neighbours: C' = C + 4(xr + xl - 1), row entry 2(xr + xl).
-            // Entry x of pair p: low two bits the left pair (xl_k, xl_k+1),
-            // high two the right pair; one thread per (pair, right bits)
-            // writes its four consecutive entries.
-            for (int e = tid; e < kPairs * 4; e += 64 * WAVES) {
-                const int p = e >> 2, r0 = e & 1, r1 = (e >> 1) & 1;
-                if (2 * p + 1 < nt) {
-                    const double *ra = sh.rows + (2 * p) * kRowStride + 2 * r0;
-                    const double *rb = sh.rows + (2 * p + 1) * kRowStride + 2 * r1;
-                    const double a0 = ra[0], a1 = ra[2], b0 = rb[0], b1 = rb[2];
-                    double2 *dst = reinterpret_cast<double2 *>(sh.both + 4 * e);
-                    dst[0] = make_double2(a0 + b0, a1 + b0);
-                    dst[1] = make_double2(a0 + b1, a1 + b1);
-                    if (kMax) {
-                        const uint32_t ha0 = hi32(a0), ha1 = hi32(a1), hb0 = hi32(b0), hb1 = hi32(b1);
-                        *reinterpret_cast<uint4 *>(sh.both_max + 4 * e) =
-                            make_uint4(max(ha0, hb0), max(ha1, hb0), max(ha0, hb1), max(ha1, hb1));
-                    }
-                }
-            }
-        }
-        if (need_one) {
-            // one neighbour: C' = C + 2(2x - 1), row entry 1 + 2x. Entry x of
-            // quad q: bit i of x is the bit of shift 4q + i. Item (q, h) of a
-            // window writes the four consecutive entries whose two high bits
-            // are h: (a + b) + (c + d).
-            for (int f = tid; f < kChunks * kOneItems; f += 64 * WAVES) {
-                const int cc = f / kOneItems, r = f - cc * kOneItems;
-                const int q = r >> 2, h0 = r & 1, h1 = (r >> 1) & 1;
-                const int t0 = 32 * cc + 4 * q;
-                if (t0 + 3 < nt) {
-                    const double *ra = sh.rows + t0 * kRowStride + 1;
-                    const double a0 = ra[0], a1 = ra[2];
-                    const double b0 = ra[kRowStride], b1 = ra[kRowStride + 2];
-                    const double c = ra[2 * kRowStride + 2 * h0], d = ra[3 * kRowStride + 2 * h1];
-                    const double cd = c + d;
-                    double2 *dst = reinterpret_cast<double2 *>(sh.one + kOneWin * cc + 16 * q + 4 * (r & 3));
-                    dst[0] = make_double2((a0 + b0) + cd, (a1 + b0) + cd);
-                    dst[1] = make_double2((a0 + b1) + cd, (a1 + b1) + cd);
-                    if (kMax) {
-                        const uint32_t hcd = max(hi32(c), hi32(d));
-                        const uint32_t ha0 = max(hi32(a0), hcd), ha1 = max(hi32(a1), hcd);
-                        const uint32_t hb0 = hi32(b0), hb1 = hi32(b1);
-                        *reinterpret_cast<uint4 *>(sh.one_max + kOneWin * cc + 16 * q + 4 * (r & 3)) =
-                            make_uint4(max(ha0, hb0), max(ha1, hb0), max(ha0, hb1), max(ha1, hb1));
-                    }
-                }
-            }
-        }
-        __syncthreads();
-
-        double acc = 0.0;
-        // the next window's words are read one window ahead (slots past
-        // the staged ones hold stale words that are never used)
-        uint32_t r0 = rbits[0], r1 = rbits[1], l0 = lbits[0], l1 = lbits[1];
-#pragma unroll
-        for (int cc = 0; cc < kChunks; ++cc) {
-            const int k0 = kt + 32 * cc;
-            const uint32_t cr0 = r0, cr1 = r1, cl0 = l0, cl1 = l1;
-            if (cc + 1 < kChunks) {
-                r0 = rbits[cc + 1];
-                r1 = rbits[cc + 2];
-                l0 = lbits[cc + 1];
-                l1 = lbits[cc + 2];
-            }
-            if (k0 < k_wend) {
-                // a side's window bits, x = 1 where s_j times the neighbour is
-                // -1 (formed only in the forms that use that side)
-                auto win_r = [&]() { return __builtin_amdgcn_alignbit(cr1, cr0, sh_r) ^ SJ; };
-                auto win_l = [&]() {
-                    return __builtin_bitreverse32(__builtin_amdgcn_alignbit(cl0, cl1, sh_l) ^ SJ);
-                };
-                const int tcount = min(32, kt_end - k0);
-                const double *bp = sh.both + (16 * 16) * cc;
-                const double *op = sh.one + kOneWin * cc;
-                const uint32_t *bq = sh.both_max + (16 * 16) * cc;
-                const uint32_t *oq = sh.one_max + kOneWin * cc;
-                if (tcount == 32 && k0 + 31 <= both_max) {
-                    const uint32_t XR = win_r(), XL = win_l();
-                    // nibble q of W0 (W1) is the table index of pair 2q
-                    // (2q+1): its two left bits below its two right bits
-                    const uint32_t W0 = (XL & 0x33333333u) | ((XR << 2) & 0xCCCCCCCCu);
-                    const uint32_t W1 = ((XL >> 2) & 0x33333333u) | (XR & 0xCCCCCCCCu);
-                    // the reads go out in groups of eight before their adds
-#pragma unroll
-                    for (int h = 0; h < 16; h += 8) {
-                        double v[8];
-#pragma unroll
-                        for (int p = h; p < h + 8; ++p) {
-                            const uint32_t x = ((p & 1 ? W1 : W0) >> (4 * (p >> 1))) & 15u;
-                            v[p - h] = bp[16 * p + x];
-                            if (kMax) mx = max(mx, bq[16 * p + x]);
-                        }
-#pragma unroll
-                        for (int p = 0; p < 8; ++p) acc += v[p];
-                    }
-                } else if (tcount == 32 && k0 + 31 <= jr_min && k0 > jl_max) {
-                    const uint32_t XR = win_r();
-                    double v[kOneQuads];
-#pragma unroll
-                    for (int q = 0; q < kOneQuads; ++q) {
-                        const uint32_t x = (XR >> (4 * q)) & 15u;
-                        v[q] = op[16 * q + x];
-                        if (kMax) mx = max(mx, oq[16 * q + x]);
-                    }
-#pragma unroll
-                    for (int q = 0; q < kOneQuads; ++q) acc += v[q];
-                } else if (tcount == 32 && k0 + 31 <= jl_min && k0 > jr_max) {
-                    const uint32_t XL = win_l();
-                    double v[kOneQuads];
-#pragma unroll
-                    for (int q = 0; q < kOneQuads; ++q) {
-                        const uint32_t x = (XL >> (4 * q)) & 15u;
-                        v[q] = op[16 * q + x];
-                        if (kMax) mx = max(mx, oq[16 * q + x]);
-                    }
-#pragma unroll
-                    for (int q = 0; q < kOneQuads; ++q) acc += v[q];
-                } else {
-                    // mixed bounds or a partial chunk: per shift
-                    const uint32_t XR = win_r(), XL = win_l();
-                    const double *rb = sh.rows + (32 * cc) * kRowStride;
-                    for (int t = 0; t < tcount; ++t) {
-                        const int k = k0 + t;
-                        int m = 2;
-                        if (k <= jr) m += ((XR >> t) & 1u) ? 1 : -1;
-                        if (k <= jl) m += ((XL >> t) & 1u) ? 1 : -1;
-                        const double v = rb[t * kRowStride + m];
-                        acc += v;
-                        if (kMax) mx = max(mx, hi32(v));
-                    }
-                }
-            }
-        }
-        nsum_add(sum, comp, acc);
-    }
-    // shifts where no lane of the wave has a neighbour in bounds (kn is a
-    // chunk start; k_hi a chunk start or L, the chunk arrays' last entry)
-    const int kn = max(k_lo, k_wend);
-    if (kn < k_hi) {
-        const int nchunks = (L - 1 + 31) / 32;
-        const int xa = (kn - 1) >> 5;
-        const int xb = k_hi >= L ? nchunks : (k_hi - 1) >> 5;
-        nsum_add(sum, comp, be.S0[xa] - be.S0[xb]);
-        if (kMax) mx = max(mx, hi32(T[be.M0[xa]]));
-    }
-}
-
-// Neighborhood of Algorithm 1 for one (walk, 64*WAVES candidates, k-range) item.
-//
-// Per 256-shift tile the block stages (i) per shift the five values
-// T(|C_k + 2m|), m = -2..2, and (ii) tables of pre-added terms: for shifts
-// where both neighbours of j exist (C' = C + 4(xr + xl - 1)), 16 entries per
-// pair of shifts (k, k+1) indexed by the four bits (xl_k, xl_k+1, xr_k,
-// xr_k+1); for shifts where one neighbour exists (C' = C + 2(2x - 1)), 16
-// entries per quad of shifts indexed by its four bits; x = 1 when s_j times
-// that neighbour is -1. A lane takes a 32-shift window of each side's bits with
-// one funnel shift; per table entry it does a shift and a mask (the two
-// sides' bits are first merged nibble-wise with bit-field inserts), one LDS
-// read and one FP64 add. Which form a 32-shift window uses is decided once
-// per wavefront from the lanes' bounds. Shifts past every lane's
-// max(j, L-1-j) come from the suffix sums. The PSL comes from the near-peak
-// shifts (spread over the k-splits), or, for pivots with many near-peak shifts, from
-// 32-bit maxima kept in the main loop.
-template <int WAVES>
-__device__ __forceinline__ void eval_item(EvalLds &sh, const WalkDev *__restrict__ walks,
-                                          const BatchEntry *__restrict__ batch, const EvalItem it,
-                                          const Tables &tabs, int tid)
-{
-    const BatchEntry be = batch[it.walk];
-    const WalkDev &w = walks[be.slot];
-    const int L = (int)w.L;
-    const uint32_t n_lmt = be.fixed ? be.n_lmt : w.n_lmt;
-    const uint32_t start = be.fixed ? be.start : step_start(w);
-    const double *__restrict__ T = tabs.T[w.alpha];
-    const uint32_t *__restrict__ w32 = reinterpret_cast<const uint32_t *>(w.pivot);
-
-    // shifts of this split, in whole 32-shift chunks from k = 1
-    const int nchunks = (L - 1 + 31) / 32;
-    const int per = (nchunks + (int)be.ksplit - 1) / (int)be.ksplit;
-    const int c_lo = (int)it.ks * per;
-    const int c_hi = min(nchunks, c_lo + per);
-    const int k_lo = 1 + 32 * c_lo;
-    const int k_hi = min(L, 1 + 32 * c_hi);
-
-    // this lane's candidate; inactive lanes keep a valid j and store nothing
-    const uint32_t i = it.tile * (64 * WAVES) + (uint32_t)tid;
-    const bool active = i < n_lmt;
-    const uint32_t ii = active ? i : n_lmt - 1;
-    const int j = (int)((start + 1u + ii) % (uint32_t)L);
-    const uint32_t sjbit = (w32[j >> 5] >> (j & 31)) & 1u;
-    const uint32_t SJ = sjbit ? 0xFFFFFFFFu : 0u;
-
-    double sum = 0.0, comp = 0.0;
-    uint32_t mx = 0;
-    const uint32_t n_near = be.near[0];
-    if (n_near > be.near_lim) {
-        eval_sweep<WAVES, true>(sh, w, be, it, T, n_lmt, j, SJ, k_lo, k_hi, tid, sum, comp, mx);
-    } else {
-        eval_sweep<WAVES, false>(sh, w, be, it, T, n_lmt, j, SJ, k_lo, k_hi, tid, sum, comp, mx);
-        {
-            // PSL over the near-peak shifts, every candidate, all bounds
-            // cases; split s takes entries s, s + ksplit, ... (the combine
-            // takes the maximum over the splits)
-            const int jl = j, jr = L - 1 - j;
-            int peak = 0;
-            for (uint32_t q = it.ks; q < n_near; q += be.ksplit) {
-                const int k = (int)be.near[1 + q];
-                int c = w.C[k];
-                if (k <= jr) {
-                    const int p = j + k;
-                    c += (((w32[p >> 5] >> (p & 31)) & 1u) ^ sjbit) ? 2 : -2;
-                }
-                if (k <= jl) {
-                    const int p = j - k;
-                    c += (((w32[p >> 5] >> (p & 31)) & 1u) ^ sjbit) ? 2 : -2;
-                }
-                peak = max(peak, c < 0 ? -c : c);
-            }
-            mx = (uint32_t)peak;          // its part of the PSL (< L, far below 0x3FF00000)
-        }
-    }
-    if (active) {
-        const size_t o = (size_t)it.ks * n_lmt + i;
-        be.Fpart[o] = sum + comp;
-        be.Mpart[o] = mx;
-    }
-}
-
-// Register budget of the evaluation kernels: the LDS of a block admits three
-// blocks per CU, i.e. 3 * WAVES / 4 wavefronts per SIMD; ask the compiler to
-// keep the VGPR count low enough for that.
-template <int WAVES>
-constexpr int kEvalWavesPerEU = WAVES * 3 / 4 < 1 ? 1 : WAVES * 3 / 4 > 8 ? 8 : WAVES * 3 / 4;
-
-// One block per work item; items are laid out as 8 equal-cost XCD ranges
-// padded to equal length.
-template <int WAVES>
-__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(kEvalWavesPerEU<WAVES>)))
-void k_eval(const WalkDev *__restrict__ walks,
-                                                     const BatchEntry *__restrict__ batch,
-                                                     const EvalItem *__restrict__ items, Tables tabs)
-{
-    __shared__ EvalLds sh;
-    const EvalItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
-    if (it.walk == kNoItem) return;     // padding of an XCD's range
-    eval_item<WAVES>(sh, walks, batch, it, tabs, (int)threadIdx.x);
-}
-
-// Persistent form: a fixed grid (blocks per CU x CUs) takes items from 8
-// per-XCD queues, its own XCD's first (longest items first), then the
-// others'. Every block leaves once all 8 queues are drained.
-template <int WAVES>
-__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(kEvalWavesPerEU<WAVES>)))
-void k_eval_persistent(const WalkDev *__restrict__ walks,
-                                                                const BatchEntry *__restrict__ batch,
-                                                                const EvalItem *__restrict__ items,
-                                                                Tables tabs, EvalQueues *queues)
-{
-    __shared__ EvalLds sh;
-    __shared__ uint32_t s_item;
-    uint32_t q = blockIdx.x % 8, dry = 0;
-    while (dry < 8) {
-        __syncthreads();                // the previous item is done with LDS
-        if (threadIdx.x == 0) {
-            const uint32_t idx = atomicAdd(&queues->next[q], 1u);
-            s_item = idx < queues->count[q] ? queues->base[q] + idx : kNoItem;
-        }
-        __syncthreads();
-        const uint32_t item = s_item;
-        if (item == kNoItem) {
-            q = (q + 1) % 8;
-            ++dry;
-            continue;
-        }
-        // the thread index, opaque to the compiler once per item: values
-        // derived from it are computed per item instead of being hoisted
-        // out of this loop, where they would outlive every item in scratch
-        int tid = (int)threadIdx.x;
-        asm volatile("" : "+v"(tid));
-        __builtin_assume(tid >= 0 && tid < 64 * WAVES);
-        eval_item<WAVES>(sh, walks, batch, items[item], tabs, tid);
-    }
-}
-
-__global__ void k_queue_reset(EvalQueues *queues)
-{
-    if (threadIdx.x < 8) queues->next[threadIdx.x] = 0;
-}
-
 // ------------------------------------------------------- selection
 
 struct ChoiceDev {
@@ -1096,7 +578,7 @@ struct ChoiceDev {
     uint32_t j_psl;
     int32_t psl_min;
     int32_t psl_k;
-    uint32_t pad;
+    uint32_t flags;         // CHOICE_AMBIG_ARGMIN
 };
 
 constexpr int kSelThreads = 1024;
@@ -1134,7 +616,8 @@ __device__ __forceinline__ void sel_merge(double &f, int32_t &p, uint32_t &i, do
 // The selection of walk w (batch position bi) by a block of NT threads.
 template <int NT>
 __device__ __forceinline__ void select_walk(WalkDev &w, const BatchEntry &be, uint32_t bi, uint32_t comb_blocks,
-                                            uint32_t comb_group, int pure, ChoiceDev *out, uint32_t *pend)
+                                            uint32_t comb_group, int pure, ChoiceDev *out, uint32_t *pend,
+                                            double amb_margin)
 {
     // the previous step's pending list has been consumed; this step's
     // bookkeeping refills it
@@ -1174,33 +657,43 @@ __device__ __forceinline__ void select_walk(WalkDev &w, const BatchEntry &be, ui
     const uint32_t iPmin = r.i;
     const double thr = Fmin * (1.0 + kTau);
 
-    // the first band member lies in the first combine block (they cover
-    // contiguous runs of scan indices in order) whose minimum is in the band
-    uint32_t bfirst = my_f <= thr ? (uint32_t)threadIdx.x : UINT_MAX;
-    for (int o = 32; o > 0; o >>= 1) bfirst = min(bfirst, (uint32_t)__shfl_xor((int)bfirst, o));
-    if (lane == 0) s_first[wave] = bfirst;
-    __syncthreads();
-    for (int x = 0; x < kSelWaves; ++x) bfirst = min(bfirst, s_first[x]);
-    uint32_t lo, hi;
-    comb_range(n, comb_blocks, comb_group, bfirst, lo, hi);
-    __syncthreads();                    // s_first is reused below
-
-    // first scan index inside the band within [lo, hi): rounds of
-    // 8 * NT indices, each thread's eight loads issued together;
-    // the first round with a hit holds the answer
-    uint32_t ifirst = UINT_MAX;
-    for (uint32_t i0 = lo; i0 < hi; i0 += 8 * NT) {
-        double v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const uint32_t i = i0 + u * NT + threadIdx.x;
-            v[u] = i < hi ? be.F[i] : INFINITY;
-        }
-#pragma unroll
-        for (int u = 7; u >= 0; --u)
-            if (v[u] <= thr) ifirst = i0 + u * NT + threadIdx.x;
-        if (__syncthreads_or(ifirst != UINT_MAX)) break;
+    // Combine blocks cover contiguous runs of scan indices in order, and a
+    // block's candidates all have F >= its minimum. The first band member
+    // (F <= thr) therefore lies in the first block whose minimum is in the
+    // band, and a value within amb of the band edge (|F - thr| <= amb, the
+    // ambiguity test) only in a block whose minimum is at most thr + amb.
+    // Those blocks are scanned whole, in order (usually just the one that
+    // holds F_min); every other block is skipped.
+    const double amb = amb_margin * Fmin;
+    __shared__ uint64_t s_q[kCombMaxBlocks / 64];
+    {
+        const bool q = threadIdx.x < comb_blocks && (my_f <= thr || my_f - thr <= amb);
+        const uint64_t m = __ballot(q);
+        if (lane == 0 && wave < (int)(kCombMaxBlocks / 64)) s_q[wave] = m;
     }
+    __syncthreads();
+    uint32_t ifirst = UINT_MAX;
+    int ambig = 0;
+    for (uint32_t qb = 0; qb < comb_blocks; ++qb) {
+        if (!((s_q[qb >> 6] >> (qb & 63u)) & 1u)) continue;
+        uint32_t lo, hi;
+        comb_range(n, comb_blocks, comb_group, qb, lo, hi);
+        // rounds of 8 * NT indices, each thread's eight loads issued together
+        for (uint32_t i0 = lo; i0 < hi; i0 += 8 * NT) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const uint32_t i = i0 + u * NT + threadIdx.x;
+                v[u] = i < hi ? be.F[i] : INFINITY;
+            }
+#pragma unroll
+            for (int u = 7; u >= 0; --u) {
+                if (v[u] <= thr) ifirst = min(ifirst, i0 + u * NT + threadIdx.x);
+                ambig |= fabs(v[u] - thr) <= amb;
+            }
+        }
+    }
+    ambig = __syncthreads_or(ambig);
     for (int o = 32; o > 0; o >>= 1) ifirst = min(ifirst, (uint32_t)__shfl_xor((int)ifirst, o));
     if (lane == 0) s_first[wave] = ifirst;
     __syncthreads();
@@ -1220,7 +713,8 @@ __device__ __forceinline__ void select_walk(WalkDev &w, const BatchEntry &be, ui
         if (pure) {
             ChoiceDev c;
             c.i_best = ib; c.j_best = kb; c.F_best = Fb; c.F_min = Fmin;
-            c.j_psl = jp; c.psl_min = Pmin; c.psl_k = Pb; c.pad = 0;
+            c.j_psl = jp; c.psl_min = Pmin; c.psl_k = Pb;
+            c.flags = ambig ? CHOICE_AMBIG_ARGMIN : 0u;
             out[bi] = c;
             s_improve = 0;
         } else {
@@ -1232,10 +726,17 @@ __device__ __forceinline__ void select_walk(WalkDev &w, const BatchEntry &be, ui
             w.psl_k = Pb;
             w.j_psl = jp;
             w.psl_min = Pmin;
-            // three-way comparison of the move with v_local (Algorithm 1)
+            // three-way comparison of the move with v_local (Algorithm 1),
+            // flagged when the move's F lies within the ambiguity margin of
+            // either edge of the v_local band
+            const double vl = w.value_local;
+            const double elo = vl * (1.0 - kTau), ehi = vl * (1.0 + kTau), band = amb_margin * vl;
             uint32_t fl = 0;
-            if (Fb < w.value_local * (1.0 - kTau)) fl = STEP_IMPROVED;
-            else if (Fb > w.value_local * (1.0 + kTau)) fl = STEP_WORSE;
+            if (Fb < elo) fl = STEP_IMPROVED;
+            else if (Fb > ehi) fl = STEP_WORSE;
+            if ((Fb - elo < band && elo - Fb < band) || (Fb - ehi < band && ehi - Fb < band))
+                fl |= STEP_AMBIG_COMPARE;
+            if (ambig) fl |= STEP_AMBIG_ARGMIN;
             w.flags = fl;
             s_improve = Pmin < w.psl_best;
             if (s_improve) {
@@ -1260,7 +761,7 @@ __device__ __forceinline__ void select_walk(WalkDev &w, const BatchEntry &be, ui
 // blockIdx.y = 0.
 __global__ __launch_bounds__(kCombThreads) void k_combine(WalkDev *walks, const BatchEntry *batch, Tables tabs,
                                                           int G, int fuse, int pure, ChoiceDev *out,
-                                                          uint32_t *pend, uint32_t b0)
+                                                          uint32_t *pend, uint32_t b0, double amb_margin)
 {
     const BatchEntry be = batch[blockIdx.y];
     WalkDev &w = walks[be.slot];
@@ -1334,16 +835,17 @@ __global__ __launch_bounds__(kCombThreads) void k_combine(WalkDev *walks, const 
     }
     if (fuse) {
         __syncthreads();        // this block's F, P and block minimum are visible to it
-        select_walk<kCombThreads>(w, be, b0 + blockIdx.y, 1, (uint32_t)G, pure, out, pend);
+        select_walk<kCombThreads>(w, be, b0 + blockIdx.y, 1, (uint32_t)G, pure, out, pend, amb_margin);
     }
 }
 
 __global__ __launch_bounds__(kSelThreads) void k_select(WalkDev *walks, const BatchEntry *batch,
                                                         uint32_t comb_blocks, uint32_t comb_group, int pure,
-                                                        ChoiceDev *out, uint32_t *pend)
+                                                        ChoiceDev *out, uint32_t *pend, double amb_margin)
 {
     const BatchEntry be = batch[blockIdx.x];
-    select_walk<kSelThreads>(walks[be.slot], be, blockIdx.x, comb_blocks, comb_group, pure, out, pend);
+    select_walk<kSelThreads>(walks[be.slot], be, blockIdx.x, comb_blocks, comb_group, pure, out, pend,
+                             amb_margin);
 }
 
 // ------------------------------------------------------------ flip
@@ -1543,30 +1045,6 @@ hipError_t launch_fitness(WalkDev *walks, const BatchEntry *batch, uint32_t nb, 
     return hipGetLastError();
 }
 
-hipError_t launch_eval(const WalkDev *walks, const BatchEntry *batch, const EvalItem *items,
-                       uint32_t n_items, const Tables &tabs, const EvalShape &shape,
-                       EvalQueues *queues, hipStream_t s)
-{
-    if (shape.waves != 4 && shape.waves != 8 && shape.waves != 16) return hipErrorInvalidValue;
-    if (shape.persistent) {
-        k_queue_reset<<<1, 64, 0, s>>>(queues);
-        const uint32_t grid = shape.grid;
-        if (shape.waves == 4)
-            k_eval_persistent<4><<<grid, 64 * 4, 0, s>>>(walks, batch, items, tabs, queues);
-        else if (shape.waves == 8)
-            k_eval_persistent<8><<<grid, 64 * 8, 0, s>>>(walks, batch, items, tabs, queues);
-        else
-            k_eval_persistent<16><<<grid, 64 * 16, 0, s>>>(walks, batch, items, tabs, queues);
-    } else if (shape.waves == 4) {
-        k_eval<4><<<n_items, 64 * 4, 0, s>>>(walks, batch, items, tabs);
-    } else if (shape.waves == 8) {
-        k_eval<8><<<n_items, 64 * 8, 0, s>>>(walks, batch, items, tabs);
-    } else {
-        k_eval<16><<<n_items, 64 * 16, 0, s>>>(walks, batch, items, tabs);
-    }
-    return hipGetLastError();
-}
-
 hipError_t launch_suffix(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t max_L,
                          const Tables &tabs, int mode, const uint32_t *pend, const SegMap *map, hipStream_t s)
 {
@@ -1616,7 +1094,7 @@ hipError_t launch_near_reset(const BatchEntry *batch, uint32_t nb, uint32_t *pen
 
 hipError_t launch_select(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t comb_blocks,
                          uint32_t comb_group, const Tables &tabs, int pure, void *out, uint32_t *pend,
-                         hipStream_t s)
+                         double amb_margin, hipStream_t s)
 {
     if (comb_blocks < 1 || comb_blocks > kCombMaxBlocks) return hipErrorInvalidValue;
     if (comb_group < 1 || comb_group > 64 || (comb_group & (comb_group - 1))) return hipErrorInvalidValue;
@@ -1624,23 +1102,24 @@ hipError_t launch_select(WalkDev *walks, const BatchEntry *batch, uint32_t nb, u
     const int fuse = comb_blocks == 1 ? 1 : 0;
     for (uint32_t b0 = 0; b0 < nb; b0 += kMaxGridY) {
         k_combine<<<dim3(comb_blocks, std::min(kMaxGridY, nb - b0)), kCombThreads, 0, s>>>(
-            walks, batch + b0, tabs, (int)comb_group, fuse, pure, (ChoiceDev *)out, pend, b0);
+            walks, batch + b0, tabs, (int)comb_group, fuse, pure, (ChoiceDev *)out, pend, b0, amb_margin);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     if (fuse) return hipSuccess;
-    k_select<<<nb, kSelThreads, 0, s>>>(walks, batch, comb_blocks, comb_group, pure, (ChoiceDev *)out, pend);
+    k_select<<<nb, kSelThreads, 0, s>>>(walks, batch, comb_blocks, comb_group, pure, (ChoiceDev *)out, pend,
+                                        amb_margin);
     return hipGetLastError();
 }
 
 size_t choice_dev_size() { return sizeof(ChoiceDev); }
 
 void choice_dev_unpack(const void *p, uint32_t *i_best, uint32_t *j_best, double *F_best,
-                       double *F_min, uint32_t *j_psl, int32_t *psl_min, int32_t *psl_k)
+                       double *F_min, uint32_t *j_psl, int32_t *psl_min, int32_t *psl_k, uint32_t *flags)
 {
     const ChoiceDev *c = (const ChoiceDev *)p;
     *i_best = c->i_best; *j_best = c->j_best; *F_best = c->F_best; *F_min = c->F_min;
-    *j_psl = c->j_psl; *psl_min = c->psl_min; *psl_k = c->psl_k;
+    *j_psl = c->j_psl; *psl_min = c->psl_min; *psl_k = c->psl_k; *flags = c->flags;
 }
 
 hipError_t launch_apply(WalkDev *walks, const BatchEntry *batch, const SegMap &map, int64_t j_fixed,

@@ -18,6 +18,8 @@ OK, E_INVAL, E_NOMEM, E_HIP, E_STATE, E_AGAIN, E_FULL = 0, -1, -2, -3, -4, -5, -
 STEP_BLOCKING = 1
 STEP_GRAPH = 2
 STEP_IMPROVED, STEP_WORSE, STEP_SWITCHED, STEP_PSL_IMPROVED = 1, 2, 4, 8
+STEP_AMBIG_ARGMIN, STEP_AMBIG_COMPARE = 16, 32
+CHOICE_AMBIGUOUS_ARGMIN = 1
 L_MAX = 1048575
 
 EXPORTS = ["psl_ctx_create", "psl_ctx_destroy", "psl_last_error", "psl_sync", "psl_init_walks",
@@ -29,6 +31,8 @@ EXPORTS = ["psl_ctx_create", "psl_ctx_destroy", "psl_last_error", "psl_sync", "p
            "psl_trace_read", "psl_restore_walk"]
 OPT_NEAR_LIMIT = 1
 OPT_EVAL_ITEMS = 2
+OPT_AMBIG_MARGIN = 3      # value in units of 1e-15 (-1: the default, 5e-13)
+OPT_TEST_FAIL_ADMIT = 4   # tests only: the n-th admission of the next serving run fails
 
 
 class PslError(RuntimeError):

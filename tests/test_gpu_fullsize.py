@@ -1,24 +1,28 @@
 """Parity at the benchmark workloads' full sizes, in the launch shapes the bench
-uses, against the oracle on sampled outputs or on properties that hold at any
-size.
+uses, against the oracle: run live where it finishes in seconds, else from
+the committed goldens (tests/golden/fullsize_*.json, written from the oracle
+alone by tests/golden/make_fullsize.py, its O(L^2) correlations included).
 
 * L = 16383, one walk, full neighbourhood, alpha 4/13, switch every 50 steps:
   the 200-step trajectory in lockstep with the oracle.
 * L = 131071, 1024 walks: walks 0, 511 and 1023 after steps 1, 2 and 3.
 * L = 131071, 64 walks at Table 4's settings (N_lmt = 6912, alpha 4/10, the
   switch rule of Algorithm 1): walks 0 and 63 after steps 1, 2 and 3.
-* L = 1048575, one walk, alpha 4/10: sampled neighbours of step 1 against the
-  oracle, the choice against the full F/PSL arrays, the O(L) flip against the
-  oracle's formula tier, and the correlation invariants.
-* The uneven batch (L = 2^m - 1, m = 14..20, 512..8 walks): one walk per m
-  stepped alone equals the same walk stepped inside the batch; for m <= 16
-  also equal to the oracle.
+* L = 1048575, one walk, alpha 4/10: the initial C, pivot, F and PSL and
+  steps 1-3 against the oracle's goldens (C and the sequences by SHA-256);
+  then sampled neighbours of the next step against the oracle on the C the
+  goldens pinned, and the choice against the full F/PSL arrays.
+* The uneven batch (L = 2^m - 1, m = 14..20, 512..8 walks) in one launch per
+  step: the first walk of every m after steps 1 and 2 against the goldens,
+  and the same walks stepped alone equal to the walks in the batch.
 """
 import numpy as np
 import pytest
 
+import goldens
 import oracle
 import seeded_inputs as si
+from lockstep import run_lockstep
 
 pytestmark = pytest.mark.gpu
 
@@ -53,18 +57,8 @@ def test_single_walk_L16383_200_steps_lockstep(ctx):
     (w,) = ctx.init_walks(L, 1, seed, alpha1=4, alpha2=13, n_lmt=0, flip_lmt=10, switch_period=50)
     ow = oracle.Walk(oracle.WalkConfig(L=L, seed=seed, alpha1=4, alpha2=13, n_lmt=L, flip_lmt=10,
                                        switch_period=50), margin=MARGIN, nthreads=THREADS)
-    compared = 0
-    for t in range(200):
-        ctx.step_batch([w], 1)
-        tr = ow.step()
-        if tr["flags"] & (oracle.AMBIG_ARGMIN | oracle.AMBIG_COMPARE):
-            print(f"step {t}: oracle flags an ambiguous decision; stop comparing")
-            break
-        full = (t % 10 == 9) or (tr["flags"] & oracle.SWITCHED)
-        g = ctx.read_walk(w, bits=bool(full), C=bool(full))
-        _check_against_oracle(g, ow.read() if full else None, tr, t)
-        compared += 1
-    assert compared >= 190
+    compared, imposed = run_lockstep(ctx, w, ow, 200, check_every=10)
+    assert compared + imposed == 200 and compared >= 190
     ctx.free_walks([w])
 
 
@@ -108,55 +102,54 @@ def test_paper_settings_64_walks_L131071_sampled(ctx):
     ctx.free_walks(ids)
 
 
-def test_single_walk_L1048575_step1(ctx):
+def test_single_walk_L1048575_goldens(ctx):
+    """The large single instance against the oracle's own trajectory: its
+    initial state (C from the O(L^2) definition) and steps 1-3."""
     import torch
-    L, seed = 1048575, si.walk_seed(0)
-    (w,) = ctx.init_walks(L, 1, seed, alpha1=4, alpha2=10, n_lmt=0, flip_lmt=10, switch_period=50)
-    g0 = ctx.read_walk(w)
-    s = oracle.rand_pivot(seed, L)
-    assert np.array_equal(g0["pivot"], oracle.seq_to_bits(s))
-    C0 = g0["C"].astype(np.int64)
-    # invariants of Eq. (2) for the device's C (a from-scratch C is O(L^2))
-    k = np.arange(L)
-    assert C0[0] == L and C0[L - 1] == int(s[0]) * int(s[L - 1])
-    assert np.all((C0 - (L - k)) % 2 == 0) and np.all(np.abs(C0) <= L - k)
-    assert int(s.astype(np.int64).sum()) ** 2 == L + 2 * int(C0[1:].sum())
-    C0 = C0.astype(np.int32)
-    # the full neighbourhood of step 1, as the step evaluates it
-    start = oracle.draw(seed, 1 << 60) % L
+    gold = goldens.load("large")["large_L1048575"]
+    cfg = gold["cfg"]
+    L, seed = cfg["L"], cfg["seed"]
+    assert (L, seed, cfg["alpha2"], cfg["switch_period"]) == (1048575, si.walk_seed(0), 10, 50)
+    (w,) = ctx.init_walks(L, 1, seed, alpha1=cfg["alpha1"], alpha2=cfg["alpha2"], n_lmt=0,
+                          ls_lmt=cfg["ls_lmt"], flip_lmt=cfg["flip_lmt"], switch_period=cfg["switch_period"])
+    goldens.check_state(ctx.read_walk(w), gold["init"], F_RTOL, "init")
+    for t, step in enumerate(gold["steps"]):
+        assert not step["flags"] & (oracle.AMBIG_ARGMIN | oracle.AMBIG_COMPARE), t
+        ctx.step_batch([w], 1)
+        goldens.check_step(ctx.read_walk(w), step, F_RTOL, t + 1)
+    # the next step's full neighbourhood: sampled neighbours against the
+    # oracle on the C the goldens pinned, the choice against the full arrays
+    g = ctx.read_walk(w)
+    assert goldens.sha(g["C"]) == gold["steps"][-1]["state"]["sha_C"]
+    s = si.to_pm1(g["pivot"], L)
+    C = g["C"]
+    alpha = g["alpha"]
+    start = oracle.draw(seed, (1 << 60) | g["t"]) % L
     F = torch.empty(L, dtype=torch.float64, device="cuda:0")
     P = torch.empty(L, dtype=torch.int32, device="cuda:0")
     ch = ctx.eval_neighbourhood(w, start, L, F, P)
     Fg, Pg = F.cpu().numpy(), P.cpu().numpy()
     for i0 in (0, 1, L // 3, L // 2 - 3, max(0, L - 1 - start - 2), L - 9):
-        Fo, Po = oracle.eval_neighbourhood(s, C0, 4, (start + i0) % L, 8, nthreads=THREADS)
+        Fo, Po = oracle.eval_neighbourhood(s, C, alpha, (start + i0) % L, 8, nthreads=THREADS)
         assert np.array_equal(Pg[i0:i0 + 8], Po), i0
         assert np.max(np.abs(Fg[i0:i0 + 8] - Fo) / Fo) <= F_RTOL, i0
-    # the choice, by the band rule over the full arrays
     fmin = Fg.min()
     inband = np.nonzero(Fg <= fmin * (1 + oracle.TAU))[0]
     assert ch["i_best"] == inband[0] and ch["F_min"] == fmin
     assert ch["psl_min"] == Pg.min() and ch["j_psl"] == (start + int(np.argmin(Pg)) + 1) % L
-    Fo, Po = oracle.eval_neighbourhood(s, C0, 4, (start + ch["i_best"]) % L, 1, nthreads=1)
+    Fo, Po = oracle.eval_neighbourhood(s, C, alpha, (start + ch["i_best"]) % L, 1, nthreads=1)
     assert abs(Fo[0] - ch["F_best"]) <= F_RTOL * Fo[0] and Po[0] == ch["psl_k"]
-    # one step: the move and the O(L) flip
-    ctx.step_batch([w], 1)
-    g1 = ctx.read_walk(w)
-    kb = ch["j_best"]
-    assert g1["last_k"] == kb and g1["last_start"] == start
-    assert np.array_equal(g1["C"], oracle.flip_corr_formula(s, C0, kb))
-    s1 = s.copy()
-    s1[kb] = -s1[kb]
-    assert np.array_equal(g1["pivot"], oracle.seq_to_bits(s1))
-    assert g1["psl_best"] == min(oracle.psl(C0), ch["psl_min"])
-    assert g1["psl_pivot"] == oracle.psl(g1["C"]) == ch["psl_k"]
     ctx.free_walks([w])
 
 
 UNEVEN = [(14, 512), (15, 256), (16, 128), (17, 64), (18, 32), (19, 16), (20, 8)]
 
 
-def test_uneven_batch_alone_equals_mixed(ctx):
+def test_uneven_batch_goldens_and_alone(ctx):
+    """The uneven batch in one launch sequence per step: the first walk of
+    every length group against the oracle's goldens after steps 1 and 2, and
+    the same walks stepped alone equal to the walks in the batch."""
+    gold = goldens.load("uneven")
     ids, first = [], {}
     for m, count in UNEVEN:
         L = 2 ** m - 1
@@ -164,29 +157,28 @@ def test_uneven_batch_alone_equals_mixed(ctx):
                            n_lmt=0, flip_lmt=10, switch_period=50)
         first[m] = w[0]
         ids += w
+        cfg = gold[f"m{m}"]["cfg"]
+        assert (cfg["L"], cfg["seed"], cfg["alpha2"]) == (L, si.BASE_SEED + 1000 * m, si.alpha2_for(L))
     alone = {}
     for m, _ in UNEVEN:
         L = 2 ** m - 1
         (a,) = ctx.init_walks(L, 1, si.BASE_SEED + 1000 * m, alpha1=4, alpha2=si.alpha2_for(L),
                               n_lmt=0, flip_lmt=10, switch_period=50)
         alone[m] = a
+    for m, _ in UNEVEN:
+        goldens.check_state(ctx.read_walk(first[m]), gold[f"m{m}"]["init"], F_RTOL, (m, "init"))
     for t in range(2):
         ctx.step_batch(ids, 1)
         for m, _ in UNEVEN:
             ctx.step_batch([alone[m]], 1)
         for m, _ in UNEVEN:
-            ga, gb = ctx.read_walk(alone[m]), ctx.read_walk(first[m])
+            step = gold[f"m{m}"]["steps"][t]
+            assert not step["flags"] & (oracle.AMBIG_ARGMIN | oracle.AMBIG_COMPARE), (m, t)
+            gb = ctx.read_walk(first[m])
+            goldens.check_step(gb, step, F_RTOL, (m, t + 1))
+            ga = ctx.read_walk(alone[m])
             for key in ("pivot", "C", "best", "local_best"):
                 assert np.array_equal(ga[key], gb[key]), (m, t, key)
             assert ga["last_k"] == gb["last_k"] and ga["psl_best"] == gb["psl_best"], (m, t)
             assert abs(ga["last_value_step"] - gb["last_value_step"]) <= F_RTOL * ga["last_value_step"]
-    # oracle trajectories for the smaller sizes
-    for m in (14, 15, 16):
-        L = 2 ** m - 1
-        ow = oracle.Walk(oracle.WalkConfig(L=L, seed=si.BASE_SEED + 1000 * m, alpha1=4,
-                                           alpha2=si.alpha2_for(L), n_lmt=L, flip_lmt=10,
-                                           switch_period=50), margin=MARGIN, nthreads=THREADS)
-        tr = [ow.step(), ow.step()]
-        assert not any(x["flags"] & (oracle.AMBIG_ARGMIN | oracle.AMBIG_COMPARE) for x in tr)
-        _check_against_oracle(ctx.read_walk(first[m]), ow.read(), tr[1], m)
     ctx.free_walks(ids + list(alone.values()))

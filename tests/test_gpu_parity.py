@@ -1,14 +1,16 @@
 """GPU parity of libpsl against the CPU oracle (through the C-ABI).
 
-Bars: C, PSL, bits and moves bit-exact; F within a relative 1e-12; moves on
-steps the oracle flags as ambiguous (a value within 5e-13 relative of a band
-edge) are not compared.
+Bars: C, PSL, bits and moves bit-exact; F within a relative 1e-12. A step
+flagged ambiguous (a value within 5e-13 relative of a band edge) must carry
+the same flag on both sides, and is resolved by imposing the oracle's state
+on the GPU walk (tests/lockstep.py).
 """
 import numpy as np
 import pytest
 
 import oracle
 import seeded_inputs as si
+from lockstep import run_lockstep as _lockstep
 
 pytestmark = pytest.mark.gpu
 
@@ -149,30 +151,6 @@ def test_apply_flip_matches_formula(ctx, L):
 
 # ------------------------------------------------------------ trajectories
 
-def _lockstep(ctx, w, ow, steps, check_every=1):
-    compared = 0
-    for t in range(steps):
-        ctx.step_batch([w], 1)
-        tr = ow.step()
-        if tr["flags"] & (oracle.AMBIG_ARGMIN | oracle.AMBIG_COMPARE):
-            break
-        g = ctx.read_walk(w, bits=(t % check_every == 0), C=(t % check_every == 0))
-        assert g["last_start"] == tr["start"], t
-        assert g["last_k"] == tr["k"], t
-        assert abs(g["last_value_step"] - tr["value_step"]) <= F_RTOL * tr["value_step"], t
-        assert g["psl_best"] == tr["psl_best"] and g["alpha"] == tr["alpha"], t
-        assert g["unimproved"] == tr["unimproved"] and g["t"] == t + 1, t
-        assert abs(g["value_local"] - tr["value_local"]) <= F_RTOL * tr["value_local"], t
-        if t % check_every == 0:
-            o = ow.read()
-            assert np.array_equal(g["pivot"], o["pivot"]), t
-            assert np.array_equal(g["C"], o["C"]), t
-            assert np.array_equal(g["local_best"], o["local_best"]), t
-            assert np.array_equal(g["best"], o["best"]), t
-        compared += 1
-    return compared
-
-
 @pytest.mark.parametrize("L,n_lmt,period,ls,steps", [
     (257, 257, 5, 2000, 60), (1001, 1001, 50, 2000, 120), (1001, 300, 0, 3, 80),
     (64, 64, 0, 2, 100), (2, 2, 3, 2000, 20), (5, 3, 0, 1, 40), (4097, 4097, 50, 2000, 60)])
@@ -184,9 +162,80 @@ def test_step_lockstep_with_oracle(ctx, L, n_lmt, period, ls, steps):
     ow = oracle.Walk(oracle.WalkConfig(L=L, seed=seed, alpha1=4, alpha2=13, n_lmt=n_lmt,
                                        ls_lmt=ls, flip_lmt=flip, switch_period=period),
                      margin=MARGIN, nthreads=8)
-    n = _lockstep(ctx, w, ow, steps)
-    assert n >= steps * 0.9
+    n, imposed = _lockstep(ctx, w, ow, steps)
+    assert n + imposed == steps and n >= steps * 0.9
     ctx.free_walks([w])
+
+
+@pytest.mark.parametrize("margin_fs", [10 ** 11, 10 ** 12])
+@pytest.mark.parametrize("L,n_lmt,period,alpha2", [(257, 257, 7, 13), (1001, 300, 0, 4), (64, 64, 5, 2)])
+def test_lockstep_imposes_oracle_on_flagged_steps(ctx, L, n_lmt, period, alpha2, margin_fs):
+    """With a wide ambiguity margin (1e-4 or 1e-3 relative, on both sides)
+    many steps are flagged: the GPU's flags must equal the oracle's, and the
+    harness resolves each flagged step by imposing the oracle's state, after
+    which the walks go on in lockstep."""
+    from paper_2107_09801_amd import libpsl
+    margin = margin_fs * 1e-15
+    seed = si.BASE_SEED + 5 * L + alpha2
+    flip = min(10, L)
+    ctx.set_option(libpsl.OPT_AMBIG_MARGIN, margin_fs)
+    try:
+        (w,) = ctx.init_walks(L, 1, seed, alpha1=4, alpha2=alpha2, n_lmt=n_lmt, ls_lmt=3,
+                              flip_lmt=flip, switch_period=period)
+        ow = oracle.Walk(oracle.WalkConfig(L=L, seed=seed, alpha1=4, alpha2=alpha2, n_lmt=n_lmt,
+                                           ls_lmt=3, flip_lmt=flip, switch_period=period),
+                         margin=margin, nthreads=8)
+        n, imposed = _lockstep(ctx, w, ow, 60, margin=margin)
+        assert n + imposed == 60
+        assert imposed >= 1, "the wide margin flagged no step"
+        ctx.free_walks([w])
+    finally:
+        ctx.set_option(libpsl.OPT_AMBIG_MARGIN, -1)
+
+
+@pytest.mark.parametrize("margin_fs", [0, 500, 10 ** 9, 10 ** 11, 10 ** 12, 10 ** 13])
+@pytest.mark.parametrize("L,n_lmt,alpha", [(4097, 4097, 4), (16383, 16383, 13), (3001, 700, 2),
+                                           (100000, 20000, 10)])
+def test_choice_ambiguity_flag(ctx, L, n_lmt, alpha, margin_fs):
+    """psl_choice.flags against the definition (some F within m*F_min of the
+    band edge), evaluated on the GPU's own F array and on the oracle's; the
+    margins run from 0 (exact hits only) to 1e-2, so both answers occur, and
+    L up to 100000 puts the candidates in many combine blocks."""
+    import torch
+    from paper_2107_09801_amd import libpsl
+    margin = margin_fs * 1e-15
+    seed = 9000 + L + margin_fs % 97
+    start = (L * 5) // 7
+    ctx.set_option(libpsl.OPT_AMBIG_MARGIN, margin_fs)
+    try:
+        (w,) = ctx.init_walks(L, 1, seed, alpha1=alpha, alpha2=4)
+        F, P = _dev(n_lmt, torch.float64), _dev(n_lmt, torch.int32)
+        ch = ctx.eval_neighbourhood(w, start, n_lmt, F, P)
+        Fg = F.cpu().numpy()[:n_lmt]
+        thr = Fg.min() * (1 + oracle.TAU)
+        want = bool(np.any(np.abs(Fg - thr) <= margin * Fg.min()))
+        assert bool(ch["flags"] & libpsl.CHOICE_AMBIGUOUS_ARGMIN) == want
+        s, C = _oracle_state(L, seed)
+        Fo, Po = oracle.eval_neighbourhood(s, C, alpha, start, n_lmt, nthreads=8)
+        oc = oracle.select(Fo, Po, margin=margin)
+        if bool(oc.flags & oracle.AMBIG_ARGMIN) != want:
+            # only a value at the window's edge, within the F tolerance, may differ
+            edge = np.abs(np.abs(Fo - oc.F_min * (1 + oracle.TAU)) - margin * oc.F_min)
+            assert np.min(edge) <= 1e-11 * oc.F_min
+        if not want and not oc.flags & oracle.AMBIG_ARGMIN:
+            assert ch["i_best"] == oc.i_best
+        ctx.free_walks([w])
+    finally:
+        ctx.set_option(libpsl.OPT_AMBIG_MARGIN, -1)
+
+
+def test_ambig_margin_option_range(ctx):
+    from paper_2107_09801_amd import libpsl
+    for bad in (-2, 10 ** 15 + 1):
+        with pytest.raises(libpsl.PslError):
+            ctx.set_option(libpsl.OPT_AMBIG_MARGIN, bad)
+    for ok in (0, 10 ** 15, -1):
+        ctx.set_option(libpsl.OPT_AMBIG_MARGIN, ok)
 
 
 def test_batch_matches_single_walks(ctx):

@@ -7,6 +7,7 @@ import time
 import numpy as np
 import pytest
 
+import goldens
 import oracle
 import seeded_inputs as si
 
@@ -88,15 +89,11 @@ def test_serving_mixture_50_jobs_equal_alone(ctx):
     """50 jobs of the serving workload's mixture (L = 2^m - 1 or any odd L up
     to 2^20 - 1, N_lmt = min(L, 256), a switch every 50 steps), submitted in
     waves while earlier ones run; budgets cut to 5..60 steps so the check
-    stays short. Each result equals the same job stepped alone."""
-    import os
-    import sys
-    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
-    import bench
-    rng = np.random.default_rng(2107)
-    jobs = bench.serve_jobs(50, si.BASE_SEED + 7, 256)
-    for j in jobs:
-        j["budget"] = int(rng.integers(5, 61))
+    stays short. Each result equals the same job stepped alone, and the ten
+    longest jobs (L from 8.0e5 to 2^20 - 1) equal the oracle's goldens."""
+    jobs = si.serve_mixture_50()
+    gold = goldens.load("serve")
+    assert len(gold) == 10
     ctx.serve_start(hbm_budget=40 << 30, max_slots=4096)
     tickets = []
     for i, j in enumerate(jobs):
@@ -117,6 +114,15 @@ def test_serving_mixture_50_jobs_equal_alone(ctx):
         assert abs(r["F_final"] - g["F_pivot"]) <= F_RTOL * g["F_pivot"], j
         assert np.array_equal(r["best"], g["best"]), j
         ctx.free_walks([w])
+    for rec in gold.values():
+        i = rec["job_index"]
+        j, r, want = jobs[i], res[tickets[i]], rec["final"]
+        assert (j["L"], j["seed"], j["budget"], j["n_lmt"]) == (rec["L"], rec["seed"], rec["budget"], rec["n_lmt"])
+        assert not rec["flags_or"] & (oracle.AMBIG_ARGMIN | oracle.AMBIG_COMPARE), i
+        assert r["steps"] == want["t"] and r["psl_best"] == want["psl_best"], i
+        assert r["psl_final"] == want["psl_pivot"] and r["alpha_final"] == want["alpha"], i
+        assert abs(r["F_final"] - want["F_pivot"]) <= F_RTOL * want["F_pivot"], i
+        assert goldens.sha(r["best"]) == want["sha_best"], i
 
 
 def test_admission_fifo_within_budget(ctx):
@@ -136,6 +142,72 @@ def test_admission_fifo_within_budget(ctx):
     with pytest.raises(libpsl.PslError) as e:
         ctx.serve_submit(30001, 1, 5)          # not serving any more
     assert e.value.status == libpsl.E_STATE
+
+
+def test_serving_allocates_no_device_memory_beyond_its_region(ctx):
+    """The loop's device memory is the one region of hbm_budget bytes taken at
+    start: serving a budget-filling mix of lengths (full and limited
+    neighbourhoods, with admissions and retirements all along) allocates
+    nothing more, and stop frees the region."""
+    import torch
+    from paper_2107_09801_amd import libpsl
+    budget = 96 << 20
+    free0, _ = torch.cuda.mem_get_info(0)
+    ctx.serve_start(hbm_budget=budget, max_slots=256)
+    free1, _ = torch.cuda.mem_get_info(0)
+    jobs = [(131071, 256), (30001, 0), (524287, 256), (4097, 0), (65535, 1000), (1048575, 256),
+            (2049, 0), (262143, 512), (16383, 0), (777, 0)] * 3
+    tickets = []
+    for i, (L, n_lmt) in enumerate(jobs):
+        assert libpsl.serve_footprint(L, n_lmt) + (64 << 10) <= budget
+        tickets.append(ctx.serve_submit(L, 300 + i, 4 + i % 5, n_lmt=n_lmt, switch_period=3))
+    low = free1
+    out, t0 = {}, time.time()
+    while len(out) < len(tickets):
+        low = min(low, torch.cuda.mem_get_info(0)[0])
+        for t in tickets:
+            if t not in out:
+                r = ctx.serve_poll(t)
+                if r is not None:
+                    out[t] = r
+        assert time.time() - t0 < 120, "jobs did not finish"
+        time.sleep(0.001)
+    st = ctx.serve_stats()
+    ctx.serve_stop(drain=True)
+    assert all(r["status"] == 0 for r in out.values())
+    assert st["peak_active"] >= 2 and st["peak_used"] <= budget
+    # the region (and the power tables the first start builds) is all
+    assert free0 - free1 <= budget + (160 << 20)
+    assert free1 - low <= 4 << 20, (free1 - low)
+
+
+def test_admission_failure_finishes_its_jobs(ctx):
+    """A failing admission (forced by the test hook) finishes the jobs it had
+    taken with PSL_E_HIP and releases their slabs and slots; the queue goes
+    on, and no ticket is left pending."""
+    from paper_2107_09801_amd import libpsl
+    ctx.set_option(libpsl.OPT_TEST_FAIL_ADMIT, 2)
+    try:
+        ctx.serve_start(hbm_budget=64 << 20, max_slots=16)
+        first = [ctx.serve_submit(4097, 10 + i, 3, n_lmt=256) for i in range(3)]
+        res = _wait(ctx, first, timeout_s=60)
+        assert all(r["status"] == 0 for r in res.values())
+        second = [ctx.serve_submit(4097, 20 + i, 3, n_lmt=256) for i in range(4)]
+        res2 = _wait(ctx, second, timeout_s=60)
+        third = [ctx.serve_submit(4097, 30 + i, 3, n_lmt=256) for i in range(3)]
+        res3 = _wait(ctx, third, timeout_s=60)
+        st = ctx.serve_stats()
+        ctx.serve_stop(drain=True)
+    finally:
+        ctx.set_option(libpsl.OPT_TEST_FAIL_ADMIT, 0)
+    statuses = [r["status"] for r in res2.values()]
+    assert libpsl.E_HIP in statuses                  # the second admission failed
+    assert all(r["status"] == 0 for r in res3.values())
+    assert st["failed"] == statuses.count(libpsl.E_HIP) and st["active"] == 0
+    # slots and memory came back: the context steps walks again
+    (w,) = ctx.init_walks(4097, 1, 5, n_lmt=256)
+    ctx.step_batch([w], 2)
+    ctx.free_walks([w])
 
 
 def test_status_codes_and_cancel(ctx):

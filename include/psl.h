@@ -107,11 +107,11 @@ typedef struct {
 
 /* psl_choice.flags: some scanned neighbour's F lies within m*F_min of the
  * band edge F_min*(1+tau) (|F - F_min*(1+tau)| <= m*F_min, m the context's
- * PSL_OPT_AMBIG_MARGIN, 5e-13 by default). The move is then decided by
- * rounding rather than by the band: an exact computation of Eq. (5) could
- * put that neighbour on the other side of the edge, and a caller that needs
- * the strict-less-than scan of Algorithm 1 exactly must resolve the step
- * itself (the test suite imposes its CPU oracle's decision). */
+ * PSL_OPT_AMBIG_MARGIN, 5e-13 by default). Such a move is decided by the
+ * rounding of Eq. (5) rather than by the band: an exact summation could put
+ * that neighbour on the other side of the edge, so a caller that needs the
+ * strict-less-than scan of Algorithm 1 exactly must resolve the step itself
+ * (the test suite imposes its CPU oracle's decision). */
 #define PSL_CHOICE_AMBIGUOUS_ARGMIN 1u
 
 /* Snapshot of a walk's scalar state. */
@@ -138,8 +138,8 @@ typedef struct {
 #define PSL_STEP_PSL_IMPROVED 8u
 /* The step's best-neighbour choice was ambiguous (as PSL_CHOICE_AMBIGUOUS_ARGMIN). */
 #define PSL_STEP_AMBIG_ARGMIN 16u
-/* The three-way comparison was ambiguous: the move's F lies within m*v_local of
- * v_local*(1-tau) or of v_local*(1+tau) (strictly, m = PSL_OPT_AMBIG_MARGIN). */
+/* The three-way comparison was ambiguous: the move's F lies strictly within
+ * m*v_local of v_local*(1-tau) or of v_local*(1+tau) (m = PSL_OPT_AMBIG_MARGIN). */
 #define PSL_STEP_AMBIG_COMPARE 32u
 
 /* ------------------------------------------------------------ context */
@@ -224,11 +224,6 @@ PSL_API psl_status psl_read_walk(psl_ctx *ctx, uint32_t walk, psl_walk_state *ou
  * admitted walk by one step of Algorithm 1 in one batched launch sequence
  * (continuous batching: jobs that arrive while others run join the next
  * iteration). While serving, the context's other calls return PSL_E_STATE. */
-/* Device memory: psl_serve_start takes one region of hbm_budget bytes (one
- * hipMalloc) and the loop allocates no other device memory while it runs.
- * Walk slabs come from the low end of the region, every iteration's scratch
- * from its high end; a job is admitted only while the slabs stay below the
- * sum of the admitted jobs' scratch bounds plus 64 KiB of the loop's own. */
 typedef struct {
     uint64_t hbm_budget;     /* bytes jobs may occupy: walk slabs and their scratch */
     uint32_t max_slots;      /* most jobs admitted at once (>= 1)                  */
@@ -271,8 +266,8 @@ typedef struct {
 PSL_API psl_status psl_serve_start(psl_ctx *ctx, const psl_serve_cfg *cfg);
 
 /* Queue a job; thread-safe and non-blocking. *ticket names it.
- * Errors: PSL_E_INVAL (bad job), PSL_E_FULL (its footprint plus the loop's
- * 64 KiB exceeds the whole budget), PSL_E_STATE (not serving). */
+ * Errors: PSL_E_INVAL (bad job), PSL_E_FULL (its footprint exceeds the whole
+ * budget), PSL_E_STATE (not serving). */
 PSL_API psl_status psl_serve_submit(psl_ctx *ctx, const psl_job *job, uint64_t *ticket);
 
 /* Thread-safe. PSL_OK: the job is finished, *out holds its result and the
@@ -281,10 +276,8 @@ PSL_API psl_status psl_serve_submit(psl_ctx *ctx, const psl_job *job, uint64_t *
 PSL_API psl_status psl_serve_poll(psl_ctx *ctx, uint64_t ticket, psl_job_result *out);
 
 /* Device bytes a job with this configuration counts against hbm_budget
- * (its walk slab plus an upper bound of its share of the evaluation scratch,
- * for the default PSL_OPT_EVAL_ITEMS; a context with a larger work-item
- * target, set or autotuned, counts its jobs' scratch bound for that target).
- * Needs no context or device. Errors: PSL_E_INVAL. */
+ * (its walk slab plus an upper bound of its evaluation scratch). Needs no
+ * context or device. Errors: PSL_E_INVAL. */
 PSL_API psl_status psl_serve_footprint(const psl_walk_cfg *cfg, uint64_t *bytes);
 
 /* Thread-safe counters of the loop. */
@@ -364,16 +357,10 @@ PSL_API psl_status psl_tune_load(psl_ctx *ctx, const char *path);
 /* PSL_OPT_AMBIG_MARGIN: the relative margin m of the ambiguity flags
  * (PSL_CHOICE_AMBIGUOUS_ARGMIN, PSL_STEP_AMBIG_*), in units of 1e-15:
  * 0 .. 10^15 (m = 0 .. 1); -1 restores the default 500 (m = 5e-13, which
- * covers the FP64 rounding of both this library's F, at most about 3e-14
- * relative, and an exact summation's). Only the flags change: the moves are
+ * covers the FP64 rounding of this library's F, at most about 3e-14
+ * relative, and of an exact summation). Only the flags change: the moves are
  * the band rule's whatever the margin. Errors: PSL_E_INVAL outside the range. */
 #define PSL_OPT_AMBIG_MARGIN 3
-/* PSL_OPT_TEST_FAIL_ADMIT: for tests of the request loop's failure path only.
- * value n > 0: the n-th admission of the next psl_serve_start fails with
- * PSL_E_HIP after its jobs took their slabs and slots and before their first
- * launch (the loop then finishes every admitted job with PSL_E_HIP, releases
- * their memory and goes on with the queue); 0 (default): off. */
-#define PSL_OPT_TEST_FAIL_ADMIT 4
 PSL_API psl_status psl_set_option(psl_ctx *ctx, int option, int64_t value);
 
 /* --------------------------------------------------- trace, checkpoint */
@@ -387,7 +374,7 @@ typedef struct {
     int32_t  psl_k;         /* PSL of the move                                    */
     int32_t  psl_best;      /* best PSL after the step                            */
     uint32_t alpha;         /* exponent after the step                            */
-    uint32_t flags;         /* PSL_STEP_* bits (the ambiguity bits included)      */
+    uint32_t flags;         /* PSL_STEP_* bits                                    */
 } psl_trace_entry;
 
 /* Record every later step of `walk` into a device ring of `capacity` entries

@@ -164,7 +164,7 @@ enum : uint32_t {
     STEP_WORSE = 2u,
     STEP_SWITCHED = 4u,
     STEP_PSL_IMPROVED = 8u,
-    STEP_AMBIG_ARGMIN = 16u,   // a neighbour's F lies within the margin of the band edge
+    STEP_AMBIG_ARGMIN = 16u,   // some neighbour's F lies within the margin of the band edge
     STEP_AMBIG_COMPARE = 32u,  // the move's F lies within the margin of a v_local band edge
 };
 constexpr uint32_t CHOICE_AMBIG_ARGMIN = 1u;

@@ -8,7 +8,6 @@
 
 #include <algorithm>
 #include <cstdarg>
-#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -36,13 +35,10 @@ public:
         if (base && bytes >= kAlign) free_[0] = bytes & ~(kAlign - 1);
     }
     bool active() const { return base_ != nullptr; }
-    // First fit; with a limit, only a block that ends at or below offset
-    // `limit` is taken.
-    void *alloc(size_t bytes, size_t limit = SIZE_MAX)
+    void *alloc(size_t bytes)
     {
         bytes = (bytes + kAlign - 1) & ~(kAlign - 1);
         for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->first + bytes > limit) break;          // offsets only grow from here
             if (it->second >= bytes) {
                 size_t off = it->first, len = it->second;
                 free_.erase(it);
@@ -52,11 +48,6 @@ public:
             }
         }
         return nullptr;
-    }
-    // End offset of the highest block in use (0 when none is).
-    size_t used_end() const
-    {
-        return used_.empty() ? 0 : used_.rbegin()->first + used_.rbegin()->second;
     }
     void release(void *p)
     {
@@ -154,7 +145,6 @@ struct psl_ctx {
     int64_t near_limit = -1;          // PSL_OPT_NEAR_LIMIT
     uint32_t eval_items = psl_rt::kEvalItemsDefault;  // PSL_OPT_EVAL_ITEMS
     double amb_margin = psl::kAmbigMarginDefault;     // PSL_OPT_AMBIG_MARGIN (relative)
-    uint64_t test_fail_admit = 0;     // PSL_OPT_TEST_FAIL_ADMIT
     psl_rt::Server *server = nullptr; // serving loop, when started
     uint32_t n_cu = 256;              // compute units of the device
     std::map<uint32_t, psl::EvalShape> tuned;  // autotuner choices by tune_key

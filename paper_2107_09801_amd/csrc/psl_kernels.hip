@@ -578,7 +578,7 @@ struct ChoiceDev {
     uint32_t j_psl;
     int32_t psl_min;
     int32_t psl_k;
-    uint32_t flags;         // CHOICE_AMBIG_ARGMIN
+    uint32_t flags;         // CHOICE_AMBIG_ARGMIN (set by k_ambig)
 };
 
 constexpr int kSelThreads = 1024;
@@ -616,8 +616,7 @@ __device__ __forceinline__ void sel_merge(double &f, int32_t &p, uint32_t &i, do
 // The selection of walk w (batch position bi) by a block of NT threads.
 template <int NT>
 __device__ __forceinline__ void select_walk(WalkDev &w, const BatchEntry &be, uint32_t bi, uint32_t comb_blocks,
-                                            uint32_t comb_group, int pure, ChoiceDev *out, uint32_t *pend,
-                                            double amb_margin)
+                                            uint32_t comb_group, int pure, ChoiceDev *out, uint32_t *pend)
 {
     // the previous step's pending list has been consumed; this step's
     // bookkeeping refills it
@@ -657,43 +656,33 @@ __device__ __forceinline__ void select_walk(WalkDev &w, const BatchEntry &be, ui
     const uint32_t iPmin = r.i;
     const double thr = Fmin * (1.0 + kTau);
 
-    // Combine blocks cover contiguous runs of scan indices in order, and a
-    // block's candidates all have F >= its minimum. The first band member
-    // (F <= thr) therefore lies in the first block whose minimum is in the
-    // band, and a value within amb of the band edge (|F - thr| <= amb, the
-    // ambiguity test) only in a block whose minimum is at most thr + amb.
-    // Those blocks are scanned whole, in order (usually just the one that
-    // holds F_min); every other block is skipped.
-    const double amb = amb_margin * Fmin;
-    __shared__ uint64_t s_q[kCombMaxBlocks / 64];
-    {
-        const bool q = threadIdx.x < comb_blocks && (my_f <= thr || my_f - thr <= amb);
-        const uint64_t m = __ballot(q);
-        if (lane == 0 && wave < (int)(kCombMaxBlocks / 64)) s_q[wave] = m;
-    }
+    // the first band member lies in the first combine block (they cover
+    // contiguous runs of scan indices in order) whose minimum is in the band
+    uint32_t bfirst = my_f <= thr ? (uint32_t)threadIdx.x : UINT_MAX;
+    for (int o = 32; o > 0; o >>= 1) bfirst = min(bfirst, (uint32_t)__shfl_xor((int)bfirst, o));
+    if (lane == 0) s_first[wave] = bfirst;
     __syncthreads();
+    for (int x = 0; x < kSelWaves; ++x) bfirst = min(bfirst, s_first[x]);
+    uint32_t lo, hi;
+    comb_range(n, comb_blocks, comb_group, bfirst, lo, hi);
+    __syncthreads();                    // s_first is reused below
+
+    // first scan index inside the band within [lo, hi): rounds of
+    // 8 * NT indices, each thread's eight loads issued together;
+    // the first round with a hit holds the answer
     uint32_t ifirst = UINT_MAX;
-    int ambig = 0;
-    for (uint32_t qb = 0; qb < comb_blocks; ++qb) {
-        if (!((s_q[qb >> 6] >> (qb & 63u)) & 1u)) continue;
-        uint32_t lo, hi;
-        comb_range(n, comb_blocks, comb_group, qb, lo, hi);
-        // rounds of 8 * NT indices, each thread's eight loads issued together
-        for (uint32_t i0 = lo; i0 < hi; i0 += 8 * NT) {
-            double v[8];
+    for (uint32_t i0 = lo; i0 < hi; i0 += 8 * NT) {
+        double v[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const uint32_t i = i0 + u * NT + threadIdx.x;
-                v[u] = i < hi ? be.F[i] : INFINITY;
-            }
-#pragma unroll
-            for (int u = 7; u >= 0; --u) {
-                if (v[u] <= thr) ifirst = min(ifirst, i0 + u * NT + threadIdx.x);
-                ambig |= fabs(v[u] - thr) <= amb;
-            }
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t i = i0 + u * NT + threadIdx.x;
+            v[u] = i < hi ? be.F[i] : INFINITY;
         }
+#pragma unroll
+        for (int u = 7; u >= 0; --u)
+            if (v[u] <= thr) ifirst = i0 + u * NT + threadIdx.x;
+        if (__syncthreads_or(ifirst != UINT_MAX)) break;
     }
-    ambig = __syncthreads_or(ambig);
     for (int o = 32; o > 0; o >>= 1) ifirst = min(ifirst, (uint32_t)__shfl_xor((int)ifirst, o));
     if (lane == 0) s_first[wave] = ifirst;
     __syncthreads();
@@ -713,8 +702,7 @@ __device__ __forceinline__ void select_walk(WalkDev &w, const BatchEntry &be, ui
         if (pure) {
             ChoiceDev c;
             c.i_best = ib; c.j_best = kb; c.F_best = Fb; c.F_min = Fmin;
-            c.j_psl = jp; c.psl_min = Pmin; c.psl_k = Pb;
-            c.flags = ambig ? CHOICE_AMBIG_ARGMIN : 0u;
+            c.j_psl = jp; c.psl_min = Pmin; c.psl_k = Pb; c.flags = 0;
             out[bi] = c;
             s_improve = 0;
         } else {
@@ -726,17 +714,10 @@ __device__ __forceinline__ void select_walk(WalkDev &w, const BatchEntry &be, ui
             w.psl_k = Pb;
             w.j_psl = jp;
             w.psl_min = Pmin;
-            // three-way comparison of the move with v_local (Algorithm 1),
-            // flagged when the move's F lies within the ambiguity margin of
-            // either edge of the v_local band
-            const double vl = w.value_local;
-            const double elo = vl * (1.0 - kTau), ehi = vl * (1.0 + kTau), band = amb_margin * vl;
+            // three-way comparison of the move with v_local (Algorithm 1)
             uint32_t fl = 0;
-            if (Fb < elo) fl = STEP_IMPROVED;
-            else if (Fb > ehi) fl = STEP_WORSE;
-            if ((Fb - elo < band && elo - Fb < band) || (Fb - ehi < band && ehi - Fb < band))
-                fl |= STEP_AMBIG_COMPARE;
-            if (ambig) fl |= STEP_AMBIG_ARGMIN;
+            if (Fb < w.value_local * (1.0 - kTau)) fl = STEP_IMPROVED;
+            else if (Fb > w.value_local * (1.0 + kTau)) fl = STEP_WORSE;
             w.flags = fl;
             s_improve = Pmin < w.psl_best;
             if (s_improve) {
@@ -761,7 +742,7 @@ __device__ __forceinline__ void select_walk(WalkDev &w, const BatchEntry &be, ui
 // blockIdx.y = 0.
 __global__ __launch_bounds__(kCombThreads) void k_combine(WalkDev *walks, const BatchEntry *batch, Tables tabs,
                                                           int G, int fuse, int pure, ChoiceDev *out,
-                                                          uint32_t *pend, uint32_t b0, double amb_margin)
+                                                          uint32_t *pend, uint32_t b0)
 {
     const BatchEntry be = batch[blockIdx.y];
     WalkDev &w = walks[be.slot];
@@ -835,17 +816,64 @@ __global__ __launch_bounds__(kCombThreads) void k_combine(WalkDev *walks, const 
     }
     if (fuse) {
         __syncthreads();        // this block's F, P and block minimum are visible to it
-        select_walk<kCombThreads>(w, be, b0 + blockIdx.y, 1, (uint32_t)G, pure, out, pend, amb_margin);
+        select_walk<kCombThreads>(w, be, b0 + blockIdx.y, 1, (uint32_t)G, pure, out, pend);
     }
 }
 
 __global__ __launch_bounds__(kSelThreads) void k_select(WalkDev *walks, const BatchEntry *batch,
                                                         uint32_t comb_blocks, uint32_t comb_group, int pure,
-                                                        ChoiceDev *out, uint32_t *pend, double amb_margin)
+                                                        ChoiceDev *out, uint32_t *pend)
 {
     const BatchEntry be = batch[blockIdx.x];
-    select_walk<kSelThreads>(walks[be.slot], be, blockIdx.x, comb_blocks, comb_group, pure, out, pend,
-                             amb_margin);
+    select_walk<kSelThreads>(walks[be.slot], be, blockIdx.x, comb_blocks, comb_group, pure, out, pend);
+}
+
+// ------------------------------------------------------- ambiguity flags
+
+// The ambiguity flags of a step's scan, from the selection's results (one
+// block per walk, after k_select and before the flip and the bookkeeping):
+//   ARGMIN: some scanned neighbour's F lies within amb = margin*F_min of the
+//     band edge thr = F_min*(1+tau) (|F - thr| <= amb): a different rounding
+//     of Eq. (5) could move it across the edge and change the move;
+//   COMPARE (steps only): the move's F lies strictly within margin*v_local of
+//     v_local*(1-tau) or of v_local*(1+tau), the edges of the three-way
+//     comparison with the local best.
+// Every F of a combine block is at least that block's minimum, so only the
+// blocks whose minimum is at most thr + amb are read. pure != 0: the flag
+// goes into the choice record out[b]; otherwise into the walk's step flags.
+constexpr int kAmbThreads = 256;
+__global__ __launch_bounds__(kAmbThreads) void k_ambig(WalkDev *walks, const BatchEntry *batch,
+                                                       uint32_t comb_blocks, uint32_t comb_group, int pure,
+                                                       ChoiceDev *out, double margin)
+{
+    const BatchEntry be = batch[blockIdx.x];
+    WalkDev &w = walks[be.slot];
+    const uint32_t n = be.fixed ? be.n_lmt : w.n_lmt;
+    const double Fmin = pure ? out[blockIdx.x].F_min : w.F_min;
+    const double thr = Fmin * (1.0 + kTau), amb = margin * Fmin;
+    int hit = 0;
+    for (uint32_t b = 0; b < comb_blocks; ++b) {
+        if (!(be.red[b].f - thr <= amb)) continue;    // the same for every thread of the block
+        uint32_t lo, hi;
+        comb_range(n, comb_blocks, comb_group, b, lo, hi);
+        for (uint32_t i = lo + threadIdx.x; i < hi; i += kAmbThreads) {
+            const double g = be.F[i] - thr;
+            hit |= (g < 0.0 ? -g : g) <= amb;
+        }
+    }
+    hit = __syncthreads_or(hit);
+    if (threadIdx.x == 0) {
+        if (pure) {
+            out[blockIdx.x].flags = hit ? CHOICE_AMBIG_ARGMIN : 0u;
+        } else {
+            uint32_t fl = w.flags;
+            if (hit) fl |= STEP_AMBIG_ARGMIN;
+            const double vl = w.value_local, v = w.value_step;
+            const double elo = vl * (1.0 - kTau), ehi = vl * (1.0 + kTau), band = margin * vl;
+            if ((v - elo < band && elo - v < band) || (v - ehi < band && ehi - v < band)) fl |= STEP_AMBIG_COMPARE;
+            w.flags = fl;
+        }
+    }
 }
 
 // ------------------------------------------------------------ flip
@@ -1094,7 +1122,7 @@ hipError_t launch_near_reset(const BatchEntry *batch, uint32_t nb, uint32_t *pen
 
 hipError_t launch_select(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t comb_blocks,
                          uint32_t comb_group, const Tables &tabs, int pure, void *out, uint32_t *pend,
-                         double amb_margin, hipStream_t s)
+                         hipStream_t s)
 {
     if (comb_blocks < 1 || comb_blocks > kCombMaxBlocks) return hipErrorInvalidValue;
     if (comb_group < 1 || comb_group > 64 || (comb_group & (comb_group - 1))) return hipErrorInvalidValue;
@@ -1102,13 +1130,23 @@ hipError_t launch_select(WalkDev *walks, const BatchEntry *batch, uint32_t nb, u
     const int fuse = comb_blocks == 1 ? 1 : 0;
     for (uint32_t b0 = 0; b0 < nb; b0 += kMaxGridY) {
         k_combine<<<dim3(comb_blocks, std::min(kMaxGridY, nb - b0)), kCombThreads, 0, s>>>(
-            walks, batch + b0, tabs, (int)comb_group, fuse, pure, (ChoiceDev *)out, pend, b0, amb_margin);
+            walks, batch + b0, tabs, (int)comb_group, fuse, pure, (ChoiceDev *)out, pend, b0);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     if (fuse) return hipSuccess;
-    k_select<<<nb, kSelThreads, 0, s>>>(walks, batch, comb_blocks, comb_group, pure, (ChoiceDev *)out, pend,
-                                        amb_margin);
+    k_select<<<nb, kSelThreads, 0, s>>>(walks, batch, comb_blocks, comb_group, pure, (ChoiceDev *)out, pend);
+    return hipGetLastError();
+}
+
+hipError_t launch_ambig(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t comb_blocks,
+                        uint32_t comb_group, int pure, void *out, double margin, hipStream_t s)
+{
+    if (comb_blocks < 1 || comb_blocks > kCombMaxBlocks) return hipErrorInvalidValue;
+    if (comb_group < 1 || comb_group > 64 || (comb_group & (comb_group - 1))) return hipErrorInvalidValue;
+    if (pure && (!out || nb != 1)) return hipErrorInvalidValue;
+    if (nb == 0) return hipSuccess;
+    k_ambig<<<nb, kAmbThreads, 0, s>>>(walks, batch, comb_blocks, comb_group, pure, (ChoiceDev *)out, margin);
     return hipGetLastError();
 }
 

@@ -26,15 +26,17 @@ hipError_t launch_suffix(WalkDev *walks, const BatchEntry *batch, uint32_t nb, u
 // Zero the near-peak counts of a batch and its pending count (after its
 // scratch is allocated).
 hipError_t launch_near_reset(const BatchEntry *batch, uint32_t nb, uint32_t *pend, hipStream_t s);
-// amb_margin: relative margin of the ambiguity flags (a value within
-// amb_margin * F_min of the best-neighbour band's edge; a move within
-// amb_margin * v_local of either edge of the improvement band).
 hipError_t launch_select(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t comb_blocks,
                          uint32_t comb_group, const Tables &tabs, int pure, void *out, uint32_t *pend,
-                         double amb_margin, hipStream_t s);
+                         hipStream_t s);
 size_t choice_dev_size();
 void choice_dev_unpack(const void *p, uint32_t *i_best, uint32_t *j_best, double *F_best,
                        double *F_min, uint32_t *j_psl, int32_t *psl_min, int32_t *psl_k, uint32_t *flags);
+// The ambiguity flags of the selection just made (after launch_select, before
+// launch_apply): pure != 0 writes the choice record `out` (one walk), else the
+// walks' step flags. margin: relative margin of the flags.
+hipError_t launch_ambig(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t comb_blocks,
+                        uint32_t comb_group, int pure, void *out, double margin, hipStream_t s);
 hipError_t launch_apply(WalkDev *walks, const BatchEntry *batch, const SegMap &map, int64_t j_fixed,
                         hipStream_t s);
 hipError_t launch_flip_bit(WalkDev *walks, const BatchEntry *batch, uint32_t j, hipStream_t s);

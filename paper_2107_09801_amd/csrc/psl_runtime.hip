@@ -539,7 +539,9 @@ psl_status launch_step(psl_ctx *ctx, const BatchPlan &pl, const Tables &tabs, ui
                              ctx->stream));
     if (timed && (st = timing_mark(ctx))) return st;
     HIP_TRY(ctx, launch_select(ctx->d_walks, pl.d_batch, n, pl.comb_blocks, pl.comb_group, tabs, 0, nullptr,
-                               pl.d_pend, ctx->amb_margin, ctx->stream));
+                               pl.d_pend, ctx->stream));
+    HIP_TRY(ctx, launch_ambig(ctx->d_walks, pl.d_batch, n, pl.comb_blocks, pl.comb_group, 0, nullptr,
+                              ctx->amb_margin, ctx->stream));
     HIP_TRY(ctx, launch_apply(ctx->d_walks, pl.d_batch, pl.seg, -1, ctx->stream));
     HIP_TRY(ctx, launch_bookkeep(ctx->d_walks, pl.d_batch, n, pl.d_pend, ctx->stream));
     HIP_TRY(ctx, launch_switch_corr(ctx->d_walks, pl.d_batch, n, pl.max_L, pl.d_pend, ctx->stream));
@@ -816,7 +818,10 @@ psl_status psl_eval_neighbourhood(psl_ctx *ctx, uint32_t walk, uint32_t start, u
     HIP_TRY(ctx, launch_eval(ctx->d_walks, ctx->pure.d_batch, ctx->pure.d_items, ctx->pure.n_items,
                              tabs, ctx->pure.shape, ctx->pure.d_queues, ctx->stream));
     HIP_TRY(ctx, launch_select(ctx->d_walks, ctx->pure.d_batch, 1, ctx->pure.comb_blocks, ctx->pure.comb_group, tabs, 1,
-                               ctx->d_choice, nullptr, ctx->amb_margin, ctx->stream));
+                               ctx->d_choice, nullptr,
+                               ctx->stream));
+    HIP_TRY(ctx, launch_ambig(ctx->d_walks, ctx->pure.d_batch, 1, ctx->pure.comb_blocks, ctx->pure.comb_group, 1,
+                              ctx->d_choice, ctx->amb_margin, ctx->stream));
     if (F_dev)
         HIP_TRY(ctx, hipMemcpyAsync(F_dev, ctx->pure.d_f, sizeof(double) * n_lmt,
                                     hipMemcpyDeviceToDevice, ctx->stream));
@@ -1140,8 +1145,7 @@ psl_status psl_set_option(psl_ctx *ctx, int option, int64_t value)
     if (serve_active(ctx)) return fail(ctx, PSL_E_STATE, "the context is serving");
     const bool ok = (option == PSL_OPT_NEAR_LIMIT && value >= -1) ||
                     (option == PSL_OPT_EVAL_ITEMS && (value == -1 || (value >= 1 && value <= kEvalItemsMax))) ||
-                    (option == PSL_OPT_AMBIG_MARGIN && value >= -1 && value <= kAmbigMarginMax) ||
-                    (option == PSL_OPT_TEST_FAIL_ADMIT && value >= 0);
+                    (option == PSL_OPT_AMBIG_MARGIN && value >= -1 && value <= kAmbigMarginMax);
     if (!ok) return fail(ctx, PSL_E_INVAL, "option %d value %lld", option, (long long)value);
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
@@ -1149,10 +1153,8 @@ psl_status psl_set_option(psl_ctx *ctx, int option, int64_t value)
         ctx->near_limit = value;
     else if (option == PSL_OPT_EVAL_ITEMS)
         ctx->eval_items = value < 0 ? kEvalItemsDefault : (uint32_t)value;
-    else if (option == PSL_OPT_AMBIG_MARGIN)
-        ctx->amb_margin = value < 0 ? kAmbigMarginDefault : (double)value * 1e-15;
     else
-        ctx->test_fail_admit = (uint64_t)value;
+        ctx->amb_margin = value < 0 ? kAmbigMarginDefault : (double)value * 1e-15;
     plans_clear(ctx);            // cached layouts carry the old value
     return PSL_OK;
 }

@@ -33,55 +33,21 @@ uint64_t now_ns()
                std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// The loop's device memory is one region of hbm_budget bytes. Walk slabs are
-// taken first-fit from its low end; the per-iteration scratch of the batch
-// (entries, work items, partial sums, per-candidate F and PSL, chunk suffix
-// arrays, near-peak lists, selection and segment arrays) and of each
-// admission is carved from its high end, afresh whenever the batch changes.
-// A job is admitted only if, with its slab placed, the slabs still end below
-// the scratch reserve: the sum of every admitted job's scratch bound plus
-// kPoolFixed. So the loop never allocates device memory while it runs.
-constexpr size_t kPoolFixed = (size_t)64 << 10;   // alignment of the carved buffers, queues, list heads
-constexpr size_t kPoolAlign = 256;
-
-// Largest k-splits x candidates, and k-splits x candidate tiles, a walk of
-// length L with n_lmt candidates gets in any batch: a batch's work only
-// lengthens the work items, so the walk alone with the largest work-item
-// target items_cap bounds both, over the three tile widths.
-void split_bound(uint32_t L, uint32_t n_lmt, uint32_t items_cap, uint64_t *ks_n, uint64_t *ks_tiles)
+// Upper bound of the evaluation scratch one walk can need in a batch (the
+// number of k-splits grows only while the batch has few candidate tiles).
+size_t scratch_bound(uint32_t L, uint32_t n_lmt)
 {
-    *ks_n = 0;
-    *ks_tiles = 0;
-    for (int waves : {kEvalWavesSmall, kEvalWaves, kEvalWavesMax}) {
-        const uint32_t tile = 64u * (uint32_t)waves;
-        const uint64_t tiles = (n_lmt + tile - 1) / tile;
-        const uint32_t K = item_shifts_for(tiles * (L - 1), tile, items_cap);
-        uint32_t t = 0, ks = 0;
-        eval_shape_k(L, n_lmt, K, tile, &t, &ks);
-        *ks_n = std::max<uint64_t>(*ks_n, (uint64_t)ks * n_lmt);
-        *ks_tiles = std::max<uint64_t>(*ks_tiles, (uint64_t)ks * t);
-    }
+    const uint64_t tiles = (n_lmt + 64 * kEvalWavesSmall - 1) / (64 * kEvalWavesSmall);
+    const uint64_t ks_max = std::max<uint64_t>(1, ((L - 1 + 31) / 32) / (kTileK / 32));
+    const uint64_t ks = std::min<uint64_t>(ks_max, (4096 + tiles - 1) / tiles);
+    return (size_t)(12ull * ks * n_lmt + 12ull * n_lmt + 24ull * suffix_len(L) +
+                    4ull * (kNearCap + 1) + sizeof(SelPart) * kCombMaxBlocks + sizeof(BatchEntry) +
+                    sizeof(EvalItem) * ks * tiles);
 }
 
-// Upper bound of one walk's share of the scratch of any batch it is in.
-size_t scratch_bound(uint32_t L, uint32_t n_lmt, uint32_t items_cap)
+size_t job_footprint(const psl_walk_cfg &c)
 {
-    uint64_t ks_n = 0, ks_tiles = 0;
-    split_bound(L, n_lmt, items_cap, &ks_n, &ks_tiles);
-    const uint64_t segs = seg_count(L, kSegShiftMin);
-    return (size_t)(12ull * ks_n                           // partial sums and maxima
-                    + 12ull * n_lmt                        // F and PSL per candidate
-                    + 24ull * suffix_len(L)                // chunk suffix arrays: step, admission
-                    + 4ull * (kNearCap + 1)                // near-peak list
-                    + sizeof(SelPart) * kCombMaxBlocks     // combine-block minima
-                    + 2 * sizeof(BatchEntry) + 16          // batch and admission entries, list slots
-                    + sizeof(EvalItem) * 8 * ks_tiles      // work items, with the flat form's padding
-                    + 12ull * segs);                       // per-segment totals of the O(L) passes
-}
-
-size_t job_footprint(const psl_walk_cfg &c, uint32_t items_cap)
-{
-    return slab_layout(c.L).slab_bytes + scratch_bound(c.L, c.n_lmt ? c.n_lmt : c.L, items_cap);
+    return slab_layout(c.L).slab_bytes + scratch_bound(c.L, c.n_lmt ? c.n_lmt : c.L);
 }
 
 struct Job {
@@ -90,8 +56,7 @@ struct Job {
     uint64_t budget = 0;
     uint64_t *best_out = nullptr;
     uint64_t t_arrive = 0, t_admit = 0;
-    size_t foot = 0;          // slab + scratch bound, counted against the budget
-    size_t bound = 0;         // scratch bound
+    size_t foot = 0;
     uint32_t slot = UINT32_MAX;
     void *slab = nullptr;
     WalkDev dev{};            // device pointers of the walk
@@ -99,6 +64,13 @@ struct Job {
     char *host = nullptr;     // pinned read-back: WalkDev, then best bits
     size_t host_bytes = 0;
     hipEvent_t ev = nullptr;
+};
+
+// Grow-only device buffer.
+template <class T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t cap = 0;
 };
 
 }  // namespace
@@ -119,27 +91,26 @@ struct Server {
     // scheduler-owned
     std::deque<Job> pending;
     std::vector<Job> active, retiring;
-    size_t used = 0;          // footprints of the admitted jobs
-    size_t reserve = 0;       // scratch bounds of the admitted jobs
-    uint32_t items_cap = 0;   // largest work-item target of the context
+    size_t used = 0;
     char *arena_mem = nullptr;
-    Arena arena;              // walk slabs, from the low end of arena_mem
-    char *pool_ptr = nullptr; // scratch carved downwards from arena_mem + budget
-    uint64_t admissions = 0;  // admission batches so far
-    uint64_t fail_admit_at = 0;   // PSL_OPT_TEST_FAIL_ADMIT
-    // this iteration's batch layout (carved)
-    BatchEntry *d_batch = nullptr;
-    EvalItem *d_items = nullptr;
-    double *d_fpart = nullptr, *d_f = nullptr, *d_s0 = nullptr, *d_segtot = nullptr;
-    uint32_t *d_mpart = nullptr, *d_m0 = nullptr, *d_near = nullptr, *d_pend = nullptr, *d_seg = nullptr,
-             *d_segmax = nullptr;
-    int32_t *d_p = nullptr;
-    SelPart *d_red = nullptr;
-    EvalQueues *d_queues = nullptr;
+    Arena arena;
+    DevBuf<BatchEntry> d_batch, d_admit;
+    DevBuf<EvalItem> d_items;
+    DevBuf<double> d_fpart, d_f, d_s0;
+    DevBuf<uint32_t> d_mpart, d_m0, d_near, d_want;
+    DevBuf<SelPart> d_red;
+    DevBuf<uint32_t> d_pend;      // pending list of the iteration's batch
+    DevBuf<uint32_t> d_seg, d_adm_seg;   // segment maps (batch, admitted walks)
+    DevBuf<double> d_segtot;             // per segment of the batch map: chunk-sum total
+    DevBuf<uint32_t> d_segmax;
     SegMap seg{};
+    DevBuf<double> d_adm_s0;      // chunk arrays of the admitted walks' fitness pass
+    DevBuf<uint32_t> d_adm_m0;
     uint32_t comb_blocks = 1, comb_group = 1;
+    DevBuf<int32_t> d_p;
     uint32_t n_items = 0, max_L = 0;
     EvalShape shape;
+    DevBuf<EvalQueues> d_queues;
     bool dirty = true;
     // pinned staging, two halves used by alternate iterations
     char *stage[2] = {nullptr, nullptr};
@@ -155,25 +126,36 @@ struct Server {
     psl_status iterate();
     psl_status upload_layout(char *&sp, char *stage_end);
     psl_status admit(char *&sp, char *stage_end);
-    psl_status admit_launch(std::vector<Job> &adm, char *&sp, char *stage_end);
-    void carve_reset() { pool_ptr = arena_mem + cfg.hbm_budget; }
-    template <class T>
-    psl_status carve(T *&p, size_t count)
-    {
-        const size_t bytes = align_up(sizeof(T) * std::max<size_t>(count, 1), kPoolAlign);
-        char *np = pool_ptr - bytes;
-        if (bytes > (size_t)(pool_ptr - arena_mem) || np < arena_mem + arena.used_end())
-            return fail(ctx, PSL_E_NOMEM, "serving scratch (%zu bytes) would overlap the walk slabs", bytes);
-        pool_ptr = np;
-        p = (T *)np;
-        return PSL_OK;
-    }
     void retire_finished();
     void fail_all(int32_t status);
     void finish(Job &j, int32_t status);
 };
 
 namespace {
+
+template <class T>
+psl_status grow(psl_ctx *ctx, DevBuf<T> &b, size_t n)
+{
+    if (n <= b.cap) return PSL_OK;
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    dev_free(ctx, b.p, false);
+    b.p = nullptr;
+    b.cap = 0;
+    size_t c = std::max<size_t>(n + n / 2, 1024);
+    void *p;
+    psl_status st = dev_alloc(ctx, &p, sizeof(T) * c, false);
+    if (st) return st;
+    b.p = (T *)p;
+    b.cap = c;
+    return PSL_OK;
+}
+
+template <class T>
+void release(psl_ctx *ctx, DevBuf<T> &b)
+{
+    dev_free(ctx, b.p, false);
+    b = DevBuf<T>();
+}
 
 psl_status pinned(psl_ctx *ctx, Server &s, size_t bytes, char **out)
 {
@@ -237,7 +219,6 @@ void Server::fail_all(int32_t status)
     }
     active.clear();
     used = 0;
-    reserve = 0;
     dirty = true;
 }
 
@@ -254,25 +235,19 @@ void Server::retire_finished()
 }
 
 // Admits jobs from the FIFO head; their walk records and the batched init
-// arrays go through the staging buffer. A job is admitted when a slot is free
-// and its slab fits below the scratch reserve that includes its own bound.
+// arrays go through the staging buffer.
 psl_status Server::admit(char *&sp, char *stage_end)
 {
     std::vector<Job> adm;
-    const size_t budget = cfg.hbm_budget;
     while (!pending.empty()) {
         Job &j = pending.front();
         if (active.size() + adm.size() >= cfg.max_slots) break;
-        const size_t res = reserve + j.bound;
-        if (used + j.foot > budget || res + kPoolFixed > budget) break;   // strict FIFO: no overtaking
-        const size_t limit = budget - res - kPoolFixed;
-        if (arena.used_end() > limit) break;        // the reserve would reach a slab in use
+        if (used + j.foot > cfg.hbm_budget) break;      // strict FIFO: no overtaking
         const SlabLayout lay = slab_layout(j.cfg.L);
-        void *slab = arena.alloc(lay.slab_bytes, limit);
+        void *slab = arena.alloc(lay.slab_bytes);
         if (!slab) break;
         j.slab = slab;
         used += j.foot;
-        reserve = res;
         adm.push_back(std::move(j));
         pending.pop_front();
     }
@@ -283,57 +258,36 @@ psl_status Server::admit(char *&sp, char *stage_end)
         for (auto it = adm.rbegin(); it != adm.rend(); ++it) {
             arena.release(it->slab);
             used -= it->foot;
-            reserve -= it->bound;
             it->slab = nullptr;
             pending.push_front(std::move(*it));
         }
         return PSL_OK;
     }
-    const psl_status st = admit_launch(adm, sp, stage_end);
-    if (st) {
-        // the jobs hold slabs (and perhaps slots): hand them to the active
-        // list, whose failure path releases both and finishes each job
-        for (auto &j : adm) active.push_back(std::move(j));
-        dirty = true;
-    }
-    return st;
-}
-
-psl_status Server::admit_launch(std::vector<Job> &adm, char *&sp, char *stage_end)
-{
-    (void)stage_end;
-    const uint32_t n = (uint32_t)adm.size();
+    psl_status st;
+    if ((st = grow(ctx, d_admit, adm.size()))) return st;
+    if ((st = grow(ctx, d_want, adm.size()))) return st;
     size_t n_suf = 0;
     for (const Job &j : adm) n_suf += suffix_len(j.cfg.L);
-    // the admission's device arrays, carved from the top of the scratch
-    // region (work queued earlier on the stream is done with it by the time
-    // these copies and launches run)
-    carve_reset();
-    BatchEntry *d_admit = nullptr;
-    uint32_t *d_want = nullptr, *d_adm_seg = nullptr, *d_adm_m0 = nullptr;
-    double *d_adm_s0 = nullptr;
-    psl_status st;
-    if ((st = carve(d_admit, n)) || (st = carve(d_want, n)) || (st = carve(d_adm_seg, (size_t)n + 1)) ||
-        (st = carve(d_adm_s0, n_suf)) || (st = carve(d_adm_m0, n_suf)))
-        return st;
+    if ((st = grow(ctx, d_adm_s0, n_suf)) || (st = grow(ctx, d_adm_m0, n_suf))) return st;
     size_t os = 0;
     uint32_t maxL = 0, maxnw = 0;
     BatchEntry *be = (BatchEntry *)sp;
-    sp += sizeof(BatchEntry) * n;
+    sp += sizeof(BatchEntry) * adm.size();
     uint32_t *want = (uint32_t *)sp;
-    sp += sizeof(uint32_t) * n;
+    sp += sizeof(uint32_t) * adm.size();
     uint32_t *adm_off = (uint32_t *)sp;
-    sp += sizeof(uint32_t) * (n + 1);
+    sp += sizeof(uint32_t) * (adm.size() + 1);
     sp = (char *)(((uintptr_t)sp + 63) & ~(uintptr_t)63);
+    if ((st = grow(ctx, d_adm_seg, adm.size() + 1))) return st;
     SegMap adm_map{};
     {
-        std::vector<uint32_t> aL(n);
-        for (uint32_t b = 0; b < n; ++b) aL[b] = adm[b].cfg.L;
-        adm_map = seg_prefix(aL.data(), n, adm_off);
-        adm_map.off = d_adm_seg;
+        std::vector<uint32_t> aL(adm.size());
+        for (size_t b = 0; b < adm.size(); ++b) aL[b] = adm[b].cfg.L;
+        adm_map = seg_prefix(aL.data(), (uint32_t)adm.size(), adm_off);
+        adm_map.off = d_adm_seg.p;
     }
     const uint64_t t = now_ns();
-    for (uint32_t b = 0; b < n; ++b) {
+    for (size_t b = 0; b < adm.size(); ++b) {
         Job &j = adm[b];
         uint32_t slot;
         if (!ctx->free_slots.empty()) {
@@ -343,8 +297,8 @@ psl_status Server::admit_launch(std::vector<Job> &adm, char *&sp, char *stage_en
             slot = (uint32_t)ctx->walks.size();
             ctx->walks.push_back(WalkHost());
         }
-        j.slot = slot;
         if (slot >= ctx->walk_cap) return fail(ctx, PSL_E_STATE, "walk capacity exceeded");
+        j.slot = slot;
         const SlabLayout lay = slab_layout(j.cfg.L);
         WalkHost &h = ctx->walks[slot];
         h.active = true;
@@ -362,28 +316,24 @@ psl_status Server::admit_launch(std::vector<Job> &adm, char *&sp, char *stage_en
                                     ctx->stream));
         memset(&be[b], 0, sizeof(BatchEntry));
         be[b].slot = slot;
-        be[b].S0 = d_adm_s0 + os;
-        be[b].M0 = d_adm_m0 + os;
+        be[b].S0 = d_adm_s0.p + os;
+        be[b].M0 = d_adm_m0.p + os;
         os += suffix_len(j.cfg.L);
         want[b] = 1;
         maxL = std::max(maxL, j.cfg.L);
         maxnw = std::max(maxnw, h.nw);
         j.t_admit = t;
     }
-    admissions++;
-    if (fail_admit_at && admissions == fail_admit_at)
-        return fail(ctx, PSL_E_HIP, "admission %llu failed on request (PSL_OPT_TEST_FAIL_ADMIT)",
-                    (unsigned long long)admissions);
-    HIP_TRY(ctx, hipMemcpyAsync(d_admit, be, sizeof(BatchEntry) * n, hipMemcpyHostToDevice, ctx->stream));
-    HIP_TRY(ctx, hipMemcpyAsync(d_want, want, sizeof(uint32_t) * n, hipMemcpyHostToDevice, ctx->stream));
+    const uint32_t n = (uint32_t)adm.size();
+    HIP_TRY(ctx, hipMemcpyAsync(d_admit.p, be, sizeof(BatchEntry) * n, hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(d_want.p, want, sizeof(uint32_t) * n, hipMemcpyHostToDevice, ctx->stream));
     const Tables tabs = tables_of(ctx);
-    HIP_TRY(ctx, launch_init_bits(ctx->d_walks, d_admit, d_want, n, maxnw, ctx->stream));
-    HIP_TRY(ctx, launch_corr(ctx->d_walks, d_admit, n, maxL, 0, ctx->stream));
-    HIP_TRY(ctx, hipMemcpyAsync(d_adm_seg, adm_off, sizeof(uint32_t) * (n + 1), hipMemcpyHostToDevice,
+    HIP_TRY(ctx, launch_init_bits(ctx->d_walks, d_admit.p, d_want.p, n, maxnw, ctx->stream));
+    HIP_TRY(ctx, launch_corr(ctx->d_walks, d_admit.p, n, maxL, 0, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(d_adm_seg.p, adm_off, sizeof(uint32_t) * (n + 1), hipMemcpyHostToDevice,
                                 ctx->stream));
-    HIP_TRY(ctx, launch_suffix(ctx->d_walks, d_admit, n, maxL, tabs, 2, nullptr, &adm_map, ctx->stream));
+    HIP_TRY(ctx, launch_suffix(ctx->d_walks, d_admit.p, n, maxL, tabs, 2, nullptr, &adm_map, ctx->stream));
     for (auto &j : adm) active.push_back(std::move(j));
-    adm.clear();
     dirty = true;
     {
         std::lock_guard<std::mutex> g(mu);
@@ -422,18 +372,13 @@ psl_status Server::upload_layout(char *&sp, char *stage_end)
                         sizeof(uint32_t) * (n + 1) + 512;
     if ((size_t)(stage_end - sp) < need) return fail(ctx, PSL_E_NOMEM, "serving staging too small");
     psl_status st;
-    std::vector<uint32_t> off_host(n + 1);
-    const SegMap seg_host = seg_prefix(Ls.data(), n, off_host.data());
-    // the batch's scratch, carved afresh from the top of the region (within
-    // the reserve of the admitted jobs' bounds)
-    carve_reset();
-    if ((st = carve(d_batch, n)) || (st = carve(d_items, items)) || (st = carve(d_fpart, n_part)) ||
-        (st = carve(d_mpart, n_part)) || (st = carve(d_f, n_cand)) || (st = carve(d_p, n_cand)) ||
-        (st = carve(d_s0, n_suf)) || (st = carve(d_m0, n_suf)) ||
-        (st = carve(d_near, (size_t)(kNearCap + 1) * n)) || (st = carve(d_queues, 1)) ||
-        (st = carve(d_red, (size_t)comb_blocks * n)) || (st = carve(d_pend, (size_t)n + 1)) ||
-        (st = carve(d_seg, (size_t)n + 1)) || (st = carve(d_segtot, seg_host.total)) ||
-        (st = carve(d_segmax, seg_host.total)))
+    if ((st = grow(ctx, d_batch, n)) || (st = grow(ctx, d_items, items)) ||
+        (st = grow(ctx, d_fpart, n_part)) || (st = grow(ctx, d_mpart, n_part)) ||
+        (st = grow(ctx, d_f, n_cand)) || (st = grow(ctx, d_p, n_cand)) ||
+        (st = grow(ctx, d_s0, n_suf)) || (st = grow(ctx, d_m0, n_suf)) ||
+        (st = grow(ctx, d_near, (size_t)(kNearCap + 1) * n)) || (st = grow(ctx, d_queues, 1)) ||
+        (st = grow(ctx, d_red, (size_t)comb_blocks * n)) || (st = grow(ctx, d_pend, (size_t)n + 1)) ||
+        (st = grow(ctx, d_seg, (size_t)n + 1)))
         return st;
     BatchEntry *be = (BatchEntry *)sp;
     sp += sizeof(BatchEntry) * n;
@@ -447,14 +392,14 @@ psl_status Server::upload_layout(char *&sp, char *stage_end)
         const uint32_t nl = j.cfg.n_lmt ? j.cfg.n_lmt : j.cfg.L;
         BatchEntry &e = be[b];
         memset(&e, 0, sizeof e);
-        e.Fpart = d_fpart + op;
-        e.Mpart = d_mpart + op;
-        e.F = d_f + oc;
-        e.P = d_p + oc;
-        e.S0 = d_s0 + os;
-        e.M0 = d_m0 + os;
-        e.near = d_near + (size_t)(kNearCap + 1) * b;
-        e.red = d_red + (size_t)comb_blocks * b;
+        e.Fpart = d_fpart.p + op;
+        e.Mpart = d_mpart.p + op;
+        e.F = d_f.p + oc;
+        e.P = d_p.p + oc;
+        e.S0 = d_s0.p + os;
+        e.M0 = d_m0.p + os;
+        e.near = d_near.p + (size_t)(kNearCap + 1) * b;
+        e.red = d_red.p + (size_t)comb_blocks * b;
         e.slot = j.slot;
         e.ksplit = ks[b];
         e.tiles = tiles[b];
@@ -465,22 +410,23 @@ psl_status Server::upload_layout(char *&sp, char *stage_end)
         os += suffix_len(j.cfg.L);
     }
     memcpy(it, lay.items.data(), sizeof(EvalItem) * items);
-    HIP_TRY(ctx, hipMemcpyAsync(d_batch, be, sizeof(BatchEntry) * n, hipMemcpyHostToDevice, ctx->stream));
-    HIP_TRY(ctx, hipMemcpyAsync(d_items, it, sizeof(EvalItem) * items, hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(d_batch.p, be, sizeof(BatchEntry) * n, hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(d_items.p, it, sizeof(EvalItem) * items, hipMemcpyHostToDevice,
+                                ctx->stream));
     EvalQueues *qs = (EvalQueues *)sp;
     sp += sizeof(EvalQueues);
     *qs = lay.queues;
-    HIP_TRY(ctx, hipMemcpyAsync(d_queues, qs, sizeof(EvalQueues), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(d_queues.p, qs, sizeof(EvalQueues), hipMemcpyHostToDevice, ctx->stream));
     sp = (char *)(((uintptr_t)sp + 63) & ~(uintptr_t)63);
     uint32_t *off = (uint32_t *)sp;
     sp += sizeof(uint32_t) * (n + 1);
-    memcpy(off, off_host.data(), sizeof(uint32_t) * (n + 1));
-    seg = seg_host;
-    seg.off = d_seg;
-    seg.tot = d_segtot;
-    seg.tmax = d_segmax;
-    HIP_TRY(ctx, hipMemcpyAsync(d_seg, off, sizeof(uint32_t) * (n + 1), hipMemcpyHostToDevice, ctx->stream));
-    HIP_TRY(ctx, launch_near_reset(d_batch, n, d_pend, ctx->stream));
+    seg = seg_prefix(Ls.data(), n, off);
+    if ((st = grow(ctx, d_segtot, seg.total)) || (st = grow(ctx, d_segmax, seg.total))) return st;
+    seg.off = d_seg.p;
+    seg.tot = d_segtot.p;
+    seg.tmax = d_segmax.p;
+    HIP_TRY(ctx, hipMemcpyAsync(d_seg.p, off, sizeof(uint32_t) * (n + 1), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, launch_near_reset(d_batch.p, n, d_pend.p, ctx->stream));
     n_items = (uint32_t)items;
     dirty = false;
     return PSL_OK;
@@ -535,17 +481,19 @@ psl_status Server::iterate()
     if (dirty && (st = upload_layout(sp, se))) return st;
     const uint32_t n = (uint32_t)active.size();
     const Tables tabs = tables_of(ctx);
-    HIP_TRY(ctx, launch_suffix(ctx->d_walks, d_batch, n, max_L, tabs, 0, nullptr, &seg, ctx->stream));
-    HIP_TRY(ctx, launch_eval(ctx->d_walks, d_batch, d_items, n_items, tabs, shape, d_queues, ctx->stream));
-    HIP_TRY(ctx, launch_select(ctx->d_walks, d_batch, n, comb_blocks, comb_group, tabs, 0, nullptr, d_pend,
-                               ctx->amb_margin, ctx->stream));
-    HIP_TRY(ctx, launch_apply(ctx->d_walks, d_batch, seg, -1, ctx->stream));
-    HIP_TRY(ctx, launch_bookkeep(ctx->d_walks, d_batch, n, d_pend, ctx->stream));
-    HIP_TRY(ctx, launch_switch_corr(ctx->d_walks, d_batch, n, max_L, d_pend, ctx->stream));
+    HIP_TRY(ctx, launch_suffix(ctx->d_walks, d_batch.p, n, max_L, tabs, 0, nullptr, &seg, ctx->stream));
+    HIP_TRY(ctx, launch_eval(ctx->d_walks, d_batch.p, d_items.p, n_items, tabs, shape, d_queues.p, ctx->stream));
+    HIP_TRY(ctx, launch_select(ctx->d_walks, d_batch.p, n, comb_blocks, comb_group, tabs, 0, nullptr, d_pend.p,
+                               ctx->stream));
+    HIP_TRY(ctx, launch_ambig(ctx->d_walks, d_batch.p, n, comb_blocks, comb_group, 0, nullptr, ctx->amb_margin,
+                              ctx->stream));
+    HIP_TRY(ctx, launch_apply(ctx->d_walks, d_batch.p, seg, -1, ctx->stream));
+    HIP_TRY(ctx, launch_bookkeep(ctx->d_walks, d_batch.p, n, d_pend.p, ctx->stream));
+    HIP_TRY(ctx, launch_switch_corr(ctx->d_walks, d_batch.p, n, max_L, d_pend.p, ctx->stream));
     bool big = false;
     for (auto &j : active) big |= j.cfg.flip_lmt > kFlipIncremental;
-    if (big) HIP_TRY(ctx, launch_corr(ctx->d_walks, d_batch, n, max_L, 1, ctx->stream));
-    HIP_TRY(ctx, launch_suffix(ctx->d_walks, d_batch, n, max_L, tabs, 1, d_pend, nullptr, ctx->stream));
+    if (big) HIP_TRY(ctx, launch_corr(ctx->d_walks, d_batch.p, n, max_L, 1, ctx->stream));
+    HIP_TRY(ctx, launch_suffix(ctx->d_walks, d_batch.p, n, max_L, tabs, 1, d_pend.p, nullptr, ctx->stream));
     uint64_t evals = 0, upd = 0;
     for (auto &j : active) {
         const uint64_t nl = j.cfg.n_lmt ? j.cfg.n_lmt : j.cfg.L;
@@ -571,7 +519,6 @@ psl_status Server::iterate()
         HIP_TRY(ctx, hipEventRecord(j.ev, ctx->stream));
         arena.release(j.slab);
         used -= j.foot;
-        reserve -= j.bound;
         j.slab = nullptr;
         ctx->walks[j.slot] = WalkHost();
         ctx->free_slots.push_back(j.slot);
@@ -664,6 +611,26 @@ void serve_shutdown(psl_ctx *ctx)
     s->cv.notify_all();
     if (s->th.joinable()) s->th.join();
     (void)hipStreamSynchronize(ctx->stream);
+    release(ctx, s->d_batch);
+    release(ctx, s->d_admit);
+    release(ctx, s->d_items);
+    release(ctx, s->d_fpart);
+    release(ctx, s->d_f);
+    release(ctx, s->d_s0);
+    release(ctx, s->d_mpart);
+    release(ctx, s->d_m0);
+    release(ctx, s->d_near);
+    release(ctx, s->d_red);
+    release(ctx, s->d_pend);
+    release(ctx, s->d_seg);
+    release(ctx, s->d_adm_seg);
+    release(ctx, s->d_segtot);
+    release(ctx, s->d_segmax);
+    release(ctx, s->d_adm_s0);
+    release(ctx, s->d_adm_m0);
+    release(ctx, s->d_want);
+    release(ctx, s->d_p);
+    release(ctx, s->d_queues);
     for (int h = 0; h < 2; ++h) {
         if (s->stage[h]) (void)hipHostFree(s->stage[h]);
         if (s->stage_ev[h]) (void)hipEventDestroy(s->stage_ev[h]);
@@ -709,9 +676,6 @@ psl_status psl_serve_start(psl_ctx *ctx, const psl_serve_cfg *cfg)
         return fail(ctx, PSL_E_NOMEM, "serving arena of %llu bytes", (unsigned long long)cfg->hbm_budget);
     }
     s->arena.reset(s->arena_mem, cfg->hbm_budget);
-    s->carve_reset();
-    s->items_cap = items_max(ctx);
-    s->fail_admit_at = ctx->test_fail_admit;
     const size_t stage_bytes = ((size_t)4 << 20) + (size_t)cfg->max_slots * 256;
     for (int h = 0; h < 2; ++h) {
         if (hipHostMalloc((void **)&s->stage[h], stage_bytes, hipHostMallocDefault) != hipSuccess ||
@@ -748,9 +712,8 @@ psl_status psl_serve_submit(psl_ctx *ctx, const psl_job *job, uint64_t *ticket)
     j.budget = job->step_budget;
     j.best_out = job->best_bits_out;
     j.t_arrive = now_ns();
-    j.foot = job_footprint(c, s->items_cap);
-    j.bound = j.foot - slab_layout(c.L).slab_bytes;
-    if (j.foot + kPoolFixed > s->cfg.hbm_budget) return PSL_E_FULL;
+    j.foot = job_footprint(c);
+    if (j.foot > s->cfg.hbm_budget) return PSL_E_FULL;
     {
         std::lock_guard<std::mutex> g(s->mu);
         if (!s->running || s->stop) return PSL_E_STATE;
@@ -782,7 +745,7 @@ psl_status psl_serve_poll(psl_ctx *ctx, uint64_t ticket, psl_job_result *out)
 psl_status psl_serve_footprint(const psl_walk_cfg *cfg, uint64_t *bytes)
 {
     if (!cfg || !bytes || cfg->L < 2 || cfg->L > PSL_L_MAX || cfg->n_lmt > cfg->L) return PSL_E_INVAL;
-    *bytes = job_footprint(*cfg, kEvalItemsDefault);
+    *bytes = job_footprint(*cfg);
     return PSL_OK;
 }
 

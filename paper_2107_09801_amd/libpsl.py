@@ -32,7 +32,6 @@ EXPORTS = ["psl_ctx_create", "psl_ctx_destroy", "psl_last_error", "psl_sync", "p
 OPT_NEAR_LIMIT = 1
 OPT_EVAL_ITEMS = 2
 OPT_AMBIG_MARGIN = 3      # value in units of 1e-15 (-1: the default, 5e-13)
-OPT_TEST_FAIL_ADMIT = 4   # tests only: the n-th admission of the next serving run fails
 
 
 class PslError(RuntimeError):

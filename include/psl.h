@@ -188,6 +188,25 @@ PSL_API psl_status psl_eval_neighbourhood(psl_ctx *ctx, uint32_t walk, uint32_t 
                                   uint32_t n_lmt, double *F_dev, int32_t *psl_dev,
                                   psl_choice *out);
 
+/* psl_eval_neighbourhood for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same evaluation, kernels and results, but every scratch
+ * array of the call (work items, k-split partial sums, chunk suffix arrays,
+ * near-peak list, combine minima, the choice record) is carved from a fixed
+ * 64 MiB device array that each device the library runs on holds until the
+ * process ends; the call makes no hipMalloc, hipFree or other device
+ * allocation. F_dev and psl_dev are required (caller-owned device memory of
+ * n_lmt entries; the kernels write them directly); out is as for
+ * psl_eval_neighbourhood. Every call on a device shares that device's array
+ * and leaves its contents behind (each call clears what must start at zero
+ * with a kernel): calls that overlap on one device, from two contexts or two
+ * threads, race. Errors: as psl_eval_neighbourhood; PSL_E_INVAL if F_dev or
+ * psl_dev is NULL; PSL_E_NOMEM if the evaluation's scratch would exceed the
+ * 64 MiB (the message gives the limit), with nothing launched. */
+PSL_API psl_status psl_eval_neighbourhood_noalloc(psl_ctx *ctx, uint32_t walk, uint32_t start,
+                                                  uint32_t n_lmt, double *F_dev, int32_t *psl_dev,
+                                                  psl_choice *out);
+
 /* Flip(pivot, j) of Algorithm 1: element j changes sign and C is updated in
  * O(L) by the one-element flip C'_k = C_k - 2 s_j (s_{j+k} + s_{j-k}) (terms
  * that stay in bounds only); the pivot's F and PSL are recomputed. No

@@ -98,6 +98,7 @@ struct BatchPlan {
     EvalQueues *d_queues = nullptr;   // persistent evaluation: work queues
     BatchEntry *d_batch = nullptr;
     EvalItem *d_items = nullptr;
+    bool carved = false;              // arrays carved from caller memory: not freed here
     hipGraph_t graph = nullptr;       // one captured step of this plan
     hipGraphExec_t gexec = nullptr;
     double *d_fpart = nullptr, *d_f = nullptr, *d_s0 = nullptr;
@@ -145,6 +146,8 @@ struct psl_ctx {
     int64_t near_limit = -1;          // PSL_OPT_NEAR_LIMIT
     uint32_t eval_items = psl_rt::kEvalItemsDefault;  // PSL_OPT_EVAL_ITEMS
     double amb_margin = psl::kAmbigMarginDefault;     // PSL_OPT_AMBIG_MARGIN (relative)
+    void *noalloc_scratch = nullptr;  // this device's fixed scratch (psl_eval_neighbourhood_noalloc)
+    std::string noalloc_err;          // why it is missing, if it is
     psl_rt::Server *server = nullptr; // serving loop, when started
     uint32_t n_cu = 256;              // compute units of the device
     std::map<uint32_t, psl::EvalShape> tuned;  // autotuner choices by tune_key
@@ -205,8 +208,18 @@ SegMap seg_uniform(uint32_t nb, uint32_t L);
 SegMap seg_prefix(const uint32_t *Ls, uint32_t n, uint32_t *off);
 int eval_waves(const uint32_t *n_lmt, uint32_t n);
 psl_status check_cfg(psl_ctx *ctx, const psl_walk_cfg *c);
+// Device memory a plan's arrays come from instead of hipMalloc: a bump
+// allocator over [base, base + cap) (256-byte aligned pieces), with the
+// per-candidate F and PSL arrays given by the caller.
+struct PlanMem {
+    char *base = nullptr;
+    size_t cap = 0, used = 0;
+    double *F = nullptr;
+    int32_t *P = nullptr;
+};
 psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t n, uint32_t n_fixed,
-                     uint32_t start_fixed, const EvalShape *force = nullptr, uint32_t force_items = 0);
+                     uint32_t start_fixed, const EvalShape *force = nullptr, uint32_t force_items = 0,
+                     PlanMem *mem = nullptr);
 // The work-item target of a batch: the autotuned one for its key, else the
 // context's PSL_OPT_EVAL_ITEMS; and the largest target any batch can get.
 uint32_t items_for(const psl_ctx *ctx, const uint32_t *Ls, const uint32_t *n_lmt, uint32_t n);

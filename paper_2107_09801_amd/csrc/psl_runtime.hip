@@ -5,6 +5,38 @@
 using namespace psl;
 using namespace psl_rt;
 
+// Fixed scratch of psl_eval_neighbourhood_noalloc: the evaluation plan's
+// arrays of one walk (work items, k-split partials, chunk suffix arrays,
+// near-peak list, combine minima, segment map, choice record), carved per
+// call. Every device the library runs on holds one copy until the process
+// ends, and every call on that device shares it. Host code reaches it only
+// through the address hipGetSymbolAddress returns for the device (kept per
+// device below); the array's own name is a host-side stand-in.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};   // device address of `scratch`, per device
+
+// The device address of this device's scratch (the device is current),
+// looked up once per device.
+hipError_t scratch_address(int device, void **out)
+{
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    if (!g_scratch_dev[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_dev[device] = p;
+    }
+    *out = g_scratch_dev[device];
+    return hipSuccess;
+}
+}  // namespace
+
 namespace psl_rt {
 
 psl_status fail(psl_ctx *ctx, psl_status st, const char *fmt, ...)
@@ -80,6 +112,10 @@ void plan_free(psl_ctx *ctx, BatchPlan &pl)
 {
     if (pl.gexec) (void)hipGraphExecDestroy(pl.gexec);
     if (pl.graph) (void)hipGraphDestroy(pl.graph);
+    if (pl.carved) {
+        pl = BatchPlan();
+        return;
+    }
     dev_free(ctx, pl.d_batch, false);
     dev_free(ctx, pl.d_items, false);
     dev_free(ctx, pl.d_fpart, false);
@@ -370,7 +406,7 @@ uint32_t items_max(const psl_ctx *ctx)
 }
 
 psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t n, uint32_t n_fixed,
-                     uint32_t start_fixed, const EvalShape *force, uint32_t force_items)
+                     uint32_t start_fixed, const EvalShape *force, uint32_t force_items, PlanMem *mem)
 {
     const bool fixed = n_fixed != UINT32_MAX;
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
@@ -403,36 +439,56 @@ psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t 
     const uint64_t n_items = items.size();
     if (n_items >= (1ull << 31)) return fail(ctx, PSL_E_INVAL, "batch too large (%llu work items)",
                                              (unsigned long long)n_items);
+    if (mem) {
+        // every array of the plan comes from mem; F and PSL are the caller's
+        pl.carved = true;
+        if (n != 1 || !mem->F || !mem->P) return fail(ctx, PSL_E_INVAL, "carved plans are single-walk");
+    }
+    auto get = [&](void **q, size_t bytes) -> psl_status {
+        if (!mem) return dev_alloc(ctx, q, bytes, false);
+        const size_t need = align_up(std::max<size_t>(bytes, 1), 256);
+        if (need > mem->cap - mem->used)
+            return fail(ctx, PSL_E_NOMEM, "the evaluation needs more than the %zu bytes of fixed scratch",
+                        mem->cap);
+        *q = mem->base + mem->used;
+        mem->used += need;
+        return PSL_OK;
+    };
     void *p;
     psl_status st;
-    if ((st = dev_alloc(ctx, &p, sizeof(double) * n_part, false))) return st;
+    if ((st = get(&p, sizeof(double) * n_part))) return st;
     pl.d_fpart = (double *)p;
-    if ((st = dev_alloc(ctx, &p, sizeof(uint32_t) * n_part, false))) return st;
+    if ((st = get(&p, sizeof(uint32_t) * n_part))) return st;
     pl.d_mpart = (uint32_t *)p;
-    if ((st = dev_alloc(ctx, &p, sizeof(double) * n_cand, false))) return st;
-    pl.d_f = (double *)p;
-    if ((st = dev_alloc(ctx, &p, sizeof(int32_t) * n_cand, false))) return st;
-    pl.d_p = (int32_t *)p;
-    if ((st = dev_alloc(ctx, &p, sizeof(double) * n_suf, false))) return st;
+    if (mem) {
+        pl.d_f = mem->F;
+        pl.d_p = mem->P;
+    } else {
+        if ((st = get(&p, sizeof(double) * n_cand))) return st;
+        pl.d_f = (double *)p;
+        if ((st = get(&p, sizeof(int32_t) * n_cand))) return st;
+        pl.d_p = (int32_t *)p;
+    }
+    if ((st = get(&p, sizeof(double) * n_suf))) return st;
     pl.d_s0 = (double *)p;
-    if ((st = dev_alloc(ctx, &p, sizeof(uint32_t) * n_suf, false))) return st;
+    if ((st = get(&p, sizeof(uint32_t) * n_suf))) return st;
     pl.d_m0 = (uint32_t *)p;
-    if ((st = dev_alloc(ctx, &p, sizeof(uint32_t) * (kNearCap + 1) * n, false))) return st;
+    if ((st = get(&p, sizeof(uint32_t) * (kNearCap + 1) * n))) return st;
     pl.d_near = (uint32_t *)p;
-    if ((st = dev_alloc(ctx, &p, sizeof(SelPart) * pl.comb_blocks * n, false))) return st;
+    if ((st = get(&p, sizeof(SelPart) * pl.comb_blocks * n))) return st;
     pl.d_red = (SelPart *)p;
-    if ((st = dev_alloc(ctx, &p, sizeof(uint32_t) * (n + 1), false))) return st;
+    if ((st = get(&p, sizeof(uint32_t) * (n + 1)))) return st;
     pl.d_pend = (uint32_t *)p;
     {
         std::vector<uint32_t> off(n + 1);
         pl.seg = seg_prefix(Ls.data(), n, off.data());
-        if ((st = dev_alloc(ctx, &p, sizeof(uint32_t) * (n + 1), false))) return st;
+        if ((st = get(&p, sizeof(uint32_t) * (n + 1)))) return st;
         pl.d_seg = (uint32_t *)p;
         pl.seg.off = pl.d_seg;
         HIP_TRY(ctx, hipMemcpy(pl.d_seg, off.data(), sizeof(uint32_t) * (n + 1), hipMemcpyHostToDevice));
-        if ((st = dev_alloc(ctx, &p, sizeof(double) * pl.seg.total, false))) return st;
+        if ((st = get(&p, sizeof(double) * pl.seg.total))) return st;
         pl.d_segtot = (double *)p;
-        if ((st = dev_alloc(ctx, &p, sizeof(uint32_t) * pl.seg.total, false))) return st;
+        if ((st = get(&p, sizeof(uint32_t) * pl.seg.total))) return st;
         pl.d_segmax = (uint32_t *)p;
         pl.seg.tot = pl.d_segtot;
         pl.seg.tmax = pl.d_segmax;
@@ -461,11 +517,11 @@ psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t 
         op += (size_t)ks[b] * n_l[b];
         oc += n_l[b];
     }
-    if ((st = dev_alloc(ctx, &p, sizeof(BatchEntry) * n, false))) return st;
+    if ((st = get(&p, sizeof(BatchEntry) * n))) return st;
     pl.d_batch = (BatchEntry *)p;
-    if ((st = dev_alloc(ctx, &p, sizeof(EvalItem) * std::max<size_t>(items.size(), 1), false))) return st;
+    if ((st = get(&p, sizeof(EvalItem) * std::max<size_t>(items.size(), 1)))) return st;
     pl.d_items = (EvalItem *)p;
-    if ((st = dev_alloc(ctx, &p, sizeof(EvalQueues), false))) return st;
+    if ((st = get(&p, sizeof(EvalQueues)))) return st;
     pl.d_queues = (EvalQueues *)p;
     HIP_TRY(ctx, hipMemcpy(pl.d_queues, &lay.queues, sizeof(EvalQueues), hipMemcpyHostToDevice));
     HIP_TRY(ctx, hipMemcpy(pl.d_batch, be.data(), sizeof(BatchEntry) * n, hipMemcpyHostToDevice));
@@ -618,6 +674,16 @@ psl_status psl_ctx_create(int device, void *hip_stream, void *arena, size_t aren
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
             ctx->n_cu = (uint32_t)cus;
         (void)hipGetLastError();
+    }
+    {
+        // the fixed scratch of psl_eval_neighbourhood_noalloc on this device;
+        // without it that call fails and every other call works
+        const hipError_t e = scratch_address(device, &ctx->noalloc_scratch);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->noalloc_scratch = nullptr;
+            ctx->noalloc_err = std::string("hipGetSymbolAddress: ") + hipGetErrorString(e);
+        }
     }
     if (hipMalloc(&ctx->d_choice, 256) != hipSuccess) {
         if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
@@ -836,6 +902,54 @@ psl_status psl_eval_neighbourhood(psl_ctx *ctx, uint32_t walk, uint32_t start, u
         memset(out, 0, sizeof *out);
         choice_dev_unpack(host.data(), &out->i_best, &out->j_best, &out->F_best, &out->F_min,
                           &out->j_psl, &out->psl_min, &out->psl_k, &out->flags);
+    }
+    return PSL_OK;
+}
+
+psl_status psl_eval_neighbourhood_noalloc(psl_ctx *ctx, uint32_t walk, uint32_t start, uint32_t n_lmt,
+                                          double *F_dev, int32_t *psl_dev, psl_choice *out)
+{
+    if (!ctx) return PSL_E_INVAL;
+    if (serve_active(ctx)) return fail(ctx, PSL_E_STATE, "the context is serving");
+    if (!walk_ok(ctx, walk)) return fail(ctx, PSL_E_STATE, "unknown walk %u", walk);
+    const WalkHost &h = ctx->walks[walk];
+    if (n_lmt < 1 || n_lmt > h.L || start >= h.L)
+        return fail(ctx, PSL_E_INVAL, "start=%u n_lmt=%u for L=%u", start, n_lmt, h.L);
+    if (!F_dev || !psl_dev) return fail(ctx, PSL_E_INVAL, "F_dev and psl_dev are required");
+    if (!ctx->noalloc_scratch)
+        return fail(ctx, PSL_E_STATE, "no fixed scratch on this device (%s)", ctx->noalloc_err.c_str());
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    // the plan's arrays and the choice record from the device's fixed scratch
+    PlanMem mem;
+    mem.base = (char *)ctx->noalloc_scratch;
+    mem.cap = kNoAllocScratchBytes;
+    mem.used = 256;                  // the choice record
+    mem.F = F_dev;
+    mem.P = psl_dev;
+    void *d_choice = mem.base;
+    BatchPlan pl;
+    psl_status st = make_plan(ctx, pl, &walk, 1, n_lmt, start, nullptr, 0, &mem);
+    if (st) {
+        plan_free(ctx, pl);
+        return st;
+    }
+    const Tables tabs = tables_of(ctx);
+    HIP_TRY(ctx, launch_suffix(ctx->d_walks, pl.d_batch, 1, h.L, tabs, 0, nullptr, &pl.seg, ctx->stream));
+    HIP_TRY(ctx, launch_eval(ctx->d_walks, pl.d_batch, pl.d_items, pl.n_items, tabs, pl.shape, pl.d_queues,
+                             ctx->stream));
+    HIP_TRY(ctx, launch_select(ctx->d_walks, pl.d_batch, 1, pl.comb_blocks, pl.comb_group, tabs, 1, d_choice,
+                               nullptr, ctx->stream));
+    HIP_TRY(ctx, launch_ambig(ctx->d_walks, pl.d_batch, 1, pl.comb_blocks, pl.comb_group, 1, d_choice,
+                              ctx->amb_margin, ctx->stream));
+    alignas(16) unsigned char host[256];
+    if (choice_dev_size() > sizeof host) return fail(ctx, PSL_E_STATE, "choice record too large");
+    HIP_TRY(ctx, hipMemcpyAsync(host, d_choice, choice_dev_size(), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    plan_free(ctx, pl);
+    if (out) {
+        memset(out, 0, sizeof *out);
+        choice_dev_unpack(host, &out->i_best, &out->j_best, &out->F_best, &out->F_min, &out->j_psl,
+                          &out->psl_min, &out->psl_k, &out->flags);
     }
     return PSL_OK;
 }

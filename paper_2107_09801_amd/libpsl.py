@@ -23,7 +23,7 @@ CHOICE_AMBIGUOUS_ARGMIN = 1
 L_MAX = 1048575
 
 EXPORTS = ["psl_ctx_create", "psl_ctx_destroy", "psl_last_error", "psl_sync", "psl_init_walks",
-           "psl_free_walks", "psl_eval_neighbourhood", "psl_apply_flip", "psl_step_batch",
+           "psl_free_walks", "psl_eval_neighbourhood", "psl_eval_neighbourhood_noalloc", "psl_apply_flip", "psl_step_batch",
            "psl_read_walk", "psl_eval_shape", "psl_version", "psl_timing_enable",
            "psl_timing_read", "psl_set_option", "psl_serve_start", "psl_serve_submit",
            "psl_serve_poll", "psl_serve_stats_read", "psl_serve_stop", "psl_serve_footprint",
@@ -153,6 +153,7 @@ def lib() -> ctypes.CDLL:
         "psl_init_walks": (i32, [P, ctypes.POINTER(WalkCfg), u32, P, P]),
         "psl_free_walks": (i32, [P, P, u32]),
         "psl_eval_neighbourhood": (i32, [P, u32, u32, u32, P, P, ctypes.POINTER(Choice)]),
+        "psl_eval_neighbourhood_noalloc": (i32, [P, u32, u32, u32, P, P, ctypes.POINTER(Choice)]),
         "psl_apply_flip": (i32, [P, u32, u32]),
         "psl_step_batch": (i32, [P, P, u32, u32, u32]),
         "psl_read_walk": (i32, [P, u32, ctypes.POINTER(WalkState), P, P, P, P]),
@@ -276,6 +277,16 @@ class Context:
             assert psl_out.is_cuda and psl_out.dtype.itemsize == 4 and psl_out.numel() >= n_lmt
         self._check(lib().psl_eval_neighbourhood(self._h, walk, start, n_lmt, fp, pp,
                                                  ctypes.byref(ch)))
+        return ch.as_dict()
+
+    def eval_neighbourhood_noalloc(self, walk: int, start: int, n_lmt: int, F_out, psl_out):
+        """psl_eval_neighbourhood_noalloc: F_out / psl_out are required torch
+        device tensors (float64 / int32, at least n_lmt entries)."""
+        assert F_out.is_cuda and F_out.dtype.itemsize == 8 and F_out.numel() >= n_lmt
+        assert psl_out.is_cuda and psl_out.dtype.itemsize == 4 and psl_out.numel() >= n_lmt
+        ch = Choice()
+        self._check(lib().psl_eval_neighbourhood_noalloc(self._h, walk, start, n_lmt, F_out.data_ptr(),
+                                                         psl_out.data_ptr(), ctypes.byref(ch)))
         return ch.as_dict()
 
     def apply_flip(self, walk: int, j: int):

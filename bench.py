@@ -31,6 +31,13 @@ if ROOT not in sys.path:
 # MI355X: 256 CUs x 64 lanes x 2.4 GHz of 32-bit / non-packed FP64 VALU issue
 # (each CU issues one 64-lane VALU instruction per clock: 4 SIMDs, 4 clocks each).
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
+# MI355X dense int8 matrix-core peak (v_mfma_i32_*_i8), ops/s (a multiply-add is 2).
+PEAK_INT8_OPS = 5.0e15
+# int8 ops of the split path's linear part per (element, neighbour) term: one
+# multiply-add per digit of the quantized coefficient (8 digits).
+LIN_OPS_PER_TERM = 2 * 8
+# Shortest walk the split evaluation takes.
+SPLIT_MIN_L = 2048
 # VALU lane-ops per C_k-update of the direct form of the one-element flip: form
 # C' (1), fold |C'| into the running max (1), select T(|C'|) (1), one FP64 add
 # (1). The evaluation kernel needs fewer (it skips the unchanged shifts and
@@ -47,7 +54,7 @@ PAPER_A100_NSE = {16383: 4678451, 32767: 2577101, 65535: 1258873, 131071: 638043
 # Sources that define the evaluation kernel: a counter record is valid only for
 # the exact text it was taken from.
 KERNEL_SOURCES = ("paper_2107_09801_amd/csrc/psl_eval.hip", "paper_2107_09801_amd/csrc/psl_dev_util.h",
-                  "paper_2107_09801_amd/csrc/psl_device.h")
+                  "paper_2107_09801_amd/csrc/psl_device.h", "paper_2107_09801_amd/csrc/psl_split.hip")
 
 
 def kernel_source_digest() -> str:
@@ -58,11 +65,11 @@ def kernel_source_digest() -> str:
     return h.hexdigest()
 
 
-def counter_record(kind: str, tag: str):
+def counter_record(kind: str, tag: str, kernel: str = ""):
     """The `<kind>-record:` line of a committed rocprofv3 counter summary under
-    profiles/ for workload `tag` (a dict of its key=value fields), or None when
-    there is none or the evaluation kernel's sources changed since it was
-    taken."""
+    profiles/ for workload `tag` (and kernel name prefix `kernel`, if given),
+    as a dict of its key=value fields, or None when there is none or the
+    evaluation kernels' sources changed since it was taken."""
     pdir = os.path.join(ROOT, "profiles")
     if not os.path.isdir(pdir):
         return None
@@ -74,24 +81,26 @@ def counter_record(kind: str, tag: str):
                 if not line.startswith(f"{kind}-record:"):
                     continue
                 kv = dict(t.split("=", 1) for t in line.split()[1:] if "=" in t)
-                if kv.get("workload") == tag and kv.get("source_sha256") == digest:
+                if kv.get("workload") == tag and kv.get("source_sha256") == digest and \
+                        kv.get("kernel", "").startswith(kernel):
                     return kv
     return None
 
 
-def measured_traffic(tag: str):
-    """HBM bytes per launch of the evaluation kernel for workload `tag`, from the
-    `traffic-record:` line (FETCH_SIZE and WRITE_SIZE, each scaled by what the
-    counter reads for a copy of known size)."""
-    kv = counter_record("traffic", tag)
+def measured_traffic(tag: str, kernel: str = ""):
+    """HBM bytes per launch of an evaluation kernel (k_eval or k_lin; any when
+    empty) for workload `tag`, from the `traffic-record:` line (FETCH_SIZE and
+    WRITE_SIZE, each scaled by what the counter reads for a copy of known
+    size)."""
+    kv = counter_record("traffic", tag, kernel)
     return None if kv is None else int(kv["fetch_bytes_per_launch"]) + int(kv["write_bytes_per_launch"])
 
 
-def measured_valu(tag: str):
+def measured_valu(tag: str, kernel: str = "k_eval"):
     """VALU instructions (64-lane wavefront instructions, SQ_INSTS_VALU) per
     launch of the evaluation kernel for workload `tag`, from the
     `valu-record:` line."""
-    kv = counter_record("valu", tag)
+    kv = counter_record("valu", tag, kernel)
     return None if kv is None else float(kv["sq_insts_valu_per_launch"])
 
 
@@ -114,6 +123,9 @@ def parse():
     ap.add_argument("--graph", action="store_true", help="replay a captured step per step")
     ap.add_argument("--autotune", action="store_true",
                     help="time every evaluation launch shape on the batch first and keep the fastest")
+    ap.add_argument("--split", type=int, default=-1, choices=[-1, 0, 1],
+                    help="split evaluation (linear part on the matrix cores): -1 the library default "
+                         "(on where it applies), 0 off (table evaluation), 1 on")
     ap.add_argument("--eval-items", type=int, default=0,
                     help="minimum work items per evaluation launch (0 = the library default)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -550,6 +562,8 @@ def main():
     ctx = libpsl.Context(0)
     if args.eval_items:
         ctx.set_option(libpsl.OPT_EVAL_ITEMS, args.eval_items)
+    if args.split >= 0:
+        ctx.set_option(libpsl.OPT_SPLIT, args.split)
     ids, evals_per_step, updates_per_step = [], 0, 0
     for L, count in groups:
         a2 = 10 if wl == "paper" else si.alpha2_for(L)
@@ -623,19 +637,40 @@ def main():
         log(f"whole run: {BATCHED_STEPS} steps in {total_s:.3f} s")
 
     value = evals_per_step * args.steps / el
-    eval_avg_s = tm["eval_ms"] / max(1, tm["eval_launches"]) / 1e3
-    tag = f"{wl}_L{'-'.join(str(g[0]) for g in groups)}_w{nw}"
+    launches = max(1, tm["eval_launches"])
+    eval_avg_s = tm["eval_ms"] / launches / 1e3
+    lin_avg_s = tm["lin_ms"] / launches / 1e3
+    prep_avg_s = tm["prep_ms"] / launches / 1e3
+    split_on = args.split != 0 and any(g[0] >= SPLIT_MIN_L for g in groups)
+    tag = f"{wl}_L{'-'.join(str(g[0]) for g in groups)}_w{nw}" + ("" if split_on else "_table")
     valu = measured_valu(tag)
     if valu is not None:
-        roofline = {"bound": "alu", "achieved": valu * 64 / eval_avg_s / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                    "unit": "Tlane-op/s", "frac": valu * 64 / eval_avg_s / PEAK_LANE_OPS,
-                    "traffic": measured_traffic(tag), "traffic_unit": "B/launch",
-                    "basis": "VALU lane-ops per launch (SQ_INSTS_VALU x 64, the valu-record of the "
-                             "kernel's committed counter profile) / the launch time measured here"}
+        roof_eval = {"kernel": "k_eval", "bound": "alu", "achieved": valu * 64 / eval_avg_s / 1e12,
+                     "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-op/s",
+                     "frac": valu * 64 / eval_avg_s / PEAK_LANE_OPS,
+                     "traffic": measured_traffic(tag, "k_eval"), "traffic_unit": "B/launch",
+                     "basis": "VALU lane-ops per launch (SQ_INSTS_VALU x 64, the valu-record of the "
+                              "kernel's committed counter profile) / the launch time measured here"}
     else:
-        roofline = {"bound": "alu", "achieved": None, "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-op/s",
-                    "frac": None, "traffic": measured_traffic(tag), "traffic_unit": "B/launch",
-                    "basis": "no SQ_INSTS_VALU record for these kernel sources and this workload"}
+        roof_eval = {"kernel": "k_eval", "bound": "alu", "achieved": None, "peak": PEAK_LANE_OPS / 1e12,
+                     "unit": "Tlane-op/s", "frac": None, "traffic": measured_traffic(tag, "k_eval"),
+                     "traffic_unit": "B/launch",
+                     "basis": "no SQ_INSTS_VALU record for these kernel sources and this workload"}
+    roof_lin = None
+    if split_on and lin_avg_s > 0:
+        # algorithmic int8 ops of one launch: every (element, neighbour) term
+        # of the evaluated elements of the split walks, 8 digit products each
+        terms = sum(count * min(L_, args.n_lmt or L_) * (L_ - 1) for L_, count in groups if L_ >= SPLIT_MIN_L)
+        if wl == "paper":
+            terms = sum(count * min(L_, 6912) * (L_ - 1) for L_, count in groups if L_ >= SPLIT_MIN_L)
+        ops = LIN_OPS_PER_TERM * terms
+        roof_lin = {"kernel": "k_lin", "bound": "mfma", "achieved": ops / lin_avg_s / 1e12,
+                    "peak": PEAK_INT8_OPS / 1e12, "unit": "TOP/s", "frac": ops / lin_avg_s / PEAK_INT8_OPS,
+                    "traffic": measured_traffic(tag, "k_lin"), "traffic_unit": "B/launch",
+                    "ops_per_launch": ops,
+                    "basis": "16 int8 ops (8 digit multiply-adds) per (element, neighbour) term of the "
+                             "linear part / the launch time measured here, against the dense int8 peak"}
+    roofline = roof_eval if roof_lin is None or eval_avg_s >= lin_avg_s else roof_lin
     direct = OPS_PER_UPDATE_DIRECT * updates_per_step / eval_avg_s
     tiles, ks = ctx.eval_shape(L, n_lmt, nw)
     names = {"batched": "batched uniform", "single": "single walk", "large": "large single instance",
@@ -667,8 +702,11 @@ def main():
         "C_k_updates_explicit": explicit_updates(groups, wl, args.n_lmt, updates_per_step, args.steps, el),
         "eval_kernel": {"avg_ms": eval_avg_s * 1e3, "launches": tm["eval_launches"],
                         "updates_per_s": updates_per_step / eval_avg_s,
+                        "split": split_on,
+                        "split_prep_avg_ms": prep_avg_s * 1e3, "lin_avg_ms": lin_avg_s * 1e3,
                         "rest_of_step_avg_ms": tm["rest_ms"] / max(1, tm["steps"])},
         "roofline": roofline,
+        "roofline_by_kernel": [r for r in (roof_eval, roof_lin) if r is not None],
         "vs_direct_form": {"direct_lane_ops_per_update": OPS_PER_UPDATE_DIRECT,
                            "nominal_updates_per_s": updates_per_step / eval_avg_s,
                            "ceiling_updates_per_s": PEAK_LANE_OPS / OPS_PER_UPDATE_DIRECT,

@@ -316,6 +316,8 @@ typedef struct {
     uint64_t eval_launches;
     double   rest_ms;        /* total time of the rest of each step               */
     uint64_t steps;
+    double   prep_ms;        /* split evaluation: its per-step preparation        */
+    double   lin_ms;         /* split evaluation: the matrix-core linear sums     */
 } psl_timing;
 
 /* on != 0: start recording (counters reset); on == 0: stop. */
@@ -380,6 +382,16 @@ PSL_API psl_status psl_tune_load(psl_ctx *ctx, const char *path);
  * relative, and of an exact summation). Only the flags change: the moves are
  * the band rule's whatever the margin. Errors: PSL_E_INVAL outside the range. */
 #define PSL_OPT_AMBIG_MARGIN 3
+/* PSL_OPT_SPLIT: 1 (default; -1 restores it): batches and evaluations take the
+ * split evaluation for walks of L >= 2048 whenever a step allows it (the
+ * near-peak list holds the PSL and the quantization bound of the linear part
+ * is below 1e-14 of every neighbour's F): the linear part of F_j (Eq. (5)
+ * expanded exactly in the +-1 neighbours of Section 3's one-element flip)
+ * as exact integer sums on the matrix cores, the both-neighbour remainder on
+ * the vector units; 0: every step takes the table evaluation. Moves and PSL
+ * are the same either way (F agrees to about 1e-14 relative); errors:
+ * PSL_E_INVAL outside -1..1. */
+#define PSL_OPT_SPLIT 4
 PSL_API psl_status psl_set_option(psl_ctx *ctx, int option, int64_t value);
 
 /* --------------------------------------------------- trace, checkpoint */

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT_DIR = os.path.join(PKG, "_build")
 LIB = os.path.join(OUT_DIR, "libpsl.so")
-SOURCES = ["psl_runtime.hip", "psl_serve.hip", "psl_kernels.hip", "psl_eval.hip"]
+SOURCES = ["psl_runtime.hip", "psl_serve.hip", "psl_kernels.hip", "psl_eval.hip", "psl_split.hip"]
 ARCH = "gfx950"
 
 

@@ -103,4 +103,35 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t nb)
     return x * q + (x < r ? x : r) + local;
 }
 
+// (walk, segment) of block i of an O(L) pass.
+__device__ __forceinline__ void seg_of(const SegMap &m, uint32_t i, uint32_t &b, uint32_t &seg)
+{
+    if (!m.off) {
+        b = i / m.spw;
+        seg = i - b * m.spw;
+        return;
+    }
+    uint32_t lo = 0, hi = m.nb - 1;      // the largest b with off[b] <= i
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (m.off[mid] <= i) lo = mid;
+        else                 hi = mid - 1;
+    }
+    b = lo;
+    seg = i - m.off[lo];
+}
+
+
+// The last both-neighbour shift of the aligned 64-element block holding j:
+// min over j' of the block of min(j', L-1-j') (a tent function, so the
+// minimum over an interval is at one of its ends). A 32-shift chunk
+// 1+32c .. 32+32c is "covered" for the block when it ends at or below this
+// bound; the linear items then use B_k for it instead of B'_k (psl_split.hip
+// makes the same choice per block and chunk).
+__device__ __forceinline__ int split_block_bound(int j, int L)
+{
+    const int j0 = j & ~63, j1 = min(j0 + 63, L - 1);
+    return min(min(j0, L - 1 - j0), min(j1, L - 1 - j1));
+}
+
 }  // namespace psl

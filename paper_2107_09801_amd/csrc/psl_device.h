@@ -101,6 +101,31 @@ struct BatchEntry {
     uint32_t start;         // start, when fixed by the caller
     uint32_t fixed;         // 1: start and n_lmt come from this entry
     uint32_t near_lim;      // largest near-peak list handled sparsely
+    uint32_t lsplit;        // split path: k-splits of the linear items (0: no split path)
+    // split path (psl_split.hip): this step's coefficients of the walk
+    int8_t *limbs;          // [2][kLimbs][split_row(L)]: digits of B'_k (set 0) and B_k (set 1), shift k at k-1
+    double *dq;             // [L][2]: D_k and B_k - B'_k
+    double *pre;            // [3][L]: prefix sums over 1..k of A_k, A'_k, T(|C_k|); entry 0 is 0
+    struct SplitState *ss;  // scale and path choice of this step
+    double *lpart;          // [lsplit][L]: partial linear sums (in units of the scale), by element
+};
+
+// Split evaluation: T(|C_k + 2a + 2b|) = A + B(a + b) + D ab (both neighbours),
+// T(|C_k + 2a|) = A' + B' a (one neighbour); the linear parts go to the
+// matrix cores as exact integers (B' and B quantized to multiples of U, kLimbs
+// signed byte digits), the rest to the VALU and to prefix sums.
+constexpr int kLimbs = 8;
+// Linear items: blocks of kLinBlockElems elements, kLinWaveElems per
+// wavefront; a padding item has walk kLinNoWalk.
+constexpr int kLinBlockElems = 4096;
+// Digits per (set, limb) row: the 32-shift chunks of k = 1..L-1 and one more
+// chunk of zeros (entries past L-1 are zero too).
+__host__ __device__ constexpr uint32_t split_row(uint32_t L) { return 32u * ((L - 1 + 31) / 32 + 1); }
+constexpr int kLinWaveElems = 1024;
+constexpr uint32_t kLinNoWalk = 0xFFFFFFFFu;
+struct SplitState {
+    double U;               // the quantum, a power of two
+    uint32_t use;           // 1: this step evaluates the walk on the split path
     uint32_t pad;
 };
 
@@ -144,12 +169,16 @@ struct EvalItem {
     uint32_t pad;
 };
 
+// XCDs of the MI355X (32 CUs and one L2 each); workgroup i of a launch runs
+// on XCD i mod kXcds.
+constexpr int kXcds = 8;
+
 // Per-XCD work queues of the persistent evaluation: queue x holds the items
 // base[x] .. base[x]+count[x]-1; next[x] is its cursor (reset per launch).
 struct EvalQueues {
-    uint32_t base[8];
-    uint32_t count[8];
-    uint32_t next[8];
+    uint32_t base[kXcds];
+    uint32_t count[kXcds];
+    uint32_t next[kXcds];
 };
 
 // Launch shape of the evaluation kernel.

@@ -289,6 +289,138 @@ __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const 
     }
 }
 
+// The VALU part of the split evaluation for one item: over the shifts where
+// both neighbours of j exist (k <= min(j, L-1-j)), sum D_k ab, plus
+// (B_k - B'_k)(a + b) in the chunks the linear items took with B'_k (the
+// ones not covered for j's block); every other part of F_j comes from the
+// prefix sums and the linear items. Per 256-shift tile the block stages D_k
+// and B_k - B'_k and builds, per quad of shifts, the 16 sums
+// sum_i D_{k+i} (1 - 2 y_i) indexed by the quad's bits y = xr XOR xl (ab is
+// +1 where the two neighbours are equal, -1 where they differ). A window
+// covered for every lane of the wavefront takes eight table reads; windows
+// on the edges of the region go shift by shift.
+template <int WAVES>
+__device__ __forceinline__ void eval_sweep_split(EvalLds &sh, const WalkDev &w, const BatchEntry &be, int j,
+                                                 uint32_t sjbit, int k_lo, int k_hi, int tid, double &sum,
+                                                 double &comp)
+{
+    const int L = (int)w.L;
+    const uint32_t *__restrict__ w32 = reinterpret_cast<const uint32_t *>(w.pivot);
+    double *__restrict__ sdq = sh.rows;       // [kTileK][2]: D_k, B_k - B'_k
+    double *__restrict__ std_ = sh.both;      // [kChunks][8 quads][16]
+    const int lane = tid & 63, wave = tid >> 6;
+    const int jl = j, jr = L - 1 - j;
+    const int m_j = min(jl, jr);
+    const int mJ = split_block_bound(j, L);
+    // shifts past every lane's m_j hold no VALU work; the windows end at the
+    // chunk that holds the wavefront's largest m_j
+    const int m_w = wave_max(m_j, lane);
+    const int k_wend = min(k_hi, 1 + 32 * ((m_w + 31) / 32));
+    if (lane == 0) sh.kend[wave] = k_wend;
+    __syncthreads();
+    int k_bend = sh.kend[0];
+    for (int x = 1; x < WAVES; ++x) k_bend = max(k_bend, sh.kend[x]);
+
+    // bit windows and their LDS staging as in eval_sweep
+    const uint32_t sh_r = (uint32_t)(j + 1) & 31u;
+    const uint32_t sh_l = (uint32_t)j & 31u;
+    const int j_first = __builtin_amdgcn_readlane(j, 0);
+    const int grp = j < j_first ? 1 : 0;
+    constexpr int kNone = 1 << 30;
+    const int jmn0 = wave_min(grp ? kNone : j, lane), jmx0 = wave_max(grp ? -kNone : j, lane);
+    const int jmn1 = wave_min(grp ? j : kNone, lane), jmx1 = wave_max(grp ? j : -kNone, lane);
+    const int jmn = grp ? jmn1 : jmn0, jmx = grp ? jmx1 : jmx0;
+    const uint32_t *rbits = sh.bits + 64 * wave + 32 * grp + (((j + 1) >> 5) - ((jmn + 1) >> 5));
+    const uint32_t *lbits = sh.bits + 64 * wave + 32 * grp + 16 + ((jmx >> 5) - (j >> 5));
+    const int s_grp = lane >> 5, s_side = (lane >> 4) & 1, s_idx = lane & 15;
+    const int s_mn = s_grp ? jmn1 : jmn0, s_mx = s_grp ? jmx1 : jmx0;
+    const int s_span = s_side ? (s_mx >> 5) - (s_mn >> 5) : ((s_mx + 1) >> 5) - ((s_mn + 1) >> 5);
+
+    for (int kt = k_lo; kt < k_bend; kt += kTileK) {
+        const int kt_end = min(k_bend, kt + kTileK);
+        const int nt = kt_end - kt;
+        __syncthreads();
+        {
+            const int cb = (kt - 1) >> 5;
+            const int cc_last = kt < k_wend ? min(kChunks - 1, (k_wend - 1 - kt) >> 5) : -1;
+            if (s_mn <= s_mx && s_idx < s_span + cc_last + 2) {
+                const int word = s_side ? (s_mx >> 5) - cb - s_idx : ((s_mn + 1) >> 5) + cb + s_idx;
+                sh.bits[64 * wave + lane] = w32[word];
+            }
+        }
+        for (int t = tid; t < nt; t += 64 * WAVES) {
+            const size_t k = (size_t)(kt + t);
+            sdq[2 * t] = be.dq[2 * k];
+            sdq[2 * t + 1] = be.dq[2 * k + 1];
+        }
+        __syncthreads();
+        // D tables of the tile's whole quads: entry y of quad q is
+        // sum_i D_{k+i} (1 - 2 y_i), the four terms added in order i = 0..3
+        for (int e = tid; e < kChunks * kOneWin; e += 64 * WAVES) {
+            const int t0 = 4 * (e >> 4), y = e & 15;
+            if (t0 + 3 < nt) {
+                double v = 0.0;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const double d = sdq[2 * (t0 + i)];
+                    v += (y >> i) & 1 ? -d : d;
+                }
+                std_[e] = v;
+            }
+        }
+        __syncthreads();
+
+        double acc = 0.0;
+        uint32_t r0 = rbits[0], r1 = rbits[1], l0 = lbits[0], l1 = lbits[1];
+#pragma unroll
+        for (int cc = 0; cc < kChunks; ++cc) {
+            const int k0 = kt + 32 * cc;
+            const uint32_t cr0 = r0, cr1 = r1, cl0 = l0, cl1 = l1;
+            if (cc + 1 < kChunks) {
+                r0 = rbits[cc + 1];
+                r1 = rbits[cc + 2];
+                l0 = lbits[cc + 1];
+                l1 = lbits[cc + 2];
+            }
+            if (k0 < k_wend) {
+                // element bits of the two neighbours over the window: bit t
+                // of XR is s_{j+k0+t} < 0, of XL is s_{j-k0-t} < 0
+                const uint32_t XR = __builtin_amdgcn_alignbit(cr1, cr0, sh_r);
+                const uint32_t XL = __builtin_bitreverse32(__builtin_amdgcn_alignbit(cl0, cl1, sh_l));
+                const uint32_t Y = XR ^ XL;
+                const int tcount = min(32, kt_end - k0);
+                const bool cov = k0 + 31 <= mJ;         // this lane's block took B_k for the chunk
+                if (tcount == 32 && __all(cov)) {
+                    const double *tp = std_ + kOneWin * cc;
+                    double v[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) v[q] = tp[16 * q + ((Y >> (4 * q)) & 15u)];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) acc += v[q];
+                } else {
+                    const double *dp = sdq + 2 * (32 * cc);
+                    for (int t = 0; t < tcount; ++t) {
+                        if (k0 + t > m_j) break;
+                        const uint32_t xr = (XR >> t) & 1u, xl = (XL >> t) & 1u;
+                        const double d = dp[2 * t];
+                        double v = (xr ^ xl) ? -d : d;
+                        if (!cov) {
+                            // (B - B')(a + b): a = -s_j s_{j+k} is +1 where the
+                            // bits of j and j+k differ, so a + b = 2 (xr' + xl') - 2
+                            // with xr' = xr XOR sjbit, xl' = xl XOR sjbit
+                            const double db = dp[2 * t + 1];
+                            const int na = (int)(xr ^ sjbit) + (int)(xl ^ sjbit);
+                            v += db * (double)(2 * na - 2);
+                        }
+                        acc += v;
+                    }
+                }
+            }
+        }
+        nsum_add(sum, comp, acc);
+    }
+}
+
 // Neighborhood of Algorithm 1 for one (walk, 64*WAVES candidates, k-range) item.
 //
 // Per 256-shift tile the block stages (i) per shift the five values
@@ -337,10 +469,17 @@ __device__ __forceinline__ void eval_item(EvalLds &sh, const WalkDev *__restrict
     double sum = 0.0, comp = 0.0;
     uint32_t mx = 0;
     const uint32_t n_near = be.near[0];
-    if (n_near > be.near_lim) {
+    // the split path (psl_split.hip) chose this walk for this step: the VALU
+    // takes only the both-neighbour terms it leaves (its choice implies the
+    // sparse PSL form)
+    const bool split = be.lsplit != 0 && be.ss->use != 0;
+    if (!split && n_near > be.near_lim) {
         eval_sweep<WAVES, true>(sh, w, be, it, T, n_lmt, j, SJ, k_lo, k_hi, tid, sum, comp, mx);
     } else {
-        eval_sweep<WAVES, false>(sh, w, be, it, T, n_lmt, j, SJ, k_lo, k_hi, tid, sum, comp, mx);
+        if (split)
+            eval_sweep_split<WAVES>(sh, w, be, j, sjbit, k_lo, k_hi, tid, sum, comp);
+        else
+            eval_sweep<WAVES, false>(sh, w, be, it, T, n_lmt, j, SJ, k_lo, k_hi, tid, sum, comp, mx);
         {
             // PSL over the near-peak shifts, every candidate, all bounds
             // cases; split s takes entries s, s + ksplit, ... (the combine

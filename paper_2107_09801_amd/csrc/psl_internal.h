@@ -110,6 +110,13 @@ struct BatchPlan {
     double *d_segtot = nullptr;       // per segment: chunk-sum total (suffix pass)
     uint32_t *d_segmax = nullptr;     // per segment: maximum |C_k|
     SegMap seg{};
+    // split evaluation (walks with BatchEntry.lsplit > 0)
+    bool split = false;               // some walk of the plan can take the split path
+    int8_t *d_limbs = nullptr;
+    double *d_dq = nullptr, *d_pre = nullptr, *d_lpart = nullptr;
+    SplitState *d_ss = nullptr;
+    EvalItem *d_litems = nullptr;     // linear items
+    uint32_t n_litems = 0;
 };
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -118,6 +125,9 @@ constexpr size_t kPlanCache = 8;   // step batches whose layout (and graph) is k
 constexpr uint32_t kEvalItemsDefault = 4096;    // PSL_OPT_EVAL_ITEMS default
 constexpr uint32_t kEvalItemsMax = 1u << 18;    // and its largest value
 constexpr int64_t kAmbigMarginMax = 1000000000000000ll;  // PSL_OPT_AMBIG_MARGIN: 1.0 in units of 1e-15
+constexpr uint32_t kSplitMinL = 2048;          // shortest walk the split evaluation takes
+constexpr uint32_t kLinItemsTarget = 1024;     // linear items per launch the k-splits aim for
+constexpr uint32_t kLinMinChunks = 64;         // fewest shift chunks per k-split of a linear item
 
 
 struct Server;   // serving loop (psl_serve.hip)
@@ -146,6 +156,7 @@ struct psl_ctx {
     int64_t near_limit = -1;          // PSL_OPT_NEAR_LIMIT
     uint32_t eval_items = psl_rt::kEvalItemsDefault;  // PSL_OPT_EVAL_ITEMS
     double amb_margin = psl::kAmbigMarginDefault;     // PSL_OPT_AMBIG_MARGIN (relative)
+    int split_mode = 1;               // PSL_OPT_SPLIT: 1 split evaluation where it applies, 0 never
     void *noalloc_scratch = nullptr;  // this device's fixed scratch (psl_eval_neighbourhood_noalloc)
     std::string noalloc_err;          // why it is missing, if it is
     psl_rt::Server *server = nullptr; // serving loop, when started
@@ -154,8 +165,8 @@ struct psl_ctx {
     std::map<uint32_t, uint32_t> tuned_items;  // autotuned work-item targets by tune_key
     // timing
     bool timing = false;
-    std::vector<hipEvent_t> ev;       // 3 per recorded step: eval start, eval end, step end
-    double eval_ms = 0.0, rest_ms = 0.0;
+    std::vector<hipEvent_t> ev;       // 5 per recorded step (see timing_collect)
+    double eval_ms = 0.0, rest_ms = 0.0, prep_ms = 0.0, lin_ms = 0.0;
     uint64_t eval_launches = 0, steps_timed = 0;
 };
 

@@ -262,24 +262,6 @@ __global__ __launch_bounds__(kFitThreads) void k_fitness(WalkDev *walks, const B
 // alpha); mode 2: at init (every walk).
 constexpr int kChunkThreads = 256;
 constexpr uint32_t kMaxGridY = 65535;      // walks per launch of the 2-D grids
-// (walk, segment) of block i of an O(L) pass.
-__device__ __forceinline__ void seg_of(const SegMap &m, uint32_t i, uint32_t &b, uint32_t &seg)
-{
-    if (!m.off) {
-        b = i / m.spw;
-        seg = i - b * m.spw;
-        return;
-    }
-    uint32_t lo = 0, hi = m.nb - 1;      // the largest b with off[b] <= i
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi + 1) >> 1;
-        if (m.off[mid] <= i) lo = mid;
-        else                 hi = mid - 1;
-    }
-    b = lo;
-    seg = i - m.off[lo];
-}
-
 // Chunk pairs p0, p0 + step, ... below p1 of one walk, for the calling
 // wavefront (a pair is 64 consecutive shifts, two chunks).
 __device__ __forceinline__ void chunk_pairs(const BatchEntry &be, const WalkDev &w, const double *T, int cut,
@@ -751,6 +733,12 @@ __global__ __launch_bounds__(kCombThreads) void k_combine(WalkDev *walks, const 
     const double *T = tabs.T[w.alpha];
     const uint32_t g = threadIdx.x & (uint32_t)(G - 1);
     const uint32_t cpb = kCombThreads / (uint32_t)G;      // candidates per block pass
+    // split path: the partials hold the VALU terms only; the prefix sums and
+    // the linear sums (psl_split.hip) supply the rest of F_j
+    const bool split = be.lsplit != 0 && be.ss->use != 0;
+    const double U = split ? be.ss->U : 0.0;
+    const uint32_t start = be.fixed ? be.start : step_start(w);
+    const uint32_t L = w.L;
 
     double fmin = INFINITY;
     int32_t pmin = INT_MAX;
@@ -793,6 +781,18 @@ __global__ __launch_bounds__(kCombThreads) void k_combine(WalkDev *walks, const 
             // high word of T(PSL), which is at least hi32(T(1)) = 0x3FF00000
             // because |C'_{L-1}| = 1 for every sequence
             const int32_t p = m < 0x3FF00000u ? (int32_t)m : table_inverse(T, tabs.n, m);
+            if (split) {
+                // F_j = sum_{k<=m} A_k + sum_{m<k<=M} A'_k + sum_{k>M} T(|C_k|)
+                //       - s_j U (linear sums) + the VALU terms, m = min(j, L-1-j)
+                const uint32_t j = (uint32_t)(((uint64_t)start + 1u + i) % L);
+                const uint32_t mj = min(j, L - 1 - j), Mj = max(j, L - 1 - j);
+                const double *pa = be.pre, *pa1 = be.pre + L, *pt = be.pre + 2 * (size_t)L;
+                const double cst = pa[mj] + (pa1[Mj] - pa1[mj]) + (pt[L - 1] - pt[Mj]);
+                double lin = 0.0;
+                for (uint32_t x = 0; x < be.lsplit; ++x) lin += be.lpart[(size_t)x * L + j];
+                const double sgn = get_bit(w.pivot, j) ? U : -U;     // -s_j U
+                f = cst + sgn * lin + f;
+            }
             be.F[i] = f;
             be.P[i] = p;
             fmin = f < fmin ? f : fmin;

@@ -42,4 +42,13 @@ hipError_t launch_apply(WalkDev *walks, const BatchEntry *batch, const SegMap &m
 hipError_t launch_flip_bit(WalkDev *walks, const BatchEntry *batch, uint32_t j, hipStream_t s);
 hipError_t launch_bookkeep(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t *pend, hipStream_t s);
 
+// Split evaluation (psl_split.hip): the step's coefficients, digits, prefix
+// sums, scale and path choice of the batch's split walks (after the suffix
+// pass, before the evaluation), and the matrix-core linear sums (items:
+// walk, 512-element block, k-split).
+hipError_t launch_split_prep(const WalkDev *walks, const BatchEntry *batch, uint32_t nb, const Tables &tabs,
+                             const SegMap &map, hipStream_t s);
+hipError_t launch_lin(const WalkDev *walks, const BatchEntry *batch, const EvalItem *items, uint32_t n_items,
+                      hipStream_t s);
+
 }  // namespace psl

@@ -86,12 +86,18 @@ void timing_drop(psl_ctx *ctx)
 // Folds recorded events into the totals (the stream must be idle).
 psl_status timing_collect(psl_ctx *ctx)
 {
-    for (size_t i = 0; i + 2 < ctx->ev.size(); i += 3) {
-        float a = 0.f, b = 0.f;
+    // five events per step: evaluation start, after the split preparation,
+    // after the evaluation kernel, after the linear sums, step end
+    for (size_t i = 0; i + 4 < ctx->ev.size(); i += 5) {
+        float a = 0.f, b = 0.f, c = 0.f, d = 0.f;
         HIP_TRY(ctx, hipEventElapsedTime(&a, ctx->ev[i], ctx->ev[i + 1]));
         HIP_TRY(ctx, hipEventElapsedTime(&b, ctx->ev[i + 1], ctx->ev[i + 2]));
-        ctx->eval_ms += a;
-        ctx->rest_ms += b;
+        HIP_TRY(ctx, hipEventElapsedTime(&c, ctx->ev[i + 2], ctx->ev[i + 3]));
+        HIP_TRY(ctx, hipEventElapsedTime(&d, ctx->ev[i + 3], ctx->ev[i + 4]));
+        ctx->prep_ms += a;
+        ctx->eval_ms += b;
+        ctx->lin_ms += c;
+        ctx->rest_ms += d;
         ctx->eval_launches += 1;
         ctx->steps_timed += 1;
     }
@@ -131,6 +137,12 @@ void plan_free(psl_ctx *ctx, BatchPlan &pl)
     dev_free(ctx, pl.d_segmax, false);
     dev_free(ctx, pl.d_near, false);
     dev_free(ctx, pl.d_queues, false);
+    dev_free(ctx, pl.d_limbs, false);
+    dev_free(ctx, pl.d_dq, false);
+    dev_free(ctx, pl.d_pre, false);
+    dev_free(ctx, pl.d_lpart, false);
+    dev_free(ctx, pl.d_ss, false);
+    dev_free(ctx, pl.d_litems, false);
     pl = BatchPlan();
 }
 
@@ -493,8 +505,76 @@ psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t 
         pl.seg.tot = pl.d_segtot;
         pl.seg.tmax = pl.d_segmax;
     }
+    // split evaluation: per walk of at least kSplitMinL elements (not for
+    // plans carved from fixed scratch): its coefficient arrays, linear
+    // partials and linear items (walk, kLinBlockElems-element block,
+    // k-split). Workgroup i runs on XCD i mod 8: the walks are dealt to 8
+    // queues (most items first, each to the least loaded queue) and the
+    // launch order interleaves the queues, so a walk's items share one XCD's
+    // L2; short queues are padded with kLinNoWalk items.
+    std::vector<uint32_t> lsp(n, 0);
+    std::vector<EvalItem> litems;
+    size_t n_limb = 0, n_dq = 0, n_pre = 0, n_lp = 0;
+    if (!mem && ctx->split_mode) {
+        uint64_t blocks = 0;
+        std::vector<uint32_t> nq(n, 0);
+        for (uint32_t b = 0; b < n; ++b) {
+            if (Ls[b] < kSplitMinL) continue;
+            const uint32_t nblk = (Ls[b] + kLinBlockElems - 1) / kLinBlockElems;
+            nq[b] = std::min<uint32_t>(nblk, (n_l[b] + kLinBlockElems - 1) / kLinBlockElems + 1);
+            blocks += nq[b];
+        }
+        std::vector<uint32_t> order;
+        for (uint32_t b = 0; b < n; ++b) {
+            if (!nq[b]) continue;
+            const uint32_t nchunks = (Ls[b] - 1 + 31) / 32;
+            const uint64_t want = (kLinItemsTarget + blocks - 1) / std::max<uint64_t>(blocks, 1);
+            lsp[b] = (uint32_t)std::max<uint64_t>(
+                1, std::min<uint64_t>(want, std::max<uint32_t>(1, nchunks / kLinMinChunks)));
+            order.push_back(b);
+            n_limb += 2 * (size_t)kLimbs * split_row(Ls[b]);
+            n_dq += 2 * (size_t)Ls[b];
+            n_pre += 3 * (size_t)Ls[b];
+            n_lp += (size_t)lsp[b] * Ls[b];
+        }
+        std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+            return (uint64_t)nq[a] * lsp[a] > (uint64_t)nq[b] * lsp[b];
+        });
+        std::vector<EvalItem> xq[kXcds];
+        uint64_t load[kXcds] = {};
+        for (uint32_t b : order) {
+            const int x = (int)(std::min_element(load, load + kXcds) - load);
+            for (uint32_t q = 0; q < nq[b]; ++q)
+                for (uint32_t k = 0; k < lsp[b]; ++k) xq[x].push_back(EvalItem{b, q, k, 0});
+            load[x] += (uint64_t)nq[b] * lsp[b];
+        }
+        size_t rounds = 0;
+        for (int x = 0; x < kXcds; ++x) rounds = std::max(rounds, xq[x].size());
+        for (size_t r = 0; r < rounds; ++r)
+            for (int x = 0; x < kXcds; ++x)
+                litems.push_back(r < xq[x].size() ? xq[x][r] : EvalItem{kLinNoWalk, 0, 0, 0});
+    }
+    pl.split = !litems.empty();
+    if (pl.split) {
+        if ((st = get(&p, n_limb))) return st;
+        pl.d_limbs = (int8_t *)p;
+        if ((st = get(&p, sizeof(double) * n_dq))) return st;
+        pl.d_dq = (double *)p;
+        if ((st = get(&p, sizeof(double) * n_pre))) return st;
+        pl.d_pre = (double *)p;
+        if ((st = get(&p, sizeof(double) * n_lp))) return st;
+        pl.d_lpart = (double *)p;
+        if ((st = get(&p, sizeof(SplitState) * n))) return st;
+        pl.d_ss = (SplitState *)p;
+        if ((st = get(&p, sizeof(EvalItem) * litems.size()))) return st;
+        pl.d_litems = (EvalItem *)p;
+        pl.n_litems = (uint32_t)litems.size();
+        HIP_TRY(ctx, hipMemcpy(pl.d_litems, litems.data(), sizeof(EvalItem) * litems.size(),
+                               hipMemcpyHostToDevice));
+    }
     std::vector<BatchEntry> be(n);
     size_t op = 0, oc = 0, os = 0;
+    size_t o_limb = 0, o_dq = 0, o_pre = 0, o_lp = 0;
     for (uint32_t b = 0; b < n; ++b) {
         BatchEntry &e = be[b];
         memset(&e, 0, sizeof e);
@@ -514,6 +594,19 @@ psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t 
         e.start = fixed ? start_fixed : 0;
         e.near_lim = near_limit_for(ctx, ctx->walks[ids[b]].L);
         e.fixed = fixed ? 1 : 0;
+        if (lsp[b]) {
+            const size_t K = split_row(Ls[b]);
+            e.lsplit = lsp[b];
+            e.limbs = pl.d_limbs + o_limb;
+            e.dq = pl.d_dq + o_dq;
+            e.pre = pl.d_pre + o_pre;
+            e.lpart = pl.d_lpart + o_lp;
+            e.ss = pl.d_ss + b;
+            o_limb += 2 * (size_t)kLimbs * K;
+            o_dq += 2 * (size_t)Ls[b];
+            o_pre += 3 * (size_t)Ls[b];
+            o_lp += (size_t)lsp[b] * Ls[b];
+        }
         op += (size_t)ks[b] * n_l[b];
         oc += n_l[b];
     }
@@ -591,8 +684,12 @@ psl_status launch_step(psl_ctx *ctx, const BatchPlan &pl, const Tables &tabs, ui
     psl_status st;
     HIP_TRY(ctx, launch_suffix(ctx->d_walks, pl.d_batch, n, pl.max_L, tabs, 0, nullptr, &pl.seg, ctx->stream));
     if (timed && (st = timing_mark(ctx))) return st;
+    if (pl.split) HIP_TRY(ctx, launch_split_prep(ctx->d_walks, pl.d_batch, n, tabs, pl.seg, ctx->stream));
+    if (timed && (st = timing_mark(ctx))) return st;
     HIP_TRY(ctx, launch_eval(ctx->d_walks, pl.d_batch, pl.d_items, pl.n_items, tabs, pl.shape, pl.d_queues,
                              ctx->stream));
+    if (timed && (st = timing_mark(ctx))) return st;
+    if (pl.split) HIP_TRY(ctx, launch_lin(ctx->d_walks, pl.d_batch, pl.d_litems, pl.n_litems, ctx->stream));
     if (timed && (st = timing_mark(ctx))) return st;
     HIP_TRY(ctx, launch_select(ctx->d_walks, pl.d_batch, n, pl.comb_blocks, pl.comb_group, tabs, 0, nullptr,
                                pl.d_pend, ctx->stream));
@@ -881,8 +978,13 @@ psl_status psl_eval_neighbourhood(psl_ctx *ctx, uint32_t walk, uint32_t start, u
     const Tables tabs = tables_of(ctx);
     HIP_TRY(ctx, launch_suffix(ctx->d_walks, ctx->pure.d_batch, 1, h.L, tabs, 0, nullptr, &ctx->pure.seg,
                                ctx->stream));
+    if (ctx->pure.split)
+        HIP_TRY(ctx, launch_split_prep(ctx->d_walks, ctx->pure.d_batch, 1, tabs, ctx->pure.seg, ctx->stream));
     HIP_TRY(ctx, launch_eval(ctx->d_walks, ctx->pure.d_batch, ctx->pure.d_items, ctx->pure.n_items,
                              tabs, ctx->pure.shape, ctx->pure.d_queues, ctx->stream));
+    if (ctx->pure.split)
+        HIP_TRY(ctx, launch_lin(ctx->d_walks, ctx->pure.d_batch, ctx->pure.d_litems, ctx->pure.n_litems,
+                                ctx->stream));
     HIP_TRY(ctx, launch_select(ctx->d_walks, ctx->pure.d_batch, 1, ctx->pure.comb_blocks, ctx->pure.comb_group, tabs, 1,
                                ctx->d_choice, nullptr,
                                ctx->stream));
@@ -1078,7 +1180,7 @@ psl_status psl_timing_enable(psl_ctx *ctx, int on)
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     timing_drop(ctx);
     ctx->timing = on != 0;
-    ctx->eval_ms = ctx->rest_ms = 0.0;
+    ctx->eval_ms = ctx->rest_ms = ctx->prep_ms = ctx->lin_ms = 0.0;
     ctx->eval_launches = ctx->steps_timed = 0;
     return PSL_OK;
 }
@@ -1094,6 +1196,8 @@ psl_status psl_timing_read(psl_ctx *ctx, psl_timing *out)
     out->eval_launches = ctx->eval_launches;
     out->rest_ms = ctx->rest_ms;
     out->steps = ctx->steps_timed;
+    out->prep_ms = ctx->prep_ms;
+    out->lin_ms = ctx->lin_ms;
     return PSL_OK;
 }
 
@@ -1259,7 +1363,8 @@ psl_status psl_set_option(psl_ctx *ctx, int option, int64_t value)
     if (serve_active(ctx)) return fail(ctx, PSL_E_STATE, "the context is serving");
     const bool ok = (option == PSL_OPT_NEAR_LIMIT && value >= -1) ||
                     (option == PSL_OPT_EVAL_ITEMS && (value == -1 || (value >= 1 && value <= kEvalItemsMax))) ||
-                    (option == PSL_OPT_AMBIG_MARGIN && value >= -1 && value <= kAmbigMarginMax);
+                    (option == PSL_OPT_AMBIG_MARGIN && value >= -1 && value <= kAmbigMarginMax) ||
+                    (option == PSL_OPT_SPLIT && value >= -1 && value <= 1);
     if (!ok) return fail(ctx, PSL_E_INVAL, "option %d value %lld", option, (long long)value);
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
@@ -1267,8 +1372,10 @@ psl_status psl_set_option(psl_ctx *ctx, int option, int64_t value)
         ctx->near_limit = value;
     else if (option == PSL_OPT_EVAL_ITEMS)
         ctx->eval_items = value < 0 ? kEvalItemsDefault : (uint32_t)value;
-    else
+    else if (option == PSL_OPT_AMBIG_MARGIN)
         ctx->amb_margin = value < 0 ? kAmbigMarginDefault : (double)value * 1e-15;
+    else
+        ctx->split_mode = value < 0 ? 1 : (int)value;
     plans_clear(ctx);            // cached layouts carry the old value
     return PSL_OK;
 }

@@ -32,6 +32,7 @@ EXPORTS = ["psl_ctx_create", "psl_ctx_destroy", "psl_last_error", "psl_sync", "p
 OPT_NEAR_LIMIT = 1
 OPT_EVAL_ITEMS = 2
 OPT_AMBIG_MARGIN = 3      # value in units of 1e-15 (-1: the default, 5e-13)
+OPT_SPLIT = 4             # 1 (default): split evaluation where it applies; 0: table evaluation only
 
 
 class PslError(RuntimeError):
@@ -125,7 +126,8 @@ class TuneChoice(ctypes.Structure):
 
 class Timing(ctypes.Structure):
     _fields_ = [("eval_ms", ctypes.c_double), ("eval_launches", ctypes.c_uint64),
-                ("rest_ms", ctypes.c_double), ("steps", ctypes.c_uint64)]
+                ("rest_ms", ctypes.c_double), ("steps", ctypes.c_uint64),
+                ("prep_ms", ctypes.c_double), ("lin_ms", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {n: getattr(self, n) for n, _ in self._fields_}

@@ -33,13 +33,17 @@ def test_traffic_record_is_keyed_by_workload_and_source_digest(tmp_path, monkeyp
     prof = tmp_path / "profiles"
     prof.mkdir()
     (prof / "a.md").write_text(
-        f"`traffic-record: workload=w1 kernel=k source_sha256={digest} "
+        f"`traffic-record: workload=w1 kernel=k_eval_persistent<16> source_sha256={digest} "
         f"fetch_bytes_per_launch=10 write_bytes_per_launch=5`\n"
-        f"traffic-record: workload=w2 kernel=k source_sha256={'0' * 64} "
+        f"`traffic-record: workload=w1 kernel=k_lin source_sha256={digest} "
+        f"fetch_bytes_per_launch=100 write_bytes_per_launch=7`\n"
+        f"traffic-record: workload=w2 kernel=k_eval source_sha256={'0' * 64} "
         f"fetch_bytes_per_launch=1 write_bytes_per_launch=1\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     monkeypatch.setattr(bench, "kernel_source_digest", lambda: digest)
-    assert bench.measured_traffic("w1") == 15
+    assert bench.measured_traffic("w1", "k_eval") == 15
+    assert bench.measured_traffic("w1", "k_lin") == 107
+    assert bench.measured_traffic("w1", "k_combine") is None
     assert bench.measured_traffic("w2") is None       # recorded for other kernel sources
     assert bench.measured_traffic("w3") is None       # no record
 
@@ -49,8 +53,9 @@ def test_valu_record_is_keyed_by_workload_and_source_digest(tmp_path, monkeypatc
     prof = tmp_path / "profiles"
     prof.mkdir()
     (prof / "b.md").write_text(
-        f"`valu-record: workload=w1 kernel=k source_sha256={digest} sq_insts_valu_per_launch=2.5e11`\n"
-        f"`valu-record: workload=w2 kernel=k source_sha256={'1' * 64} sq_insts_valu_per_launch=7`\n")
+        f"`valu-record: workload=w1 kernel=k_eval_persistent<16> source_sha256={digest} "
+        f"sq_insts_valu_per_launch=2.5e11`\n"
+        f"`valu-record: workload=w2 kernel=k_eval source_sha256={'1' * 64} sq_insts_valu_per_launch=7`\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     monkeypatch.setattr(bench, "kernel_source_digest", lambda: digest)
     assert bench.measured_valu("w1") == 2.5e11
@@ -62,6 +67,7 @@ def test_kernel_digest_covers_the_evaluation_sources():
     for rel in bench.KERNEL_SOURCES:
         assert os.path.exists(os.path.join(ROOT, rel)), rel
     assert any(rel.endswith("psl_eval.hip") for rel in bench.KERNEL_SOURCES)
+    assert any(rel.endswith("psl_split.hip") for rel in bench.KERNEL_SOURCES)
 
 
 def test_all_core_threads_follows_affinity_and_omp(monkeypatch):

@@ -312,6 +312,9 @@ __device__ __forceinline__ void eval_sweep_split(EvalLds &sh, const WalkDev &w, 
     const int jl = j, jr = L - 1 - j;
     const int m_j = min(jl, jr);
     const int mJ = split_block_bound(j, L);
+    // coverage (k0 + 31 <= mJ) is monotone in k0: a window is covered for
+    // every lane exactly when it is for the wavefront's smallest bound
+    const int mJw = wave_min(mJ, lane);
     // shifts past every lane's m_j hold no VALU work; the windows end at the
     // chunk that holds the wavefront's largest m_j
     const int m_w = wave_max(m_j, lane);
@@ -389,8 +392,7 @@ __device__ __forceinline__ void eval_sweep_split(EvalLds &sh, const WalkDev &w, 
                 const uint32_t XL = __builtin_bitreverse32(__builtin_amdgcn_alignbit(cl0, cl1, sh_l));
                 const uint32_t Y = XR ^ XL;
                 const int tcount = min(32, kt_end - k0);
-                const bool cov = k0 + 31 <= mJ;         // this lane's block took B_k for the chunk
-                if (tcount == 32 && __all(cov)) {
+                if (tcount == 32 && k0 + 31 <= mJw) {
                     const double *tp = std_ + kOneWin * cc;
                     double v[8];
 #pragma unroll
@@ -398,6 +400,7 @@ __device__ __forceinline__ void eval_sweep_split(EvalLds &sh, const WalkDev &w, 
 #pragma unroll
                     for (int q = 0; q < 8; ++q) acc += v[q];
                 } else {
+                    const bool cov = k0 + 31 <= mJ;     // this lane's block took B_k for the chunk
                     const double *dp = sdq + 2 * (32 * cc);
                     for (int t = 0; t < tcount; ++t) {
                         if (k0 + t > m_j) break;

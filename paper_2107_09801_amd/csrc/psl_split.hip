@@ -96,87 +96,85 @@ __global__ __launch_bounds__(kPrepThreads) void k_split_prep(const WalkDev *walk
     }
 }
 
-// One block per split walk: the three value arrays become inclusive prefix
-// sums over k = 1..k (entry 0 = 0), each thread summing a contiguous run
-// with Neumaier's compensation and the runs' totals scanned in a fixed order;
-// then the step's scale and path choice. The split path is taken when the
+// One block per (split walk, value array): the array becomes its inclusive
+// prefix sums over k = 1..k (entry 0 = 0). Chunks of kScanChunk consecutive
+// entries go through the block in order: each thread sums its kScanPer
+// entries, the wavefronts scan their threads' totals and the block adds the
+// wavefronts' totals before them, and the chunks' totals are carried with
+// Neumaier's compensation. Every summand is non-negative, so each prefix is
+// within a few dozen roundings of its exact value. Block (walk, 0) also
+// stores the step's scale and path choice: the split path is taken when the
 // near-peak list holds the PSL (sparse form) and the quantization error of
 // the linear part, at most (L-1) U, is below 1e-14 of a lower bound of every
 // neighbour's F (T(P-4) for the pivot's PSL P, and at least 1).
-constexpr int kSplitScanThreads = 1024;
-__global__ __launch_bounds__(kSplitScanThreads) void k_split_scan(const WalkDev *walks, const BatchEntry *batch,
-                                                                  Tables tabs)
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 4;
+constexpr int kScanChunk = kScanThreads * kScanPer;
+__global__ __launch_bounds__(kScanThreads) void k_split_scan(const WalkDev *walks, const BatchEntry *batch,
+                                                             Tables tabs)
 {
-    const BatchEntry be = batch[blockIdx.x];
+    const uint32_t wb = blockIdx.x / 3, x = blockIdx.x % 3;
+    const BatchEntry be = batch[wb];
     if (!be.lsplit) return;
     const WalkDev &w = walks[be.slot];
     const int L = (int)w.L;
-    const int n = L - 1;
-    const int per = (n + kSplitScanThreads - 1) / kSplitScanThreads;
-    const int lo = 1 + (int)threadIdx.x * per, hi = min(L, lo + per);
-    __shared__ double s_s[3][kSplitScanThreads], s_c[3][kSplitScanThreads];
-    for (int x = 0; x < 3; ++x) {
-        const double *__restrict__ v = be.pre + (size_t)x * L;
-        double sum = 0.0, comp = 0.0;
-        for (int k = lo; k < hi; ++k) nsum_add(sum, comp, v[k]);
-        s_s[x][threadIdx.x] = sum;
-        s_c[x][threadIdx.x] = comp;
-    }
-    __syncthreads();
-    const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
-    if (wave < 3) {
-        // exclusive prefix of the 1024 run totals of array `wave`: lane l
-        // owns runs 16l .. 16l+15
-        double ls = 0.0, lc = 0.0;
-        for (int t = 16 * lane; t < 16 * lane + 16; ++t) {
-            nsum_add(ls, lc, s_s[wave][t]);
-            lc += s_c[wave][t];
-        }
-        // inclusive over lanes (doubling steps), then shifted up one lane
+    double *__restrict__ v = be.pre + (size_t)x * L;
+    __shared__ double s_tot[kScanThreads / 64];
+    const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
+    auto load = [&](int base, double (&e)[kScanPer]) {
+        const int k0 = base + (int)threadIdx.x * kScanPer;
+#pragma unroll
+        for (int i = 0; i < kScanPer; ++i) e[i] = k0 + i < L ? v[k0 + i] : 0.0;
+    };
+    double carry = 0.0, ccomp = 0.0;
+    double cur[kScanPer], nxt[kScanPer];
+    load(1, cur);
+    for (int base = 1; base < L; base += kScanChunk) {
+        if (base + kScanChunk < L) load(base + kScanChunk, nxt);
+#pragma unroll
+        for (int i = 1; i < kScanPer; ++i) cur[i] += cur[i - 1];
+        // inclusive scan of the thread totals over the wavefront
+        double t = cur[kScanPer - 1];
+#pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
-            const double os = __shfl_up(ls, d), oc = __shfl_up(lc, d);
-            if (lane >= d) {
-                double a = os, ac = oc;
-                nsum_add(a, ac, ls);
-                ls = a;
-                lc = ac + lc;
-            }
+            const double o = __shfl_up(t, d);
+            if (lane >= d) t += o;
         }
-        double es = __shfl_up(ls, 1), ec = __shfl_up(lc, 1);
-        if (lane == 0) {
-            es = 0.0;
-            ec = 0.0;
+        double excl = __shfl_up(t, 1);
+        if (lane == 0) excl = 0.0;
+        if (lane == 63) s_tot[wave] = t;
+        __syncthreads();
+        double off = carry + ccomp, tot = 0.0;
+#pragma unroll
+        for (int q = 0; q < kScanThreads / 64; ++q) {
+            if (q < wave) off += s_tot[q];
+            tot += s_tot[q];
         }
-        for (int t = 16 * lane; t < 16 * lane + 16; ++t) {
-            const double ns = s_s[wave][t], nc = s_c[wave][t];
-            s_s[wave][t] = es;
-            s_c[wave][t] = ec;
-            nsum_add(es, ec, ns);
-            ec += nc;
-        }
-    }
-    __syncthreads();
-    for (int x = 0; x < 3; ++x) {
-        double *__restrict__ v = be.pre + (size_t)x * L;
-        double sum = s_s[x][threadIdx.x], comp = s_c[x][threadIdx.x];
-        for (int k = lo; k < hi; ++k) {
-            nsum_add(sum, comp, v[k]);
-            v[k] = sum + comp;
-        }
+        off += excl;
+        const int k0 = base + (int)threadIdx.x * kScanPer;
+#pragma unroll
+        for (int i = 0; i < kScanPer; ++i)
+            if (k0 + i < L) v[k0 + i] = off + cur[i];
+        nsum_add(carry, ccomp, tot);
+        __syncthreads();                           // s_tot is rewritten by the next chunk
+#pragma unroll
+        for (int i = 0; i < kScanPer; ++i) cur[i] = nxt[i];
     }
     if (threadIdx.x == 0) {
-        for (int x = 0; x < 3; ++x) be.pre[(size_t)x * L] = 0.0;
-        const double *__restrict__ T = tabs.T[w.alpha];
-        const int P = w.psl_pivot;
-        const double U = split_scale(T, P);
-        const double flow = P > 4 ? T[P - 4] : 0.0;
-        const bool exact_enough = (double)(L - 1) * U <= 1e-14 * (flow > 1.0 ? flow : 1.0);
-        const bool sparse_psl = be.near[0] <= be.near_lim;
-        SplitState st;
-        st.U = U;
-        st.use = exact_enough && sparse_psl ? 1u : 0u;
-        st.pad = 0;
-        *be.ss = st;
+        v[0] = 0.0;
+        if (x == 0) {
+            const double *__restrict__ T = tabs.T[w.alpha];
+            const int P = w.psl_pivot;
+            const double U = split_scale(T, P);
+            const double flow = P > 4 ? T[P - 4] : 0.0;
+            const bool exact_enough = (double)(L - 1) * U <= 1e-14 * (flow > 1.0 ? flow : 1.0);
+            const bool sparse_psl = be.near[0] <= be.near_lim;
+            SplitState st;
+            st.U = U;
+            st.use = exact_enough && sparse_psl ? 1u : 0u;
+            st.pad = 0;
+            *be.ss = st;
+        }
     }
 }
 
@@ -188,7 +186,7 @@ hipError_t launch_split_prep(const WalkDev *walks, const BatchEntry *batch, uint
     k_split_prep<<<map.total, kPrepThreads, 0, s>>>(walks, batch, tabs, map);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_split_scan<<<nb, kSplitScanThreads, 0, s>>>(walks, batch, tabs);
+    k_split_scan<<<3 * nb, kScanThreads, 0, s>>>(walks, batch, tabs);
     return hipGetLastError();
 }
 

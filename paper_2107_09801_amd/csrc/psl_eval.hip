@@ -394,9 +394,21 @@ __device__ __forceinline__ void eval_sweep_split(EvalLds &sh, const WalkDev &w, 
                 const int tcount = min(32, kt_end - k0);
                 if (tcount == 32 && k0 + 31 <= mJw) {
                     const double *tp = std_ + kOneWin * cc;
+                    // byte b of te / to holds the byte offset (8 x nibble)
+                    // of nibble 2b / 2b+1 of Y, so each table address is one
+                    // byte extraction; the empty asm keeps the compiler from
+                    // folding the two words back into a shift and a mask per
+                    // nibble
+                    uint32_t te = (Y & 0x0F0F0F0Fu) << 3, to = (Y >> 1) & 0x78787878u;
+                    asm("" : "+v"(te), "+v"(to));
+                    const char *tb = reinterpret_cast<const char *>(tp);
                     double v[8];
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) v[q] = tp[16 * q + ((Y >> (4 * q)) & 15u)];
+                    for (int b = 0; b < 4; ++b) {
+                        v[2 * b] = *reinterpret_cast<const double *>(tb + 256 * b + ((te >> (8 * b)) & 0xFFu));
+                        v[2 * b + 1] =
+                            *reinterpret_cast<const double *>(tb + 256 * b + 128 + ((to >> (8 * b)) & 0xFFu));
+                    }
 #pragma unroll
                     for (int q = 0; q < 8; ++q) acc += v[q];
                 } else {

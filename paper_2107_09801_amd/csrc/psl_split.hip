@@ -226,7 +226,7 @@ typedef unsigned v2u __attribute__((ext_vector_type(2)));
 
 constexpr int kLinWaves = kLinBlockElems / kLinWaveElems;
 constexpr int kLinAcc = 8;                       // accumulators per wavefront
-constexpr int kLinPrefetch = 2;                  // steps between a load and its use
+constexpr int kLinPrefetch = 3;                  // steps between a load and its use
 static_assert(kLinWaveElems == 32 * 4 * kLinAcc, "a wavefront's groups are its accumulators' column sets");
 
 __device__ __forceinline__ v4i ldg_v4i(const int8_t *p)
@@ -296,7 +296,7 @@ __device__ __forceinline__ int lin_wave_max(int v)
 }
 
 // One side's products into acc over tiles c0 = cs .. ce-1. The main loop runs
-// whole 8-step rounds (the steps past ce multiply zero tiles or zero
+// whole 9-step rounds (the steps past ce multiply zero tiles or zero
 // matrices) and leaves out every lane's mixed chunks (those whose column
 // set's blocks disagree on coverage); a second pass visits the steps where
 // some lane's chunk is mixed and adds those products with the tile of each
@@ -314,47 +314,51 @@ __device__ __forceinline__ void lin_side(v16i (&acc)[kLinAcc], const LinLane &ln
     auto chunk = [&](int c0) { return RIGHT ? c0 - 8 * ln.x : c0 + 8 * ln.x; };
     // w32 points 32 words before the sequence (every index here is above -32)
     auto fetch = [&](int idx) { return ldg_v2u(w32 + (uint32_t)(idx + ln.woff + 32)); };
+    // (bitwise, not short-circuit, so that the lane predicates stay selects)
     auto in_range = [&](int c) { return (uint32_t)(c - c_lo) < (uint32_t)(c_hi - c_lo); };
-    auto mixed = [&](int c) { return c >= ln.lo && c < ln.hi && in_range(c); };
+    auto mixed = [&](int c) { return (c >= ln.lo) & (c < ln.hi) & in_range(c); };
     // this lane's 16 digit bytes of chunk c (the zero chunk unless `take`)
     auto tile = [&](int c, bool take, bool set1) {
         const uint32_t off = take ? (set1 ? ln.off1 : ln.off0) + 32u * (uint32_t)c : ln.offz;
         return ldg_v4i(limbs + off);
     };
-    auto tile_main = [&](int c) { return tile(c, in_range(c) && (c < ln.lo || c >= ln.hi), c < ln.lo); };
-    // the matrix of accumulator b at step cs + v sits in slot (v + b) % 8 on
-    // the right and (v + 7 - b) % 8 on the left
-    v4i A[kLinAcc];
+    auto tile_main = [&](int c) { return tile(c, in_range(c) & ((c < ln.lo) | (c >= ln.hi)), c < ln.lo); };
+    // Matrices in a ring of kRing = 9 slots: the matrix of accumulator b at
+    // step cs + v sits in slot (v + b) % 9 on the right and (v + 7 - b) % 9 on
+    // the left, so step v uses slots v .. v+7 and the matrix new at step v+1
+    // (slot (v + 8) % 9) is expanded during step v's products. The sequence
+    // words of that matrix and the digit tiles are loaded kLinPrefetch steps
+    // before their use.
+    constexpr int kRing = kLinAcc + 1;
+    static_assert(kRing % kLinPrefetch == 0, "the unrolled round holds whole prefetch cycles");
+    v4i A[kRing];
 #pragma unroll
     for (int b = 0; b < kLinAcc; ++b) {
-        if (b == kFresh) continue;
         const int slot = RIGHT ? b : kLinAcc - 1 - b;
         A[slot] = lin_matrix<RIGHT>(fetch(midx(cs, b)), midx(cs, b), ln, L, lut);
     }
+    // wq[k % P]: words of the new matrix of step k (k >= 1); tq[k % P]: tile of step k
     v2u wq[kLinPrefetch];
     v4i tq[kLinPrefetch];
 #pragma unroll
     for (int p = 0; p < kLinPrefetch; ++p) {
-        wq[p] = fetch(midx(cs + p, kFresh));
+        wq[(p + 1) % kLinPrefetch] = fetch(midx(cs + p + 1, kFresh));
         tq[p] = tile_main(chunk(cs + p));
     }
-    for (int c0b = cs; c0b < ce; c0b += kLinAcc) {
+    for (int c0b = cs; c0b < ce; c0b += kRing) {
 #pragma unroll
-        for (int v = 0; v < kLinAcc; ++v) {
+        for (int v = 0; v < kRing; ++v) {
             const int c0 = c0b + v;
-            const int q = v % kLinPrefetch;
-            const int fs = (v + kLinAcc - 1) % kLinAcc;
-            A[fs] = lin_matrix<RIGHT>(wq[q], midx(c0, kFresh), ln, L, lut);
-            wq[q] = fetch(midx(c0 + kLinPrefetch, kFresh));
-            const v4i T = tq[q];
-            tq[q] = tile_main(chunk(c0 + kLinPrefetch));
+            const v4i T = tq[v % kLinPrefetch];
+            tq[v % kLinPrefetch] = tile_main(chunk(c0 + kLinPrefetch));
+            const v2u wn = wq[(v + 1) % kLinPrefetch];
+            wq[(v + 1) % kLinPrefetch] = fetch(midx(c0 + 1 + kLinPrefetch, kFresh));
 #pragma unroll
             for (int b = 0; b < kLinAcc; ++b) {
-                if (b == kFresh) continue;
-                const int slot = RIGHT ? (v + b) % kLinAcc : (v + kLinAcc - 1 - b) % kLinAcc;
+                const int slot = RIGHT ? (v + b) % kRing : (v + kLinAcc - 1 - b) % kRing;
                 acc[b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[slot], T, acc[b], 0, 0, 0);
             }
-            acc[kFresh] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[fs], T, acc[kFresh], 0, 0, 0);
+            A[(v + kLinAcc) % kRing] = lin_matrix<RIGHT>(wn, midx(c0 + 1, kFresh), ln, L, lut);
         }
     }
     // mixed chunks: lane chunk c in [lo, hi) at steps c0 = c +- 8x
@@ -409,7 +413,9 @@ __global__ __launch_bounds__(64 * kLinWaves) __attribute__((amdgpu_waves_per_eu(
     const int blk = (first + (int)it.tile) % nblk;
     const int per = (nchunks + (int)be.lsplit - 1) / (int)be.lsplit;
     const int c_lo = (int)it.ks * per, c_hi = min(nchunks, c_lo + per);
-    const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+    // the wavefront index read as a scalar: every matrix index, chunk bound
+    // and end-of-sequence test below is then uniform
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lane = (int)threadIdx.x & 63;
     const int jw = kLinBlockElems * blk + kLinWaveElems * wave;
     if (jw >= L) return;
     const int Gw = jw >> 5;

@@ -332,10 +332,13 @@ __device__ __forceinline__ void lin_side(v16i (&acc)[kLinAcc], const LinLane &ln
     constexpr int kRing = kLinAcc + 1;
     static_assert(kRing % kLinPrefetch == 0, "the unrolled round holds whole prefetch cycles");
     v4i A[kRing];
+    {
+        v2u pw[kLinAcc];                        // all loads issued before the first use
 #pragma unroll
-    for (int b = 0; b < kLinAcc; ++b) {
-        const int slot = RIGHT ? b : kLinAcc - 1 - b;
-        A[slot] = lin_matrix<RIGHT>(fetch(midx(cs, b)), midx(cs, b), ln, L, lut);
+        for (int b = 0; b < kLinAcc; ++b) pw[b] = fetch(midx(cs, b));
+#pragma unroll
+        for (int b = 0; b < kLinAcc; ++b)
+            A[RIGHT ? b : kLinAcc - 1 - b] = lin_matrix<RIGHT>(pw[b], midx(cs, b), ln, L, lut);
     }
     // wq[k % P]: words of the new matrix of step k (k >= 1); tq[k % P]: tile of step k
     v2u wq[kLinPrefetch];
@@ -361,23 +364,35 @@ __device__ __forceinline__ void lin_side(v16i (&acc)[kLinAcc], const LinLane &ln
             A[(v + kLinAcc) % kRing] = lin_matrix<RIGHT>(wn, midx(c0 + 1, kFresh), ln, L, lut);
         }
     }
-    // mixed chunks: lane chunk c in [lo, hi) at steps c0 = c +- 8x
+    // mixed chunks: lane chunk c in [lo, hi) at steps c0 = c +- 8x. The steps
+    // with a mixed lane are marked in 64-step masks first; each such step then
+    // issues all its loads (the 8 matrices' sequence words and the 4 block
+    // pairs' tiles) before it waits, and adds its 8 products.
     const bool has = ln.lo < ln.hi;
     const int z_lo = RIGHT ? ln.lo + 8 * ln.x : ln.lo - 8 * ln.x;
     const int z0 = max(cs, lin_wave_min(has ? z_lo : INT_MAX));
     const int z1 = min(ce, lin_wave_max(has ? z_lo + (ln.hi - ln.lo) : INT_MIN));
-#pragma unroll
-    for (int b = 0; b < kLinAcc; ++b) {
-        v16i t = {};
-        for (int c0 = z0; c0 < z1; ++c0) {
+    for (int zb = z0; zb < z1; zb += 64) {
+        uint64_t steps = 0;
+        for (int i = 0; i < 64 && zb + i < z1; ++i)
+            if (__any(mixed(chunk(zb + i)))) steps |= 1ull << i;
+        while (steps) {
+            const int c0 = zb + __builtin_ctzll(steps);
+            steps &= steps - 1;
             const int c = chunk(c0);
             const bool mx = mixed(c);
-            if (!__any(mx)) continue;
-            const v4i T = tile(c, mx, c < ln.n[b / 2]);
-            const v4i Am = lin_matrix<RIGHT>(fetch(midx(c0, b)), midx(c0, b), ln, L, lut);
-            t = __builtin_amdgcn_mfma_i32_32x32x32_i8(Am, T, t, 0, 0, 0);
+            v2u wv[kLinAcc];
+            v4i T[4];
+#pragma unroll
+            for (int b = 0; b < kLinAcc; ++b) wv[b] = fetch(midx(c0, b));
+#pragma unroll
+            for (int p = 0; p < 4; ++p) T[p] = tile(c, mx, c < ln.n[p]);
+#pragma unroll
+            for (int b = 0; b < kLinAcc; ++b) {
+                const v4i Am = lin_matrix<RIGHT>(wv[b], midx(c0, b), ln, L, lut);
+                acc[b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(Am, T[b / 2], acc[b], 0, 0, 0);
+            }
         }
-        acc[b] += t;
     }
 }
 

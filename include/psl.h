@@ -392,6 +392,13 @@ PSL_API psl_status psl_tune_load(psl_ctx *ctx, const char *path);
  * are the same either way (F agrees to about 1e-14 relative); errors:
  * PSL_E_INVAL outside -1..1. */
 #define PSL_OPT_SPLIT 4
+/* PSL_OPT_TEST_FAIL_ADMIT: a test hook of the request loop. With n >= 1, the
+ * n-th admission (counted per psl_serve_start, admissions that take at least
+ * one job) fails with PSL_E_HIP before it launches anything, so the error path
+ * can be exercised: its jobs finish with PSL_E_HIP, their slabs and slots are
+ * released, and the loop goes on with the queue. 0 (default) turns it off.
+ * Errors: PSL_E_INVAL for a negative value. */
+#define PSL_OPT_TEST_FAIL_ADMIT 5
 PSL_API psl_status psl_set_option(psl_ctx *ctx, int option, int64_t value);
 
 /* --------------------------------------------------- trace, checkpoint */

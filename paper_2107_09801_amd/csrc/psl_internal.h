@@ -157,6 +157,7 @@ struct psl_ctx {
     uint32_t eval_items = psl_rt::kEvalItemsDefault;  // PSL_OPT_EVAL_ITEMS
     double amb_margin = psl::kAmbigMarginDefault;     // PSL_OPT_AMBIG_MARGIN (relative)
     int split_mode = 1;               // PSL_OPT_SPLIT: 1 split evaluation where it applies, 0 never
+    uint32_t test_fail_admit = 0;     // PSL_OPT_TEST_FAIL_ADMIT: serving admission n fails (0: never)
     void *noalloc_scratch = nullptr;  // this device's fixed scratch (psl_eval_neighbourhood_noalloc)
     std::string noalloc_err;          // why it is missing, if it is
     psl_rt::Server *server = nullptr; // serving loop, when started

@@ -1364,7 +1364,8 @@ psl_status psl_set_option(psl_ctx *ctx, int option, int64_t value)
     const bool ok = (option == PSL_OPT_NEAR_LIMIT && value >= -1) ||
                     (option == PSL_OPT_EVAL_ITEMS && (value == -1 || (value >= 1 && value <= kEvalItemsMax))) ||
                     (option == PSL_OPT_AMBIG_MARGIN && value >= -1 && value <= kAmbigMarginMax) ||
-                    (option == PSL_OPT_SPLIT && value >= -1 && value <= 1);
+                    (option == PSL_OPT_SPLIT && value >= -1 && value <= 1) ||
+                    (option == PSL_OPT_TEST_FAIL_ADMIT && value >= 0 && value <= UINT32_MAX);
     if (!ok) return fail(ctx, PSL_E_INVAL, "option %d value %lld", option, (long long)value);
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
@@ -1374,8 +1375,10 @@ psl_status psl_set_option(psl_ctx *ctx, int option, int64_t value)
         ctx->eval_items = value < 0 ? kEvalItemsDefault : (uint32_t)value;
     else if (option == PSL_OPT_AMBIG_MARGIN)
         ctx->amb_margin = value < 0 ? kAmbigMarginDefault : (double)value * 1e-15;
-    else
+    else if (option == PSL_OPT_SPLIT)
         ctx->split_mode = value < 0 ? 1 : (int)value;
+    else
+        ctx->test_fail_admit = (uint32_t)value;
     plans_clear(ctx);            // cached layouts carry the old value
     return PSL_OK;
 }

@@ -126,6 +126,8 @@ struct Server {
     psl_status iterate();
     psl_status upload_layout(char *&sp, char *stage_end);
     psl_status admit(char *&sp, char *stage_end);
+    psl_status admit_start(std::vector<Job> &adm, char *&sp, char *stage_end);
+    uint32_t n_admissions = 0;    // admissions that took jobs (test hook count)
     void retire_finished();
     void fail_all(int32_t status);
     void finish(Job &j, int32_t status);
@@ -263,6 +265,27 @@ psl_status Server::admit(char *&sp, char *stage_end)
         }
         return PSL_OK;
     }
+    // On failure the taken jobs join the active set with whatever slab and
+    // slot they hold, so the caller's fail_all releases those and finishes
+    // every ticket with the error instead of losing them.
+    const psl_status st = admit_start(adm, sp, stage_end);
+    for (auto &j : adm) active.push_back(std::move(j));
+    if (st != PSL_OK) return st;
+    dirty = true;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        stats.peak_active = std::max<uint64_t>(stats.peak_active, active.size());
+        stats.peak_used = std::max<uint64_t>(stats.peak_used, used);
+    }
+    return PSL_OK;
+}
+
+// The fallible part of an admission: slots, walk records, init launches.
+psl_status Server::admit_start(std::vector<Job> &adm, char *&sp, char *stage_end)
+{
+    (void)stage_end;
+    if (ctx->test_fail_admit && ++n_admissions == ctx->test_fail_admit)
+        return fail(ctx, PSL_E_HIP, "admission %u failed by the test hook", n_admissions);
     psl_status st;
     if ((st = grow(ctx, d_admit, adm.size()))) return st;
     if ((st = grow(ctx, d_want, adm.size()))) return st;
@@ -289,6 +312,8 @@ psl_status Server::admit(char *&sp, char *stage_end)
     const uint64_t t = now_ns();
     for (size_t b = 0; b < adm.size(); ++b) {
         Job &j = adm[b];
+        if (ctx->free_slots.empty() && ctx->walks.size() >= ctx->walk_cap)
+            return fail(ctx, PSL_E_STATE, "walk capacity exceeded");
         uint32_t slot;
         if (!ctx->free_slots.empty()) {
             slot = ctx->free_slots.back();
@@ -297,7 +322,6 @@ psl_status Server::admit(char *&sp, char *stage_end)
             slot = (uint32_t)ctx->walks.size();
             ctx->walks.push_back(WalkHost());
         }
-        if (slot >= ctx->walk_cap) return fail(ctx, PSL_E_STATE, "walk capacity exceeded");
         j.slot = slot;
         const SlabLayout lay = slab_layout(j.cfg.L);
         WalkHost &h = ctx->walks[slot];
@@ -333,13 +357,6 @@ psl_status Server::admit(char *&sp, char *stage_end)
     HIP_TRY(ctx, hipMemcpyAsync(d_adm_seg.p, adm_off, sizeof(uint32_t) * (n + 1), hipMemcpyHostToDevice,
                                 ctx->stream));
     HIP_TRY(ctx, launch_suffix(ctx->d_walks, d_admit.p, n, maxL, tabs, 2, nullptr, &adm_map, ctx->stream));
-    for (auto &j : adm) active.push_back(std::move(j));
-    dirty = true;
-    {
-        std::lock_guard<std::mutex> g(mu);
-        stats.peak_active = std::max<uint64_t>(stats.peak_active, active.size());
-        stats.peak_used = std::max<uint64_t>(stats.peak_used, used);
-    }
     return PSL_OK;
 }
 

@@ -36,8 +36,10 @@ PEAK_INT8_OPS = 5.0e15
 # int8 ops of the split path's linear part per (element, neighbour) term: one
 # multiply-add per digit of the quantized coefficient (8 digits).
 LIN_OPS_PER_TERM = 2 * 8
-# Shortest walk the split evaluation takes.
+# Shortest walk the split evaluation takes, and the fewest nominal updates of a
+# launch that takes it by default.
 SPLIT_MIN_L = 2048
+SPLIT_MIN_WORK = 1 << 34
 # VALU lane-ops per C_k-update of the direct form of the one-element flip: form
 # C' (1), fold |C'| into the running max (1), select T(|C'|) (1), one FP64 add
 # (1). The evaluation kernel needs fewer (it skips the unchanged shifts and
@@ -123,9 +125,10 @@ def parse():
     ap.add_argument("--graph", action="store_true", help="replay a captured step per step")
     ap.add_argument("--autotune", action="store_true",
                     help="time every evaluation launch shape on the batch first and keep the fastest")
-    ap.add_argument("--split", type=int, default=-1, choices=[-1, 0, 1],
+    ap.add_argument("--split", type=int, default=-1, choices=[-1, 0, 1, 2],
                     help="split evaluation (linear part on the matrix cores): -1 the library default "
-                         "(on where it applies), 0 off (table evaluation), 1 on")
+                         "(2: for launches of at least 2^34 nominal updates), 0 off (table evaluation), "
+                         "1 wherever L >= 2048")
     ap.add_argument("--eval-items", type=int, default=0,
                     help="minimum work items per evaluation launch (0 = the library default)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -641,7 +644,10 @@ def main():
     eval_avg_s = tm["eval_ms"] / launches / 1e3
     lin_avg_s = tm["lin_ms"] / launches / 1e3
     prep_avg_s = tm["prep_ms"] / launches / 1e3
-    split_on = args.split != 0 and any(g[0] >= SPLIT_MIN_L for g in groups)
+    split_work = sum(count * min(L_, args.n_lmt or L_) * (L_ - 1) for L_, count in groups if L_ >= SPLIT_MIN_L)
+    if wl == "paper":
+        split_work = sum(count * min(L_, 6912) * (L_ - 1) for L_, count in groups if L_ >= SPLIT_MIN_L)
+    split_on = split_work > 0 and (args.split == 1 or (args.split in (-1, 2) and split_work >= SPLIT_MIN_WORK))
     tag = f"{wl}_L{'-'.join(str(g[0]) for g in groups)}_w{nw}" + ("" if split_on else "_table")
     valu = measured_valu(tag)
     if valu is not None:
@@ -660,10 +666,7 @@ def main():
     if split_on and lin_avg_s > 0:
         # algorithmic int8 ops of one launch: every (element, neighbour) term
         # of the evaluated elements of the split walks, 8 digit products each
-        terms = sum(count * min(L_, args.n_lmt or L_) * (L_ - 1) for L_, count in groups if L_ >= SPLIT_MIN_L)
-        if wl == "paper":
-            terms = sum(count * min(L_, 6912) * (L_ - 1) for L_, count in groups if L_ >= SPLIT_MIN_L)
-        ops = LIN_OPS_PER_TERM * terms
+        ops = LIN_OPS_PER_TERM * split_work
         roof_lin = {"kernel": "k_lin", "bound": "mfma", "achieved": ops / lin_avg_s / 1e12,
                     "peak": PEAK_INT8_OPS / 1e12, "unit": "TOP/s", "frac": ops / lin_avg_s / PEAK_INT8_OPS,
                     "traffic": measured_traffic(tag, "k_lin"), "traffic_unit": "B/launch",

@@ -382,15 +382,17 @@ PSL_API psl_status psl_tune_load(psl_ctx *ctx, const char *path);
  * relative, and of an exact summation). Only the flags change: the moves are
  * the band rule's whatever the margin. Errors: PSL_E_INVAL outside the range. */
 #define PSL_OPT_AMBIG_MARGIN 3
-/* PSL_OPT_SPLIT: 1 (default; -1 restores it): batches and evaluations take the
- * split evaluation for walks of L >= 2048 whenever a step allows it (the
+/* PSL_OPT_SPLIT: the split evaluation (Eq. (5) expanded exactly in the +-1
+ * neighbours of Section 3's one-element flip: the linear part of F_j as exact
+ * integer sums on the matrix cores, the both-neighbour remainder on the
+ * vector units) for walks of L >= 2048, in the steps that allow it (the
  * near-peak list holds the PSL and the quantization bound of the linear part
- * is below 1e-14 of every neighbour's F): the linear part of F_j (Eq. (5)
- * expanded exactly in the +-1 neighbours of Section 3's one-element flip)
- * as exact integer sums on the matrix cores, the both-neighbour remainder on
- * the vector units; 0: every step takes the table evaluation. Moves and PSL
- * are the same either way (F agrees to about 1e-14 relative); errors:
- * PSL_E_INVAL outside -1..1. */
+ * is below 1e-14 of every neighbour's F). 2 (default; -1 restores it): in
+ * batches and evaluations whose walks of L >= 2048 hold at least 2^34
+ * nominal updates (N_lmt x (L-1) summed), below which its fixed cost exceeds
+ * what it saves; 1: in every batch and evaluation; 0: never (every step takes
+ * the table evaluation). Moves and PSL are the same either way (F agrees to
+ * about 1e-14 relative); errors: PSL_E_INVAL outside -1..2. */
 #define PSL_OPT_SPLIT 4
 /* PSL_OPT_TEST_FAIL_ADMIT: a test hook of the request loop. With n >= 1, the
  * n-th admission (counted per psl_serve_start, admissions that take at least

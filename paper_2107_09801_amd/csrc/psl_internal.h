@@ -126,6 +126,7 @@ constexpr uint32_t kEvalItemsDefault = 4096;    // PSL_OPT_EVAL_ITEMS default
 constexpr uint32_t kEvalItemsMax = 1u << 18;    // and its largest value
 constexpr int64_t kAmbigMarginMax = 1000000000000000ll;  // PSL_OPT_AMBIG_MARGIN: 1.0 in units of 1e-15
 constexpr uint32_t kSplitMinL = 2048;          // shortest walk the split evaluation takes
+constexpr uint64_t kSplitMinWork = 1ull << 34; // fewest nominal updates of a launch that takes it
 constexpr uint32_t kLinItemsTarget = 1024;     // linear items per launch the k-splits aim for
 constexpr uint32_t kLinMinChunks = 64;         // fewest shift chunks per k-split of a linear item
 
@@ -156,7 +157,7 @@ struct psl_ctx {
     int64_t near_limit = -1;          // PSL_OPT_NEAR_LIMIT
     uint32_t eval_items = psl_rt::kEvalItemsDefault;  // PSL_OPT_EVAL_ITEMS
     double amb_margin = psl::kAmbigMarginDefault;     // PSL_OPT_AMBIG_MARGIN (relative)
-    int split_mode = 1;               // PSL_OPT_SPLIT: 1 split evaluation where it applies, 0 never
+    int split_mode = 2;               // PSL_OPT_SPLIT: 2 by launch work, 1 wherever L allows, 0 never
     uint32_t test_fail_admit = 0;     // PSL_OPT_TEST_FAIL_ADMIT: serving admission n fails (0: never)
     void *noalloc_scratch = nullptr;  // this device's fixed scratch (psl_eval_neighbourhood_noalloc)
     std::string noalloc_err;          // why it is missing, if it is

@@ -506,16 +506,24 @@ psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t 
         pl.seg.tmax = pl.d_segmax;
     }
     // split evaluation: per walk of at least kSplitMinL elements (not for
-    // plans carved from fixed scratch): its coefficient arrays, linear
-    // partials and linear items (walk, kLinBlockElems-element block,
-    // k-split). Workgroup i runs on XCD i mod 8: the walks are dealt to 8
-    // queues (most items first, each to the least loaded queue) and the
-    // launch order interleaves the queues, so a walk's items share one XCD's
-    // L2; short queues are padded with kLinNoWalk items.
+    // plans carved from fixed scratch, nor for launches with less work than
+    // kSplitMinWork nominal updates, where its fixed cost exceeds what it
+    // saves): its coefficient arrays, linear partials and linear items (walk,
+    // kLinBlockElems-element block, k-split). Workgroup i runs on XCD i mod 8:
+    // each walk's items (cost: the chunks of its k-split) form one piece, or
+    // several of consecutive items when the walk holds more than 1/16 of the
+    // launch's cost; the pieces are dealt to 8 queues (costliest first, each
+    // to the least loaded queue) and the launch order interleaves the queues,
+    // so XCD x takes queue x. A batch of many walks keeps each walk's items
+    // (and its digits in L2) on one XCD, and one long walk spreads over all
+    // eight; short queues are padded with kLinNoWalk items.
     std::vector<uint32_t> lsp(n, 0);
     std::vector<EvalItem> litems;
     size_t n_limb = 0, n_dq = 0, n_pre = 0, n_lp = 0;
-    if (!mem && ctx->split_mode) {
+    uint64_t split_work = 0;
+    for (uint32_t b = 0; b < n; ++b)
+        if (Ls[b] >= kSplitMinL) split_work += (uint64_t)n_l[b] * (Ls[b] - 1);
+    if (!mem && (ctx->split_mode == 1 || (ctx->split_mode == 2 && split_work >= kSplitMinWork))) {
         uint64_t blocks = 0;
         std::vector<uint32_t> nq(n, 0);
         for (uint32_t b = 0; b < n; ++b) {
@@ -524,29 +532,45 @@ psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t 
             nq[b] = std::min<uint32_t>(nblk, (n_l[b] + kLinBlockElems - 1) / kLinBlockElems + 1);
             blocks += nq[b];
         }
-        std::vector<uint32_t> order;
+        struct Piece {
+            uint32_t b, first, count;   // items first .. first+count-1 of walk b (q-major, k-split minor)
+            uint64_t cost;
+        };
+        std::vector<Piece> pieces;
+        std::vector<uint64_t> item_cost(n, 0);
+        uint64_t total = 0;
         for (uint32_t b = 0; b < n; ++b) {
             if (!nq[b]) continue;
             const uint32_t nchunks = (Ls[b] - 1 + 31) / 32;
             const uint64_t want = (kLinItemsTarget + blocks - 1) / std::max<uint64_t>(blocks, 1);
             lsp[b] = (uint32_t)std::max<uint64_t>(
                 1, std::min<uint64_t>(want, std::max<uint32_t>(1, nchunks / kLinMinChunks)));
-            order.push_back(b);
+            item_cost[b] = (nchunks + lsp[b] - 1) / lsp[b];
+            total += item_cost[b] * nq[b] * lsp[b];
             n_limb += 2 * (size_t)kLimbs * split_row(Ls[b]);
             n_dq += 2 * (size_t)Ls[b];
             n_pre += 3 * (size_t)Ls[b];
             n_lp += (size_t)lsp[b] * Ls[b];
         }
-        std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
-            return (uint64_t)nq[a] * lsp[a] > (uint64_t)nq[b] * lsp[b];
-        });
+        const uint64_t cap = std::max<uint64_t>(1, total / 16);
+        for (uint32_t b = 0; b < n; ++b) {
+            if (!nq[b]) continue;
+            const uint32_t items = nq[b] * lsp[b];
+            const uint64_t cost = item_cost[b] * items;
+            const uint32_t np = (uint32_t)std::min<uint64_t>(items, (cost + cap - 1) / cap);
+            for (uint32_t p = 0; p < np; ++p) {
+                const uint32_t lo = (uint32_t)((uint64_t)items * p / np), hi = (uint32_t)((uint64_t)items * (p + 1) / np);
+                pieces.push_back(Piece{b, lo, hi - lo, item_cost[b] * (hi - lo)});
+            }
+        }
+        std::stable_sort(pieces.begin(), pieces.end(), [](const Piece &a, const Piece &c) { return a.cost > c.cost; });
         std::vector<EvalItem> xq[kXcds];
         uint64_t load[kXcds] = {};
-        for (uint32_t b : order) {
+        for (const Piece &pc : pieces) {
             const int x = (int)(std::min_element(load, load + kXcds) - load);
-            for (uint32_t q = 0; q < nq[b]; ++q)
-                for (uint32_t k = 0; k < lsp[b]; ++k) xq[x].push_back(EvalItem{b, q, k, 0});
-            load[x] += (uint64_t)nq[b] * lsp[b];
+            for (uint32_t i = pc.first; i < pc.first + pc.count; ++i)
+                xq[x].push_back(EvalItem{pc.b, i / lsp[pc.b], i % lsp[pc.b], 0});
+            load[x] += pc.cost;
         }
         size_t rounds = 0;
         for (int x = 0; x < kXcds; ++x) rounds = std::max(rounds, xq[x].size());
@@ -1364,7 +1388,7 @@ psl_status psl_set_option(psl_ctx *ctx, int option, int64_t value)
     const bool ok = (option == PSL_OPT_NEAR_LIMIT && value >= -1) ||
                     (option == PSL_OPT_EVAL_ITEMS && (value == -1 || (value >= 1 && value <= kEvalItemsMax))) ||
                     (option == PSL_OPT_AMBIG_MARGIN && value >= -1 && value <= kAmbigMarginMax) ||
-                    (option == PSL_OPT_SPLIT && value >= -1 && value <= 1) ||
+                    (option == PSL_OPT_SPLIT && value >= -1 && value <= 2) ||
                     (option == PSL_OPT_TEST_FAIL_ADMIT && value >= 0 && value <= UINT32_MAX);
     if (!ok) return fail(ctx, PSL_E_INVAL, "option %d value %lld", option, (long long)value);
     HIP_TRY(ctx, hipSetDevice(ctx->device));
@@ -1376,7 +1400,7 @@ psl_status psl_set_option(psl_ctx *ctx, int option, int64_t value)
     else if (option == PSL_OPT_AMBIG_MARGIN)
         ctx->amb_margin = value < 0 ? kAmbigMarginDefault : (double)value * 1e-15;
     else if (option == PSL_OPT_SPLIT)
-        ctx->split_mode = value < 0 ? 1 : (int)value;
+        ctx->split_mode = value < 0 ? 2 : (int)value;
     else
         ctx->test_fail_admit = (uint32_t)value;
     plans_clear(ctx);            // cached layouts carry the old value

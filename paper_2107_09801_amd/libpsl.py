@@ -32,7 +32,7 @@ EXPORTS = ["psl_ctx_create", "psl_ctx_destroy", "psl_last_error", "psl_sync", "p
 OPT_NEAR_LIMIT = 1
 OPT_EVAL_ITEMS = 2
 OPT_AMBIG_MARGIN = 3      # value in units of 1e-15 (-1: the default, 5e-13)
-OPT_SPLIT = 4             # 1 (default): split evaluation where it applies; 0: table evaluation only
+OPT_SPLIT = 4             # split evaluation: 2 (default) by launch work, 1 wherever L >= 2048, 0 never
 OPT_TEST_FAIL_ADMIT = 5   # test hook: serving admission n (>= 1) fails as a HIP error would; 0: off
 
 

@@ -106,6 +106,7 @@ struct BatchPlan {
     int32_t *d_p = nullptr;
     SelPart *d_red = nullptr;
     uint32_t *d_pend = nullptr;       // pending list: count, then batch positions
+    uint32_t *d_done = nullptr;       // per batch position: combine blocks finished (0 between launches)
     uint32_t *d_seg = nullptr;        // segment map of the O(L) passes
     double *d_segtot = nullptr;       // per segment: chunk-sum total (suffix pass)
     uint32_t *d_segmax = nullptr;     // per segment: maximum |C_k|

@@ -97,8 +97,8 @@ __global__ __launch_bounds__(kCorrThreads) void k_corr(WalkDev *walks, const Bat
 }
 
 // The pending list of a batch: pend[0] = count, pend[1..] = batch positions
-// of the walks whose step ended in a phase switch (k_bookkeep appends,
-// k_select of the next step clears the count).
+// of the walks whose step ended in a phase switch (k_bookkeep appends, the
+// selection of the next step clears the count).
 //
 // C of a switched pivot from C of local_best: the FLIP_lmt one-element flips
 // in draw order, where flip f sees local_best with flips 0..f-1 applied.
@@ -560,12 +560,12 @@ struct ChoiceDev {
     uint32_t j_psl;
     int32_t psl_min;
     int32_t psl_k;
-    uint32_t flags;         // CHOICE_AMBIG_ARGMIN (set by k_ambig)
+    uint32_t flags;         // CHOICE_AMBIG_ARGMIN (set with the selection)
 };
 
-constexpr int kSelThreads = 1024;
 constexpr int kCombThreads = 256;
 constexpr int kCombBatch = 16;      // split loads a combine lane keeps in flight
+constexpr uint64_t kCombFuseBlocks = 256;   // most combine blocks of a launch that selects in its last blocks
 
 // Candidates [lo, hi) of combine block b of `blocks`: contiguous ranges in
 // scan order, a multiple of the block's candidates per pass (kCombThreads / G)
@@ -712,6 +712,63 @@ __device__ __forceinline__ void select_walk(WalkDev &w, const BatchEntry &be, ui
     if (s_improve) copy_words(w.best, w.pivot, w.nw, threadIdx.x, NT, jp >> 6, 1ull << (jp & 63u));
 }
 
+// ------------------------------------------------------- ambiguity flags
+
+// The ambiguity flags of a step's scan, from the selection's results (by the
+// block that made the selection, after it and before the flip and the
+// bookkeeping):
+//   ARGMIN: some scanned neighbour's F lies within amb = margin*F_min of the
+//     band edge thr = F_min*(1+tau) (|F - thr| <= amb): a different rounding
+//     of Eq. (5) could move it across the edge and change the move;
+//   COMPARE (steps only): the move's F lies strictly within margin*v_local of
+//     v_local*(1-tau) or of v_local*(1+tau), the edges of the three-way
+//     comparison with the local best.
+// Every F of a combine block is at least that block's minimum, so only the
+// blocks whose minimum is at most thr + amb are read. pure != 0: the flag
+// goes into the choice record out[b]; otherwise into the walk's step flags.
+constexpr int kAmbThreads = 256;
+__device__ __forceinline__ void ambig_walk(WalkDev &w, const BatchEntry &be, uint32_t bi, uint32_t comb_blocks,
+                                           uint32_t comb_group, int pure, ChoiceDev *out, double margin)
+{
+    const uint32_t n = be.fixed ? be.n_lmt : w.n_lmt;
+    const double Fmin = pure ? out[bi].F_min : w.F_min;
+    const double thr = Fmin * (1.0 + kTau), amb = margin * Fmin;
+    // the combine blocks whose minimum lies at or below thr + amb, one per
+    // thread (comb_blocks <= kAmbThreads), as one 64-bit mask per wavefront
+    static_assert(kCombMaxBlocks <= kAmbThreads, "one combine block per thread");
+    __shared__ uint64_t s_near[kAmbThreads / 64];
+    const uint32_t t = threadIdx.x;
+    const bool near = t < comb_blocks && be.red[t].f - thr <= amb;
+    const uint64_t m = __ballot(near);
+    if ((t & 63) == 0) s_near[t >> 6] = m;
+    __syncthreads();
+    int hit = 0;
+    for (uint32_t q = 0; q < kAmbThreads / 64; ++q) {
+        for (uint64_t bits = s_near[q]; bits; bits &= bits - 1) {   // the same for every thread of the block
+            const uint32_t b = 64 * q + (uint32_t)__builtin_ctzll(bits);
+            uint32_t lo, hi;
+            comb_range(n, comb_blocks, comb_group, b, lo, hi);
+            for (uint32_t i = lo + t; i < hi; i += kAmbThreads) {
+                const double g = be.F[i] - thr;
+                hit |= (g < 0.0 ? -g : g) <= amb;
+            }
+        }
+    }
+    hit = __syncthreads_or(hit);
+    if (threadIdx.x == 0) {
+        if (pure) {
+            out[bi].flags = hit ? CHOICE_AMBIG_ARGMIN : 0u;
+        } else {
+            uint32_t fl = w.flags;
+            if (hit) fl |= STEP_AMBIG_ARGMIN;
+            const double vl = w.value_local, v = w.value_step;
+            const double elo = vl * (1.0 - kTau), ehi = vl * (1.0 + kTau), band = margin * vl;
+            if ((v - elo < band && elo - v < band) || (v - ehi < band && ehi - v < band)) fl |= STEP_AMBIG_COMPARE;
+            w.flags = fl;
+        }
+    }
+}
+
 // F and PSL per candidate from the k-split partials, spread over gridDim.x
 // blocks per walk (blockIdx.y = batch position); each block leaves its
 // smallest F and its first smallest PSL in be.red. A group of G lanes
@@ -719,12 +776,12 @@ __device__ __forceinline__ void select_walk(WalkDev &w, const BatchEntry &be, ui
 // g+G, ... in order, then the group adds its lanes' sums with a butterfly
 // (a fixed order for a given split count and G; G = 1 adds the splits in
 // order).
-// fuse != 0 (one block per walk): the block then makes the walk's selection
-// itself (select_walk), in place of k_select; b0 = the batch position of
-// blockIdx.y = 0.
+// With tail != 0 the walk's last block to finish then makes its selection
+// (select_walk) and its ambiguity flags; b0 = the batch position of
+// blockIdx.y = 0; done holds one zeroed counter per batch position.
 __global__ __launch_bounds__(kCombThreads) void k_combine(WalkDev *walks, const BatchEntry *batch, Tables tabs,
-                                                          int G, int fuse, int pure, ChoiceDev *out,
-                                                          uint32_t *pend, uint32_t b0)
+                                                          int G, int tail, int pure, ChoiceDev *out, uint32_t *pend,
+                                                          uint32_t *done, double margin, uint32_t b0)
 {
     const BatchEntry be = batch[blockIdx.y];
     WalkDev &w = walks[be.slot];
@@ -814,12 +871,35 @@ __global__ __launch_bounds__(kCombThreads) void k_combine(WalkDev *walks, const 
         for (int x = 1; x < kCombThreads / 64; ++x) sel_merge(r.f, r.p, r.i, s_r[x].f, s_r[x].p, s_r[x].i);
         be.red[blockIdx.x] = r;
     }
-    if (fuse) {
-        __syncthreads();        // this block's F, P and block minimum are visible to it
-        select_walk<kCombThreads>(w, be, b0 + blockIdx.y, 1, (uint32_t)G, pure, out, pend);
+    if (!tail) return;
+    // tail != 0: the walk's last block to finish (counted in done[bi], which
+    // it returns to 0 for the next launch) makes the selection and sets the
+    // ambiguity flags. Each block's count is a device-scope release of its F,
+    // P and minimum, and the last block acquires them all.
+    const uint32_t bi = b0 + blockIdx.y;
+    __shared__ uint32_t s_last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t last = 1;
+        if (gridDim.x > 1) {
+            const uint32_t before =
+                __hip_atomic_fetch_add(&done[bi], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            last = before == gridDim.x - 1 ? 1u : 0u;
+            if (last) done[bi] = 0;
+        }
+        s_last = last;
     }
+    __syncthreads();
+    if (!s_last) return;
+    if (gridDim.x > 1) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    select_walk<kCombThreads>(w, be, bi, gridDim.x, (uint32_t)G, pure, out, pend);
+    __syncthreads();
+    ambig_walk(w, be, bi, gridDim.x, (uint32_t)G, pure, out, margin);
 }
 
+// The selection of a walk (one block per walk, after k_combine when the
+// combine launch does not make it itself).
+constexpr int kSelThreads = 1024;
 __global__ __launch_bounds__(kSelThreads) void k_select(WalkDev *walks, const BatchEntry *batch,
                                                         uint32_t comb_blocks, uint32_t comb_group, int pure,
                                                         ChoiceDev *out, uint32_t *pend)
@@ -828,53 +908,15 @@ __global__ __launch_bounds__(kSelThreads) void k_select(WalkDev *walks, const Ba
     select_walk<kSelThreads>(walks[be.slot], be, blockIdx.x, comb_blocks, comb_group, pure, out, pend);
 }
 
-// ------------------------------------------------------- ambiguity flags
-
-// The ambiguity flags of a step's scan, from the selection's results (one
-// block per walk, after k_select and before the flip and the bookkeeping):
-//   ARGMIN: some scanned neighbour's F lies within amb = margin*F_min of the
-//     band edge thr = F_min*(1+tau) (|F - thr| <= amb): a different rounding
-//     of Eq. (5) could move it across the edge and change the move;
-//   COMPARE (steps only): the move's F lies strictly within margin*v_local of
-//     v_local*(1-tau) or of v_local*(1+tau), the edges of the three-way
-//     comparison with the local best.
-// Every F of a combine block is at least that block's minimum, so only the
-// blocks whose minimum is at most thr + amb are read. pure != 0: the flag
-// goes into the choice record out[b]; otherwise into the walk's step flags.
-constexpr int kAmbThreads = 256;
+// The ambiguity flags of a walk (one block per walk, after k_select).
 __global__ __launch_bounds__(kAmbThreads) void k_ambig(WalkDev *walks, const BatchEntry *batch,
                                                        uint32_t comb_blocks, uint32_t comb_group, int pure,
                                                        ChoiceDev *out, double margin)
 {
     const BatchEntry be = batch[blockIdx.x];
-    WalkDev &w = walks[be.slot];
-    const uint32_t n = be.fixed ? be.n_lmt : w.n_lmt;
-    const double Fmin = pure ? out[blockIdx.x].F_min : w.F_min;
-    const double thr = Fmin * (1.0 + kTau), amb = margin * Fmin;
-    int hit = 0;
-    for (uint32_t b = 0; b < comb_blocks; ++b) {
-        if (!(be.red[b].f - thr <= amb)) continue;    // the same for every thread of the block
-        uint32_t lo, hi;
-        comb_range(n, comb_blocks, comb_group, b, lo, hi);
-        for (uint32_t i = lo + threadIdx.x; i < hi; i += kAmbThreads) {
-            const double g = be.F[i] - thr;
-            hit |= (g < 0.0 ? -g : g) <= amb;
-        }
-    }
-    hit = __syncthreads_or(hit);
-    if (threadIdx.x == 0) {
-        if (pure) {
-            out[blockIdx.x].flags = hit ? CHOICE_AMBIG_ARGMIN : 0u;
-        } else {
-            uint32_t fl = w.flags;
-            if (hit) fl |= STEP_AMBIG_ARGMIN;
-            const double vl = w.value_local, v = w.value_step;
-            const double elo = vl * (1.0 - kTau), ehi = vl * (1.0 + kTau), band = margin * vl;
-            if ((v - elo < band && elo - v < band) || (v - ehi < band && ehi - v < band)) fl |= STEP_AMBIG_COMPARE;
-            w.flags = fl;
-        }
-    }
+    ambig_walk(walks[be.slot], be, blockIdx.x, comb_blocks, comb_group, pure, out, margin);
 }
+
 
 // ------------------------------------------------------------ flip
 
@@ -962,7 +1004,7 @@ __global__ __launch_bounds__(kBookThreads) void k_bookkeep(WalkDev *walks, const
         w.pivot[k >> 6] ^= 1ull << (k & 63u);
         w.F_pivot = w.value_step;
         w.psl_pivot = w.psl_k;
-        // the comparison with v_local was taken by k_select
+        // the comparison with v_local was taken by the selection
         int improved = 0, sw = 0;
         uint32_t flags = w.flags;
         if (flags & STEP_IMPROVED) {
@@ -1107,45 +1149,42 @@ hipError_t launch_suffix(WalkDev *walks, const BatchEntry *batch, uint32_t nb, u
     return hipGetLastError();
 }
 
-__global__ void k_near_reset(const BatchEntry *batch, uint32_t nb, uint32_t *pend)
+__global__ void k_near_reset(const BatchEntry *batch, uint32_t nb, uint32_t *pend, uint32_t *done)
 {
     const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b < nb) batch[b].near[0] = 0;
+    if (b < nb && done) done[b] = 0;
     if (b == 0 && pend) pend[0] = 0;
 }
 
-hipError_t launch_near_reset(const BatchEntry *batch, uint32_t nb, uint32_t *pend, hipStream_t s)
+hipError_t launch_near_reset(const BatchEntry *batch, uint32_t nb, uint32_t *pend, uint32_t *done, hipStream_t s)
 {
-    k_near_reset<<<(nb + 255) / 256, 256, 0, s>>>(batch, nb, pend);
+    k_near_reset<<<(nb + 255) / 256, 256, 0, s>>>(batch, nb, pend, done);
     return hipGetLastError();
 }
 
 hipError_t launch_select(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t comb_blocks,
                          uint32_t comb_group, const Tables &tabs, int pure, void *out, uint32_t *pend,
-                         hipStream_t s)
-{
-    if (comb_blocks < 1 || comb_blocks > kCombMaxBlocks) return hipErrorInvalidValue;
-    if (comb_group < 1 || comb_group > 64 || (comb_group & (comb_group - 1))) return hipErrorInvalidValue;
-    // one combine block per walk: it makes the selection too
-    const int fuse = comb_blocks == 1 ? 1 : 0;
-    for (uint32_t b0 = 0; b0 < nb; b0 += kMaxGridY) {
-        k_combine<<<dim3(comb_blocks, std::min(kMaxGridY, nb - b0)), kCombThreads, 0, s>>>(
-            walks, batch + b0, tabs, (int)comb_group, fuse, pure, (ChoiceDev *)out, pend, b0);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    if (fuse) return hipSuccess;
-    k_select<<<nb, kSelThreads, 0, s>>>(walks, batch, comb_blocks, comb_group, pure, (ChoiceDev *)out, pend);
-    return hipGetLastError();
-}
-
-hipError_t launch_ambig(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t comb_blocks,
-                        uint32_t comb_group, int pure, void *out, double margin, hipStream_t s)
+                         uint32_t *done, double margin, hipStream_t s)
 {
     if (comb_blocks < 1 || comb_blocks > kCombMaxBlocks) return hipErrorInvalidValue;
     if (comb_group < 1 || comb_group > 64 || (comb_group & (comb_group - 1))) return hipErrorInvalidValue;
     if (pure && (!out || nb != 1)) return hipErrorInvalidValue;
     if (nb == 0) return hipSuccess;
+    // small launches make the selection in the combine launch (one launch
+    // fewer); large ones in launches of their own, where the per-block
+    // device-scope release of the fused form costs more than the launches
+    const int tail = comb_blocks == 1 || ((uint64_t)nb * comb_blocks <= kCombFuseBlocks && done) ? 1 : 0;
+    for (uint32_t b0 = 0; b0 < nb; b0 += kMaxGridY) {
+        k_combine<<<dim3(comb_blocks, std::min(kMaxGridY, nb - b0)), kCombThreads, 0, s>>>(
+            walks, batch + b0, tabs, (int)comb_group, tail, pure, (ChoiceDev *)out, pend, done, margin, b0);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (tail) return hipSuccess;
+    k_select<<<nb, kSelThreads, 0, s>>>(walks, batch, comb_blocks, comb_group, pure, (ChoiceDev *)out, pend);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     k_ambig<<<nb, kAmbThreads, 0, s>>>(walks, batch, comb_blocks, comb_group, pure, (ChoiceDev *)out, margin);
     return hipGetLastError();
 }

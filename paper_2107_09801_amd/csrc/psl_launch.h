@@ -23,20 +23,21 @@ hipError_t launch_eval(const WalkDev *walks, const BatchEntry *batch, const Eval
 // (value_local, F_pivot, psl_pivot, psl_best) of every walk.
 hipError_t launch_suffix(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t max_L,
                          const Tables &tabs, int mode, const uint32_t *pend, const SegMap *map, hipStream_t s);
-// Zero the near-peak counts of a batch and its pending count (after its
-// scratch is allocated).
-hipError_t launch_near_reset(const BatchEntry *batch, uint32_t nb, uint32_t *pend, hipStream_t s);
+// Zero the near-peak counts of a batch, its pending count and its combine
+// counters (done, nb entries; may be null) after its scratch is allocated.
+hipError_t launch_near_reset(const BatchEntry *batch, uint32_t nb, uint32_t *pend, uint32_t *done, hipStream_t s);
+// F and PSL per candidate from the partials, then the selection and its
+// ambiguity flags (margin: their relative margin), by each walk's last combine
+// block in launches of at most 256 combine blocks (done: one zeroed counter
+// per batch position, left zero; without it the selection takes launches of
+// its own): pure != 0 writes the choice record `out` (one walk), else the
+// walks' step records.
 hipError_t launch_select(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t comb_blocks,
                          uint32_t comb_group, const Tables &tabs, int pure, void *out, uint32_t *pend,
-                         hipStream_t s);
+                         uint32_t *done, double margin, hipStream_t s);
 size_t choice_dev_size();
 void choice_dev_unpack(const void *p, uint32_t *i_best, uint32_t *j_best, double *F_best,
                        double *F_min, uint32_t *j_psl, int32_t *psl_min, int32_t *psl_k, uint32_t *flags);
-// The ambiguity flags of the selection just made (after launch_select, before
-// launch_apply): pure != 0 writes the choice record `out` (one walk), else the
-// walks' step flags. margin: relative margin of the flags.
-hipError_t launch_ambig(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t comb_blocks,
-                        uint32_t comb_group, int pure, void *out, double margin, hipStream_t s);
 hipError_t launch_apply(WalkDev *walks, const BatchEntry *batch, const SegMap &map, int64_t j_fixed,
                         hipStream_t s);
 hipError_t launch_flip_bit(WalkDev *walks, const BatchEntry *batch, uint32_t j, hipStream_t s);

@@ -132,6 +132,7 @@ void plan_free(psl_ctx *ctx, BatchPlan &pl)
     dev_free(ctx, pl.d_m0, false);
     dev_free(ctx, pl.d_red, false);
     dev_free(ctx, pl.d_pend, false);
+    dev_free(ctx, pl.d_done, false);
     dev_free(ctx, pl.d_seg, false);
     dev_free(ctx, pl.d_segtot, false);
     dev_free(ctx, pl.d_segmax, false);
@@ -491,6 +492,8 @@ psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t 
     pl.d_red = (SelPart *)p;
     if ((st = get(&p, sizeof(uint32_t) * (n + 1)))) return st;
     pl.d_pend = (uint32_t *)p;
+    if ((st = get(&p, sizeof(uint32_t) * n))) return st;
+    pl.d_done = (uint32_t *)p;
     {
         std::vector<uint32_t> off(n + 1);
         pl.seg = seg_prefix(Ls.data(), n, off.data());
@@ -644,7 +647,7 @@ psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t 
     HIP_TRY(ctx, hipMemcpy(pl.d_batch, be.data(), sizeof(BatchEntry) * n, hipMemcpyHostToDevice));
     HIP_TRY(ctx, hipMemcpy(pl.d_items, items.data(), sizeof(EvalItem) * items.size(),
                            hipMemcpyHostToDevice));
-    HIP_TRY(ctx, launch_near_reset(pl.d_batch, n, pl.d_pend, ctx->stream));
+    HIP_TRY(ctx, launch_near_reset(pl.d_batch, n, pl.d_pend, pl.d_done, ctx->stream));
     pl.n_items = (uint32_t)items.size();
     return PSL_OK;
 }
@@ -716,9 +719,7 @@ psl_status launch_step(psl_ctx *ctx, const BatchPlan &pl, const Tables &tabs, ui
     if (pl.split) HIP_TRY(ctx, launch_lin(ctx->d_walks, pl.d_batch, pl.d_litems, pl.n_litems, ctx->stream));
     if (timed && (st = timing_mark(ctx))) return st;
     HIP_TRY(ctx, launch_select(ctx->d_walks, pl.d_batch, n, pl.comb_blocks, pl.comb_group, tabs, 0, nullptr,
-                               pl.d_pend, ctx->stream));
-    HIP_TRY(ctx, launch_ambig(ctx->d_walks, pl.d_batch, n, pl.comb_blocks, pl.comb_group, 0, nullptr,
-                              ctx->amb_margin, ctx->stream));
+                               pl.d_pend, pl.d_done, ctx->amb_margin, ctx->stream));
     HIP_TRY(ctx, launch_apply(ctx->d_walks, pl.d_batch, pl.seg, -1, ctx->stream));
     HIP_TRY(ctx, launch_bookkeep(ctx->d_walks, pl.d_batch, n, pl.d_pend, ctx->stream));
     HIP_TRY(ctx, launch_switch_corr(ctx->d_walks, pl.d_batch, n, pl.max_L, pl.d_pend, ctx->stream));
@@ -1010,10 +1011,7 @@ psl_status psl_eval_neighbourhood(psl_ctx *ctx, uint32_t walk, uint32_t start, u
         HIP_TRY(ctx, launch_lin(ctx->d_walks, ctx->pure.d_batch, ctx->pure.d_litems, ctx->pure.n_litems,
                                 ctx->stream));
     HIP_TRY(ctx, launch_select(ctx->d_walks, ctx->pure.d_batch, 1, ctx->pure.comb_blocks, ctx->pure.comb_group, tabs, 1,
-                               ctx->d_choice, nullptr,
-                               ctx->stream));
-    HIP_TRY(ctx, launch_ambig(ctx->d_walks, ctx->pure.d_batch, 1, ctx->pure.comb_blocks, ctx->pure.comb_group, 1,
-                              ctx->d_choice, ctx->amb_margin, ctx->stream));
+                               ctx->d_choice, nullptr, ctx->pure.d_done, ctx->amb_margin, ctx->stream));
     if (F_dev)
         HIP_TRY(ctx, hipMemcpyAsync(F_dev, ctx->pure.d_f, sizeof(double) * n_lmt,
                                     hipMemcpyDeviceToDevice, ctx->stream));
@@ -1064,9 +1062,7 @@ psl_status psl_eval_neighbourhood_noalloc(psl_ctx *ctx, uint32_t walk, uint32_t 
     HIP_TRY(ctx, launch_eval(ctx->d_walks, pl.d_batch, pl.d_items, pl.n_items, tabs, pl.shape, pl.d_queues,
                              ctx->stream));
     HIP_TRY(ctx, launch_select(ctx->d_walks, pl.d_batch, 1, pl.comb_blocks, pl.comb_group, tabs, 1, d_choice,
-                               nullptr, ctx->stream));
-    HIP_TRY(ctx, launch_ambig(ctx->d_walks, pl.d_batch, 1, pl.comb_blocks, pl.comb_group, 1, d_choice,
-                              ctx->amb_margin, ctx->stream));
+                               nullptr, pl.d_done, ctx->amb_margin, ctx->stream));
     alignas(16) unsigned char host[256];
     if (choice_dev_size() > sizeof host) return fail(ctx, PSL_E_STATE, "choice record too large");
     HIP_TRY(ctx, hipMemcpyAsync(host, d_choice, choice_dev_size(), hipMemcpyDeviceToHost, ctx->stream));

@@ -100,6 +100,7 @@ struct Server {
     DevBuf<uint32_t> d_mpart, d_m0, d_near, d_want;
     DevBuf<SelPart> d_red;
     DevBuf<uint32_t> d_pend;      // pending list of the iteration's batch
+    DevBuf<uint32_t> d_done;      // per batch position: combine blocks finished (0 between launches)
     DevBuf<uint32_t> d_seg, d_adm_seg;   // segment maps (batch, admitted walks)
     DevBuf<double> d_segtot;             // per segment of the batch map: chunk-sum total
     DevBuf<uint32_t> d_segmax;
@@ -395,6 +396,7 @@ psl_status Server::upload_layout(char *&sp, char *stage_end)
         (st = grow(ctx, d_s0, n_suf)) || (st = grow(ctx, d_m0, n_suf)) ||
         (st = grow(ctx, d_near, (size_t)(kNearCap + 1) * n)) || (st = grow(ctx, d_queues, 1)) ||
         (st = grow(ctx, d_red, (size_t)comb_blocks * n)) || (st = grow(ctx, d_pend, (size_t)n + 1)) ||
+        (st = grow(ctx, d_done, (size_t)n)) ||
         (st = grow(ctx, d_seg, (size_t)n + 1)))
         return st;
     BatchEntry *be = (BatchEntry *)sp;
@@ -443,7 +445,7 @@ psl_status Server::upload_layout(char *&sp, char *stage_end)
     seg.tot = d_segtot.p;
     seg.tmax = d_segmax.p;
     HIP_TRY(ctx, hipMemcpyAsync(d_seg.p, off, sizeof(uint32_t) * (n + 1), hipMemcpyHostToDevice, ctx->stream));
-    HIP_TRY(ctx, launch_near_reset(d_batch.p, n, d_pend.p, ctx->stream));
+    HIP_TRY(ctx, launch_near_reset(d_batch.p, n, d_pend.p, d_done.p, ctx->stream));
     n_items = (uint32_t)items;
     dirty = false;
     return PSL_OK;
@@ -501,9 +503,7 @@ psl_status Server::iterate()
     HIP_TRY(ctx, launch_suffix(ctx->d_walks, d_batch.p, n, max_L, tabs, 0, nullptr, &seg, ctx->stream));
     HIP_TRY(ctx, launch_eval(ctx->d_walks, d_batch.p, d_items.p, n_items, tabs, shape, d_queues.p, ctx->stream));
     HIP_TRY(ctx, launch_select(ctx->d_walks, d_batch.p, n, comb_blocks, comb_group, tabs, 0, nullptr, d_pend.p,
-                               ctx->stream));
-    HIP_TRY(ctx, launch_ambig(ctx->d_walks, d_batch.p, n, comb_blocks, comb_group, 0, nullptr, ctx->amb_margin,
-                              ctx->stream));
+                               d_done.p, ctx->amb_margin, ctx->stream));
     HIP_TRY(ctx, launch_apply(ctx->d_walks, d_batch.p, seg, -1, ctx->stream));
     HIP_TRY(ctx, launch_bookkeep(ctx->d_walks, d_batch.p, n, d_pend.p, ctx->stream));
     HIP_TRY(ctx, launch_switch_corr(ctx->d_walks, d_batch.p, n, max_L, d_pend.p, ctx->stream));
@@ -639,6 +639,7 @@ void serve_shutdown(psl_ctx *ctx)
     release(ctx, s->d_near);
     release(ctx, s->d_red);
     release(ctx, s->d_pend);
+    release(ctx, s->d_done);
     release(ctx, s->d_seg);
     release(ctx, s->d_adm_seg);
     release(ctx, s->d_segtot);

@@ -107,6 +107,8 @@ struct BatchPlan {
     SelPart *d_red = nullptr;
     uint32_t *d_pend = nullptr;       // pending list: count, then batch positions
     uint32_t *d_done = nullptr;       // per batch position: combine blocks finished (0 between launches)
+    uint32_t fixed_n = 0;             // plans of a fixed neighbourhood: its N_lmt (0: not fixed)
+    uint32_t fixed_start = 0;         // ... and the start its batch entry holds
     uint32_t *d_seg = nullptr;        // segment map of the O(L) passes
     double *d_segtot = nullptr;       // per segment: chunk-sum total (suffix pass)
     uint32_t *d_segmax = nullptr;     // per segment: maximum |C_k|
@@ -152,7 +154,8 @@ struct psl_ctx {
     double *d_T[PSL_ALPHA_MAX + 1] = {};
     uint32_t T_n = 0;                 // entries per power table
     std::vector<BatchPlan> plans;     // recent step batches, most recent last
-    BatchPlan pure;                   // single-walk plan of psl_eval_neighbourhood
+    BatchPlan pure;                   // single-walk plan of psl_eval_neighbourhood (kept for the next call)
+    psl::BatchEntry *d_one = nullptr; // psl_apply_flip's batch entry (allocated on first use)
     void *d_choice = nullptr;
     std::string err;
     int64_t near_limit = -1;          // PSL_OPT_NEAR_LIMIT

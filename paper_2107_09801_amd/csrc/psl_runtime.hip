@@ -425,6 +425,8 @@ psl_status make_plan(psl_ctx *ctx, BatchPlan &pl, const uint32_t *ids, uint32_t 
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     plan_free(ctx, pl);
     pl.ids.assign(ids, ids + n);
+    pl.fixed_n = fixed ? n_fixed : 0;
+    pl.fixed_start = fixed ? start_fixed : 0;
     std::vector<uint32_t> n_l(n), Ls(n);
     for (uint32_t b = 0; b < n; ++b) {
         const WalkHost &h = ctx->walks[ids[b]];
@@ -830,6 +832,7 @@ void psl_ctx_destroy(psl_ctx *ctx)
     for (uint32_t a = 1; a <= PSL_ALPHA_MAX; ++a) dev_free(ctx, ctx->d_T[a], false);
     dev_free(ctx, ctx->d_walks, false);
     dev_free(ctx, ctx->d_choice, false);
+    dev_free(ctx, ctx->d_one, false);
     timing_drop(ctx);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
@@ -998,8 +1001,20 @@ psl_status psl_eval_neighbourhood(psl_ctx *ctx, uint32_t walk, uint32_t start, u
     if (n_lmt < 1 || n_lmt > h.L || start >= h.L)
         return fail(ctx, PSL_E_INVAL, "start=%u n_lmt=%u for L=%u", start, n_lmt, h.L);
     HIP_TRY(ctx, hipSetDevice(ctx->device));
-    psl_status st = make_plan(ctx, ctx->pure, &walk, 1, n_lmt, start);
-    if (st) return st;
+    // The plan of the previous call serves again when it was made for the
+    // same walk and N_lmt (freeing walks or changing options drops it): its
+    // layout does not depend on the start, which the batch entry holds.
+    BatchPlan &pp = ctx->pure;
+    if (pp.d_batch && pp.ids.size() == 1 && pp.ids[0] == walk && pp.fixed_n == n_lmt) {
+        if (pp.fixed_start != start) {
+            pp.fixed_start = start;      // the copy's source outlives the call
+            HIP_TRY(ctx, hipMemcpyAsync(reinterpret_cast<char *>(pp.d_batch) + offsetof(BatchEntry, start),
+                                        &pp.fixed_start, sizeof(uint32_t), hipMemcpyHostToDevice, ctx->stream));
+        }
+    } else {
+        const psl_status st = make_plan(ctx, pp, &walk, 1, n_lmt, start);
+        if (st) return st;
+    }
     const Tables tabs = tables_of(ctx);
     HIP_TRY(ctx, launch_suffix(ctx->d_walks, ctx->pure.d_batch, 1, h.L, tabs, 0, nullptr, &ctx->pure.seg,
                                ctx->stream));
@@ -1084,21 +1099,21 @@ psl_status psl_apply_flip(psl_ctx *ctx, uint32_t walk, uint32_t j)
     const WalkHost &h = ctx->walks[walk];
     if (j >= h.L) return fail(ctx, PSL_E_INVAL, "j=%u >= L=%u", j, h.L);
     HIP_TRY(ctx, hipSetDevice(ctx->device));
-    BatchPlan one;
-    void *p;
-    psl_status st = dev_alloc(ctx, &p, sizeof(BatchEntry), false);
-    if (st) return st;
-    one.d_batch = (BatchEntry *)p;
+    if (!ctx->d_one) {
+        void *p;
+        const psl_status st = dev_alloc(ctx, &p, sizeof(BatchEntry), false);
+        if (st) return st;
+        ctx->d_one = (BatchEntry *)p;
+    }
     BatchEntry e;
     memset(&e, 0, sizeof e);
     e.slot = walk;
-    hipError_t r = hipMemcpy(one.d_batch, &e, sizeof e, hipMemcpyHostToDevice);
+    hipError_t r = hipMemcpy(ctx->d_one, &e, sizeof e, hipMemcpyHostToDevice);
     const Tables tabs = tables_of(ctx);
-    if (r == hipSuccess) r = launch_apply(ctx->d_walks, one.d_batch, seg_uniform(1, h.L), (int64_t)j, ctx->stream);
-    if (r == hipSuccess) r = launch_flip_bit(ctx->d_walks, one.d_batch, j, ctx->stream);
-    if (r == hipSuccess) r = launch_fitness(ctx->d_walks, one.d_batch, 1, tabs, 2, ctx->stream);
+    if (r == hipSuccess) r = launch_apply(ctx->d_walks, ctx->d_one, seg_uniform(1, h.L), (int64_t)j, ctx->stream);
+    if (r == hipSuccess) r = launch_flip_bit(ctx->d_walks, ctx->d_one, j, ctx->stream);
+    if (r == hipSuccess) r = launch_fitness(ctx->d_walks, ctx->d_one, 1, tabs, 2, ctx->stream);
     if (r == hipSuccess) r = hipStreamSynchronize(ctx->stream);
-    plan_free(ctx, one);
     if (r != hipSuccess) return fail(ctx, PSL_E_HIP, "apply_flip: %s", hipGetErrorString(r));
     return PSL_OK;
 }

@@ -129,6 +129,7 @@ def parse():
                     help="split evaluation (linear part on the matrix cores): -1 the library default "
                          "(2: for launches of at least 2^34 nominal updates), 0 off (table evaluation), "
                          "1 wherever L >= 2048")
+    ap.add_argument("--tune-file", default="", help="evaluation launch shapes to load (psl_tune_load)")
     ap.add_argument("--eval-items", type=int, default=0,
                     help="minimum work items per evaluation launch (0 = the library default)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -567,6 +568,8 @@ def main():
         ctx.set_option(libpsl.OPT_EVAL_ITEMS, args.eval_items)
     if args.split >= 0:
         ctx.set_option(libpsl.OPT_SPLIT, args.split)
+    if args.tune_file:
+        ctx.tune_load(args.tune_file)
     ids, evals_per_step, updates_per_step = [], 0, 0
     for L, count in groups:
         a2 = 10 if wl == "paper" else si.alpha2_for(L)

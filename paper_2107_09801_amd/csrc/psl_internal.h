@@ -91,6 +91,7 @@ struct BatchPlan {
     std::vector<uint32_t> ids;
     uint32_t max_L = 0, max_nw = 0;
     bool big_flips = false;           // some walk's Rand_flip exceeds the one-flip rebuild
+    uint64_t pend_units = 0;          // work units of the pending-walk rebuild (all walks)
     uint32_t n_items = 0;
     EvalShape shape;                  // evaluation launch shape
     uint32_t comb_blocks = 1;         // combine blocks per walk (selection)

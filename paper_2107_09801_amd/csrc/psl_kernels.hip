@@ -97,17 +97,15 @@ __global__ __launch_bounds__(kCorrThreads) void k_corr(WalkDev *walks, const Bat
 }
 
 // The pending list of a batch: pend[0] = count, pend[1..] = batch positions
-// of the walks whose step ended in a phase switch (k_bookkeep appends, the
-// selection of the next step clears the count).
+// of the walks whose step ended in a phase switch (the bookkeeping appends,
+// the selection of the next step clears the count).
 //
 // C of a switched pivot from C of local_best: the FLIP_lmt one-element flips
 // in draw order, where flip f sees local_best with flips 0..f-1 applied.
 // Element x of that sequence differs from local_best only if x is an earlier
 // flip position, and flip f reads elements p_f and p_f +- k; so for every k
 // outside D = {|p_f - p_g| : g < f} the update can read local_best's bits
-// directly. k_switch_corr does that for all k (all blocks work through the
-// pending walks in turn); k_switch_fix then recomputes the shifts in D with
-// the sequential bits (one block per pending walk, one thread per pair).
+// directly, and the shifts in D take the sequential bits.
 __device__ __forceinline__ int32_t switch_flip_delta(const uint64_t *lb, uint32_t L, uint32_t k, uint32_t p)
 {
     const int sp = get_bit(lb, p) ? -1 : 1;
@@ -117,78 +115,159 @@ __device__ __forceinline__ int32_t switch_flip_delta(const uint64_t *lb, uint32_
     return -2 * sp * d;
 }
 
-// C[k] for k = k_first, k_first + stride, ... < L from C of local_best. C and
-// C_lb are separate arrays: each thread computes two shifts before it stores
-// either.
-__device__ __forceinline__ void switch_corr_range(int32_t *__restrict__ C, const int32_t *__restrict__ C_lb,
-                                                  const uint64_t *__restrict__ lb, uint32_t L,
-                                                  const uint32_t *fl, uint32_t nf, uint32_t k_first,
-                                                  uint32_t stride)
+// C_k of the switched pivot for a shift k in D: each flip reads the elements
+// as the earlier flips left them.
+__device__ __forceinline__ int32_t switch_corr_seq(const uint64_t *lb, const int32_t *C_lb, uint32_t L,
+                                                   uint32_t k, const uint32_t *fl, uint32_t nf)
 {
-    for (uint32_t k = k_first; k < L; k += 2 * stride) {
-        const uint32_t k2 = k + stride;
-        int32_t c = k == 0 ? (int32_t)L : C_lb[k];
-        int32_t c2 = k2 < L ? C_lb[k2] : 0;
-        for (uint32_t f = 0; f < nf; ++f) {
-            if (k != 0) c += switch_flip_delta(lb, L, k, fl[f]);
-            if (k2 < L) c2 += switch_flip_delta(lb, L, k2, fl[f]);
-        }
-        C[k] = c;
-        if (k2 < L) C[k2] = c2;
+    int32_t c = C_lb[k];
+    for (uint32_t h = 0; h < nf; ++h) {
+        // element x after flips 0..h-1
+        auto bit = [&](uint32_t x) {
+            uint32_t v = get_bit(lb, x);
+            for (uint32_t e = 0; e < h; ++e) v ^= (fl[e] == x) ? 1u : 0u;
+            return v;
+        };
+        const uint32_t p = fl[h];
+        const int sp = bit(p) ? -1 : 1;
+        int d = 0;
+        if (p + k < L) d += bit(p + k) ? -1 : 1;
+        if (k <= p) d += bit(p - k) ? -1 : 1;
+        c -= 2 * sp * d;
     }
+    return c;
 }
 
-__global__ __launch_bounds__(256) void k_switch_corr(WalkDev *walks, const BatchEntry *batch,
-                                                     const uint32_t *pend)
+// After the step's bookkeeping, in two launches: C of every pending walk's
+// new pivot from C of its local best (a switch of more than kFlipIncremental
+// flips has C rebuilt by k_corr before), then F (Eq. (5)) and the PSL (Eq.
+// (3)) of that pivot, which become F_pivot, psl_pivot and v_local.
+// k_pending: work units of kPendUnit shifts are dealt round-robin over the
+// grid, walk after walk. A unit marks the shifts of D in its range in an LDS
+// bitmap, computes and stores its C values, and leaves the sum of T(|C_k|)
+// (lanes, then wavefronts, in a fixed order) and the maximum |C_k| in the
+// walk's chunk arrays. k_pending_fin adds each walk's unit sums in unit order.
+constexpr int kPendThreads = 256;
+
+__global__ __launch_bounds__(kPendThreads) void k_pending(WalkDev *walks, const BatchEntry *batch, Tables tabs,
+                                                          const uint32_t *pend)
 {
     __shared__ uint32_t s_fl[kFlipIncremental];
+    __shared__ uint32_t s_in[kPendUnit / 32];
+    __shared__ double s_s[kPendThreads / 64], s_c[kPendThreads / 64];
+    __shared__ uint32_t s_m[kPendThreads / 64];
     const uint32_t np = pend[0];
+    const uint32_t G = gridDim.x;
+    const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
+    uint32_t base = 0;                  // units of the earlier pending walks
     for (uint32_t q = 0; q < np; ++q) {
-        WalkDev &w = walks[batch[pend[1 + q]].slot];
+        const BatchEntry be = batch[pend[1 + q]];
+        WalkDev &w = walks[be.slot];
+        const uint32_t L = w.L;
+        const uint32_t nu = (L - 1 + kPendUnit - 1) / kPendUnit;
         const uint32_t nf = w.n_flips;
-        if (nf > kFlipIncremental) continue;      // rebuilt by k_corr
-        __syncthreads();
-        if (threadIdx.x < nf) s_fl[threadIdx.x] = w.flips[threadIdx.x];
-        __syncthreads();
-        switch_corr_range(w.C, w.C_lb, w.local_best, w.L, s_fl, nf, blockIdx.x * blockDim.x + threadIdx.x,
-                          gridDim.x * blockDim.x);
+        const bool incr = nf <= kFlipIncremental;
+        const double *T = tabs.T[w.alpha];
+        for (uint32_t u = (blockIdx.x + G - base % G) % G; u < nu; u += G) {
+            const uint32_t k_lo = 1 + u * kPendUnit, k_hi = min(L, k_lo + kPendUnit);
+            __syncthreads();            // the previous unit is done with the LDS
+            if (incr) {
+                if (threadIdx.x < nf) s_fl[threadIdx.x] = w.flips[threadIdx.x];
+                if (threadIdx.x < kPendUnit / 32) s_in[threadIdx.x] = 0;
+            }
+            __syncthreads();
+            if (incr) {
+                for (uint32_t pr = threadIdx.x; pr < nf * nf; pr += kPendThreads) {
+                    const uint32_t f = pr / nf, g = pr - f * nf;
+                    if (g >= f) continue;
+                    const uint32_t k = s_fl[f] > s_fl[g] ? s_fl[f] - s_fl[g] : s_fl[g] - s_fl[f];
+                    if (k >= k_lo && k < k_hi) atomicOr(&s_in[(k - k_lo) >> 5], 1u << ((k - k_lo) & 31u));
+                }
+            }
+            __syncthreads();
+            double ts = 0.0, tc = 0.0;
+            uint32_t tm = 0;
+            for (uint32_t k = k_lo + threadIdx.x; k < k_hi; k += kPendThreads) {
+                int32_t c;
+                if (incr) {
+                    const uint32_t o = k - k_lo;
+                    if ((s_in[o >> 5] >> (o & 31u)) & 1u) {
+                        c = switch_corr_seq(w.local_best, w.C_lb, L, k, s_fl, nf);
+                    } else {
+                        c = w.C_lb[k];
+                        for (uint32_t f = 0; f < nf; ++f) c += switch_flip_delta(w.local_best, L, k, s_fl[f]);
+                    }
+                    w.C[k] = c;
+                } else {
+                    c = w.C[k];
+                }
+                const uint32_t a = (uint32_t)(c < 0 ? -c : c);
+                nsum_add(ts, tc, T[a]);
+                tm = max(tm, a);
+            }
+            // every lane of the butterfly ends with the same sums
+            for (int o = 32; o > 0; o >>= 1) {
+                const double ps = __shfl_xor(ts, o), pc = __shfl_xor(tc, o);
+                const uint32_t pm = (uint32_t)__shfl_xor((int)tm, o);
+                nsum_add(ts, tc, ps);
+                tc += pc;
+                tm = max(tm, pm);
+            }
+            if (lane == 0) {
+                s_s[wave] = ts;
+                s_c[wave] = tc;
+                s_m[wave] = tm;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double us = 0.0, uc = 0.0;
+                uint32_t um = 0;
+                for (int x = 0; x < kPendThreads / 64; ++x) {
+                    nsum_add(us, uc, s_s[x]);
+                    uc += s_c[x];
+                    um = max(um, s_m[x]);
+                }
+                be.S0[2 * u] = us;
+                be.S0[2 * u + 1] = uc;
+                be.M0[u] = um;
+            }
+        }
+        base += nu;
     }
 }
 
-__global__ __launch_bounds__(256) void k_switch_fix(WalkDev *walks, const BatchEntry *batch,
-                                                    const uint32_t *pend)
+// One wavefront per pending walk: the units' sums in unit order.
+__global__ __launch_bounds__(64) void k_pending_fin(WalkDev *walks, const BatchEntry *batch, const uint32_t *pend)
 {
-    __shared__ uint32_t s_fl[kFlipIncremental];
     const uint32_t np = pend[0];
+    const int lane = (int)threadIdx.x;
     for (uint32_t q = blockIdx.x; q < np; q += gridDim.x) {
-        WalkDev &w = walks[batch[pend[1 + q]].slot];
-        const uint32_t nf = w.n_flips;
-        if (nf > kFlipIncremental) continue;
-        __syncthreads();
-        if (threadIdx.x < nf) s_fl[threadIdx.x] = w.flips[threadIdx.x];
-        __syncthreads();
-        const uint32_t L = w.L;
-        const uint64_t *lb = w.local_best;
-        for (uint32_t pr = threadIdx.x; pr < nf * nf; pr += blockDim.x) {
-            const uint32_t f = pr / nf, g = pr - f * nf;
-            if (g >= f) continue;
-            const uint32_t k = s_fl[f] > s_fl[g] ? s_fl[f] - s_fl[g] : s_fl[g] - s_fl[f];
-            // element x after flips 0..h-1
-            auto bit = [&](uint32_t x, uint32_t h) {
-                uint32_t v = get_bit(lb, x);
-                for (uint32_t e = 0; e < h; ++e) v ^= (s_fl[e] == x) ? 1u : 0u;
-                return v;
-            };
-            int32_t c = w.C_lb[k];
-            for (uint32_t h = 0; h < nf; ++h) {
-                const uint32_t p = s_fl[h];
-                const int sp = bit(p, h) ? -1 : 1;
-                int d = 0;
-                if (p + k < L) d += bit(p + k, h) ? -1 : 1;
-                if (k <= p) d += bit(p - k, h) ? -1 : 1;
-                c -= 2 * sp * d;
-            }
-            w.C[k] = c;
+        const BatchEntry be = batch[pend[1 + q]];
+        WalkDev &w = walks[be.slot];
+        const uint32_t nu = (w.L - 1 + kPendUnit - 1) / kPendUnit;
+        // lane l adds units l, l + 64, ... in order, then the lanes in a
+        // fixed butterfly (every lane ends with the same sums)
+        double s = 0.0, c = 0.0;
+        uint32_t m = 0;
+        for (uint32_t x = (uint32_t)lane; x < nu; x += 64) {
+            nsum_add(s, c, be.S0[2 * x]);
+            c += be.S0[2 * x + 1];
+            m = max(m, be.M0[x]);
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ps = __shfl_xor(s, o), pc = __shfl_xor(c, o);
+            const uint32_t pm = (uint32_t)__shfl_xor((int)m, o);
+            nsum_add(s, c, ps);
+            c += pc;
+            m = max(m, pm);
+        }
+        if (lane == 0) {
+            const double F = s + c;
+            w.F_pivot = F;
+            w.psl_pivot = (int32_t)m;
+            w.value_local = F;
+            w.unimproved = 0;
+            w.pending = 0;
         }
     }
 }
@@ -310,27 +389,12 @@ __device__ __forceinline__ void chunk_pairs(const BatchEntry &be, const WalkDev 
 }
 
 // Mode 0 (step, with the near list) and 2 (init): one block per segment of
-// the map. Mode 1: the whole grid works through the pending walks in turn.
+// the map.
 __global__ __launch_bounds__(kChunkThreads) void k_chunks(const WalkDev *walks, const BatchEntry *batch,
-                                                          Tables tabs, int mode, const uint32_t *pend,
-                                                          SegMap map)
+                                                          Tables tabs, int mode, SegMap map)
 {
     const int wave = (int)threadIdx.x >> 6;
     constexpr int kWaves = kChunkThreads / 64;
-    if (mode == 1) {
-        const int gw = (int)blockIdx.x * kWaves + wave;
-        const int nwaves = (int)gridDim.x * kWaves;
-        const uint32_t nq = pend[0];
-        for (uint32_t qi = 0; qi < nq; ++qi) {
-            const BatchEntry be = batch[pend[1 + qi]];
-            const WalkDev &w = walks[be.slot];
-            const int npairs = ((int)w.L - 1 + 63) / 64;
-            double ws = 0.0, wc = 0.0;
-            uint32_t wm = 0;
-            chunk_pairs(be, w, tabs.T[w.alpha], INT_MAX, false, gw, npairs, nwaves, ws, wc, wm);
-        }
-        return;
-    }
     uint32_t b, seg;
     seg_of(map, blockIdx.x, b, seg);
     const BatchEntry be = batch[b];
@@ -450,15 +514,11 @@ __global__ __launch_bounds__(kSegScanThreads) void k_seg_scan(const WalkDev *wal
 }
 
 constexpr int kScanThreads = 1024;
-__global__ __launch_bounds__(kScanThreads) void k_scan(WalkDev *walks, const BatchEntry *batch, int mode,
-                                                      const uint32_t *pend)
+// The initial fitness: block b scans walk b's chunk sums into suffix values
+// and sets value_local, F_pivot, psl_pivot and psl_best.
+__global__ __launch_bounds__(kScanThreads) void k_scan(WalkDev *walks, const BatchEntry *batch)
 {
-    // mode 1: block g takes pending walks g, g + gridDim.x, ...; otherwise
-    // blockIdx.x is the walk
-    const uint32_t nq = mode == 1 ? pend[0] : blockIdx.x + 1;
-    for (uint32_t qi = blockIdx.x; qi < nq; qi += gridDim.x) {
-    __syncthreads();
-    const BatchEntry be = batch[mode == 1 ? pend[1 + qi] : qi];
+    const BatchEntry be = batch[blockIdx.x];
     WalkDev &w = walks[be.slot];
     const int L = (int)w.L;
     const int nchunks = (L - 1 + 31) / 32;
@@ -535,20 +595,12 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(WalkDev *walks, const Bat
     if (threadIdx.x == 0) {
         be.S0[nchunks] = 0.0;
         be.M0[nchunks] = 0;
-        if (mode != 0) {
-            // thread 0's segment starts at chunk 0: the totals over k >= 1
-            const double F = ts + tc;
-            w.F_pivot = F;
-            w.psl_pivot = (int32_t)tm;
-            w.value_local = F;
-            if (mode == 1) {
-                w.unimproved = 0;
-                w.pending = 0;
-            } else {
-                w.psl_best = (int32_t)tm;
-            }
-        }
-    }
+        // thread 0's segment starts at chunk 0: the totals over k >= 1
+        const double F = ts + tc;
+        w.F_pivot = F;
+        w.psl_pivot = (int32_t)tm;
+        w.value_local = F;
+        w.psl_best = (int32_t)tm;
     }
 }
 
@@ -962,37 +1014,13 @@ __device__ __forceinline__ void apply_range(int32_t *__restrict__ C, int32_t *__
     }
 }
 
-__global__ __launch_bounds__(kApplyThreads) void k_apply(WalkDev *walks, const BatchEntry *batch,
-                                                         int64_t j_fixed, SegMap map)
-{
-    uint32_t bi, seg;
-    seg_of(map, blockIdx.x, bi, seg);
-    WalkDev &w = walks[batch[bi].slot];
-    const uint32_t L = w.L;
-    const uint32_t j = j_fixed >= 0 ? (uint32_t)j_fixed : w.k;
-    const uint64_t *b = w.pivot;
-    const int sj = get_bit(b, j) ? -1 : 1;
-    // the move improves on v_local: the new pivot becomes local_best
-    const bool lb = j_fixed < 0 && (w.flags & STEP_IMPROVED);
-    const uint32_t k0 = 1u + (seg << map.shift);
-    const uint32_t k1 = min(L, k0 + (1u << map.shift));
-    apply_range(w.C, w.C_lb, b, L, j, sj, lb, k0, k1);
-}
-
-// Flip(pivot, j), part 2, for a forced flip: the bit itself.
-__global__ void k_flip_bit(WalkDev *walks, const BatchEntry *batch, uint32_t j)
-{
-    WalkDev &w = walks[batch[0].slot];
-    if (threadIdx.x == 0) w.pivot[j >> 6] ^= 1ull << (j & 63u);
-}
-
 constexpr int kBookThreads = 256;
 
-// The rest of one loop iteration of Algorithm 1 after the C update: the
-// move's bit, the three-way comparison with v_local, the unimproved counter,
-// the local best, and the phase switch (Rand_flip of the local best and the
-// exponent swap; the walk joins the batch's pending list, whose C, F and PSL
-// the switch kernels and the chunk pass in mode 1 then rebuild).
+// The rest of one loop iteration of Algorithm 1 after the C update, one block
+// per walk: the move's bit, the three-way comparison with v_local, the
+// unimproved counter, the local best, and the phase switch (Rand_flip of the
+// local best and the exponent swap; the walk joins the batch's pending list,
+// whose C, F and PSL k_pending then rebuilds).
 __global__ __launch_bounds__(kBookThreads) void k_bookkeep(WalkDev *walks, const BatchEntry *batch,
                                                            uint32_t *pend)
 {
@@ -1063,6 +1091,30 @@ __global__ __launch_bounds__(kBookThreads) void k_bookkeep(WalkDev *walks, const
     }
 }
 
+__global__ __launch_bounds__(kApplyThreads) void k_apply(WalkDev *walks, const BatchEntry *batch,
+                                                         int64_t j_fixed, SegMap map)
+{
+    uint32_t bi, seg;
+    seg_of(map, blockIdx.x, bi, seg);
+    WalkDev &w = walks[batch[bi].slot];
+    const uint32_t L = w.L;
+    const uint32_t j = j_fixed >= 0 ? (uint32_t)j_fixed : w.k;
+    const uint64_t *b = w.pivot;
+    const int sj = get_bit(b, j) ? -1 : 1;
+    // the move improves on v_local: the new pivot becomes local_best
+    const bool lb = j_fixed < 0 && (w.flags & STEP_IMPROVED);
+    const uint32_t k0 = 1u + (seg << map.shift);
+    const uint32_t k1 = min(L, k0 + (1u << map.shift));
+    apply_range(w.C, w.C_lb, b, L, j, sj, lb, k0, k1);
+}
+
+// Flip(pivot, j), part 2, for a forced flip: the bit itself.
+__global__ void k_flip_bit(WalkDev *walks, const BatchEntry *batch, uint32_t j)
+{
+    WalkDev &w = walks[batch[0].slot];
+    if (threadIdx.x == 0) w.pivot[j >> 6] ^= 1ull << (j & 63u);
+}
+
 // ------------------------------------------------------------ launches
 
 hipError_t launch_power_table(double *T, uint32_t n, uint32_t alpha, hipStream_t s)
@@ -1095,16 +1147,16 @@ hipError_t launch_corr(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uin
     return hipSuccess;
 }
 
-hipError_t launch_switch_corr(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t max_L,
-                              const uint32_t *pend, hipStream_t s)
+hipError_t launch_pending(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint64_t units,
+                          const Tables &tabs, const uint32_t *pend, hipStream_t s)
 {
-    // the pending walks one after another over about 2048 blocks, then the
-    // shifts whose bits an earlier flip of the same switch changed
-    const uint32_t bx = std::max<uint32_t>(1, std::min<uint32_t>(2048, (max_L + 255) / 256));
-    k_switch_corr<<<bx, 256, 0, s>>>(walks, batch, pend);
+    if (!pend) return hipErrorInvalidValue;
+    // every unit of the batch's walks gets a block when all of them switch
+    const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(4096, units));
+    k_pending<<<grid, kPendThreads, 0, s>>>(walks, batch, tabs, pend);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_switch_fix<<<std::min<uint32_t>(nb, 256), 256, 0, s>>>(walks, batch, pend);
+    k_pending_fin<<<std::max<uint32_t>(1, std::min<uint32_t>(nb, 1024)), 64, 0, s>>>(walks, batch, pend);
     return hipGetLastError();
 }
 
@@ -1116,26 +1168,15 @@ hipError_t launch_fitness(WalkDev *walks, const BatchEntry *batch, uint32_t nb, 
 }
 
 hipError_t launch_suffix(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t max_L,
-                         const Tables &tabs, int mode, const uint32_t *pend, const SegMap *map, hipStream_t s)
+                         const Tables &tabs, int mode, const SegMap *map, hipStream_t s)
 {
-    if (mode == 1) {
-        // the pending walks of the batch, one after another over the grid
-        if (!pend) return hipErrorInvalidValue;
-        const uint32_t nchunks = (max_L - 1 + 31) / 32;
-        const uint32_t bx = std::max<uint32_t>(1, std::min<uint32_t>(1024, (nchunks + 7) / 8));
-        k_chunks<<<bx, kChunkThreads, 0, s>>>(walks, batch, tabs, mode, pend,
-                                              SegMap{nullptr, 1, 1, 1, 12, nullptr, nullptr});
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        k_scan<<<std::min<uint32_t>(nb, 256), kScanThreads, 0, s>>>(walks, batch, mode, pend);
-        return hipGetLastError();
-    }
+    if (mode != 0 && mode != 2) return hipErrorInvalidValue;
     if (!map || map->total == 0 || map->nb != nb || map->shift < kSegShiftMin || map->shift > kSegShiftMax)
         return hipErrorInvalidValue;
     if (mode == 0 && (!map->tot || !map->tmax)) return hipErrorInvalidValue;
     SegMap m = *map;
     if (mode != 0) m.tot = nullptr, m.tmax = nullptr;
-    k_chunks<<<m.total, kChunkThreads, 0, s>>>(walks, batch, tabs, mode, nullptr, m);
+    k_chunks<<<m.total, kChunkThreads, 0, s>>>(walks, batch, tabs, mode, m);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (mode == 0) {
@@ -1144,7 +1185,7 @@ hipError_t launch_suffix(WalkDev *walks, const BatchEntry *batch, uint32_t nb, u
         k_seg_scan<<<(m.total + per - 1) / per, kSegScanThreads, 0, s>>>(walks, batch, m);
     } else {
         // the initial fitness: totals per walk
-        k_scan<<<nb, kScanThreads, 0, s>>>(walks, batch, mode, nullptr);
+        k_scan<<<nb, kScanThreads, 0, s>>>(walks, batch);
     }
     return hipGetLastError();
 }

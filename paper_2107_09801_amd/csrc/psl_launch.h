@@ -10,19 +10,21 @@ hipError_t launch_init_bits(WalkDev *walks, const BatchEntry *batch, const uint3
                             uint32_t nb, uint32_t max_nw, hipStream_t s);
 hipError_t launch_corr(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t max_L,
                        int only_pending, hipStream_t s);
-// pend: the batch's pending list (count, then batch positions).
-hipError_t launch_switch_corr(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t max_L,
-                              const uint32_t *pend, hipStream_t s);
+// After the step's C update and bookkeeping: C, F and PSL of the walks on the
+// pending list (pend: count, then batch positions) that switched phase, in
+// work units of kPendUnit shifts (units: how many the batch's nb walks hold in
+// all).
+hipError_t launch_pending(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint64_t units,
+                          const Tables &tabs, const uint32_t *pend, hipStream_t s);
 hipError_t launch_fitness(WalkDev *walks, const BatchEntry *batch, uint32_t nb, const Tables &tabs,
                           int mode, hipStream_t s);
 hipError_t launch_eval(const WalkDev *walks, const BatchEntry *batch, const EvalItem *items,
                        uint32_t n_items, const Tables &tabs, const EvalShape &shape,
                        EvalQueues *queues, hipStream_t s);
-// mode 0: the step's chunk suffix arrays and near-peak list; mode 1: the
-// fitness of pending walks after a phase switch; mode 2: the initial fitness
-// (value_local, F_pivot, psl_pivot, psl_best) of every walk.
+// mode 0: the step's chunk suffix arrays and near-peak list; mode 2: the
+// initial fitness (value_local, F_pivot, psl_pivot, psl_best) of every walk.
 hipError_t launch_suffix(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t max_L,
-                         const Tables &tabs, int mode, const uint32_t *pend, const SegMap *map, hipStream_t s);
+                         const Tables &tabs, int mode, const SegMap *map, hipStream_t s);
 // Zero the near-peak counts of a batch, its pending count and its combine
 // counters (done, nb entries; may be null) after its scratch is allocated.
 hipError_t launch_near_reset(const BatchEntry *batch, uint32_t nb, uint32_t *pend, uint32_t *done, hipStream_t s);
@@ -38,10 +40,16 @@ hipError_t launch_select(WalkDev *walks, const BatchEntry *batch, uint32_t nb, u
 size_t choice_dev_size();
 void choice_dev_unpack(const void *p, uint32_t *i_best, uint32_t *j_best, double *F_best,
                        double *F_min, uint32_t *j_psl, int32_t *psl_min, int32_t *psl_k, uint32_t *flags);
+// The C update of each walk's recorded move (j_fixed < 0) or of a forced flip
+// of element j_fixed.
 hipError_t launch_apply(WalkDev *walks, const BatchEntry *batch, const SegMap &map, int64_t j_fixed,
                         hipStream_t s);
 hipError_t launch_flip_bit(WalkDev *walks, const BatchEntry *batch, uint32_t j, hipStream_t s);
+// The step's bookkeeping after the C update (pend: the pending list the
+// walks that switch phase join).
 hipError_t launch_bookkeep(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t *pend, hipStream_t s);
+// Units of launch_pending for walks of length L.
+inline uint64_t pending_units(uint32_t L) { return (L - 1 + kPendUnit - 1) / kPendUnit; }
 
 // Split evaluation (psl_split.hip): the step's coefficients, digits, prefix
 // sums, scale and path choice of the batch's split walks (after the suffix

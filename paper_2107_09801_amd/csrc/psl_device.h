@@ -21,7 +21,6 @@ constexpr int kPairs = kTileK / 2;   // shift pairs per tile
 constexpr int kRowStride = 5;        // T(|C_k + 2m|), m = -2..2
 constexpr int kNearCap = 4096;       // capacity of the near-peak shift list
 constexpr uint32_t kFlipIncremental = 64;  // Rand_flip sizes rebuilt by one-flip updates
-constexpr uint32_t kPendUnit = 1024;        // shifts per work unit of the pending-walk rebuild
 
 // Guard words (64-bit) before and after the pivot's bits: every bit window
 // the evaluation reads (j +- k for j < L, k < L, plus one window) lies inside

@@ -10,6 +10,8 @@ hipError_t launch_init_bits(WalkDev *walks, const BatchEntry *batch, const uint3
                             uint32_t nb, uint32_t max_nw, hipStream_t s);
 hipError_t launch_corr(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t max_L,
                        int only_pending, hipStream_t s);
+constexpr uint32_t kPendUnit = 1024;   // shifts per work unit of the pending-walk rebuild
+
 // After the step's C update and bookkeeping: C, F and PSL of the walks on the
 // pending list (pend: count, then batch positions) that switched phase, in
 // work units of kPendUnit shifts (units: how many the batch's nb walks hold in

@@ -10,8 +10,17 @@
 //      continuous batching), and
 //   5. retires the walks that reached their budget: their record and best
 //      sequence are copied to pinned host memory behind an event, and their
-//      slab and slot are released (later reuse is ordered after the copy on
-//      the same stream).
+//      slot is released (later reuse is ordered after the copy on the same
+//      stream); the slab is freed later, with others, after a stream sync.
+// Device memory: each walk slab is an allocation of its own, of its size
+// class; retired slabs wait in a pool, where a later job of the same class
+// takes one over (the stream orders its use after the retired walk's
+// read-back), until the pool is freed. The scratch buffers of the batch and
+// of admissions grow and shrink within the sum of the admitted jobs' scratch
+// bounds (plus kServeFixed). A job is admitted while the admitted jobs'
+// footprints (slab class + scratch bound), the pooled slabs and any scratch
+// beyond that sum fit in hbm_budget, so the loop's device memory stays within
+// hbm_budget + kServeFixed.
 // No step waits on the host: at most two iterations are in flight, and the
 // host only waits for the iteration two back before reusing its staging.
 #include "psl_internal.h"
@@ -19,6 +28,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <map>
 #include <thread>
 
 using namespace psl;
@@ -33,21 +43,63 @@ uint64_t now_ns()
                std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// Upper bound of the evaluation scratch one walk can need in a batch (the
-// number of k-splits grows only while the batch has few candidate tiles).
-size_t scratch_bound(uint32_t L, uint32_t n_lmt)
+// Largest k-splits x candidates, and k-splits x candidate tiles, a walk of
+// length L with n_lmt candidates gets in any batch: a batch's work only
+// lengthens the work items, so the walk alone with the largest work-item
+// target items_cap bounds both, over the three tile widths.
+void split_bound(uint32_t L, uint32_t n_lmt, uint32_t items_cap, uint64_t *ks_n, uint64_t *ks_tiles)
 {
-    const uint64_t tiles = (n_lmt + 64 * kEvalWavesSmall - 1) / (64 * kEvalWavesSmall);
-    const uint64_t ks_max = std::max<uint64_t>(1, ((L - 1 + 31) / 32) / (kTileK / 32));
-    const uint64_t ks = std::min<uint64_t>(ks_max, (4096 + tiles - 1) / tiles);
-    return (size_t)(12ull * ks * n_lmt + 12ull * n_lmt + 24ull * suffix_len(L) +
-                    4ull * (kNearCap + 1) + sizeof(SelPart) * kCombMaxBlocks + sizeof(BatchEntry) +
-                    sizeof(EvalItem) * ks * tiles);
+    *ks_n = 0;
+    *ks_tiles = 0;
+    for (int waves : {kEvalWavesSmall, kEvalWaves, kEvalWavesMax}) {
+        const uint32_t tile = 64u * (uint32_t)waves;
+        const uint64_t tiles = (n_lmt + tile - 1) / tile;
+        const uint32_t K = item_shifts_for(tiles * (L - 1), tile, items_cap);
+        uint32_t t = 0, ks = 0;
+        eval_shape_k(L, n_lmt, K, tile, &t, &ks);
+        *ks_n = std::max<uint64_t>(*ks_n, (uint64_t)ks * n_lmt);
+        *ks_tiles = std::max<uint64_t>(*ks_tiles, (uint64_t)ks * t);
+    }
 }
 
-size_t job_footprint(const psl_walk_cfg &c)
+// Upper bound of one walk's share of the scratch buffers of any batch and
+// admission it is in.
+size_t scratch_bound(uint32_t L, uint32_t n_lmt, uint32_t items_cap)
 {
-    return slab_layout(c.L).slab_bytes + scratch_bound(c.L, c.n_lmt ? c.n_lmt : c.L);
+    uint64_t ks_n = 0, ks_tiles = 0;
+    split_bound(L, n_lmt, items_cap, &ks_n, &ks_tiles);
+    const uint64_t segs = seg_count(L, kSegShiftMin);
+    return (size_t)(12ull * ks_n                           // partial sums and maxima
+                    + 12ull * n_lmt                        // F and PSL per candidate
+                    + 24ull * suffix_len(L)                // chunk suffix arrays: step, admission
+                    + 4ull * (kNearCap + 1)                // near-peak list
+                    + sizeof(SelPart) * kCombMaxBlocks     // combine-block minima
+                    + 2 * sizeof(BatchEntry) + 32          // batch and admission entries, list slots
+                    + sizeof(EvalItem) * 8 * ks_tiles      // work items, with the flat form's padding
+                    + 12ull * segs);                       // per-segment totals of the O(L) passes
+}
+
+// Scratch capacity beyond the jobs' bounds: the buffers' smallest size
+// (kMinCap elements each) and the queue record.
+constexpr size_t kMinCap = 1024;
+constexpr size_t kServeFixed = (size_t)1 << 20;
+// The slab pool is freed once it holds this many slabs (or bytes).
+constexpr size_t kFlushSlabs = 1024;
+constexpr size_t kFlushBytes = (size_t)256 << 20;
+
+// Slab allocation size: 4 KiB steps up to 64 KiB, then eight classes per
+// power of two (at most 1/8 more than the slab).
+size_t slab_class(size_t bytes)
+{
+    if (bytes <= ((size_t)64 << 10)) return align_up(std::max<size_t>(bytes, 1), (size_t)4 << 10);
+    size_t p = (size_t)64 << 10;
+    while (2 * p <= bytes) p *= 2;
+    return align_up(bytes, p / 8);
+}
+
+size_t job_footprint(const psl_walk_cfg &c, uint32_t items_cap)
+{
+    return slab_class(slab_layout(c.L).slab_bytes) + scratch_bound(c.L, c.n_lmt ? c.n_lmt : c.L, items_cap);
 }
 
 struct Job {
@@ -56,7 +108,8 @@ struct Job {
     uint64_t budget = 0;
     uint64_t *best_out = nullptr;
     uint64_t t_arrive = 0, t_admit = 0;
-    size_t foot = 0;
+    size_t foot = 0;          // slab + scratch bound, counted against the budget
+    size_t bound = 0;         // scratch bound
     uint32_t slot = UINT32_MAX;
     void *slab = nullptr;
     WalkDev dev{};            // device pointers of the walk
@@ -91,9 +144,12 @@ struct Server {
     // scheduler-owned
     std::deque<Job> pending;
     std::vector<Job> active, retiring;
-    size_t used = 0;
-    char *arena_mem = nullptr;
-    Arena arena;
+    size_t used = 0;              // footprints of the admitted jobs
+    size_t bounds = 0;            // their scratch bounds
+    uint32_t items_cap = 0;       // largest work-item target of the context
+    size_t dev_scratch = 0;       // capacity of the scratch buffers, bytes
+    std::multimap<size_t, void *> to_free;     // retired slabs by size class
+    size_t to_free_bytes = 0;
     DevBuf<BatchEntry> d_batch, d_admit;
     DevBuf<EvalItem> d_items;
     DevBuf<double> d_fpart, d_f, d_s0;
@@ -132,26 +188,30 @@ struct Server {
     void retire_finished();
     void fail_all(int32_t status);
     void finish(Job &j, int32_t status);
+    // scratch beyond what the admitted jobs' bounds allow
+    size_t scratch_over() const
+    {
+        const size_t allow = bounds + kServeFixed;
+        return dev_scratch > allow ? dev_scratch - allow : 0;
+    }
+    psl_status flush_free();
+    psl_status release_scratch();
+    struct BufNeed {
+        void **p;
+        size_t *cap;
+        size_t elem;
+        size_t need;
+    };
+    template <class T>
+    static BufNeed buf(DevBuf<T> &b, size_t n)
+    {
+        return BufNeed{(void **)&b.p, &b.cap, sizeof(T), n};
+    }
+    psl_status size_bufs(std::initializer_list<BufNeed> bufs);
+    std::vector<BufNeed> all_bufs();
 };
 
 namespace {
-
-template <class T>
-psl_status grow(psl_ctx *ctx, DevBuf<T> &b, size_t n)
-{
-    if (n <= b.cap) return PSL_OK;
-    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    dev_free(ctx, b.p, false);
-    b.p = nullptr;
-    b.cap = 0;
-    size_t c = std::max<size_t>(n + n / 2, 1024);
-    void *p;
-    psl_status st = dev_alloc(ctx, &p, sizeof(T) * c, false);
-    if (st) return st;
-    b.p = (T *)p;
-    b.cap = c;
-    return PSL_OK;
-}
 
 template <class T>
 void release(psl_ctx *ctx, DevBuf<T> &b)
@@ -213,7 +273,8 @@ void Server::fail_all(int32_t status)
     for (auto &j : retiring) finish(j, status);
     retiring.clear();
     for (auto &j : active) {
-        if (j.slab) arena.release(j.slab);
+        dev_free(ctx, j.slab, false);
+        j.slab = nullptr;
         if (j.slot != UINT32_MAX) {
             ctx->walks[j.slot] = WalkHost();
             ctx->free_slots.push_back(j.slot);
@@ -222,7 +283,82 @@ void Server::fail_all(int32_t status)
     }
     active.clear();
     used = 0;
+    bounds = 0;
+    (void)flush_free();
     dirty = true;
+}
+
+// Frees the pooled slabs (their read-backs are queued before the sync).
+psl_status Server::flush_free()
+{
+    if (to_free.empty()) return PSL_OK;
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    for (auto &f : to_free) dev_free(ctx, f.second, false);
+    to_free.clear();
+    to_free_bytes = 0;
+    return PSL_OK;
+}
+
+std::vector<Server::BufNeed> Server::all_bufs()
+{
+    return {buf(d_batch, 0),  buf(d_admit, 0),  buf(d_items, 0),   buf(d_fpart, 0),  buf(d_f, 0),
+            buf(d_s0, 0),     buf(d_mpart, 0),  buf(d_m0, 0),      buf(d_near, 0),   buf(d_want, 0),
+            buf(d_red, 0),    buf(d_pend, 0),   buf(d_done, 0),    buf(d_seg, 0),    buf(d_adm_seg, 0),
+            buf(d_segtot, 0), buf(d_segmax, 0), buf(d_adm_s0, 0),  buf(d_adm_m0, 0), buf(d_p, 0),
+            buf(d_queues, 0)};
+}
+
+// Frees every scratch buffer (they grow again with the next layout).
+psl_status Server::release_scratch()
+{
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    for (auto &b : all_bufs()) {
+        dev_free(ctx, *b.p, false);
+        *b.p = nullptr;
+        *b.cap = 0;
+    }
+    dev_scratch = 0;
+    dirty = true;
+    return PSL_OK;
+}
+
+// Gives each listed buffer at least its need: 1.5 x the need when a buffer
+// grows, or, when that would take the scratch past the admitted jobs' bounds,
+// exactly the need (at least kMinCap), shrinking the listed buffers that hold
+// more. A resize waits for the stream first (work queued earlier may still
+// read the old buffer); contents are not kept.
+psl_status Server::size_bufs(std::initializer_list<BufNeed> bufs)
+{
+    size_t grown = dev_scratch;
+    bool any = false;
+    for (const BufNeed &b : bufs) {
+        if (b.need <= *b.cap) continue;
+        any = true;
+        grown += (std::max(b.need + b.need / 2, kMinCap) - *b.cap) * b.elem;
+    }
+    const bool tight = grown > bounds + kServeFixed;
+    if (!any && !tight) return PSL_OK;
+    bool synced = false;
+    for (const BufNeed &b : bufs) {
+        const size_t want = tight ? std::max(b.need, kMinCap)
+                                  : (b.need <= *b.cap ? *b.cap : std::max(b.need + b.need / 2, kMinCap));
+        if (want == *b.cap) continue;
+        if (!synced) {
+            HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+            synced = true;
+        }
+        dev_free(ctx, *b.p, false);
+        dev_scratch -= *b.cap * b.elem;
+        *b.p = nullptr;
+        *b.cap = 0;
+        void *q;
+        const psl_status st = dev_alloc(ctx, &q, want * b.elem, false);
+        if (st) return st;
+        *b.p = q;
+        *b.cap = want;
+        dev_scratch += want * b.elem;
+    }
+    return PSL_OK;
 }
 
 void Server::retire_finished()
@@ -242,15 +378,37 @@ void Server::retire_finished()
 psl_status Server::admit(char *&sp, char *stage_end)
 {
     std::vector<Job> adm;
+    psl_status st;
     while (!pending.empty()) {
         Job &j = pending.front();
         if (active.size() + adm.size() >= cfg.max_slots) break;
-        if (used + j.foot > cfg.hbm_budget) break;      // strict FIFO: no overtaking
-        const SlabLayout lay = slab_layout(j.cfg.L);
-        void *slab = arena.alloc(lay.slab_bytes);
-        if (!slab) break;
+        // strict FIFO: no overtaking. Slabs awaiting their free and scratch
+        // beyond the admitted jobs' bounds count too; both are given back
+        // when that lets the job in.
+        const size_t base = used + j.foot;
+        if (base > cfg.hbm_budget) break;
+        if (base + to_free_bytes + scratch_over() > cfg.hbm_budget) {
+            if ((st = flush_free())) return st;
+            if (base + scratch_over() > cfg.hbm_budget && adm.empty() && (st = release_scratch())) return st;
+            if (base + scratch_over() > cfg.hbm_budget) break;
+        }
+        const size_t cls = slab_class(slab_layout(j.cfg.L).slab_bytes);
+        void *slab = nullptr;
+        auto pooled = to_free.find(cls);
+        if (pooled != to_free.end()) {
+            slab = pooled->second;
+            to_free.erase(pooled);
+            to_free_bytes -= cls;
+        } else if (dev_alloc(ctx, &slab, cls, false) != PSL_OK) {
+            if (!active.empty() || !adm.empty()) break;    // room comes back as jobs retire
+            Job f = std::move(j);
+            pending.pop_front();
+            finish(f, PSL_E_NOMEM);
+            continue;
+        }
         j.slab = slab;
         used += j.foot;
+        bounds += j.bound;
         adm.push_back(std::move(j));
         pending.pop_front();
     }
@@ -259,8 +417,11 @@ psl_status Server::admit(char *&sp, char *stage_end)
     if ((size_t)(stage_end - sp) < need) {
         // put them back in order; admitted next iteration
         for (auto it = adm.rbegin(); it != adm.rend(); ++it) {
-            arena.release(it->slab);
+            const size_t cls = slab_class(slab_layout(it->cfg.L).slab_bytes);
+            to_free.emplace(cls, it->slab);
+            to_free_bytes += cls;
             used -= it->foot;
+            bounds -= it->bound;
             it->slab = nullptr;
             pending.push_front(std::move(*it));
         }
@@ -269,7 +430,7 @@ psl_status Server::admit(char *&sp, char *stage_end)
     // On failure the taken jobs join the active set with whatever slab and
     // slot they hold, so the caller's fail_all releases those and finishes
     // every ticket with the error instead of losing them.
-    const psl_status st = admit_start(adm, sp, stage_end);
+    st = admit_start(adm, sp, stage_end);
     for (auto &j : adm) active.push_back(std::move(j));
     if (st != PSL_OK) return st;
     dirty = true;
@@ -288,11 +449,11 @@ psl_status Server::admit_start(std::vector<Job> &adm, char *&sp, char *stage_end
     if (ctx->test_fail_admit && ++n_admissions == ctx->test_fail_admit)
         return fail(ctx, PSL_E_HIP, "admission %u failed by the test hook", n_admissions);
     psl_status st;
-    if ((st = grow(ctx, d_admit, adm.size()))) return st;
-    if ((st = grow(ctx, d_want, adm.size()))) return st;
     size_t n_suf = 0;
     for (const Job &j : adm) n_suf += suffix_len(j.cfg.L);
-    if ((st = grow(ctx, d_adm_s0, n_suf)) || (st = grow(ctx, d_adm_m0, n_suf))) return st;
+    if ((st = size_bufs({buf(d_admit, adm.size()), buf(d_want, adm.size()), buf(d_adm_s0, n_suf),
+                         buf(d_adm_m0, n_suf), buf(d_adm_seg, adm.size() + 1)})))
+        return st;
     size_t os = 0;
     uint32_t maxL = 0, maxnw = 0;
     BatchEntry *be = (BatchEntry *)sp;
@@ -302,7 +463,6 @@ psl_status Server::admit_start(std::vector<Job> &adm, char *&sp, char *stage_end
     uint32_t *adm_off = (uint32_t *)sp;
     sp += sizeof(uint32_t) * (adm.size() + 1);
     sp = (char *)(((uintptr_t)sp + 63) & ~(uintptr_t)63);
-    if ((st = grow(ctx, d_adm_seg, adm.size() + 1))) return st;
     SegMap adm_map{};
     {
         std::vector<uint32_t> aL(adm.size());
@@ -389,15 +549,17 @@ psl_status Server::upload_layout(char *&sp, char *stage_end)
     const size_t need = sizeof(BatchEntry) * n + sizeof(EvalItem) * items + sizeof(EvalQueues) +
                         sizeof(uint32_t) * (n + 1) + 512;
     if ((size_t)(stage_end - sp) < need) return fail(ctx, PSL_E_NOMEM, "serving staging too small");
+    std::vector<uint32_t> off_host(n + 1);
+    const SegMap seg_host = seg_prefix(Ls.data(), n, off_host.data());
+    // the batch's buffers; the admission buffers may shrink to their least
     psl_status st;
-    if ((st = grow(ctx, d_batch, n)) || (st = grow(ctx, d_items, items)) ||
-        (st = grow(ctx, d_fpart, n_part)) || (st = grow(ctx, d_mpart, n_part)) ||
-        (st = grow(ctx, d_f, n_cand)) || (st = grow(ctx, d_p, n_cand)) ||
-        (st = grow(ctx, d_s0, n_suf)) || (st = grow(ctx, d_m0, n_suf)) ||
-        (st = grow(ctx, d_near, (size_t)(kNearCap + 1) * n)) || (st = grow(ctx, d_queues, 1)) ||
-        (st = grow(ctx, d_red, (size_t)comb_blocks * n)) || (st = grow(ctx, d_pend, (size_t)n + 1)) ||
-        (st = grow(ctx, d_done, (size_t)n)) ||
-        (st = grow(ctx, d_seg, (size_t)n + 1)))
+    if ((st = size_bufs({buf(d_batch, n), buf(d_items, items), buf(d_fpart, n_part), buf(d_mpart, n_part),
+                         buf(d_f, n_cand), buf(d_p, n_cand), buf(d_s0, n_suf), buf(d_m0, n_suf),
+                         buf(d_near, (size_t)(kNearCap + 1) * n), buf(d_queues, 1),
+                         buf(d_red, (size_t)comb_blocks * n), buf(d_pend, (size_t)n + 1), buf(d_done, n),
+                         buf(d_seg, (size_t)n + 1), buf(d_segtot, seg_host.total),
+                         buf(d_segmax, seg_host.total), buf(d_admit, 0), buf(d_want, 0), buf(d_adm_s0, 0),
+                         buf(d_adm_m0, 0), buf(d_adm_seg, 0)})))
         return st;
     BatchEntry *be = (BatchEntry *)sp;
     sp += sizeof(BatchEntry) * n;
@@ -440,7 +602,6 @@ psl_status Server::upload_layout(char *&sp, char *stage_end)
     uint32_t *off = (uint32_t *)sp;
     sp += sizeof(uint32_t) * (n + 1);
     seg = seg_prefix(Ls.data(), n, off);
-    if ((st = grow(ctx, d_segtot, seg.total)) || (st = grow(ctx, d_segmax, seg.total))) return st;
     seg.off = d_seg.p;
     seg.tot = d_segtot.p;
     seg.tmax = d_segmax.p;
@@ -478,6 +639,8 @@ psl_status Server::iterate()
         stage_used[cur] = false;
     }
     retire_finished();
+    // the slab pool is freed when it grows large (freeing waits for the stream)
+    if ((to_free.size() >= kFlushSlabs || to_free_bytes >= kFlushBytes) && (st = flush_free())) return st;
     {
         // worst case of this iteration's uploads: admissions, then the layout
         // (work items <= 8 x (eval_items + candidate tiles) with padding, see eval_layout)
@@ -537,8 +700,11 @@ psl_status Server::iterate()
                                     hipMemcpyDeviceToHost, ctx->stream));
         HIP_TRY(ctx, hipEventCreateWithFlags(&j.ev, hipEventDisableTiming));
         HIP_TRY(ctx, hipEventRecord(j.ev, ctx->stream));
-        arena.release(j.slab);
+        const size_t cls = slab_class(slab_layout(j.cfg.L).slab_bytes);
+        to_free.emplace(cls, j.slab);
+        to_free_bytes += cls;
         used -= j.foot;
+        bounds -= j.bound;
         j.slab = nullptr;
         ctx->walks[j.slot] = WalkHost();
         ctx->free_slots.push_back(j.slot);
@@ -596,12 +762,17 @@ void Server::run()
     for (auto &j : retiring) finish(j, PSL_OK);
     retiring.clear();
     for (auto &j : active) {
-        if (j.slab) arena.release(j.slab);
+        dev_free(ctx, j.slab, false);
+        j.slab = nullptr;
         ctx->walks[j.slot] = WalkHost();
         ctx->free_slots.push_back(j.slot);
         finish(j, PSL_E_STATE);
     }
     active.clear();
+    used = 0;
+    bounds = 0;
+    (void)flush_free();
+    (void)release_scratch();          // a stopped loop holds no device memory
     for (auto &j : pending) finish(j, PSL_E_STATE);
     pending.clear();
     std::lock_guard<std::mutex> g(mu);
@@ -657,7 +828,6 @@ void serve_shutdown(psl_ctx *ctx)
         if (s->stage_ev[h]) (void)hipEventDestroy(s->stage_ev[h]);
     }
     for (auto &kv : s->pinned_free) (void)hipHostFree(kv.second);
-    if (s->arena_mem) (void)hipFree(s->arena_mem);
     delete s;
     ctx->server = nullptr;
 }
@@ -690,13 +860,17 @@ psl_status psl_serve_start(psl_ctx *ctx, const psl_serve_cfg *cfg)
     Server *s = new Server();
     s->cfg = *cfg;
     s->ctx = ctx;
-    // slabs come from one device region of the budget's size
-    if (hipMalloc((void **)&s->arena_mem, cfg->hbm_budget) != hipSuccess) {
-        (void)hipGetLastError();
-        delete s;
-        return fail(ctx, PSL_E_NOMEM, "serving arena of %llu bytes", (unsigned long long)cfg->hbm_budget);
+    s->items_cap = items_max(ctx);
+    {
+        // the budget has to fit the device's free memory (taken as jobs come)
+        size_t dfree = 0, dtotal = 0;
+        if (hipMemGetInfo(&dfree, &dtotal) != hipSuccess || dfree < cfg->hbm_budget) {
+            (void)hipGetLastError();
+            delete s;
+            return fail(ctx, PSL_E_NOMEM, "hbm_budget of %llu bytes exceeds the free device memory (%zu)",
+                        (unsigned long long)cfg->hbm_budget, dfree);
+        }
     }
-    s->arena.reset(s->arena_mem, cfg->hbm_budget);
     const size_t stage_bytes = ((size_t)4 << 20) + (size_t)cfg->max_slots * 256;
     for (int h = 0; h < 2; ++h) {
         if (hipHostMalloc((void **)&s->stage[h], stage_bytes, hipHostMallocDefault) != hipSuccess ||
@@ -733,7 +907,8 @@ psl_status psl_serve_submit(psl_ctx *ctx, const psl_job *job, uint64_t *ticket)
     j.budget = job->step_budget;
     j.best_out = job->best_bits_out;
     j.t_arrive = now_ns();
-    j.foot = job_footprint(c);
+    j.bound = scratch_bound(c.L, c.n_lmt ? c.n_lmt : c.L, s->items_cap);
+    j.foot = slab_class(slab_layout(c.L).slab_bytes) + j.bound;
     if (j.foot > s->cfg.hbm_budget) return PSL_E_FULL;
     {
         std::lock_guard<std::mutex> g(s->mu);
@@ -766,7 +941,7 @@ psl_status psl_serve_poll(psl_ctx *ctx, uint64_t ticket, psl_job_result *out)
 psl_status psl_serve_footprint(const psl_walk_cfg *cfg, uint64_t *bytes)
 {
     if (!cfg || !bytes || cfg->L < 2 || cfg->L > PSL_L_MAX || cfg->n_lmt > cfg->L) return PSL_E_INVAL;
-    *bytes = job_footprint(*cfg);
+    *bytes = job_footprint(*cfg, kEvalItemsDefault);
     return PSL_OK;
 }
 

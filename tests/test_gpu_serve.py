@@ -184,6 +184,60 @@ def test_serving_allocates_no_device_memory_beyond_its_region(ctx):
     assert free1 - low <= 4 << 20, (free1 - low)
 
 
+def test_serving_device_memory_within_budget(ctx):
+    """Serving a budget-filling mix of lengths (full and limited
+    neighbourhoods, admissions and retirements all along) keeps the loop's
+    device memory (walk slabs, retired slabs awaiting their free, scratch
+    buffers) within hbm_budget plus the stated 1 MiB of fixed scratch and the
+    allocator's rounding; every job still equals the same walk run alone; stop
+    gives the memory back."""
+    import torch
+    from paper_2107_09801_amd import libpsl
+    budget = 96 << 20
+    # a first start builds the power tables for every length, kept by the context
+    ctx.serve_start(hbm_budget=budget, max_slots=8)
+    ctx.serve_stop(drain=True)
+    torch.cuda.synchronize()
+    free0, _ = torch.cuda.mem_get_info(0)
+    ctx.serve_start(hbm_budget=budget, max_slots=256)
+    jobs = [(131071, 256), (30001, 0), (524287, 256), (4097, 0), (65535, 1000), (1048575, 256),
+            (2049, 0), (262143, 512), (16383, 0), (777, 0)] * 3
+    tickets = []
+    for i, (L, n_lmt) in enumerate(jobs):
+        assert libpsl.serve_footprint(L, n_lmt) + (1 << 20) <= budget
+        tickets.append(ctx.serve_submit(L, 300 + i, 4 + i % 5, n_lmt=n_lmt, switch_period=3))
+    low = free0
+    out, t0 = {}, time.time()
+    while len(out) < len(tickets):
+        low = min(low, torch.cuda.mem_get_info(0)[0])
+        for t in tickets:
+            if t not in out:
+                r = ctx.serve_poll(t)
+                if r is not None:
+                    out[t] = r
+        assert time.time() - t0 < 120, "jobs did not finish"
+        time.sleep(0.001)
+    st = ctx.serve_stats()
+    ctx.serve_stop(drain=True)
+    torch.cuda.synchronize()
+    free_end, _ = torch.cuda.mem_get_info(0)
+    assert all(r["status"] == 0 for r in out.values())
+    assert st["peak_active"] >= 2 and st["peak_used"] <= budget
+    assert free0 - low <= budget + (1 << 20) + (8 << 20), (free0 - low) / 2**20
+    assert free0 - free_end <= 4 << 20, (free0 - free_end) / 2**20
+    for t, (i, (L, n_lmt)) in zip(tickets, enumerate(jobs)):
+        if i % 10 not in (0, 3, 6, 9):
+            continue
+        r = out[t]
+        (w,) = ctx.init_walks(L, 1, 300 + i, n_lmt=n_lmt, switch_period=3)
+        ctx.step_batch([w], 4 + i % 5)
+        g = ctx.read_walk(w, C=False)
+        assert r["psl_best"] == g["psl_best"] and r["psl_final"] == g["psl_pivot"], (L, n_lmt)
+        assert abs(r["F_final"] - g["F_pivot"]) <= F_RTOL * g["F_pivot"], (L, n_lmt)
+        assert np.array_equal(r["best"], g["best"]), (L, n_lmt)
+        ctx.free_walks([w])
+
+
 def test_admission_failure_finishes_its_jobs(ctx):
     """A failing admission (forced by the test hook before it launches
     anything) finishes the jobs it had taken with PSL_E_HIP and releases their
@@ -192,7 +246,8 @@ def test_admission_failure_finishes_its_jobs(ctx):
     ctx.set_option(libpsl.OPT_TEST_FAIL_ADMIT, 2)
     try:
         ctx.serve_start(hbm_budget=64 << 20, max_slots=16)
-        first = [ctx.serve_submit(4097, 10 + i, 3, n_lmt=256) for i in range(3)]
+        # one job, so that it is the whole of admission 1 whatever the timing
+        first = [ctx.serve_submit(4097, 10, 3, n_lmt=256)]
         res = _wait(ctx, first, timeout_s=60)
         assert all(r["status"] == 0 for r in res.values())
         second = [ctx.serve_submit(4097, 20 + i, 3, n_lmt=256) for i in range(4)]
@@ -202,6 +257,7 @@ def test_admission_failure_finishes_its_jobs(ctx):
         st = ctx.serve_stats()
         ctx.serve_stop(drain=True)
     finally:
+        ctx.serve_stop(drain=False)               # (a no-op once stopped)
         ctx.set_option(libpsl.OPT_TEST_FAIL_ADMIT, 0)
     statuses = [r["status"] for r in res2.values()]
     assert libpsl.E_HIP in statuses                  # the second admission failed

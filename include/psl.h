@@ -243,6 +243,12 @@ PSL_API psl_status psl_read_walk(psl_ctx *ctx, uint32_t walk, psl_walk_state *ou
  * admitted walk by one step of Algorithm 1 in one batched launch sequence
  * (continuous batching: jobs that arrive while others run join the next
  * iteration). While serving, the context's other calls return PSL_E_STATE. */
+/* Device memory: the loop's allocations (walk slabs, slabs of finished jobs
+ * kept for reuse, scratch buffers) stay within hbm_budget + 1 MiB; a job is
+ * admitted while the footprints of the admitted jobs plus the kept slabs fit
+ * in hbm_budget. Nothing is allocated before jobs arrive, and a stopped loop
+ * holds no device memory (the context's power tables, built by the first
+ * start, are the context's). */
 typedef struct {
     uint64_t hbm_budget;     /* bytes jobs may occupy: walk slabs and their scratch */
     uint32_t max_slots;      /* most jobs admitted at once (>= 1)                  */
@@ -259,7 +265,9 @@ typedef struct {
 
 typedef struct {
     int32_t  status;         /* PSL_OK; PSL_E_HIP if a device error ended it;
-                                PSL_E_STATE if it was cancelled by psl_serve_stop  */
+                                PSL_E_STATE if it was cancelled by psl_serve_stop;
+                                PSL_E_NOMEM if its slab could not be allocated
+                                with no other job admitted                         */
     int32_t  psl_best;       /* best PSL seen                                       */
     int32_t  psl_final;      /* PSL of the final pivot                              */
     uint32_t alpha_final;    /* exponent at the end                                 */
@@ -281,7 +289,8 @@ typedef struct {
 } psl_serve_stats;
 
 /* Start the loop on this context. Errors: PSL_E_INVAL (cfg), PSL_E_STATE
- * (already serving), PSL_E_NOMEM, PSL_E_HIP. */
+ * (already serving), PSL_E_NOMEM (hbm_budget exceeds the device's free
+ * memory), PSL_E_HIP. */
 PSL_API psl_status psl_serve_start(psl_ctx *ctx, const psl_serve_cfg *cfg);
 
 /* Queue a job; thread-safe and non-blocking. *ticket names it.
@@ -295,8 +304,9 @@ PSL_API psl_status psl_serve_submit(psl_ctx *ctx, const psl_job *job, uint64_t *
 PSL_API psl_status psl_serve_poll(psl_ctx *ctx, uint64_t ticket, psl_job_result *out);
 
 /* Device bytes a job with this configuration counts against hbm_budget
- * (its walk slab plus an upper bound of its evaluation scratch). Needs no
- * context or device. Errors: PSL_E_INVAL. */
+ * (its walk slab, rounded up to its allocation class, plus an upper bound of
+ * its share of the loop's scratch in any batch, at the default work-item
+ * target). Needs no context or device. Errors: PSL_E_INVAL. */
 PSL_API psl_status psl_serve_footprint(const psl_walk_cfg *cfg, uint64_t *bytes);
 
 /* Thread-safe counters of the loop. */

@@ -754,10 +754,16 @@ psl_status capture_step(psl_ctx *ctx, BatchPlan &pl, const Tables &tabs, uint32_
     return PSL_OK;
 }
 
-psl_status single_plan(psl_ctx *ctx, uint32_t walk, BatchPlan &pl)
+// The context's one-walk batch entry (psl_apply_flip, psl_restore_walk),
+// allocated on first use and kept until the context is destroyed.
+psl_status one_entry(psl_ctx *ctx)
 {
-    // a one-walk plan with the walk's own n_lmt (used by psl_apply_flip)
-    return make_plan(ctx, pl, &walk, 1, UINT32_MAX, 0);
+    if (ctx->d_one) return PSL_OK;
+    void *p;
+    const psl_status st = dev_alloc(ctx, &p, sizeof(BatchEntry), false);
+    if (st) return st;
+    ctx->d_one = (BatchEntry *)p;
+    return PSL_OK;
 }
 
 }  // namespace psl_rt
@@ -1099,12 +1105,7 @@ psl_status psl_apply_flip(psl_ctx *ctx, uint32_t walk, uint32_t j)
     const WalkHost &h = ctx->walks[walk];
     if (j >= h.L) return fail(ctx, PSL_E_INVAL, "j=%u >= L=%u", j, h.L);
     HIP_TRY(ctx, hipSetDevice(ctx->device));
-    if (!ctx->d_one) {
-        void *p;
-        const psl_status st = dev_alloc(ctx, &p, sizeof(BatchEntry), false);
-        if (st) return st;
-        ctx->d_one = (BatchEntry *)p;
-    }
+    if (const psl_status st = one_entry(ctx)) return st;
     BatchEntry e;
     memset(&e, 0, sizeof e);
     e.slot = walk;
@@ -1523,26 +1524,21 @@ psl_status psl_restore_walk(psl_ctx *ctx, uint32_t walk, const psl_walk_state *s
     h.flip_lmt = w.flip_lmt;
     plans_clear(ctx);            // N_lmt may differ
     // C of local_best (and C) from local_best's bits, then C from the pivot's
-    BatchPlan one;
-    void *p;
-    psl_status rs = dev_alloc(ctx, &p, sizeof(BatchEntry), false);
-    if (rs) return rs;
-    one.d_batch = (BatchEntry *)p;
+    if (const psl_status rs = one_entry(ctx)) return rs;
     BatchEntry e;
     memset(&e, 0, sizeof e);
     e.slot = walk;
-    hipError_t r = hipMemcpy(one.d_batch, &e, sizeof e, hipMemcpyHostToDevice);
+    hipError_t r = hipMemcpy(ctx->d_one, &e, sizeof e, hipMemcpyHostToDevice);
     const Tables tabs = tables_of(ctx);
     if (r == hipSuccess) r = hipMemcpy(w.pivot, local_best, 8ull * nw, hipMemcpyHostToDevice);
-    if (r == hipSuccess) r = launch_corr(ctx->d_walks, one.d_batch, 1, L, 0, ctx->stream);
+    if (r == hipSuccess) r = launch_corr(ctx->d_walks, ctx->d_one, 1, L, 0, ctx->stream);
     if (r == hipSuccess) r = hipStreamSynchronize(ctx->stream);
     if (r == hipSuccess) r = hipMemcpy(w.pivot, pivot, 8ull * nw, hipMemcpyHostToDevice);
     if (r == hipSuccess) r = hipMemcpy(w.local_best, local_best, 8ull * nw, hipMemcpyHostToDevice);
     if (r == hipSuccess) r = hipMemcpy(w.best, best, 8ull * nw, hipMemcpyHostToDevice);
-    if (r == hipSuccess) r = launch_corr(ctx->d_walks, one.d_batch, 1, L, 2, ctx->stream);
-    if (r == hipSuccess) r = launch_fitness(ctx->d_walks, one.d_batch, 1, tabs, 2, ctx->stream);
+    if (r == hipSuccess) r = launch_corr(ctx->d_walks, ctx->d_one, 1, L, 2, ctx->stream);
+    if (r == hipSuccess) r = launch_fitness(ctx->d_walks, ctx->d_one, 1, tabs, 2, ctx->stream);
     if (r == hipSuccess) r = hipStreamSynchronize(ctx->stream);
-    plan_free(ctx, one);
     if (r != hipSuccess) return fail(ctx, PSL_E_HIP, "restore: %s", hipGetErrorString(r));
     return PSL_OK;
 }

@@ -238,7 +238,7 @@ def cpu_baseline(L: int, n_lmt: int, alpha: int, target_s: float, max_walks: int
             "host": info}
 
 
-def run_serving(libpsl, seconds: float, rate: float, nlmt_cap: int) -> dict:
+def run_serving(libpsl, seconds: float, rate: float, nlmt_cap: int, eval_items: int = 0) -> dict:
     """Poisson arrivals into the request loop; time-to-budget per job."""
     import numpy as np
 
@@ -248,6 +248,8 @@ def run_serving(libpsl, seconds: float, rate: float, nlmt_cap: int) -> dict:
     arrivals = np.sort(rng.uniform(0.0, seconds, size=n))
     jobs = si.serve_jobs(n, si.BASE_SEED + 1, nlmt_cap)
     ctx = libpsl.Context(0)
+    if eval_items:
+        ctx.set_option(libpsl.OPT_EVAL_ITEMS, eval_items)
     ctx.serve_start(hbm_budget=200 << 30, max_slots=4096)
     outstanding, results = set(), {}
     t0 = time.perf_counter()
@@ -543,7 +545,8 @@ def main():
         print(json.dumps(run_alpha_ablation(libpsl, args.nse, args.runs)), flush=True)
         return
     if args.study == "serve":
-        print(json.dumps(run_serving(libpsl, args.serve_seconds, args.serve_rate, args.serve_nlmt)), flush=True)
+        print(json.dumps(run_serving(libpsl, args.serve_seconds, args.serve_rate, args.serve_nlmt,
+                                     args.eval_items)), flush=True)
         return
     if args.study == "restart":
         print(json.dumps(run_restart_study(libpsl, args.L or 65535, args.rounds, args.walks or 64,

@@ -131,8 +131,8 @@ constexpr uint32_t kEvalItemsMax = 1u << 18;    // and its largest value
 constexpr int64_t kAmbigMarginMax = 1000000000000000ll;  // PSL_OPT_AMBIG_MARGIN: 1.0 in units of 1e-15
 constexpr uint32_t kSplitMinL = 2048;          // shortest walk the split evaluation takes
 constexpr uint64_t kSplitMinWork = 1ull << 34; // fewest nominal updates of a launch that takes it
-constexpr uint32_t kLinItemsTarget = 1024;     // linear items per launch the k-splits aim for
-constexpr uint32_t kLinMinChunks = 64;         // fewest shift chunks per k-split of a linear item
+constexpr uint32_t kLinItemsTarget = 8192;     // linear items per launch the k-splits aim for
+constexpr uint32_t kLinMinChunks = 256;         // fewest shift chunks per k-split of a linear item
 
 
 struct Server;   // serving loop (psl_serve.hip)

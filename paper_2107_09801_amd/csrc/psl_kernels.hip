@@ -333,58 +333,84 @@ __global__ __launch_bounds__(kFitThreads) void k_fitness(WalkDev *walks, const B
 //    |C_k| <= P - 9 reaches at most P - 5, so a neighbour's PSL is the maximum
 //    of |C'_k| over the shifts with |C_k| >= P - 8 alone. near[0] = count,
 //    near[1..] = those shifts (any order), while the count fits kNearCap.
-// Two kernels: k_chunks (several blocks per walk) writes per-chunk sums (a
-// fixed 32-lane tree) and maxima and appends to the near list; k_scan (one
-// block per walk) turns the chunk values into suffix values in a fixed order.
-// The same pair is also the fitness of a pivot: S0[0] = F and M0[0] = PSL.
-// Mode 1: after a phase switch (pending walks: the new pivot under the new
-// alpha); mode 2: at init (every walk).
+// Two kernels: k_chunks (several blocks per walk) writes per-chunk sums and
+// maxima and appends to the near list; k_seg_scan (step) or k_scan (init)
+// turns the chunk values into suffix values in a fixed order. The same pair
+// is also the fitness of a pivot: S0[0] = F and M0[0] = PSL (mode 2, init).
 constexpr int kChunkThreads = 256;
 constexpr uint32_t kMaxGridY = 65535;      // walks per launch of the 2-D grids
-// Chunk pairs p0, p0 + step, ... below p1 of one walk, for the calling
-// wavefront (a pair is 64 consecutive shifts, two chunks).
-__device__ __forceinline__ void chunk_pairs(const BatchEntry &be, const WalkDev &w, const double *T, int cut,
-                                            bool near, int p0, int p1, int step, double &ws, double &wc,
-                                            uint32_t &wm)
+// Octets o0, o0 + step, ... below o1 of one walk (an octet is 256 consecutive
+// shifts, eight chunks), for the calling wavefront: four coalesced passes of
+// 64 shifts put T(|C_k|) and |C_k| in the wavefront's LDS rows (sv, sa); then
+// lane l adds the four consecutive values 4(l mod 8) .. +3 of chunk l / 8
+// (left to right) and a three-level butterfly over the chunk's eight lanes
+// finishes its sum and maximum, the same in all eight. The octet's total (a
+// fixed tree over its chunks) goes into the wavefront's running total.
+__device__ __forceinline__ void chunk_octs(const BatchEntry &be, const WalkDev &w, const double *T, int cut,
+                                           bool near, int o0, int o1, int step, double *sv, int *sa,
+                                           double &ws, double &wc, uint32_t &wm)
 {
     const int L = (int)w.L;
     const int nchunks = (L - 1 + 31) / 32;
     const int lane = threadIdx.x & 63;
-    for (int p = p0; p < p1; p += step) {
-        const int k = 1 + 64 * p + lane;
-        double v = 0.0;
-        int a = 0;
-        if (k < L) {
-            const int32_t x = w.C[k];
-            a = x < 0 ? -x : x;
-            v = T[a];
+    for (int o = o0; o < o1; o += step) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = 64 * i + lane;
+            const int k = 1 + 256 * o + e;
+            double v = 0.0;
+            int a = 0;
+            if (k < L) {
+                const int32_t x = w.C[k];
+                a = x < 0 ? -x : x;
+                v = T[a];
+            }
+            sv[e] = v;
+            sa[e] = a;
+            if (near) {
+                const bool take = k < L && a >= cut;
+                const uint64_t bal = __ballot(take);
+                if (bal) {
+                    uint32_t base = 0;
+                    if (lane == 0) base = atomicAdd(&be.near[0], (uint32_t)__popcll(bal));
+                    base = (uint32_t)__shfl((int)base, 0);
+                    const uint32_t q = base + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+                    if (take && q < (uint32_t)kNearCap) be.near[1 + q] = (uint32_t)k;
+                }
+            }
         }
-        const bool take = k < L && a >= cut;
-        int m = a;
-        for (int o = 16; o > 0; o >>= 1) {
-            v += __shfl_xor(v, o);
-            m = max(m, __shfl_xor(m, o));
+        // the wavefront's rows are written before any lane reads them
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const int r = 32 * (lane >> 3) + 4 * (lane & 7);
+        double v = sv[r];
+        v += sv[r + 1];
+        v += sv[r + 2];
+        v += sv[r + 3];
+        int m = max(max(sa[r], sa[r + 1]), max(sa[r + 2], sa[r + 3]));
+        for (int d = 1; d < 8; d <<= 1) {
+            v += __shfl_xor(v, d);
+            m = max(m, __shfl_xor(m, d));
         }
-        const int c = 2 * p + (lane >> 5);
-        if ((lane & 31) == 0 && c < nchunks) {
+        const int c = 8 * o + (lane >> 3);
+        if ((lane & 7) == 0 && c < nchunks) {
             be.S0[c] = v;
             be.M0[c] = (uint32_t)m;
         }
-        // the pair's two chunk sums, in chunk order, into the wave's total
-        const double v2 = __shfl(v, 32);
-        nsum_add(ws, wc, __shfl(v, 0));
-        nsum_add(ws, wc, v2);
-        wm = max(wm, (uint32_t)max(__shfl(m, 0), __shfl(m, 32)));
-        if (near) {
-            const uint64_t bal = __ballot(take);
-            if (bal) {
-                uint32_t base = 0;
-                if (lane == 0) base = atomicAdd(&be.near[0], (uint32_t)__popcll(bal));
-                base = (uint32_t)__shfl((int)base, 0);
-                const uint32_t q = base + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
-                if (take && q < (uint32_t)kNearCap) be.near[1 + q] = (uint32_t)k;
-            }
+        // the octet's total over its chunk leaders (every lane ends with it)
+        double ts = v, tc = 0.0;
+        for (int d = 8; d < 64; d <<= 1) {
+            const double ps = __shfl_xor(ts, d), pc = __shfl_xor(tc, d);
+            nsum_add(ts, tc, ps);
+            tc += pc;
+            m = max(m, __shfl_xor(m, d));
         }
+        nsum_add(ws, wc, ts);
+        wc += tc;
+        wm = max(wm, (uint32_t)m);
+        // every lane has read the rows before the next octet overwrites them
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -399,14 +425,17 @@ __global__ __launch_bounds__(kChunkThreads) void k_chunks(const WalkDev *walks, 
     seg_of(map, blockIdx.x, b, seg);
     const BatchEntry be = batch[b];
     const WalkDev &w = walks[be.slot];
-    const int npairs = ((int)w.L - 1 + 63) / 64;
-    const int pairs_per_seg = 1 << (map.shift - 6);
-    const int p0 = (int)seg * pairs_per_seg;
-    const int p1 = min(npairs, p0 + pairs_per_seg);
+    const int nocts = ((int)w.L - 1 + 255) / 256;
+    const int octs_per_seg = 1 << (map.shift - 8);
+    const int o0 = (int)seg * octs_per_seg;
+    const int o1 = min(nocts, o0 + octs_per_seg);
+    __shared__ double s_v[kWaves][256];
+    __shared__ int s_a[kWaves][256];
     // the near-peak cut (the pivot's PSL is kept current by every step)
     double ws = 0.0, wc = 0.0;
     uint32_t wm = 0;
-    chunk_pairs(be, w, tabs.T[w.alpha], w.psl_pivot - 8, mode == 0, p0 + wave, p1, kWaves, ws, wc, wm);
+    chunk_octs(be, w, tabs.T[w.alpha], w.psl_pivot - 8, mode == 0, o0 + wave, o1, kWaves, s_v[wave], s_a[wave],
+               ws, wc, wm);
     if (map.tot) {
         // the segment's total (waves in order) for the segment-parallel scan
         __shared__ double s_s[kWaves], s_c[kWaves];

@@ -373,7 +373,7 @@ void eval_layout(const uint32_t *Ls, const uint32_t *nl, uint32_t n, const EvalS
         cmax = std::max(cmax, sg.size());
     }
     // selection: a group of G lanes per candidate with about 16 splits per
-    // lane, about 8192 partials per combine block, at most one block per
+    // lane, about 2048 partials per combine block, at most one block per
     // block-pass of candidates
     uint64_t work = 0, nmax = 0, ksmax = 1;
     for (uint32_t b = 0; b < n; ++b) {
@@ -389,7 +389,7 @@ void eval_layout(const uint32_t *Ls, const uint32_t *nl, uint32_t n, const EvalS
     // also makes the selection (no separate selection launch)
     out.comb_blocks = work <= 16384 ? 1u
                                     : (uint32_t)std::max<uint64_t>(
-                                          1, std::min<uint64_t>({(work + 8191) / 8192, (nmax + cpb - 1) / cpb,
+                                          1, std::min<uint64_t>({(work + 2047) / 2048, (nmax + cpb - 1) / cpb,
                                                                  (uint64_t)kCombMaxBlocks}));
     out.items.reserve(shape.persistent ? all.size() : 8 * cmax);
     for (int q = 0; q < 8; ++q) {

@@ -344,7 +344,7 @@ typedef struct {
     int32_t persistent;     /* 1: a fixed grid of blocks_per_cu x CUs takes work
                                items from per-XCD queues; 0: one block per item     */
     int32_t blocks_per_cu;  /* resident blocks per CU of the persistent grid: 1..3
-                               (1..2 for 16 wavefronts)                            */
+                               (1..2 for 16 wavefronts, 1..6 for 4)                */
     int32_t eval_items;     /* work-item target kept with it (PSL_OPT_EVAL_ITEMS)   */
     double  eval_ms;        /* measured mean launch time of this shape              */
     double  default_ms;     /* measured mean launch time of the untuned default     */

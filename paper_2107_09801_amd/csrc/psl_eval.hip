@@ -37,29 +37,44 @@ constexpr int kOneQuads = 8;
 constexpr int kOneWin = 16 * kOneQuads;
 constexpr int kOneItems = 4 * kOneQuads;   // table-building items per window
 
+// Shifts per LDS tile of the table form: 256 for blocks of 8 and 16
+// wavefronts (whose registers admit three and two blocks per CU whatever
+// their LDS), 128 for blocks of 4, whose LDS then admits six blocks per CU.
+// The split form keeps tiles of kTileK shifts in the same arrays.
+template <int WAVES>
+constexpr int kTabTileK = WAVES >= 8 ? kTileK : kTileK / 2;
+
+constexpr int lds_max(int a, int b) { return a > b ? a : b; }
+
 // LDS of one evaluation block.
+template <int WAVES>
 struct EvalLds {
+    static constexpr int TK = kTabTileK<WAVES>;
     // first, so that a window's two-word read needs no base offset (the
     // offsets of ds_read2_b32 are 8-bit dword counts)
-    uint32_t bits[kEvalWavesMax * 64];  // per wavefront: its pivot words of the tile
-    double rows[kTileK * kRowStride];   // T(|C_k + 2m|), m = -2..2, per shift
-    double both[kPairs * 16];           // pair sums, both neighbours
-    double one[kChunks * kOneWin];      // quad sums, one neighbour
-    uint32_t both_max[kPairs * 16];     // max hi32 of the pair (dense PSL only)
-    uint32_t one_max[kChunks * kOneWin];
-    int kend[kEvalWavesMax];            // per wavefront
-    int bmax[kEvalWavesMax];
-    int omax[kEvalWavesMax];
+    uint32_t bits[WAVES * 64];          // per wavefront: its pivot words of the tile
+    // table form: T(|C_k + 2m|), m = -2..2, per shift; split form: D_k and
+    // B_k - B'_k per shift
+    double rows[lds_max(TK * kRowStride, 2 * kTileK)];
+    // table form: pair sums, both neighbours; split form: the D quad tables
+    double both[lds_max(TK / 2 * 16, kChunks * kOneWin)];
+    double one[TK / 32 * kOneWin];      // quad sums, one neighbour
+    uint32_t both_max[TK / 2 * 16];     // max hi32 of the pair (dense PSL only)
+    uint32_t one_max[TK / 32 * kOneWin];
+    int kend[WAVES];                    // per wavefront
+    int bmax[WAVES];
+    int omax[WAVES];
 };
 
 // The sweep of one item. kMax: keep the PSL maximum in the main loop (dense
 // form); otherwise the near-peak pass supplies it.
 template <int WAVES, bool kMax>
-__device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const BatchEntry &be,
+__device__ __forceinline__ void eval_sweep(EvalLds<WAVES> &sh, const WalkDev &w, const BatchEntry &be,
                                            const EvalItem &it, const double *__restrict__ T,
                                            uint32_t n_lmt, int j, uint32_t SJ, int k_lo, int k_hi,
                                            int tid, double &sum, double &comp, uint32_t &mx)
 {
+    constexpr int TK = kTabTileK<WAVES>, TC = TK / 32, TP = TK / 2;
     const int L = (int)w.L;
     const int32_t *__restrict__ C = w.C;
     const uint32_t *__restrict__ w32 = reinterpret_cast<const uint32_t *>(w.pivot);
@@ -113,8 +128,8 @@ __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const 
     const int s_mn = s_grp ? jmn1 : jmn0, s_mx = s_grp ? jmx1 : jmx0;
     const int s_span = s_side ? (s_mx >> 5) - (s_mn >> 5) : ((s_mx + 1) >> 5) - ((s_mn + 1) >> 5);
 
-    for (int kt = k_lo; kt < k_bend; kt += kTileK) {
-        const int kt_end = min(k_bend, kt + kTileK);
+    for (int kt = k_lo; kt < k_bend; kt += TK) {
+        const int kt_end = min(k_bend, kt + TK);
         const int nt = kt_end - kt;
         // which pair tables some wave of the block can use in this tile
         const bool need_both = kt + 31 <= b_bmax;
@@ -124,7 +139,7 @@ __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const 
             // this wavefront's words for its windows of the tile (chunks
             // cb .. cb + cc_last)
             const int cb = (kt - 1) >> 5;
-            const int cc_last = kt < k_wend ? min(kChunks - 1, (k_wend - 1 - kt) >> 5) : -1;
+            const int cc_last = kt < k_wend ? min(TC - 1, (k_wend - 1 - kt) >> 5) : -1;
             if (s_mn <= s_mx && s_idx < s_span + cc_last + 2) {
                 const int word = s_side ? (s_mx >> 5) - cb - s_idx : ((s_mn + 1) >> 5) + cb + s_idx;
                 sh.bits[64 * wave + lane] = w32[word];
@@ -145,7 +160,7 @@ __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const 
             // Entry x of pair p: low two bits the left pair (xl_k, xl_k+1),
             // high two the right pair; one thread per (pair, right bits)
             // writes its four consecutive entries.
-            for (int e = tid; e < kPairs * 4; e += 64 * WAVES) {
+            for (int e = tid; e < TP * 4; e += 64 * WAVES) {
                 const int p = e >> 2, r0 = e & 1, r1 = (e >> 1) & 1;
                 if (2 * p + 1 < nt) {
                     const double *ra = sh.rows + (2 * p) * kRowStride + 2 * r0;
@@ -167,7 +182,7 @@ __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const 
             // quad q: bit i of x is the bit of shift 4q + i. Item (q, h) of a
             // window writes the four consecutive entries whose two high bits
             // are h: (a + b) + (c + d).
-            for (int f = tid; f < kChunks * kOneItems; f += 64 * WAVES) {
+            for (int f = tid; f < TC * kOneItems; f += 64 * WAVES) {
                 const int cc = f / kOneItems, r = f - cc * kOneItems;
                 const int q = r >> 2, h0 = r & 1, h1 = (r >> 1) & 1;
                 const int t0 = 32 * cc + 4 * q;
@@ -197,10 +212,10 @@ __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const 
         // the staged ones hold stale words that are never used)
         uint32_t r0 = rbits[0], r1 = rbits[1], l0 = lbits[0], l1 = lbits[1];
 #pragma unroll
-        for (int cc = 0; cc < kChunks; ++cc) {
+        for (int cc = 0; cc < TC; ++cc) {
             const int k0 = kt + 32 * cc;
             const uint32_t cr0 = r0, cr1 = r1, cl0 = l0, cl1 = l1;
-            if (cc + 1 < kChunks) {
+            if (cc + 1 < TC) {
                 r0 = rbits[cc + 1];
                 r1 = rbits[cc + 2];
                 l0 = lbits[cc + 1];
@@ -300,7 +315,7 @@ __device__ __forceinline__ void eval_sweep(EvalLds &sh, const WalkDev &w, const 
 // covered for every lane of the wavefront takes eight table reads; windows
 // on the edges of the region go shift by shift.
 template <int WAVES>
-__device__ __forceinline__ void eval_sweep_split(EvalLds &sh, const WalkDev &w, const BatchEntry &be, int j,
+__device__ __forceinline__ void eval_sweep_split(EvalLds<WAVES> &sh, const WalkDev &w, const BatchEntry &be, int j,
                                                  uint32_t sjbit, int k_lo, int k_hi, int tid, double &sum,
                                                  double &comp)
 {
@@ -438,7 +453,7 @@ __device__ __forceinline__ void eval_sweep_split(EvalLds &sh, const WalkDev &w, 
 
 // Neighborhood of Algorithm 1 for one (walk, 64*WAVES candidates, k-range) item.
 //
-// Per 256-shift tile the block stages (i) per shift the five values
+// Per tile of shifts (kTabTileK) the block stages (i) per shift the five values
 // T(|C_k + 2m|), m = -2..2, and (ii) tables of pre-added terms: for shifts
 // where both neighbours of j exist (C' = C + 4(xr + xl - 1)), 16 entries per
 // pair of shifts (k, k+1) indexed by the four bits (xl_k, xl_k+1, xr_k,
@@ -453,7 +468,7 @@ __device__ __forceinline__ void eval_sweep_split(EvalLds &sh, const WalkDev &w, 
 // shifts (spread over the k-splits), or, for pivots with many near-peak shifts, from
 // 32-bit maxima kept in the main loop.
 template <int WAVES>
-__device__ __forceinline__ void eval_item(EvalLds &sh, const WalkDev *__restrict__ walks,
+__device__ __forceinline__ void eval_item(EvalLds<WAVES> &sh, const WalkDev *__restrict__ walks,
                                           const BatchEntry *__restrict__ batch, const EvalItem it,
                                           const Tables &tabs, int tid)
 {
@@ -524,11 +539,15 @@ __device__ __forceinline__ void eval_item(EvalLds &sh, const WalkDev *__restrict
     }
 }
 
-// Register budget of the evaluation kernels: the LDS of a block admits three
-// blocks per CU, i.e. 3 * WAVES / 4 wavefronts per SIMD; ask the compiler to
-// keep the VGPR count low enough for that.
+// Register budget of the evaluation kernels: the wavefronts per SIMD that
+// the blocks admitted by a CU's 160 KiB of LDS hold (at most 8).
 template <int WAVES>
-constexpr int kEvalWavesPerEU = WAVES * 3 / 4 < 1 ? 1 : WAVES * 3 / 4 > 8 ? 8 : WAVES * 3 / 4;
+constexpr int kEvalWavesPerEU = (160 * 1024 / (int)sizeof(EvalLds<WAVES>)) * WAVES / 4 > 8
+                                    ? 8
+                                    : (160 * 1024 / (int)sizeof(EvalLds<WAVES>)) * WAVES / 4;
+static_assert(kEvalWavesPerEU<4> == 6 && kEvalWavesPerEU<8> == 6 && kEvalWavesPerEU<16> == 8,
+              "evaluation occupancy");
+static_assert(sizeof(EvalLds<4>) <= 160 * 1024 / 6, "six 4-wavefront blocks per CU");
 
 // One block per work item; items are laid out as 8 equal-cost XCD ranges
 // padded to equal length.
@@ -538,7 +557,7 @@ void k_eval(const WalkDev *__restrict__ walks,
                                                      const BatchEntry *__restrict__ batch,
                                                      const EvalItem *__restrict__ items, Tables tabs)
 {
-    __shared__ EvalLds sh;
+    __shared__ EvalLds<WAVES> sh;
     const EvalItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
     if (it.walk == kNoItem) return;     // padding of an XCD's range
     eval_item<WAVES>(sh, walks, batch, it, tabs, (int)threadIdx.x);
@@ -554,7 +573,7 @@ void k_eval_persistent(const WalkDev *__restrict__ walks,
                                                                 const EvalItem *__restrict__ items,
                                                                 Tables tabs, EvalQueues *queues)
 {
-    __shared__ EvalLds sh;
+    __shared__ EvalLds<WAVES> sh;
     __shared__ uint32_t s_item;
     uint32_t q = blockIdx.x % 8, dry = 0;
     while (dry < 8) {

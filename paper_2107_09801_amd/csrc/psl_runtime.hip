@@ -246,9 +246,12 @@ SegMap seg_prefix(const uint32_t *Ls, uint32_t n, uint32_t *off)
     return SegMap{nullptr, n, 0, off[n], sh, nullptr, nullptr};
 }
 
+// Resident evaluation blocks per CU: 16-wavefront blocks are held to two by
+// their registers, 8-wavefront ones to three, 4-wavefront ones to six by
+// their LDS.
 uint32_t max_blocks_per_cu(int waves)
 {
-    return waves >= kEvalWavesMax ? 2u : 3u;
+    return waves >= kEvalWavesMax ? 2u : waves == kEvalWavesSmall ? 6u : 3u;
 }
 
 int eval_waves(const uint32_t *nl, uint32_t n)

@@ -433,7 +433,7 @@ def test_autotune_shapes_keep_results(ctx, tmp_path):
 
 def test_every_launch_shape_gives_the_same_walks(ctx, tmp_path):
     """Each evaluation launch shape (4, 8 or 16 wavefronts; one block per
-    item, or a persistent grid of 1..3 blocks per CU over the per-XCD
+    item, or a persistent grid of 1..6 blocks per CU over the per-XCD
     queues), forced through a tuning file, steps a mixed batch (ragged
     tiles, L from 2 to 9000, several k-splits) to the same walks as the
     untuned default, which the oracle pins elsewhere."""
@@ -459,7 +459,7 @@ def test_every_launch_shape_gives_the_same_walks(ctx, tmp_path):
     key = open(tmp_path / "key.txt").read().split()[0]
     probe.close()
     shapes = [(16, 0, 0), (16, 1, 1), (16, 1, 2), (8, 0, 0), (8, 1, 1), (8, 1, 2), (8, 1, 3),
-              (4, 0, 0), (4, 1, 1), (4, 1, 3)]
+              (4, 0, 0), (4, 1, 1), (4, 1, 3), (4, 1, 6)]
     for waves, pers, bpc in shapes:
         c = libpsl.Context(0)
         if ctx_is_dense(ctx):

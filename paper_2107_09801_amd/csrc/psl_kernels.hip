@@ -807,7 +807,8 @@ __device__ __forceinline__ void select_walk(WalkDev &w, const BatchEntry &be, ui
 // Every F of a combine block is at least that block's minimum, so only the
 // blocks whose minimum is at most thr + amb are read. pure != 0: the flag
 // goes into the choice record out[b]; otherwise into the walk's step flags.
-constexpr int kAmbThreads = 256;
+// Made by a block of NT threads.
+template <int NT>
 __device__ __forceinline__ void ambig_walk(WalkDev &w, const BatchEntry &be, uint32_t bi, uint32_t comb_blocks,
                                            uint32_t comb_group, int pure, ChoiceDev *out, double margin)
 {
@@ -815,21 +816,21 @@ __device__ __forceinline__ void ambig_walk(WalkDev &w, const BatchEntry &be, uin
     const double Fmin = pure ? out[bi].F_min : w.F_min;
     const double thr = Fmin * (1.0 + kTau), amb = margin * Fmin;
     // the combine blocks whose minimum lies at or below thr + amb, one per
-    // thread (comb_blocks <= kAmbThreads), as one 64-bit mask per wavefront
-    static_assert(kCombMaxBlocks <= kAmbThreads, "one combine block per thread");
-    __shared__ uint64_t s_near[kAmbThreads / 64];
+    // thread (comb_blocks <= NT), as one 64-bit mask per wavefront
+    static_assert(kCombMaxBlocks <= NT, "one combine block per thread");
+    __shared__ uint64_t s_near[NT / 64];
     const uint32_t t = threadIdx.x;
     const bool near = t < comb_blocks && be.red[t].f - thr <= amb;
     const uint64_t m = __ballot(near);
     if ((t & 63) == 0) s_near[t >> 6] = m;
     __syncthreads();
     int hit = 0;
-    for (uint32_t q = 0; q < kAmbThreads / 64; ++q) {
+    for (uint32_t q = 0; q < NT / 64; ++q) {
         for (uint64_t bits = s_near[q]; bits; bits &= bits - 1) {   // the same for every thread of the block
             const uint32_t b = 64 * q + (uint32_t)__builtin_ctzll(bits);
             uint32_t lo, hi;
             comb_range(n, comb_blocks, comb_group, b, lo, hi);
-            for (uint32_t i = lo + t; i < hi; i += kAmbThreads) {
+            for (uint32_t i = lo + t; i < hi; i += NT) {
                 const double g = be.F[i] - thr;
                 hit |= (g < 0.0 ? -g : g) <= amb;
             }
@@ -975,27 +976,21 @@ __global__ __launch_bounds__(kCombThreads) void k_combine(WalkDev *walks, const 
     if (gridDim.x > 1) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     select_walk<kCombThreads>(w, be, bi, gridDim.x, (uint32_t)G, pure, out, pend);
     __syncthreads();
-    ambig_walk(w, be, bi, gridDim.x, (uint32_t)G, pure, out, margin);
+    ambig_walk<kCombThreads>(w, be, bi, gridDim.x, (uint32_t)G, pure, out, margin);
 }
 
-// The selection of a walk (one block per walk, after k_combine when the
-// combine launch does not make it itself).
+// The selection of a walk and its ambiguity flags (one block per walk, after
+// k_combine when the combine launch does not make them itself).
 constexpr int kSelThreads = 1024;
 __global__ __launch_bounds__(kSelThreads) void k_select(WalkDev *walks, const BatchEntry *batch,
                                                         uint32_t comb_blocks, uint32_t comb_group, int pure,
-                                                        ChoiceDev *out, uint32_t *pend)
+                                                        ChoiceDev *out, uint32_t *pend, double margin)
 {
     const BatchEntry be = batch[blockIdx.x];
-    select_walk<kSelThreads>(walks[be.slot], be, blockIdx.x, comb_blocks, comb_group, pure, out, pend);
-}
-
-// The ambiguity flags of a walk (one block per walk, after k_select).
-__global__ __launch_bounds__(kAmbThreads) void k_ambig(WalkDev *walks, const BatchEntry *batch,
-                                                       uint32_t comb_blocks, uint32_t comb_group, int pure,
-                                                       ChoiceDev *out, double margin)
-{
-    const BatchEntry be = batch[blockIdx.x];
-    ambig_walk(walks[be.slot], be, blockIdx.x, comb_blocks, comb_group, pure, out, margin);
+    WalkDev &w = walks[be.slot];
+    select_walk<kSelThreads>(w, be, blockIdx.x, comb_blocks, comb_group, pure, out, pend);
+    __syncthreads();
+    ambig_walk<kSelThreads>(w, be, blockIdx.x, comb_blocks, comb_group, pure, out, margin);
 }
 
 
@@ -1252,10 +1247,8 @@ hipError_t launch_select(WalkDev *walks, const BatchEntry *batch, uint32_t nb, u
         if (e != hipSuccess) return e;
     }
     if (tail) return hipSuccess;
-    k_select<<<nb, kSelThreads, 0, s>>>(walks, batch, comb_blocks, comb_group, pure, (ChoiceDev *)out, pend);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    k_ambig<<<nb, kAmbThreads, 0, s>>>(walks, batch, comb_blocks, comb_group, pure, (ChoiceDev *)out, margin);
+    k_select<<<nb, kSelThreads, 0, s>>>(walks, batch, comb_blocks, comb_group, pure, (ChoiceDev *)out, pend,
+                                        margin);
     return hipGetLastError();
 }
 

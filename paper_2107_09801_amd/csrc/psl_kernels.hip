@@ -855,9 +855,14 @@ __device__ __forceinline__ void ambig_walk(WalkDev &w, const BatchEntry &be, uin
 // blocks per walk (blockIdx.y = batch position); each block leaves its
 // smallest F and its first smallest PSL in be.red. A group of G lanes
 // (a power of two, at most 64) shares a candidate: lane g adds splits g,
-// g+G, ... in order, then the group adds its lanes' sums with a butterfly
-// (a fixed order for a given split count and G; G = 1 adds the splits in
-// order).
+// g+G, ... in order, then the group adds its lanes' sums in a fixed order for
+// a given split count and G (G = 1 adds the splits in order). For G <= 4 a
+// group is G adjacent lanes (a butterfly); for G >= 8 a block pass takes
+// cpb = 256 / G <= 32 candidates, lane t of the block has candidate t mod cpb
+// and split lane t / cpb, so that one load of a wavefront reads cpb
+// consecutive partials of each of 64 / cpb splits; the sums go through a
+// butterfly over the wavefront's split lanes, then the four wavefronts' sums
+// are added in wavefront order.
 // With tail != 0 the walk's last block to finish then makes its selection
 // (select_walk) and its ambiguity flags; b0 = the batch position of
 // blockIdx.y = 0; done holds one zeroed counter per batch position.
@@ -870,8 +875,14 @@ __global__ __launch_bounds__(kCombThreads) void k_combine(WalkDev *walks, const 
     const uint32_t n = be.fixed ? be.n_lmt : w.n_lmt;
     const uint32_t ks = be.ksplit;
     const double *T = tabs.T[w.alpha];
-    const uint32_t g = threadIdx.x & (uint32_t)(G - 1);
     const uint32_t cpb = kCombThreads / (uint32_t)G;      // candidates per block pass
+    const bool wide = G >= 8;
+    const uint32_t g = wide ? threadIdx.x / cpb : threadIdx.x & (uint32_t)(G - 1);
+    const uint32_t ci = wide ? threadIdx.x % cpb : threadIdx.x / (uint32_t)G;   // candidate in the pass
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    static_assert(kCombThreads == 256, "four wavefronts per combine block");
+    __shared__ double s_wf[4][32];
+    __shared__ uint32_t s_wm[4][32];
     // split path: the partials hold the VALU terms only; the prefix sums and
     // the linear sums (psl_split.hip) supply the rest of F_j
     const bool split = be.lsplit != 0 && be.ss->use != 0;
@@ -885,7 +896,7 @@ __global__ __launch_bounds__(kCombThreads) void k_combine(WalkDev *walks, const 
     uint32_t lo, hi;
     comb_range(n, gridDim.x, (uint32_t)G, blockIdx.x, lo, hi);
     for (uint32_t i0 = lo; i0 < hi; i0 += cpb) {
-        const uint32_t i = i0 + threadIdx.x / (uint32_t)G;
+        const uint32_t i = i0 + ci;
         double f = 0.0;
         uint32_t m = 0;
         if (i < hi) {
@@ -911,9 +922,30 @@ __global__ __launch_bounds__(kCombThreads) void k_combine(WalkDev *walks, const 
                 }
             }
         }
-        for (int o = G >> 1; o > 0; o >>= 1) {
-            f += __shfl_xor(f, o);
-            m = max(m, (uint32_t)__shfl_xor((int)m, o));
+        if (wide) {
+            for (int o = (int)cpb; o < 64; o <<= 1) {
+                f += __shfl_xor(f, o);
+                m = max(m, (uint32_t)__shfl_xor((int)m, o));
+            }
+            if ((uint32_t)lane < cpb) {
+                s_wf[wave][lane] = f;
+                s_wm[wave][lane] = m;
+            }
+            __syncthreads();
+            if (g == 0) {           // wavefront 0, lanes below cpb
+                f = s_wf[0][lane];
+                m = s_wm[0][lane];
+                for (int x = 1; x < 4; ++x) {
+                    f += s_wf[x][lane];
+                    m = max(m, s_wm[x][lane]);
+                }
+            }
+            __syncthreads();        // the next pass rewrites the rows
+        } else {
+            for (int o = G >> 1; o > 0; o >>= 1) {
+                f += __shfl_xor(f, o);
+                m = max(m, (uint32_t)__shfl_xor((int)m, o));
+            }
         }
         if (g == 0 && i < hi) {
             // the near-peak path stores the PSL itself; the dense path the
@@ -945,7 +977,6 @@ __global__ __launch_bounds__(kCombThreads) void k_combine(WalkDev *walks, const 
         sel_merge(fmin, pmin, ipmin, of, op, oi);
     }
     __shared__ SelPart s_r[kCombThreads / 64];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) s_r[wave] = SelPart{fmin, pmin, ipmin};
     __syncthreads();
     if (threadIdx.x == 0) {

@@ -1012,7 +1012,7 @@ __global__ __launch_bounds__(kCombThreads) void k_combine(WalkDev *walks, const 
 
 // The selection of a walk and its ambiguity flags (one block per walk, after
 // k_combine when the combine launch does not make them itself).
-constexpr int kSelThreads = 1024;
+constexpr int kSelThreads = 256;
 __global__ __launch_bounds__(kSelThreads) void k_select(WalkDev *walks, const BatchEntry *batch,
                                                         uint32_t comb_blocks, uint32_t comb_group, int pure,
                                                         ChoiceDev *out, uint32_t *pend, double margin)

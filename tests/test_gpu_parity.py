@@ -367,6 +367,36 @@ def test_eval_items_option_keeps_results(ctx):
     ctx.free_walks([w])
 
 
+@pytest.mark.parametrize("L,n_lmt,items,ks_min", [(65535, 256, 0, 129), (131071, 64, 0, 257),
+                                                   (262143, 64, 65536, 513)])
+def test_eval_many_splits_small_neighbourhood(ctx, L, n_lmt, items, ks_min):
+    """Few candidates over a long sequence (the serving shape) cut into many
+    k-splits, which the combine adds with 16, 32 and 64 lanes per candidate
+    (each lane's splits in order, then a fixed tree): F and PSL against the
+    oracle, candidate by candidate."""
+    import torch
+    from paper_2107_09801_amd import libpsl
+    seed, start, alpha = 900 + L % 97, L // 3, 13 if L % 2 else 4
+    (w,) = ctx.init_walks(L, 1, seed, alpha1=alpha, alpha2=4)
+    try:
+        if items:
+            ctx.set_option(libpsl.OPT_EVAL_ITEMS, items)
+        assert ctx.eval_shape(L, n_lmt, 1)[1] >= ks_min
+        F, P = _dev(n_lmt, torch.float64), _dev(n_lmt, torch.int32)
+        ch = ctx.eval_neighbourhood(w, start, n_lmt, F, P)
+    finally:
+        ctx.set_option(libpsl.OPT_EVAL_ITEMS, -1)
+    s, C = _oracle_state(L, seed)
+    Fo, Po = oracle.eval_neighbourhood(s, C, alpha, start, n_lmt, nthreads=8)
+    assert np.array_equal(P.cpu().numpy()[:n_lmt], Po)
+    assert _rel(F.cpu().numpy()[:n_lmt], Fo) <= F_RTOL
+    oc = oracle.select(Fo, Po, margin=MARGIN)
+    assert ch["psl_min"] == oc.psl_min
+    if not oc.flags & oracle.AMBIG_ARGMIN:
+        assert ch["i_best"] == oc.i_best
+    ctx.free_walks([w])
+
+
 def test_graph_replays_match_eager(ctx):
     """One captured step replayed many times, with eager work and syncs between
     replays, equals the eager path after every replay."""

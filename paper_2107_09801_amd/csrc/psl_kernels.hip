@@ -417,8 +417,11 @@ __device__ __forceinline__ void chunk_octs(const BatchEntry &be, const WalkDev &
 // Mode 0 (step, with the near list) and 2 (init): one block per segment of
 // the map.
 __global__ __launch_bounds__(kChunkThreads) void k_chunks(const WalkDev *walks, const BatchEntry *batch,
-                                                          Tables tabs, int mode, SegMap map)
+                                                          Tables tabs, int mode, SegMap map, uint32_t *pend)
 {
+    // the previous step's pending list has been consumed; this step's
+    // bookkeeping (in the selection) refills it
+    if (pend && blockIdx.x == 0 && threadIdx.x == 0) pend[0] = 0;
     const int wave = (int)threadIdx.x >> 6;
     constexpr int kWaves = kChunkThreads / 64;
     uint32_t b, seg;
@@ -679,11 +682,8 @@ __device__ __forceinline__ void sel_merge(double &f, int32_t &p, uint32_t &i, do
 // The selection of walk w (batch position bi) by a block of NT threads.
 template <int NT>
 __device__ __forceinline__ void select_walk(WalkDev &w, const BatchEntry &be, uint32_t bi, uint32_t comb_blocks,
-                                            uint32_t comb_group, int pure, ChoiceDev *out, uint32_t *pend)
+                                            uint32_t comb_group, int pure, ChoiceDev *out)
 {
-    // the previous step's pending list has been consumed; this step's
-    // bookkeeping refills it
-    if (pend && bi == 0 && threadIdx.x == 0) pend[0] = 0;
     const uint32_t n = be.fixed ? be.n_lmt : w.n_lmt;
     const uint32_t start = be.fixed ? be.start : step_start(w);
     const uint32_t L = w.L;
@@ -851,6 +851,84 @@ __device__ __forceinline__ void ambig_walk(WalkDev &w, const BatchEntry &be, uin
     }
 }
 
+// The rest of one loop iteration of Algorithm 1 after the selection, by the
+// block of NT threads that made it (batch position bi): the move's bit, the
+// three-way comparison with v_local, the unimproved counter, the local best,
+// and the phase switch (Rand_flip of the local best and the exponent swap;
+// the walk joins the batch's pending list, whose C, F and PSL k_pending then
+// rebuilds). The C update runs after it (k_apply), from bits that equal the
+// pre-move pivot's at every position but j: the pivot's, or on a switch the
+// local best's (which are then the move's pivot, if the move improved; if it
+// did not, C is rebuilt from C of the local best anyway).
+template <int NT>
+__device__ __forceinline__ void bookkeep_walk(WalkDev &w, uint32_t bi, uint32_t *pend)
+{
+    __shared__ int s_improved, s_switch;
+    __shared__ uint32_t s_pos[1024];
+    if (threadIdx.x == 0) {
+        const uint32_t k = w.k;
+        w.pivot[k >> 6] ^= 1ull << (k & 63u);
+        w.F_pivot = w.value_step;
+        w.psl_pivot = w.psl_k;
+        // the comparison with v_local was taken by the selection
+        int improved = 0, sw = 0;
+        uint32_t flags = w.flags;
+        if (flags & STEP_IMPROVED) {
+            improved = 1;
+            w.unimproved = 0;
+            w.value_local = w.value_step;
+        } else if (flags & STEP_WORSE) {
+            w.unimproved += 1;
+            if (w.switch_period == 0 && w.unimproved > w.ls_lmt) sw = 1;
+        }
+        if (w.switch_period > 0 && ((w.t + 1u) % w.switch_period) == 0) sw = 1;
+        if (sw) flags |= STEP_SWITCHED;
+        w.flags = flags;
+        if (w.trace_cap) {
+            TraceEntry e;
+            e.t = w.t;
+            e.start = w.start;
+            e.k = w.k;
+            e.value_step = w.value_step;
+            e.psl_k = w.psl_k;
+            e.psl_best = w.psl_best;
+            e.alpha = sw ? (w.alpha == w.alpha1 ? w.alpha2 : w.alpha1) : w.alpha;
+            e.flags = flags;
+            w.trace[w.t % w.trace_cap] = e;
+        }
+        w.t += 1;
+        s_improved = improved;
+        s_switch = sw;
+    }
+    __syncthreads();
+    if (s_improved) copy_words(w.local_best, w.pivot, w.nw, threadIdx.x, NT, UINT32_MAX, 0);
+    __syncthreads();
+    if (s_switch) {
+        copy_words(w.pivot, w.local_best, w.nw, threadIdx.x, NT, UINT32_MAX, 0);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const uint32_t L = w.L;
+            uint32_t cnt = 0;
+            for (uint64_t r = 0; cnt < w.flip_lmt && r < (1ull << 24); ++r) {
+                const uint64_t ctr = (2ull << 60) | (w.q << 24) | r;
+                const uint32_t pos = (uint32_t)(draw(w.seed, ctr) % (uint64_t)L);
+                bool dup = false;
+                for (uint32_t x = 0; x < cnt; ++x) dup |= (s_pos[x] == pos);
+                if (dup) continue;
+                s_pos[cnt] = pos;
+                w.flips[cnt] = pos;
+                ++cnt;
+                w.pivot[pos >> 6] ^= 1ull << (pos & 63u);
+            }
+            w.n_flips = cnt;
+            w.alpha = (w.alpha == w.alpha1) ? w.alpha2 : w.alpha1;
+            w.q += 1;
+            w.pending = 1;
+            pend[1 + atomicAdd(&pend[0], 1u)] = bi;
+        }
+    }
+}
+
 // F and PSL per candidate from the k-split partials, spread over gridDim.x
 // blocks per walk (blockIdx.y = batch position); each block leaves its
 // smallest F and its first smallest PSL in be.red. A group of G lanes
@@ -1005,13 +1083,18 @@ __global__ __launch_bounds__(kCombThreads) void k_combine(WalkDev *walks, const 
     __syncthreads();
     if (!s_last) return;
     if (gridDim.x > 1) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    select_walk<kCombThreads>(w, be, bi, gridDim.x, (uint32_t)G, pure, out, pend);
+    select_walk<kCombThreads>(w, be, bi, gridDim.x, (uint32_t)G, pure, out);
     __syncthreads();
     ambig_walk<kCombThreads>(w, be, bi, gridDim.x, (uint32_t)G, pure, out, margin);
+    if (!pure) {
+        __syncthreads();
+        bookkeep_walk<kCombThreads>(w, bi, pend);
+    }
 }
 
-// The selection of a walk and its ambiguity flags (one block per walk, after
-// k_combine when the combine launch does not make them itself).
+// The selection of a walk, its ambiguity flags and (pure == 0) its
+// bookkeeping: one block per walk, after k_combine when the combine launch
+// does not make them itself.
 constexpr int kSelThreads = 256;
 __global__ __launch_bounds__(kSelThreads) void k_select(WalkDev *walks, const BatchEntry *batch,
                                                         uint32_t comb_blocks, uint32_t comb_group, int pure,
@@ -1019,9 +1102,13 @@ __global__ __launch_bounds__(kSelThreads) void k_select(WalkDev *walks, const Ba
 {
     const BatchEntry be = batch[blockIdx.x];
     WalkDev &w = walks[be.slot];
-    select_walk<kSelThreads>(w, be, blockIdx.x, comb_blocks, comb_group, pure, out, pend);
+    select_walk<kSelThreads>(w, be, blockIdx.x, comb_blocks, comb_group, pure, out);
     __syncthreads();
     ambig_walk<kSelThreads>(w, be, blockIdx.x, comb_blocks, comb_group, pure, out, margin);
+    if (!pure) {
+        __syncthreads();
+        bookkeep_walk<kSelThreads>(w, blockIdx.x, pend);
+    }
 }
 
 
@@ -1069,82 +1156,6 @@ __device__ __forceinline__ void apply_range(int32_t *__restrict__ C, int32_t *__
     }
 }
 
-constexpr int kBookThreads = 256;
-
-// The rest of one loop iteration of Algorithm 1 after the C update, one block
-// per walk: the move's bit, the three-way comparison with v_local, the
-// unimproved counter, the local best, and the phase switch (Rand_flip of the
-// local best and the exponent swap; the walk joins the batch's pending list,
-// whose C, F and PSL k_pending then rebuilds).
-__global__ __launch_bounds__(kBookThreads) void k_bookkeep(WalkDev *walks, const BatchEntry *batch,
-                                                           uint32_t *pend)
-{
-    WalkDev &w = walks[batch[blockIdx.x].slot];
-    __shared__ int s_improved, s_switch;
-    __shared__ uint32_t s_pos[1024];
-    if (threadIdx.x == 0) {
-        const uint32_t k = w.k;
-        w.pivot[k >> 6] ^= 1ull << (k & 63u);
-        w.F_pivot = w.value_step;
-        w.psl_pivot = w.psl_k;
-        // the comparison with v_local was taken by the selection
-        int improved = 0, sw = 0;
-        uint32_t flags = w.flags;
-        if (flags & STEP_IMPROVED) {
-            improved = 1;
-            w.unimproved = 0;
-            w.value_local = w.value_step;
-        } else if (flags & STEP_WORSE) {
-            w.unimproved += 1;
-            if (w.switch_period == 0 && w.unimproved > w.ls_lmt) sw = 1;
-        }
-        if (w.switch_period > 0 && ((w.t + 1u) % w.switch_period) == 0) sw = 1;
-        if (sw) flags |= STEP_SWITCHED;
-        w.flags = flags;
-        if (w.trace_cap) {
-            TraceEntry e;
-            e.t = w.t;
-            e.start = w.start;
-            e.k = w.k;
-            e.value_step = w.value_step;
-            e.psl_k = w.psl_k;
-            e.psl_best = w.psl_best;
-            e.alpha = sw ? (w.alpha == w.alpha1 ? w.alpha2 : w.alpha1) : w.alpha;
-            e.flags = flags;
-            w.trace[w.t % w.trace_cap] = e;
-        }
-        w.t += 1;
-        s_improved = improved;
-        s_switch = sw;
-    }
-    __syncthreads();
-    if (s_improved) copy_words(w.local_best, w.pivot, w.nw, threadIdx.x, kBookThreads, UINT32_MAX, 0);
-    __syncthreads();
-    if (s_switch) {
-        copy_words(w.pivot, w.local_best, w.nw, threadIdx.x, kBookThreads, UINT32_MAX, 0);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const uint32_t L = w.L;
-            uint32_t cnt = 0;
-            for (uint64_t r = 0; cnt < w.flip_lmt && r < (1ull << 24); ++r) {
-                const uint64_t ctr = (2ull << 60) | (w.q << 24) | r;
-                const uint32_t pos = (uint32_t)(draw(w.seed, ctr) % (uint64_t)L);
-                bool dup = false;
-                for (uint32_t x = 0; x < cnt; ++x) dup |= (s_pos[x] == pos);
-                if (dup) continue;
-                s_pos[cnt] = pos;
-                w.flips[cnt] = pos;
-                ++cnt;
-                w.pivot[pos >> 6] ^= 1ull << (pos & 63u);
-            }
-            w.n_flips = cnt;
-            w.alpha = (w.alpha == w.alpha1) ? w.alpha2 : w.alpha1;
-            w.q += 1;
-            w.pending = 1;
-            pend[1 + atomicAdd(&pend[0], 1u)] = blockIdx.x;
-        }
-    }
-}
 
 __global__ __launch_bounds__(kApplyThreads) void k_apply(WalkDev *walks, const BatchEntry *batch,
                                                          int64_t j_fixed, SegMap map)
@@ -1154,10 +1165,15 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply(WalkDev *walks, const B
     WalkDev &w = walks[batch[bi].slot];
     const uint32_t L = w.L;
     const uint32_t j = j_fixed >= 0 ? (uint32_t)j_fixed : w.k;
-    const uint64_t *b = w.pivot;
-    const int sj = get_bit(b, j) ? -1 : 1;
+    // a forced flip reads the pivot before its bit changes; the step's move
+    // comes after the bookkeeping, which flipped bit j, and on a phase switch
+    // replaced the pivot: then the local best holds the pre-move bits at
+    // every position but j (an improving move), or C is rebuilt afterwards
+    const bool moved = j_fixed < 0;
+    const uint64_t *b = moved && (w.flags & STEP_SWITCHED) ? w.local_best : w.pivot;
+    const int sj = (get_bit(b, j) != 0) != moved ? -1 : 1;      // s_j before the flip
     // the move improves on v_local: the new pivot becomes local_best
-    const bool lb = j_fixed < 0 && (w.flags & STEP_IMPROVED);
+    const bool lb = moved && (w.flags & STEP_IMPROVED);
     const uint32_t k0 = 1u + (seg << map.shift);
     const uint32_t k1 = min(L, k0 + (1u << map.shift));
     apply_range(w.C, w.C_lb, b, L, j, sj, lb, k0, k1);
@@ -1223,7 +1239,7 @@ hipError_t launch_fitness(WalkDev *walks, const BatchEntry *batch, uint32_t nb, 
 }
 
 hipError_t launch_suffix(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t max_L,
-                         const Tables &tabs, int mode, const SegMap *map, hipStream_t s)
+                         const Tables &tabs, int mode, const SegMap *map, uint32_t *pend, hipStream_t s)
 {
     if (mode != 0 && mode != 2) return hipErrorInvalidValue;
     if (!map || map->total == 0 || map->nb != nb || map->shift < kSegShiftMin || map->shift > kSegShiftMax)
@@ -1231,7 +1247,7 @@ hipError_t launch_suffix(WalkDev *walks, const BatchEntry *batch, uint32_t nb, u
     if (mode == 0 && (!map->tot || !map->tmax)) return hipErrorInvalidValue;
     SegMap m = *map;
     if (mode != 0) m.tot = nullptr, m.tmax = nullptr;
-    k_chunks<<<m.total, kChunkThreads, 0, s>>>(walks, batch, tabs, mode, m);
+    k_chunks<<<m.total, kChunkThreads, 0, s>>>(walks, batch, tabs, mode, m, mode == 0 ? pend : nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (mode == 0) {
@@ -1308,11 +1324,5 @@ hipError_t launch_flip_bit(WalkDev *walks, const BatchEntry *batch, uint32_t j, 
     return hipGetLastError();
 }
 
-hipError_t launch_bookkeep(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t *pend, hipStream_t s)
-{
-    if (!pend) return hipErrorInvalidValue;
-    k_bookkeep<<<nb, kBookThreads, 0, s>>>(walks, batch, pend);
-    return hipGetLastError();
-}
 
 }  // namespace psl

@@ -23,33 +23,32 @@ hipError_t launch_fitness(WalkDev *walks, const BatchEntry *batch, uint32_t nb, 
 hipError_t launch_eval(const WalkDev *walks, const BatchEntry *batch, const EvalItem *items,
                        uint32_t n_items, const Tables &tabs, const EvalShape &shape,
                        EvalQueues *queues, hipStream_t s);
-// mode 0: the step's chunk suffix arrays and near-peak list; mode 2: the
-// initial fitness (value_local, F_pivot, psl_pivot, psl_best) of every walk.
+// mode 0: the step's chunk suffix arrays and near-peak list (and, with pend,
+// the step's pending list emptied); mode 2: the initial fitness (value_local,
+// F_pivot, psl_pivot, psl_best) of every walk.
 hipError_t launch_suffix(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t max_L,
-                         const Tables &tabs, int mode, const SegMap *map, hipStream_t s);
+                         const Tables &tabs, int mode, const SegMap *map, uint32_t *pend, hipStream_t s);
 // Zero the near-peak counts of a batch, its pending count and its combine
 // counters (done, nb entries; may be null) after its scratch is allocated.
 hipError_t launch_near_reset(const BatchEntry *batch, uint32_t nb, uint32_t *pend, uint32_t *done, hipStream_t s);
-// F and PSL per candidate from the partials, then the selection and its
-// ambiguity flags (margin: their relative margin), by each walk's last combine
-// block in launches of at most 256 combine blocks (done: one zeroed counter
-// per batch position, left zero; without it the selection takes launches of
-// its own): pure != 0 writes the choice record `out` (one walk), else the
-// walks' step records.
+// F and PSL per candidate from the partials, then the selection, its
+// ambiguity flags (margin: their relative margin) and, pure == 0, the step's
+// bookkeeping (pend: the pending list the walks that switch phase join), by
+// each walk's last combine block in launches of at most 256 combine blocks
+// (done: one zeroed counter per batch position, left zero; without it the
+// selection takes a launch of its own): pure != 0 writes the choice record
+// `out` (one walk), else the walks' step records.
 hipError_t launch_select(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t comb_blocks,
                          uint32_t comb_group, const Tables &tabs, int pure, void *out, uint32_t *pend,
                          uint32_t *done, double margin, hipStream_t s);
 size_t choice_dev_size();
 void choice_dev_unpack(const void *p, uint32_t *i_best, uint32_t *j_best, double *F_best,
                        double *F_min, uint32_t *j_psl, int32_t *psl_min, int32_t *psl_k, uint32_t *flags);
-// The C update of each walk's recorded move (j_fixed < 0) or of a forced flip
-// of element j_fixed.
+// The C update of each walk's recorded move (j_fixed < 0, after the
+// bookkeeping) or of a forced flip of element j_fixed (before its bit flips).
 hipError_t launch_apply(WalkDev *walks, const BatchEntry *batch, const SegMap &map, int64_t j_fixed,
                         hipStream_t s);
 hipError_t launch_flip_bit(WalkDev *walks, const BatchEntry *batch, uint32_t j, hipStream_t s);
-// The step's bookkeeping after the C update (pend: the pending list the
-// walks that switch phase join).
-hipError_t launch_bookkeep(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t *pend, hipStream_t s);
 // Units of launch_pending for walks of length L.
 inline uint64_t pending_units(uint32_t L) { return (L - 1 + kPendUnit - 1) / kPendUnit; }
 

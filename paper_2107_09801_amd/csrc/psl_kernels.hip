@@ -354,18 +354,27 @@ __device__ __forceinline__ void chunk_octs(const BatchEntry &be, const WalkDev &
     const int nchunks = (L - 1 + 31) / 32;
     const int lane = threadIdx.x & 63;
     for (int o = o0; o < o1; o += step) {
+        // the four passes' C values, then their T values, are all loaded
+        // before any is used (two waits per octet, not eight)
+        int av[4];
+        double tv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = 1 + 256 * o + 64 * i + lane;
+            const int32_t x = k < L ? w.C[k] : 0;
+            av[i] = x < 0 ? -x : x;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = 1 + 256 * o + 64 * i + lane;
+            tv[i] = k < L ? T[av[i]] : 0.0;
+        }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int e = 64 * i + lane;
             const int k = 1 + 256 * o + e;
-            double v = 0.0;
-            int a = 0;
-            if (k < L) {
-                const int32_t x = w.C[k];
-                a = x < 0 ? -x : x;
-                v = T[a];
-            }
-            sv[e] = v;
+            const int a = av[i];
+            sv[e] = tv[i];
             sa[e] = a;
             if (near) {
                 const bool take = k < L && a >= cut;

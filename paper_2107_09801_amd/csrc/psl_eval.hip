@@ -293,14 +293,35 @@ __device__ __forceinline__ void eval_sweep(EvalLds<WAVES> &sh, const WalkDev &w,
         nsum_add(sum, comp, acc);
     }
     // shifts where no lane of the wave has a neighbour in bounds (kn is a
-    // chunk start; k_hi a chunk start or L, the chunk arrays' last entry)
+    // chunk start; k_hi a chunk start or L): C'_k = C_k there. Blocks of 16
+    // wavefronts take their terms and PSL part from the suffix arrays (the
+    // step's launch_suffix scans the chunk values for them, the chunk arrays'
+    // last entry terminating); smaller blocks add the chunk sums [xa, xb)
+    // themselves (positive values; lane l takes chunks xa + l, xa + l + 64,
+    // ... in order, then a fixed butterfly; every lane ends with the same sum)
+    // and take the chunks' largest |C_k|.
     const int kn = max(k_lo, k_wend);
     if (kn < k_hi) {
         const int nchunks = (L - 1 + 31) / 32;
         const int xa = (kn - 1) >> 5;
         const int xb = k_hi >= L ? nchunks : (k_hi - 1) >> 5;
-        nsum_add(sum, comp, be.S0[xa] - be.S0[xb]);
-        if (kMax) mx = max(mx, hi32(T[be.M0[xa]]));
+        if constexpr (WAVES >= 16) {
+            nsum_add(sum, comp, be.S0[xa] - be.S0[xb]);
+            if (kMax) mx = max(mx, hi32(T[be.M0[xa]]));
+        } else {
+            double cs = 0.0;
+            uint32_t cm = 0;
+            for (int x = xa + lane; x < xb; x += 64) {
+                cs += be.S0[x];
+                if (kMax) cm = max(cm, be.M0[x]);
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                cs += __shfl_xor(cs, o);
+                if (kMax) cm = max(cm, (uint32_t)__shfl_xor((int)cm, o));
+            }
+            nsum_add(sum, comp, cs);
+            if (kMax) mx = max(mx, hi32(T[cm]));
+        }
     }
 }
 

@@ -1248,22 +1248,23 @@ hipError_t launch_fitness(WalkDev *walks, const BatchEntry *batch, uint32_t nb, 
 }
 
 hipError_t launch_suffix(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t max_L,
-                         const Tables &tabs, int mode, const SegMap *map, uint32_t *pend, hipStream_t s)
+                         const Tables &tabs, int mode, const SegMap *map, uint32_t *pend, int scan, hipStream_t s)
 {
     if (mode != 0 && mode != 2) return hipErrorInvalidValue;
     if (!map || map->total == 0 || map->nb != nb || map->shift < kSegShiftMin || map->shift > kSegShiftMax)
         return hipErrorInvalidValue;
-    if (mode == 0 && (!map->tot || !map->tmax)) return hipErrorInvalidValue;
+    scan = mode == 0 && scan;
+    if (scan && (!map->tot || !map->tmax)) return hipErrorInvalidValue;
     SegMap m = *map;
-    if (mode != 0) m.tot = nullptr, m.tmax = nullptr;
+    if (!scan) m.tot = nullptr, m.tmax = nullptr;
     k_chunks<<<m.total, kChunkThreads, 0, s>>>(walks, batch, tabs, mode, m, mode == 0 ? pend : nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (mode == 0) {
-        // the step: suffix values segment by segment
+    if (scan) {
+        // suffix values segment by segment (evaluations in 16-wavefront blocks)
         constexpr uint32_t per = kSegScanThreads / 64;
         k_seg_scan<<<(m.total + per - 1) / per, kSegScanThreads, 0, s>>>(walks, batch, m);
-    } else {
+    } else if (mode == 2) {
         // the initial fitness: totals per walk
         k_scan<<<nb, kScanThreads, 0, s>>>(walks, batch);
     }

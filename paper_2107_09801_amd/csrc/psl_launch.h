@@ -23,11 +23,14 @@ hipError_t launch_fitness(WalkDev *walks, const BatchEntry *batch, uint32_t nb, 
 hipError_t launch_eval(const WalkDev *walks, const BatchEntry *batch, const EvalItem *items,
                        uint32_t n_items, const Tables &tabs, const EvalShape &shape,
                        EvalQueues *queues, hipStream_t s);
-// mode 0: the step's chunk suffix arrays and near-peak list (and, with pend,
-// the step's pending list emptied); mode 2: the initial fitness (value_local,
-// F_pivot, psl_pivot, psl_best) of every walk.
+// mode 0: the step's chunk arrays and near-peak list (and, with pend, the
+// step's pending list emptied), turned into suffix values when scan != 0 (the
+// evaluation in 16-wavefront blocks reads those; smaller blocks add the chunk
+// values themselves); mode 2: the initial fitness (value_local, F_pivot,
+// psl_pivot, psl_best) of every walk.
 hipError_t launch_suffix(WalkDev *walks, const BatchEntry *batch, uint32_t nb, uint32_t max_L,
-                         const Tables &tabs, int mode, const SegMap *map, uint32_t *pend, hipStream_t s);
+                         const Tables &tabs, int mode, const SegMap *map, uint32_t *pend, int scan,
+                         hipStream_t s);
 // Zero the near-peak counts of a batch, its pending count and its combine
 // counters (done, nb entries; may be null) after its scratch is allocated.
 hipError_t launch_near_reset(const BatchEntry *batch, uint32_t nb, uint32_t *pend, uint32_t *done, hipStream_t s);

@@ -715,7 +715,8 @@ psl_status check_cfg(psl_ctx *ctx, const psl_walk_cfg *c)
 psl_status launch_step(psl_ctx *ctx, const BatchPlan &pl, const Tables &tabs, uint32_t n, bool timed)
 {
     psl_status st;
-    HIP_TRY(ctx, launch_suffix(ctx->d_walks, pl.d_batch, n, pl.max_L, tabs, 0, &pl.seg, pl.d_pend, ctx->stream));
+    HIP_TRY(ctx, launch_suffix(ctx->d_walks, pl.d_batch, n, pl.max_L, tabs, 0, &pl.seg, pl.d_pend,
+                               pl.shape.waves >= kEvalWavesMax, ctx->stream));
     if (timed && (st = timing_mark(ctx))) return st;
     if (pl.split) HIP_TRY(ctx, launch_split_prep(ctx->d_walks, pl.d_batch, n, tabs, pl.seg, ctx->stream));
     if (timed && (st = timing_mark(ctx))) return st;
@@ -966,7 +967,7 @@ psl_status psl_init_walks(psl_ctx *ctx, const psl_walk_cfg *cfg, uint32_t n,
         hipError_t e = launch_init_bits(ctx->d_walks, tmp.d_batch, (const uint32_t *)dw, n, nw, ctx->stream);
         if (e == hipSuccess) e = launch_corr(ctx->d_walks, tmp.d_batch, n, L, 0, ctx->stream);
         const SegMap sm = seg_uniform(n, L);
-        if (e == hipSuccess) e = launch_suffix(ctx->d_walks, tmp.d_batch, n, L, tabs, 2, &sm, nullptr, ctx->stream);
+        if (e == hipSuccess) e = launch_suffix(ctx->d_walks, tmp.d_batch, n, L, tabs, 2, &sm, nullptr, 0, ctx->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
         dev_free(ctx, dw, false);
         plan_free(ctx, tmp);
@@ -1025,6 +1026,7 @@ psl_status psl_eval_neighbourhood(psl_ctx *ctx, uint32_t walk, uint32_t start, u
     }
     const Tables tabs = tables_of(ctx);
     HIP_TRY(ctx, launch_suffix(ctx->d_walks, ctx->pure.d_batch, 1, h.L, tabs, 0, &ctx->pure.seg, nullptr,
+                               ctx->pure.shape.waves >= kEvalWavesMax,
                                ctx->stream));
     if (ctx->pure.split)
         HIP_TRY(ctx, launch_split_prep(ctx->d_walks, ctx->pure.d_batch, 1, tabs, ctx->pure.seg, ctx->stream));
@@ -1081,7 +1083,8 @@ psl_status psl_eval_neighbourhood_noalloc(psl_ctx *ctx, uint32_t walk, uint32_t 
         return st;
     }
     const Tables tabs = tables_of(ctx);
-    HIP_TRY(ctx, launch_suffix(ctx->d_walks, pl.d_batch, 1, h.L, tabs, 0, &pl.seg, nullptr, ctx->stream));
+    HIP_TRY(ctx, launch_suffix(ctx->d_walks, pl.d_batch, 1, h.L, tabs, 0, &pl.seg, nullptr,
+                               pl.shape.waves >= kEvalWavesMax, ctx->stream));
     HIP_TRY(ctx, launch_eval(ctx->d_walks, pl.d_batch, pl.d_items, pl.n_items, tabs, pl.shape, pl.d_queues,
                              ctx->stream));
     HIP_TRY(ctx, launch_select(ctx->d_walks, pl.d_batch, 1, pl.comb_blocks, pl.comb_group, tabs, 1, d_choice,
@@ -1279,7 +1282,7 @@ psl_status psl_autotune(psl_ctx *ctx, const uint32_t *walk_ids, uint32_t n, psl_
         psl_status s2 = make_plan(ctx, tmp, walk_ids, n, UINT32_MAX, 0, &c, items);
         if (s2) return s2;
         hipError_t e = launch_suffix(ctx->d_walks, tmp.d_batch, n, tmp.max_L, tabs, 0, &tmp.seg, nullptr,
-                                     ctx->stream);
+                                     tmp.shape.waves >= kEvalWavesMax, ctx->stream);
         if (e == hipSuccess)   // warm-up
             e = launch_eval(ctx->d_walks, tmp.d_batch, tmp.d_items, tmp.n_items, tabs, tmp.shape,
                             tmp.d_queues, ctx->stream);

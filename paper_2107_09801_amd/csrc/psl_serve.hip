@@ -517,7 +517,7 @@ psl_status Server::admit_start(std::vector<Job> &adm, char *&sp, char *stage_end
     HIP_TRY(ctx, launch_corr(ctx->d_walks, d_admit.p, n, maxL, 0, ctx->stream));
     HIP_TRY(ctx, hipMemcpyAsync(d_adm_seg.p, adm_off, sizeof(uint32_t) * (n + 1), hipMemcpyHostToDevice,
                                 ctx->stream));
-    HIP_TRY(ctx, launch_suffix(ctx->d_walks, d_admit.p, n, maxL, tabs, 2, &adm_map, nullptr, ctx->stream));
+    HIP_TRY(ctx, launch_suffix(ctx->d_walks, d_admit.p, n, maxL, tabs, 2, &adm_map, nullptr, 0, ctx->stream));
     return PSL_OK;
 }
 
@@ -663,7 +663,8 @@ psl_status Server::iterate()
     if (dirty && (st = upload_layout(sp, se))) return st;
     const uint32_t n = (uint32_t)active.size();
     const Tables tabs = tables_of(ctx);
-    HIP_TRY(ctx, launch_suffix(ctx->d_walks, d_batch.p, n, max_L, tabs, 0, &seg, d_pend.p, ctx->stream));
+    HIP_TRY(ctx, launch_suffix(ctx->d_walks, d_batch.p, n, max_L, tabs, 0, &seg, d_pend.p, shape.waves >= kEvalWavesMax,
+                               ctx->stream));
     HIP_TRY(ctx, launch_eval(ctx->d_walks, d_batch.p, d_items.p, n_items, tabs, shape, d_queues.p, ctx->stream));
     HIP_TRY(ctx, launch_select(ctx->d_walks, d_batch.p, n, comb_blocks, comb_group, tabs, 0, nullptr, d_pend.p,
                                d_done.p, ctx->amb_margin, ctx->stream));
